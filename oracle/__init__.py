@@ -1,0 +1,211 @@
+"""CPU oracle for the TPC tracking path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it and the
+two share no code.  The arithmetic lives in ``tpc_oracle.c`` (plain C,
+single-precision neighbour search with every operation rounded, double
+precision fit); this module builds it with gcc and wraps it with ctypes.
+
+Every function takes its parameters explicitly; none has a built-in default
+for a physics or algorithm constant.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tpc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+             "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (no fused multiply-add contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class FitParams(ctypes.Structure):
+    _fields_ = [("bz", ctypes.c_double), ("sigma_y", ctypes.c_double),
+                ("sigma_z", ctypes.c_double), ("max_sin", ctypes.c_double),
+                ("var_sin0", ctypes.c_double), ("var_tgl0", ctypes.c_double),
+                ("var_qpt0", ctypes.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32 = ctypes.c_int32
+        f32 = ctypes.c_float
+        L.oracle_neighbours.argtypes = [i32, i32, P, P, P, f32, f32, f32, f32, P, P]
+        L.oracle_neighbours.restype = None
+        L.oracle_ca_seed.argtypes = [i32, i32, i32, P, P, P, i32, i32, i32, P, P, P, P, P, P, P]
+        L.oracle_ca_seed.restype = i32
+        L.oracle_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
+        L.oracle_propagate.restype = i32
+        L.oracle_fit.argtypes = [i32, P, P, P, P, P, P, P, i32, P, ctypes.POINTER(FitParams),
+                                 P, P, P, P, P, P]
+        L.oracle_fit.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+def neighbours(row_offsets, y, z, n_rows, win_y, win_z, cut_y, cut_z):
+    """Returns (up, dn) int32 arrays: best triplet partners per cluster."""
+    off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    n = int(off[-1])
+    up = np.empty(n, np.int32)
+    dn = np.empty(n, np.int32)
+    lib().oracle_neighbours(len(off) - 1, n_rows, _p(off), _p(y), _p(z), win_y, win_z,
+                            cut_y, cut_z, _p(up), _p(dn))
+    return up, dn
+
+
+def ca_seed(row_offsets, up, dn, n_sectors, n_rows, min_hits):
+    """Returns dict(offsets, hits, frame, sector, first_row) of the seeds."""
+    off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    up = np.ascontiguousarray(up, dtype=np.int32)
+    dn = np.ascontiguousarray(dn, dtype=np.int32)
+    n = int(off[-1])
+    cap_s, cap_h = max(1, n // 2), max(1, n)
+    offsets = np.empty(cap_s + 1, np.int32)
+    hits = np.empty(cap_h, np.int32)
+    fr = np.empty(cap_s, np.int32)
+    se = np.empty(cap_s, np.int32)
+    rw = np.empty(cap_s, np.int32)
+    ns = ctypes.c_int32()
+    nh = ctypes.c_int32()
+    st = lib().oracle_ca_seed(len(off) - 1, n_sectors, n_rows, _p(off), _p(up), _p(dn), min_hits,
+                              cap_s, cap_h, ctypes.byref(ns), ctypes.byref(nh), _p(offsets),
+                              _p(hits), _p(fr), _p(se), _p(rw))
+    if st != 0:
+        raise RuntimeError("oracle seed capacity exceeded")
+    k, h = ns.value, nh.value
+    return dict(offsets=offsets[:k + 1].copy(), hits=hits[:h].copy(), frame=fr[:k].copy(),
+                sector=se[:k].copy(), first_row=rw[:k].copy())
+
+
+def propagate(p, dx, bz, max_sin):
+    """Exact helix step of the oracle: returns (status, p_out[5], F[5,5])."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    po = np.empty(5)
+    F = np.empty(25)
+    st = lib().oracle_propagate(_p(p), float(dx), float(bz), float(max_sin), _p(po), _p(F))
+    return st, po, F.reshape(5, 5)
+
+
+def fit(seeds: dict, y, z, row_x, n_rows, *, bz, sigma_y, sigma_z, max_sin, var_sin0,
+        var_tgl0, var_qpt0, map_: Optional[np.ndarray] = None):
+    """Double-precision Kalman fit of every seed.
+
+    ``y``, ``z`` are promoted to float64 (pass float64 truth to avoid the
+    float32 rounding of stored clusters).  ``map_`` is [S, R, 2] (dy, dz)
+    subtracted from the clusters of each (sector, row).
+    """
+    offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
+    hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
+    sec = np.ascontiguousarray(seeds["sector"], dtype=np.int32)
+    fr = np.ascontiguousarray(seeds["first_row"], dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    rx = np.ascontiguousarray(row_x, dtype=np.float64)
+    T = len(offsets) - 1
+    prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
+    mp = None if map_ is None else np.ascontiguousarray(map_, dtype=np.float64)
+    out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
+               ndf=np.empty(T, np.int32), status=np.empty(T, np.int32))
+    lib().oracle_fit(T, _p(offsets), _p(hits), _p(sec), _p(fr), _p(y), _p(z), _p(rx), n_rows,
+                     None if mp is None else _p(mp), ctypes.byref(prm), _p(out["x"]),
+                     _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndf"]),
+                     _p(out["status"]))
+    return out
+
+
+def unpack_cov(c15: np.ndarray) -> np.ndarray:
+    """Packed lower triangle (row by row) -> symmetric [.., 5, 5]."""
+    c15 = np.asarray(c15)
+    out = np.zeros(c15.shape[:-1] + (5, 5), dtype=c15.dtype)
+    q = 0
+    for i in range(5):
+        for j in range(i + 1):
+            out[..., i, j] = c15[..., q]
+            out[..., j, i] = c15[..., q]
+            q += 1
+    return out
+
+
+def chi2_sum(seeds, y, z, row_x, n_rows, map_, **prm) -> float:
+    """Loss of the differentiable workload: sum of chi2 over tracks whose fit succeeds."""
+    r = fit(seeds, y, z, row_x, n_rows, map_=map_, **prm)
+    ok = r["status"] == 0
+    return float(r["chi2"][ok].sum())
+
+
+def fd_map_gradient(seeds, y, z, row_x, n_rows, map_, entries, h=1e-3, **prm):
+    """Central finite differences (five-point) of ``chi2_sum`` w.r.t. map entries.
+
+    ``entries`` is a list of (sector, row, axis).  Only the tracks of that
+    sector that include that row are refitted (the others do not depend on it).
+    """
+    offsets = np.asarray(seeds["offsets"])
+    n = np.diff(offsets)
+    fr = np.asarray(seeds["first_row"])
+    sec = np.asarray(seeds["sector"])
+    out = np.empty(len(entries))
+    for i, (s, r, a) in enumerate(entries):
+        sel = np.nonzero((sec == s) & (fr <= r) & (fr + n > r))[0]
+        if sel.size == 0:
+            out[i] = 0.0
+            continue
+        sub = subset_seeds(seeds, sel)
+        mp = np.array(map_, dtype=np.float64, copy=True)
+        v0 = mp[s, r, a]
+        vals = []
+        for m in (2, 1, -1, -2):          # five-point central stencil, error O(h^4)
+            mp[s, r, a] = v0 + m * h
+            vals.append(chi2_sum(sub, y, z, row_x, n_rows, mp, **prm))
+        out[i] = (-vals[0] + 8 * vals[1] - 8 * vals[2] + vals[3]) / (12 * h)
+    return out
+
+
+def subset_seeds(seeds, sel):
+    offsets = np.asarray(seeds["offsets"])
+    hits = np.asarray(seeds["hits"])
+    n = np.diff(offsets)[sel]
+    no = np.zeros(len(sel) + 1, np.int32)
+    np.cumsum(n, out=no[1:])
+    nh = np.concatenate([hits[offsets[i]:offsets[i + 1]] for i in sel]) if len(sel) else np.zeros(0, np.int32)
+    return dict(offsets=no, hits=nh.astype(np.int32),
+                frame=np.asarray(seeds["frame"])[sel], sector=np.asarray(seeds["sector"])[sel],
+                first_row=np.asarray(seeds["first_row"])[sel])

@@ -1,0 +1,413 @@
+/*
+ * CPU oracle for TPC track reconstruction: neighbour finding, cellular
+ * automaton seeding and a Kalman helix fit.  TEST INFRASTRUCTURE ONLY: the
+ * tests, the smoke check and the CPU baseline leg of the benchmark call it;
+ * the GPU library never does, and the two share no code.
+ *
+ * The paper (Sec. 4.2 and Sec. 5) states that TPC track reconstruction is the
+ * work that fully loads the farm's GPUs, but it does not describe the
+ * algorithm.  Every step below is therefore a textbook reading, written as
+ * plainly as possible:
+ *
+ *   neighbours      windowed triplet search with a second-difference score;
+ *                   single precision, every operation rounded (no FMA), so a
+ *                   GPU implementation can match it bit for bit
+ *   ca_seed         mutual links -> maximal chains -> end claims -> seeds
+ *   fit             exact three-point helix start + extended Kalman filter
+ *                   through the hits inwards, double precision throughout
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "tpc_oracle.h"
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbours.  For every cluster h of pad row r (1 <= r <= R-2) of every     */
+/* (frame, sector), choose the pair (d in row r-1, u in row r+1) that passes  */
+/* the position windows and the second-difference cuts and minimises          */
+/*   q = (dy*dy + dz*dz),  dy = (y_u - y_h) - (y_h - y_d),  dz likewise,      */
+/* ties broken by the smaller u id, then the smaller d id.  Rows 0 and R-1    */
+/* get no partners.  A non-finite coordinate fails every comparison.          */
+/* ------------------------------------------------------------------------ */
+void oracle_neighbours(int32_t n_segments, int32_t n_rows, const int32_t *row_offsets,
+                       const float *y, const float *z, float win_y, float win_z,
+                       float cut_y, float cut_z, int32_t *up, int32_t *dn)
+{
+    int32_t n = row_offsets[n_segments];
+    for (int32_t i = 0; i < n; ++i) { up[i] = -1; dn[i] = -1; }
+
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t seg = 0; seg < n_segments; ++seg) {
+        int32_t r = seg % n_rows;
+        if (r == 0 || r == n_rows - 1) continue;
+        int32_t h0 = row_offsets[seg], h1 = row_offsets[seg + 1];
+        int32_t u0 = row_offsets[seg + 1], u1 = row_offsets[seg + 2];   /* row r+1 */
+        int32_t d0 = row_offsets[seg - 1], d1 = row_offsets[seg];       /* row r-1 */
+        for (int32_t h = h0; h < h1; ++h) {
+            int found = 0;
+            float best_q = 0.0f;
+            int32_t best_u = -1, best_d = -1;
+            for (int32_t u = u0; u < u1; ++u) {
+                float ay = y[u] - y[h];
+                float az = z[u] - z[h];
+                if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
+                for (int32_t d = d0; d < d1; ++d) {
+                    float by = y[h] - y[d];
+                    float bz = z[h] - z[d];
+                    if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
+                    float dy = ay - by;
+                    float dz = az - bz;
+                    if (!(fabsf(dy) <= cut_y && fabsf(dz) <= cut_z)) continue;
+                    float qy = dy * dy;
+                    float qz = dz * dz;
+                    float q = qy + qz;
+                    /* u and d ascend, so strict '<' keeps the smallest (q, u, d) */
+                    if (!found || q < best_q) {
+                        found = 1; best_q = q; best_u = u; best_d = d;
+                    }
+                }
+            }
+            up[h] = best_u;
+            dn[h] = best_d;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Seeding.                                                                   */
+/*  links:  Lup[h] = up[h] if dn[up[h]] == h;  Ldn[h] = dn[h] if up[dn[h]]==h */
+/*  chains: from a bottom b (no Ldn, has Lup) follow Lup to the top t;        */
+/*          core length m (>= 2)                                              */
+/*  claims: a chain with m >= min_hits-2 claims dn[b] and up[t] if these are  */
+/*          not linked; each claimed cluster goes to the smallest key         */
+/*          (-m, b)                                                           */
+/*  seeds:  [dn[b] if won] + core + [up[t] if won], kept if >= min_hits hits, */
+/*          listed in ascending id of their first hit                         */
+/* ------------------------------------------------------------------------ */
+typedef struct { int32_t first; int32_t b; int32_t len; int32_t eb; int32_t et; } seed_rec;
+
+static int cmp_seed(const void *a, const void *b)
+{
+    const seed_rec *x = (const seed_rec *)a, *y = (const seed_rec *)b;
+    return (x->first > y->first) - (x->first < y->first);
+}
+
+int32_t oracle_ca_seed(int32_t n_segments, int32_t n_sectors, int32_t n_rows,
+                       const int32_t *row_offsets, const int32_t *up, const int32_t *dn,
+                       int32_t min_hits, int32_t cap_seeds, int32_t cap_hits,
+                       int32_t *n_seeds_out, int32_t *n_hits_out, int32_t *offsets,
+                       int32_t *hits, int32_t *frame, int32_t *sector, int32_t *first_row)
+{
+    int32_t n = row_offsets[n_segments];
+    int32_t *Lup = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *Ldn = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *seg_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint64_t *claim = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *top = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *core = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    seed_rec *recs = (seed_rec *)malloc(sizeof(seed_rec) * (size_t)(n > 0 ? n : 1));
+
+    for (int32_t s = 0; s < n_segments; ++s)
+        for (int32_t i = row_offsets[s]; i < row_offsets[s + 1]; ++i) seg_of[i] = s;
+
+    for (int32_t h = 0; h < n; ++h) {
+        Lup[h] = (up[h] >= 0 && dn[up[h]] == h) ? up[h] : -1;
+        Ldn[h] = (dn[h] >= 0 && up[dn[h]] == h) ? dn[h] : -1;
+        claim[h] = UINT64_MAX;
+        top[h] = -1;
+        core[h] = 0;
+    }
+    /* chains */
+    for (int32_t b = 0; b < n; ++b) {
+        if (!(Ldn[b] == -1 && Lup[b] != -1)) continue;
+        int32_t t = b, m = 1;
+        while (Lup[t] != -1) { t = Lup[t]; ++m; }
+        top[b] = t;
+        core[b] = m;
+    }
+    /* claims */
+    for (int32_t b = 0; b < n; ++b) {
+        if (top[b] < 0 || core[b] < min_hits - 2) continue;
+        uint64_t key = ((uint64_t)(2147483648u - (uint32_t)core[b]) << 32) | (uint32_t)b;
+        int32_t ends[2] = {dn[b], up[top[b]]};
+        for (int k = 0; k < 2; ++k) {
+            int32_t e = ends[k];
+            if (e < 0 || Lup[e] != -1 || Ldn[e] != -1) continue;
+            if (key < claim[e]) claim[e] = key;
+        }
+    }
+    /* seeds */
+    int32_t ns = 0;
+    for (int32_t b = 0; b < n; ++b) {
+        if (top[b] < 0) continue;
+        int32_t m = core[b];
+        int won_b = 0, won_t = 0;
+        if (m >= min_hits - 2) {
+            uint64_t key = ((uint64_t)(2147483648u - (uint32_t)m) << 32) | (uint32_t)b;
+            int32_t eb = dn[b], et = up[top[b]];
+            won_b = (eb >= 0 && claim[eb] == key);
+            won_t = (et >= 0 && claim[et] == key);
+        }
+        int32_t len = m + won_b + won_t;
+        if (len < min_hits) continue;
+        recs[ns].b = b;
+        recs[ns].len = len;
+        recs[ns].eb = won_b ? dn[b] : -1;
+        recs[ns].et = won_t ? up[top[b]] : -1;
+        recs[ns].first = won_b ? dn[b] : b;
+        ++ns;
+    }
+    qsort(recs, (size_t)ns, sizeof(seed_rec), cmp_seed);
+
+    int32_t nh = 0;
+    for (int32_t i = 0; i < ns; ++i) nh += recs[i].len;
+    *n_seeds_out = ns;
+    *n_hits_out = nh;
+    int32_t status = 0;
+    if (ns > cap_seeds || nh > cap_hits) status = -2;
+    else {
+        int32_t pos = 0;
+        for (int32_t i = 0; i < ns; ++i) {
+            offsets[i] = pos;
+            int32_t f = recs[i].first;
+            int32_t seg = seg_of[f];
+            frame[i] = seg / (n_sectors * n_rows);
+            sector[i] = (seg / n_rows) % n_sectors;
+            first_row[i] = seg % n_rows;
+            if (recs[i].eb >= 0) hits[pos++] = recs[i].eb;
+            for (int32_t c = recs[i].b; c != -1; c = Lup[c]) hits[pos++] = c;
+            if (recs[i].et >= 0) hits[pos++] = recs[i].et;
+        }
+        offsets[ns] = pos;
+    }
+    free(Lup); free(Ldn); free(seg_of); free(claim); free(top); free(core); free(recs);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Helix propagation between pad-row planes, double precision.               */
+/* State p = (y, z, s = sin phi, t = tan lambda, w = q/pT) at plane x; the    */
+/* track is oriented towards +x.  Curvature kappa = -c * Bz * w (ccw > 0).    */
+/* ------------------------------------------------------------------------ */
+#define C_LIGHT 0.00299792458
+
+/* g(u) = asin(u)/u, g(0) = 1 */
+static double g_of(double u)
+{
+    if (fabs(u) < 1e-2) {
+        double u2 = u * u;
+        return 1.0 + u2 * (1.0 / 6.0 + u2 * (3.0 / 40.0 + u2 * (5.0 / 112.0)));
+    }
+    return asin(u) / u;
+}
+
+/* g'(u) = (u / sqrt(1-u^2) - asin(u)) / u^2 */
+static double gprime_of(double u)
+{
+    if (fabs(u) < 1e-2) {
+        double u2 = u * u;
+        return u * (1.0 / 3.0 + u2 * (3.0 / 10.0 + u2 * (15.0 / 56.0)));
+    }
+    return (u / sqrt(1.0 - u * u) - asin(u)) / (u * u);
+}
+
+/* Moves p from plane x to plane x + dx along the exact helix.  F (row-major
+ * 5x5, may be NULL) receives d p_out / d p_in.  Returns 0, or 2 if the
+ * direction reaches |sin phi| >= max_sin. */
+int32_t oracle_propagate(const double *p, double dx, double bz, double max_sin,
+                         double *pout, double *F)
+{
+    double y = p[0], z = p[1], s = p[2], t = p[3], w = p[4];
+    double kap = -C_LIGHT * bz * w;
+    double s2 = s + kap * dx;
+    if (!(fabs(s) < max_sin) || !(fabs(s2) < max_sin)) return 2;
+    double c1 = sqrt(1.0 - s * s);
+    double c2 = sqrt(1.0 - s2 * s2);
+    double den = c1 + c2;
+    double T = (s + s2) / den;
+    double ady = fabs(dx);
+    double sgn = dx >= 0.0 ? 1.0 : -1.0;
+    double chord = ady * sqrt(1.0 + T * T);
+    double u = kap * chord / 2.0;
+    double ds = sgn * chord * g_of(u);
+    pout[0] = y + dx * T;
+    pout[1] = z + t * ds;
+    pout[2] = s2;
+    pout[3] = t;
+    pout[4] = w;
+    if (F) {
+        double dkap_dw = -C_LIGHT * bz;
+        /* partial derivatives of T(s, s2) */
+        double dT_ds_p = (den + (s + s2) * s / c1) / (den * den);
+        double dT_ds2_p = (den + (s + s2) * s2 / c2) / (den * den);
+        double dT_ds = dT_ds_p + dT_ds2_p;             /* ds2/ds = 1 */
+        double dT_dw = dT_ds2_p * dx * dkap_dw;        /* ds2/dw = dx dkap/dw */
+        /* ds = sgn * chord * g(kap * chord / 2) */
+        double dds_dchord = sgn / sqrt(1.0 - u * u);   /* d(chord g(u))/dchord = g + u g' */
+        double dds_dkap = sgn * chord * chord / 2.0 * gprime_of(u);
+        double dchord_dT = ady * T / sqrt(1.0 + T * T);
+        double dds_ds = dds_dchord * dchord_dT * dT_ds;
+        double dds_dw = dds_dchord * dchord_dT * dT_dw + dds_dkap * dkap_dw;
+        for (int i = 0; i < 25; ++i) F[i] = 0.0;
+        for (int i = 0; i < 5; ++i) F[i * 5 + i] = 1.0;
+        F[0 * 5 + 2] = dx * dT_ds;
+        F[0 * 5 + 4] = dx * dT_dw;
+        F[1 * 5 + 2] = t * dds_ds;
+        F[1 * 5 + 3] = ds;
+        F[1 * 5 + 4] = t * dds_dw;
+        F[2 * 5 + 4] = dx * dkap_dw;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fit.  For each seed with hits k = 0..n-1 (ascending pad row):             */
+/*  start  exact circle through hits A = n-1, B = (n-1)/2, C = 0 gives the    */
+/*         curvature, the direction at A and tan lambda; state at x_A with    */
+/*         y, z of A and covariance diag(sy^2, sz^2, v_s, v_t, v_w)           */
+/*  filter for k = n-2 .. 0: propagate to x_k, C <- F C F^T, then update with */
+/*         the measurement (y_k, z_k): r = m - (y, z), S = C_yz + diag(sy^2,  */
+/*         sz^2), K = C H^T S^-1, p += K r, C -= K H C, chi2 += r^T S^-1 r    */
+/*  output state and covariance at x_0, chi2, ndf = 2n - 5                    */
+/* Measurements are corrected by a per (sector, row) map when one is given.   */
+/* ------------------------------------------------------------------------ */
+static void mat5_mul(const double *A, const double *B, double *C)
+{
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 5; ++k) acc += A[i * 5 + k] * B[k * 5 + j];
+            C[i * 5 + j] = acc;
+        }
+}
+
+static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
+                    const double *y, const double *z, const double *row_x, int32_t n_rows,
+                    const double *map, const oracle_fit_params *prm,
+                    double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto)
+{
+    double xs[512], ys[512], zs[512];
+    *ndfo = 2 * n - 5;
+    *chi2o = 0.0;
+    *xo = 0.0;
+    for (int i = 0; i < 5; ++i) po[i] = 0.0;
+    for (int i = 0; i < 15; ++i) co[i] = 0.0;
+    if (n < 3 || n > 512) { *sto = 1; return; }
+    for (int k = 0; k < n; ++k) {
+        int32_t r = row0 + k;
+        xs[k] = row_x[r];
+        ys[k] = y[hit[k]];
+        zs[k] = z[hit[k]];
+        if (map) {
+            ys[k] -= map[((size_t)sec * n_rows + r) * 2 + 0];
+            zs[k] -= map[((size_t)sec * n_rows + r) * 2 + 1];
+        }
+    }
+    /* start */
+    int a = n - 1, b = (n - 1) / 2, c = 0;
+    double bcx = xs[b] - xs[c], bcy = ys[b] - ys[c];
+    double abx = xs[a] - xs[b], aby = ys[a] - ys[b];
+    double acx = xs[a] - xs[c], acy = ys[a] - ys[c];
+    double lbc = sqrt(bcx * bcx + bcy * bcy);
+    double lab = sqrt(abx * abx + aby * aby);
+    double lac = sqrt(acx * acx + acy * acy);
+    double cross = bcx * aby - bcy * abx;
+    double prod = lbc * lab * lac;
+    double kap0 = 2.0 * cross / prod;
+    double ua = kap0 * lab / 2.0, uc = kap0 * lac / 2.0;
+    int32_t st = 0;
+    if (!(prod > 0.0) || !(fabs(ua) < 1.0) || !(fabs(uc) < 1.0)) st = 1;
+    double phiA = atan2(aby, abx) + asin(st ? 0.0 : ua);
+    double p[5], C[25];
+    p[0] = ys[a];
+    p[1] = zs[a];
+    p[2] = sin(phiA);
+    p[3] = (zs[a] - zs[c]) / (lac * g_of(uc));
+    p[4] = -kap0 / (C_LIGHT * prm->bz);
+    if (!st && (!(cos(phiA) > 0.0) || !(fabs(p[2]) < prm->max_sin))) st = 1;
+    for (int i = 0; i < 25; ++i) C[i] = 0.0;
+    C[0] = prm->sigma_y * prm->sigma_y;
+    C[6] = prm->sigma_z * prm->sigma_z;
+    C[12] = prm->var_sin0;
+    C[18] = prm->var_tgl0;
+    C[24] = prm->var_qpt0;
+    double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
+    double chi2 = 0.0;
+    double xcur = xs[a];
+    for (int k = n - 2; k >= 0 && !st; --k) {
+        double pp[5], F[25], FC[25], Ft[25], Cp[25];
+        double dx = xs[k] - xs[k + 1];
+        if (oracle_propagate(p, dx, prm->bz, prm->max_sin, pp, F)) { st = 2; break; }
+        mat5_mul(F, C, FC);
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j) Ft[i * 5 + j] = F[j * 5 + i];
+        mat5_mul(FC, Ft, Cp);
+        xcur = xs[k];
+        /* update with m = (ys[k], zs[k]), H = [I2 0] */
+        double r0 = ys[k] - pp[0], r1 = zs[k] - pp[1];
+        double S00 = Cp[0] + vy, S01 = Cp[1], S10 = Cp[5], S11 = Cp[6] + vz;
+        double det = S00 * S11 - S01 * S10;
+        if (!(det > 0.0)) { st = 3; break; }
+        double Si00 = S11 / det, Si01 = -S01 / det, Si10 = -S10 / det, Si11 = S00 / det;
+        double K[10];
+        for (int i = 0; i < 5; ++i) {
+            K[i * 2 + 0] = Cp[i * 5 + 0] * Si00 + Cp[i * 5 + 1] * Si10;
+            K[i * 2 + 1] = Cp[i * 5 + 0] * Si01 + Cp[i * 5 + 1] * Si11;
+        }
+        for (int i = 0; i < 5; ++i) p[i] = pp[i] + K[i * 2 + 0] * r0 + K[i * 2 + 1] * r1;
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j)
+                C[i * 5 + j] = Cp[i * 5 + j] - (K[i * 2 + 0] * Cp[0 * 5 + j] + K[i * 2 + 1] * Cp[1 * 5 + j]);
+        chi2 += r0 * (Si00 * r0 + Si01 * r1) + r1 * (Si10 * r0 + Si11 * r1);
+        int finite = isfinite(chi2);
+        for (int i = 0; i < 5; ++i) finite &= isfinite(p[i]);
+        if (!finite) { st = 3; break; }
+    }
+    *xo = xcur;
+    for (int i = 0; i < 5; ++i) po[i] = p[i];
+    /* packed lower triangle, row by row: (0,0) (1,0) (1,1) (2,0) ... */
+    int q = 0;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) co[q++] = C[i * 5 + j];
+    *chi2o = chi2;
+    *sto = st;
+}
+
+void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                const int32_t *sector, const int32_t *first_row,
+                const double *y, const double *z, const double *row_x, int32_t n_rows,
+                const double *map, const oracle_fit_params *prm,
+                double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status)
+{
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        fit_one(offsets[i + 1] - offsets[i], hits + offsets[i], sector[i], first_row[i],
+                y, z, row_x, n_rows, map, prm, &x_out[i], &par[(size_t)i * 5],
+                &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i]);
+    }
+}

@@ -1,0 +1,35 @@
+/* CPU oracle (test infrastructure only): declarations.  See tpc_oracle.c. */
+#ifndef TPC_ORACLE_H
+#define TPC_ORACLE_H
+#include <stdint.h>
+
+typedef struct oracle_fit_params {
+    double bz;          /* T */
+    double sigma_y;     /* cm */
+    double sigma_z;     /* cm */
+    double max_sin;     /* |sin phi| limit */
+    double var_sin0, var_tgl0, var_qpt0;   /* start covariance of s, t, w */
+} oracle_fit_params;
+
+void oracle_set_threads(int n);
+int oracle_max_threads(void);
+
+void oracle_neighbours(int32_t n_segments, int32_t n_rows, const int32_t *row_offsets,
+                       const float *y, const float *z, float win_y, float win_z,
+                       float cut_y, float cut_z, int32_t *up, int32_t *dn);
+
+int32_t oracle_ca_seed(int32_t n_segments, int32_t n_sectors, int32_t n_rows,
+                       const int32_t *row_offsets, const int32_t *up, const int32_t *dn,
+                       int32_t min_hits, int32_t cap_seeds, int32_t cap_hits,
+                       int32_t *n_seeds_out, int32_t *n_hits_out, int32_t *offsets,
+                       int32_t *hits, int32_t *frame, int32_t *sector, int32_t *first_row);
+
+int32_t oracle_propagate(const double *p, double dx, double bz, double max_sin,
+                         double *pout, double *F);
+
+void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                const int32_t *sector, const int32_t *first_row,
+                const double *y, const double *z, const double *row_x, int32_t n_rows,
+                const double *map, const oracle_fit_params *prm,
+                double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status);
+#endif

@@ -1,0 +1,426 @@
+"""Seeded synthetic TPC time frames: helix crossings of pad-row planes.
+
+This module only produces inputs (cluster positions per frame, sector and pad
+row, plus the truth behind them).  It contains none of the reconstruction
+arithmetic: no neighbour search, no chaining, no track fit.  Both the CPU
+oracle and the GPU library consume what it returns.
+
+Geometry (a proposal; the paper fixes no detector numbers beyond the drift
+volume being read out continuously in time frames, Sec. 4):
+
+* ``n_sectors`` trapezoidal sectors; sector ``s`` has centre angle
+  ``alpha_s = (s mod 18 + 1/2) * 20 deg`` and reads the A side (z > 0) for
+  ``s < 18`` and the C side (z < 0) otherwise.  A single-sector geometry has
+  ``alpha = 0`` and accepts both z signs.
+* ``R`` pad rows per sector are planes at sector-local ``x = row_x[r]``,
+  ``row_x[r] = fl32(85 + r * 160 / (R - 1))`` cm; a row is ``x * tan 10 deg``
+  wide on either side of the centre line; the drift length is 250 cm.
+* A track is a helix from the origin in a solenoidal field ``B_z``; its
+  signed curvature (counter-clockwise positive) is ``-c * B_z * q / pT``.
+  Crossings are exact circle/plane intersections in global coordinates, in
+  float64, ordered by path length.
+
+Randomness: one ``numpy.random.Generator(PCG64(seed))`` per call, drawn in a
+fixed order, so a (config, seed) pair always yields the same frames.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+C_LIGHT = 0.00299792458          # cm^-1 GeV T^-1
+TAN10 = math.tan(math.radians(10.0))
+DRIFT_LENGTH = 250.0             # cm
+R_OUTER = 250.0                  # cm, transverse radius at which a track leaves the gas volume
+V_DRIFT = 2.5                    # cm / us (apparent z shift per us of collision time offset)
+
+
+def make_row_x(n_rows: int = 152, x_first: float = 85.0, x_last: float = 245.0) -> np.ndarray:
+    """Pad-row plane positions (float32), uniform pitch."""
+    r = np.arange(n_rows, dtype=np.float64)
+    return (x_first + r * (x_last - x_first) / (n_rows - 1)).astype(np.float32)
+
+
+def sector_alpha(n_sectors: int) -> np.ndarray:
+    if n_sectors == 1:
+        return np.zeros(1)
+    s = np.arange(n_sectors)
+    return np.radians((s % 18 + 0.5) * 20.0)
+
+
+def sector_side(n_sectors: int) -> np.ndarray:
+    """+1 for A side (z>0), -1 for C side, 0 for a single sector reading both."""
+    if n_sectors == 1:
+        return np.zeros(1, dtype=np.int8)
+    s = np.arange(n_sectors)
+    return np.where(s < 18, 1, -1).astype(np.int8)
+
+
+@dataclasses.dataclass
+class Frames:
+    """Clusters grouped per (frame, sector, row), global id order = storage order."""
+    n_frames: int
+    n_sectors: int
+    n_rows: int
+    row_x: np.ndarray            # float32 [R]
+    row_offsets: np.ndarray      # int32 [F*S*R + 1]
+    y: np.ndarray                # float32 [N]
+    z: np.ndarray                # float32 [N]
+    bz: float = 0.5
+    sigma_y: float = 0.05
+    sigma_z: float = 0.06
+    # truth (optional)
+    track_of: Optional[np.ndarray] = None     # int32 [N], -1 for noise
+    y_true: Optional[np.ndarray] = None       # float64 [N] (local y before smearing, after shift/distortion)
+    z_true: Optional[np.ndarray] = None
+    s_true: Optional[np.ndarray] = None       # sin(phi) in the +x orientation
+    t_true: Optional[np.ndarray] = None       # tan(lambda) in the +x orientation
+    w_true: Optional[np.ndarray] = None       # q/pT in the +x orientation
+    distortion: Optional[np.ndarray] = None   # float32 [S, R, 2] (dy, dz) added to the clusters
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_clusters(self) -> int:
+        return int(self.y.shape[0])
+
+    def row_slice(self, f: int, s: int, r: int) -> slice:
+        i = (f * self.n_sectors + s) * self.n_rows + r
+        return slice(int(self.row_offsets[i]), int(self.row_offsets[i + 1]))
+
+    def frame_view(self, f: int) -> "Frames":
+        """Frame ``f`` alone, with ids rebased to 0 (truth arrays sliced alike)."""
+        SR = self.n_sectors * self.n_rows
+        off = self.row_offsets[f * SR:(f + 1) * SR + 1]
+        a, b = int(off[0]), int(off[-1])
+        sl = slice(a, b)
+        def cut(v):
+            return None if v is None else v[sl]
+        return Frames(1, self.n_sectors, self.n_rows, self.row_x, (off - a).astype(np.int32),
+                      self.y[sl], self.z[sl], self.bz, self.sigma_y, self.sigma_z,
+                      cut(self.track_of), cut(self.y_true), cut(self.z_true), cut(self.s_true),
+                      cut(self.t_true), cut(self.w_true), self.distortion, dict(self.meta))
+
+
+# ----------------------------------------------------------------------------
+# helix crossings
+
+@dataclasses.dataclass
+class Tracks:
+    q: np.ndarray        # +-1
+    inv_pt: np.ndarray   # 1/pT [GeV^-1] > 0
+    phi0: np.ndarray     # direction at the origin (global)
+    tgl: np.ndarray      # tan(lambda)
+    nmax: np.ndarray     # crossings kept (truncation), large = all
+    frame: np.ndarray    # frame index
+    t0: np.ndarray       # collision time offset [us]
+
+    def __len__(self):
+        return int(self.q.shape[0])
+
+
+def _crossings(tr: Tracks, row_x: np.ndarray, n_sectors: int, bz: float, max_turns: int,
+               chunk: int = 4096):
+    """All kept crossings of every track with every row plane, as flat arrays.
+
+    Returns dict of arrays: track, sector, row, arc, y, z, s, t, w (truth in the
+    +x orientation) ordered by (track, arc).
+    """
+    R = row_x.shape[0]
+    xr = row_x.astype(np.float64)
+    alpha = sector_alpha(n_sectors)
+    side = sector_side(n_sectors)
+    out = {k: [] for k in ("track", "sector", "row", "arc", "y", "z", "s", "t", "w")}
+    for c0 in range(0, len(tr), chunk):
+        c1 = min(len(tr), c0 + chunk)
+        idx = np.arange(c0, c1)
+        q = tr.q[idx].astype(np.float64)
+        kap = -C_LIGHT * bz * q * tr.inv_pt[idx]          # signed curvature, ccw > 0
+        Rc = 1.0 / np.abs(kap)
+        ph0 = tr.phi0[idx]
+        tgl = tr.tgl[idx]
+        wtr = q * tr.inv_pt[idx]                           # q/pT
+        cx = -np.sin(ph0) / kap                            # centre = origin + n / kappa, n = left normal
+        cy = np.cos(ph0) / kap
+        th0 = np.arctan2(-cy, -cx)
+        looper = 2.0 * Rc < R_OUTER
+        s_exit = np.where(looper, np.inf,
+                          2.0 * np.arcsin(np.minimum(1.0, R_OUTER * np.abs(kap) / 2.0)) / np.abs(kap))
+        zside = np.sign(tgl)
+        # candidate sectors: global polar angle of the track at the radii each row plane spans
+        if n_sectors == 1:
+            pair_t = np.arange(len(idx))
+            pair_s = np.zeros(len(idx), dtype=np.int64)
+        else:
+            # the polar angle of a branch is monotone in radius, so the sectors a
+            # plane segment [x, x / cos 10deg] can be crossed in are those of its ends
+            c10 = math.cos(math.radians(10.0))
+            ak = np.abs(kap)[:, None]
+            ua = ak * xr[None, :] / 2.0                                          # [n, R]
+            ub = np.minimum(ak * xr[None, :] / (2.0 * c10), 1.0)
+            ok = ua <= 1.0
+            sg = np.sign(kap)[:, None]
+            mask = np.zeros((len(idx), 18), dtype=bool)
+            for uu in (ua, ub):
+                a1 = np.arcsin(np.minimum(uu, 1.0))
+                for psi, okb in ((ph0[:, None] + sg * a1, ok),
+                                 (ph0[:, None] + sg * (math.pi - a1), ok & looper[:, None])):
+                    sec18 = (np.floor(np.mod(psi, 2 * math.pi) / math.radians(20.0)).astype(np.int64)) % 18
+                    rows_i, cols_i = np.nonzero(okb)
+                    mask[rows_i, sec18[rows_i, cols_i]] = True
+            pair_t, s18 = np.nonzero(mask)
+            pair_s = np.where(zside[pair_t] >= 0, s18, s18 + 18)
+        if pair_t.size == 0:
+            continue
+        al = alpha[pair_s]
+        ux, uy = np.cos(al), np.sin(al)
+        vx, vy = -uy, ux
+        pcx, pcy = cx[pair_t], cy[pair_t]
+        d = (ux * pcx + uy * pcy)[:, None] - xr[None, :]                  # [P, R]
+        h2 = Rc[pair_t][:, None] ** 2 - d ** 2
+        hval = np.sqrt(np.maximum(h2, 0.0))
+        yc = (vx * pcx + vy * pcy)[:, None]
+        for sgn in (1.0, -1.0):
+            yl = yc + sgn * hval
+            keep = (h2 >= 0.0) & (np.abs(yl) <= xr[None, :] * TAN10)
+            if sgn < 0:
+                keep &= h2 > 0.0            # tangent point counted once
+            pi_, ri_ = np.nonzero(keep)
+            if pi_.size == 0:
+                continue
+            ti = pair_t[pi_]
+            dk, hk = d[pi_, ri_], hval[pi_, ri_]
+            px = -dk * ux[pi_] + sgn * hk * vx[pi_]          # point minus centre
+            py = -dk * uy[pi_] + sgn * hk * vy[pi_]
+            th = np.arctan2(py, px)
+            kk = kap[ti]
+            dth = np.where(kk > 0, th - th0[ti], th0[ti] - th)
+            arc0 = Rc[ti] * np.mod(dth, 2 * math.pi)
+            ylv = yl[pi_, ri_]
+            for turn in range(max_turns):
+                arc = arc0 + turn * 2 * math.pi * Rc[ti]
+                zz = tgl[ti] * arc
+                sec = pair_s[pi_]
+                ok = (arc <= s_exit[ti]) & (np.abs(zz) <= DRIFT_LENGTH)
+                if n_sectors > 1:
+                    ok &= np.where(side[sec] > 0, zz >= 0, zz < 0)
+                if turn > 0:
+                    ok &= looper[ti]
+                if not ok.any():
+                    break
+                phi_loc = ph0[ti] + kk * arc - al[pi_]
+                cphi = np.cos(phi_loc)
+                fwd = cphi >= 0
+                sfit = np.where(fwd, np.sin(phi_loc), -np.sin(phi_loc))
+                tfit = np.where(fwd, tgl[ti], -tgl[ti])
+                wfit = np.where(fwd, wtr[ti], -wtr[ti])
+                sel = np.nonzero(ok)[0]
+                out["track"].append(ti[sel] + c0)
+                out["sector"].append(sec[sel])
+                out["row"].append(ri_[sel])
+                out["arc"].append(arc[sel])
+                out["y"].append(ylv[sel])
+                out["z"].append(zz[sel])
+                out["s"].append(sfit[sel])
+                out["t"].append(tfit[sel])
+                out["w"].append(wfit[sel])
+    res = {k: (np.concatenate(v) if v else np.zeros(0)) for k, v in out.items()}
+    for k in ("track", "sector", "row"):
+        res[k] = res[k].astype(np.int64)
+    order = np.lexsort((res["arc"], res["track"]))
+    res = {k: v[order] for k, v in res.items()}
+    # truncation: keep the first nmax crossings of each track along its path
+    if res["track"].size:
+        t = res["track"]
+        start = np.r_[0, np.nonzero(np.diff(t))[0] + 1]
+        rank = np.arange(t.size) - np.repeat(start, np.diff(np.r_[start, t.size]))
+        keep = rank < tr.nmax[t]
+        res = {k: v[keep] for k, v in res.items()}
+    return res
+
+
+def _crossings_job(args):
+    tr, row_x, n_sectors, bz, max_turns, base = args
+    res = _crossings(tr, row_x, n_sectors, bz, max_turns)
+    res["track"] = res["track"] + base
+    return res
+
+
+def _crossings_parallel(tr: Tracks, row_x, n_sectors, bz, max_turns, workers=None):
+    """Same result as ``_crossings``; large track sets are split over processes."""
+    import os
+    n = len(tr)
+    if workers is None:
+        workers = min(16, len(os.sched_getaffinity(0)))
+    if n < 20000 or workers <= 1:
+        return _crossings(tr, row_x, n_sectors, bz, max_turns)
+    import multiprocessing as mp
+    bounds = np.linspace(0, n, workers * 4 + 1).astype(int)
+    jobs = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        sub = Tracks(*[getattr(tr, f.name)[a:b] for f in dataclasses.fields(Tracks)])
+        jobs.append((sub, row_x, n_sectors, bz, max_turns, a))
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_crossings_job, jobs)
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+
+
+def _draw_tracks(rng, n, phi_range, looper_frac, trunc_frac, n_rows, frame=0, t0=None):
+    q = np.where(rng.random(n) < 0.5, -1, 1).astype(np.int8)
+    inv_pt = rng.uniform(0.2, 5.0, n)
+    if looper_frac > 0:
+        lo = rng.random(n) < looper_frac
+        inv_pt = np.where(lo, rng.uniform(1 / 0.3, 1 / 0.07, n), inv_pt)
+    phi0 = rng.uniform(phi_range[0], phi_range[1], n)
+    tgl = rng.uniform(-1.0, 1.0, n)
+    nmax = np.full(n, 1 << 30, dtype=np.int64)
+    if trunc_frac > 0:
+        tr = rng.random(n) < trunc_frac
+        nmax = np.where(tr, rng.integers(5, n_rows + 1, n), nmax)
+    fr = np.full(n, frame, dtype=np.int32)
+    tt = np.zeros(n) if t0 is None else t0
+    return Tracks(q, inv_pt, phi0, tgl, nmax, fr, tt)
+
+
+def _concat_tracks(parts: Sequence[Tracks]) -> Tracks:
+    return Tracks(*[np.concatenate([getattr(p, f.name) for p in parts]) for f in dataclasses.fields(Tracks)])
+
+
+def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Sequence[int] = (1000,),
+                seed: int = 0, phi_range=(0.0, 2 * math.pi), looper_frac: float = 0.0,
+                trunc_frac: float = 0.0, noise_frac: float = 0.0, n_collisions: int = 1,
+                drift_window_us: float = 0.0, distortion_amp: float = 0.0, distortion_period: float = 38.0,
+                bz: float = 0.5, sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True,
+                shuffle: bool = True, max_turns: int = 3, keep_truth: bool = False,
+                tracks: Optional[Tracks] = None) -> Frames:
+    """General generator; ``make_config`` fixes the parameters of the five workloads."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    row_x = make_row_x(n_rows)
+    F = len(tracks_per_frame)
+    if tracks is None:
+        parts = []
+        for f, nt in enumerate(tracks_per_frame):
+            if n_collisions > 1:
+                per = np.full(n_collisions, nt // n_collisions)
+                per[: nt - per.sum()] += 1
+                tcol = rng.uniform(0.0, drift_window_us, n_collisions)
+                t0 = np.repeat(tcol, per)
+            else:
+                t0 = np.zeros(nt)
+            parts.append(_draw_tracks(rng, nt, phi_range, looper_frac, trunc_frac, n_rows, f, t0))
+        tracks = _concat_tracks(parts)
+    cr = _crossings_parallel(tracks, row_x, n_sectors, bz, max_turns)
+    n_sig = cr["track"].size
+    y_true = cr["y"].copy()
+    z_true = cr["z"].copy()
+    frame = tracks.frame[cr["track"]].astype(np.int64)
+    # drift shift: apparent z moves away from the membrane by v_drift * t0
+    shift = V_DRIFT * tracks.t0[cr["track"]]
+    zsgn = np.sign(z_true)
+    zsgn[zsgn == 0] = 1.0
+    z_true = z_true + zsgn * shift
+    dist = None
+    if distortion_amp > 0:
+        amp = rng.uniform(0.0, distortion_amp, (n_sectors, 2))
+        ph = rng.uniform(0.0, 2 * math.pi, (n_sectors, 2))
+        r = np.arange(n_rows)
+        dist = (amp[:, None, :] * np.sin(2 * math.pi * r[None, :, None] / distortion_period + ph[:, None, :]))
+        dist = dist.astype(np.float32)
+        y_true = y_true + dist[cr["sector"], cr["row"], 0].astype(np.float64)
+        z_true = z_true + dist[cr["sector"], cr["row"], 1].astype(np.float64)
+    if smear:
+        ym = y_true + rng.normal(0.0, sigma_y, n_sig)
+        zm = z_true + rng.normal(0.0, sigma_z, n_sig)
+    else:
+        ym, zm = y_true.copy(), z_true.copy()
+    sec = cr["sector"]
+    row = cr["row"]
+    tid = cr["track"].astype(np.int64)
+    # noise: a fraction of the total cluster count, uniform over rows and row area
+    n_noise = int(round(noise_frac / (1.0 - noise_frac) * n_sig)) if noise_frac > 0 else 0
+    if n_noise:
+        nf = rng.integers(0, F, n_noise)
+        ns = rng.integers(0, n_sectors, n_noise)
+        nr = rng.integers(0, n_rows, n_noise)
+        half = row_x[nr].astype(np.float64) * TAN10
+        ny = rng.uniform(-1.0, 1.0, n_noise) * half
+        zmax = DRIFT_LENGTH + (V_DRIFT * drift_window_us if n_collisions > 1 else 0.0)
+        sd = sector_side(n_sectors)[ns]
+        zr = rng.uniform(0.0, zmax, n_noise)
+        nz = np.where(sd > 0, zr, np.where(sd < 0, -zr, rng.uniform(-zmax, zmax, n_noise)))
+        frame = np.concatenate([frame, nf])
+        sec = np.concatenate([sec, ns])
+        row = np.concatenate([row, nr])
+        tid = np.concatenate([tid, np.full(n_noise, -1)])
+        ym = np.concatenate([ym, ny])
+        zm = np.concatenate([zm, nz])
+        nanv = np.full(n_noise, np.nan)
+        y_true = np.concatenate([y_true, nanv])
+        z_true = np.concatenate([z_true, nanv])
+        st, tt, wt = (np.concatenate([cr[k], nanv]) for k in ("s", "t", "w"))
+    else:
+        st, tt, wt = cr["s"], cr["t"], cr["w"]
+    key = (frame * n_sectors + sec) * n_rows + row
+    tieb = rng.random(key.size) if shuffle else np.arange(key.size, dtype=np.float64)
+    order = np.lexsort((tieb, key))
+    NR = F * n_sectors * n_rows
+    counts = np.bincount(key, minlength=NR)
+    offs = np.zeros(NR + 1, dtype=np.int64)
+    np.cumsum(counts, out=offs[1:])
+    if offs[-1] >= 2 ** 31:
+        raise ValueError("too many clusters for int32 ids")
+    fr = Frames(F, n_sectors, n_rows, row_x, offs.astype(np.int32),
+                ym[order].astype(np.float32), zm[order].astype(np.float32), bz, sigma_y, sigma_z)
+    fr.track_of = tid[order].astype(np.int32)
+    if keep_truth:
+        fr.y_true, fr.z_true = y_true[order], z_true[order]
+        fr.s_true, fr.t_true, fr.w_true = st[order], tt[order], wt[order]
+    fr.distortion = dist
+    fr.meta = dict(n_tracks=len(tracks), n_signal=n_sig, n_noise=n_noise, seed=seed)
+    fr.meta["tracks"] = tracks
+    return fr
+
+
+CONFIG_NAMES = (
+    "single-sector-200",
+    "full-tpc-event-1e4",
+    "continuous-tf-50x1e4",
+    "batched-64-uneven",
+    "differentiable-1e5",
+)
+
+
+def config_params(k: int, scale: float = 1.0) -> dict:
+    """Generator parameters of the five workloads; ``scale`` shrinks track counts."""
+    def n(v):
+        return max(1, int(round(v * scale)))
+    if k == 0:
+        return dict(n_sectors=1, tracks_per_frame=(n(200),), seed=0,
+                    phi_range=(-math.radians(10.0), math.radians(10.0)), noise_frac=0.05)
+    if k == 1:
+        return dict(n_sectors=36, tracks_per_frame=(n(10000),), seed=1, looper_frac=0.08,
+                    trunc_frac=0.5, noise_frac=0.10)
+    if k == 2:
+        return dict(n_sectors=36, tracks_per_frame=(n(500000),), seed=2, looper_frac=0.08,
+                    trunc_frac=0.5, noise_frac=0.10, n_collisions=50, drift_window_us=100.0)
+    if k == 3:
+        rng = np.random.Generator(np.random.PCG64(1003))
+        counts = np.floor(np.exp(rng.uniform(math.log(100), math.log(20000), 64))).astype(int)
+        return dict(n_sectors=36, tracks_per_frame=tuple(n(c) for c in counts), seed=3,
+                    looper_frac=0.08, trunc_frac=0.5, noise_frac=0.10)
+    if k == 4:
+        return dict(n_sectors=36, tracks_per_frame=(n(100000),), seed=4, looper_frac=0.08,
+                    trunc_frac=0.5, noise_frac=0.10, distortion_amp=0.5)
+    raise ValueError(k)
+
+
+def make_config(k: int, scale: float = 1.0, keep_truth: bool = False, **over) -> Frames:
+    p = config_params(k, scale)
+    p.update(over)
+    fr = make_frames(keep_truth=keep_truth, **p)
+    fr.meta["config"] = k
+    fr.meta["name"] = CONFIG_NAMES[k]
+    fr.meta["scale"] = scale
+    return fr
