@@ -1,0 +1,171 @@
+/*
+ * tpcreco -- TPC track reconstruction on one MI355X (gfx950): neighbour
+ * finding between adjacent pad rows, cellular-automaton seeding and a Kalman
+ * helix fit, plus the adjoint of the summed fit chi2 with respect to a
+ * per-(sector, pad row) cluster correction map.
+ *
+ * The paper this library follows (arXiv 2412.13755) names TPC track
+ * reconstruction as the computation that fully loads the GPUs of the online
+ * farm (Sec. 4.2, Sec. 5), processed one continuous-readout time frame at a
+ * time with the whole frame resident in GPU memory and memory reused across
+ * processing steps (Sec. 4).  It does not describe the algorithm; the
+ * operations below are this library's reading, stated in each comment.
+ *
+ * Conventions for every call
+ *   - Units: cm, GeV/c, tesla.  Coordinates are sector-local: x is the pad-row
+ *     plane position, y runs along the pad row, z is the drift coordinate.
+ *   - Clusters are grouped per (frame, sector, pad row): segment
+ *     i = (frame * n_sectors + sector) * n_rows + row owns global cluster ids
+ *     [row_offsets[i], row_offsets[i+1]).  Order within a row is arbitrary.
+ *   - Every pointer inside tpc_frames, tpc_seeds and tpc_tracks and every
+ *     array argument is a DEVICE pointer owned by the caller, unless the
+ *     comment says "host".  The library never frees or retains them.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream) and allocate nothing: scratch memory is the caller's workspace
+ *     of at least tpc_workspace_bytes() bytes, device memory, any alignment of
+ *     256 bytes or more.  Nothing is synchronised unless stated.
+ *   - Errors found on the host (bad arguments, short workspace) are returned
+ *     before anything is enqueued.  Errors found on the device (capacity
+ *     overflow) are written to the caller's device status word.
+ *     tpc_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef TPCRECO_H
+#define TPCRECO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tpc_status;
+#define TPC_OK               0
+#define TPC_ERR_ARG         -1   /* invalid argument (null pointer, bad size, bad config) */
+#define TPC_ERR_CAPACITY    -2   /* device-detected: seed or hit capacity exceeded */
+#define TPC_ERR_HIP         -3   /* a HIP runtime call failed */
+#define TPC_ERR_UNSUPPORTED -4   /* current device is not gfx950 */
+#define TPC_ERR_WORKSPACE   -5   /* workspace missing or smaller than tpc_workspace_bytes() */
+
+/* Per-track fit status (tpc_tracks.status). */
+#define TPC_FIT_OK           0
+#define TPC_FIT_INIT_FAIL    1   /* three-point start degenerate or |sin phi| >= max_sin */
+#define TPC_FIT_SIN_FAIL     2   /* propagation reached |sin phi| >= max_sin */
+#define TPC_FIT_NUM_FAIL     3   /* singular residual covariance or non-finite state */
+
+/* Reconstruction constants.  Copied at tpc_create(); the context is immutable. */
+typedef struct tpc_config {
+    int32_t n_sectors;        /* sectors per frame, >= 1 */
+    int32_t n_rows;           /* pad rows per sector, 3..256 */
+    const float *row_x;       /* HOST [n_rows]: plane x of each row, strictly increasing */
+    float bz;                 /* solenoid field (T), |bz| >= 1e-6 */
+    float sigma_y, sigma_z;   /* cluster resolution (cm), > 0 */
+    float win_y, win_z;       /* neighbour position windows (cm), > 0 */
+    float cut_y, cut_z;       /* neighbour second-difference cuts (cm), > 0 */
+    int32_t min_hits;         /* shortest seed kept, >= 3 */
+    float max_sin;            /* |sin phi| limit of the fit, in (0, 1) */
+    float var_sin0, var_tgl0, var_qpt0;   /* start covariance of sin phi, tan lambda, q/pT */
+    int32_t ckpt_rows;        /* fit-state checkpoint spacing for the adjoint, 1..64 */
+} tpc_config;
+
+/* Clusters of n_frames stacked time frames. */
+typedef struct tpc_frames {
+    int32_t n_frames;              /* >= 1 */
+    int32_t n_clusters;            /* N = row_offsets[n_frames*n_sectors*n_rows], < 2^31 */
+    const int32_t *row_offsets;    /* [n_frames*n_sectors*n_rows + 1], non-decreasing, [0] = 0 */
+    const float *y, *z;            /* [N] single precision */
+} tpc_frames;
+
+/* Seeds in CSR form, ordered by the global id of their first (lowest-row) hit. */
+typedef struct tpc_seeds {
+    int32_t cap_seeds, cap_hits;   /* capacities of the arrays below */
+    int32_t *n_seeds, *n_hits;     /* device scalars: required sizes (also on overflow) */
+    int32_t *offsets;              /* [cap_seeds + 1] hits of seed i: [offsets[i], offsets[i+1]) */
+    int32_t *hits;                 /* [cap_hits] global cluster ids, ascending pad row */
+    int32_t *frame, *sector, *first_row;   /* [cap_seeds] */
+} tpc_seeds;
+
+/* Fitted tracks, one per seed (index = seed index). */
+typedef struct tpc_tracks {
+    float *x;                  /* [cap_seeds] plane x of the innermost hit */
+    float *par;                /* [cap_seeds][5] y, z, sin phi, tan lambda, q/pT at x */
+    float *cov;                /* [cap_seeds][15] covariance, packed lower triangle row by row */
+    float *chi2;               /* [cap_seeds] */
+    int32_t *ndf;              /* [cap_seeds] 2 n - 5 */
+    int32_t *status;           /* [cap_seeds] TPC_FIT_* */
+} tpc_tracks;
+
+typedef struct tpc_context tpc_context;
+
+/* Validates `cfg`, checks that the current HIP device is gfx950 and uploads
+ * the row table (the only allocation the library makes).  On success *out
+ * owns a context for the current device; free it with tpc_destroy(). */
+tpc_status tpc_create(const tpc_config *cfg, tpc_context **out);
+void tpc_destroy(tpc_context *ctx);
+
+/* Stage bits for tpc_workspace_bytes(). */
+#define TPC_STAGE_NEIGHBOURS  1
+#define TPC_STAGE_SEED        2
+#define TPC_STAGE_FIT         4
+#define TPC_STAGE_ADJOINT     8
+#define TPC_STAGE_ALL        15
+
+/* Workspace bytes needed by the stages in `stage_mask` for frames of this
+ * shape (only n_frames and n_clusters are read; host call, no device work).
+ * One workspace of the returned size serves every listed stage. */
+tpc_status tpc_workspace_bytes(const tpc_context *ctx, const tpc_frames *frames,
+                               int32_t stage_mask, size_t *bytes);
+
+/* Neighbour finding.  For each cluster h of row r (1 <= r <= n_rows-2) of each
+ * (frame, sector), the pair (d of row r-1, u of row r+1) with
+ *   |y_u - y_h| <= win_y, |z_u - z_h| <= win_z, |y_h - y_d| <= win_y,
+ *   |z_h - z_d| <= win_z, |dy| <= cut_y, |dz| <= cut_z,
+ *   dy = (y_u - y_h) - (y_h - y_d), dz likewise,
+ * that minimises q = dy*dy + dz*dz; ties go to the smaller u id, then the
+ * smaller d id.  Every operation is one IEEE single-precision rounding (no
+ * fused multiply-add), so the result is exactly defined; non-finite
+ * coordinates never link.  Writes up[h], dn[h] (global ids, -1 for none) for
+ * every cluster, -1 in rows 0 and n_rows-1.
+ * up, dn: [N] device int32, written.  ws: TPC_STAGE_NEIGHBOURS workspace. */
+tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *frames,
+                          int32_t *up, int32_t *dn, void *ws, size_t ws_bytes, void *stream);
+
+/* Cellular-automaton seeding from the neighbour links.
+ *   links   h -> up[h] is kept if dn[up[h]] == h (and symmetrically);
+ *   chains  maximal runs of kept links, bottom b to top t, m >= 2 clusters;
+ *   claims  a chain with m >= min_hits-2 claims dn[b] and up[t] when these are
+ *           in no chain; each claimed cluster goes to the smallest (-m, b);
+ *   seeds   [dn[b] if won] + chain + [up[t] if won], kept with >= min_hits
+ *           clusters, ordered by the global id of their first cluster.
+ * up, dn: [N] from tpc_neighbours.  seeds: caller arrays and capacities.
+ * dev_status: device int32, set to TPC_OK or TPC_ERR_CAPACITY (then
+ * *n_seeds/*n_hits hold the required sizes and the arrays hold a prefix).
+ * ws: TPC_STAGE_SEED workspace. */
+tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
+                       const int32_t *up, const int32_t *dn, tpc_seeds *seeds,
+                       int32_t *dev_status, void *ws, size_t ws_bytes, void *stream);
+
+/* Kalman helix fit of every seed (count read on the device from *n_seeds,
+ * clamped to cap_seeds).  State (y, z, sin phi, tan lambda, q/pT) on the
+ * pad-row planes, curvature -0.00299792458 * bz * q/pT per cm; start: exact
+ * circle through the outermost, middle and innermost hits at the outermost
+ * hit with covariance diag(sigma_y^2, sigma_z^2, var_sin0, var_tgl0,
+ * var_qpt0); then for each hit inwards an exact helix step with its analytic
+ * Jacobian (no process noise) and a Kalman update with the hit.  chi2 is the
+ * sum of the predicted-residual chi2, ndf = 2n - 5.  Arithmetic is single
+ * precision.  map: optional [n_sectors][n_rows][2] (dy, dz) subtracted from
+ * every cluster of that (sector, row) before fitting (NULL = none).
+ * ws: TPC_STAGE_FIT workspace. */
+tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *frames,
+                          const tpc_seeds *seeds, const float *map, tpc_tracks *tracks,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Status code name. */
+const char *tpc_status_string(tpc_status s);
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char *tpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

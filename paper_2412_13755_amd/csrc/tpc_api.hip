@@ -1,0 +1,201 @@
+// C-ABI of libtpcreco: argument validation, workspace sizing and launches.
+// Every check that can be made on the host is made before anything is
+// enqueued; nothing here allocates except tpc_create (the row table).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "tpc_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512];
+
+tpc_status fail(tpc_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+tpc_status hip_fail(hipError_t e, const char *what) {
+    return fail(TPC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t n_segments(const tpc_context *ctx, const tpc_frames *fr) {
+    return (int64_t)fr->n_frames * ctx->cfg.n_sectors * ctx->cfg.n_rows;
+}
+
+tpc_status check_frames(const tpc_context *ctx, const tpc_frames *fr) {
+    if (!ctx) return fail(TPC_ERR_ARG, "null context");
+    if (!fr) return fail(TPC_ERR_ARG, "null frames");
+    if (fr->n_frames < 1) return fail(TPC_ERR_ARG, "n_frames < 1");
+    if (fr->n_clusters < 0) return fail(TPC_ERR_ARG, "n_clusters < 0");
+    const int64_t NR = n_segments(ctx, fr);
+    if (NR + (int64_t)fr->n_clusters + 1 >= ((int64_t)1 << 31))
+        return fail(TPC_ERR_ARG, "clusters plus segments must stay below 2^31");
+    if (NR > (int64_t)0x7fffffff) return fail(TPC_ERR_ARG, "too many segments");
+    if (!fr->row_offsets) return fail(TPC_ERR_ARG, "null row_offsets");
+    if (fr->n_clusters > 0 && (!fr->y || !fr->z)) return fail(TPC_ERR_ARG, "null y or z");
+    return TPC_OK;
+}
+
+tpc_status check_ws(void *ws, size_t have, size_t need) {
+    if (need == 0) return TPC_OK;
+    if (!ws) return fail(TPC_ERR_WORKSPACE, "workspace is null, %zu bytes needed", need);
+    if (((uintptr_t)ws & 255) != 0) return fail(TPC_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (have < need) return fail(TPC_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", have, need);
+    return TPC_OK;
+}
+
+size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
+    const int64_t N = fr->n_clusters, NR = n_segments(ctx, fr);
+    size_t b = 0;
+    if (mask & TPC_STAGE_NEIGHBOURS) b = std::max(b, nb_ws_layout(nullptr, N, NR, nullptr));
+    if (mask & TPC_STAGE_SEED) b = std::max(b, ca_ws_layout(nullptr, N, NR, nullptr));
+    if (mask & TPC_STAGE_FIT) b = std::max(b, fit_ws_layout(nullptr, N));
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tpc_status_string(tpc_status s) {
+    switch (s) {
+        case TPC_OK: return "TPC_OK";
+        case TPC_ERR_ARG: return "TPC_ERR_ARG";
+        case TPC_ERR_CAPACITY: return "TPC_ERR_CAPACITY";
+        case TPC_ERR_HIP: return "TPC_ERR_HIP";
+        case TPC_ERR_UNSUPPORTED: return "TPC_ERR_UNSUPPORTED";
+        case TPC_ERR_WORKSPACE: return "TPC_ERR_WORKSPACE";
+        default: return "TPC_ERR_UNKNOWN";
+    }
+}
+
+const char *tpc_last_error(void) { return g_err; }
+
+tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
+    g_err[0] = 0;
+    if (!out) return fail(TPC_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    if (!cfg) return fail(TPC_ERR_ARG, "null config");
+    const tpc_config &c = *cfg;
+    if (c.n_sectors < 1) return fail(TPC_ERR_ARG, "n_sectors < 1");
+    if (c.n_rows < 3 || c.n_rows > TPC_MAX_ROWS) return fail(TPC_ERR_ARG, "n_rows outside 3..%d", TPC_MAX_ROWS);
+    if (!c.row_x) return fail(TPC_ERR_ARG, "null row_x");
+    for (int r = 0; r < c.n_rows; ++r) {
+        if (!isfinite(c.row_x[r])) return fail(TPC_ERR_ARG, "row_x[%d] not finite", r);
+        if (r > 0 && !(c.row_x[r] > c.row_x[r - 1])) return fail(TPC_ERR_ARG, "row_x not increasing at %d", r);
+    }
+    if (!(fabsf(c.bz) >= 1e-6f) || !isfinite(c.bz)) return fail(TPC_ERR_ARG, "|bz| < 1e-6");
+    if (!(c.sigma_y > 0.f) || !(c.sigma_z > 0.f)) return fail(TPC_ERR_ARG, "sigma_y, sigma_z must be > 0");
+    if (!(c.win_y > 0.f) || !(c.win_z > 0.f) || !isfinite(c.win_y) || !isfinite(c.win_z))
+        return fail(TPC_ERR_ARG, "windows must be finite and > 0");
+    if (!(c.cut_y > 0.f) || !(c.cut_z > 0.f)) return fail(TPC_ERR_ARG, "cuts must be > 0");
+    if (c.min_hits < 3) return fail(TPC_ERR_ARG, "min_hits < 3");
+    if (!(c.max_sin > 0.f && c.max_sin < 1.f)) return fail(TPC_ERR_ARG, "max_sin outside (0, 1)");
+    if (!(c.var_sin0 > 0.f) || !(c.var_tgl0 > 0.f) || !(c.var_qpt0 > 0.f))
+        return fail(TPC_ERR_ARG, "start variances must be > 0");
+    if (c.ckpt_rows < 1 || c.ckpt_rows > 64) return fail(TPC_ERR_ARG, "ckpt_rows outside 1..64");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(TPC_ERR_UNSUPPORTED, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    tpc_context *ctx = new (std::nothrow) tpc_context;
+    if (!ctx) return fail(TPC_ERR_ARG, "out of host memory");
+    ctx->cfg = c;
+    memcpy(ctx->row_x_host, c.row_x, sizeof(float) * c.n_rows);
+    ctx->cfg.row_x = ctx->row_x_host;
+    ctx->device = dev;
+    ctx->d_row_x = nullptr;
+    e = hipMalloc(&ctx->d_row_x, sizeof(float) * TPC_MAX_ROWS);
+    if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipMalloc(row table)"); }
+    e = hipMemcpy(ctx->d_row_x, ctx->row_x_host, sizeof(float) * c.n_rows, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(ctx->d_row_x); delete ctx; return hip_fail(e, "hipMemcpy(row table)"); }
+    *out = ctx;
+    return TPC_OK;
+}
+
+void tpc_destroy(tpc_context *ctx) {
+    if (!ctx) return;
+    if (ctx->d_row_x) (void)hipFree(ctx->d_row_x);
+    delete ctx;
+}
+
+tpc_status tpc_workspace_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t stage_mask,
+                               size_t *bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(TPC_ERR_ARG, "null bytes");
+    if (!ctx || !fr) return fail(TPC_ERR_ARG, "null context or frames");
+    if (fr->n_frames < 1 || fr->n_clusters < 0) return fail(TPC_ERR_ARG, "bad frame sizes");
+    if ((stage_mask & ~TPC_STAGE_ALL) != 0) return fail(TPC_ERR_ARG, "unknown stage bits");
+    *bytes = stage_bytes(ctx, fr, stage_mask);
+    return TPC_OK;
+}
+
+tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
+                          void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
+    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_NEIGHBOURS));
+    if (s) return s;
+    if (fr->n_clusters == 0) return TPC_OK;
+    NbWs l;
+    nb_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
+    hipError_t e = launch_neighbours(ctx, fr, up, dn, l, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "neighbour kernels");
+}
+
+tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const int32_t *up,
+                       const int32_t *dn, tpc_seeds *sd, int32_t *dev_status, void *ws,
+                       size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
+    if (!sd || !dev_status) return fail(TPC_ERR_ARG, "null seeds or dev_status");
+    if (sd->cap_seeds < 0 || sd->cap_hits < 0) return fail(TPC_ERR_ARG, "negative capacity");
+    if (!sd->n_seeds || !sd->n_hits || !sd->offsets) return fail(TPC_ERR_ARG, "null seed counters or offsets");
+    if (sd->cap_seeds > 0 && (!sd->frame || !sd->sector || !sd->first_row))
+        return fail(TPC_ERR_ARG, "null seed arrays");
+    if (sd->cap_hits > 0 && !sd->hits) return fail(TPC_ERR_ARG, "null seed hits");
+    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_SEED));
+    if (s) return s;
+    CaWs l;
+    ca_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
+    hipError_t e = launch_ca_seed(ctx, fr, up, dn, sd, dev_status, l, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "seeding kernels");
+}
+
+tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                          const float *map, tpc_tracks *tr, void *ws, size_t ws_bytes,
+                          void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if (!sd || !tr) return fail(TPC_ERR_ARG, "null seeds or tracks");
+    if (sd->cap_seeds < 0) return fail(TPC_ERR_ARG, "negative capacity");
+    if (!sd->n_seeds || !sd->offsets) return fail(TPC_ERR_ARG, "null seed counters or offsets");
+    if (sd->cap_seeds > 0 && (!sd->hits || !sd->sector || !sd->first_row))
+        return fail(TPC_ERR_ARG, "null seed arrays");
+    if (sd->cap_seeds > 0 && (!tr->x || !tr->par || !tr->cov || !tr->chi2 || !tr->ndf || !tr->status))
+        return fail(TPC_ERR_ARG, "null track arrays");
+    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_FIT));
+    if (s) return s;
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_fit(ctx, fr, sd, map, tr, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations shared by the kernels and the C-ABI of libtpcreco.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpcreco.h"
+
+#define TPC_MAX_ROWS 256
+#define TPC_BLOCK 256          // threads per workgroup: four 64-wide wavefronts
+#define TPC_WAVE 64
+#define TPC_CELL_CAP 4096      // neighbour-search cells per pad row (LDS histogram size)
+
+struct tpc_context {
+    tpc_config cfg;            // row_x points at row_x_host below
+    float row_x_host[TPC_MAX_ROWS];
+    float *d_row_x;            // device copy of the row table
+    int device;
+};
+
+// Per-segment neighbour-search grid: cell (iy, iz) of a cluster is
+// clamp(floor((y - y0) * iwy)), clamp(floor((z - z0) * iwz)); cell id iy*nz+iz.
+struct SegGrid {
+    float y0, z0, iwy, iwz;
+    int32_t ny, nz, pad0, pad1;
+};
+
+// Workspace carving: every buffer starts on a 256-byte boundary.
+struct WsCarver {
+    char *base;
+    size_t off;
+    __host__ __device__ explicit WsCarver(void *b) : base(static_cast<char *>(b)), off(0) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct NbWs {
+    SegGrid *grid;      // [NR]
+    int32_t *cstart;    // [N + NR + 1]: cell starts of segment s at row_offsets[s] + s
+    float *sy, *sz;     // [N] clusters sorted by cell within each segment
+    int32_t *sid;       // [N] their global ids
+};
+
+struct CaWs {
+    unsigned long long *claim;   // [N] smallest claim key per cluster
+    int32_t *core;               // [N] chain length at a bottom, 0 elsewhere
+    int32_t *ctop;               // [N] chain top at a bottom
+    int32_t *memb;               // [N] bottom of the chain a linked cluster is in
+    int32_t *mpos;               // [N] its position in that chain
+    int32_t *fbot;               // [N] at a seed's first cluster: the chain bottom, else -1
+    int32_t *flen;               // [N] at a seed's first cluster: seed length
+    int32_t *choff;              // [N] at a bottom: hit offset of the chain core, -1 if no seed
+    int32_t *segcnt, *seghits;   // [NR] seeds / seed hits starting in the segment
+    int32_t *segbs, *segbh;      // [NR] exclusive prefixes of the above
+};
+
+size_t nb_ws_layout(void *ws, int64_t N, int64_t NR, NbWs *out);
+size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out);
+size_t fit_ws_layout(void *ws, int64_t T);
+
+// launchers (return hipError_t of the last launch)
+hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32_t *up,
+                             int32_t *dn, const NbWs &ws, hipStream_t st);
+hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const int32_t *up,
+                          const int32_t *dn, const tpc_seeds *sd, int32_t *dev_status,
+                          const CaWs &ws, hipStream_t st);
+hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                      const float *map, const tpc_tracks *tr, void *ws, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+__device__ inline int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < TPC_WAVE; d <<= 1) {
+        int t = __shfl_up(v, d, TPC_WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the TPC_BLOCK threads of a workgroup; returns the prefix
+// of this thread and writes the block total to *total.  `sh` holds
+// TPC_BLOCK / TPC_WAVE ints of LDS.  Contains barriers: call from every thread.
+__device__ inline int block_exclusive_scan(int v, int *sh, int *total) {
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    const int wid = threadIdx.x / TPC_WAVE;
+    int inc = wave_inclusive_scan(v);
+    if (lane == TPC_WAVE - 1) sh[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < TPC_BLOCK / TPC_WAVE; ++w) {
+        int s = sh[w];
+        before += (w < wid) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+__device__ inline float wave_min(float v) {
+#pragma unroll
+    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, TPC_WAVE));
+    return v;
+}
+__device__ inline float wave_max(float v) {
+#pragma unroll
+    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, TPC_WAVE));
+    return v;
+}

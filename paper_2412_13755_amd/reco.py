@@ -1,0 +1,216 @@
+"""Python face of libtpcreco: torch tensors in, torch tensors out.
+
+Every computation runs in the library's HIP kernels; this module only
+allocates device memory with torch, fills the C structs and passes the
+current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _capi as C
+
+
+@dataclasses.dataclass
+class RecoConfig:
+    """Reconstruction constants (cm, GeV/c, T).  See include/tpcreco.h."""
+    row_x: np.ndarray
+    n_sectors: int = 36
+    bz: float = 0.5
+    sigma_y: float = 0.05
+    sigma_z: float = 0.06
+    win_y: float = 2.5
+    win_z: float = 2.5
+    cut_y: float = 0.6
+    cut_z: float = 0.75
+    min_hits: int = 5
+    max_sin: float = 0.999
+    var_sin0: float = 1.0
+    var_tgl0: float = 1.0
+    var_qpt0: float = 100.0
+    ckpt_rows: int = 16
+
+    @property
+    def n_rows(self) -> int:
+        return int(len(self.row_x))
+
+
+class DeviceFrames:
+    """Clusters of ``n_frames`` frames resident on the device."""
+
+    def __init__(self, row_offsets: torch.Tensor, y: torch.Tensor, z: torch.Tensor, n_frames: int):
+        self.row_offsets, self.y, self.z = row_offsets, y, z
+        self.n_frames = int(n_frames)
+        self.n_clusters = int(y.numel())
+        self.c = C.FramesC(self.n_frames, self.n_clusters, row_offsets.data_ptr(),
+                           y.data_ptr() if self.n_clusters else None,
+                           z.data_ptr() if self.n_clusters else None)
+
+    @staticmethod
+    def from_numpy(row_offsets, y, z, n_frames, n_sectors, n_rows, device="cuda") -> "DeviceFrames":
+        off = np.ascontiguousarray(row_offsets, dtype=np.int64)
+        if off.ndim != 1 or off.size != n_frames * n_sectors * n_rows + 1:
+            raise ValueError("row_offsets must have n_frames*n_sectors*n_rows+1 entries")
+        if off[0] != 0 or np.any(np.diff(off) < 0) or off[-1] != len(y) or len(y) != len(z):
+            raise ValueError("row_offsets must start at 0, not decrease and end at len(y)")
+        if off[-1] + off.size >= 2 ** 31:
+            raise ValueError("too many clusters for int32 ids")
+        t_off = torch.from_numpy(off.astype(np.int32)).to(device)
+        t_y = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(device)
+        t_z = torch.from_numpy(np.ascontiguousarray(z, dtype=np.float32)).to(device)
+        return DeviceFrames(t_off, t_y, t_z, n_frames)
+
+
+@dataclasses.dataclass
+class Seeds:
+    n_seeds: torch.Tensor      # device int32 scalar
+    n_hits: torch.Tensor
+    offsets: torch.Tensor
+    hits: torch.Tensor
+    frame: torch.Tensor
+    sector: torch.Tensor
+    first_row: torch.Tensor
+    status: torch.Tensor       # device int32 status word
+
+    def c(self) -> C.SeedsC:
+        return C.SeedsC(self.frame.numel(), self.hits.numel(), self.n_seeds.data_ptr(),
+                        self.n_hits.data_ptr(), self.offsets.data_ptr(), self.hits.data_ptr(),
+                        self.frame.data_ptr(), self.sector.data_ptr(), self.first_row.data_ptr())
+
+    def to_numpy(self) -> dict:
+        ns = int(self.n_seeds.item())
+        nh = int(self.n_hits.item())
+        return dict(offsets=self.offsets[:ns + 1].cpu().numpy(), hits=self.hits[:nh].cpu().numpy(),
+                    frame=self.frame[:ns].cpu().numpy(), sector=self.sector[:ns].cpu().numpy(),
+                    first_row=self.first_row[:ns].cpu().numpy())
+
+
+@dataclasses.dataclass
+class Tracks:
+    x: torch.Tensor
+    par: torch.Tensor
+    cov: torch.Tensor
+    chi2: torch.Tensor
+    ndf: torch.Tensor
+    status: torch.Tensor
+
+    def c(self) -> C.TracksC:
+        return C.TracksC(self.x.data_ptr(), self.par.data_ptr(), self.cov.data_ptr(),
+                         self.chi2.data_ptr(), self.ndf.data_ptr(), self.status.data_ptr())
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Reco:
+    """One reconstruction context on one device."""
+
+    def __init__(self, cfg: RecoConfig, device: str = "cuda:0"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the reconstruction runs on a HIP device only")
+        self._row_x = np.ascontiguousarray(cfg.row_x, dtype=np.float32)
+        cc = C.Config(cfg.n_sectors, len(self._row_x), self._row_x.ctypes.data_as(ctypes.c_void_p),
+                      cfg.bz, cfg.sigma_y, cfg.sigma_z, cfg.win_y, cfg.win_z, cfg.cut_y, cfg.cut_z,
+                      cfg.min_hits, cfg.max_sin, cfg.var_sin0, cfg.var_tgl0, cfg.var_qpt0,
+                      cfg.ckpt_rows)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            C.check(C.lib().tpc_create(ctypes.byref(cc), ctypes.byref(h)))
+        self._ctx = h
+        self._ws: Optional[torch.Tensor] = None
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            C.lib().tpc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def workspace_bytes(self, frames: DeviceFrames, stages: int = C.TPC_STAGE_ALL) -> int:
+        n = ctypes.c_size_t()
+        C.check(C.lib().tpc_workspace_bytes(self._ctx, ctypes.byref(frames.c), stages, ctypes.byref(n)))
+        return int(n.value)
+
+    def workspace(self, frames: DeviceFrames, stages: int = C.TPC_STAGE_ALL) -> torch.Tensor:
+        """A cached workspace (grown on demand) large enough for ``stages``."""
+        need = max(256, self.workspace_bytes(frames, stages))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def upload(self, fr) -> DeviceFrames:
+        """Frames object with numpy fields (row_offsets, y, z, n_frames) -> device."""
+        return DeviceFrames.from_numpy(fr.row_offsets, fr.y, fr.z, fr.n_frames, self.cfg.n_sectors,
+                                       self.cfg.n_rows, self.device)
+
+    # ------------------------------------------------------------------
+    def neighbours(self, frames: DeviceFrames, up=None, dn=None, ws=None):
+        N = frames.n_clusters
+        up = torch.empty(N, dtype=torch.int32, device=self.device) if up is None else up
+        dn = torch.empty(N, dtype=torch.int32, device=self.device) if dn is None else dn
+        ws = self.workspace(frames) if ws is None else ws
+        C.check(C.lib().tpc_neighbours(self._ctx, ctypes.byref(frames.c), up.data_ptr(), dn.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return up, dn
+
+    def alloc_seeds(self, frames: DeviceFrames, cap_seeds=None, cap_hits=None) -> Seeds:
+        N = frames.n_clusters
+        # every seed holds >= min_hits distinct clusters: these bounds never overflow
+        cs = N // self.cfg.min_hits + 1 if cap_seeds is None else int(cap_seeds)
+        ch = max(N, 1) if cap_hits is None else int(cap_hits)
+        d, i = self.device, torch.int32
+        return Seeds(torch.zeros(1, dtype=i, device=d), torch.zeros(1, dtype=i, device=d),
+                     torch.zeros(cs + 1, dtype=i, device=d), torch.empty(ch, dtype=i, device=d),
+                     torch.empty(cs, dtype=i, device=d), torch.empty(cs, dtype=i, device=d),
+                     torch.empty(cs, dtype=i, device=d), torch.zeros(1, dtype=i, device=d))
+
+    def seed(self, frames: DeviceFrames, up, dn, seeds: Optional[Seeds] = None, ws=None) -> Seeds:
+        seeds = self.alloc_seeds(frames) if seeds is None else seeds
+        ws = self.workspace(frames) if ws is None else ws
+        sc = seeds.c()
+        C.check(C.lib().tpc_ca_seed(self._ctx, ctypes.byref(frames.c), up.data_ptr(), dn.data_ptr(),
+                                    ctypes.byref(sc), seeds.status.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _stream_handle(self.device)))
+        return seeds
+
+    def alloc_tracks(self, seeds: Seeds) -> Tracks:
+        T = seeds.frame.numel()
+        d = self.device
+        return Tracks(torch.empty(T, device=d), torch.empty(T, 5, device=d), torch.empty(T, 15, device=d),
+                      torch.empty(T, device=d), torch.empty(T, dtype=torch.int32, device=d),
+                      torch.empty(T, dtype=torch.int32, device=d))
+
+    def fit(self, frames: DeviceFrames, seeds: Seeds, map_: Optional[torch.Tensor] = None,
+            tracks: Optional[Tracks] = None, ws=None) -> Tracks:
+        tracks = self.alloc_tracks(seeds) if tracks is None else tracks
+        ws = self.workspace(frames) if ws is None else ws
+        if map_ is not None:
+            if map_.dtype != torch.float32 or not map_.is_contiguous() or \
+                    tuple(map_.shape) != (self.cfg.n_sectors, self.cfg.n_rows, 2):
+                raise ValueError("map must be contiguous float32 [n_sectors, n_rows, 2]")
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_kalman_fit(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
+                                       None if map_ is None else map_.data_ptr(), ctypes.byref(tc),
+                                       ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return tracks
+
+    def reconstruct(self, frames: DeviceFrames, map_=None):
+        """neighbours -> seeds -> fit on one stream, no host synchronisation."""
+        up, dn = self.neighbours(frames)
+        seeds = self.seed(frames, up, dn)
+        tracks = self.fit(frames, seeds, map_)
+        return up, dn, seeds, tracks

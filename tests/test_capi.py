@@ -1,0 +1,113 @@
+"""Host-side checks of the C-ABI (no GPU needed): the library loads, exports
+every function include/tpcreco.h declares, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tpcreco.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpc_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2412_13755_amd import _capi
+    return _capi
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
+              "tpc_kalman_fit", "tpc_status_string", "tpc_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(capi):
+    L = capi.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+    # and the binding declares a signature for each
+    assert set(declared_functions()) <= set(capi.SIGNATURES)
+
+
+def test_library_is_gfx950_only():
+    """The shared object carries device code for gfx950 and no other target."""
+    from paper_2412_13755_amd import _capi
+    data = open(_capi.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+    for other in (b"gfx90a", b"gfx942", b"gfx1100", b"gfx908"):
+        assert other not in data
+
+
+def _cfg(capi, **over):
+    row_x = np.linspace(85, 245, 152).astype(np.float32)
+    d = dict(n_sectors=36, n_rows=152, row_x=row_x.ctypes.data_as(ctypes.c_void_p), bz=0.5,
+             sigma_y=0.05, sigma_z=0.06, win_y=2.5, win_z=2.5, cut_y=0.6, cut_z=0.75, min_hits=5,
+             max_sin=0.999, var_sin0=1.0, var_tgl0=1.0, var_qpt0=100.0, ckpt_rows=16)
+    d.update(over)
+    return capi.Config(**d), row_x
+
+
+@pytest.mark.parametrize("bad", [dict(n_rows=2), dict(n_rows=300), dict(n_sectors=0), dict(bz=0.0),
+                                 dict(sigma_y=0.0), dict(win_z=-1.0), dict(min_hits=2),
+                                 dict(max_sin=1.0), dict(var_qpt0=0.0), dict(ckpt_rows=0),
+                                 dict(row_x=None)])
+def test_create_rejects_bad_config(capi, bad):
+    cfg, _keep = _cfg(capi, **bad)
+    h = ctypes.c_void_p()
+    rc = capi.lib().tpc_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == capi.TPC_ERR_ARG, capi.last_error()
+    assert h.value is None
+    assert capi.last_error()
+
+
+def test_create_rejects_decreasing_rows(capi):
+    row_x = np.linspace(245, 85, 152).astype(np.float32)
+    cfg, _ = _cfg(capi, row_x=row_x.ctypes.data_as(ctypes.c_void_p))
+    h = ctypes.c_void_p()
+    assert capi.lib().tpc_create(ctypes.byref(cfg), ctypes.byref(h)) == capi.TPC_ERR_ARG
+
+
+def test_calls_reject_null_context_and_frames(capi):
+    L = capi.lib()
+    fr = capi.FramesC(1, 0, None, None, None)
+    assert L.tpc_neighbours(None, ctypes.byref(fr), None, None, None, 0, None) == capi.TPC_ERR_ARG
+    sd = capi.SeedsC()
+    assert L.tpc_ca_seed(None, ctypes.byref(fr), None, None, ctypes.byref(sd), None, None, 0,
+                         None) == capi.TPC_ERR_ARG
+    tr = capi.TracksC()
+    assert L.tpc_kalman_fit(None, ctypes.byref(fr), ctypes.byref(sd), None, ctypes.byref(tr), None,
+                            0, None) == capi.TPC_ERR_ARG
+    n = ctypes.c_size_t()
+    assert L.tpc_workspace_bytes(None, ctypes.byref(fr), 1, ctypes.byref(n)) == capi.TPC_ERR_ARG
+
+
+def test_status_strings(capi):
+    assert capi.status_string(0) == "TPC_OK"
+    assert capi.status_string(-2) == "TPC_ERR_CAPACITY"
+    assert capi.status_string(-5) == "TPC_ERR_WORKSPACE"
+    assert capi.status_string(-99) == "TPC_ERR_UNKNOWN"
+
+
+def test_binding_refuses_non_hip_device():
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    with pytest.raises(ValueError):
+        Reco(RecoConfig(row_x=np.linspace(85, 245, 152).astype(np.float32)), device="cpu")
+
+
+def test_upload_validates_offsets():
+    from paper_2412_13755_amd.reco import DeviceFrames
+    y = np.zeros(4, np.float32)
+    with pytest.raises(ValueError):
+        DeviceFrames.from_numpy(np.array([0, 3, 2, 4]), y, y, 1, 1, 3, device="cpu")
+    with pytest.raises(ValueError):
+        DeviceFrames.from_numpy(np.array([0, 1, 2, 3]), y, y, 1, 1, 3, device="cpu")
