@@ -152,13 +152,44 @@ tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
  * hit with covariance diag(sigma_y^2, sigma_z^2, var_sin0, var_tgl0,
  * var_qpt0); then for each hit inwards an exact helix step with its analytic
  * Jacobian (no process noise) and a Kalman update with the hit.  chi2 is the
- * sum of the predicted-residual chi2, ndf = 2n - 5.  Arithmetic is single
- * precision.  map: optional [n_sectors][n_rows][2] (dy, dz) subtracted from
- * every cluster of that (sector, row) before fitting (NULL = none).
- * ws: TPC_STAGE_FIT workspace. */
+ * sum of the predicted-residual chi2, ndf = 2n - 5.  The state, covariance
+ * and update are carried in double precision, the Jacobian in single
+ * precision; outputs are single precision.
+ * map: optional [n_sectors][n_rows][2] (dy, dz) subtracted from every
+ * cluster of that (sector, row) before fitting (NULL = none).
+ * ckpt: optional device buffer of >= tpc_ckpt_bytes() bytes (8-byte
+ * aligned); when given, the filter state every ckpt_rows updates is stored
+ * there for tpc_fit_adjoint().  ws: TPC_STAGE_FIT workspace. */
 tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *frames,
                           const tpc_seeds *seeds, const float *map, tpc_tracks *tracks,
-                          void *ws, size_t ws_bytes, void *stream);
+                          void *ckpt, size_t ckpt_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* Checkpoint-buffer bytes for seeds of these capacities (host call). */
+tpc_status tpc_ckpt_bytes(const tpc_context *ctx, const tpc_seeds *seeds, size_t *bytes);
+
+/* loss (device float scalar) = sum of chi2 over tracks with status
+ * TPC_FIT_OK, accumulated in double precision in a fixed order
+ * (bit-reproducible).  ws: TPC_STAGE_FIT workspace. */
+tpc_status tpc_chi2_sum(const tpc_context *ctx, const tpc_seeds *seeds, const tpc_tracks *tracks,
+                        float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of L(M) = sum of chi2 over tracks with status TPC_FIT_OK with
+ * respect to the correction map M [n_sectors][n_rows][2] used in the fit:
+ * grad_map = dloss * dL/dM, through the start, the helix steps (including
+ * the dependence of each Jacobian on the state), the gains and the chi2.
+ * Seeds stay fixed.  Requires the checkpoints of a tpc_kalman_fit() call
+ * with the same frames, seeds and map; tracks.status comes from that call.
+ * Reverse mode: each ckpt_rows-step segment is recomputed from its
+ * checkpoint, then run backwards.  Per-row sums are formed in a fixed order,
+ * so the result is bit-reproducible.  dloss: device float scalar (NULL = 1).
+ * grad_map: [n_sectors][n_rows][2] device floats, overwritten.
+ * ws: TPC_STAGE_ADJOINT workspace (sized for the default capacities
+ * cap_hits = N and cap_seeds = N / min_hits + 1; larger capacities need more,
+ * reported as TPC_ERR_WORKSPACE). */
+tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *frames,
+                           const tpc_seeds *seeds, const float *map, const tpc_tracks *tracks,
+                           const void *ckpt, size_t ckpt_bytes, const float *dloss,
+                           float *grad_map, void *ws, size_t ws_bytes, void *stream);
 
 /* Status code name. */
 const char *tpc_status_string(tpc_status s);

@@ -71,7 +71,13 @@ SIGNATURES = {
     "tpc_ca_seed": (i32, [P, ctypes.POINTER(FramesC), P, P, ctypes.POINTER(SeedsC), P, P,
                           ctypes.c_size_t, P]),
     "tpc_kalman_fit": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
-                             ctypes.POINTER(TracksC), P, ctypes.c_size_t, P]),
+                             ctypes.POINTER(TracksC), P, ctypes.c_size_t, P, ctypes.c_size_t, P]),
+    "tpc_ckpt_bytes": (i32, [P, ctypes.POINTER(SeedsC), ctypes.POINTER(ctypes.c_size_t)]),
+    "tpc_chi2_sum": (i32, [P, ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), P, P, ctypes.c_size_t,
+                           P]),
+    "tpc_fit_adjoint": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
+                              ctypes.POINTER(TracksC), P, ctypes.c_size_t, P, P, P, ctypes.c_size_t,
+                              P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),
 }

@@ -25,6 +25,7 @@ SOURCES = {
     "tpc_neighbours.hip": ["-ffp-contract=off"],
     "tpc_ca_seed.hip": [],
     "tpc_fit.hip": [],
+    "tpc_adjoint.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

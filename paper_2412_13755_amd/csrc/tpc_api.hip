@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "tpc_internal.hpp"
@@ -52,13 +53,47 @@ tpc_status check_ws(void *ws, size_t have, size_t need) {
     return TPC_OK;
 }
 
+// Seeds hold >= min_hits distinct clusters: default capacities never overflow.
+int64_t seed_cap_bound(const tpc_context *ctx, int64_t N) { return N / ctx->cfg.min_hits + 1; }
+
+size_t fit_bytes(int64_t cap_seeds) { return chi2_ws_layout(nullptr, cap_seeds, nullptr); }
+
+size_t adjoint_bytes(const tpc_context *ctx, const tpc_frames *fr, int64_t cap_hits, int64_t cap_seeds) {
+    const int64_t n_fs = (int64_t)fr->n_frames * ctx->cfg.n_sectors;
+    return adj_ws_layout(nullptr, cap_hits, cap_seeds, n_fs, ctx->cfg.n_rows, ctx->cfg.ckpt_rows,
+                         nullptr, nullptr, nullptr);
+}
+
 size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
     const int64_t N = fr->n_clusters, NR = n_segments(ctx, fr);
+    const int64_t cs = seed_cap_bound(ctx, N);
     size_t b = 0;
     if (mask & TPC_STAGE_NEIGHBOURS) b = std::max(b, nb_ws_layout(nullptr, N, NR, nullptr));
     if (mask & TPC_STAGE_SEED) b = std::max(b, ca_ws_layout(nullptr, N, NR, nullptr));
-    if (mask & TPC_STAGE_FIT) b = std::max(b, fit_ws_layout(nullptr, N));
+    if (mask & TPC_STAGE_FIT) b = std::max(b, fit_bytes(cs));
+    if (mask & TPC_STAGE_ADJOINT) b = std::max(b, adjoint_bytes(ctx, fr, N > 0 ? N : 1, cs));
     return b;
+}
+
+size_t ckpt_bytes(const tpc_context *ctx, const tpc_seeds *sd) {
+    const int64_t slots = (int64_t)sd->cap_hits / ctx->cfg.ckpt_rows + sd->cap_seeds + 1;
+    return (size_t)slots * 20 * sizeof(double);
+}
+
+tpc_status check_seeds_for_fit(const tpc_seeds *sd) {
+    if (!sd) return fail(TPC_ERR_ARG, "null seeds");
+    if (sd->cap_seeds < 0 || sd->cap_hits < 0) return fail(TPC_ERR_ARG, "negative capacity");
+    if (!sd->n_seeds || !sd->offsets) return fail(TPC_ERR_ARG, "null seed counters or offsets");
+    if (sd->cap_seeds > 0 && (!sd->hits || !sd->sector || !sd->first_row || !sd->frame))
+        return fail(TPC_ERR_ARG, "null seed arrays");
+    return TPC_OK;
+}
+
+tpc_status check_tracks(const tpc_seeds *sd, const tpc_tracks *tr) {
+    if (!tr) return fail(TPC_ERR_ARG, "null tracks");
+    if (sd->cap_seeds > 0 && (!tr->x || !tr->par || !tr->cov || !tr->chi2 || !tr->ndf || !tr->status))
+        return fail(TPC_ERR_ARG, "null track arrays");
+    return TPC_OK;
 }
 
 }  // namespace
@@ -178,24 +213,66 @@ tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const int32
     return e == hipSuccess ? TPC_OK : hip_fail(e, "seeding kernels");
 }
 
+tpc_status tpc_ckpt_bytes(const tpc_context *ctx, const tpc_seeds *seeds, size_t *bytes) {
+    g_err[0] = 0;
+    if (!ctx || !seeds || !bytes) return fail(TPC_ERR_ARG, "null argument");
+    if (seeds->cap_seeds < 0 || seeds->cap_hits < 0) return fail(TPC_ERR_ARG, "negative capacity");
+    *bytes = ckpt_bytes(ctx, seeds);
+    return TPC_OK;
+}
+
 tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
-                          const float *map, tpc_tracks *tr, void *ws, size_t ws_bytes,
-                          void *stream) {
+                          const float *map, tpc_tracks *tr, void *ckpt, size_t ckpt_bytes_have,
+                          void *ws, size_t ws_bytes, void *stream) {
     g_err[0] = 0;
     tpc_status s = check_frames(ctx, fr);
     if (s) return s;
-    if (!sd || !tr) return fail(TPC_ERR_ARG, "null seeds or tracks");
-    if (sd->cap_seeds < 0) return fail(TPC_ERR_ARG, "negative capacity");
-    if (!sd->n_seeds || !sd->offsets) return fail(TPC_ERR_ARG, "null seed counters or offsets");
-    if (sd->cap_seeds > 0 && (!sd->hits || !sd->sector || !sd->first_row))
-        return fail(TPC_ERR_ARG, "null seed arrays");
-    if (sd->cap_seeds > 0 && (!tr->x || !tr->par || !tr->cov || !tr->chi2 || !tr->ndf || !tr->status))
-        return fail(TPC_ERR_ARG, "null track arrays");
-    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_FIT));
-    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if (ckpt) {
+        if (((uintptr_t)ckpt & 7) != 0) return fail(TPC_ERR_ARG, "checkpoint buffer not 8-byte aligned");
+        const size_t need = ckpt_bytes(ctx, sd);
+        if (ckpt_bytes_have < need)
+            return fail(TPC_ERR_WORKSPACE, "checkpoint buffer has %zu bytes, %zu needed", ckpt_bytes_have, need);
+    }
+    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds)))) return s;
     if (sd->cap_seeds == 0) return TPC_OK;
-    hipError_t e = launch_fit(ctx, fr, sd, map, tr, ws, (hipStream_t)stream);
+    hipError_t e = launch_fit(ctx, fr, sd, map, tr, (double *)ckpt, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
+}
+
+tpc_status tpc_chi2_sum(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr,
+                        float *loss, void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!ctx) return fail(TPC_ERR_ARG, "null context");
+    tpc_status s = check_seeds_for_fit(sd);
+    if (s) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if (!loss) return fail(TPC_ERR_ARG, "null loss");
+    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds)))) return s;
+    hipError_t e = launch_chi2_sum(sd, tr, loss, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "chi2 sum kernels");
+}
+
+tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                           const float *map, const tpc_tracks *tr, const void *ckpt,
+                           size_t ckpt_bytes_have, const float *dloss, float *grad_map, void *ws,
+                           size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if (!grad_map) return fail(TPC_ERR_ARG, "null grad_map");
+    if (!ckpt) return fail(TPC_ERR_ARG, "null checkpoint buffer");
+    if (((uintptr_t)ckpt & 7) != 0) return fail(TPC_ERR_ARG, "checkpoint buffer not 8-byte aligned");
+    const size_t need_ck = ckpt_bytes(ctx, sd);
+    if (ckpt_bytes_have < need_ck)
+        return fail(TPC_ERR_WORKSPACE, "checkpoint buffer has %zu bytes, %zu needed", ckpt_bytes_have, need_ck);
+    if ((s = check_ws(ws, ws_bytes, adjoint_bytes(ctx, fr, sd->cap_hits, sd->cap_seeds)))) return s;
+    hipError_t e = launch_adjoint(ctx, fr, sd, map, tr, (const double *)ckpt, dloss, grad_map, ws,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "adjoint kernels");
 }
 
 }  // extern "C"

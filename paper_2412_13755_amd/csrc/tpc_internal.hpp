@@ -61,7 +61,9 @@ struct CaWs {
 
 size_t nb_ws_layout(void *ws, int64_t N, int64_t NR, NbWs *out);
 size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out);
-size_t fit_ws_layout(void *ws, int64_t T);
+size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part);
+size_t adj_ws_layout(void *ws, int64_t cap_hits, int64_t cap_seeds, int64_t n_fs, int32_t n_rows,
+                     int32_t K, float2 **g, double **tape, float2 **partial);
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32_t *up,
@@ -70,7 +72,12 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
                           const int32_t *dn, const tpc_seeds *sd, int32_t *dev_status,
                           const CaWs &ws, hipStream_t st);
 hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
-                      const float *map, const tpc_tracks *tr, void *ws, hipStream_t st);
+                      const float *map, const tpc_tracks *tr, double *ckpt, hipStream_t st);
+hipError_t launch_chi2_sum(const tpc_seeds *sd, const tpc_tracks *tr, float *loss, void *ws,
+                           hipStream_t st);
+hipError_t launch_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                          const float *map, const tpc_tracks *tr, const double *ckpt,
+                          const float *dloss, float *grad_map, void *ws, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // device helpers

@@ -193,20 +193,65 @@ class Reco:
                       torch.empty(T, device=d), torch.empty(T, dtype=torch.int32, device=d),
                       torch.empty(T, dtype=torch.int32, device=d))
 
+    def _check_map(self, map_):
+        if map_ is not None:
+            if map_.dtype != torch.float32 or not map_.is_contiguous() or map_.device != self.device or \
+                    tuple(map_.shape) != (self.cfg.n_sectors, self.cfg.n_rows, 2):
+                raise ValueError("map must be a contiguous float32 [n_sectors, n_rows, 2] device tensor")
+
+    def ckpt_bytes(self, seeds: Seeds) -> int:
+        n = ctypes.c_size_t()
+        sc = seeds.c()
+        C.check(C.lib().tpc_ckpt_bytes(self._ctx, ctypes.byref(sc), ctypes.byref(n)))
+        return int(n.value)
+
+    def alloc_ckpt(self, seeds: Seeds) -> torch.Tensor:
+        return torch.empty(self.ckpt_bytes(seeds) // 8, dtype=torch.float64, device=self.device)
+
     def fit(self, frames: DeviceFrames, seeds: Seeds, map_: Optional[torch.Tensor] = None,
-            tracks: Optional[Tracks] = None, ws=None) -> Tracks:
+            tracks: Optional[Tracks] = None, ws=None, ckpt: Optional[torch.Tensor] = None) -> Tracks:
         tracks = self.alloc_tracks(seeds) if tracks is None else tracks
         ws = self.workspace(frames) if ws is None else ws
-        if map_ is not None:
-            if map_.dtype != torch.float32 or not map_.is_contiguous() or \
-                    tuple(map_.shape) != (self.cfg.n_sectors, self.cfg.n_rows, 2):
-                raise ValueError("map must be contiguous float32 [n_sectors, n_rows, 2]")
+        self._check_map(map_)
         sc = seeds.c()
         tc = tracks.c()
         C.check(C.lib().tpc_kalman_fit(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
                                        None if map_ is None else map_.data_ptr(), ctypes.byref(tc),
+                                       None if ckpt is None else ckpt.data_ptr(),
+                                       0 if ckpt is None else ckpt.numel() * ckpt.element_size(),
                                        ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return tracks
+
+    def chi2_sum(self, seeds: Seeds, tracks: Tracks, loss: Optional[torch.Tensor] = None, ws=None):
+        """Sum of chi2 over successfully fitted tracks (device float scalar)."""
+        loss = torch.empty((), dtype=torch.float32, device=self.device) if loss is None else loss
+        if ws is None:
+            ws = self._ws if self._ws is not None else torch.empty(
+                max(256, 8 * (seeds.frame.numel() // 256 + 2)), dtype=torch.uint8, device=self.device)
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_chi2_sum(self._ctx, ctypes.byref(sc), ctypes.byref(tc), loss.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return loss
+
+    def fit_adjoint(self, frames: DeviceFrames, seeds: Seeds, map_: torch.Tensor, tracks: Tracks,
+                    ckpt: torch.Tensor, dloss: Optional[torch.Tensor] = None,
+                    grad: Optional[torch.Tensor] = None, ws=None) -> torch.Tensor:
+        """dloss * d(sum chi2)/d(map), seeds fixed (needs the checkpoints of ``fit``)."""
+        self._check_map(map_)
+        grad = torch.empty(self.cfg.n_sectors, self.cfg.n_rows, 2, dtype=torch.float32,
+                           device=self.device) if grad is None else grad
+        ws = self.workspace(frames) if ws is None else ws
+        if dloss is not None:
+            dloss = dloss.to(device=self.device, dtype=torch.float32).contiguous()
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_fit_adjoint(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
+                                        None if map_ is None else map_.data_ptr(), ctypes.byref(tc),
+                                        ckpt.data_ptr(), ckpt.numel() * ckpt.element_size(),
+                                        None if dloss is None else dloss.data_ptr(), grad.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return grad
 
     def reconstruct(self, frames: DeviceFrames, map_=None):
         """neighbours -> seeds -> fit on one stream, no host synchronisation."""
@@ -214,3 +259,25 @@ class Reco:
         seeds = self.seed(frames, up, dn)
         tracks = self.fit(frames, seeds, map_)
         return up, dn, seeds, tracks
+
+
+class KalmanChi2(torch.autograd.Function):
+    """loss = sum of fit chi2 over the (fixed) seeds, as a function of the
+    [n_sectors, n_rows, 2] cluster correction map; backward runs the
+    library's hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, map_: torch.Tensor, reco: "Reco", frames: DeviceFrames, seeds: Seeds):
+        m = map_.detach().contiguous()
+        ckpt = reco.alloc_ckpt(seeds)
+        tracks = reco.fit(frames, seeds, m, ckpt=ckpt)
+        loss = reco.chi2_sum(seeds, tracks)
+        ctx.reco, ctx.frames, ctx.seeds = reco, frames, seeds
+        ctx.tracks, ctx.ckpt, ctx.map = tracks, ckpt, m
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.reco.fit_adjoint(ctx.frames, ctx.seeds, ctx.map, ctx.tracks, ctx.ckpt,
+                                 dloss=grad_out.reshape(()))
+        return g, None, None, None
