@@ -27,7 +27,8 @@ def capi():
 def test_header_declares_the_path():
     names = declared_functions()
     for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
-              "tpc_kalman_fit", "tpc_status_string", "tpc_last_error"):
+              "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
+              "tpc_status_string", "tpc_last_error"):
         assert n in names
 
 
@@ -86,7 +87,13 @@ def test_calls_reject_null_context_and_frames(capi):
                          None) == capi.TPC_ERR_ARG
     tr = capi.TracksC()
     assert L.tpc_kalman_fit(None, ctypes.byref(fr), ctypes.byref(sd), None, ctypes.byref(tr), None,
-                            0, None) == capi.TPC_ERR_ARG
+                            0, None, 0, None) == capi.TPC_ERR_ARG
+    assert L.tpc_fit_adjoint(None, ctypes.byref(fr), ctypes.byref(sd), None, ctypes.byref(tr), None,
+                             0, None, None, None, 0, None) == capi.TPC_ERR_ARG
+    assert L.tpc_chi2_sum(None, ctypes.byref(sd), ctypes.byref(tr), None, None, 0,
+                          None) == capi.TPC_ERR_ARG
+    n = ctypes.c_size_t()
+    assert L.tpc_ckpt_bytes(None, ctypes.byref(sd), ctypes.byref(n)) == capi.TPC_ERR_ARG
     n = ctypes.c_size_t()
     assert L.tpc_workspace_bytes(None, ctypes.byref(fr), 1, ctypes.byref(n)) == capi.TPC_ERR_ARG
 
