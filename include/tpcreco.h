@@ -108,7 +108,8 @@ void tpc_destroy(tpc_context *ctx);
 #define TPC_STAGE_SEED        2
 #define TPC_STAGE_FIT         4
 #define TPC_STAGE_ADJOINT     8
-#define TPC_STAGE_ALL        15
+#define TPC_STAGE_PERSISTENT 16
+#define TPC_STAGE_ALL        31
 
 /* Workspace bytes needed by the stages in `stage_mask` for frames of this
  * shape (only n_frames and n_clusters are read; host call, no device work).
@@ -139,7 +140,8 @@ tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *frames,
  *           clusters, ordered by the global id of their first cluster.
  * up, dn: [N] from tpc_neighbours.  seeds: caller arrays and capacities.
  * dev_status: device int32, set to TPC_OK or TPC_ERR_CAPACITY (then
- * *n_seeds/*n_hits hold the required sizes and the arrays hold a prefix).
+ * the counters n_seeds and n_hits hold the required sizes and the arrays
+ * hold a prefix).
  * ws: TPC_STAGE_SEED workspace. */
 tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
                        const int32_t *up, const int32_t *dn, tpc_seeds *seeds,
@@ -190,6 +192,37 @@ tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *frames,
                            const tpc_seeds *seeds, const float *map, const tpc_tracks *tracks,
                            const void *ckpt, size_t ckpt_bytes, const float *dloss,
                            float *grad_map, void *ws, size_t ws_bytes, void *stream);
+
+/* Whole path (tpc_neighbours, tpc_ca_seed, tpc_kalman_fit without map or
+ * checkpoints) for all n_frames frames of `frames`; results are identical in
+ * both modes.
+ *   TPC_MODE_STAGED      the three stage calls one after another (several
+ *                        kernel launches per stage)
+ *   TPC_MODE_PERSISTENT  one persistent kernel (plus a small initialisation
+ *                        and status kernel) on a grid of workgroups that are
+ *                        resident at once, moving through the stages with
+ *                        grid-wide barriers; the fit visits seeds longest
+ *                        first.  If the grid cannot synchronise (a barrier
+ *                        wait exceeds its bounded polling), every workgroup
+ *                        leaves and *dev_status is set to TPC_ERR_HIP.
+ * tune: NULL or { grid: workgroups (0 = resident capacity, larger values are
+ * clamped to it), sort_fit: 1 = longest seeds first, 0 = seed order }.
+ * Both modes are graph-capturable (no allocation, no host synchronisation).
+ * ws: TPC_STAGE_NEIGHBOURS|SEED|FIT workspace (staged) or
+ * TPC_STAGE_PERSISTENT workspace (persistent). */
+#define TPC_MODE_STAGED      0
+#define TPC_MODE_PERSISTENT  1
+typedef struct tpc_tune {
+    int32_t grid;
+    int32_t sort_fit;
+} tpc_tune;
+tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *frames, int32_t mode,
+                           const tpc_tune *tune, int32_t *up, int32_t *dn, tpc_seeds *seeds,
+                           tpc_tracks *tracks, int32_t *dev_status, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Workgroups the persistent kernel can keep resident on the context's device. */
+int32_t tpc_persistent_grid(const tpc_context *ctx);
 
 /* Status code name. */
 const char *tpc_status_string(tpc_status s);

@@ -4,7 +4,7 @@ seeding and Kalman helix fit behind the C-ABI library libtpcreco.so (gfx950).
 The Python layer only moves data: every step runs in the library's HIP
 kernels, and importing the bindings fails loudly if the library is missing.
 """
-__all__ = ["Reco", "RecoConfig", "DeviceFrames", "Seeds", "Tracks", "KalmanChi2"]
+__all__ = ["Reco", "RecoConfig", "DeviceFrames", "Seeds", "Tracks", "KalmanChi2", "ReconstructGraph"]
 
 
 def __getattr__(name):

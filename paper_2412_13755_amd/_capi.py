@@ -27,7 +27,7 @@ TPC_STAGE_NEIGHBOURS = 1
 TPC_STAGE_SEED = 2
 TPC_STAGE_FIT = 4
 TPC_STAGE_ADJOINT = 8
-TPC_STAGE_ALL = 15
+TPC_STAGE_ALL = 31
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32
@@ -54,6 +54,15 @@ class TracksC(ctypes.Structure):
     _fields_ = [("x", P), ("par", P), ("cov", P), ("chi2", P), ("ndf", P), ("status", P)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("grid", i32), ("sort_fit", i32)]
+
+
+TPC_MODE_STAGED = 0
+TPC_MODE_PERSISTENT = 1
+TPC_STAGE_PERSISTENT = 16
+
+
 class TpcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (status_string(code), code, msg))
@@ -78,6 +87,10 @@ SIGNATURES = {
     "tpc_fit_adjoint": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
                               ctypes.POINTER(TracksC), P, ctypes.c_size_t, P, P, P, ctypes.c_size_t,
                               P]),
+    "tpc_reconstruct": (i32, [P, ctypes.POINTER(FramesC), i32, ctypes.POINTER(Tune), P, P,
+                              ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), P, P, ctypes.c_size_t,
+                              P]),
+    "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),
 }

@@ -26,6 +26,7 @@ SOURCES = {
     "tpc_ca_seed.hip": [],
     "tpc_fit.hip": [],
     "tpc_adjoint.hip": [],
+    "tpc_persistent.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

@@ -72,6 +72,7 @@ size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
     if (mask & TPC_STAGE_SEED) b = std::max(b, ca_ws_layout(nullptr, N, NR, nullptr));
     if (mask & TPC_STAGE_FIT) b = std::max(b, fit_bytes(cs));
     if (mask & TPC_STAGE_ADJOINT) b = std::max(b, adjoint_bytes(ctx, fr, N > 0 ? N : 1, cs));
+    if (mask & TPC_STAGE_PERSISTENT) b = std::max(b, persist_ws_layout(nullptr, N, NR, cs, nullptr));
     return b;
 }
 
@@ -156,6 +157,7 @@ tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
     if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipMalloc(row table)"); }
     e = hipMemcpy(ctx->d_row_x, ctx->row_x_host, sizeof(float) * c.n_rows, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(ctx->d_row_x); delete ctx; return hip_fail(e, "hipMemcpy(row table)"); }
+    ctx->persist_grid = persist_grid(ctx);
     *out = ctx;
     return TPC_OK;
 }
@@ -274,5 +276,40 @@ tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *fr, const t
                                   (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "adjoint kernels");
 }
+
+tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *fr, int32_t mode,
+                           const tpc_tune *tune, int32_t *up, int32_t *dn, tpc_seeds *sd,
+                           tpc_tracks *tr, int32_t *dev_status, void *ws, size_t ws_bytes,
+                           void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if (mode != TPC_MODE_STAGED && mode != TPC_MODE_PERSISTENT) return fail(TPC_ERR_ARG, "unknown mode %d", mode);
+    if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
+    if (!dev_status) return fail(TPC_ERR_ARG, "null dev_status");
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if (!sd->n_hits || (sd->cap_hits > 0 && !sd->hits)) return fail(TPC_ERR_ARG, "null seed hits");
+    if ((s = check_tracks(sd, tr))) return s;
+    if (tune && (tune->grid < 0 || tune->sort_fit < 0 || tune->sort_fit > 1))
+        return fail(TPC_ERR_ARG, "bad tune values");
+    hipStream_t st = (hipStream_t)stream;
+    if (mode == TPC_MODE_STAGED) {
+        if ((s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_NEIGHBOURS | TPC_STAGE_SEED | TPC_STAGE_FIT))))
+            return s;
+        if ((s = tpc_neighbours(ctx, fr, up, dn, ws, ws_bytes, stream))) return s;
+        if ((s = tpc_ca_seed(ctx, fr, up, dn, sd, dev_status, ws, ws_bytes, stream))) return s;
+        return tpc_kalman_fit(ctx, fr, sd, nullptr, tr, nullptr, 0, ws, ws_bytes, stream);
+    }
+    const int64_t NR = n_segments(ctx, fr);
+    if ((s = check_ws(ws, ws_bytes, persist_ws_layout(nullptr, fr->n_clusters, NR, sd->cap_seeds, nullptr))))
+        return s;
+    int grid = ctx->persist_grid;
+    if (tune && tune->grid > 0 && tune->grid < grid) grid = tune->grid;
+    const int sort_fit = tune ? tune->sort_fit : 1;
+    hipError_t e = launch_persistent(ctx, fr, up, dn, sd, tr, dev_status, ws, grid, sort_fit, st);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "persistent kernel");
+}
+
+int32_t tpc_persistent_grid(const tpc_context *ctx) { return ctx ? ctx->persist_grid : 0; }
 
 }  // extern "C"

@@ -1,0 +1,197 @@
+#pragma once
+// Cellular-automaton seeding (gfx950): mutual links -> chains -> end claims
+// -> seeds in CSR form, ordered by the global id of their first cluster.
+// Per-segment device functions, used by the stage kernels and by the
+// persistent kernel.
+//
+// All kernels but the segment scan run one workgroup per (frame, sector,
+// row) segment with threads over the segment's clusters, so the pad row of
+// a cluster is known without a search.  Integer-only; the result is unique
+// (claims resolve with a 64-bit atomicMin on a key that orders by chain
+// length, then bottom id; seeds are placed by prefix sums in cluster-id
+// order), so it matches the sequential definition exactly.
+//
+//   ca_chains  bottoms (no kept link down, a kept link up) walk their chain,
+//              recording the bottom and position of every member, its length
+//              and top; every cluster's claim slot is reset
+//   ca_claims  chains of >= min_hits-2 clusters claim their unlinked ends
+//   ca_firsts  each seed is recognised at its first cluster (the won bottom
+//              end or the bottom itself); per-segment seed and hit counts
+//   ca_scan    exclusive prefix over segments, totals, capacity check
+//   ca_place   seed records, end clusters, core offsets
+//   ca_members every chain member writes itself into its seed
+#include "tpc_internal.hpp"
+
+namespace tpc_ca {
+
+
+// Link helpers.  Ids outside [0, N) read as "no link", so corrupt input can
+// never address memory outside the arrays.
+__device__ inline int32_t link_up(const int32_t *up, const int32_t *dn, int32_t N, int32_t h) {
+    int32_t u = up[h];
+    return ((uint32_t)u < (uint32_t)N && dn[u] == h) ? u : -1;
+}
+__device__ inline int32_t link_dn(const int32_t *up, const int32_t *dn, int32_t N, int32_t h) {
+    int32_t d = dn[h];
+    return ((uint32_t)d < (uint32_t)N && up[d] == h) ? d : -1;
+}
+__device__ inline bool linked(const int32_t *up, const int32_t *dn, int32_t N, int32_t h) {
+    return link_up(up, dn, N, h) >= 0 || link_dn(up, dn, N, h) >= 0;
+}
+__device__ inline bool valid_id(int32_t v, int32_t N) { return (uint32_t)v < (uint32_t)N; }
+__device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
+    return ((unsigned long long)(2147483648u - (uint32_t)m) << 32) | (uint32_t)b;
+}
+
+__device__ inline void ca_chains_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                     int32_t n_rows, const CaWs &ws) {
+    const int a = off[seg], b = off[seg + 1];
+    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
+        ws.claim[h] = ~0ull;
+        int32_t u = link_up(up, dn, N, h);
+        bool bottom = (u >= 0) && link_dn(up, dn, N, h) < 0;
+        if (!bottom) {
+            ws.core[h] = 0;
+            continue;
+        }
+        ws.memb[h] = h;
+        ws.mpos[h] = 0;
+        int32_t cur = h, m = 1;
+        // walk: one dependent load pair per step; a chain holds at most one
+        // cluster per row, which also bounds the walk on corrupt input
+        while (u >= 0 && m < n_rows) {
+            cur = u;
+            ws.memb[cur] = h;
+            ws.mpos[cur] = m;
+            ++m;
+            u = link_up(up, dn, N, cur);
+        }
+        ws.core[h] = m;
+        ws.ctop[h] = cur;
+        ws.choff[h] = -1;
+    }
+}
+
+__device__ inline void ca_claims_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                     int32_t min_hits, const CaWs &ws) {
+    const int a = off[seg], b = off[seg + 1];
+    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
+        int32_t m = ws.core[h];
+        if (m < 2 || m < min_hits - 2) continue;
+        unsigned long long key = claim_key(m, h);
+        int32_t eb = dn[h], et = up[ws.ctop[h]];
+        if (valid_id(eb, N) && !linked(up, dn, N, eb)) atomicMin(&ws.claim[eb], key);
+        if (valid_id(et, N) && !linked(up, dn, N, et)) atomicMin(&ws.claim[et], key);
+    }
+}
+
+// Seed length of the chain with bottom bb (0 if it is no seed).
+__device__ inline int32_t seed_len(const int32_t *up, const int32_t *dn, int32_t N, int32_t min_hits,
+                                   const CaWs &ws, int32_t bb, int32_t *won_b) {
+    int32_t m = ws.core[bb];
+    int32_t wb = 0, wt = 0;
+    if (m >= min_hits - 2) {
+        unsigned long long key = claim_key(m, bb);
+        int32_t eb = dn[bb], et = up[ws.ctop[bb]];
+        wb = (valid_id(eb, N) && ws.claim[eb] == key);
+        wt = (valid_id(et, N) && ws.claim[et] == key);
+    }
+    *won_b = wb;
+    int32_t len = m + wb + wt;
+    return len >= min_hits ? len : 0;
+}
+
+// Contains barriers: call from the whole workgroup.
+__device__ inline void ca_firsts_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                     int32_t min_hits, const CaWs &ws) {
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    const int a = off[seg], b = off[seg + 1];
+    int cnt = 0, hits = 0;
+    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
+        int32_t fb = -1, len = 0;
+        if (ws.core[h] >= 2) {                       // h is a bottom
+            int32_t wb;
+            int32_t l = seed_len(up, dn, N, min_hits, ws, h, &wb);
+            if (l > 0 && !wb) { fb = h; len = l; }
+        } else if (ws.claim[h] != ~0ull) {           // h is a claimed end
+            int32_t bb = (int32_t)(ws.claim[h] & 0xffffffffull);
+            if (valid_id(bb, N) && dn[bb] == h) {    // claimed as the bottom end of bb
+                int32_t wb;
+                int32_t l = seed_len(up, dn, N, min_hits, ws, bb, &wb);
+                if (l > 0) { fb = bb; len = l; }
+            }
+        }
+        ws.fbot[h] = fb;
+        ws.flen[h] = len;
+        cnt += fb >= 0;
+        hits += len;
+    }
+    int tc, th;
+    block_exclusive_scan(cnt, sh, &tc);
+    block_exclusive_scan(hits, sh, &th);
+    if (threadIdx.x == 0) {
+        ws.segcnt[seg] = tc;
+        ws.seghits[seg] = th;
+    }
+}
+
+// Contains barriers: call from the whole workgroup.  Returns nothing; seeds
+// of the segment go to [segbs[seg], ...) within capacity.
+__device__ inline void ca_place_seg(int seg, const int32_t *__restrict__ off,
+                                    const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                    int32_t n_sectors, int32_t n_rows, int32_t cap_seeds,
+                                    int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws,
+                                    int32_t *len_hist = nullptr) {
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    const int a = off[seg], b = off[seg + 1];
+    int carry_c = ws.segbs[seg], carry_h = ws.segbh[seg];
+    const int frame = seg / (n_sectors * n_rows);
+    const int sector = (seg / n_rows) % n_sectors;
+    const int row = seg % n_rows;
+    for (int base = a; base < b; base += TPC_BLOCK) {
+        const int h = base + threadIdx.x;
+        int32_t fb = -1, len = 0;
+        if (h < b) { fb = ws.fbot[h]; len = ws.flen[h]; }
+        int tc, th;
+        int pc = block_exclusive_scan(fb >= 0 ? 1 : 0, sh, &tc);
+        int ph = block_exclusive_scan(len, sh, &th);
+        if (fb >= 0) {
+            const int i = carry_c + pc;
+            const int o = carry_h + ph;
+            if (i < cap_seeds && o + len <= cap_hits) {
+                sd.offsets[i] = o;
+                sd.offsets[i + 1] = o + len;   // equals the next seed's offset: the placed
+                                               // prefix stays well formed on overflow
+                sd.frame[i] = frame;
+                sd.sector[i] = sector;
+                sd.first_row[i] = row;
+                const int32_t wb = (h != fb);
+                if (wb) sd.hits[o] = h;
+                const int32_t m = ws.core[fb];
+                if (len > m + wb) sd.hits[o + len - 1] = up[ws.ctop[fb]];
+                ws.choff[fb] = o + wb;
+                if (len_hist) atomicAdd(&len_hist[len < TPC_MAX_ROWS ? len : TPC_MAX_ROWS], 1);
+            }
+        }
+        carry_c += tc;
+        carry_h += th;
+    }
+}
+
+__device__ inline void ca_members_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                      const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                      int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws) {
+    const int a = off[seg], b = off[seg + 1];
+    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
+        if (!linked(up, dn, N, h)) continue;
+        const int32_t bb = ws.memb[h];
+        if (!valid_id(bb, N)) continue;
+        const int32_t o = ws.choff[bb], k = ws.mpos[h];
+        if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) sd.hits[o + k] = h;
+    }
+}
+
+}  // namespace tpc_ca

@@ -65,6 +65,7 @@ FitArgs make_fit_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
     A.first_row = sd->first_row;
     A.n_seeds = sd->n_seeds;
     A.cap_seeds = sd->cap_seeds;
+    A.cap_hits = sd->cap_hits;
     A.y = fr->y;
     A.z = fr->z;
     A.row_x = ctx->d_row_x;

@@ -8,7 +8,7 @@
 
 struct FitArgs {
     const int32_t *offsets, *hits, *sector, *first_row, *n_seeds;
-    int32_t cap_seeds;
+    int32_t cap_seeds, cap_hits;
     const float *y, *z, *row_x, *map;
     int32_t n_rows, n_sectors, n_clusters;
     float kbz, max_sin;
@@ -34,7 +34,7 @@ __host__ __device__ inline SeedView seed_view(const FitArgs &A, int i) {
     v.row0 = A.first_row[i];
     v.sec = A.sector[i];
     v.sane = v.n >= 3 && v.row0 >= 0 && v.row0 + v.n <= A.n_rows && v.sec >= 0 &&
-             v.sec < A.n_sectors && v.o0 >= 0;
+             v.sec < A.n_sectors && v.o0 >= 0 && v.o0 <= A.cap_hits - v.n;
     v.hh = A.hits + v.o0;
     v.mp = (A.map && v.sane) ? A.map + (size_t)v.sec * A.n_rows * 2 : nullptr;
     return v;

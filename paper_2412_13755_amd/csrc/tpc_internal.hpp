@@ -16,6 +16,7 @@ struct tpc_context {
     float row_x_host[TPC_MAX_ROWS];
     float *d_row_x;            // device copy of the row table
     int device;
+    int persist_grid;          // resident workgroups of the persistent kernel
 };
 
 // Per-segment neighbour-search grid: cell (iy, iz) of a cluster is
@@ -64,6 +65,13 @@ size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out);
 size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part);
 size_t adj_ws_layout(void *ws, int64_t cap_hits, int64_t cap_seeds, int64_t n_fs, int32_t n_rows,
                      int32_t K, float2 **g, double **tape, float2 **partial);
+
+struct PersistArgs;
+size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, PersistArgs *P);
+int persist_grid(const tpc_context *ctx);
+hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
+                             const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status,
+                             void *ws, int grid, int sort_fit, hipStream_t st);
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32_t *up,

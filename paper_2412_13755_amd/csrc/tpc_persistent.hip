@@ -1,0 +1,304 @@
+// Persistent form of the whole path (gfx950): neighbour search, seeding and
+// fit of all frames in one launch of a grid sized to what the device holds
+// at once (occupancy x compute units).  Every phase runs the same
+// per-segment / per-seed device functions as the stage kernels, looping over
+// its work items grid-stride, so results are identical to the stage path.
+// Phases are separated by a grid-wide barrier: an arrival counter and a
+// generation word in device memory, with agent-scope fences on both sides
+// (the eight XCDs keep separate L2 caches).  A waiting workgroup polls with
+// a sleep and gives up after a bounded number of polls, setting an error flag
+// that makes every workgroup leave, so the kernel always terminates.
+//
+// Phases:  bin | query | chains | claims | firsts | chunk sums | chunk scan
+//          (one workgroup) | segment scan | place + length histogram |
+//          members + length scan (one workgroup) | order by length | fit
+// The fit visits seeds longest first, so the lanes of a wavefront carry
+// seeds of similar length (the loop length is the seed length).
+#include "tpc_ca_device.hpp"
+#include "tpc_fit_common.hpp"
+#include "tpc_nb_device.hpp"
+
+#define TPC_SCAN_CHUNK 1024        // segments per chunk of the two-level segment scan
+#define TPC_SPIN_LIMIT (1 << 22)   // polls before a barrier wait is abandoned
+
+struct PersistArgs {
+    // frames
+    const int32_t *off;
+    const float *y, *z;
+    int32_t N, NR, n_rows, n_sectors;
+    float win_y, win_z, cut_y, cut_z;
+    int32_t min_hits;
+    // outputs
+    int32_t *up, *dn;
+    tpc_seeds sd;
+    int32_t *dev_status;
+    FitArgs F;
+    // workspace
+    NbWs nb;
+    CaWs ca;
+    unsigned *bar;       // [2] arrival count, generation
+    int32_t *err;        // [1]
+    int32_t *chunk_c, *chunk_h;   // [nchunks]
+    int32_t *len_hist;   // [TPC_MAX_ROWS + 1], then bin starts
+    int32_t *len_cur;    // [TPC_MAX_ROWS + 1]
+    int32_t *perm;       // [cap_seeds]
+    int32_t *n_placed;   // [1]
+    int32_t nchunks;
+    int32_t sort_fit;
+};
+
+namespace {
+
+__device__ inline bool grid_sync(const PersistArgs &P) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = 1;
+        __threadfence();
+        const unsigned gen = __hip_atomic_load(&P.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = atomicAdd(&P.bar[0], 1u);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&P.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&P.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int spins = 0;
+            while (__hip_atomic_load(&P.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > TPC_SPIN_LIMIT) {
+                    atomicExch(P.err, 1);
+                    good = 0;
+                    break;
+                }
+                if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    good = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) good = 0;
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__device__ inline int block_sum(int v, int *sh) {
+    int tot;
+    block_exclusive_scan(v, sh, &tot);
+    return tot;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+persist_init(PersistArgs P) {
+    const int t = blockIdx.x * TPC_BLOCK + threadIdx.x;
+    if (t < 2) P.bar[t] = 0;
+    if (t == 0) { *P.err = 0; *P.n_placed = 0; }
+    if (t <= TPC_MAX_ROWS) { P.len_hist[t] = 0; P.len_cur[t] = 0; }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+persist_reco(PersistArgs P) {
+    __shared__ float xs[TPC_MAX_ROWS];
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    __shared__ int bc[2];
+    const int G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
+    for (int r = tid; r < P.n_rows; r += TPC_BLOCK) xs[r] = P.F.row_x[r];
+
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_nb::nb_bin_seg(seg, P.off, P.y, P.z, P.win_y, P.win_z, P.nb.grid, P.nb.cstart, P.nb.sy,
+                           P.nb.sz, P.nb.sid);
+    if (!grid_sync(P)) return;
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.win_y, P.win_z, P.cut_y, P.cut_z, P.nb.grid,
+                             P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn);
+    if (!grid_sync(P)) return;
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_ca::ca_chains_seg(seg, P.N, P.off, P.up, P.dn, P.n_rows, P.ca);
+    if (!grid_sync(P)) return;
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_ca::ca_claims_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
+    if (!grid_sync(P)) return;
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_ca::ca_firsts_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
+    if (!grid_sync(P)) return;
+    // chunk sums of the per-segment seed and hit counts
+    for (int ch = bid; ch < P.nchunks; ch += G) {
+        const int s0 = ch * TPC_SCAN_CHUNK;
+        int vc = 0, vh = 0;
+        for (int s = s0 + tid; s < s0 + TPC_SCAN_CHUNK && s < P.NR; s += TPC_BLOCK) {
+            vc += P.ca.segcnt[s];
+            vh += P.ca.seghits[s];
+        }
+        const int tc = block_sum(vc, sh);
+        const int th = block_sum(vh, sh);
+        if (tid == 0) { P.chunk_c[ch] = tc; P.chunk_h[ch] = th; }
+    }
+    if (!grid_sync(P)) return;
+    // exclusive scan of the chunk sums and the totals (one workgroup)
+    if (bid == 0) {
+        if (tid == 0) { bc[0] = 0; bc[1] = 0; }
+        __syncthreads();
+        for (int base = 0; base < P.nchunks; base += TPC_BLOCK) {
+            const int ch = base + tid;
+            const int vc = ch < P.nchunks ? P.chunk_c[ch] : 0;
+            const int vh = ch < P.nchunks ? P.chunk_h[ch] : 0;
+            int tc, th;
+            const int pc = block_exclusive_scan(vc, sh, &tc);
+            const int ph = block_exclusive_scan(vh, sh, &th);
+            const int cc = bc[0], chh = bc[1];
+            if (ch < P.nchunks) { P.chunk_c[ch] = cc + pc; P.chunk_h[ch] = chh + ph; }
+            __syncthreads();
+            if (tid == 0) { bc[0] = cc + tc; bc[1] = chh + th; }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int ns = bc[0], nh = bc[1];
+            *P.sd.n_seeds = ns;
+            *P.sd.n_hits = nh;
+            const bool ok = ns <= P.sd.cap_seeds && nh <= P.sd.cap_hits;
+            *P.dev_status = ok ? TPC_OK : TPC_ERR_CAPACITY;
+            if (ns <= P.sd.cap_seeds) P.sd.offsets[ns] = ok ? nh : 0;
+        }
+    }
+    if (!grid_sync(P)) return;
+    // per-segment exclusive prefixes within each chunk
+    for (int ch = bid; ch < P.nchunks; ch += G) {
+        const int s0 = ch * TPC_SCAN_CHUNK;
+        if (tid == 0) { bc[0] = P.chunk_c[ch]; bc[1] = P.chunk_h[ch]; }
+        __syncthreads();
+        for (int base = s0; base < s0 + TPC_SCAN_CHUNK && base < P.NR; base += TPC_BLOCK) {
+            const int s = base + tid;
+            const bool in = s < s0 + TPC_SCAN_CHUNK && s < P.NR;
+            const int vc = in ? P.ca.segcnt[s] : 0;
+            const int vh = in ? P.ca.seghits[s] : 0;
+            int tc, th;
+            const int pc = block_exclusive_scan(vc, sh, &tc);
+            const int ph = block_exclusive_scan(vh, sh, &th);
+            const int cc = bc[0], chh = bc[1];
+            if (in) { P.ca.segbs[s] = cc + pc; P.ca.segbh[s] = chh + ph; }
+            __syncthreads();
+            if (tid == 0) { bc[0] = cc + tc; bc[1] = chh + th; }
+            __syncthreads();
+        }
+    }
+    if (!grid_sync(P)) return;
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_ca::ca_place_seg(seg, P.off, P.up, P.dn, P.n_sectors, P.n_rows, P.sd.cap_seeds,
+                             P.sd.cap_hits, P.sd, P.ca, P.len_hist);
+    if (!grid_sync(P)) return;
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_ca::ca_members_seg(seg, P.N, P.off, P.up, P.dn, P.sd.cap_hits, P.sd, P.ca);
+    if (bid == 0 && P.sort_fit) {
+        // bin starts in descending length order
+        if (tid == 0) {
+            int run = 0;
+            for (int len = TPC_MAX_ROWS; len >= 0; --len) {
+                const int c = P.len_hist[len];
+                P.len_hist[len] = run;
+                run += c;
+            }
+            *P.n_placed = run;
+        }
+    }
+    if (!grid_sync(P)) return;
+    if (P.sort_fit) {
+        // placed seeds form the prefix [0, n_placed): order them by length
+        const int np = *P.n_placed;
+        for (int i = bid * TPC_BLOCK + tid; i < np; i += G * TPC_BLOCK) {
+            const int n = P.sd.offsets[i + 1] - P.sd.offsets[i];
+            const int len = n < TPC_MAX_ROWS ? (n > 0 ? n : 0) : TPC_MAX_ROWS;
+            const int slot = P.len_hist[len] + atomicAdd(&P.len_cur[len], 1);
+            if (slot < np) P.perm[slot] = i;
+        }
+        if (!grid_sync(P)) return;
+        for (int k = bid * TPC_BLOCK + tid; k < np; k += G * TPC_BLOCK) fit_one(P.F, P.perm[k], xs);
+    } else {
+        int T = *P.sd.n_seeds;
+        if (T > P.sd.cap_seeds) T = P.sd.cap_seeds;
+        for (int i = bid * TPC_BLOCK + tid; i < T; i += G * TPC_BLOCK) fit_one(P.F, i, xs);
+    }
+}
+
+__global__ void persist_status(PersistArgs P) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *P.err != 0) *P.dev_status = TPC_ERR_HIP;
+}
+
+}  // namespace
+
+size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, PersistArgs *P) {
+    WsCarver w(ws);
+    NbWs nb;
+    CaWs ca;
+    // the neighbour and seeding buffers live side by side (both are in use
+    // in one launch)
+    const size_t nbb = nb_ws_layout(ws ? w.base : nullptr, N, NR, &nb);
+    w.off = nbb;
+    const size_t cab = ca_ws_layout(ws ? w.base + nbb : nullptr, N, NR, &ca);
+    w.off = nbb + cab;
+    unsigned *bar = w.take<unsigned>(2);
+    int32_t *err = w.take<int32_t>(1);
+    const int64_t nchunks = (NR + TPC_SCAN_CHUNK - 1) / TPC_SCAN_CHUNK;
+    int32_t *cc = w.take<int32_t>(nchunks > 0 ? nchunks : 1);
+    int32_t *chh = w.take<int32_t>(nchunks > 0 ? nchunks : 1);
+    int32_t *hist = w.take<int32_t>(TPC_MAX_ROWS + 1);
+    int32_t *cur = w.take<int32_t>(TPC_MAX_ROWS + 1);
+    int32_t *perm = w.take<int32_t>(cap_seeds > 0 ? cap_seeds : 1);
+    int32_t *np = w.take<int32_t>(1);
+    if (P) {
+        P->nb = nb;
+        P->ca = ca;
+        P->bar = bar;
+        P->err = err;
+        P->chunk_c = cc;
+        P->chunk_h = chh;
+        P->len_hist = hist;
+        P->len_cur = cur;
+        P->perm = perm;
+        P->n_placed = np;
+        P->nchunks = (int32_t)nchunks;
+    }
+    return (w.off + 255) & ~size_t(255);
+}
+
+int persist_grid(const tpc_context *ctx) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_reco, TPC_BLOCK, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
+    return per_cu * cus;
+}
+
+hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
+                             const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status,
+                             void *ws, int grid, int sort_fit, hipStream_t st) {
+    const tpc_config &c = ctx->cfg;
+    PersistArgs P;
+    P.off = fr->row_offsets;
+    P.y = fr->y;
+    P.z = fr->z;
+    P.N = fr->n_clusters;
+    P.NR = fr->n_frames * c.n_sectors * c.n_rows;
+    P.n_rows = c.n_rows;
+    P.n_sectors = c.n_sectors;
+    P.win_y = c.win_y;
+    P.win_z = c.win_z;
+    P.cut_y = c.cut_y;
+    P.cut_z = c.cut_z;
+    P.min_hits = c.min_hits;
+    P.up = up;
+    P.dn = dn;
+    P.sd = *sd;
+    P.dev_status = dev_status;
+    P.F = make_fit_args(ctx, fr, sd, nullptr);
+    P.F.out = *tr;
+    P.sort_fit = sort_fit;
+    persist_ws_layout(ws, fr->n_clusters, P.NR, sd->cap_seeds, &P);
+    hipLaunchKernelGGL(persist_init, dim3(2), dim3(TPC_BLOCK), 0, st, P);
+    hipLaunchKernelGGL(persist_reco, dim3(grid), dim3(TPC_BLOCK), 0, st, P);
+    hipLaunchKernelGGL(persist_status, dim3(1), dim3(64), 0, st, P);
+    return hipGetLastError();
+}

@@ -43,8 +43,10 @@ class RecoConfig:
 class DeviceFrames:
     """Clusters of ``n_frames`` frames resident on the device."""
 
-    def __init__(self, row_offsets: torch.Tensor, y: torch.Tensor, z: torch.Tensor, n_frames: int):
+    def __init__(self, row_offsets: torch.Tensor, y: torch.Tensor, z: torch.Tensor, n_frames: int,
+                 offsets_host: Optional[np.ndarray] = None):
         self.row_offsets, self.y, self.z = row_offsets, y, z
+        self.offsets_host = offsets_host
         self.n_frames = int(n_frames)
         self.n_clusters = int(y.numel())
         self.c = C.FramesC(self.n_frames, self.n_clusters, row_offsets.data_ptr(),
@@ -63,7 +65,14 @@ class DeviceFrames:
         t_off = torch.from_numpy(off.astype(np.int32)).to(device)
         t_y = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(device)
         t_z = torch.from_numpy(np.ascontiguousarray(z, dtype=np.float32)).to(device)
-        return DeviceFrames(t_off, t_y, t_z, n_frames)
+        return DeviceFrames(t_off, t_y, t_z, n_frames, off)
+
+    def frame_view(self, f: int, segments_per_frame: int) -> "DeviceFrames":
+        """Frame ``f`` alone: cluster ids rebased to 0 (y, z are views)."""
+        off = self.offsets_host[f * segments_per_frame:(f + 1) * segments_per_frame + 1]
+        a, b = int(off[0]), int(off[-1])
+        t_off = torch.from_numpy((off - a).astype(np.int32)).to(self.y.device)
+        return DeviceFrames(t_off, self.y[a:b], self.z[a:b], 1, off - a)
 
 
 @dataclasses.dataclass
@@ -253,12 +262,62 @@ class Reco:
                                         ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return grad
 
-    def reconstruct(self, frames: DeviceFrames, map_=None):
-        """neighbours -> seeds -> fit on one stream, no host synchronisation."""
-        up, dn = self.neighbours(frames)
-        seeds = self.seed(frames, up, dn)
-        tracks = self.fit(frames, seeds, map_)
+    def persistent_grid(self) -> int:
+        return int(C.lib().tpc_persistent_grid(self._ctx))
+
+    def reconstruct(self, frames: DeviceFrames, mode: str = "staged", tune=None, out=None, ws=None):
+        """neighbours -> seeds -> fit for all frames, on one stream, no host
+        synchronisation.  mode "staged" runs the stage kernels, "persistent"
+        one persistent kernel.  ``out`` = (up, dn, seeds, tracks) to reuse
+        buffers (e.g. for graph capture).  tune = (grid, sort_fit) or None."""
+        if out is None:
+            N = frames.n_clusters
+            up = torch.empty(N, dtype=torch.int32, device=self.device)
+            dn = torch.empty(N, dtype=torch.int32, device=self.device)
+            seeds = self.alloc_seeds(frames)
+            tracks = self.alloc_tracks(seeds)
+        else:
+            up, dn, seeds, tracks = out
+        m = {"staged": C.TPC_MODE_STAGED, "persistent": C.TPC_MODE_PERSISTENT}[mode]
+        if ws is None:
+            ws = self.workspace(frames, C.TPC_STAGE_PERSISTENT if m else C.TPC_STAGE_ALL)
+        t = None if tune is None else C.Tune(int(tune[0]), int(tune[1]))
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_reconstruct(self._ctx, ctypes.byref(frames.c), m,
+                                        None if t is None else ctypes.byref(t), up.data_ptr(),
+                                        dn.data_ptr(), ctypes.byref(sc), ctypes.byref(tc),
+                                        seeds.status.data_ptr(), ws.data_ptr(), ws.numel(),
+                                        _stream_handle(self.device)))
         return up, dn, seeds, tracks
+
+
+class ReconstructGraph:
+    """The whole path for fixed frames and buffers, captured once as a HIP
+    graph (through torch's graph capture) and replayed with one launch."""
+
+    def __init__(self, reco: Reco, frames: DeviceFrames, mode: str = "persistent", tune=None):
+        self.reco, self.frames, self.mode, self.tune = reco, frames, mode, tune
+        N = frames.n_clusters
+        d = reco.device
+        self.up = torch.empty(N, dtype=torch.int32, device=d)
+        self.dn = torch.empty(N, dtype=torch.int32, device=d)
+        self.seeds = reco.alloc_seeds(frames)
+        self.tracks = reco.alloc_tracks(self.seeds)
+        stages = C.TPC_STAGE_PERSISTENT if mode == "persistent" else C.TPC_STAGE_ALL
+        self.ws = torch.empty(max(256, reco.workspace_bytes(frames, stages)), dtype=torch.uint8, device=d)
+        out = (self.up, self.dn, self.seeds, self.tracks)
+        # one eager run (also warms the code objects), then capture on a side stream
+        reco.reconstruct(frames, mode, tune, out, self.ws)
+        torch.cuda.synchronize(d)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            reco.reconstruct(frames, mode, tune, out, self.ws)
+        torch.cuda.synchronize(d)
+
+    def replay(self):
+        self.graph.replay()
+        return self.up, self.dn, self.seeds, self.tracks
 
 
 class KalmanChi2(torch.autograd.Function):

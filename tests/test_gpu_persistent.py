@@ -1,0 +1,116 @@
+"""GPU: the persistent single-launch form and its graph replay give the same
+results as the staged kernels and as the oracle; frames processed one by one
+(plain per-frame calls) agree with the batched call after rebasing ids."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import NB, MIN_HITS, FIT
+from tests import parity
+from tpcsynth import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _reco(fr):
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    return Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT),
+                "cuda:0")
+
+
+def _host(up, dn, seeds, tracks):
+    import torch
+    torch.cuda.synchronize()
+    sd = seeds.to_numpy()
+    T = len(sd["offsets"]) - 1
+    tr = {k: getattr(tracks, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "chi2", "ndf", "status")}
+    return up.cpu().numpy(), dn.cpu().numpy(), sd, tr, int(seeds.status.item())
+
+
+def _same(a, b, exact_fit=True):
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    parity.assert_seeds_equal(a[2], b[2])
+    assert a[4] == b[4] == 0
+    if exact_fit:
+        for k in ("x", "par", "cov", "chi2", "ndf", "status"):
+            np.testing.assert_array_equal(a[3][k], b[3][k], err_msg=k)
+
+
+def test_persistent_equals_staged_and_oracle():
+    fr = make_config(3, scale=0.02)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    print("[persistent] grid %d, N=%d" % (reco.persistent_grid(), fr.n_clusters), flush=True)
+    st = _host(*reco.reconstruct(dfr, "staged"))
+    pe = _host(*reco.reconstruct(dfr, "persistent"))
+    _same(st, pe)
+    ru, rd = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    np.testing.assert_array_equal(pe[0], ru)
+    rs = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, MIN_HITS)
+    parity.assert_seeds_equal(pe[2], rs)
+    rt = oracle.fit(rs, fr.y, fr.z, fr.row_x, fr.n_rows, **FIT)
+    print("[persistent]", parity.compare_fit(pe[3], rt), flush=True)
+
+
+@pytest.mark.parametrize("tune", [(0, 0), (64, 1), (7, 1)])
+def test_persistent_tune_variants_identical(tune):
+    fr = make_config(1, scale=0.1)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    ref = _host(*reco.reconstruct(dfr, "staged"))
+    got = _host(*reco.reconstruct(dfr, "persistent", tune=tune))
+    _same(ref, got)
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    from paper_2412_13755_amd.reco import ReconstructGraph
+    fr = make_config(3, scale=0.01)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    eager = _host(*reco.reconstruct(dfr, "staged"))
+    for mode in ("persistent", "staged"):
+        g = ReconstructGraph(reco, dfr, mode)
+        for rep in range(3):
+            # scribble over the outputs between replays so stale values cannot pass
+            g.up.fill_(-7)
+            g.seeds.hits.fill_(-7)
+            g.tracks.par.fill_(float("nan"))
+            torch.cuda.synchronize()
+            got = _host(*g.replay())
+            _same(eager, got)
+            print("[graph] %s replay %d ok" % (mode, rep), flush=True)
+
+
+def test_plain_per_frame_equals_batched():
+    import torch
+    fr = make_config(3, scale=0.01)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    batched = _host(*reco.reconstruct(dfr, "persistent"))
+    SR = fr.n_sectors * fr.n_rows
+    all_hits, all_first = [], []
+    for f in range(fr.n_frames):
+        v = dfr.frame_view(f, SR)
+        base = int(fr.row_offsets[f * SR])
+        up, dn, seeds, tracks = reco.reconstruct(v, "staged")
+        h = _host(up, dn, seeds, tracks)
+        np.testing.assert_array_equal(np.where(h[0] >= 0, h[0] + base, -1),
+                                      batched[0][base:base + v.n_clusters])
+        o = h[2]["offsets"]
+        all_first.append(h[2]["hits"][o[:-1]] + base if len(o) > 1 else np.zeros(0, np.int64))
+        all_hits.append(h[2]["hits"] + base)
+    np.testing.assert_array_equal(np.concatenate(all_hits), batched[2]["hits"])
+
+
+def test_autotuner_returns_a_valid_choice(tmp_path, monkeypatch):
+    from paper_2412_13755_amd import tune
+    monkeypatch.setenv("TPCRECO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    fr = make_config(1, scale=0.05)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    best = tune.autotune(reco, dfr, repeats=2)
+    assert best["mode"] in ("staged", "persistent") and len(best["table"]) >= 3
+    again = tune.autotune(reco, dfr)
+    assert again["cached"] and again["mode"] == best["mode"]
