@@ -1,13 +1,22 @@
 """Throughput of the TPC tracking path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,batched,adjoint]
 
 One step = neighbour finding + cellular-automaton seeding + Kalman fit of one
 synthetic time frame whose clusters are already resident in device memory
-(no host transfer inside the timed region).  The default workload is one
+(no host transfer inside the timed region).  The headline workload is one
 central Pb-Pb-like event over the full TPC: 36 sectors x 152 pad rows,
 10^4 helix tracks (8% low-pT loopers, half truncated), 10% noise, about
-1.3 M clusters.  Prints one JSON line.
+1.3 M clusters.  The launch form (staged kernels or one persistent kernel,
+grid, fit order) is the autotuner's choice for this workload.
+
+Extra legs, reported beside the headline value:
+  batched  64 time frames of uneven size (log-uniform 100..20000 tracks):
+           plain per-frame calls vs all frames in one persistent launch
+           replayed as a graph
+  adjoint  10^5 tracks with an injected distortion map: full gradient
+           evaluations per second (fit with checkpoints + chi2 sum + adjoint)
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,23 +31,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Method parameters of the workload (cm, GeV/c, T).
+# Method parameters of the workloads (cm, GeV/c, T).
 NB = dict(win_y=2.5, win_z=2.5, cut_y=0.6, cut_z=0.75)
 FIT = dict(bz=0.5, sigma_y=0.05, sigma_z=0.06, max_sin=0.999, var_sin0=1.0, var_tgl0=1.0,
            var_qpt0=100.0)
 MIN_HITS = 5
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VECTOR_PEAK = 157.3       # MI355X FP32 vector TFLOP/s
+VALU_PEAK_TFLOPS = 78.6        # MI355X vector FMA, FP64 (= non-packed FP32), TFLOP/s
 
-# Algorithmic traffic per unit (bytes): the method's own inputs and outputs at
-# each stage boundary.
+# Algorithmic work per unit: the method's own inputs and outputs per stage.
 B_NB_PER_CLUSTER = 16          # read y, z; write up, dn
 B_SEED_PER_CLUSTER = 8         # read up, dn
 B_SEED_PER_HIT = 4             # write seed hit id
 B_SEED_PER_SEED = 16           # write offset, frame, sector, first row
 B_FIT_PER_HIT = 12             # read hit id, y, z
-B_FIT_PER_TRACK = 24 + 96      # read seed record (offsets, first row, sector) + write 24 words
+B_FIT_PER_TRACK = 24 + 96      # read seed record; write 24 words
+FLOP_FIT_PER_HIT = 300         # helix step ~35, Jacobian ~30, F C F^T ~110, update ~125
 
 
 def parse():
@@ -46,10 +55,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="full-tpc-event-1e4")
+    ap.add_argument("--legs", default="main,batched,adjoint")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_reco(fr):
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    return Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT),
+                "cuda:0")
 
 
 def cpu_baseline(fr, budget_s):
@@ -68,10 +87,155 @@ def cpu_baseline(fr, budget_s):
         if time.perf_counter() - t_start > budget_s or len(times) >= 20:
             break
     t = float(np.median(times))
-    return {"value": fr.n_clusters / t / 1e6, "unit": "M clusters/s", "cores": int(oracle.max_threads()),
-            "kind": "oracle",
-            "sample": "whole frame (%d clusters), %d runs, median %.3f s; FP32 neighbours, "
-                      "integer seeding, FP64 fit" % (fr.n_clusters, len(times), t)}
+    return {"value": round(fr.n_clusters / t / 1e6, 4), "unit": "M clusters/s",
+            "cores": int(oracle.max_threads()), "kind": "oracle",
+            "sample": "the whole headline frame (%d clusters), %d runs, median %.3f s; FP32 "
+                      "neighbours, integer seeding, FP64 fit" % (fr.n_clusters, len(times), t)}
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def leg_main(args):
+    import torch
+    from paper_2412_13755_amd import tune
+    from paper_2412_13755_amd.reco import ReconstructGraph
+    from tpcsynth import make_config
+    fr = make_config(1)
+    log("headline workload: %d clusters" % fr.n_clusters)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    best = tune.autotune(reco, dfr, use_cache=False, repeats=5)
+    log("autotune: %s" % json.dumps(best))
+    out = reco.reconstruct(dfr, best["mode"], best["tune"])
+    torch.cuda.synchronize()
+    seeds = out[2]
+    n_seeds, n_hits = int(seeds.n_seeds.item()), int(seeds.n_hits.item())
+    assert int(seeds.status.item()) == 0
+    ms_eager = timed(lambda: reco.reconstruct(dfr, best["mode"], best["tune"], out),
+                     args.steps, args.warmup)
+    g = ReconstructGraph(reco, dfr, best["mode"], best["tune"])
+    ms_graph = timed(g.replay, args.steps, args.warmup)
+    ms = min(ms_eager, ms_graph)
+    # per-stage event timing of the staged path on the launch stream
+    stream = torch.cuda.current_stream()
+    ws = reco.workspace(dfr)
+    up, dn, sd, tr = reco.reconstruct(dfr, "staged")
+    evs = []
+    for i in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        reco.neighbours(dfr, up, dn, ws)
+        e[1].record(stream)
+        reco.seed(dfr, up, dn, sd, ws)
+        e[2].record(stream)
+        reco.fit(dfr, sd, None, tr, ws)
+        e[3].record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    st = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs])
+    stage_ms = st.mean(axis=0)
+    N = dfr.n_clusters
+    names = ["tpc_neighbours", "tpc_ca_seed", "tpc_kalman_fit (fit_tracks)"]
+    fit_ms = float(stage_ms[2])
+    fit_flops = FLOP_FIT_PER_HIT * n_hits
+    achieved = fit_flops / (fit_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5), "traffic": None,
+            "kernel": "fit_tracks", "avg_ms": round(fit_ms, 5),
+            "algorithmic_flops": int(fit_flops),
+            "algorithmic_bytes": int(B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds),
+            "hbm_frac": round((B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds)
+                              / (fit_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
+    nb_gbs = B_NB_PER_CLUSTER * N / (stage_ms[0] * 1e-3) / 1e9
+    seed_bytes = B_SEED_PER_CLUSTER * N + B_SEED_PER_HIT * n_hits + B_SEED_PER_SEED * n_seeds
+    res = {
+        "value": round(N / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 5),
+        "config": {"workload": fr.meta["name"], "clusters": N, "tracks_generated": fr.meta["n_tracks"],
+                   "seeds": n_seeds, "seed_hits": n_hits, "sectors": fr.n_sectors, "rows": fr.n_rows,
+                   "mode": best["mode"], "tune": best["tune"],
+                   "graph": ms_graph <= ms_eager},
+        "tracks_per_s": round(n_seeds / (ms * 1e-3), 1),
+        "ms_eager": round(ms_eager, 5), "ms_graph": round(ms_graph, 5),
+        "autotune_table": best["table"],
+        "stage_ms_staged": {n: round(float(v), 5) for n, v in zip(names, stage_ms)},
+        "stage_hbm_frac": {"tpc_neighbours": round(nb_gbs / HBM_PEAK_GBS, 5),
+                           "tpc_ca_seed": round(seed_bytes / (stage_ms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "roofline": roof,
+    }
+    return res, fr
+
+
+def leg_batched(args):
+    import torch
+    from paper_2412_13755_amd import tune
+    from paper_2412_13755_amd.reco import ReconstructGraph
+    from tpcsynth import make_config
+    fr = make_config(3)
+    log("batched workload: %d frames, %d clusters" % (fr.n_frames, fr.n_clusters))
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    SR = fr.n_sectors * fr.n_rows
+    views = [dfr.frame_view(f, SR) for f in range(fr.n_frames)]
+    outs = [reco.reconstruct(v, "staged") for v in views]
+    wsz = max(reco.workspace_bytes(v) for v in views)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+
+    def plain():
+        for v, o in zip(views, outs):
+            reco.reconstruct(v, "staged", None, o, ws)
+    steps = max(3, args.steps // 10)
+    ms_plain = timed(plain, steps, 2)
+    best = tune.autotune(reco, dfr, use_cache=False, repeats=3)
+    log("batched autotune: %s" % json.dumps({k: best[k] for k in ("mode", "tune", "ms")}))
+    g = ReconstructGraph(reco, dfr, "persistent", best["tune"] if best["mode"] == "persistent" else None)
+    ms_persist = timed(g.replay, steps, 2)
+    gs = ReconstructGraph(reco, dfr, "staged")
+    ms_staged_batched = timed(gs.replay, steps, 2)
+    N = dfr.n_clusters
+    return {"workload": fr.meta["name"], "frames": fr.n_frames, "clusters": N,
+            "plain_per_frame": {"ms": round(ms_plain, 4), "M_clusters_per_s": round(N / ms_plain / 1e3, 3)},
+            "batched_persistent_graph": {"ms": round(ms_persist, 4),
+                                         "M_clusters_per_s": round(N / ms_persist / 1e3, 3),
+                                         "tune": best["tune"] if best["mode"] == "persistent" else None},
+            "batched_staged_graph": {"ms": round(ms_staged_batched, 4),
+                                     "M_clusters_per_s": round(N / ms_staged_batched / 1e3, 3)},
+            "speedup_persistent_vs_plain": round(ms_plain / ms_persist, 3)}
+
+
+def leg_adjoint(args):
+    import torch
+    from paper_2412_13755_amd.reco import KalmanChi2
+    from tpcsynth import make_config
+    fr = make_config(4)
+    log("adjoint workload: %d clusters" % fr.n_clusters)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    torch.cuda.synchronize()
+    T = int(seeds.n_seeds.item())
+    H = int(seeds.n_hits.item())
+    m = torch.zeros(fr.n_sectors, fr.n_rows, 2, device="cuda", requires_grad=True)
+
+    def step():
+        m.grad = None
+        loss = KalmanChi2.apply(m, reco, dfr, seeds)
+        loss.backward()
+    steps = max(3, args.steps // 5)
+    ms = timed(step, steps, 2)
+    return {"workload": fr.meta["name"], "clusters": dfr.n_clusters, "seeds": T, "seed_hits": H,
+            "ms_per_gradient": round(ms, 4), "grads_per_s": round(1e3 / ms, 3),
+            "tracks_per_s": round(T / ms * 1e3, 1), "ckpt_rows": reco.cfg.ckpt_rows}
 
 
 def main():
@@ -80,84 +244,20 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import torch
-    from paper_2412_13755_amd.reco import Reco, RecoConfig
-    from tpcsynth import make_config, CONFIG_NAMES
-
-    k = CONFIG_NAMES.index(args.workload)
-    fr = make_config(k)
-    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT),
-                "cuda:0")
-    dfr = reco.upload(fr)
-    ws = reco.workspace(dfr)
-    up = torch.empty(dfr.n_clusters, dtype=torch.int32, device="cuda")
-    dn = torch.empty_like(up)
-    seeds = reco.alloc_seeds(dfr)
-    tracks = reco.alloc_tracks(seeds)
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        reco.neighbours(dfr, up, dn, ws)
-        if ev:
-            ev[1].record(stream)
-        reco.seed(dfr, up, dn, seeds, ws)
-        if ev:
-            ev[2].record(stream)
-        reco.fit(dfr, seeds, None, tracks, ws)
-        if ev:
-            ev[3].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    n_seeds = int(seeds.n_seeds.item())
-    n_hits = int(seeds.n_hits.item())
-    assert int(seeds.status.item()) == 0
-
-    # whole-step timing
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms = elapsed / args.steps * 1e3
-
-    # per-stage timing with events on the launch stream (separate pass)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    st = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs])  # ms
-    stage_ms = st.mean(axis=0)
-    N = dfr.n_clusters
-    stage_bytes = [
-        B_NB_PER_CLUSTER * N,
-        B_SEED_PER_CLUSTER * N + B_SEED_PER_HIT * n_hits + B_SEED_PER_SEED * n_seeds,
-        B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds,
-    ]
-    names = ["tpc_neighbours", "tpc_ca_seed", "tpc_kalman_fit"]
-    dom = int(np.argmax(stage_ms))
-    achieved = stage_bytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": names[dom],
-            "algorithmic_bytes": int(stage_bytes[dom]), "avg_ms": round(float(stage_ms[dom]), 5)}
-
-    value = N / (ms * 1e-3) / 1e6
+    legs = set(args.legs.split(","))
+    main_res, fr = leg_main(args)
     out = {
         "metric": "M clusters/s through CA seed+Kalman fit (plain vs batched); adjoint grads/s",
-        "value": round(value, 3), "unit": "M clusters/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": fr.meta["name"], "clusters": N, "tracks_generated": fr.meta["n_tracks"],
-                   "seeds": n_seeds, "seed_hits": n_hits, "sectors": fr.n_sectors, "rows": fr.n_rows,
-                   "mode": "plain"},
-        "tracks_per_s": round(n_seeds / (ms * 1e-3), 1),
-        "stage_ms": {n: round(float(v), 5) for n, v in zip(names, stage_ms)},
-        "roofline": roof,
+        "value": main_res.pop("value"), "unit": "M clusters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_res.pop("ms_per_step"), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": main_res.pop("config"),
     }
+    out.update(main_res)
+    if "batched" in legs:
+        out["batched"] = leg_batched(args)
+    if "adjoint" in legs:
+        out["adjoint"] = leg_adjoint(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fr, args.cpu_seconds)
     print(json.dumps(out), flush=True)
