@@ -16,6 +16,8 @@ Extra legs, reported beside the headline value:
            replayed as a graph
   adjoint  10^5 tracks with an injected distortion map: full gradient
            evaluations per second (fit with checkpoints + chi2 sum + adjoint)
+  copy     a 1 GiB device copy (reference for the HBM traffic counters; run
+           alone with --legs copy)
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -238,6 +240,17 @@ def leg_adjoint(args):
             "tracks_per_s": round(T / ms * 1e3, 1), "ckpt_rows": reco.cfg.ckpt_rows}
 
 
+def leg_copy(args):
+    """A plain device copy of known size (calibrates the HBM traffic counters)."""
+    import torch
+    n = 1 << 28                                   # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = timed(lambda: b.copy_(a), 5, 1)
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": round(ms, 4),
+            "GB_per_s": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -245,6 +258,9 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
+    if legs == {"copy"}:
+        print(json.dumps({"copy": leg_copy(args)}), flush=True)
+        return
     main_res, fr = leg_main(args)
     out = {
         "metric": "M clusters/s through CA seed+Kalman fit (plain vs batched); adjoint grads/s",
@@ -258,6 +274,8 @@ def main():
         out["batched"] = leg_batched(args)
     if "adjoint" in legs:
         out["adjoint"] = leg_adjoint(args)
+    if "copy" in legs:
+        out["copy"] = leg_copy(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fr, args.cpu_seconds)
     print(json.dumps(out), flush=True)
