@@ -135,12 +135,14 @@ static int adj_blocks(int32_t cap_seeds) {
 }
 
 size_t adj_ws_layout(void *ws, int64_t cap_hits, int64_t cap_seeds, int64_t n_fs, int32_t n_rows,
-                     int32_t K, float2 **g, double **tape, float2 **partial) {
+                     int32_t K, float2 **g, double **tape, float2 **partial, float2 **hyz) {
     WsCarver w(ws);
     float2 *pg = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
     const int64_t nthreads = (int64_t)adj_blocks((int32_t)(cap_seeds < 0x7fffffff ? cap_seeds : 0x7fffffff)) * TPC_BLOCK;
     double *pt = w.take<double>(nthreads * K * TPC_CKPT_WORDS);
     float2 *pp = w.take<float2>(n_fs * TPC_ADJ_GROUPS * n_rows);
+    float2 *ph = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
+    if (hyz) *hyz = ph;
     if (g) *g = pg;
     if (tape) *tape = pt;
     if (partial) *partial = pp;
@@ -157,7 +159,10 @@ hipError_t launch_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tp
     A.status = tr->status;
     A.ckpt = ckpt;
     float2 *partial;
-    adj_ws_layout(ws, sd->cap_hits, sd->cap_seeds, n_fs, c.n_rows, c.ckpt_rows, &A.g, &A.tape, &partial);
+    float2 *hyz;
+    adj_ws_layout(ws, sd->cap_hits, sd->cap_seeds, n_fs, c.n_rows, c.ckpt_rows, &A.g, &A.tape, &partial, &hyz);
+    A.F.hyz = hyz;
+    launch_gather(fr, sd, hyz, st);
     const int blocks = adj_blocks(sd->cap_seeds);
     A.nthreads = blocks * TPC_BLOCK;
     hipLaunchKernelGGL(adj_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);

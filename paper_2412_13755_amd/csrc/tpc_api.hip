@@ -56,12 +56,14 @@ tpc_status check_ws(void *ws, size_t have, size_t need) {
 // Seeds hold >= min_hits distinct clusters: default capacities never overflow.
 int64_t seed_cap_bound(const tpc_context *ctx, int64_t N) { return N / ctx->cfg.min_hits + 1; }
 
-size_t fit_bytes(int64_t cap_seeds) { return chi2_ws_layout(nullptr, cap_seeds, nullptr); }
+size_t fit_bytes(int64_t cap_seeds, int64_t cap_hits) {
+    return fit_ws_layout(nullptr, cap_seeds, cap_hits, nullptr, nullptr);
+}
 
 size_t adjoint_bytes(const tpc_context *ctx, const tpc_frames *fr, int64_t cap_hits, int64_t cap_seeds) {
     const int64_t n_fs = (int64_t)fr->n_frames * ctx->cfg.n_sectors;
     return adj_ws_layout(nullptr, cap_hits, cap_seeds, n_fs, ctx->cfg.n_rows, ctx->cfg.ckpt_rows,
-                         nullptr, nullptr, nullptr);
+                         nullptr, nullptr, nullptr, nullptr);
 }
 
 size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
@@ -70,9 +72,10 @@ size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
     size_t b = 0;
     if (mask & TPC_STAGE_NEIGHBOURS) b = std::max(b, nb_ws_layout(nullptr, N, NR, nullptr));
     if (mask & TPC_STAGE_SEED) b = std::max(b, ca_ws_layout(nullptr, N, NR, nullptr));
-    if (mask & TPC_STAGE_FIT) b = std::max(b, fit_bytes(cs));
+    if (mask & TPC_STAGE_FIT) b = std::max(b, fit_bytes(cs, N > 0 ? N : 1));
     if (mask & TPC_STAGE_ADJOINT) b = std::max(b, adjoint_bytes(ctx, fr, N > 0 ? N : 1, cs));
-    if (mask & TPC_STAGE_PERSISTENT) b = std::max(b, persist_ws_layout(nullptr, N, NR, cs, nullptr));
+    if (mask & TPC_STAGE_PERSISTENT)
+        b = std::max(b, persist_ws_layout(nullptr, N, NR, cs, N > 0 ? N : 1, nullptr));
     return b;
 }
 
@@ -237,9 +240,9 @@ tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *fr, const tp
         if (ckpt_bytes_have < need)
             return fail(TPC_ERR_WORKSPACE, "checkpoint buffer has %zu bytes, %zu needed", ckpt_bytes_have, need);
     }
-    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds)))) return s;
+    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds, sd->cap_hits)))) return s;
     if (sd->cap_seeds == 0) return TPC_OK;
-    hipError_t e = launch_fit(ctx, fr, sd, map, tr, (double *)ckpt, (hipStream_t)stream);
+    hipError_t e = launch_fit(ctx, fr, sd, map, tr, (double *)ckpt, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
 }
 
@@ -251,7 +254,7 @@ tpc_status tpc_chi2_sum(const tpc_context *ctx, const tpc_seeds *sd, const tpc_t
     if (s) return s;
     if ((s = check_tracks(sd, tr))) return s;
     if (!loss) return fail(TPC_ERR_ARG, "null loss");
-    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds)))) return s;
+    if ((s = check_ws(ws, ws_bytes, chi2_ws_layout(nullptr, sd->cap_seeds, nullptr)))) return s;
     hipError_t e = launch_chi2_sum(sd, tr, loss, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "chi2 sum kernels");
 }
@@ -301,7 +304,8 @@ tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *fr, int32_t
         return tpc_kalman_fit(ctx, fr, sd, nullptr, tr, nullptr, 0, ws, ws_bytes, stream);
     }
     const int64_t NR = n_segments(ctx, fr);
-    if ((s = check_ws(ws, ws_bytes, persist_ws_layout(nullptr, fr->n_clusters, NR, sd->cap_seeds, nullptr))))
+    if ((s = check_ws(ws, ws_bytes, persist_ws_layout(nullptr, fr->n_clusters, NR, sd->cap_seeds,
+                                                      sd->cap_hits, nullptr))))
         return s;
     int grid = ctx->persist_grid;
     if (tune && tune->grid > 0 && tune->grid < grid) grid = tune->grid;

@@ -11,10 +11,11 @@
 // length, then bottom id; seeds are placed by prefix sums in cluster-id
 // order), so it matches the sequential definition exactly.
 //
-//   ca_chains  bottoms (no kept link down, a kept link up) walk their chain,
-//              recording the bottom and position of every member, its length
-//              and top; every cluster's claim slot is reset
-//   ca_claims  chains of >= min_hits-2 clusters claim their unlinked ends
+//   ca_links   reset claim slots and chain lengths; jump words point one
+//              kept link down
+//   ca_jump    pointer jumping to the chain bottom gives every chain member
+//              its bottom and position; each chain's top records its length
+//              and claims the chain's unlinked ends (>= min_hits-2 clusters)
 //   ca_firsts  each seed is recognised at its first cluster (the won bottom
 //              end or the bottom itself); per-segment seed and hit counts
 //   ca_scan    exclusive prefix over segments, totals, capacity check
@@ -43,47 +44,67 @@ __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
     return ((unsigned long long)(2147483648u - (uint32_t)m) << 32) | (uint32_t)b;
 }
 
-__device__ inline void ca_chains_seg(int seg, int32_t N, const int32_t *__restrict__ off,
-                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
-                                     int32_t n_rows, const CaWs &ws) {
+// Chain ranking by pointer jumping.  pack[h] = (distance << 32) | node: the
+// node h currently points to (towards the chain bottom) and how many links
+// down it is.  A bottom or unlinked cluster points to itself at distance 0.
+
+// Step 1: reset the claim slot, chain length, and the jump word of every
+// cluster of the segment.
+__device__ inline void ca_links_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                    const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                    const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
         ws.claim[h] = ~0ull;
-        int32_t u = link_up(up, dn, N, h);
-        bool bottom = (u >= 0) && link_dn(up, dn, N, h) < 0;
-        if (!bottom) {
-            ws.core[h] = 0;
-            continue;
-        }
-        ws.memb[h] = h;
-        ws.mpos[h] = 0;
-        int32_t cur = h, m = 1;
-        // walk: one dependent load pair per step; a chain holds at most one
-        // cluster per row, which also bounds the walk on corrupt input
-        while (u >= 0 && m < n_rows) {
-            cur = u;
-            ws.memb[cur] = h;
-            ws.mpos[cur] = m;
-            ++m;
-            u = link_up(up, dn, N, cur);
-        }
-        ws.core[h] = m;
-        ws.ctop[h] = cur;
-        ws.choff[h] = -1;
+        ws.core[h] = 0;
+        const int32_t d = link_dn(up, dn, N, h);
+        ws.pack[h] = d >= 0 ? ((1ull << 32) | (uint32_t)d) : (unsigned long long)(uint32_t)h;
     }
 }
 
-__device__ inline void ca_claims_seg(int seg, int32_t N, const int32_t *__restrict__ off,
-                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
-                                     int32_t min_hits, const CaWs &ws) {
+// Step 2: every linked cluster jumps its pointer to the chain bottom
+// (w <- pack[ptr(w)], distances added), which takes about log2(chain length)
+// rounds when the chain's clusters jump concurrently.  Each word is written
+// only by its own thread and always holds a valid (node, distance) pair, so
+// the result does not depend on timing; every round moves the pointer
+// strictly closer to the bottom, so the loop ends.  Then the top of each
+// chain records the chain length and top at the bottom and claims the
+// chain's unlinked end clusters (chains of >= min_hits - 2 clusters).
+__device__ inline void ca_jump_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                   const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                   int32_t min_hits, int32_t n_rows, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        int32_t m = ws.core[h];
-        if (m < 2 || m < min_hits - 2) continue;
-        unsigned long long key = claim_key(m, h);
-        int32_t eb = dn[h], et = up[ws.ctop[h]];
-        if (valid_id(eb, N) && !linked(up, dn, N, eb)) atomicMin(&ws.claim[eb], key);
-        if (valid_id(et, N) && !linked(up, dn, N, et)) atomicMin(&ws.claim[et], key);
+        const int32_t u = link_up(up, dn, N, h);
+        const int32_t d = link_dn(up, dn, N, h);
+        if (u < 0 && d < 0) continue;                 // not linked
+        unsigned long long w = ws.pack[h];
+        for (int it = 0; it < n_rows; ++it) {         // bound: a chain has < n_rows links
+            const int32_t p = (int32_t)(uint32_t)w;
+            if (p == h) break;                        // h is the bottom
+            const unsigned long long v =
+                __hip_atomic_load(&ws.pack[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t pp = (int32_t)(uint32_t)v;
+            if (pp == p) break;                       // p is the bottom
+            w = (((w >> 32) + (v >> 32)) << 32) | (uint32_t)pp;
+            __hip_atomic_store(&ws.pack[h], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const int32_t bot = (int32_t)(uint32_t)w;
+        const int32_t pos = (int32_t)(w >> 32);
+        ws.memb[h] = bot;
+        ws.mpos[h] = pos;
+        if (u < 0) {                                  // h is the top: chain of pos + 1 clusters
+            const int32_t m = pos + 1;
+            ws.core[bot] = m;
+            ws.ctop[bot] = h;
+            ws.choff[bot] = -1;
+            if (m >= min_hits - 2) {
+                const unsigned long long key = claim_key(m, bot);
+                const int32_t eb = dn[bot], et = up[h];
+                if (valid_id(eb, N) && !linked(up, dn, N, eb)) atomicMin(&ws.claim[eb], key);
+                if (valid_id(et, N) && !linked(up, dn, N, et)) atomicMin(&ws.claim[et], key);
+            }
+        }
     }
 }
 

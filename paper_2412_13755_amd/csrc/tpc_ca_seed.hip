@@ -8,13 +8,14 @@ namespace {
 using namespace tpc_ca;
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-ca_chains(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t n_rows, CaWs ws) {
-    ca_chains_seg(blockIdx.x, N, off, up, dn, n_rows, ws);
+ca_links(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, CaWs ws) {
+    ca_links_seg(blockIdx.x, N, off, up, dn, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-ca_claims(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t min_hits, CaWs ws) {
-    ca_claims_seg(blockIdx.x, N, off, up, dn, min_hits, ws);
+ca_jump(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t min_hits,
+        int32_t n_rows, CaWs ws) {
+    ca_jump_seg(blockIdx.x, N, off, up, dn, min_hits, n_rows, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -87,8 +88,8 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
     const int NR = fr->n_frames * c.n_sectors * c.n_rows;
     const int32_t *off = fr->row_offsets;
     const int32_t N = fr->n_clusters;
-    hipLaunchKernelGGL(ca_chains, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.n_rows, ws);
-    hipLaunchKernelGGL(ca_claims, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, ws);
+    hipLaunchKernelGGL(ca_links, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, ws);
+    hipLaunchKernelGGL(ca_jump, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, c.n_rows, ws);
     hipLaunchKernelGGL(ca_firsts, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, ws);
     hipLaunchKernelGGL(ca_scan, dim3(1), dim3(1024), 0, st, NR, ws, sd->n_seeds, sd->n_hits,
                        sd->cap_seeds, sd->cap_hits, sd->offsets, dev_status);
@@ -102,6 +103,7 @@ size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out) {
     WsCarver w(ws);
     CaWs l;
     l.claim = w.take<unsigned long long>(N);
+    l.pack = w.take<unsigned long long>(N);
     l.core = w.take<int32_t>(N);
     l.ctop = w.take<int32_t>(N);
     l.memb = w.take<int32_t>(N);

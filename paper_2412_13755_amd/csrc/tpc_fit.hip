@@ -20,6 +20,19 @@ fit_tracks(FitArgs A) {
         fit_one(A, i, xs);
 }
 
+// (y, z) of every seed hit in seed-hit order, so the fit reads each seed's
+// measurements contiguously instead of through the id indirection.
+__global__ void __launch_bounds__(TPC_BLOCK)
+gather_hits(const int32_t *__restrict__ n_hits, int32_t cap_hits, const int32_t *__restrict__ hits,
+            const float *__restrict__ y, const float *__restrict__ z, int32_t N, float2 *__restrict__ hyz) {
+    int H = *n_hits;
+    if (H > cap_hits) H = cap_hits;
+    for (int j = blockIdx.x * TPC_BLOCK + threadIdx.x; j < H; j += gridDim.x * TPC_BLOCK) {
+        const int32_t id = hits[j];
+        hyz[j] = (uint32_t)id < (uint32_t)N ? make_float2(y[id], z[id]) : make_float2(0.f, 0.f);
+    }
+}
+
 // Deterministic sum of chi2 over successful tracks: fixed partition of the
 // seed range into blocks, fixed reduction tree, FP64 accumulation.
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -82,15 +95,29 @@ FitArgs make_fit_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
     A.var_w = c.var_qpt0;
     A.ckpt = nullptr;
     A.ckpt_rows = c.ckpt_rows;
+    A.hyz = nullptr;
     A.out = tpc_tracks{};
     return A;
 }
 
+hipError_t launch_gather(const tpc_frames *fr, const tpc_seeds *sd, float2 *hyz, hipStream_t st) {
+    int blocks = (sd->cap_hits + TPC_BLOCK - 1) / TPC_BLOCK;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(gather_hits, dim3(blocks), dim3(TPC_BLOCK), 0, st, sd->n_hits, sd->cap_hits,
+                       sd->hits, fr->y, fr->z, fr->n_clusters, hyz);
+    return hipGetLastError();
+}
+
 hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
-                      const float *map, const tpc_tracks *tr, double *ckpt, hipStream_t st) {
+                      const float *map, const tpc_tracks *tr, double *ckpt, void *ws, hipStream_t st) {
     FitArgs A = make_fit_args(ctx, fr, sd, map);
     A.out = *tr;
     A.ckpt = ckpt;
+    float2 *hyz;
+    fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz);
+    A.hyz = hyz;
+    launch_gather(fr, sd, hyz, st);
     int blocks = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
@@ -103,6 +130,16 @@ size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part) {
     const int64_t nb = (cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     double *p = w.take<double>(nb > 0 ? nb : 1);
     if (part) *part = p;
+    return (w.off + 255) & ~size_t(255);
+}
+
+// Fit workspace: the chi2 partials, then the seed-ordered hit coordinates.
+size_t fit_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, double **part, float2 **hyz) {
+    const size_t a = chi2_ws_layout(ws, cap_seeds, part);
+    WsCarver w(ws);
+    w.off = a;
+    float2 *h = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
+    if (hyz) *hyz = h;
     return (w.off + 255) & ~size_t(255);
 }
 

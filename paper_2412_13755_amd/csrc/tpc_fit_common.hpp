@@ -10,6 +10,7 @@ struct FitArgs {
     const int32_t *offsets, *hits, *sector, *first_row, *n_seeds;
     int32_t cap_seeds, cap_hits;
     const float *y, *z, *row_x, *map;
+    const float2 *hyz;     // (y, z) of every seed hit in seed-hit order, or null
     int32_t n_rows, n_sectors, n_clusters;
     float kbz, max_sin;
     double vy, vz, var_s, var_t, var_w;
@@ -40,25 +41,37 @@ __host__ __device__ inline SeedView seed_view(const FitArgs &A, int i) {
     return v;
 }
 
-// Corrected measurement of hit k (global id `id`) in double precision.
-__host__ __device__ inline void hit_meas(const FitArgs &A, const SeedView &v, int k, int32_t id, double &my,
-                                double &mz) {
+// Raw (y, z) of hit k of the seed (global id `id`): from the seed-ordered
+// copy when there is one (contiguous per seed, no id indirection).
+__host__ __device__ inline float2 hit_raw(const FitArgs &A, const SeedView &v, int k, int32_t id) {
+    if (A.hyz) return A.hyz[v.o0 + k];
     const uint32_t NC = (uint32_t)A.n_clusters;
     const int32_t j = (uint32_t)id < NC ? id : 0;
-    my = (double)A.y[j];
-    mz = (double)A.z[j];
+    return make_float2(A.y[j], A.z[j]);
+}
+
+// Corrected measurement of hit k in double precision.
+__host__ __device__ inline void hit_fix(const FitArgs &A, const SeedView &v, int k, float2 raw,
+                                        double &my, double &mz) {
+    my = (double)raw.x;
+    mz = (double)raw.y;
     if (v.mp) {
         my -= (double)v.mp[(v.row0 + k) * 2];
         mz -= (double)v.mp[(v.row0 + k) * 2 + 1];
     }
 }
 
+__host__ __device__ inline void hit_meas(const FitArgs &A, const SeedView &v, int k, int32_t id, double &my,
+                                         double &mz) {
+    hit_fix(A, v, k, hit_raw(A, v, k, id), my, mz);
+}
+
 __host__ __device__ inline bool start_state(const FitArgs &A, const SeedView &v, const float *xs, double p[5]) {
     const int ka = v.n - 1, kb = (v.n - 1) / 2;
     double ya, za, yb, zb, yc, zc;
-    hit_meas(A, v, ka, v.hh[ka], ya, za);
-    hit_meas(A, v, kb, v.hh[kb], yb, zb);
-    hit_meas(A, v, 0, v.hh[0], yc, zc);
+    hit_meas(A, v, ka, A.hyz ? 0 : v.hh[ka], ya, za);
+    hit_meas(A, v, kb, A.hyz ? 0 : v.hh[kb], yb, zb);
+    hit_meas(A, v, 0, A.hyz ? 0 : v.hh[0], yc, zc);
     (void)zb;
     return helix_start<double>(xs[v.row0 + ka], ya, za, xs[v.row0 + kb], yb, xs[v.row0], yc, zc,
                                A.kbz, A.max_sin, p);
@@ -103,12 +116,12 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
     double *ck = A.ckpt ? A.ckpt + (size_t)ckpt_slot(sv.o0, i, A.ckpt_rows) * TPC_CKPT_WORDS : nullptr;
     if (status == TPC_FIT_OK) {
         if (ck) write_ckpt(ck, p, C);
-        int32_t id_next = sv.hh[sv.n - 2];
+        float2 raw_next = hit_raw(A, sv, sv.n - 2, A.hyz ? 0 : sv.hh[sv.n - 2]);
         for (int k = sv.n - 2, j = 1; k >= 0; --k, ++j) {
-            const int32_t id = id_next;
-            if (k > 0) id_next = sv.hh[k - 1];          // prefetch the next id
+            const float2 raw = raw_next;
+            if (k > 0) raw_next = hit_raw(A, sv, k - 1, A.hyz ? 0 : sv.hh[k - 1]);   // prefetch
             double my, mz;
-            hit_meas(A, sv, k, id, my, mz);
+            hit_fix(A, sv, k, raw, my, mz);
             const float xk = xs[sv.row0 + k];
             StepJac J;
             if (!helix_step(p, xk - xcur, A.kbz, A.max_sin, J)) {
@@ -196,7 +209,7 @@ __host__ __device__ inline void adj_one(const FitArgs &F, const int32_t *status,
             const int k = n - 1 - j;
             tape_put(tp, stride, j - j0 - 1, p, C);
             double my, mz;
-            hit_meas(F, sv, k, sv.hh[k], my, mz);
+            hit_meas(F, sv, k, F.hyz ? 0 : sv.hh[k], my, mz);
             const float xk = xs[sv.row0 + k];
             StepJac J;
             helix_step(p, xk - xcur, F.kbz, 2.0f, J);
@@ -210,7 +223,7 @@ __host__ __device__ inline void adj_one(const FitArgs &F, const int32_t *status,
             SymT<double> Cb;
             tape_get(tp, stride, j - j0 - 1, pb, Cb);
             double my, mz;
-            hit_meas(F, sv, k, sv.hh[k], my, mz);
+            hit_meas(F, sv, k, F.hyz ? 0 : sv.hh[k], my, mz);
             const float dx = xs[sv.row0 + k] - xs[sv.row0 + k + 1];
             double mby, mbz;
             step_adjoint<double>(pb, Cb, dx, F.kbz, my, mz, F.vy, F.vz, 1.0, pbar, Cbar, mby, mbz);
@@ -220,9 +233,9 @@ __host__ __device__ inline void adj_one(const FitArgs &F, const int32_t *status,
     // three-point start: hits A = n-1, B = (n-1)/2, C = 0
     const int ka = n - 1, kb = (n - 1) / 2;
     double ya, za, yb, zb, yc, zc;
-    hit_meas(F, sv, ka, sv.hh[ka], ya, za);
-    hit_meas(F, sv, kb, sv.hh[kb], yb, zb);
-    hit_meas(F, sv, 0, sv.hh[0], yc, zc);
+    hit_meas(F, sv, ka, F.hyz ? 0 : sv.hh[ka], ya, za);
+    hit_meas(F, sv, kb, F.hyz ? 0 : sv.hh[kb], yb, zb);
+    hit_meas(F, sv, 0, F.hyz ? 0 : sv.hh[0], yc, zc);
     (void)zb;
     double bya, bza, byb, byc, bzc;
     start_adjoint<double>(xs[sv.row0 + ka], ya, za, xs[sv.row0 + kb], yb, xs[sv.row0], yc, zc, F.kbz,

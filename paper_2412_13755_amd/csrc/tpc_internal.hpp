@@ -49,6 +49,7 @@ struct NbWs {
 
 struct CaWs {
     unsigned long long *claim;   // [N] smallest claim key per cluster
+    unsigned long long *pack;    // [N] pointer-jumping word: (distance << 32) | node
     int32_t *core;               // [N] chain length at a bottom, 0 elsewhere
     int32_t *ctop;               // [N] chain top at a bottom
     int32_t *memb;               // [N] bottom of the chain a linked cluster is in
@@ -63,11 +64,14 @@ struct CaWs {
 size_t nb_ws_layout(void *ws, int64_t N, int64_t NR, NbWs *out);
 size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out);
 size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part);
+size_t fit_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, double **part, float2 **hyz);
+hipError_t launch_gather(const tpc_frames *fr, const tpc_seeds *sd, float2 *hyz, hipStream_t st);
 size_t adj_ws_layout(void *ws, int64_t cap_hits, int64_t cap_seeds, int64_t n_fs, int32_t n_rows,
-                     int32_t K, float2 **g, double **tape, float2 **partial);
+                     int32_t K, float2 **g, double **tape, float2 **partial, float2 **hyz);
 
 struct PersistArgs;
-size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, PersistArgs *P);
+size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, int64_t cap_hits,
+                         PersistArgs *P);
 int persist_grid(const tpc_context *ctx);
 hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
                              const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status,
@@ -80,7 +84,7 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
                           const int32_t *dn, const tpc_seeds *sd, int32_t *dev_status,
                           const CaWs &ws, hipStream_t st);
 hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
-                      const float *map, const tpc_tracks *tr, double *ckpt, hipStream_t st);
+                      const float *map, const tpc_tracks *tr, double *ckpt, void *ws, hipStream_t st);
 hipError_t launch_chi2_sum(const tpc_seeds *sd, const tpc_tracks *tr, float *loss, void *ws,
                            hipStream_t st);
 hipError_t launch_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,

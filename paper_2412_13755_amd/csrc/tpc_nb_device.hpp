@@ -10,14 +10,16 @@
 // functions below carry "fp contract(off)" and the stage file is compiled
 // with -ffp-contract=off, so no multiply-add is fused.
 //
-// Design: two passes, one workgroup per (frame, sector, row) segment.
-//  1. nb_bin: per segment, a y-z cell grid sized from the data (cell edges at
-//     least 1.01 x the window, at most one cell per cluster, at most
-//     TPC_CELL_CAP cells); an LDS counting sort writes the segment's clusters
-//     cell by cell (coalesced SoA y, z, id) and the cell start table.
-//  2. nb_query: each thread takes one cluster h in cell order, so a wavefront
-//     walks neighbouring cells of rows r+1 and r-1 together; for each
-//     candidate the window/cut predicates are evaluated exactly as defined.
+// Design: one workgroup per h-row (frame, sector, row) segment.  Each of
+// the two neighbouring rows is put on a y-z cell grid sized from the data
+// (cell edges at least 1.01 x the window, at most one cell per cluster) and
+// counting-sorted by cell; then every thread takes clusters h of its row and
+// scans the 3x3 cells around h in the up row, and for each up candidate in
+// the window, the 3x3 cells in the down row.  Rows of up to TPC_LDS_ROW
+// clusters are binned by the query workgroup itself into LDS (the row pair
+// is read once, coalesced, and every candidate access is an LDS access);
+// larger rows use a cell-sorted copy in global memory written beforehand by
+// nb_bin (at most TPC_CELL_CAP cells per row).
 // Candidates with |y_u - y_h| <= win differ by at most one cell because the
 // cell edge exceeds the window by 1%, far more than the rounding of the cell
 // coordinate, and clamping keeps that bound; so scanning the 3x3 cells
@@ -36,38 +38,39 @@ __device__ inline int cell_coord(float v, float v0, float iw, int n) {
     return (int)c;                                  // floor for c >= 0
 }
 
-// Bins the clusters of segment `seg` (whole workgroup; contains barriers).
-__device__ inline void nb_bin_seg(int seg, const int32_t *__restrict__ off, const float *__restrict__ y,
-                                  const float *__restrict__ z, float win_y, float win_z,
-                                  SegGrid *__restrict__ grid, int32_t *__restrict__ cstart,
-                                  float *__restrict__ sy, float *__restrict__ sz,
-                                  int32_t *__restrict__ sid) {
+// Grid of one row: cell edges >= 1.01 x the window, at most min(n, cap)
+// cells.  ext = (ymin, ymax, zmin, zmax) of the finite coordinates.
+__device__ inline SegGrid row_grid(float ymin, float ymax, float zmin, float zmax, int n, int cap,
+                                   float win_y, float win_z) {
 #pragma clang fp contract(off)
-    __shared__ int cnt[TPC_CELL_CAP];
-    __shared__ float red[4][TPC_BLOCK / TPC_WAVE];
-    __shared__ int scan_sh[TPC_BLOCK / TPC_WAVE];
-    __syncthreads();                 // LDS reuse across calls in a persistent loop
-    const int a = off[seg], b = off[seg + 1], n = b - a;
-    const int base = a + seg;
-    const int tid = threadIdx.x;
-    if (n == 0) {
-        if (tid == 0) {
-            SegGrid g = {0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
-            grid[seg] = g;
-            cstart[base] = a;
-        }
-        return;
-    }
-    // finite extent of the segment
+    if (!(ymin <= ymax)) { ymin = 0.f; ymax = 0.f; }
+    if (!(zmin <= zmax)) { zmin = 0.f; zmax = 0.f; }
+    const int c = n < cap ? n : cap;
+    const float ry = ymax - ymin, rz = zmax - zmin;
+    const float fz = rz / (1.01f * win_z), fy = ry / (1.01f * win_y);
+    const int nzmax = fz >= (float)c ? c : (fz >= 1.0f ? (int)fz : 1);
+    const int nymax = fy >= (float)c ? c : (fy >= 1.0f ? (int)fy : 1);
+    const int nz = nzmax;
+    int ny = c / nz;
+    if (ny > nymax) ny = nymax;
+    if (ny < 1) ny = 1;
+    SegGrid g = {ymin, zmin, ny > 1 ? (float)ny / ry : 0.f, nz > 1 ? (float)nz / rz : 0.f, ny, nz, 0, 0};
+    return g;
+}
+
+// Finite extent of clusters [a, b) (whole workgroup; contains barriers).
+__device__ inline void row_extent(const float *__restrict__ y, const float *__restrict__ z, int a, int b,
+                                  float (*red)[TPC_BLOCK / TPC_WAVE], float ext[4]) {
     float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
-    for (int i = a + tid; i < b; i += TPC_BLOCK) {
-        float yv = y[i], zv = z[i];
+    for (int i = a + (int)threadIdx.x; i < b; i += TPC_BLOCK) {
+        const float yv = y[i], zv = z[i];
         if (isfinite(yv)) { ymin = fminf(ymin, yv); ymax = fmaxf(ymax, yv); }
         if (isfinite(zv)) { zmin = fminf(zmin, zv); zmax = fmaxf(zmax, zv); }
     }
     ymin = wave_min(ymin); ymax = wave_max(ymax);
     zmin = wave_min(zmin); zmax = wave_max(zmax);
-    const int wid = tid / TPC_WAVE, lane = tid & (TPC_WAVE - 1);
+    const int wid = threadIdx.x / TPC_WAVE, lane = threadIdx.x & (TPC_WAVE - 1);
+    __syncthreads();
     if (lane == 0) { red[0][wid] = ymin; red[1][wid] = ymax; red[2][wid] = zmin; red[3][wid] = zmax; }
     __syncthreads();
     ymin = red[0][0]; ymax = red[1][0]; zmin = red[2][0]; zmax = red[3][0];
@@ -75,29 +78,27 @@ __device__ inline void nb_bin_seg(int seg, const int32_t *__restrict__ off, cons
         ymin = fminf(ymin, red[0][w]); ymax = fmaxf(ymax, red[1][w]);
         zmin = fminf(zmin, red[2][w]); zmax = fmaxf(zmax, red[3][w]);
     }
-    if (!(ymin <= ymax)) { ymin = 0.f; ymax = 0.f; }
-    if (!(zmin <= zmax)) { zmin = 0.f; zmax = 0.f; }
-    // cell counts: edges >= 1.01 * window, cells <= min(n, cap)
-    const int cap = n < TPC_CELL_CAP ? n : TPC_CELL_CAP;
-    const float ry = ymax - ymin, rz = zmax - zmin;
-    float fz = rz / (1.01f * win_z), fy = ry / (1.01f * win_y);
-    int nzmax = fz >= (float)cap ? cap : (fz >= 1.0f ? (int)fz : 1);
-    int nymax = fy >= (float)cap ? cap : (fy >= 1.0f ? (int)fy : 1);
-    int nz = nzmax;
-    int ny = cap / nz;
-    if (ny > nymax) ny = nymax;
-    if (ny < 1) ny = 1;
-    const float iwy = ny > 1 ? (float)ny / ry : 0.f;
-    const float iwz = nz > 1 ? (float)nz / rz : 0.f;
-    const int cells = ny * nz;
+    ext[0] = ymin; ext[1] = ymax; ext[2] = zmin; ext[3] = zmax;
+}
+
+// Counting sort of clusters [a, b) by cell of grid g (whole workgroup;
+// contains barriers).  Writes y, z, global id in cell order to
+// dy/dz/did[obase + k] and cell starts cs[c] = obase + first position of
+// cell c, cs[cells] = obase + n.  cnt: LDS scratch of >= cells ints.
+__device__ inline void row_sort(const float *__restrict__ y, const float *__restrict__ z, int a, int b,
+                                const SegGrid &g, int *cnt, int *scan_sh, float *dy, float *dz, int32_t *did,
+                                int32_t *cs, int obase) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const int cells = g.ny * g.nz;
     for (int c = tid; c < cells; c += TPC_BLOCK) cnt[c] = 0;
     __syncthreads();
     for (int i = a + tid; i < b; i += TPC_BLOCK) {
-        int c = cell_coord(y[i], ymin, iwy, ny) * nz + cell_coord(z[i], zmin, iwz, nz);
+        const int c = cell_coord(y[i], g.y0, g.iwy, g.ny) * g.nz + cell_coord(z[i], g.z0, g.iwz, g.nz);
         atomicAdd(&cnt[c], 1);
     }
     __syncthreads();
-    // exclusive scan of cnt: each thread owns a contiguous run of cells
+    // exclusive scan: each thread owns a contiguous run of cells
     const int per = (cells + TPC_BLOCK - 1) / TPC_BLOCK;
     const int c0 = tid * per;
     int c1 = c0 + per;
@@ -107,25 +108,68 @@ __device__ inline void nb_bin_seg(int seg, const int32_t *__restrict__ off, cons
     int total;
     int run = block_exclusive_scan(local, scan_sh, &total);
     for (int c = c0; c < c1; ++c) {
-        int v = cnt[c];
-        cnt[c] = a + run;             // becomes the scatter cursor
-        cstart[base + c] = a + run;
+        const int v = cnt[c];
+        cnt[c] = obase + run;         // becomes the scatter cursor
+        cs[c] = obase + run;
         run += v;
     }
-    if (tid == 0) {
-        cstart[base + cells] = b;
-        SegGrid g = {ymin, zmin, iwy, iwz, ny, nz, 0, 0};
-        grid[seg] = g;
-    }
+    if (tid == 0) cs[cells] = obase + (b - a);
     __syncthreads();
     for (int i = a + tid; i < b; i += TPC_BLOCK) {
-        float yv = y[i], zv = z[i];
-        int c = cell_coord(yv, ymin, iwy, ny) * nz + cell_coord(zv, zmin, iwz, nz);
-        int slot = atomicAdd(&cnt[c], 1);
-        sy[slot] = yv;
-        sz[slot] = zv;
-        sid[slot] = i;
+        const float yv = y[i], zv = z[i];
+        const int c = cell_coord(yv, g.y0, g.iwy, g.ny) * g.nz + cell_coord(zv, g.z0, g.iwz, g.nz);
+        const int slot = atomicAdd(&cnt[c], 1);
+        dy[slot] = yv;
+        dz[slot] = zv;
+        did[slot] = i;
     }
+    __syncthreads();
+}
+
+// Rows of at most this many clusters are binned in LDS by the query
+// workgroup itself; larger rows go through the global cell-sorted copy.
+#define TPC_LDS_ROW 1024
+
+__device__ inline int seg_size(const int32_t *off, int s) { return off[s + 1] - off[s]; }
+
+// Does the query of h-row `seg` use the global cell-sorted rows?
+__device__ inline bool query_global(const int32_t *off, int seg, int n_rows) {
+    const int r = seg % n_rows;
+    if (r == 0 || r == n_rows - 1) return false;
+    return seg_size(off, seg - 1) > TPC_LDS_ROW || seg_size(off, seg + 1) > TPC_LDS_ROW;
+}
+
+// Global binning of segment `seg`, done only when a neighbouring h-row's
+// query needs it (whole workgroup; contains barriers).
+__device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict__ off,
+                                  const float *__restrict__ y, const float *__restrict__ z, float win_y,
+                                  float win_z, SegGrid *__restrict__ grid, int32_t *__restrict__ cstart,
+                                  float *__restrict__ sy, float *__restrict__ sz,
+                                  int32_t *__restrict__ sid) {
+#pragma clang fp contract(off)
+    __shared__ int cnt[TPC_CELL_CAP];
+    __shared__ float red[4][TPC_BLOCK / TPC_WAVE];
+    __shared__ int scan_sh[TPC_BLOCK / TPC_WAVE];
+    const int r = seg % n_rows;
+    const bool need = (r >= 1 && query_global(off, seg - 1, n_rows)) ||
+                      (r <= n_rows - 2 && query_global(off, seg + 1, n_rows));
+    if (!need) return;
+    __syncthreads();                 // LDS reuse across calls in a persistent loop
+    const int a = off[seg], b = off[seg + 1], n = b - a;
+    const int base = a + seg;
+    if (n == 0) {
+        if (threadIdx.x == 0) {
+            SegGrid g = {0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
+            grid[seg] = g;
+            cstart[base] = a;
+        }
+        return;
+    }
+    float ext[4];
+    row_extent(y, z, a, b, red, ext);
+    const SegGrid g = row_grid(ext[0], ext[1], ext[2], ext[3], n, TPC_CELL_CAP, win_y, win_z);
+    if (threadIdx.x == 0) grid[seg] = g;
+    row_sort(y, z, a, b, g, cnt, scan_sh, sy, sz, sid, cstart + base, a);
 }
 
 struct Best {
@@ -141,63 +185,110 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
     return d < b.d;
 }
 
-// Best triplet of every cluster of segment `seg` (no barriers).
+// Best (up, down) pair for cluster (yh, zh) over the 3x3 cells around it in
+// the cell-sorted up row (UY, UZ, UI, UCS, gu) and down row (D...).  UCS[c]
+// indexes the first cluster of cell c in UY/UZ/UI.  Every operation is one
+// single-precision rounding.
+template <class FP, class IP>
+__device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, IP UCS, const SegGrid &gu,
+                                 FP DY, FP DZ, IP DI, IP DCS, const SegGrid &gd, float win_y,
+                                 float win_z, float cut_y, float cut_z) {
+#pragma clang fp contract(off)
+    Best best = {0.f, -1, -1};
+    if (gu.ny <= 0 || gd.ny <= 0) return best;
+    const int cyu = cell_coord(yh, gu.y0, gu.iwy, gu.ny), czu = cell_coord(zh, gu.z0, gu.iwz, gu.nz);
+    const int cyd = cell_coord(yh, gd.y0, gd.iwy, gd.ny), czd = cell_coord(zh, gd.z0, gd.iwz, gd.nz);
+    const int zu0 = czu > 0 ? czu - 1 : 0, zu1 = czu < gu.nz - 1 ? czu + 1 : gu.nz - 1;
+    const int zd0 = czd > 0 ? czd - 1 : 0, zd1 = czd < gd.nz - 1 ? czd + 1 : gd.nz - 1;
+    const int yu0 = cyu > 0 ? cyu - 1 : 0, yu1 = cyu < gu.ny - 1 ? cyu + 1 : gu.ny - 1;
+    const int yd0 = cyd > 0 ? cyd - 1 : 0, yd1 = cyd < gd.ny - 1 ? cyd + 1 : gd.ny - 1;
+    for (int iyu = yu0; iyu <= yu1; ++iyu) {
+        const int ue0 = UCS[iyu * gu.nz + zu0];
+        const int ue1 = UCS[iyu * gu.nz + zu1 + 1];
+        for (int ku = ue0; ku < ue1; ++ku) {
+            const float ay = UY[ku] - yh;
+            const float az = UZ[ku] - zh;
+            if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
+            const int32_t u = UI[ku];
+            for (int iyd = yd0; iyd <= yd1; ++iyd) {
+                const int de0 = DCS[iyd * gd.nz + zd0];
+                const int de1 = DCS[iyd * gd.nz + zd1 + 1];
+                for (int kd = de0; kd < de1; ++kd) {
+                    const float by = yh - DY[kd];
+                    const float bz = zh - DZ[kd];
+                    if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
+                    const float dy = ay - by;
+                    const float dz = az - bz;
+                    if (!(fabsf(dy) <= cut_y && fabsf(dz) <= cut_z)) continue;
+                    const float qy = dy * dy;
+                    const float qz = dz * dz;
+                    const float q = qy + qz;
+                    const int32_t d = DI[kd];
+                    if (better(q, u, d, best)) { best.q = q; best.u = u; best.d = d; }
+                }
+            }
+        }
+    }
+    return best;
+}
+
+// Best triplet of every cluster of h-row `seg` (whole workgroup; contains
+// barriers).  When both neighbouring rows hold at most TPC_LDS_ROW clusters
+// the workgroup bins them itself into LDS (coalesced reads, then every
+// candidate access is an LDS access); otherwise it reads the global
+// cell-sorted rows written by nb_bin_seg.
 __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, int32_t n_rows,
+                                    const float *__restrict__ y, const float *__restrict__ z,
                                     float win_y, float win_z, float cut_y, float cut_z,
                                     const SegGrid *__restrict__ grid, const int32_t *__restrict__ cstart,
                                     const float *__restrict__ sy, const float *__restrict__ sz,
                                     const int32_t *__restrict__ sid, int32_t *__restrict__ up,
                                     int32_t *__restrict__ dn) {
 #pragma clang fp contract(off)
+    __shared__ float ly[2][TPC_LDS_ROW], lz[2][TPC_LDS_ROW];
+    __shared__ int32_t lid[2][TPC_LDS_ROW];
+    __shared__ int32_t lcs[2][TPC_LDS_ROW + 1];
+    __shared__ int cnt[TPC_LDS_ROW];
+    __shared__ float red[4][TPC_BLOCK / TPC_WAVE];
+    __shared__ int scan_sh[TPC_BLOCK / TPC_WAVE];
     const int r = seg % n_rows;
     const int a = off[seg], b = off[seg + 1];
     if (r == 0 || r == n_rows - 1) {
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) { up[i] = -1; dn[i] = -1; }
         return;
     }
-    const SegGrid gu = grid[seg + 1], gd = grid[seg - 1];
-    const int baseu = off[seg + 1] + seg + 1, based = off[seg - 1] + seg - 1;
-    for (int j = a + threadIdx.x; j < b; j += TPC_BLOCK) {
-        const float yh = sy[j], zh = sz[j];
-        const int32_t h = sid[j];
-        Best best = {0.f, -1, -1};
-        if (gu.ny > 0 && gd.ny > 0) {
-            const int cyu = cell_coord(yh, gu.y0, gu.iwy, gu.ny), czu = cell_coord(zh, gu.z0, gu.iwz, gu.nz);
-            const int cyd = cell_coord(yh, gd.y0, gd.iwy, gd.ny), czd = cell_coord(zh, gd.z0, gd.iwz, gd.nz);
-            const int zu0 = czu > 0 ? czu - 1 : 0, zu1 = czu < gu.nz - 1 ? czu + 1 : gu.nz - 1;
-            const int zd0 = czd > 0 ? czd - 1 : 0, zd1 = czd < gd.nz - 1 ? czd + 1 : gd.nz - 1;
-            const int yu0 = cyu > 0 ? cyu - 1 : 0, yu1 = cyu < gu.ny - 1 ? cyu + 1 : gu.ny - 1;
-            const int yd0 = cyd > 0 ? cyd - 1 : 0, yd1 = cyd < gd.ny - 1 ? cyd + 1 : gd.ny - 1;
-            for (int iyu = yu0; iyu <= yu1; ++iyu) {
-                const int ue0 = cstart[baseu + iyu * gu.nz + zu0];
-                const int ue1 = cstart[baseu + iyu * gu.nz + zu1 + 1];
-                for (int ku = ue0; ku < ue1; ++ku) {
-                    const float ay = sy[ku] - yh;
-                    const float az = sz[ku] - zh;
-                    if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
-                    const int32_t u = sid[ku];
-                    for (int iyd = yd0; iyd <= yd1; ++iyd) {
-                        const int de0 = cstart[based + iyd * gd.nz + zd0];
-                        const int de1 = cstart[based + iyd * gd.nz + zd1 + 1];
-                        for (int kd = de0; kd < de1; ++kd) {
-                            const float by = yh - sy[kd];
-                            const float bz = zh - sz[kd];
-                            if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
-                            const float dy = ay - by;
-                            const float dz = az - bz;
-                            if (!(fabsf(dy) <= cut_y && fabsf(dz) <= cut_z)) continue;
-                            const float qy = dy * dy;
-                            const float qz = dz * dz;
-                            const float q = qy + qz;
-                            const int32_t d = sid[kd];
-                            if (better(q, u, d, best)) { best.q = q; best.u = u; best.d = d; }
-                        }
-                    }
-                }
+    if (a == b) return;
+    if (!query_global(off, seg, n_rows)) {
+        SegGrid g[2];
+        for (int side = 0; side < 2; ++side) {
+            const int rs = side == 0 ? seg - 1 : seg + 1;
+            const int ra = off[rs], rb = off[rs + 1];
+            if (ra == rb) {
+                g[side] = SegGrid{0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
+                continue;
             }
+            float ext[4];
+            row_extent(y, z, ra, rb, red, ext);
+            g[side] = row_grid(ext[0], ext[1], ext[2], ext[3], rb - ra, TPC_LDS_ROW, win_y, win_z);
+            row_sort(y, z, ra, rb, g[side], cnt, scan_sh, ly[side], lz[side], lid[side], lcs[side], 0);
         }
-        up[h] = best.u;
-        dn[h] = best.d;
+        for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
+            const Best bt = best_pair(y[i], z[i], ly[1], lz[1], lid[1], lcs[1], g[1], ly[0], lz[0], lid[0],
+                                      lcs[0], g[0], win_y, win_z, cut_y, cut_z);
+            up[i] = bt.u;
+            dn[i] = bt.d;
+        }
+        __syncthreads();             // LDS reuse across calls in a persistent loop
+        return;
+    }
+    const SegGrid gu = grid[seg + 1], gd = grid[seg - 1];
+    const int32_t *csu = cstart + off[seg + 1] + seg + 1;
+    const int32_t *csd = cstart + off[seg - 1] + seg - 1;
+    for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
+        const Best bt = best_pair(y[i], z[i], sy, sz, sid, csu, gu, sy, sz, sid, csd, gd, win_y, win_z,
+                                  cut_y, cut_z);
+        up[i] = bt.u;
+        dn[i] = bt.d;
     }
 }
 

@@ -1,21 +1,24 @@
 // Neighbour search stage kernels: one workgroup per (frame, sector, row)
-// segment; the per-segment work is in tpc_nb_device.hpp.
+// segment; the per-segment work is in tpc_nb_device.hpp.  nb_bin only works
+// on segments next to a row too large for the LDS path.
 #include "tpc_nb_device.hpp"
 
 namespace {
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-nb_bin(const int32_t *__restrict__ off, const float *__restrict__ y, const float *__restrict__ z,
-       float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy, float *sz, int32_t *sid) {
-    tpc_nb::nb_bin_seg(blockIdx.x, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid);
+nb_bin(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
+       const float *__restrict__ z, float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy,
+       float *sz, int32_t *sid) {
+    tpc_nb::nb_bin_seg(blockIdx.x, n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-nb_query(const int32_t *__restrict__ off, int32_t n_rows, float win_y, float win_z, float cut_y,
-         float cut_z, const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
+nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
+         const float *__restrict__ z, float win_y, float win_z, float cut_y, float cut_z,
+         const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
          const int32_t *sid, int32_t *up, int32_t *dn) {
-    tpc_nb::nb_query_seg(blockIdx.x, off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz,
-                         sid, up, dn);
+    tpc_nb::nb_query_seg(blockIdx.x, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
+                         sz, sid, up, dn);
 }
 
 }  // namespace
@@ -25,10 +28,10 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
                              int32_t *dn, const NbWs &ws, hipStream_t st) {
     const int NR = fr->n_frames * ctx->cfg.n_sectors * ctx->cfg.n_rows;
     const tpc_config &c = ctx->cfg;
-    hipLaunchKernelGGL(nb_bin, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, fr->y, fr->z,
-                       c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid);
-    hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows,
-                       c.win_y, c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz,
+    hipLaunchKernelGGL(nb_bin, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
+                       fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid);
+    hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
+                       fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz,
                        ws.sid, up, dn);
     return hipGetLastError();
 }

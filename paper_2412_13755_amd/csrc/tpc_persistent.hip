@@ -9,9 +9,10 @@
 // a sleep and gives up after a bounded number of polls, setting an error flag
 // that makes every workgroup leave, so the kernel always terminates.
 //
-// Phases:  bin | query | chains | claims | firsts | chunk sums | chunk scan
+// Phases:  bin | query | links | jump + claims | firsts | chunk sums | chunk scan
 //          (one workgroup) | segment scan | place + length histogram |
-//          members + length scan (one workgroup) | order by length | fit
+//          members + length scan (one workgroup) | gather hit coordinates +
+//          order by length | fit
 // The fit visits seeds longest first, so the lanes of a wavefront carry
 // seeds of similar length (the loop length is the seed length).
 #include "tpc_ca_device.hpp"
@@ -43,6 +44,7 @@ struct PersistArgs {
     int32_t *len_cur;    // [TPC_MAX_ROWS + 1]
     int32_t *perm;       // [cap_seeds]
     int32_t *n_placed;   // [1]
+    float2 *hyz;         // [cap_hits] seed-ordered hit coordinates
     int32_t nchunks;
     int32_t sort_fit;
 };
@@ -106,18 +108,18 @@ persist_reco(PersistArgs P) {
     for (int r = tid; r < P.n_rows; r += TPC_BLOCK) xs[r] = P.F.row_x[r];
 
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_nb::nb_bin_seg(seg, P.off, P.y, P.z, P.win_y, P.win_z, P.nb.grid, P.nb.cstart, P.nb.sy,
-                           P.nb.sz, P.nb.sid);
+        tpc_nb::nb_bin_seg(seg, P.n_rows, P.off, P.y, P.z, P.win_y, P.win_z, P.nb.grid, P.nb.cstart,
+                           P.nb.sy, P.nb.sz, P.nb.sid);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.win_y, P.win_z, P.cut_y, P.cut_z, P.nb.grid,
-                             P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn);
+        tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.y, P.z, P.win_y, P.win_z, P.cut_y, P.cut_z,
+                             P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_chains_seg(seg, P.N, P.off, P.up, P.dn, P.n_rows, P.ca);
+        tpc_ca::ca_links_seg(seg, P.N, P.off, P.up, P.dn, P.ca);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_claims_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
+        tpc_ca::ca_jump_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_ca::ca_firsts_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
@@ -202,16 +204,28 @@ persist_reco(PersistArgs P) {
         }
     }
     if (!grid_sync(P)) return;
-    if (P.sort_fit) {
-        // placed seeds form the prefix [0, n_placed): order them by length
-        const int np = *P.n_placed;
-        for (int i = bid * TPC_BLOCK + tid; i < np; i += G * TPC_BLOCK) {
-            const int n = P.sd.offsets[i + 1] - P.sd.offsets[i];
-            const int len = n < TPC_MAX_ROWS ? (n > 0 ? n : 0) : TPC_MAX_ROWS;
-            const int slot = P.len_hist[len] + atomicAdd(&P.len_cur[len], 1);
-            if (slot < np) P.perm[slot] = i;
+    {
+        // seed-ordered hit coordinates for the fit; placed seeds form the
+        // prefix [0, n_placed): with sort_fit, order them by length
+        int H = *P.sd.n_hits;
+        if (H > P.sd.cap_hits) H = P.sd.cap_hits;
+        for (int j = bid * TPC_BLOCK + tid; j < H; j += G * TPC_BLOCK) {
+            const int32_t id = P.sd.hits[j];
+            P.hyz[j] = (uint32_t)id < (uint32_t)P.N ? make_float2(P.y[id], P.z[id]) : make_float2(0.f, 0.f);
         }
-        if (!grid_sync(P)) return;
+        if (P.sort_fit) {
+            const int np = *P.n_placed;
+            for (int i = bid * TPC_BLOCK + tid; i < np; i += G * TPC_BLOCK) {
+                const int n = P.sd.offsets[i + 1] - P.sd.offsets[i];
+                const int len = n < TPC_MAX_ROWS ? (n > 0 ? n : 0) : TPC_MAX_ROWS;
+                const int slot = P.len_hist[len] + atomicAdd(&P.len_cur[len], 1);
+                if (slot < np) P.perm[slot] = i;
+            }
+        }
+    }
+    if (!grid_sync(P)) return;
+    if (P.sort_fit) {
+        const int np = *P.n_placed;
         for (int k = bid * TPC_BLOCK + tid; k < np; k += G * TPC_BLOCK) fit_one(P.F, P.perm[k], xs);
     } else {
         int T = *P.sd.n_seeds;
@@ -226,7 +240,8 @@ __global__ void persist_status(PersistArgs P) {
 
 }  // namespace
 
-size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, PersistArgs *P) {
+size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, int64_t cap_hits,
+                         PersistArgs *P) {
     WsCarver w(ws);
     NbWs nb;
     CaWs ca;
@@ -245,7 +260,9 @@ size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, Per
     int32_t *cur = w.take<int32_t>(TPC_MAX_ROWS + 1);
     int32_t *perm = w.take<int32_t>(cap_seeds > 0 ? cap_seeds : 1);
     int32_t *np = w.take<int32_t>(1);
+    float2 *hyz = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
     if (P) {
+        P->hyz = hyz;
         P->nb = nb;
         P->ca = ca;
         P->bar = bar;
@@ -296,7 +313,8 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
     P.F = make_fit_args(ctx, fr, sd, nullptr);
     P.F.out = *tr;
     P.sort_fit = sort_fit;
-    persist_ws_layout(ws, fr->n_clusters, P.NR, sd->cap_seeds, &P);
+    persist_ws_layout(ws, fr->n_clusters, P.NR, sd->cap_seeds, sd->cap_hits, &P);
+    P.F.hyz = P.hyz;
     hipLaunchKernelGGL(persist_init, dim3(2), dim3(TPC_BLOCK), 0, st, P);
     hipLaunchKernelGGL(persist_reco, dim3(grid), dim3(TPC_BLOCK), 0, st, P);
     hipLaunchKernelGGL(persist_status, dim3(1), dim3(64), 0, st, P);
