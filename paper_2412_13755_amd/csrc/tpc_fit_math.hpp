@@ -208,29 +208,30 @@ __host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy,
     const R k20 = C.c20 * i00 + C.c21 * i01, k21 = C.c20 * i01 + C.c21 * i11;
     const R k30 = C.c30 * i00 + C.c31 * i01, k31 = C.c30 * i01 + C.c31 * i11;
     const R k40 = C.c40 * i00 + C.c41 * i01, k41 = C.c40 * i01 + C.c41 * i11;
-    p[0] += k00 * r0 + k01 * r1;
-    p[1] += k10 * r0 + k11 * r1;
-    p[2] += k20 * r0 + k21 * r1;
-    p[3] += k30 * r0 + k31 * r1;
-    p[4] += k40 * r0 + k41 * r1;
+    // written as chains of multiply-adds (one rounding per term)
+    p[0] = p[0] + k00 * r0 + k01 * r1;
+    p[1] = p[1] + k10 * r0 + k11 * r1;
+    p[2] = p[2] + k20 * r0 + k21 * r1;
+    p[3] = p[3] + k30 * r0 + k31 * r1;
+    p[4] = p[4] + k40 * r0 + k41 * r1;
     // C -= K H C, H C = rows 0 and 1 of C
     const R r00 = C.c00, r01 = C.c10, r02 = C.c20, r03 = C.c30, r04 = C.c40;
     const R r11 = C.c11, r12 = C.c21, r13 = C.c31, r14 = C.c41;
-    C.c00 -= k00 * r00 + k01 * r01;
-    C.c10 -= k10 * r00 + k11 * r01;
-    C.c11 -= k10 * r01 + k11 * r11;
-    C.c20 -= k20 * r00 + k21 * r01;
-    C.c21 -= k20 * r01 + k21 * r11;
-    C.c22 -= k20 * r02 + k21 * r12;
-    C.c30 -= k30 * r00 + k31 * r01;
-    C.c31 -= k30 * r01 + k31 * r11;
-    C.c32 -= k30 * r02 + k31 * r12;
-    C.c33 -= k30 * r03 + k31 * r13;
-    C.c40 -= k40 * r00 + k41 * r01;
-    C.c41 -= k40 * r01 + k41 * r11;
-    C.c42 -= k40 * r02 + k41 * r12;
-    C.c43 -= k40 * r03 + k41 * r13;
-    C.c44 -= k40 * r04 + k41 * r14;
+    C.c00 = C.c00 - k00 * r00 - k01 * r01;
+    C.c10 = C.c10 - k10 * r00 - k11 * r01;
+    C.c11 = C.c11 - k10 * r01 - k11 * r11;
+    C.c20 = C.c20 - k20 * r00 - k21 * r01;
+    C.c21 = C.c21 - k20 * r01 - k21 * r11;
+    C.c22 = C.c22 - k20 * r02 - k21 * r12;
+    C.c30 = C.c30 - k30 * r00 - k31 * r01;
+    C.c31 = C.c31 - k30 * r01 - k31 * r11;
+    C.c32 = C.c32 - k30 * r02 - k31 * r12;
+    C.c33 = C.c33 - k30 * r03 - k31 * r13;
+    C.c40 = C.c40 - k40 * r00 - k41 * r01;
+    C.c41 = C.c41 - k40 * r01 - k41 * r11;
+    C.c42 = C.c42 - k40 * r02 - k41 * r12;
+    C.c43 = C.c43 - k40 * r03 - k41 * r13;
+    C.c44 = C.c44 - k40 * r04 - k41 * r14;
     return r0 * (i00 * r0 + i01 * r1) + r1 * (i01 * r0 + i11 * r1);
 }
 
