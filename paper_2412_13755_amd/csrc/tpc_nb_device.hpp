@@ -12,14 +12,15 @@
 //
 // Design: one workgroup per h-row (frame, sector, row) segment.  Each of
 // the two neighbouring rows is put on a y-z cell grid sized from the data
-// (cell edges at least 1.01 x the window, at most one cell per cluster) and
-// counting-sorted by cell; then every thread takes clusters h of its row and
-// scans the 3x3 cells around h in the up row, and for each up candidate in
-// the window, the 3x3 cells in the down row.  Rows of up to TPC_LDS_ROW
-// clusters are binned by the query workgroup itself into LDS (the row pair
-// is read once, coalesced, and every candidate access is an LDS access);
-// larger rows use a cell-sorted copy in global memory written beforehand by
-// nb_bin (at most TPC_CELL_CAP cells per row).
+// (cell edges at least 1.01 x the window) and counting-sorted by cell; then
+// every thread takes clusters h of its row and scans the 3x3 cells around h
+// in the up row, and for each up candidate in the window, the 3x3 cells in
+// the down row.  Rows of up to TPC_LDS_ROW clusters are binned by the query
+// workgroup itself into LDS, both rows in one counting sort with up to four
+// cells per cluster (the row pair is read once, coalesced, and every
+// candidate access is an LDS access); larger rows use a cell-sorted copy in
+// global memory written beforehand by nb_bin (at most one cell per cluster
+// and TPC_CELL_CAP cells per row).
 // Candidates with |y_u - y_h| <= win differ by at most one cell because the
 // cell edge exceeds the window by 1%, far more than the rounding of the cell
 // coordinate, and clamping keeps that bound; so scanning the 3x3 cells
@@ -187,12 +188,13 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
 
 // Best (up, down) pair for cluster (yh, zh) over the 3x3 cells around it in
 // the cell-sorted up row (UY, UZ, UI, UCS, gu) and down row (D...).  UCS[c]
-// indexes the first cluster of cell c in UY/UZ/UI.  Every operation is one
+// indexes the first cluster of cell c in UY/UZ/UI; a stored id k stands for
+// cluster ubase + k (dbase + k in the down row).  Every operation is one
 // single-precision rounding.
-template <class FP, class IP>
-__device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, IP UCS, const SegGrid &gu,
-                                 FP DY, FP DZ, IP DI, IP DCS, const SegGrid &gd, float win_y,
-                                 float win_z, float cut_y, float cut_z) {
+template <class FP, class IP, class CP>
+__device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS, const SegGrid &gu,
+                                 int32_t ubase, FP DY, FP DZ, IP DI, CP DCS, const SegGrid &gd,
+                                 int32_t dbase, float win_y, float win_z, float cut_y, float cut_z) {
 #pragma clang fp contract(off)
     Best best = {0.f, -1, -1};
     if (gu.ny <= 0 || gd.ny <= 0) return best;
@@ -209,7 +211,7 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, IP UCS
             const float ay = UY[ku] - yh;
             const float az = UZ[ku] - zh;
             if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
-            const int32_t u = UI[ku];
+            const int32_t u = ubase + (int32_t)UI[ku];
             for (int iyd = yd0; iyd <= yd1; ++iyd) {
                 const int de0 = DCS[iyd * gd.nz + zd0];
                 const int de1 = DCS[iyd * gd.nz + zd1 + 1];
@@ -223,13 +225,119 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, IP UCS
                     const float qy = dy * dy;
                     const float qz = dz * dz;
                     const float q = qy + qz;
-                    const int32_t d = DI[kd];
+                    const int32_t d = dbase + (int32_t)DI[kd];
                     if (better(q, u, d, best)) { best.q = q; best.u = u; best.d = d; }
                 }
             }
         }
     }
     return best;
+}
+
+// LDS form of a row pair: both rows of up to TPC_LDS_ROW clusters each, with
+// finer cells than the global form (up to 4 per cluster, TPC_LDS_CELLS per
+// row) so that the 3x3 cells around h hold few candidates.
+#define TPC_LDS_CELLS 2048
+
+struct PairLds {
+    float y[2 * TPC_LDS_ROW], z[2 * TPC_LDS_ROW];
+    uint16_t rel[2 * TPC_LDS_ROW];              // cluster id minus its row's first id
+    int32_t cs[2 * TPC_LDS_CELLS + 2];          // cell starts of both rows, concatenated
+    float red[8][TPC_BLOCK / TPC_WAVE];
+    int scan_sh[TPC_BLOCK / TPC_WAVE];
+};
+
+// Bins the down row [ra0, rb0) and the up row [ra1, rb1) with one LDS
+// counting sort over the concatenated cell range (whole workgroup; contains
+// barriers).  On return the down row occupies cells [0, C0) with grid gd, the
+// up row cells C0 + [0, C1) with grid gu, and cell c holds positions
+// [cs[c], cs[c+1]) of y/z/rel.
+__device__ inline int pair_cell(float yv, float zv, const SegGrid &g) {
+    return cell_coord(yv, g.y0, g.iwy, g.ny) * g.nz + cell_coord(zv, g.z0, g.iwz, g.nz);
+}
+
+__device__ inline SegGrid pair_grid(float ymin, float ymax, float zmin, float zmax, int n, float win_y,
+                                    float win_z) {
+    if (n == 0) return SegGrid{0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
+    const int cap = 4 * n < TPC_LDS_CELLS ? 4 * n : TPC_LDS_CELLS;
+    return row_grid(ymin, ymax, zmin, zmax, cap, cap, win_y, win_z);
+}
+
+__device__ inline void pair_bin(const float *__restrict__ y, const float *__restrict__ z, int ra0, int rb0,
+                                int ra1, int rb1, float win_y, float win_z, PairLds &L, SegGrid &gd,
+                                SegGrid &gu, int &C0) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const int n0 = rb0 - ra0, n1 = rb1 - ra1, nt = n0 + n1;
+    // finite extents of both rows in one pass
+    float e[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int k = tid; k < nt; k += TPC_BLOCK) {
+        if (k < n0) {
+            const float yv = y[ra0 + k], zv = z[ra0 + k];
+            if (isfinite(yv)) { e[0] = fminf(e[0], yv); e[1] = fmaxf(e[1], yv); }
+            if (isfinite(zv)) { e[2] = fminf(e[2], zv); e[3] = fmaxf(e[3], zv); }
+        } else {
+            const float yv = y[ra1 + k - n0], zv = z[ra1 + k - n0];
+            if (isfinite(yv)) { e[4] = fminf(e[4], yv); e[5] = fmaxf(e[5], yv); }
+            if (isfinite(zv)) { e[6] = fminf(e[6], zv); e[7] = fmaxf(e[7], zv); }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = (j & 1) ? wave_max(e[j]) : wave_min(e[j]);
+    const int wid = tid / TPC_WAVE, lane = tid & (TPC_WAVE - 1);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) L.red[j][wid] = e[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float v = L.red[j][0];
+#pragma unroll
+        for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w)
+            v = (j & 1) ? fmaxf(v, L.red[j][w]) : fminf(v, L.red[j][w]);
+        e[j] = v;
+    }
+    gd = pair_grid(e[0], e[1], e[2], e[3], n0, win_y, win_z);
+    gu = pair_grid(e[4], e[5], e[6], e[7], n1, win_y, win_z);
+    C0 = gd.ny * gd.nz;
+    const int C = C0 + gu.ny * gu.nz;
+    for (int c = tid; c < C + 2; c += TPC_BLOCK) L.cs[c] = 0;
+    __syncthreads();
+    // count cell c into cs[c + 2]
+    for (int k = tid; k < nt; k += TPC_BLOCK) {
+        const int c = k < n0 ? pair_cell(y[ra0 + k], z[ra0 + k], gd)
+                             : C0 + pair_cell(y[ra1 + k - n0], z[ra1 + k - n0], gu);
+        atomicAdd(&L.cs[c + 2], 1);
+    }
+    __syncthreads();
+    // inclusive scan of cs[1 .. C+1] (cs[1] is 0): cs[c + 1] = first position of cell c
+    const int len = C + 1;
+    const int per = (len + TPC_BLOCK - 1) / TPC_BLOCK;
+    const int j0 = 1 + tid * per;
+    const int j1 = j0 + per < 1 + len ? j0 + per : 1 + len;
+    int local = 0;
+    for (int j = j0; j < j1; ++j) local += L.cs[j];
+    int total;
+    int run = block_exclusive_scan(local, L.scan_sh, &total);
+    for (int j = j0; j < j1; ++j) {
+        run += L.cs[j];
+        L.cs[j] = run;
+    }
+    __syncthreads();
+    // scatter; the cursor of cell c moves from its start to its end, which
+    // leaves cs[c] = start of cell c for every c in [0, C]
+    for (int k = tid; k < nt; k += TPC_BLOCK) {
+        const bool lo = k < n0;
+        const int i = lo ? ra0 + k : ra1 + k - n0;
+        const float yv = y[i], zv = z[i];
+        const int c = lo ? pair_cell(yv, zv, gd) : C0 + pair_cell(yv, zv, gu);
+        const int slot = atomicAdd(&L.cs[c + 1], 1);
+        L.y[slot] = yv;
+        L.z[slot] = zv;
+        L.rel[slot] = (uint16_t)(lo ? k : k - n0);
+    }
+    __syncthreads();
 }
 
 // Best triplet of every cluster of h-row `seg` (whole workgroup; contains
@@ -245,12 +353,7 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
                                     const int32_t *__restrict__ sid, int32_t *__restrict__ up,
                                     int32_t *__restrict__ dn) {
 #pragma clang fp contract(off)
-    __shared__ float ly[2][TPC_LDS_ROW], lz[2][TPC_LDS_ROW];
-    __shared__ int32_t lid[2][TPC_LDS_ROW];
-    __shared__ int32_t lcs[2][TPC_LDS_ROW + 1];
-    __shared__ int cnt[TPC_LDS_ROW];
-    __shared__ float red[4][TPC_BLOCK / TPC_WAVE];
-    __shared__ int scan_sh[TPC_BLOCK / TPC_WAVE];
+    __shared__ PairLds L;
     const int r = seg % n_rows;
     const int a = off[seg], b = off[seg + 1];
     if (r == 0 || r == n_rows - 1) {
@@ -259,22 +362,13 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
     }
     if (a == b) return;
     if (!query_global(off, seg, n_rows)) {
-        SegGrid g[2];
-        for (int side = 0; side < 2; ++side) {
-            const int rs = side == 0 ? seg - 1 : seg + 1;
-            const int ra = off[rs], rb = off[rs + 1];
-            if (ra == rb) {
-                g[side] = SegGrid{0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
-                continue;
-            }
-            float ext[4];
-            row_extent(y, z, ra, rb, red, ext);
-            g[side] = row_grid(ext[0], ext[1], ext[2], ext[3], rb - ra, TPC_LDS_ROW, win_y, win_z);
-            row_sort(y, z, ra, rb, g[side], cnt, scan_sh, ly[side], lz[side], lid[side], lcs[side], 0);
-        }
+        const int ra0 = off[seg - 1], ra1 = off[seg + 1];
+        SegGrid gd, gu;
+        int C0;
+        pair_bin(y, z, ra0, a, ra1, off[seg + 2], win_y, win_z, L, gd, gu, C0);
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
-            const Best bt = best_pair(y[i], z[i], ly[1], lz[1], lid[1], lcs[1], g[1], ly[0], lz[0], lid[0],
-                                      lcs[0], g[0], win_y, win_z, cut_y, cut_z);
+            const Best bt = best_pair(y[i], z[i], L.y, L.z, L.rel, L.cs + C0, gu, ra1, L.y, L.z, L.rel,
+                                      L.cs, gd, ra0, win_y, win_z, cut_y, cut_z);
             up[i] = bt.u;
             dn[i] = bt.d;
         }
@@ -285,8 +379,8 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
     const int32_t *csu = cstart + off[seg + 1] + seg + 1;
     const int32_t *csd = cstart + off[seg - 1] + seg - 1;
     for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
-        const Best bt = best_pair(y[i], z[i], sy, sz, sid, csu, gu, sy, sz, sid, csd, gd, win_y, win_z,
-                                  cut_y, cut_z);
+        const Best bt = best_pair(y[i], z[i], sy, sz, sid, csu, gu, 0, sy, sz, sid, csd, gd, 0, win_y,
+                                  win_z, cut_y, cut_z);
         up[i] = bt.u;
         dn[i] = bt.d;
     }
