@@ -18,6 +18,9 @@ Extra legs, reported beside the headline value:
            evaluations per second (fit with checkpoints + chi2 sum + adjoint)
   copy     a 1 GiB device copy (reference for the HBM traffic counters; run
            alone with --legs copy)
+  stages   the three stage calls on the headline workload, --steps times,
+           nothing else (the launch sequence the counter profiles use; run
+           alone with --legs stages)
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -251,6 +254,26 @@ def leg_copy(args):
             "GB_per_s": round(8 * n / (ms * 1e-3) / 1e9, 1)}
 
 
+def leg_stages(args):
+    """Only the staged stage calls on the headline workload (for profilers)."""
+    import torch
+    from tpcsynth import make_config
+    fr = make_config(1)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    ws = reco.workspace(dfr)
+    up, dn, sd, tr = reco.reconstruct(dfr, "staged")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reco.neighbours(dfr, up, dn, ws)
+        reco.seed(dfr, up, dn, sd, ws)
+        reco.fit(dfr, sd, None, tr, ws)
+    torch.cuda.synchronize()
+    return {"workload": fr.meta["name"], "clusters": dfr.n_clusters, "steps": args.steps,
+            "ms_per_step": round((time.perf_counter() - t0) / max(args.steps, 1) * 1e3, 5)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -260,6 +283,9 @@ def main():
     legs = set(args.legs.split(","))
     if legs == {"copy"}:
         print(json.dumps({"copy": leg_copy(args)}), flush=True)
+        return
+    if legs == {"stages"}:
+        print(json.dumps({"stages": leg_stages(args)}), flush=True)
         return
     main_res, fr = leg_main(args)
     out = {

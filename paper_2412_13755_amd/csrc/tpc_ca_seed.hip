@@ -9,18 +9,21 @@ using namespace tpc_ca;
 
 __global__ void __launch_bounds__(TPC_BLOCK)
 ca_links(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, CaWs ws) {
-    ca_links_seg(blockIdx.x, N, off, up, dn, ws);
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    ca_links_seg(seg, N, off, up, dn, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
 ca_jump(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t min_hits,
         int32_t n_rows, CaWs ws) {
-    ca_jump_seg(blockIdx.x, N, off, up, dn, min_hits, n_rows, ws);
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    ca_jump_seg(seg, N, off, up, dn, min_hits, n_rows, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
 ca_firsts(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t min_hits, CaWs ws) {
-    ca_firsts_seg(blockIdx.x, N, off, up, dn, min_hits, ws);
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    ca_firsts_seg(seg, N, off, up, dn, min_hits, ws);
 }
 
 // Single workgroup: exclusive scan of the per-segment counts, chunk by chunk.
@@ -69,13 +72,15 @@ ca_scan(int32_t NR, CaWs ws, int32_t *__restrict__ n_seeds, int32_t *__restrict_
 __global__ void __launch_bounds__(TPC_BLOCK)
 ca_place(const int32_t *off, const int32_t *up, const int32_t *dn, int32_t n_sectors, int32_t n_rows,
          int32_t cap_seeds, int32_t cap_hits, tpc_seeds sd, CaWs ws) {
-    ca_place_seg(blockIdx.x, off, up, dn, n_sectors, n_rows, cap_seeds, cap_hits, sd, ws);
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    ca_place_seg(seg, off, up, dn, n_sectors, n_rows, cap_seeds, cap_hits, sd, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
 ca_members(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t cap_hits,
            tpc_seeds sd, CaWs ws) {
-    ca_members_seg(blockIdx.x, N, off, up, dn, cap_hits, sd, ws);
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    ca_members_seg(seg, N, off, up, dn, cap_hits, sd, ws);
 }
 
 }  // namespace

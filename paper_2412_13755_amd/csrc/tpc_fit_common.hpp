@@ -116,12 +116,14 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
     double *ck = A.ckpt ? A.ckpt + (size_t)ckpt_slot(sv.o0, i, A.ckpt_rows) * TPC_CKPT_WORDS : nullptr;
     if (status == TPC_FIT_OK) {
         if (ck) write_ckpt(ck, p, C);
-        float2 raw_next = hit_raw(A, sv, sv.n - 2, A.hyz ? 0 : sv.hh[sv.n - 2]);
+        // Each hit is read one step ahead, into the register its predecessor
+        // has just been consumed from (no copy at the loop edge, so the load
+        // is waited for only at its use a whole step later).
+        float2 raw = hit_raw(A, sv, sv.n - 2, A.hyz ? 0 : sv.hh[sv.n - 2]);
         for (int k = sv.n - 2, j = 1; k >= 0; --k, ++j) {
-            const float2 raw = raw_next;
-            if (k > 0) raw_next = hit_raw(A, sv, k - 1, A.hyz ? 0 : sv.hh[k - 1]);   // prefetch
             double my, mz;
             hit_fix(A, sv, k, raw, my, mz);
+            if (k > 0) raw = hit_raw(A, sv, k - 1, A.hyz ? 0 : sv.hh[k - 1]);
             const float xk = xs[sv.row0 + k];
             StepJac J;
             if (!helix_step(p, xk - xcur, A.kbz, A.max_sin, J)) {

@@ -4,16 +4,18 @@
 // x, track oriented towards +x, curvature kappa = -c Bz w (counter-clockwise
 // positive); covariance as the 15 entries of its lower triangle.
 //
-// Precision split.  The Jacobian entries are evaluated in single precision
-// (their rounding acts as a 1e-7 relative change of the linear model); the
-// state and its helix transport, the covariance transport F C F^T and the
-// Kalman update are carried in the type R (double in the library): a short
-// track's curvature is fixed by sub-micron sagittas, so single-precision
-// transport of y alone moves q/pT by ~1e-4 relative.  A single-precision
-// covariance update loses up to all significant digits when the diffuse start
-// covariance collapses onto the first hits (C - K H C cancels); on gfx950 the
-// FP64 vector FMA issues at the same rate as the non-packed FP32 FMA, so the
-// covariance algebra is kept in FP64 instead of reformulating it.
+// Precision.  The forward filter (state, helix transport, Jacobian,
+// covariance transport F C F^T and Kalman update) runs in the type R, double
+// in the library: a short track's curvature is fixed by sub-micron
+// sagittas, so single-precision transport of y alone moves q/pT by ~1e-4
+// relative, and a single-precision covariance update loses up to all
+// significant digits when the diffuse start covariance collapses onto the
+// first hits (C - K H C cancels).  On gfx950 the FP64 vector FMA issues at the
+// rate of the non-packed FP32 one, so double costs no more than float here.
+// Reciprocals and square roots in the inner loop use the hardware estimates
+// refined by Newton steps rather than the correctly rounded sequences.  The
+// second-order term of the adjoint (derivative of the Jacobian) is evaluated
+// in single precision.
 // No MFMA: a 5x5 symmetric update is not a dense contraction.
 #pragma once
 
@@ -57,8 +59,45 @@ __host__ __device__ inline float asin_over_dd(float u) {
 
 // Jacobian entries that differ from the identity.
 struct StepJac {
-    float f02, f04, f12, f13, f14, f24;
+    double f02, f04, f12, f13, f14, f24;
 };
+
+// Reciprocal and square root of positive, finite, normal doubles for the
+// filter's inner loop.  On the device: the hardware estimates refined by
+// Newton-Raphson (reciprocal, two steps) and by one coupled Goldschmidt step
+// plus one Newton correction (square root); relative error far below the
+// 1e-12 the filter needs, but not correctly rounded.  On the host: the
+// library operations.
+__host__ __device__ inline double recip_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+// sqrt(x), and 1/sqrt(x) in *inv (the latter to about 1e-13 relative).
+__host__ __device__ inline double sqrt_pos(double x, double *inv) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    if (inv) *inv = h + h;
+    return g;
+#else
+    const double g = sqrt(x);
+    if (inv) *inv = 1.0 / g;
+    return g;
+#endif
+}
 
 // asin(u)/u in the state precision (Taylor series to u^8 near 0)
 template <class R>
@@ -70,9 +109,20 @@ __host__ __device__ inline R asin_over_r(R u) {
     return asin(u) / u;
 }
 
-// Exact helix step from x to x + dx.  The state moves in precision R; the
-// Jacobian entries are formed in single precision from the same
-// intermediates.  Returns false when |sin phi| reaches max_sin (p is then
+// first derivative of asin(u)/u in the state precision
+template <class R>
+__host__ __device__ inline R asin_over_d_r(R u) {
+    if (fabs(u) < (R)0.05) {
+        const R u2 = u * u;
+        return u * ((R)1 / 3 + u2 * ((R)3 / 10 + u2 * ((R)15 / 56 + u2 * ((R)35 / 144))));
+    }
+    return (u / sqrt(((R)1 - u) * ((R)1 + u)) - asin(u)) / (u * u);
+}
+
+// Exact helix step from x to x + dx, state and Jacobian in precision R
+// (double in the library: on gfx950 the FP64 vector FMA issues at the rate
+// of the non-packed FP32 one, so a single-precision Jacobian would only add
+// conversions).  Returns false when |sin phi| reaches max_sin (p is then
 // left unchanged).
 template <class R>
 __host__ __device__ inline bool helix_step(R p[5], float dx, float kbz, float max_sin, StepJac &J) {
@@ -81,37 +131,37 @@ __host__ __device__ inline bool helix_step(R p[5], float dx, float kbz, float ma
     const R kap = (R)kbz * w;
     const R s2 = s + kap * (R)dx;
     if (!(fabs(s) < (R)max_sin) || !(fabs(s2) < (R)max_sin)) return false;
-    const R c1 = sqrt(((R)1 - s) * ((R)1 + s));
-    const R c2 = sqrt(((R)1 - s2) * ((R)1 + s2));
+    R ic1, ic2, isq;
+    const R c1 = sqrt_pos(((R)1 - s) * ((R)1 + s), &ic1);
+    const R c2 = sqrt_pos(((R)1 - s2) * ((R)1 + s2), &ic2);
     const R den = c1 + c2;
-    const R iden = (R)1 / den;
+    const R iden = recip_pos(den);
     const R A1 = s + s2;
     const R T = A1 * iden;                        // tan of the chord direction
-    const float adx = fabsf(dx);
-    const R sq = sqrt((R)1 + T * T);
-    const R chord = (R)adx * sq;
+    const R adx = fabs((R)dx);
+    const R sq = sqrt_pos((R)1 + T * T, &isq);
+    const R chord = adx * sq;
     const R u = (R)0.5 * kap * chord;
-    const float sgn = dx >= 0.0f ? 1.0f : -1.0f;
-    const R arc = (R)sgn * chord * asin_over_r(u);  // signed transverse path length
-    // Jacobian (single precision)
-    const float fs = (float)s, fs2 = (float)s2, fc1 = (float)c1, fc2 = (float)c2;
-    const float fden = (float)den, fiden = (float)iden, fA1 = (float)A1, fT = (float)T;
-    const float fsq = (float)sq, fchord = (float)chord, fu = (float)u, ft = (float)t;
-    const float iden2 = fiden * fiden;
-    const float dTs_p = (fden + fA1 * fs / fc1) * iden2;
-    const float dTs2_p = (fden + fA1 * fs2 / fc2) * iden2;
-    const float dT_ds = dTs_p + dTs2_p;
-    const float dT_dw = dTs2_p * dx * kbz;
-    const float darc_dchord = sgn / sqrtf((1.0f - fu) * (1.0f + fu));
-    const float darc_dkap = sgn * 0.5f * fchord * fchord * asin_over_d(fu);
-    const float dchord_dT = adx * fT / fsq;
-    const float q = darc_dchord * dchord_dT;
-    J.f02 = dx * dT_ds;
-    J.f04 = dx * dT_dw;
-    J.f12 = ft * q * dT_ds;
-    J.f13 = (float)arc;
-    J.f14 = ft * (q * dT_dw + darc_dkap * kbz);
-    J.f24 = dx * kbz;
+    const R sgn = dx >= 0.0f ? (R)1 : (R)-1;
+    const R arc = sgn * chord * asin_over_r(u);  // signed transverse path length
+    // Jacobian
+    const R iden2 = iden * iden;
+    const R dTs_p = (den + A1 * s * ic1) * iden2;
+    const R dTs2_p = (den + A1 * s2 * ic2) * iden2;
+    const R dT_ds = dTs_p + dTs2_p;
+    const R dT_dw = dTs2_p * (R)dx * (R)kbz;
+    R darc_dchord;                                // d(chord g(u))/dchord = 1/sqrt(1 - u^2)
+    sqrt_pos(((R)1 - u) * ((R)1 + u), &darc_dchord);
+    darc_dchord *= sgn;
+    const R darc_dkap = sgn * (R)0.5 * chord * chord * asin_over_d_r(u);
+    const R dchord_dT = adx * T * isq;
+    const R q = darc_dchord * dchord_dT;
+    J.f02 = (R)dx * dT_ds;
+    J.f04 = (R)dx * dT_dw;
+    J.f12 = t * q * dT_ds;
+    J.f13 = arc;
+    J.f14 = t * (q * dT_dw + darc_dkap * (R)kbz);
+    J.f24 = (R)dx * (R)kbz;
     p[0] += (R)dx * T;
     p[1] += t * arc;
     p[2] = s2;
@@ -200,7 +250,7 @@ __host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy,
     const R S00 = C.c00 + vy, S01 = C.c10, S11 = C.c11 + vz;
     const R det = S00 * S11 - S01 * S01;
     if (!(det > (R)0)) return (R)-1;
-    const R idet = (R)1 / det;
+    const R idet = recip_pos(det);
     const R i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
     // K = C[:, 0:2] S^-1
     const R k00 = C.c00 * i00 + C.c10 * i01, k01 = C.c00 * i01 + C.c10 * i11;

@@ -94,6 +94,18 @@ hipError_t launch_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tp
 // ---------------------------------------------------------------------------
 // device helpers
 
+// Workgroups go to the eight XCDs round-robin by block id, and each XCD has
+// its own L2.  Segment kernels renumber their blocks so that every XCD takes
+// one contiguous range of segments: the rows r-1, r, r+1 that a segment's
+// work touches are then mostly read through the same L2.  A bijection on
+// [0, G).
+#define TPC_XCDS 8
+__device__ inline int xcd_item(int b, int G) {
+    const int x = b % TPC_XCDS, j = b / TPC_XCDS;
+    const int q = G / TPC_XCDS, r = G % TPC_XCDS;
+    return x * q + (x < r ? x : r) + j;
+}
+
 __device__ inline int wave_inclusive_scan(int v) {
     const int lane = threadIdx.x & (TPC_WAVE - 1);
 #pragma unroll

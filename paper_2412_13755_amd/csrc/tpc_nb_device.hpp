@@ -13,18 +13,17 @@
 // Design: one workgroup per h-row (frame, sector, row) segment.  Each of
 // the two neighbouring rows is put on a y-z cell grid sized from the data
 // (cell edges at least 1.01 x the window) and counting-sorted by cell; then
-// every thread takes clusters h of its row and scans the 3x3 cells around h
-// in the up row, and for each up candidate in the window, the 3x3 cells in
-// the down row.  Rows of up to TPC_LDS_ROW clusters are binned by the query
-// workgroup itself into LDS, both rows in one counting sort with up to four
-// cells per cluster (the row pair is read once, coalesced, and every
-// candidate access is an LDS access); larger rows use a cell-sorted copy in
-// global memory written beforehand by nb_bin (at most one cell per cluster
-// and TPC_CELL_CAP cells per row).
-// Candidates with |y_u - y_h| <= win differ by at most one cell because the
-// cell edge exceeds the window by 1%, far more than the rounding of the cell
-// coordinate, and clamping keeps that bound; so scanning the 3x3 cells
-// around h over-covers the window and the exact predicates decide.
+// every thread takes clusters h of its row and scans the up-row cells that
+// overlap its window, and for each up candidate in the window, the down-row
+// cells that overlap the cut interval around the straight-line prediction.
+// Rows of up to TPC_LDS_ROW clusters are binned by the query workgroup
+// itself into LDS, both rows in one counting sort with up to four cells per
+// cluster (the row pair is read once, coalesced, and every candidate access
+// is an LDS access); larger rows use a cell-sorted copy in global memory
+// written beforehand by nb_bin (at most one cell per cluster and
+// TPC_CELL_CAP cells per row).  The cells scanned are derived from the
+// window and cut intervals with a safety margin (see best_pair), so they
+// over-cover the candidates and the exact predicates decide.
 #include "tpc_internal.hpp"
 
 namespace tpc_nb {
@@ -186,24 +185,31 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
     return d < b.d;
 }
 
-// Best (up, down) pair for cluster (yh, zh) over the 3x3 cells around it in
-// the cell-sorted up row (UY, UZ, UI, UCS, gu) and down row (D...).  UCS[c]
-// indexes the first cluster of cell c in UY/UZ/UI; a stored id k stands for
-// cluster ubase + k (dbase + k in the down row).  Every operation is one
-// single-precision rounding.
+// Best (up, down) pair for cluster (yh, zh) in the cell-sorted up row (UY,
+// UZ, UI, UCS, gu) and down row (D...).  UCS[c] indexes the first cluster of
+// cell c in UY/UZ/UI; a stored id k stands for cluster ubase + k (dbase + k
+// in the down row).  Every operation is one single-precision rounding.
+//
+// Cells scanned: in the up row, those overlapping [h - win - m, h + win + m];
+// for an up candidate u in the window, in the down row those overlapping
+// [c - cut - m, c + cut + m] around the straight-line prediction c = h - (u - h)
+// (a down partner's second difference is at most the cut).  The margin m is
+// far above the rounding of the predicates and of c, and cell_coord is
+// monotonic, so every cluster that can pass the exact predicates is visited.
+// A cluster h with a non-finite coordinate fails every window, so it is
+// skipped.
 template <class FP, class IP, class CP>
 __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS, const SegGrid &gu,
                                  int32_t ubase, FP DY, FP DZ, IP DI, CP DCS, const SegGrid &gd,
                                  int32_t dbase, float win_y, float win_z, float cut_y, float cut_z) {
 #pragma clang fp contract(off)
     Best best = {0.f, -1, -1};
-    if (gu.ny <= 0 || gd.ny <= 0) return best;
-    const int cyu = cell_coord(yh, gu.y0, gu.iwy, gu.ny), czu = cell_coord(zh, gu.z0, gu.iwz, gu.nz);
-    const int cyd = cell_coord(yh, gd.y0, gd.iwy, gd.ny), czd = cell_coord(zh, gd.z0, gd.iwz, gd.nz);
-    const int zu0 = czu > 0 ? czu - 1 : 0, zu1 = czu < gu.nz - 1 ? czu + 1 : gu.nz - 1;
-    const int zd0 = czd > 0 ? czd - 1 : 0, zd1 = czd < gd.nz - 1 ? czd + 1 : gd.nz - 1;
-    const int yu0 = cyu > 0 ? cyu - 1 : 0, yu1 = cyu < gu.ny - 1 ? cyu + 1 : gu.ny - 1;
-    const int yd0 = cyd > 0 ? cyd - 1 : 0, yd1 = cyd < gd.ny - 1 ? cyd + 1 : gd.ny - 1;
+    if (gu.ny <= 0 || gd.ny <= 0 || !isfinite(yh) || !isfinite(zh)) return best;
+    const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
+    const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
+    const float wy = win_y + my, wz = win_z + mz, ky = cut_y + my, kz = cut_z + mz;
+    const int yu0 = cell_coord(yh - wy, gu.y0, gu.iwy, gu.ny), yu1 = cell_coord(yh + wy, gu.y0, gu.iwy, gu.ny);
+    const int zu0 = cell_coord(zh - wz, gu.z0, gu.iwz, gu.nz), zu1 = cell_coord(zh + wz, gu.z0, gu.iwz, gu.nz);
     for (int iyu = yu0; iyu <= yu1; ++iyu) {
         const int ue0 = UCS[iyu * gu.nz + zu0];
         const int ue1 = UCS[iyu * gu.nz + zu1 + 1];
@@ -212,6 +218,11 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
             const float az = UZ[ku] - zh;
             if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
             const int32_t u = ubase + (int32_t)UI[ku];
+            const float cy = yh - ay, cz = zh - az;
+            const int yd0 = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
+            const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
+            const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
+            const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
             for (int iyd = yd0; iyd <= yd1; ++iyd) {
                 const int de0 = DCS[iyd * gd.nz + zd0];
                 const int de1 = DCS[iyd * gd.nz + zd1 + 1];
@@ -238,6 +249,7 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
 // finer cells than the global form (up to 4 per cluster, TPC_LDS_CELLS per
 // row) so that the 3x3 cells around h hold few candidates.
 #define TPC_LDS_CELLS 2048
+#define TPC_PAIR_PT (2 * TPC_LDS_ROW / TPC_BLOCK)   // row-pair clusters per thread
 
 struct PairLds {
     float y[2 * TPC_LDS_ROW], z[2 * TPC_LDS_ROW];
@@ -269,17 +281,31 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
 #pragma clang fp contract(off)
     const int tid = threadIdx.x;
     const int n0 = rb0 - ra0, n1 = rb1 - ra1, nt = n0 + n1;
-    // finite extents of both rows in one pass
+    // both rows are read once, into registers (one global round trip)
+    float vy[TPC_PAIR_PT], vz[TPC_PAIR_PT];
+#pragma unroll
+    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+        const int k = tid + j * TPC_BLOCK;
+        vy[j] = 0.f;
+        vz[j] = 0.f;
+        if (k < nt) {
+            const int i = k < n0 ? ra0 + k : ra1 + (k - n0);
+            vy[j] = y[i];
+            vz[j] = z[i];
+        }
+    }
+    // finite extents of both rows
     float e[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
-    for (int k = tid; k < nt; k += TPC_BLOCK) {
+#pragma unroll
+    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+        const int k = tid + j * TPC_BLOCK;
+        const bool fy = k < nt && isfinite(vy[j]), fz = k < nt && isfinite(vz[j]);
         if (k < n0) {
-            const float yv = y[ra0 + k], zv = z[ra0 + k];
-            if (isfinite(yv)) { e[0] = fminf(e[0], yv); e[1] = fmaxf(e[1], yv); }
-            if (isfinite(zv)) { e[2] = fminf(e[2], zv); e[3] = fmaxf(e[3], zv); }
+            if (fy) { e[0] = fminf(e[0], vy[j]); e[1] = fmaxf(e[1], vy[j]); }
+            if (fz) { e[2] = fminf(e[2], vz[j]); e[3] = fmaxf(e[3], vz[j]); }
         } else {
-            const float yv = y[ra1 + k - n0], zv = z[ra1 + k - n0];
-            if (isfinite(yv)) { e[4] = fminf(e[4], yv); e[5] = fmaxf(e[5], yv); }
-            if (isfinite(zv)) { e[6] = fminf(e[6], zv); e[7] = fmaxf(e[7], zv); }
+            if (fy) { e[4] = fminf(e[4], vy[j]); e[5] = fmaxf(e[5], vy[j]); }
+            if (fz) { e[6] = fminf(e[6], vz[j]); e[7] = fmaxf(e[7], vz[j]); }
         }
     }
 #pragma unroll
@@ -305,10 +331,12 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
     for (int c = tid; c < C + 2; c += TPC_BLOCK) L.cs[c] = 0;
     __syncthreads();
     // count cell c into cs[c + 2]
-    for (int k = tid; k < nt; k += TPC_BLOCK) {
-        const int c = k < n0 ? pair_cell(y[ra0 + k], z[ra0 + k], gd)
-                             : C0 + pair_cell(y[ra1 + k - n0], z[ra1 + k - n0], gu);
-        atomicAdd(&L.cs[c + 2], 1);
+    int cell[TPC_PAIR_PT];
+#pragma unroll
+    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+        const int k = tid + j * TPC_BLOCK;
+        cell[j] = k < n0 ? pair_cell(vy[j], vz[j], gd) : C0 + pair_cell(vy[j], vz[j], gu);
+        if (k < nt) atomicAdd(&L.cs[cell[j] + 2], 1);
     }
     __syncthreads();
     // inclusive scan of cs[1 .. C+1] (cs[1] is 0): cs[c + 1] = first position of cell c
@@ -327,15 +355,15 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
     __syncthreads();
     // scatter; the cursor of cell c moves from its start to its end, which
     // leaves cs[c] = start of cell c for every c in [0, C]
-    for (int k = tid; k < nt; k += TPC_BLOCK) {
-        const bool lo = k < n0;
-        const int i = lo ? ra0 + k : ra1 + k - n0;
-        const float yv = y[i], zv = z[i];
-        const int c = lo ? pair_cell(yv, zv, gd) : C0 + pair_cell(yv, zv, gu);
-        const int slot = atomicAdd(&L.cs[c + 1], 1);
-        L.y[slot] = yv;
-        L.z[slot] = zv;
-        L.rel[slot] = (uint16_t)(lo ? k : k - n0);
+#pragma unroll
+    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+        const int k = tid + j * TPC_BLOCK;
+        if (k < nt) {
+            const int slot = atomicAdd(&L.cs[cell[j] + 1], 1);
+            L.y[slot] = vy[j];
+            L.z[slot] = vz[j];
+            L.rel[slot] = (uint16_t)(k < n0 ? k : k - n0);
+        }
     }
     __syncthreads();
 }
@@ -363,11 +391,21 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
     if (a == b) return;
     if (!query_global(off, seg, n_rows)) {
         const int ra0 = off[seg - 1], ra1 = off[seg + 1];
+        // the first h of each thread is loaded together with the row pair
+        float hy = 0.f, hz = 0.f;
+        if (a + (int)threadIdx.x < b) {
+            hy = y[a + threadIdx.x];
+            hz = z[a + threadIdx.x];
+        }
         SegGrid gd, gu;
         int C0;
         pair_bin(y, z, ra0, a, ra1, off[seg + 2], win_y, win_z, L, gd, gu, C0);
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
-            const Best bt = best_pair(y[i], z[i], L.y, L.z, L.rel, L.cs + C0, gu, ra1, L.y, L.z, L.rel,
+            if (i >= a + TPC_BLOCK) {
+                hy = y[i];
+                hz = z[i];
+            }
+            const Best bt = best_pair(hy, hz, L.y, L.z, L.rel, L.cs + C0, gu, ra1, L.y, L.z, L.rel,
                                       L.cs, gd, ra0, win_y, win_z, cut_y, cut_z);
             up[i] = bt.u;
             dn[i] = bt.d;

@@ -9,7 +9,8 @@ __global__ void __launch_bounds__(TPC_BLOCK)
 nb_bin(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
        const float *__restrict__ z, float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy,
        float *sz, int32_t *sid) {
-    tpc_nb::nb_bin_seg(blockIdx.x, n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid);
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    tpc_nb::nb_bin_seg(seg, n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -17,7 +18,8 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
          const float *__restrict__ z, float win_y, float win_z, float cut_y, float cut_z,
          const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
          const int32_t *sid, int32_t *up, int32_t *dn) {
-    tpc_nb::nb_query_seg(blockIdx.x, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    tpc_nb::nb_query_seg(seg, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
                          sz, sid, up, dn);
 }
 
