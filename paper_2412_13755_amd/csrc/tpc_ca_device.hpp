@@ -11,11 +11,16 @@
 // length, then bottom id; seeds are placed by prefix sums in cluster-id
 // order), so it matches the sequential definition exactly.
 //
-//   ca_links   reset claim slots and chain lengths; jump words point one
-//              kept link down
-//   ca_jump    pointer jumping to the chain bottom gives every chain member
-//              its bottom and position; each chain's top records its length
-//              and claims the chain's unlinked ends (>= min_hits-2 clusters)
+//   ca_links   reset claim slots and chain lengths; record every cluster's
+//              kept link down (dlk)
+//   ca_block   per (frame, sector, block of TPC_CA_ROWS rows): pointer
+//              jumping in LDS gives every cluster its lowest chain member
+//              inside the block and the distance to it (pack)
+//   ca_tops    every chain member follows the block-local lowest members
+//              down across block edges to the chain bottom (at most one hop
+//              per block) and gets its bottom and position; each chain's top
+//              records its length and claims the chain's unlinked ends
+//              (>= min_hits-2 clusters)
 //   ca_firsts  each seed is recognised at its first cluster (the won bottom
 //              end or the bottom itself); per-segment seed and hit counts
 //   ca_scan    exclusive prefix over segments, totals, capacity check
@@ -44,12 +49,14 @@ __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
     return ((unsigned long long)(2147483648u - (uint32_t)m) << 32) | (uint32_t)b;
 }
 
-// Chain ranking by pointer jumping.  pack[h] = (distance << 32) | node: the
-// node h currently points to (towards the chain bottom) and how many links
-// down it is.  A bottom or unlinked cluster points to itself at distance 0.
+// Chain ranking.  dlk[h] is the kept link down of h (or -1); a chain is a
+// path of such links, one row per link.  Rows are grouped in blocks of
+// TPC_CA_ROWS per (frame, sector); pack[h] = (distance << 32) | node holds
+// the lowest member of h's chain inside h's block and how many links down
+// it is.
 
-// Step 1: reset the claim slot, chain length, and the jump word of every
-// cluster of the segment.
+// Step 1: reset the claim slot and chain length, and record the kept link
+// down of every cluster of the segment.
 __device__ inline void ca_links_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
                                     const CaWs &ws) {
@@ -57,43 +64,108 @@ __device__ inline void ca_links_seg(int seg, int32_t N, const int32_t *__restric
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
         ws.claim[h] = ~0ull;
         ws.core[h] = 0;
-        const int32_t d = link_dn(up, dn, N, h);
-        ws.pack[h] = d >= 0 ? ((1ull << 32) | (uint32_t)d) : (unsigned long long)(uint32_t)h;
+        ws.dlk[h] = link_dn(up, dn, N, h);
     }
 }
 
-// Step 2: every linked cluster jumps its pointer to the chain bottom
-// (w <- pack[ptr(w)], distances added), which takes about log2(chain length)
-// rounds when the chain's clusters jump concurrently.  Each word is written
-// only by its own thread and always holds a valid (node, distance) pair, so
-// the result does not depend on timing; every round moves the pointer
-// strictly closer to the bottom, so the loop ends.  Then the top of each
-// chain records the chain length and top at the bottom and claims the
-// chain's unlinked end clusters (chains of >= min_hits - 2 clusters).
-__device__ inline void ca_jump_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+#define TPC_CA_ROWS 16          // rows per ranking block
+#define TPC_CA_CAP 8192         // clusters per block ranked in LDS
+#define TPC_CA_ROUNDS 5         // > log2(TPC_CA_ROWS): links inside a block
+#define TPC_CA_NODE 0xFFFFF     // LDS word: (distance << 20) | local node
+
+__host__ __device__ inline int ca_blocks_per_sector(int n_rows) {
+    return (n_rows + TPC_CA_ROWS - 1) / TPC_CA_ROWS;
+}
+
+// Step 2, block `item` of (frame, sector, row block): in-place pointer
+// jumping (a word always holds a valid (node, distance) pair, so reading a
+// neighbour's word before or after its update in the same round is
+// equally correct, and every round at least doubles the span of a pointer
+// that has not reached its target).  Blocks of at most TPC_CA_CAP clusters
+// jump in LDS (W: TPC_CA_CAP ints); larger ones in pack itself.  Contains
+// barriers: call from the whole workgroup.
+__device__ inline void ca_block_item(int item, int32_t n_rows, const int32_t *__restrict__ off,
+                                     const CaWs &ws, int32_t *W) {
+    const int nbs = ca_blocks_per_sector(n_rows);
+    const int fs = item / nbs, bb = item % nbs;
+    const int r0 = bb * TPC_CA_ROWS;
+    const int r1 = r0 + TPC_CA_ROWS < n_rows ? r0 + TPC_CA_ROWS : n_rows;
+    const int lo = off[fs * n_rows + r0], hi = off[fs * n_rows + r1];
+    const int n = hi - lo, tid = threadIdx.x;
+    if (n <= TPC_CA_CAP) {
+        for (int k = tid; k < n; k += TPC_BLOCK) {
+            const int32_t d = ws.dlk[lo + k];
+            W[k] = (d >= lo && d < hi && d != lo + k) ? ((1 << 20) | (d - lo)) : k;
+        }
+        __syncthreads();
+        for (int round = 0; round < TPC_CA_ROUNDS; ++round) {
+            for (int k = tid; k < n; k += TPC_BLOCK) {
+                const int32_t v = W[k], p = v & TPC_CA_NODE;
+                if (p == k) continue;
+                const int32_t v2 = W[p], q = v2 & TPC_CA_NODE;
+                if (q != p) W[k] = (((v >> 20) + (v2 >> 20)) << 20) | q;
+            }
+            __syncthreads();
+        }
+        for (int k = tid; k < n; k += TPC_BLOCK) {
+            const int32_t v = W[k];
+            ws.pack[lo + k] = ((unsigned long long)(uint32_t)(v >> 20) << 32) |
+                              (uint32_t)(lo + (v & TPC_CA_NODE));
+        }
+        __syncthreads();             // LDS reuse across calls in a persistent loop
+        return;
+    }
+    // large block: the same rounds on the global words (written by this
+    // workgroup only, so workgroup-scope accesses suffice)
+    for (int k = lo + tid; k < hi; k += TPC_BLOCK) {
+        const int32_t d = ws.dlk[k];
+        const unsigned long long w = (d >= lo && d < hi && d != k) ? ((1ull << 32) | (uint32_t)d)
+                                                                  : (unsigned long long)(uint32_t)k;
+        __hip_atomic_store(&ws.pack[k], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    for (int round = 0; round < TPC_CA_ROUNDS; ++round) {
+        for (int k = lo + tid; k < hi; k += TPC_BLOCK) {
+            const unsigned long long v =
+                __hip_atomic_load(&ws.pack[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int32_t p = (int32_t)(uint32_t)v;
+            if (p == k) continue;
+            const unsigned long long v2 =
+                __hip_atomic_load(&ws.pack[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int32_t q = (int32_t)(uint32_t)v2;
+            if (q != p)
+                __hip_atomic_store(&ws.pack[k], (((v >> 32) + (v2 >> 32)) << 32) | (uint32_t)q,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+    }
+}
+
+// Step 3: every linked cluster follows the block-local lowest members down
+// across block edges (a lowest member whose kept link leaves the block
+// continues below it) to the chain bottom; then the top of each chain
+// records the chain length and top at the bottom and claims the chain's
+// unlinked end clusters (chains of >= min_hits - 2 clusters).
+__device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                    const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
                                    int32_t min_hits, int32_t n_rows, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
         const int32_t u = link_up(up, dn, N, h);
-        const int32_t d = link_dn(up, dn, N, h);
-        if (u < 0 && d < 0) continue;                 // not linked
+        if (u < 0 && ws.dlk[h] < 0) continue;         // not linked
         unsigned long long w = ws.pack[h];
-        for (int it = 0; it < n_rows; ++it) {         // bound: a chain has < n_rows links
-            const int32_t p = (int32_t)(uint32_t)w;
-            if (p == h) break;                        // h is the bottom
-            const unsigned long long v =
-                __hip_atomic_load(&ws.pack[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int32_t pp = (int32_t)(uint32_t)v;
-            if (pp == p) break;                       // p is the bottom
-            w = (((w >> 32) + (v >> 32)) << 32) | (uint32_t)pp;
-            __hip_atomic_store(&ws.pack[h], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t bot = (int32_t)(uint32_t)w;
+        int32_t pos = (int32_t)(w >> 32);
+        for (int it = 0; it < n_rows; ++it) {         // bound: one hop per block
+            const int32_t e = valid_id(bot, N) ? ws.dlk[bot] : -1;
+            if (e < 0) break;
+            w = ws.pack[e];
+            pos += 1 + (int32_t)(w >> 32);
+            bot = (int32_t)(uint32_t)w;
         }
-        const int32_t bot = (int32_t)(uint32_t)w;
-        const int32_t pos = (int32_t)(w >> 32);
         ws.memb[h] = bot;
         ws.mpos[h] = pos;
-        if (u < 0) {                                  // h is the top: chain of pos + 1 clusters
+        if (u < 0 && valid_id(bot, N)) {              // h is the top: chain of pos + 1 clusters
             const int32_t m = pos + 1;
             ws.core[bot] = m;
             ws.ctop[bot] = h;

@@ -14,10 +14,16 @@ ca_links(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, Ca
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-ca_jump(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t min_hits,
+ca_block(int32_t n_rows, const int32_t *off, CaWs ws) {
+    __shared__ int32_t W[TPC_CA_CAP];
+    ca_block_item(xcd_item(blockIdx.x, gridDim.x), n_rows, off, ws, W);
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+ca_tops(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t min_hits,
         int32_t n_rows, CaWs ws) {
     const int seg = xcd_item(blockIdx.x, gridDim.x);
-    ca_jump_seg(seg, N, off, up, dn, min_hits, n_rows, ws);
+    ca_tops_seg(seg, N, off, up, dn, min_hits, n_rows, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -94,7 +100,9 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
     const int32_t *off = fr->row_offsets;
     const int32_t N = fr->n_clusters;
     hipLaunchKernelGGL(ca_links, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, ws);
-    hipLaunchKernelGGL(ca_jump, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, c.n_rows, ws);
+    const int NB = fr->n_frames * c.n_sectors * ca_blocks_per_sector(c.n_rows);
+    hipLaunchKernelGGL(ca_block, dim3(NB), dim3(TPC_BLOCK), 0, st, c.n_rows, off, ws);
+    hipLaunchKernelGGL(ca_tops, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, c.n_rows, ws);
     hipLaunchKernelGGL(ca_firsts, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, ws);
     hipLaunchKernelGGL(ca_scan, dim3(1), dim3(1024), 0, st, NR, ws, sd->n_seeds, sd->n_hits,
                        sd->cap_seeds, sd->cap_hits, sd->offsets, dev_status);
@@ -109,6 +117,7 @@ size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out) {
     CaWs l;
     l.claim = w.take<unsigned long long>(N);
     l.pack = w.take<unsigned long long>(N);
+    l.dlk = w.take<int32_t>(N);
     l.core = w.take<int32_t>(N);
     l.ctop = w.take<int32_t>(N);
     l.memb = w.take<int32_t>(N);

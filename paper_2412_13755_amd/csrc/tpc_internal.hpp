@@ -49,7 +49,8 @@ struct NbWs {
 
 struct CaWs {
     unsigned long long *claim;   // [N] smallest claim key per cluster
-    unsigned long long *pack;    // [N] pointer-jumping word: (distance << 32) | node
+    unsigned long long *pack;    // [N] (distance << 32) | lowest chain member in the row block
+    int32_t *dlk;                // [N] kept link down, -1 if none
     int32_t *core;               // [N] chain length at a bottom, 0 elsewhere
     int32_t *ctop;               // [N] chain top at a bottom
     int32_t *memb;               // [N] bottom of the chain a linked cluster is in

@@ -369,7 +369,7 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
 }
 
 // Best triplet of every cluster of h-row `seg` (whole workgroup; contains
-// barriers).  When both neighbouring rows hold at most TPC_LDS_ROW clusters
+// barriers; L is the workgroup's LDS scratch).  When both neighbouring rows hold at most TPC_LDS_ROW clusters
 // the workgroup bins them itself into LDS (coalesced reads, then every
 // candidate access is an LDS access); otherwise it reads the global
 // cell-sorted rows written by nb_bin_seg.
@@ -379,9 +379,8 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
                                     const SegGrid *__restrict__ grid, const int32_t *__restrict__ cstart,
                                     const float *__restrict__ sy, const float *__restrict__ sz,
                                     const int32_t *__restrict__ sid, int32_t *__restrict__ up,
-                                    int32_t *__restrict__ dn) {
+                                    int32_t *__restrict__ dn, PairLds &L) {
 #pragma clang fp contract(off)
-    __shared__ PairLds L;
     const int r = seg % n_rows;
     const int a = off[seg], b = off[seg + 1];
     if (r == 0 || r == n_rows - 1) {

@@ -18,9 +18,10 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
          const float *__restrict__ z, float win_y, float win_z, float cut_y, float cut_z,
          const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
          const int32_t *sid, int32_t *up, int32_t *dn) {
+    __shared__ tpc_nb::PairLds L;
     const int seg = xcd_item(blockIdx.x, gridDim.x);
     tpc_nb::nb_query_seg(seg, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
-                         sz, sid, up, dn);
+                         sz, sid, up, dn, L);
 }
 
 }  // namespace

@@ -9,10 +9,10 @@
 // a sleep and gives up after a bounded number of polls, setting an error flag
 // that makes every workgroup leave, so the kernel always terminates.
 //
-// Phases:  bin | query | links | jump + claims | firsts | chunk sums | chunk scan
-//          (one workgroup) | segment scan | place + length histogram |
-//          members + length scan (one workgroup) | gather hit coordinates +
-//          order by length | fit
+// Phases:  bin | query | links | block ranking | tops + claims | firsts |
+//          chunk sums | chunk scan (one workgroup) | segment scan |
+//          place + length histogram | members + length scan (one workgroup) |
+//          gather hit coordinates + order by length | fit
 // The fit visits seeds longest first, so the lanes of a wavefront carry
 // seeds of similar length (the loop length is the seed length).
 #include "tpc_ca_device.hpp"
@@ -26,7 +26,7 @@ struct PersistArgs {
     // frames
     const int32_t *off;
     const float *y, *z;
-    int32_t N, NR, n_rows, n_sectors;
+    int32_t N, NR, NB, n_rows, n_sectors;   // NB: chain-ranking blocks
     float win_y, win_z, cut_y, cut_z;
     int32_t min_hits;
     // outputs
@@ -102,6 +102,10 @@ persist_init(PersistArgs P) {
 __global__ void __launch_bounds__(TPC_BLOCK)
 persist_reco(PersistArgs P) {
     __shared__ float xs[TPC_MAX_ROWS];
+    __shared__ union {
+        tpc_nb::PairLds nb;
+        int32_t caw[TPC_CA_CAP];
+    } U;
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     __shared__ int bc[2];
     const int G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
@@ -113,13 +117,16 @@ persist_reco(PersistArgs P) {
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.y, P.z, P.win_y, P.win_z, P.cut_y, P.cut_z,
-                             P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn);
+                             P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.nb);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_ca::ca_links_seg(seg, P.N, P.off, P.up, P.dn, P.ca);
     if (!grid_sync(P)) return;
+    for (int item = bid; item < P.NB; item += G)
+        tpc_ca::ca_block_item(item, P.n_rows, P.off, P.ca, U.caw);
+    if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_jump_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
+        tpc_ca::ca_tops_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_ca::ca_firsts_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
@@ -299,6 +306,7 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
     P.z = fr->z;
     P.N = fr->n_clusters;
     P.NR = fr->n_frames * c.n_sectors * c.n_rows;
+    P.NB = fr->n_frames * c.n_sectors * tpc_ca::ca_blocks_per_sector(c.n_rows);
     P.n_rows = c.n_rows;
     P.n_sectors = c.n_sectors;
     P.win_y = c.win_y;
