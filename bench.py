@@ -26,6 +26,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -50,7 +51,7 @@ B_NB_PER_CLUSTER = 16          # read y, z; write up, dn
 B_SEED_PER_CLUSTER = 8         # read up, dn
 B_SEED_PER_HIT = 4             # write seed hit id
 B_SEED_PER_SEED = 16           # write offset, frame, sector, first row
-B_FIT_PER_HIT = 12             # read hit id, y, z
+B_FIT_PER_HIT = 8              # read the hit's y, z
 B_FIT_PER_TRACK = 24 + 96      # read seed record; write 24 words
 FLOP_FIT_PER_HIT = 300         # helix step ~35, Jacobian ~30, F C F^T ~110, update ~125
 
@@ -96,6 +97,33 @@ def cpu_baseline(fr, budget_s):
             "cores": int(oracle.max_threads()), "kind": "oracle",
             "sample": "the whole headline frame (%d clusters), %d runs, median %.3f s; FP32 "
                       "neighbours, integer seeding, FP64 fit" % (fr.n_clusters, len(times), t)}
+
+
+# HBM traffic of the fit kernel per launch, from the committed counter
+# profile; used only while the kernel sources are those it was taken on.
+FIT_SOURCES = ("tpc_fit.hip", "tpc_fit_common.hpp", "tpc_fit_math.hpp", "tpc_internal.hpp")
+FIT_PROFILE = os.path.join(ROOT, "profiles", "fit_full_tpc_event_1e4_hbm.txt")
+
+
+def fit_source_sha():
+    h = hashlib.sha256()
+    for f in FIT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_13755_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def fit_profile_traffic():
+    """Calibrated HBM bytes per fit_tracks launch, or None if the profile is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(FIT_PROFILE) as f:
+            kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != fit_source_sha():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
 
 
 def timed(fn, steps, warmup):
@@ -150,17 +178,20 @@ def leg_main(args):
     st = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs])
     stage_ms = st.mean(axis=0)
     N = dfr.n_clusters
-    names = ["tpc_neighbours", "tpc_ca_seed", "tpc_kalman_fit (fit_tracks)"]
+    names = ["tpc_neighbours", "tpc_ca_seed", "tpc_kalman_fit"]
+    # Roofline of the dominant kernel: the Kalman filter (fit_tracks, the only
+    # kernel of tpc_kalman_fit when the seeds carry their hit coordinates),
+    # timed by the events around tpc_kalman_fit on its launch stream.
     fit_ms = float(stage_ms[2])
     fit_flops = FLOP_FIT_PER_HIT * n_hits
     achieved = fit_flops / (fit_ms * 1e-3) / 1e12
+    fit_bytes = B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds
     roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
+            "traffic": fit_profile_traffic(),
             "kernel": "fit_tracks", "avg_ms": round(fit_ms, 5),
-            "algorithmic_flops": int(fit_flops),
-            "algorithmic_bytes": int(B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds),
-            "hbm_frac": round((B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds)
-                              / (fit_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
+            "algorithmic_flops": int(fit_flops), "algorithmic_bytes": int(fit_bytes),
+            "hbm_frac": round(fit_bytes / (fit_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
     nb_gbs = B_NB_PER_CLUSTER * N / (stage_ms[0] * 1e-3) / 1e9
     seed_bytes = B_SEED_PER_CLUSTER * N + B_SEED_PER_HIT * n_hits + B_SEED_PER_SEED * n_seeds
     res = {

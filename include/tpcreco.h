@@ -83,6 +83,8 @@ typedef struct tpc_seeds {
     int32_t *offsets;              /* [cap_seeds + 1] hits of seed i: [offsets[i], offsets[i+1]) */
     int32_t *hits;                 /* [cap_hits] global cluster ids, ascending pad row */
     int32_t *frame, *sector, *first_row;   /* [cap_seeds] */
+    float *hit_yz;                 /* optional [cap_hits][2], 8-byte aligned, or NULL: (y, z)
+                                      of every seed hit, written by tpc_ca_seed */
 } tpc_seeds;
 
 /* Fitted tracks, one per seed (index = seed index). */
@@ -143,6 +145,11 @@ tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *frames,
  * the counters n_seeds and n_hits hold the required sizes and the arrays
  * hold a prefix).
  * ws: TPC_STAGE_SEED workspace. */
+/* (tpc_ca_seed, continued) When seeds->hit_yz is not NULL, the (y, z) of
+ * every placed seed hit is copied there from the frames, in seed-hit order,
+ * by the workgroups that place the hits (coalesced reads of the frames).
+ * The fit and the adjoint then read hit coordinates from it instead of
+ * gathering them by id. */
 tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
                        const int32_t *up, const int32_t *dn, tpc_seeds *seeds,
                        int32_t *dev_status, void *ws, size_t ws_bytes, void *stream);
@@ -154,9 +161,11 @@ tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
  * hit with covariance diag(sigma_y^2, sigma_z^2, var_sin0, var_tgl0,
  * var_qpt0); then for each hit inwards an exact helix step with its analytic
  * Jacobian (no process noise) and a Kalman update with the hit.  chi2 is the
- * sum of the predicted-residual chi2, ndf = 2n - 5.  The state, covariance
- * and update are carried in double precision, the Jacobian in single
- * precision; outputs are single precision.
+ * sum of the predicted-residual chi2, ndf = 2n - 5.  The state, Jacobian,
+ * covariance and update are carried in double precision; outputs are single
+ * precision.  Hit coordinates come from seeds->hit_yz when it is not NULL
+ * (it must then hold the coordinates of `frames`, as tpc_ca_seed writes
+ * them), else from frames->y/z by hit id.
  * map: optional [n_sectors][n_rows][2] (dy, dz) subtracted from every
  * cluster of that (sector, row) before fitting (NULL = none).
  * ckpt: optional device buffer of >= tpc_ckpt_bytes() bytes (8-byte

@@ -47,7 +47,8 @@ class FramesC(ctypes.Structure):
 
 class SeedsC(ctypes.Structure):
     _fields_ = [("cap_seeds", i32), ("cap_hits", i32), ("n_seeds", P), ("n_hits", P),
-                ("offsets", P), ("hits", P), ("frame", P), ("sector", P), ("first_row", P)]
+                ("offsets", P), ("hits", P), ("frame", P), ("sector", P), ("first_row", P),
+                ("hit_yz", P)]
 
 
 class TracksC(ctypes.Structure):

@@ -161,8 +161,12 @@ hipError_t launch_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tp
     float2 *partial;
     float2 *hyz;
     adj_ws_layout(ws, sd->cap_hits, sd->cap_seeds, n_fs, c.n_rows, c.ckpt_rows, &A.g, &A.tape, &partial, &hyz);
-    A.F.hyz = hyz;
-    launch_gather(fr, sd, hyz, st);
+    if (sd->hit_yz) {
+        A.F.hyz = reinterpret_cast<const float2 *>(sd->hit_yz);
+    } else {
+        A.F.hyz = hyz;
+        launch_gather(fr, sd, hyz, st);
+    }
     const int blocks = adj_blocks(sd->cap_seeds);
     A.nthreads = blocks * TPC_BLOCK;
     hipLaunchKernelGGL(adj_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);

@@ -90,6 +90,7 @@ tpc_status check_seeds_for_fit(const tpc_seeds *sd) {
     if (!sd->n_seeds || !sd->offsets) return fail(TPC_ERR_ARG, "null seed counters or offsets");
     if (sd->cap_seeds > 0 && (!sd->hits || !sd->sector || !sd->first_row || !sd->frame))
         return fail(TPC_ERR_ARG, "null seed arrays");
+    if (((uintptr_t)sd->hit_yz & 7) != 0) return fail(TPC_ERR_ARG, "hit_yz not 8-byte aligned");
     return TPC_OK;
 }
 
@@ -210,6 +211,7 @@ tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const int32
     if (sd->cap_seeds > 0 && (!sd->frame || !sd->sector || !sd->first_row))
         return fail(TPC_ERR_ARG, "null seed arrays");
     if (sd->cap_hits > 0 && !sd->hits) return fail(TPC_ERR_ARG, "null seed hits");
+    if (((uintptr_t)sd->hit_yz & 7) != 0) return fail(TPC_ERR_ARG, "hit_yz not 8-byte aligned");
     s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_SEED));
     if (s) return s;
     CaWs l;

@@ -45,6 +45,10 @@ __device__ inline bool linked(const int32_t *up, const int32_t *dn, int32_t N, i
     return link_up(up, dn, N, h) >= 0 || link_dn(up, dn, N, h) >= 0;
 }
 __device__ inline bool valid_id(int32_t v, int32_t N) { return (uint32_t)v < (uint32_t)N; }
+// (y, z) of seed hit j into the optional coordinate copy (one 8-byte store)
+__device__ inline void put_yz(float *hit_yz, int32_t j, float yv, float zv) {
+    reinterpret_cast<float2 *>(hit_yz)[j] = make_float2(yv, zv);
+}
 __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
     return ((unsigned long long)(2147483648u - (uint32_t)m) << 32) | (uint32_t)b;
 }
@@ -233,8 +237,9 @@ __device__ inline void ca_firsts_seg(int seg, int32_t N, const int32_t *__restri
 
 // Contains barriers: call from the whole workgroup.  Returns nothing; seeds
 // of the segment go to [segbs[seg], ...) within capacity.
-__device__ inline void ca_place_seg(int seg, const int32_t *__restrict__ off,
+__device__ inline void ca_place_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                    const float *__restrict__ y, const float *__restrict__ z,
                                     int32_t n_sectors, int32_t n_rows, int32_t cap_seeds,
                                     int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws,
                                     int32_t *len_hist = nullptr) {
@@ -262,9 +267,16 @@ __device__ inline void ca_place_seg(int seg, const int32_t *__restrict__ off,
                 sd.sector[i] = sector;
                 sd.first_row[i] = row;
                 const int32_t wb = (h != fb);
-                if (wb) sd.hits[o] = h;
+                if (wb) {
+                    sd.hits[o] = h;
+                    if (sd.hit_yz) put_yz(sd.hit_yz, o, y[h], z[h]);
+                }
                 const int32_t m = ws.core[fb];
-                if (len > m + wb) sd.hits[o + len - 1] = up[ws.ctop[fb]];
+                if (len > m + wb) {
+                    const int32_t et = up[ws.ctop[fb]];
+                    sd.hits[o + len - 1] = et;
+                    if (sd.hit_yz && valid_id(et, N)) put_yz(sd.hit_yz, o + len - 1, y[et], z[et]);
+                }
                 ws.choff[fb] = o + wb;
                 if (len_hist) atomicAdd(&len_hist[len < TPC_MAX_ROWS ? len : TPC_MAX_ROWS], 1);
             }
@@ -276,6 +288,7 @@ __device__ inline void ca_place_seg(int seg, const int32_t *__restrict__ off,
 
 __device__ inline void ca_members_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                       const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                      const float *__restrict__ y, const float *__restrict__ z,
                                       int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
@@ -283,7 +296,10 @@ __device__ inline void ca_members_seg(int seg, int32_t N, const int32_t *__restr
         const int32_t bb = ws.memb[h];
         if (!valid_id(bb, N)) continue;
         const int32_t o = ws.choff[bb], k = ws.mpos[h];
-        if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) sd.hits[o + k] = h;
+        if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) {
+            sd.hits[o + k] = h;
+            if (sd.hit_yz) put_yz(sd.hit_yz, o + k, y[h], z[h]);
+        }
     }
 }
 

@@ -76,17 +76,17 @@ ca_scan(int32_t NR, CaWs ws, int32_t *__restrict__ n_seeds, int32_t *__restrict_
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-ca_place(const int32_t *off, const int32_t *up, const int32_t *dn, int32_t n_sectors, int32_t n_rows,
-         int32_t cap_seeds, int32_t cap_hits, tpc_seeds sd, CaWs ws) {
+ca_place(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, const float *y, const float *z,
+         int32_t n_sectors, int32_t n_rows, int32_t cap_seeds, int32_t cap_hits, tpc_seeds sd, CaWs ws) {
     const int seg = xcd_item(blockIdx.x, gridDim.x);
-    ca_place_seg(seg, off, up, dn, n_sectors, n_rows, cap_seeds, cap_hits, sd, ws);
+    ca_place_seg(seg, N, off, up, dn, y, z, n_sectors, n_rows, cap_seeds, cap_hits, sd, ws);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-ca_members(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, int32_t cap_hits,
-           tpc_seeds sd, CaWs ws) {
+ca_members(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, const float *y,
+           const float *z, int32_t cap_hits, tpc_seeds sd, CaWs ws) {
     const int seg = xcd_item(blockIdx.x, gridDim.x);
-    ca_members_seg(seg, N, off, up, dn, cap_hits, sd, ws);
+    ca_members_seg(seg, N, off, up, dn, y, z, cap_hits, sd, ws);
 }
 
 }  // namespace
@@ -106,9 +106,10 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
     hipLaunchKernelGGL(ca_firsts, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, ws);
     hipLaunchKernelGGL(ca_scan, dim3(1), dim3(1024), 0, st, NR, ws, sd->n_seeds, sd->n_hits,
                        sd->cap_seeds, sd->cap_hits, sd->offsets, dev_status);
-    hipLaunchKernelGGL(ca_place, dim3(NR), dim3(TPC_BLOCK), 0, st, off, up, dn, c.n_sectors,
-                       c.n_rows, sd->cap_seeds, sd->cap_hits, *sd, ws);
-    hipLaunchKernelGGL(ca_members, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, sd->cap_hits, *sd, ws);
+    hipLaunchKernelGGL(ca_place, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, fr->y, fr->z,
+                       c.n_sectors, c.n_rows, sd->cap_seeds, sd->cap_hits, *sd, ws);
+    hipLaunchKernelGGL(ca_members, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, fr->y, fr->z,
+                       sd->cap_hits, *sd, ws);
     return hipGetLastError();
 }
 

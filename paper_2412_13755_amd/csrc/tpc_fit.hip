@@ -114,10 +114,14 @@ hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
     FitArgs A = make_fit_args(ctx, fr, sd, map);
     A.out = *tr;
     A.ckpt = ckpt;
-    float2 *hyz;
-    fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz);
-    A.hyz = hyz;
-    launch_gather(fr, sd, hyz, st);
+    if (sd->hit_yz) {
+        A.hyz = reinterpret_cast<const float2 *>(sd->hit_yz);
+    } else {
+        float2 *hyz;
+        fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz);
+        A.hyz = hyz;
+        launch_gather(fr, sd, hyz, st);
+    }
     int blocks = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;

@@ -193,11 +193,11 @@ persist_reco(PersistArgs P) {
     }
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_place_seg(seg, P.off, P.up, P.dn, P.n_sectors, P.n_rows, P.sd.cap_seeds,
+        tpc_ca::ca_place_seg(seg, P.N, P.off, P.up, P.dn, P.y, P.z, P.n_sectors, P.n_rows, P.sd.cap_seeds,
                              P.sd.cap_hits, P.sd, P.ca, P.len_hist);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_members_seg(seg, P.N, P.off, P.up, P.dn, P.sd.cap_hits, P.sd, P.ca);
+        tpc_ca::ca_members_seg(seg, P.N, P.off, P.up, P.dn, P.y, P.z, P.sd.cap_hits, P.sd, P.ca);
     if (bid == 0 && P.sort_fit) {
         // bin starts in descending length order
         if (tid == 0) {
@@ -212,10 +212,12 @@ persist_reco(PersistArgs P) {
     }
     if (!grid_sync(P)) return;
     {
-        // seed-ordered hit coordinates for the fit; placed seeds form the
+        // seed-ordered hit coordinates for the fit (unless the seeds carry
+        // them); placed seeds form the
         // prefix [0, n_placed): with sort_fit, order them by length
         int H = *P.sd.n_hits;
         if (H > P.sd.cap_hits) H = P.sd.cap_hits;
+        if (P.sd.hit_yz) H = 0;         // placement has written them already
         for (int j = bid * TPC_BLOCK + tid; j < H; j += G * TPC_BLOCK) {
             const int32_t id = P.sd.hits[j];
             P.hyz[j] = (uint32_t)id < (uint32_t)P.N ? make_float2(P.y[id], P.z[id]) : make_float2(0.f, 0.f);
@@ -322,6 +324,7 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
     P.F.out = *tr;
     P.sort_fit = sort_fit;
     persist_ws_layout(ws, fr->n_clusters, P.NR, sd->cap_seeds, sd->cap_hits, &P);
+    if (sd->hit_yz) P.hyz = reinterpret_cast<float2 *>(sd->hit_yz);
     P.F.hyz = P.hyz;
     hipLaunchKernelGGL(persist_init, dim3(2), dim3(TPC_BLOCK), 0, st, P);
     hipLaunchKernelGGL(persist_reco, dim3(grid), dim3(TPC_BLOCK), 0, st, P);

@@ -85,11 +85,13 @@ class Seeds:
     sector: torch.Tensor
     first_row: torch.Tensor
     status: torch.Tensor       # device int32 status word
+    hit_yz: Optional[torch.Tensor] = None   # [cap_hits, 2] float32 seed-hit coordinates, or None
 
     def c(self) -> C.SeedsC:
         return C.SeedsC(self.frame.numel(), self.hits.numel(), self.n_seeds.data_ptr(),
                         self.n_hits.data_ptr(), self.offsets.data_ptr(), self.hits.data_ptr(),
-                        self.frame.data_ptr(), self.sector.data_ptr(), self.first_row.data_ptr())
+                        self.frame.data_ptr(), self.sector.data_ptr(), self.first_row.data_ptr(),
+                        self.hit_yz.data_ptr() if self.hit_yz is not None else None)
 
     def to_numpy(self) -> dict:
         ns = int(self.n_seeds.item())
@@ -175,7 +177,9 @@ class Reco:
                                        ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return up, dn
 
-    def alloc_seeds(self, frames: DeviceFrames, cap_seeds=None, cap_hits=None) -> Seeds:
+    def alloc_seeds(self, frames: DeviceFrames, cap_seeds=None, cap_hits=None, hit_yz=True) -> Seeds:
+        """Seed buffers; with hit_yz the seeding also stores the coordinates of
+        every seed hit, which the fit and the adjoint then read directly."""
         N = frames.n_clusters
         # every seed holds >= min_hits distinct clusters: these bounds never overflow
         cs = N // self.cfg.min_hits + 1 if cap_seeds is None else int(cap_seeds)
@@ -184,7 +188,8 @@ class Reco:
         return Seeds(torch.zeros(1, dtype=i, device=d), torch.zeros(1, dtype=i, device=d),
                      torch.zeros(cs + 1, dtype=i, device=d), torch.empty(ch, dtype=i, device=d),
                      torch.empty(cs, dtype=i, device=d), torch.empty(cs, dtype=i, device=d),
-                     torch.empty(cs, dtype=i, device=d), torch.zeros(1, dtype=i, device=d))
+                     torch.empty(cs, dtype=i, device=d), torch.zeros(1, dtype=i, device=d),
+                     torch.empty(ch, 2, dtype=torch.float32, device=d) if hit_yz else None)
 
     def seed(self, frames: DeviceFrames, up, dn, seeds: Optional[Seeds] = None, ws=None) -> Seeds:
         seeds = self.alloc_seeds(frames) if seeds is None else seeds

@@ -235,3 +235,28 @@ def test_fit_with_map_matches_oracle(torch_dev):
               status=tr.status[:T].cpu().numpy())
     rt = oracle.fit(sd, fr.y, fr.z, fr.row_x, fr.n_rows, map_=mp.astype(np.float64), **FIT)
     parity.compare_fit(gt, rt)
+
+
+def test_seed_hit_coordinates_and_gather_path(torch_dev):
+    """The coordinates stored by the seeding are the frames' coordinates of
+    the seed hits, and the fit gives bit-identical tracks whether it reads
+    them or gathers them by id (seeds without coordinates)."""
+    import torch
+    fr = make_config(1, scale=0.2)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours(dfr)
+    with_yz = reco.seed(dfr, up, dn)
+    without = reco.seed(dfr, up, dn, seeds=reco.alloc_seeds(dfr, hit_yz=False))
+    ta = reco.fit(dfr, with_yz)
+    tb = reco.fit(dfr, without)
+    torch.cuda.synchronize()
+    sd = with_yz.to_numpy()
+    parity.assert_seeds_equal(sd, without.to_numpy())
+    H, T = len(sd["hits"]), len(sd["offsets"]) - 1
+    yz = with_yz.hit_yz[:H].cpu().numpy()
+    np.testing.assert_array_equal(yz[:, 0], fr.y[sd["hits"]])
+    np.testing.assert_array_equal(yz[:, 1], fr.z[sd["hits"]])
+    for k in ("x", "par", "cov", "chi2", "ndf", "status"):
+        np.testing.assert_array_equal(getattr(ta, k)[:T].cpu().numpy(), getattr(tb, k)[:T].cpu().numpy(),
+                                      err_msg=k)
