@@ -125,24 +125,19 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
             hit_fix(A, sv, k, raw, my, mz);
             if (k > 0) raw = hit_raw(A, sv, k - 1, A.hyz ? 0 : sv.hh[k - 1]);
             const float xk = xs[sv.row0 + k];
+            // one exit test per step: the step and the update are evaluated
+            // unconditionally and a failed track's final state is not used
             StepJac J;
-            if (!helix_step(p, xk - xcur, A.kbz, A.max_sin, J)) {
-                status = TPC_FIT_SIN_FAIL;
+            const bool stepped = helix_step(p, xk - xcur, A.kbz, A.max_sin, J);
+            sym_transport<double, false>(C, J);
+            const double dchi = kalman_update<double>(p, C, my, mz, A.vy, A.vz);
+            chi2 += dchi;
+            const double chk = chi2 + p[0] + p[1] + p[2] + p[3] + p[4];
+            if (!stepped || !(dchi >= 0.0) || !(chk - chk == 0.0)) {   // non-finite state too
+                status = stepped ? TPC_FIT_NUM_FAIL : TPC_FIT_SIN_FAIL;
                 break;
             }
             xcur = xk;
-            sym_transport<double, false>(C, J);
-            const double dchi = kalman_update<double>(p, C, my, mz, A.vy, A.vz);
-            if (!(dchi >= 0.0)) {
-                status = TPC_FIT_NUM_FAIL;
-                break;
-            }
-            chi2 += dchi;
-            const double chk = chi2 + p[0] + p[1] + p[2] + p[3] + p[4];
-            if (!(chk - chk == 0.0)) {                 // non-finite state
-                status = TPC_FIT_NUM_FAIL;
-                break;
-            }
             // state after j updates opens segment j / K of the adjoint
             if (ck && j % A.ckpt_rows == 0 && k > 0)
                 write_ckpt(ck + (size_t)(j / A.ckpt_rows) * TPC_CKPT_WORDS, p, C);

@@ -99,6 +99,16 @@ __host__ __device__ inline double sqrt_pos(double x, double *inv) {
 #endif
 }
 
+// asin(u)/u and its derivative away from 0 (|u| >= 0.05: a step that turns
+// the track by more than ~6 degrees).  Out of line: rarely taken, and the
+// library asin would otherwise occupy registers in the filter loop.
+__host__ __device__ __attribute__((noinline)) inline double asin_over_far(double u) {
+    return asin(u) / u;
+}
+__host__ __device__ __attribute__((noinline)) inline double asin_over_d_far(double u) {
+    return (u / sqrt((1.0 - u) * (1.0 + u)) - asin(u)) / (u * u);
+}
+
 // asin(u)/u in the state precision (Taylor series to u^8 near 0)
 template <class R>
 __host__ __device__ inline R asin_over_r(R u) {
@@ -106,7 +116,7 @@ __host__ __device__ inline R asin_over_r(R u) {
         const R u2 = u * u;
         return (R)1 + u2 * ((R)1 / 6 + u2 * ((R)3 / 40 + u2 * ((R)5 / 112 + u2 * ((R)35 / 1152))));
     }
-    return asin(u) / u;
+    return (R)asin_over_far((double)u);
 }
 
 // first derivative of asin(u)/u in the state precision
@@ -116,21 +126,22 @@ __host__ __device__ inline R asin_over_d_r(R u) {
         const R u2 = u * u;
         return u * ((R)1 / 3 + u2 * ((R)3 / 10 + u2 * ((R)15 / 56 + u2 * ((R)35 / 144))));
     }
-    return (u / sqrt(((R)1 - u) * ((R)1 + u)) - asin(u)) / (u * u);
+    return (R)asin_over_d_far((double)u);
 }
 
 // Exact helix step from x to x + dx, state and Jacobian in precision R
 // (double in the library: on gfx950 the FP64 vector FMA issues at the rate
 // of the non-packed FP32 one, so a single-precision Jacobian would only add
-// conversions).  Returns false when |sin phi| reaches max_sin (p is then
-// left unchanged).
+// conversions).  Returns false when |sin phi| reaches max_sin before or
+// after the step; the step is evaluated regardless (no early exit keeps the
+// filter loop free of branches), so p and J are then meaningless.
 template <class R>
 __host__ __device__ inline bool helix_step(R p[5], float dx, float kbz, float max_sin, StepJac &J) {
     // kbz = -c Bz, so kappa = kbz * w
     const R s = p[2], t = p[3], w = p[4];
     const R kap = (R)kbz * w;
     const R s2 = s + kap * (R)dx;
-    if (!(fabs(s) < (R)max_sin) || !(fabs(s2) < (R)max_sin)) return false;
+    const bool ok = fabs(s) < (R)max_sin && fabs(s2) < (R)max_sin;
     R ic1, ic2, isq;
     const R c1 = sqrt_pos(((R)1 - s) * ((R)1 + s), &ic1);
     const R c2 = sqrt_pos(((R)1 - s2) * ((R)1 + s2), &ic2);
@@ -165,7 +176,7 @@ __host__ __device__ inline bool helix_step(R p[5], float dx, float kbz, float ma
     p[0] += (R)dx * T;
     p[1] += t * arc;
     p[2] = s2;
-    return true;
+    return ok;
 }
 
 // Symmetric transport with the sparse step Jacobian F = I + N:
@@ -243,13 +254,14 @@ __host__ __device__ inline void sym_transport(SymT<R> &C, const StepJac &J) {
 }
 
 // Kalman update with measurement (my, mz); returns the chi2 increment, or a
-// negative value if the residual covariance is not positive definite.
+// negative value if the residual covariance is not positive definite (the
+// update is evaluated regardless, and p, C are then meaningless).
 template <class R>
 __host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy, R vz) {
     const R r0 = my - p[0], r1 = mz - p[1];
     const R S00 = C.c00 + vy, S01 = C.c10, S11 = C.c11 + vz;
     const R det = S00 * S11 - S01 * S01;
-    if (!(det > (R)0)) return (R)-1;
+    const bool pd = det > (R)0;
     const R idet = recip_pos(det);
     const R i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
     // K = C[:, 0:2] S^-1
@@ -282,7 +294,8 @@ __host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy,
     C.c42 = C.c42 - k40 * r02 - k41 * r12;
     C.c43 = C.c43 - k40 * r03 - k41 * r13;
     C.c44 = C.c44 - k40 * r04 - k41 * r14;
-    return r0 * (i00 * r0 + i01 * r1) + r1 * (i01 * r0 + i11 * r1);
+    const R chi = r0 * (i00 * r0 + i01 * r1) + r1 * (i01 * r0 + i11 * r1);
+    return pd ? chi : (R)-1;
 }
 
 // Exact circle through C (innermost), B, A (outermost): state at A, computed

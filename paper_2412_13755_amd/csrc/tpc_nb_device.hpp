@@ -188,16 +188,22 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
 // Best (up, down) pair for cluster (yh, zh) in the cell-sorted up row (UY,
 // UZ, UI, UCS, gu) and down row (D...).  UCS[c] indexes the first cluster of
 // cell c in UY/UZ/UI; a stored id k stands for cluster ubase + k (dbase + k
-// in the down row).  Every operation is one single-precision rounding.
+// in the down row).  Every operation is one single-precision rounding, and
+// the predicates are evaluated on exactly the operands of the definition:
+// ay = y_u - y_h, by = y_h - y_d, dy = ay - by (z likewise).
 //
-// Cells scanned: in the up row, those overlapping [h - win - m, h + win + m];
-// for an up candidate u in the window, in the down row those overlapping
-// [c - cut - m, c + cut + m] around the straight-line prediction c = h - (u - h)
-// (a down partner's second difference is at most the cut).  The margin m is
-// far above the rounding of the predicates and of c, and cell_coord is
-// monotonic, so every cluster that can pass the exact predicates is visited.
-// A cluster h with a non-finite coordinate fails every window, so it is
-// skipped.
+// Enumeration: the down-row clusters in h's window are collected first (up
+// to TPC_NB_DLIST in registers); then every up-row cluster in the window is
+// paired with that list.  If more down clusters are in the window, each up
+// candidate instead scans the down-row cells that overlap the cut interval
+// around its straight-line prediction c = h - (u - h).  Cells scanned are
+// those overlapping [h - win - m, h + win + m] (or [c - cut - m, c + cut + m])
+// with a margin m far above the rounding of the predicates and of c; as
+// cell_coord is monotonic, every cluster that can pass the exact predicates
+// is visited.  A cluster h with a non-finite coordinate fails every window,
+// so it is skipped.
+#define TPC_NB_DLIST 4
+
 template <class FP, class IP, class CP>
 __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS, const SegGrid &gu,
                                  int32_t ubase, FP DY, FP DZ, IP DI, CP DCS, const SegGrid &gd,
@@ -208,6 +214,32 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
     const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
     const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
     const float wy = win_y + my, wz = win_z + mz, ky = cut_y + my, kz = cut_z + mz;
+    // down clusters in the window
+    float lb[TPC_NB_DLIST][2];
+    int32_t ld[TPC_NB_DLIST];
+#pragma unroll
+    for (int j = 0; j < TPC_NB_DLIST; ++j) { lb[j][0] = 0.f; lb[j][1] = 0.f; ld[j] = -1; }
+    int nd = 0;
+    {
+        const int y0 = cell_coord(yh - wy, gd.y0, gd.iwy, gd.ny), y1 = cell_coord(yh + wy, gd.y0, gd.iwy, gd.ny);
+        const int z0 = cell_coord(zh - wz, gd.z0, gd.iwz, gd.nz), z1 = cell_coord(zh + wz, gd.z0, gd.iwz, gd.nz);
+        for (int iy = y0; iy <= y1; ++iy) {
+            const int e0 = DCS[iy * gd.nz + z0];
+            const int e1 = DCS[iy * gd.nz + z1 + 1];
+            for (int kd = e0; kd < e1; ++kd) {
+                const float by = yh - DY[kd];
+                const float bz = zh - DZ[kd];
+                if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
+                const int32_t d = dbase + (int32_t)DI[kd];
+#pragma unroll
+                for (int j = 0; j < TPC_NB_DLIST; ++j)
+                    if (nd == j) { lb[j][0] = by; lb[j][1] = bz; ld[j] = d; }
+                ++nd;
+            }
+        }
+    }
+    if (nd == 0) return best;
+    const bool listed = nd <= TPC_NB_DLIST;
     const int yu0 = cell_coord(yh - wy, gu.y0, gu.iwy, gu.ny), yu1 = cell_coord(yh + wy, gu.y0, gu.iwy, gu.ny);
     const int zu0 = cell_coord(zh - wz, gu.z0, gu.iwz, gu.nz), zu1 = cell_coord(zh + wz, gu.z0, gu.iwz, gu.nz);
     for (int iyu = yu0; iyu <= yu1; ++iyu) {
@@ -218,6 +250,20 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
             const float az = UZ[ku] - zh;
             if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
             const int32_t u = ubase + (int32_t)UI[ku];
+            if (listed) {
+#pragma unroll
+                for (int j = 0; j < TPC_NB_DLIST; ++j) {
+                    const float dy = ay - lb[j][0];
+                    const float dz = az - lb[j][1];
+                    if (j < nd && fabsf(dy) <= cut_y && fabsf(dz) <= cut_z) {
+                        const float qy = dy * dy;
+                        const float qz = dz * dz;
+                        const float q = qy + qz;
+                        if (better(q, u, ld[j], best)) { best.q = q; best.u = u; best.d = ld[j]; }
+                    }
+                }
+                continue;
+            }
             const float cy = yh - ay, cz = zh - az;
             const int yd0 = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
             const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
@@ -245,19 +291,25 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
     return best;
 }
 
-// LDS form of a row pair: both rows of up to TPC_LDS_ROW clusters each, with
-// finer cells than the global form (up to 4 per cluster, TPC_LDS_CELLS per
-// row) so that the 3x3 cells around h hold few candidates.
+// LDS form of a row pair: both rows of up to ROW clusters each, with finer
+// cells than the global form (up to 4 per cluster, CELLS per row) so that
+// the cells around h hold few candidates.  Two sizes: the small one keeps
+// the workgroup's LDS at 18 KB (8 workgroups per CU), the large one at
+// 37 KB for rows of up to TPC_LDS_ROW clusters.
 #define TPC_LDS_CELLS 2048
-#define TPC_PAIR_PT (2 * TPC_LDS_ROW / TPC_BLOCK)   // row-pair clusters per thread
+#define TPC_LDS_ROW_S 512
+#define TPC_LDS_CELLS_S 1024
 
-struct PairLds {
-    float y[2 * TPC_LDS_ROW], z[2 * TPC_LDS_ROW];
-    uint16_t rel[2 * TPC_LDS_ROW];              // cluster id minus its row's first id
-    int32_t cs[2 * TPC_LDS_CELLS + 2];          // cell starts of both rows, concatenated
+template <int ROW, int CELLS>
+struct PairLdsT {
+    float y[2 * ROW], z[2 * ROW];
+    uint16_t rel[2 * ROW];                  // cluster id minus its row's first id
+    int32_t cs[2 * CELLS + 2];              // cell starts of both rows, concatenated
     float red[8][TPC_BLOCK / TPC_WAVE];
     int scan_sh[TPC_BLOCK / TPC_WAVE];
 };
+using PairLds = PairLdsT<TPC_LDS_ROW, TPC_LDS_CELLS>;
+using PairLdsSmall = PairLdsT<TPC_LDS_ROW_S, TPC_LDS_CELLS_S>;
 
 // Bins the down row [ra0, rb0) and the up row [ra1, rb1) with one LDS
 // counting sort over the concatenated cell range (whole workgroup; contains
@@ -268,23 +320,26 @@ __device__ inline int pair_cell(float yv, float zv, const SegGrid &g) {
     return cell_coord(yv, g.y0, g.iwy, g.ny) * g.nz + cell_coord(zv, g.z0, g.iwz, g.nz);
 }
 
+template <int CELLS>
 __device__ inline SegGrid pair_grid(float ymin, float ymax, float zmin, float zmax, int n, float win_y,
                                     float win_z) {
     if (n == 0) return SegGrid{0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
-    const int cap = 4 * n < TPC_LDS_CELLS ? 4 * n : TPC_LDS_CELLS;
+    const int cap = 4 * n < CELLS ? 4 * n : CELLS;
     return row_grid(ymin, ymax, zmin, zmax, cap, cap, win_y, win_z);
 }
 
+template <int ROW, int CELLS>
 __device__ inline void pair_bin(const float *__restrict__ y, const float *__restrict__ z, int ra0, int rb0,
-                                int ra1, int rb1, float win_y, float win_z, PairLds &L, SegGrid &gd,
-                                SegGrid &gu, int &C0) {
+                                int ra1, int rb1, float win_y, float win_z, PairLdsT<ROW, CELLS> &L,
+                                SegGrid &gd, SegGrid &gu, int &C0) {
 #pragma clang fp contract(off)
+    constexpr int PT = 2 * ROW / TPC_BLOCK;      // row-pair clusters per thread
     const int tid = threadIdx.x;
     const int n0 = rb0 - ra0, n1 = rb1 - ra1, nt = n0 + n1;
     // both rows are read once, into registers (one global round trip)
-    float vy[TPC_PAIR_PT], vz[TPC_PAIR_PT];
+    float vy[PT], vz[PT];
 #pragma unroll
-    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+    for (int j = 0; j < PT; ++j) {
         const int k = tid + j * TPC_BLOCK;
         vy[j] = 0.f;
         vz[j] = 0.f;
@@ -297,7 +352,7 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
     // finite extents of both rows
     float e[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
 #pragma unroll
-    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+    for (int j = 0; j < PT; ++j) {
         const int k = tid + j * TPC_BLOCK;
         const bool fy = k < nt && isfinite(vy[j]), fz = k < nt && isfinite(vz[j]);
         if (k < n0) {
@@ -324,16 +379,16 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
             v = (j & 1) ? fmaxf(v, L.red[j][w]) : fminf(v, L.red[j][w]);
         e[j] = v;
     }
-    gd = pair_grid(e[0], e[1], e[2], e[3], n0, win_y, win_z);
-    gu = pair_grid(e[4], e[5], e[6], e[7], n1, win_y, win_z);
+    gd = pair_grid<CELLS>(e[0], e[1], e[2], e[3], n0, win_y, win_z);
+    gu = pair_grid<CELLS>(e[4], e[5], e[6], e[7], n1, win_y, win_z);
     C0 = gd.ny * gd.nz;
     const int C = C0 + gu.ny * gu.nz;
     for (int c = tid; c < C + 2; c += TPC_BLOCK) L.cs[c] = 0;
     __syncthreads();
     // count cell c into cs[c + 2]
-    int cell[TPC_PAIR_PT];
+    int cell[PT];
 #pragma unroll
-    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+    for (int j = 0; j < PT; ++j) {
         const int k = tid + j * TPC_BLOCK;
         cell[j] = k < n0 ? pair_cell(vy[j], vz[j], gd) : C0 + pair_cell(vy[j], vz[j], gu);
         if (k < nt) atomicAdd(&L.cs[cell[j] + 2], 1);
@@ -356,7 +411,7 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
     // scatter; the cursor of cell c moves from its start to its end, which
     // leaves cs[c] = start of cell c for every c in [0, C]
 #pragma unroll
-    for (int j = 0; j < TPC_PAIR_PT; ++j) {
+    for (int j = 0; j < PT; ++j) {
         const int k = tid + j * TPC_BLOCK;
         if (k < nt) {
             const int slot = atomicAdd(&L.cs[cell[j] + 1], 1);
@@ -368,27 +423,42 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
     __syncthreads();
 }
 
+// Does h-row `seg` (an interior, non-empty row) have neighbour rows that fit
+// the small LDS form?
+__device__ inline bool small_pair(const int32_t *off, int seg) {
+    return seg_size(off, seg - 1) <= TPC_LDS_ROW_S && seg_size(off, seg + 1) <= TPC_LDS_ROW_S;
+}
+
+// Which segments a query call handles.
+enum NbClass { NB_ALL = 0, NB_SMALL = 1, NB_NOT_SMALL = 2 };
+
 // Best triplet of every cluster of h-row `seg` (whole workgroup; contains
-// barriers; L is the workgroup's LDS scratch).  When both neighbouring rows hold at most TPC_LDS_ROW clusters
-// the workgroup bins them itself into LDS (coalesced reads, then every
-// candidate access is an LDS access); otherwise it reads the global
-// cell-sorted rows written by nb_bin_seg.
+// barriers; L is the workgroup's LDS scratch).  When both neighbouring rows
+// hold at most ROW clusters the workgroup bins them itself into LDS
+// (coalesced reads, then every candidate access is an LDS access);
+// otherwise it reads the global cell-sorted rows written by nb_bin_seg.
+// cls selects the segments handled (the others return at once), so that a
+// small-LDS and a large-LDS launch can share the rows between them.
+template <int ROW, int CELLS>
 __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, int32_t n_rows,
                                     const float *__restrict__ y, const float *__restrict__ z,
                                     float win_y, float win_z, float cut_y, float cut_z,
                                     const SegGrid *__restrict__ grid, const int32_t *__restrict__ cstart,
                                     const float *__restrict__ sy, const float *__restrict__ sz,
                                     const int32_t *__restrict__ sid, int32_t *__restrict__ up,
-                                    int32_t *__restrict__ dn, PairLds &L) {
+                                    int32_t *__restrict__ dn, PairLdsT<ROW, CELLS> &L, NbClass cls) {
 #pragma clang fp contract(off)
     const int r = seg % n_rows;
     const int a = off[seg], b = off[seg + 1];
-    if (r == 0 || r == n_rows - 1) {
+    const bool edge = r == 0 || r == n_rows - 1;
+    const bool small = !edge && a != b && small_pair(off, seg);
+    if ((cls == NB_SMALL && !small) || (cls == NB_NOT_SMALL && small)) return;
+    if (edge) {
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) { up[i] = -1; dn[i] = -1; }
         return;
     }
     if (a == b) return;
-    if (!query_global(off, seg, n_rows)) {
+    if (seg_size(off, seg - 1) <= ROW && seg_size(off, seg + 1) <= ROW) {
         const int ra0 = off[seg - 1], ra1 = off[seg + 1];
         // the first h of each thread is loaded together with the row pair
         float hy = 0.f, hz = 0.f;

@@ -13,6 +13,18 @@ nb_bin(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict_
     tpc_nb::nb_bin_seg(seg, n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid);
 }
 
+// Rows whose neighbour rows fit the small LDS form (18 KB per workgroup).
+__global__ void __launch_bounds__(TPC_BLOCK)
+nb_query_small(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
+               const float *__restrict__ z, float win_y, float win_z, float cut_y, float cut_z,
+               int32_t *up, int32_t *dn) {
+    __shared__ tpc_nb::PairLdsSmall L;
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    tpc_nb::nb_query_seg(seg, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, up, dn, L, tpc_nb::NB_SMALL);
+}
+
+// All other rows: large LDS form, or the global cell-sorted rows.
 __global__ void __launch_bounds__(TPC_BLOCK)
 nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
          const float *__restrict__ z, float win_y, float win_z, float cut_y, float cut_z,
@@ -21,7 +33,7 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
     __shared__ tpc_nb::PairLds L;
     const int seg = xcd_item(blockIdx.x, gridDim.x);
     tpc_nb::nb_query_seg(seg, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
-                         sz, sid, up, dn, L);
+                         sz, sid, up, dn, L, tpc_nb::NB_NOT_SMALL);
 }
 
 }  // namespace
@@ -33,6 +45,8 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
     const tpc_config &c = ctx->cfg;
     hipLaunchKernelGGL(nb_bin, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
                        fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid);
+    hipLaunchKernelGGL(nb_query_small, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows,
+                       fr->y, fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, up, dn);
     hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
                        fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz,
                        ws.sid, up, dn);

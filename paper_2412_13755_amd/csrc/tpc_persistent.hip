@@ -117,7 +117,8 @@ persist_reco(PersistArgs P) {
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.y, P.z, P.win_y, P.win_z, P.cut_y, P.cut_z,
-                             P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.nb);
+                             P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.nb,
+                             tpc_nb::NB_ALL);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_ca::ca_links_seg(seg, P.N, P.off, P.up, P.dn, P.ca);
