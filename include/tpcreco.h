@@ -144,12 +144,11 @@ tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *frames,
  * dev_status: device int32, set to TPC_OK or TPC_ERR_CAPACITY (then
  * the counters n_seeds and n_hits hold the required sizes and the arrays
  * hold a prefix).
+ * When seeds->hit_yz is not NULL, the (y, z) of every placed seed hit is
+ * copied there from the frames, in seed-hit order, by the workgroups that
+ * place the hits (coalesced reads of the frames); the fit and the adjoint
+ * then read hit coordinates from it instead of gathering them by id.
  * ws: TPC_STAGE_SEED workspace. */
-/* (tpc_ca_seed, continued) When seeds->hit_yz is not NULL, the (y, z) of
- * every placed seed hit is copied there from the frames, in seed-hit order,
- * by the workgroups that place the hits (coalesced reads of the frames).
- * The fit and the adjoint then read hit coordinates from it instead of
- * gathering them by id. */
 tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
                        const int32_t *up, const int32_t *dn, tpc_seeds *seeds,
                        int32_t *dev_status, void *ws, size_t ws_bytes, void *stream);
