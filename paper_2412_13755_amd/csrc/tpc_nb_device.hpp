@@ -29,12 +29,15 @@
 namespace tpc_nb {
 
 
+// Cell index of coordinate v on an axis of n cells starting at v0, 1/edge iw
+// (iw = 0 when n = 1).  Monotonic non-decreasing in v; NaN and values below
+// the axis go to cell 0, values beyond it (+inf too) to cell n - 1.
+// Branch-free: fmaxf returns the number when the other operand is NaN.
 __device__ inline int cell_coord(float v, float v0, float iw, int n) {
 #pragma clang fp contract(off)
-    if (n <= 1) return 0;
     float c = (v - v0) * iw;
-    if (!(c >= 0.0f)) return 0;                     // negative or NaN
-    if (c >= (float)(n - 1)) return n - 1;          // also +inf
+    c = fmaxf(c, 0.0f);
+    c = fminf(c, (float)(n - 1));
     return (int)c;                                  // floor for c >= 0
 }
 
@@ -177,12 +180,10 @@ struct Best {
     int32_t u, d;
 };
 
+// Lexicographic (q, u, d) order against the best so far (none yet: u < 0).
 __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
-    if (b.u < 0) return true;
-    if (q < b.q) return true;
-    if (q > b.q) return false;
-    if (u != b.u) return u < b.u;
-    return d < b.d;
+    const bool tie = q == b.q;
+    return (b.u < 0) | (q < b.q) | (tie & (u < b.u)) | (tie & (u == b.u) & (d < b.d));
 }
 
 // Best (up, down) pair for cluster (yh, zh) in the cell-sorted up row (UY,

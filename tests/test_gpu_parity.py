@@ -260,3 +260,20 @@ def test_seed_hit_coordinates_and_gather_path(torch_dev):
     for k in ("x", "par", "cov", "chi2", "ndf", "status"):
         np.testing.assert_array_equal(getattr(ta, k)[:T].cpu().numpy(), getattr(tb, k)[:T].cpu().numpy(),
                                       err_msg=k)
+
+
+def test_dense_rows_every_neighbour_and_ranking_form(torch_dev):
+    """Two frames dense enough that rows go through all three neighbour forms
+    (small LDS, large LDS for 513..1024 clusters, cell-sorted global copy
+    above 1024) and some 16-row blocks exceed the LDS chain-ranking
+    capacity (8192 clusters): bit-exact links and seeds, fit within
+    tolerance."""
+    from tpcsynth import make_frames
+    fr = make_frames(n_sectors=36, n_rows=48, tracks_per_frame=(2600, 6500), seed=7,
+                     phi_range=(0.03, 0.32), looper_frac=0.05, trunc_frac=0.3, noise_frac=0.1)
+    n = np.diff(fr.row_offsets)
+    assert (n > 1024).sum() > 0 and ((n > 512) & (n <= 1024)).sum() > 0 and (n <= 512).sum() > 0
+    seg0 = np.arange(0, len(n), 16)
+    blocks = fr.row_offsets[np.minimum(seg0 + 16, len(n))] - fr.row_offsets[seg0]
+    assert (blocks > 8192).any()
+    check_all(fr, "dense rows (48 rows, 2 frames)")
