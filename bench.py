@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--legs", default="main,batched,adjoint")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--stages-workload", type=int, default=1,
+                    help="workload of the stages leg (1: full-TPC event, 3: 64 uneven frames)")
     return ap.parse_args()
 
 
@@ -286,23 +288,34 @@ def leg_copy(args):
 
 
 def leg_stages(args):
-    """Only the staged stage calls on the headline workload (for profilers)."""
+    """Only the staged stage calls on one workload (for profilers)."""
     import torch
     from tpcsynth import make_config
-    fr = make_config(1)
+    fr = make_config(args.stages_workload)
     reco = make_reco(fr)
     dfr = reco.upload(fr)
     ws = reco.workspace(dfr)
     up, dn, sd, tr = reco.reconstruct(dfr, "staged")
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
         reco.neighbours(dfr, up, dn, ws)
+        e[1].record(stream)
         reco.seed(dfr, up, dn, sd, ws)
+        e[2].record(stream)
         reco.fit(dfr, sd, None, tr, ws)
+        e[3].record(stream)
+        evs.append(e)
     torch.cuda.synchronize()
+    st = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs]).mean(axis=0)
     return {"workload": fr.meta["name"], "clusters": dfr.n_clusters, "steps": args.steps,
-            "ms_per_step": round((time.perf_counter() - t0) / max(args.steps, 1) * 1e3, 5)}
+            "ms_per_step": round((time.perf_counter() - t0) / max(args.steps, 1) * 1e3, 5),
+            "stage_ms": {"tpc_neighbours": round(float(st[0]), 5), "tpc_ca_seed": round(float(st[1]), 5),
+                         "tpc_kalman_fit": round(float(st[2]), 5)}}
 
 
 def main():

@@ -59,8 +59,8 @@ __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
 // the lowest member of h's chain inside h's block and how many links down
 // it is.
 
-// Step 1: reset the claim slot and chain length, and record the kept link
-// down of every cluster of the segment.
+// Step 1: reset the claim slot, chain length and chain membership, and
+// record the kept link down of every cluster of the segment.
 __device__ inline void ca_links_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
                                     const CaWs &ws) {
@@ -68,6 +68,7 @@ __device__ inline void ca_links_seg(int seg, int32_t N, const int32_t *__restric
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
         ws.claim[h] = ~0ull;
         ws.core[h] = 0;
+        ws.memb[h] = -1;                              // set by ca_tops for chain members
         ws.dlk[h] = link_dn(up, dn, N, h);
     }
 }
@@ -292,8 +293,7 @@ __device__ inline void ca_members_seg(int seg, int32_t N, const int32_t *__restr
                                       int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        if (!linked(up, dn, N, h)) continue;
-        const int32_t bb = ws.memb[h];
+        const int32_t bb = ws.memb[h];                // -1 unless h is in a chain
         if (!valid_id(bb, N)) continue;
         const int32_t o = ws.choff[bb], k = ws.mpos[h];
         if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) {

@@ -60,7 +60,11 @@ struct CaWs {
     int32_t *choff;              // [N] at a bottom: hit offset of the chain core, -1 if no seed
     int32_t *segcnt, *seghits;   // [NR] seeds / seed hits starting in the segment
     int32_t *segbs, *segbh;      // [NR] exclusive prefixes of the above
+    int32_t *chunk_c, *chunk_h;  // [ceil(NR / TPC_SCAN_CHUNK)] chunk sums, then their prefixes
 };
+
+#define TPC_SCAN_CHUNK 1024      // segments per chunk of the two-level segment scan
+#define TPC_SCAN_DIRECT 16384    // up to this many segments one workgroup scans them directly
 
 size_t nb_ws_layout(void *ws, int64_t N, int64_t NR, NbWs *out);
 size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out);

@@ -19,7 +19,6 @@
 #include "tpc_fit_common.hpp"
 #include "tpc_nb_device.hpp"
 
-#define TPC_SCAN_CHUNK 1024        // segments per chunk of the two-level segment scan
 #define TPC_SPIN_LIMIT (1 << 22)   // polls before a barrier wait is abandoned
 
 struct PersistArgs {
