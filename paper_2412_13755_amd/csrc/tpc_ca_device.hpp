@@ -11,10 +11,9 @@
 // length, then bottom id; seeds are placed by prefix sums in cluster-id
 // order), so it matches the sequential definition exactly.
 //
-//   ca_links   reset claim slots and chain lengths; record every cluster's
-//              kept link down (dlk)
-//   ca_block   per (frame, sector, block of TPC_CA_ROWS rows): pointer
-//              jumping in LDS gives every cluster its lowest chain member
+//   ca_block   per (frame, sector, block of TPC_CA_ROWS rows): kept links
+//              of every cluster (resetting its claim, length and membership
+//              slots), then pointer jumping in LDS to the lowest chain member
 //              inside the block and the distance to it (pack)
 //   ca_tops    every chain member follows the block-local lowest members
 //              down across block edges to the chain bottom (at most one hop
@@ -55,98 +54,136 @@ __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
 
 // Chain ranking.  dlk[h] is the kept link down of h (or -1); a chain is a
 // path of such links, one row per link.  Rows are grouped in blocks of
-// TPC_CA_ROWS per (frame, sector); pack[h] = (distance << 32) | node holds
-// the lowest member of h's chain inside h's block and how many links down
-// it is.
-
-// Step 1: reset the claim slot, chain length and chain membership, and
-// record the kept link down of every cluster of the segment.
-__device__ inline void ca_links_seg(int seg, int32_t N, const int32_t *__restrict__ off,
-                                    const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
-                                    const CaWs &ws) {
-    const int a = off[seg], b = off[seg + 1];
-    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        ws.claim[h] = ~0ull;
-        ws.core[h] = 0;
-        ws.memb[h] = -1;                              // set by ca_tops for chain members
-        ws.dlk[h] = link_dn(up, dn, N, h);
-    }
-}
+// TPC_CA_ROWS per (frame, sector); pack[h] holds the lowest member of h's
+// chain inside h's block (bits 0-31, global id), how many links down it is
+// (bits 32-59) and whether h keeps a link up (bit 62) / down (bit 63).
 
 #define TPC_CA_ROWS 16          // rows per ranking block
 #define TPC_CA_CAP 8192         // clusters per block ranked in LDS
 #define TPC_CA_ROUNDS 5         // > log2(TPC_CA_ROWS): links inside a block
-#define TPC_CA_NODE 0xFFFFF     // LDS word: (distance << 20) | local node
+#define TPC_CA_UP (1ull << 62)
+#define TPC_CA_DN (1ull << 63)
+// LDS word: local node (bits 0-19), distance (20-29), up (30), down (31)
+#define TPC_CA_NODE 0xFFFFFu
+#define TPC_CA_FLAGS 0xC0000000u
 
 __host__ __device__ inline int ca_blocks_per_sector(int n_rows) {
     return (n_rows + TPC_CA_ROWS - 1) / TPC_CA_ROWS;
 }
+__device__ inline int32_t pack_node(unsigned long long w) { return (int32_t)(uint32_t)w; }
+__device__ inline int32_t pack_dist(unsigned long long w) { return (int32_t)((w >> 32) & 0xFFFFFFFull); }
+__device__ inline bool pack_linked(unsigned long long w) { return (w & (TPC_CA_UP | TPC_CA_DN)) != 0; }
 
-// Step 2, block `item` of (frame, sector, row block): in-place pointer
-// jumping (a word always holds a valid (node, distance) pair, so reading a
-// neighbour's word before or after its update in the same round is
-// equally correct, and every round at least doubles the span of a pointer
-// that has not reached its target).  Blocks of at most TPC_CA_CAP clusters
-// jump in LDS (W: TPC_CA_CAP ints); larger ones in pack itself.  Contains
-// barriers: call from the whole workgroup.
-__device__ inline void ca_block_item(int item, int32_t n_rows, const int32_t *__restrict__ off,
-                                     const CaWs &ws, int32_t *W) {
+// Step 1, block `item` of (frame, sector, row block): the kept links of
+// every cluster (its slots for claims, chain length and membership are
+// reset on the way), then in-place pointer jumping to the lowest chain
+// member inside the block (a word always holds a valid (node, distance)
+// pair, so reading a neighbour's word before or after its update in the
+// same round is equally correct, and every round at least doubles the span
+// of a pointer that has not reached its target).  Blocks of at most
+// TPC_CA_CAP clusters jump in LDS (W: TPC_CA_CAP words); larger ones in pack
+// itself.  Any workgroup size that is a multiple of 64.  Contains barriers:
+// call from the whole workgroup.
+__device__ inline void ca_block_item(int item, int32_t N, int32_t n_rows, const int32_t *__restrict__ off,
+                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                     const CaWs &ws, uint32_t *W) {
+    constexpr int U = 4;                              // clusters per thread with loads in flight
     const int nbs = ca_blocks_per_sector(n_rows);
     const int fs = item / nbs, bb = item % nbs;
     const int r0 = bb * TPC_CA_ROWS;
     const int r1 = r0 + TPC_CA_ROWS < n_rows ? r0 + TPC_CA_ROWS : n_rows;
     const int lo = off[fs * n_rows + r0], hi = off[fs * n_rows + r1];
-    const int n = hi - lo, tid = threadIdx.x;
-    if (n <= TPC_CA_CAP) {
-        for (int k = tid; k < n; k += TPC_BLOCK) {
-            const int32_t d = ws.dlk[lo + k];
-            W[k] = (d >= lo && d < hi && d != lo + k) ? ((1 << 20) | (d - lo)) : k;
+    const int n = hi - lo, tid = threadIdx.x, T = blockDim.x;
+    const bool lds = n <= TPC_CA_CAP;
+    for (int k0 = tid; k0 < n; k0 += U * T) {
+        int32_t d[U], u[U], bd[U], bu[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = k0 + j * T;
+            d[j] = k < n ? dn[lo + k] : -1;
+            u[j] = k < n ? up[lo + k] : -1;
         }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            bd[j] = valid_id(d[j], N) ? up[d[j]] : -1;
+            bu[j] = valid_id(u[j], N) ? dn[u[j]] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = k0 + j * T;
+            if (k >= n) break;
+            const int32_t h = lo + k;
+            const bool hd = bd[j] == h, hu = bu[j] == h;
+            ws.claim[h] = ~0ull;
+            ws.core[h] = 0;
+            ws.memb[h] = -1;                          // set by ca_tops for chain members
+            ws.dlk[h] = hd ? d[j] : -1;
+            const bool in = hd && d[j] >= lo && d[j] < hi && d[j] != h;
+            if (lds) {
+                W[k] = (hu ? 0x40000000u : 0u) | (hd ? 0x80000000u : 0u) |
+                       (in ? ((1u << 20) | (uint32_t)(d[j] - lo)) : (uint32_t)k);
+            } else {
+                const unsigned long long w = (hu ? TPC_CA_UP : 0ull) | (hd ? TPC_CA_DN : 0ull) |
+                                             (in ? ((1ull << 32) | (uint32_t)d[j]) : (uint32_t)h);
+                __hip_atomic_store(&ws.pack[h], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    if (lds) {
         for (int round = 0; round < TPC_CA_ROUNDS; ++round) {
-            for (int k = tid; k < n; k += TPC_BLOCK) {
-                const int32_t v = W[k], p = v & TPC_CA_NODE;
-                if (p == k) continue;
-                const int32_t v2 = W[p], q = v2 & TPC_CA_NODE;
-                if (q != p) W[k] = (((v >> 20) + (v2 >> 20)) << 20) | q;
+            for (int k0 = tid; k0 < n; k0 += U * T) {
+                uint32_t v[U], v2[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) v[j] = k0 + j * T < n ? W[k0 + j * T] : (uint32_t)(k0 + j * T);
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const uint32_t p = v[j] & TPC_CA_NODE;
+                    v2[j] = (k0 + j * T < n && p != (uint32_t)(k0 + j * T)) ? W[p] : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const int k = k0 + j * T;
+                    const uint32_t p = v[j] & TPC_CA_NODE, q = v2[j] & TPC_CA_NODE;
+                    if (k < n && p != (uint32_t)k && q != p) {
+                        const uint32_t dist = ((v[j] >> 20) & 0x3FFu) + ((v2[j] >> 20) & 0x3FFu);
+                        W[k] = (v[j] & TPC_CA_FLAGS) | ((dist & 0x3FFu) << 20) | q;
+                    }
+                }
             }
             __syncthreads();
         }
-        for (int k = tid; k < n; k += TPC_BLOCK) {
-            const int32_t v = W[k];
-            ws.pack[lo + k] = ((unsigned long long)(uint32_t)(v >> 20) << 32) |
-                              (uint32_t)(lo + (v & TPC_CA_NODE));
+        for (int k = tid; k < n; k += T) {
+            const uint32_t v = W[k];
+            ws.pack[lo + k] = ((unsigned long long)(v >> 30) << 62) |
+                              ((unsigned long long)((v >> 20) & 0x3FFu) << 32) |
+                              (uint32_t)(lo + (int32_t)(v & TPC_CA_NODE));
         }
         __syncthreads();             // LDS reuse across calls in a persistent loop
         return;
     }
     // large block: the same rounds on the global words (written by this
     // workgroup only, so workgroup-scope accesses suffice)
-    for (int k = lo + tid; k < hi; k += TPC_BLOCK) {
-        const int32_t d = ws.dlk[k];
-        const unsigned long long w = (d >= lo && d < hi && d != k) ? ((1ull << 32) | (uint32_t)d)
-                                                                  : (unsigned long long)(uint32_t)k;
-        __hip_atomic_store(&ws.pack[k], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    __syncthreads();
     for (int round = 0; round < TPC_CA_ROUNDS; ++round) {
-        for (int k = lo + tid; k < hi; k += TPC_BLOCK) {
+        for (int k = lo + tid; k < hi; k += T) {
             const unsigned long long v =
                 __hip_atomic_load(&ws.pack[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            const int32_t p = (int32_t)(uint32_t)v;
+            const int32_t p = pack_node(v);
             if (p == k) continue;
             const unsigned long long v2 =
                 __hip_atomic_load(&ws.pack[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            const int32_t q = (int32_t)(uint32_t)v2;
-            if (q != p)
-                __hip_atomic_store(&ws.pack[k], (((v >> 32) + (v2 >> 32)) << 32) | (uint32_t)q,
+            const int32_t q = pack_node(v2);
+            if (q != p) {
+                const unsigned long long dist = (unsigned long long)(pack_dist(v) + pack_dist(v2));
+                __hip_atomic_store(&ws.pack[k], (v & (TPC_CA_UP | TPC_CA_DN)) | (dist << 32) | (uint32_t)q,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
         __syncthreads();
     }
 }
 
-// Step 3: every linked cluster follows the block-local lowest members down
+// Step 2: every linked cluster follows the block-local lowest members down
 // across block edges (a lowest member whose kept link leaves the block
 // continues below it) to the chain bottom; then the top of each chain
 // records the chain length and top at the bottom and claims the chain's
@@ -156,21 +193,20 @@ __device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict
                                    int32_t min_hits, int32_t n_rows, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        const int32_t u = link_up(up, dn, N, h);
-        if (u < 0 && ws.dlk[h] < 0) continue;         // not linked
-        unsigned long long w = ws.pack[h];
-        int32_t bot = (int32_t)(uint32_t)w;
-        int32_t pos = (int32_t)(w >> 32);
+        const unsigned long long w0 = ws.pack[h];
+        if (!pack_linked(w0)) continue;
+        int32_t bot = pack_node(w0);
+        int32_t pos = pack_dist(w0);
         for (int it = 0; it < n_rows; ++it) {         // bound: one hop per block
             const int32_t e = valid_id(bot, N) ? ws.dlk[bot] : -1;
             if (e < 0) break;
-            w = ws.pack[e];
-            pos += 1 + (int32_t)(w >> 32);
-            bot = (int32_t)(uint32_t)w;
+            const unsigned long long w = ws.pack[e];
+            pos += 1 + pack_dist(w);
+            bot = pack_node(w);
         }
         ws.memb[h] = bot;
         ws.mpos[h] = pos;
-        if (u < 0 && valid_id(bot, N)) {              // h is the top: chain of pos + 1 clusters
+        if (!(w0 & TPC_CA_UP) && valid_id(bot, N)) {  // h is the top: chain of pos + 1 clusters
             const int32_t m = pos + 1;
             ws.core[bot] = m;
             ws.ctop[bot] = h;
@@ -178,8 +214,8 @@ __device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict
             if (m >= min_hits - 2) {
                 const unsigned long long key = claim_key(m, bot);
                 const int32_t eb = dn[bot], et = up[h];
-                if (valid_id(eb, N) && !linked(up, dn, N, eb)) atomicMin(&ws.claim[eb], key);
-                if (valid_id(et, N) && !linked(up, dn, N, et)) atomicMin(&ws.claim[et], key);
+                if (valid_id(eb, N) && !pack_linked(ws.pack[eb])) atomicMin(&ws.claim[eb], key);
+                if (valid_id(et, N) && !pack_linked(ws.pack[et])) atomicMin(&ws.claim[et], key);
             }
         }
     }

@@ -7,16 +7,10 @@ namespace {
 
 using namespace tpc_ca;
 
-__global__ void __launch_bounds__(TPC_BLOCK)
-ca_links(int32_t N, const int32_t *off, const int32_t *up, const int32_t *dn, CaWs ws) {
-    const int seg = xcd_item(blockIdx.x, gridDim.x);
-    ca_links_seg(seg, N, off, up, dn, ws);
-}
-
-__global__ void __launch_bounds__(TPC_BLOCK)
-ca_block(int32_t n_rows, const int32_t *off, CaWs ws) {
-    __shared__ int32_t W[TPC_CA_CAP];
-    ca_block_item(xcd_item(blockIdx.x, gridDim.x), n_rows, off, ws, W);
+__global__ void __launch_bounds__(1024)
+ca_block(int32_t N, int32_t n_rows, const int32_t *off, const int32_t *up, const int32_t *dn, CaWs ws) {
+    __shared__ uint32_t W[TPC_CA_CAP];
+    ca_block_item(xcd_item(blockIdx.x, gridDim.x), N, n_rows, off, up, dn, ws, W);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -149,9 +143,8 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
     const int NR = fr->n_frames * c.n_sectors * c.n_rows;
     const int32_t *off = fr->row_offsets;
     const int32_t N = fr->n_clusters;
-    hipLaunchKernelGGL(ca_links, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, ws);
     const int NB = fr->n_frames * c.n_sectors * ca_blocks_per_sector(c.n_rows);
-    hipLaunchKernelGGL(ca_block, dim3(NB), dim3(TPC_BLOCK), 0, st, c.n_rows, off, ws);
+    hipLaunchKernelGGL(ca_block, dim3(NB), dim3(1024), 0, st, N, c.n_rows, off, up, dn, ws);
     hipLaunchKernelGGL(ca_tops, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, c.n_rows, ws);
     hipLaunchKernelGGL(ca_firsts, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, ws);
     if (NR <= TPC_SCAN_DIRECT) {

@@ -9,7 +9,7 @@
 // a sleep and gives up after a bounded number of polls, setting an error flag
 // that makes every workgroup leave, so the kernel always terminates.
 //
-// Phases:  bin | query | links | block ranking | tops + claims | firsts |
+// Phases:  bin | query | links + block ranking | tops + claims | firsts |
 //          chunk sums | chunk scan (one workgroup) | segment scan |
 //          place + length histogram | members + length scan (one workgroup) |
 //          gather hit coordinates + order by length | fit
@@ -103,7 +103,7 @@ persist_reco(PersistArgs P) {
     __shared__ float xs[TPC_MAX_ROWS];
     __shared__ union {
         tpc_nb::PairLds nb;
-        int32_t caw[TPC_CA_CAP];
+        uint32_t caw[TPC_CA_CAP];
     } U;
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     __shared__ int bc[2];
@@ -119,11 +119,8 @@ persist_reco(PersistArgs P) {
                              P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.nb,
                              tpc_nb::NB_ALL);
     if (!grid_sync(P)) return;
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_links_seg(seg, P.N, P.off, P.up, P.dn, P.ca);
-    if (!grid_sync(P)) return;
     for (int item = bid; item < P.NB; item += G)
-        tpc_ca::ca_block_item(item, P.n_rows, P.off, P.ca, U.caw);
+        tpc_ca::ca_block_item(item, P.N, P.n_rows, P.off, P.up, P.dn, P.ca, U.caw);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_ca::ca_tops_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
