@@ -90,7 +90,11 @@ adj_partial(const int32_t *__restrict__ n_seeds, int32_t cap_seeds,
         }
         __syncthreads();
         const int cnt = hi - c0 < TPC_BLOCK ? hi - c0 : TPC_BLOCK;
+        // a frame-sector's seeds come in non-decreasing first row (seed
+        // order is first-cluster id order), so none after the first seed
+        // starting above row r reaches r
         for (int q = 0; q < cnt; ++q) {
+            if (sr[q] > r) break;
             const int k = r - sr[q];
             // seeds that fail the fit's sanity checks were never written
             const bool sane = sn[q] >= 3 && sr[q] >= 0 && sr[q] + sn[q] <= n_rows && so[q] >= 0;
@@ -126,7 +130,13 @@ adj_final(const float2 *__restrict__ partial, int32_t n_frames, int32_t n_sector
 }  // namespace
 
 #define TPC_ADJ_MAX_BLOCKS 512     // persistent grid: 131072 threads, 8 waves per CU
-#define TPC_ADJ_GROUPS 8           // workgroups per (frame, sector) in the row sums
+// Workgroups per (frame, sector) in the row sums: enough for about 4096
+// workgroups in all, at most 64 (each sums a fixed share of the seeds, so
+// the result stays bit-reproducible).
+static int adj_groups(int64_t n_fs) {
+    int64_t g = n_fs > 0 ? 4096 / n_fs : 1;
+    return (int)(g < 1 ? 1 : (g > 64 ? 64 : g));
+}
 
 static int adj_blocks(int32_t cap_seeds) {
     int b = (cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
@@ -140,7 +150,7 @@ size_t adj_ws_layout(void *ws, int64_t cap_hits, int64_t cap_seeds, int64_t n_fs
     float2 *pg = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
     const int64_t nthreads = (int64_t)adj_blocks((int32_t)(cap_seeds < 0x7fffffff ? cap_seeds : 0x7fffffff)) * TPC_BLOCK;
     double *pt = w.take<double>(nthreads * K * TPC_CKPT_WORDS);
-    float2 *pp = w.take<float2>(n_fs * TPC_ADJ_GROUPS * n_rows);
+    float2 *pp = w.take<float2>(n_fs * adj_groups(n_fs) * n_rows);
     float2 *ph = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
     if (hyz) *hyz = ph;
     if (g) *g = pg;
@@ -170,11 +180,12 @@ hipError_t launch_adjoint(const tpc_context *ctx, const tpc_frames *fr, const tp
     const int blocks = adj_blocks(sd->cap_seeds);
     A.nthreads = blocks * TPC_BLOCK;
     hipLaunchKernelGGL(adj_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(adj_partial, dim3((unsigned)n_fs, TPC_ADJ_GROUPS), dim3(TPC_BLOCK), 0, st,
+    const int groups = adj_groups(n_fs);
+    hipLaunchKernelGGL(adj_partial, dim3((unsigned)n_fs, groups), dim3(TPC_BLOCK), 0, st,
                        sd->n_seeds, sd->cap_seeds, sd->offsets, sd->first_row, sd->frame,
                        sd->sector, c.n_sectors, c.n_rows, A.g, partial);
     const int nout = c.n_sectors * c.n_rows;
     hipLaunchKernelGGL(adj_final, dim3((nout + TPC_BLOCK - 1) / TPC_BLOCK), dim3(TPC_BLOCK), 0, st,
-                       partial, fr->n_frames, c.n_sectors, c.n_rows, TPC_ADJ_GROUPS, dloss, grad_map);
+                       partial, fr->n_frames, c.n_sectors, c.n_rows, groups, dloss, grad_map);
     return hipGetLastError();
 }

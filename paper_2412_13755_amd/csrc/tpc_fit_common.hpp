@@ -120,11 +120,12 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
         // has just been consumed from (no copy at the loop edge, so the load
         // is waited for only at its use a whole step later).
         float2 raw = hit_raw(A, sv, sv.n - 2, A.hyz ? 0 : sv.hh[sv.n - 2]);
+        float xk = xs[sv.row0 + sv.n - 2];            // plane of hit k
         for (int k = sv.n - 2, j = 1; k >= 0; --k, ++j) {
             double my, mz;
             hit_fix(A, sv, k, raw, my, mz);
+            const float xnext = k > 0 ? xs[sv.row0 + k - 1] : 0.0f;
             if (k > 0) raw = hit_raw(A, sv, k - 1, A.hyz ? 0 : sv.hh[k - 1]);
-            const float xk = xs[sv.row0 + k];
             // one exit test per step: the step and the update are evaluated
             // unconditionally and a failed track's final state is not used
             StepJac J;
@@ -138,6 +139,7 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
                 break;
             }
             xcur = xk;
+            xk = xnext;
             // state after j updates opens segment j / K of the adjoint
             if (ck && j % A.ckpt_rows == 0 && k > 0)
                 write_ckpt(ck + (size_t)(j / A.ckpt_rows) * TPC_CKPT_WORDS, p, C);
