@@ -121,6 +121,9 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
         // is waited for only at its use a whole step later).
         float2 raw = hit_raw(A, sv, sv.n - 2, A.hyz ? 0 : sv.hh[sv.n - 2]);
         float xk = xs[sv.row0 + sv.n - 2];            // plane of hit k
+        // the covariance half of each update is applied at the next step,
+        // beside its helix step (G is zero before the first update)
+        Gain<double> G = {};
         for (int k = sv.n - 2, j = 1; k >= 0; --k, ++j) {
             double my, mz;
             hit_fix(A, sv, k, raw, my, mz);
@@ -128,10 +131,11 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
             if (k > 0) raw = hit_raw(A, sv, k - 1, A.hyz ? 0 : sv.hh[k - 1]);
             // one exit test per step: the step and the update are evaluated
             // unconditionally and a failed track's final state is not used
+            kalman_cov(C, G);
             StepJac J;
             const bool stepped = helix_step(p, xk - xcur, A.kbz, A.max_sin, J);
             sym_transport<double, false>(C, J);
-            const double dchi = kalman_update<double>(p, C, my, mz, A.vy, A.vz);
+            const double dchi = kalman_gain<double>(p, C, my, mz, A.vy, A.vz, G);
             chi2 += dchi;
             const double chk = chi2 + p[0] + p[1] + p[2] + p[3] + p[4];
             if (!stepped || !(dchi >= 0.0) || !(chk - chk == 0.0)) {   // non-finite state too
@@ -141,9 +145,13 @@ __host__ __device__ inline void fit_one(const FitArgs &A, int i, const float *xs
             xcur = xk;
             xk = xnext;
             // state after j updates opens segment j / K of the adjoint
-            if (ck && j % A.ckpt_rows == 0 && k > 0)
-                write_ckpt(ck + (size_t)(j / A.ckpt_rows) * TPC_CKPT_WORDS, p, C);
+            if (ck && j % A.ckpt_rows == 0 && k > 0) {
+                SymT<double> Cj = C;
+                kalman_cov(Cj, G);
+                write_ckpt(ck + (size_t)(j / A.ckpt_rows) * TPC_CKPT_WORDS, p, Cj);
+            }
         }
+        kalman_cov(C, G);                             // the last update's covariance half
     }
     A.out.x[i] = xcur;
     float *po = A.out.par + (size_t)i * 5;

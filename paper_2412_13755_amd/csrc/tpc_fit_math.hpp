@@ -253,11 +253,21 @@ __host__ __device__ inline void sym_transport(SymT<R> &C, const StepJac &J) {
     }
 }
 
-// Kalman update with measurement (my, mz); returns the chi2 increment, or a
-// negative value if the residual covariance is not positive definite (the
-// update is evaluated regardless, and p, C are then meaningless).
+// Kalman update with measurement (my, mz), in two halves: kalman_gain forms
+// the gain K = C H^T S^-1 from the predicted covariance, updates the state
+// and returns the chi2 increment (negative if the residual covariance is not
+// positive definite; everything is evaluated regardless, and p, C are then
+// meaningless); kalman_cov applies C -= K H C.  The filter loop runs the
+// covariance half of one step next to the helix step of the next, which
+// does not need it.  K and the rows H C are kept in a Gain.
 template <class R>
-__host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy, R vz) {
+struct Gain {
+    R k00, k01, k10, k11, k20, k21, k30, k31, k40, k41;   // K
+    R r00, r01, r02, r03, r04, r11, r12, r13, r14;         // rows 0 and 1 of C
+};
+
+template <class R>
+__host__ __device__ inline R kalman_gain(R p[5], const SymT<R> &C, R my, R mz, R vy, R vz, Gain<R> &G) {
     const R r0 = my - p[0], r1 = mz - p[1];
     const R S00 = C.c00 + vy, S01 = C.c10, S11 = C.c11 + vz;
     const R det = S00 * S11 - S01 * S01;
@@ -265,37 +275,49 @@ __host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy,
     const R idet = recip_pos(det);
     const R i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
     // K = C[:, 0:2] S^-1
-    const R k00 = C.c00 * i00 + C.c10 * i01, k01 = C.c00 * i01 + C.c10 * i11;
-    const R k10 = C.c10 * i00 + C.c11 * i01, k11 = C.c10 * i01 + C.c11 * i11;
-    const R k20 = C.c20 * i00 + C.c21 * i01, k21 = C.c20 * i01 + C.c21 * i11;
-    const R k30 = C.c30 * i00 + C.c31 * i01, k31 = C.c30 * i01 + C.c31 * i11;
-    const R k40 = C.c40 * i00 + C.c41 * i01, k41 = C.c40 * i01 + C.c41 * i11;
+    G.k00 = C.c00 * i00 + C.c10 * i01; G.k01 = C.c00 * i01 + C.c10 * i11;
+    G.k10 = C.c10 * i00 + C.c11 * i01; G.k11 = C.c10 * i01 + C.c11 * i11;
+    G.k20 = C.c20 * i00 + C.c21 * i01; G.k21 = C.c20 * i01 + C.c21 * i11;
+    G.k30 = C.c30 * i00 + C.c31 * i01; G.k31 = C.c30 * i01 + C.c31 * i11;
+    G.k40 = C.c40 * i00 + C.c41 * i01; G.k41 = C.c40 * i01 + C.c41 * i11;
     // written as chains of multiply-adds (one rounding per term)
-    p[0] = p[0] + k00 * r0 + k01 * r1;
-    p[1] = p[1] + k10 * r0 + k11 * r1;
-    p[2] = p[2] + k20 * r0 + k21 * r1;
-    p[3] = p[3] + k30 * r0 + k31 * r1;
-    p[4] = p[4] + k40 * r0 + k41 * r1;
-    // C -= K H C, H C = rows 0 and 1 of C
-    const R r00 = C.c00, r01 = C.c10, r02 = C.c20, r03 = C.c30, r04 = C.c40;
-    const R r11 = C.c11, r12 = C.c21, r13 = C.c31, r14 = C.c41;
-    C.c00 = C.c00 - k00 * r00 - k01 * r01;
-    C.c10 = C.c10 - k10 * r00 - k11 * r01;
-    C.c11 = C.c11 - k10 * r01 - k11 * r11;
-    C.c20 = C.c20 - k20 * r00 - k21 * r01;
-    C.c21 = C.c21 - k20 * r01 - k21 * r11;
-    C.c22 = C.c22 - k20 * r02 - k21 * r12;
-    C.c30 = C.c30 - k30 * r00 - k31 * r01;
-    C.c31 = C.c31 - k30 * r01 - k31 * r11;
-    C.c32 = C.c32 - k30 * r02 - k31 * r12;
-    C.c33 = C.c33 - k30 * r03 - k31 * r13;
-    C.c40 = C.c40 - k40 * r00 - k41 * r01;
-    C.c41 = C.c41 - k40 * r01 - k41 * r11;
-    C.c42 = C.c42 - k40 * r02 - k41 * r12;
-    C.c43 = C.c43 - k40 * r03 - k41 * r13;
-    C.c44 = C.c44 - k40 * r04 - k41 * r14;
+    p[0] = p[0] + G.k00 * r0 + G.k01 * r1;
+    p[1] = p[1] + G.k10 * r0 + G.k11 * r1;
+    p[2] = p[2] + G.k20 * r0 + G.k21 * r1;
+    p[3] = p[3] + G.k30 * r0 + G.k31 * r1;
+    p[4] = p[4] + G.k40 * r0 + G.k41 * r1;
+    G.r00 = C.c00; G.r01 = C.c10; G.r02 = C.c20; G.r03 = C.c30; G.r04 = C.c40;
+    G.r11 = C.c11; G.r12 = C.c21; G.r13 = C.c31; G.r14 = C.c41;
     const R chi = r0 * (i00 * r0 + i01 * r1) + r1 * (i01 * r0 + i11 * r1);
     return pd ? chi : (R)-1;
+}
+
+// C -= K H C (a zero Gain leaves C exactly unchanged)
+template <class R>
+__host__ __device__ inline void kalman_cov(SymT<R> &C, const Gain<R> &G) {
+    C.c00 = C.c00 - G.k00 * G.r00 - G.k01 * G.r01;
+    C.c10 = C.c10 - G.k10 * G.r00 - G.k11 * G.r01;
+    C.c11 = C.c11 - G.k10 * G.r01 - G.k11 * G.r11;
+    C.c20 = C.c20 - G.k20 * G.r00 - G.k21 * G.r01;
+    C.c21 = C.c21 - G.k20 * G.r01 - G.k21 * G.r11;
+    C.c22 = C.c22 - G.k20 * G.r02 - G.k21 * G.r12;
+    C.c30 = C.c30 - G.k30 * G.r00 - G.k31 * G.r01;
+    C.c31 = C.c31 - G.k30 * G.r01 - G.k31 * G.r11;
+    C.c32 = C.c32 - G.k30 * G.r02 - G.k31 * G.r12;
+    C.c33 = C.c33 - G.k30 * G.r03 - G.k31 * G.r13;
+    C.c40 = C.c40 - G.k40 * G.r00 - G.k41 * G.r01;
+    C.c41 = C.c41 - G.k40 * G.r01 - G.k41 * G.r11;
+    C.c42 = C.c42 - G.k40 * G.r02 - G.k41 * G.r12;
+    C.c43 = C.c43 - G.k40 * G.r03 - G.k41 * G.r13;
+    C.c44 = C.c44 - G.k40 * G.r04 - G.k41 * G.r14;
+}
+
+template <class R>
+__host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy, R vz) {
+    Gain<R> G;
+    const R chi = kalman_gain(p, C, my, mz, vy, vz, G);
+    kalman_cov(C, G);
+    return chi;
 }
 
 // Exact circle through C (innermost), B, A (outermost): state at A, computed
