@@ -30,19 +30,8 @@
 namespace tpc_ca {
 
 
-// Link helpers.  Ids outside [0, N) read as "no link", so corrupt input can
-// never address memory outside the arrays.
-__device__ inline int32_t link_up(const int32_t *up, const int32_t *dn, int32_t N, int32_t h) {
-    int32_t u = up[h];
-    return ((uint32_t)u < (uint32_t)N && dn[u] == h) ? u : -1;
-}
-__device__ inline int32_t link_dn(const int32_t *up, const int32_t *dn, int32_t N, int32_t h) {
-    int32_t d = dn[h];
-    return ((uint32_t)d < (uint32_t)N && up[d] == h) ? d : -1;
-}
-__device__ inline bool linked(const int32_t *up, const int32_t *dn, int32_t N, int32_t h) {
-    return link_up(up, dn, N, h) >= 0 || link_dn(up, dn, N, h) >= 0;
-}
+// Ids outside [0, N) read as "no link", so corrupt input can never address
+// memory outside the arrays.
 __device__ inline bool valid_id(int32_t v, int32_t N) { return (uint32_t)v < (uint32_t)N; }
 // (y, z) of seed hit j into the optional coordinate copy (one 8-byte store)
 __device__ inline void put_yz(float *hit_yz, int32_t j, float yv, float zv) {
