@@ -30,7 +30,10 @@ struct AdjArgs {
     int32_t nthreads;
 };
 
-__global__ void __launch_bounds__(TPC_BLOCK)
+// Two wavefronts per SIMD (256 registers per lane, a few spilled): the
+// step adjoint's live set is near 300 registers, and one wavefront per SIMD
+// leaves its latency exposed.
+__global__ void __launch_bounds__(TPC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 adj_tracks(AdjArgs A) {
     __shared__ float xs[TPC_MAX_ROWS];
     const FitArgs &F = A.F;
