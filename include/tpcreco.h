@@ -206,13 +206,15 @@ tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *frames,
  * both modes.
  *   TPC_MODE_STAGED      the three stage calls one after another (several
  *                        kernel launches per stage)
- *   TPC_MODE_PERSISTENT  one persistent kernel (plus a small initialisation
- *                        and status kernel) on a grid of workgroups that are
- *                        resident at once, moving through the stages with
- *                        grid-wide barriers; the fit visits seeds longest
- *                        first.  If the grid cannot synchronise (a barrier
- *                        wait exceeds its bounded polling), every workgroup
- *                        leaves and *dev_status is set to TPC_ERR_HIP.
+ *   TPC_MODE_PERSISTENT  neighbours and seeding in one persistent kernel on
+ *                        a grid of workgroups that are resident at once,
+ *                        moving through the phases with grid-wide barriers,
+ *                        then the fit as one launch over the seeds longest
+ *                        first (plus small initialisation and status
+ *                        kernels).  If the grid cannot synchronise (a
+ *                        barrier wait exceeds its bounded polling), every
+ *                        workgroup leaves and *dev_status is set to
+ *                        TPC_ERR_HIP.
  * tune: NULL or { grid: workgroups (0 = resident capacity, larger values are
  * clamped to it), sort_fit: 1 = longest seeds first, 0 = seed order }.
  * Both modes are graph-capturable (no allocation, no host synchronisation).

@@ -16,8 +16,14 @@ fit_tracks(FitArgs A) {
     __syncthreads();
     int T = *A.n_seeds;
     if (T > A.cap_seeds) T = A.cap_seeds;
-    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK)
-        fit_one(A, i, xs);
+    if (A.order) {
+        const int n = *A.n_order;
+        T = n < T ? n : T;
+    }
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+        const int s = A.order ? A.order[i] : i;
+        if ((uint32_t)s < (uint32_t)A.cap_seeds) fit_one(A, s, xs);
+    }
 }
 
 // (y, z) of every seed hit in seed-hit order, so the fit reads each seed's
@@ -97,6 +103,8 @@ FitArgs make_fit_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
     A.ckpt_rows = c.ckpt_rows;
     A.hyz = nullptr;
     A.out = tpc_tracks{};
+    A.order = nullptr;
+    A.n_order = nullptr;
     return A;
 }
 
@@ -123,6 +131,14 @@ hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
         launch_gather(fr, sd, hyz, st);
     }
     int blocks = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fit_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_args(const FitArgs &A, hipStream_t st) {
+    int blocks = (A.cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(fit_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);

@@ -17,6 +17,8 @@ struct FitArgs {
     double *ckpt;
     int32_t ckpt_rows;
     tpc_tracks out;
+    const int32_t *order;      // optional: fit seeds order[0 .. *n_order) instead of 0 .. T
+    const int32_t *n_order;
 };
 
 struct SeedView {
@@ -256,3 +258,4 @@ __host__ __device__ inline void adj_one(const FitArgs &F, const int32_t *status,
 
 FitArgs make_fit_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
                       const float *map);
+hipError_t launch_fit_args(const FitArgs &A, hipStream_t st);

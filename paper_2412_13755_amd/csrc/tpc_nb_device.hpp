@@ -143,16 +143,22 @@ __device__ inline bool query_global(const int32_t *off, int seg, int n_rows) {
 }
 
 // Global binning of segment `seg`, done only when a neighbouring h-row's
-// query needs it (whole workgroup; contains barriers).
+// query needs it (whole workgroup; contains barriers; L: LDS scratch).
+struct BinLds {
+    int cnt[TPC_CELL_CAP];
+    float red[4][TPC_BLOCK / TPC_WAVE];
+    int scan_sh[TPC_BLOCK / TPC_WAVE];
+};
+
 __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict__ off,
                                   const float *__restrict__ y, const float *__restrict__ z, float win_y,
                                   float win_z, SegGrid *__restrict__ grid, int32_t *__restrict__ cstart,
                                   float *__restrict__ sy, float *__restrict__ sz,
-                                  int32_t *__restrict__ sid) {
+                                  int32_t *__restrict__ sid, BinLds &L) {
 #pragma clang fp contract(off)
-    __shared__ int cnt[TPC_CELL_CAP];
-    __shared__ float red[4][TPC_BLOCK / TPC_WAVE];
-    __shared__ int scan_sh[TPC_BLOCK / TPC_WAVE];
+    int *cnt = L.cnt;
+    float (*red)[TPC_BLOCK / TPC_WAVE] = L.red;
+    int *scan_sh = L.scan_sh;
     const int r = seg % n_rows;
     const bool need = (r >= 1 && query_global(off, seg - 1, n_rows)) ||
                       (r <= n_rows - 2 && query_global(off, seg + 1, n_rows));

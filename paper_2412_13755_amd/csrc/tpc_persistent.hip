@@ -1,25 +1,31 @@
-// Persistent form of the whole path (gfx950): neighbour search, seeding and
-// fit of all frames in one launch of a grid sized to what the device holds
-// at once (occupancy x compute units).  Every phase runs the same
-// per-segment / per-seed device functions as the stage kernels, looping over
-// its work items grid-stride, so results are identical to the stage path.
-// Phases are separated by a grid-wide barrier: an arrival counter and a
-// generation word in device memory, with agent-scope fences on both sides
-// (the eight XCDs keep separate L2 caches).  A waiting workgroup polls with
-// a sleep and gives up after a bounded number of polls, setting an error flag
-// that makes every workgroup leave, so the kernel always terminates.
+// Persistent form of the path (gfx950): neighbour search and seeding of all
+// frames in one launch of a grid sized to what the device holds at once
+// (occupancy x compute units), then the fit as one following launch.  Every
+// phase runs the same per-segment device functions as the stage kernels,
+// looping over its work items grid-stride, so results are identical to the
+// stage path.  Phases are separated by a grid-wide barrier: an arrival
+// counter and a generation word in device memory, with agent-scope fences
+// on both sides (the eight XCDs keep separate L2 caches).  A waiting
+// workgroup polls with a sleep and gives up after a bounded number of polls,
+// setting an error flag that makes every workgroup leave, so the kernel
+// always terminates.  The phases share one LDS union.
 //
 // Phases:  bin | query | links + block ranking | tops + claims | firsts |
 //          chunk sums | chunk scan (one workgroup) | segment scan |
 //          place + length histogram | members + length scan (one workgroup) |
-//          gather hit coordinates + order by length | fit
-// The fit visits seeds longest first, so the lanes of a wavefront carry
+//          gather hit coordinates + order by length
+// The fit is not a phase: its ~230 registers per lane would cap the
+// occupancy of every phase at two wavefronts per SIMD.  It runs next, over
+// the seeds longest first (with sort_fit), so the lanes of a wavefront carry
 // seeds of similar length (the loop length is the seed length).
 #include "tpc_ca_device.hpp"
 #include "tpc_fit_common.hpp"
 #include "tpc_nb_device.hpp"
 
 #define TPC_SPIN_LIMIT (1 << 22)   // polls before a barrier wait is abandoned
+#define TPC_BAR_GROUPS 8           // arrival groups of the grid barrier
+#define TPC_BAR_STRIDE 16          // words between barrier counters (64 bytes)
+#define TPC_BAR_WORDS (TPC_BAR_STRIDE * (TPC_BAR_GROUPS + 1))
 
 struct PersistArgs {
     // frames
@@ -36,7 +42,8 @@ struct PersistArgs {
     // workspace
     NbWs nb;
     CaWs ca;
-    unsigned *bar;       // [2] arrival count, generation
+    unsigned *bar;       // [TPC_BAR_WORDS] top count, top generation, then per group
+                         // (every TPC_BAR_STRIDE words) count, generation
     int32_t *err;        // [1]
     int32_t *chunk_c, *chunk_h;   // [nchunks]
     int32_t *len_hist;   // [TPC_MAX_ROWS + 1], then bin starts
@@ -50,31 +57,53 @@ struct PersistArgs {
 
 namespace {
 
+// Wait (thread 0 of a workgroup) until *w differs from `seen`; false if the
+// bounded polling runs out (then sets the error flag) or another workgroup
+// has set it.
+__device__ inline bool wait_change(const PersistArgs &P, unsigned *w, unsigned seen) {
+    int spins = 0;
+    while (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == seen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > TPC_SPIN_LIMIT) {
+            atomicExch(P.err, 1);
+            return false;
+        }
+        if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    }
+    return true;
+}
+
+// Grid barrier in two levels, so that no single word takes every arrival or
+// every poll: workgroups arrive at one of up to TPC_BAR_GROUPS group
+// counters (block id mod groups); the last arrival of each group arrives at
+// the top counter, the last of those advances the top generation, and each
+// group's last arrival then advances its group's generation, which the rest
+// of the group polls.  Counters are reset by their last arrival before the
+// release, so a workgroup can never see the next barrier's count early.
 __device__ inline bool grid_sync(const PersistArgs &P) {
     __shared__ int ok;
     __syncthreads();
     if (threadIdx.x == 0) {
         int good = 1;
         __threadfence();
-        const unsigned gen = __hip_atomic_load(&P.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = atomicAdd(&P.bar[0], 1u);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(&P.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&P.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            int spins = 0;
-            while (__hip_atomic_load(&P.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > TPC_SPIN_LIMIT) {
-                    atomicExch(P.err, 1);
-                    good = 0;
-                    break;
-                }
-                if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    good = 0;
-                    break;
-                }
+        const int G = gridDim.x, ng = G < TPC_BAR_GROUPS ? G : TPC_BAR_GROUPS;
+        const int g = blockIdx.x % ng, members = (G - g + ng - 1) / ng;
+        unsigned *gc = P.bar + TPC_BAR_STRIDE * (g + 1), *gg = gc + 1;
+        const unsigned ggen = __hip_atomic_load(gg, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = atomicAdd(gc, 1u);
+        if (arrived == (unsigned)members - 1) {
+            __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned gen = __hip_atomic_load(&P.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned top = atomicAdd(&P.bar[0], 1u);
+            if (top == (unsigned)ng - 1) {
+                __hip_atomic_store(&P.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&P.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (!wait_change(P, &P.bar[1], gen)) {
+                good = 0;
             }
+            __hip_atomic_fetch_add(gg, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (!wait_change(P, gg, ggen)) {
+            good = 0;
         }
         __threadfence();
         if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) good = 0;
@@ -93,26 +122,25 @@ __device__ inline int block_sum(int v, int *sh) {
 __global__ void __launch_bounds__(TPC_BLOCK)
 persist_init(PersistArgs P) {
     const int t = blockIdx.x * TPC_BLOCK + threadIdx.x;
-    if (t < 2) P.bar[t] = 0;
+    if (t < TPC_BAR_WORDS) P.bar[t] = 0;
     if (t == 0) { *P.err = 0; *P.n_placed = 0; }
     if (t <= TPC_MAX_ROWS) { P.len_hist[t] = 0; P.len_cur[t] = 0; }
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
 persist_reco(PersistArgs P) {
-    __shared__ float xs[TPC_MAX_ROWS];
     __shared__ union {
         tpc_nb::PairLds nb;
+        tpc_nb::BinLds bin;
         uint32_t caw[TPC_CA_CAP];
     } U;
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     __shared__ int bc[2];
     const int G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
-    for (int r = tid; r < P.n_rows; r += TPC_BLOCK) xs[r] = P.F.row_x[r];
 
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_nb::nb_bin_seg(seg, P.n_rows, P.off, P.y, P.z, P.win_y, P.win_z, P.nb.grid, P.nb.cstart,
-                           P.nb.sy, P.nb.sz, P.nb.sid);
+                           P.nb.sy, P.nb.sz, P.nb.sid, U.bin);
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.y, P.z, P.win_y, P.win_z, P.cut_y, P.cut_z,
@@ -229,15 +257,6 @@ persist_reco(PersistArgs P) {
             }
         }
     }
-    if (!grid_sync(P)) return;
-    if (P.sort_fit) {
-        const int np = *P.n_placed;
-        for (int k = bid * TPC_BLOCK + tid; k < np; k += G * TPC_BLOCK) fit_one(P.F, P.perm[k], xs);
-    } else {
-        int T = *P.sd.n_seeds;
-        if (T > P.sd.cap_seeds) T = P.sd.cap_seeds;
-        for (int i = bid * TPC_BLOCK + tid; i < T; i += G * TPC_BLOCK) fit_one(P.F, i, xs);
-    }
 }
 
 __global__ void persist_status(PersistArgs P) {
@@ -257,7 +276,7 @@ size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, int
     w.off = nbb;
     const size_t cab = ca_ws_layout(ws ? w.base + nbb : nullptr, N, NR, &ca);
     w.off = nbb + cab;
-    unsigned *bar = w.take<unsigned>(2);
+    unsigned *bar = w.take<unsigned>(TPC_BAR_WORDS);
     int32_t *err = w.take<int32_t>(1);
     const int64_t nchunks = (NR + TPC_SCAN_CHUNK - 1) / TPC_SCAN_CHUNK;
     int32_t *cc = w.take<int32_t>(nchunks > 0 ? nchunks : 1);
@@ -325,6 +344,13 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
     P.F.hyz = P.hyz;
     hipLaunchKernelGGL(persist_init, dim3(2), dim3(TPC_BLOCK), 0, st, P);
     hipLaunchKernelGGL(persist_reco, dim3(grid), dim3(TPC_BLOCK), 0, st, P);
+    // the fit follows as its own launch, longest seeds first with sort_fit
+    FitArgs F = P.F;
+    if (sort_fit) {
+        F.order = P.perm;
+        F.n_order = P.n_placed;
+    }
+    launch_fit_args(F, st);
     hipLaunchKernelGGL(persist_status, dim3(1), dim3(64), 0, st, P);
     return hipGetLastError();
 }
