@@ -209,7 +209,7 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
 // cell_coord is monotonic, every cluster that can pass the exact predicates
 // is visited.  A cluster h with a non-finite coordinate fails every window,
 // so it is skipped.
-#define TPC_NB_DLIST 4
+#define TPC_NB_DLIST 8
 
 template <class FP, class IP, class CP>
 __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS, const SegGrid &gu,
