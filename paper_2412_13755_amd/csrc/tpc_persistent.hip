@@ -350,7 +350,7 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
         F.order = P.perm;
         F.n_order = P.n_placed;
     }
-    launch_fit_args(F, st);
+    launch_fit_args(F, st, true);
     hipLaunchKernelGGL(persist_status, dim3(1), dim3(64), 0, st, P);
     return hipGetLastError();
 }
