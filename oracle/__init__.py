@@ -43,6 +43,10 @@ class FitParams(ctypes.Structure):
                 ("var_qpt0", ctypes.c_double)]
 
 
+class FollowParams(ctypes.Structure):
+    _fields_ = [("gate", ctypes.c_double), ("max_miss", ctypes.c_int32)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -61,6 +65,10 @@ def lib():
         L.oracle_fit.argtypes = [i32, P, P, P, P, P, P, P, i32, P, ctypes.POINTER(FitParams),
                                  P, P, P, P, P, P]
         L.oracle_fit.restype = None
+        L.oracle_follow.argtypes = [i32, P, P, P, P, P, P, i32, i32, P, P, P,
+                                    ctypes.POINTER(FitParams), ctypes.POINTER(FollowParams),
+                                    P, P, P, P, P, P, P, P]
+        L.oracle_follow.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -149,6 +157,35 @@ def fit(seeds: dict, y, z, row_x, n_rows, *, bz, sigma_y, sigma_z, max_sin, var_
                      None if mp is None else _p(mp), ctypes.byref(prm), _p(out["x"]),
                      _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndf"]),
                      _p(out["status"]))
+    return out
+
+
+def follow(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, gate, max_miss, bz,
+           sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0):
+    """Track following of every seed, then duplicate removal.
+
+    Returns dict(rows [T, R] int32 cluster id per pad row or -1, x, par, cov,
+    chi2, ndf, status (0 ok, 1-3 fit failure, 4 duplicate), margin).
+    """
+    offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
+    hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
+    frm = np.ascontiguousarray(seeds["frame"], dtype=np.int32)
+    sec = np.ascontiguousarray(seeds["sector"], dtype=np.int32)
+    fr = np.ascontiguousarray(seeds["first_row"], dtype=np.int32)
+    off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    rx = np.ascontiguousarray(row_x, dtype=np.float64)
+    T = len(offsets) - 1
+    prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
+    fp = FollowParams(float(gate), int(max_miss))
+    out = dict(rows=np.empty((T, n_rows), np.int32), x=np.empty(T), par=np.empty((T, 5)),
+               cov=np.empty((T, 15)), chi2=np.empty(T), ndf=np.empty(T, np.int32),
+               status=np.empty(T, np.int32), margin=np.empty(T))
+    lib().oracle_follow(T, _p(offsets), _p(hits), _p(frm), _p(sec), _p(fr), _p(off), n_sectors, n_rows,
+                        _p(y), _p(z), _p(rx), ctypes.byref(prm), ctypes.byref(fp), _p(out["rows"]),
+                        _p(out["x"]), _p(out["par"]), _p(out["cov"]), _p(out["chi2"]),
+                        _p(out["ndf"]), _p(out["status"]), _p(out["margin"]))
     return out
 
 

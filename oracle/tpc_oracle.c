@@ -306,28 +306,71 @@ static void mat5_mul(const double *A, const double *B, double *C)
         }
 }
 
-static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
-                    const double *y, const double *z, const double *row_x, int32_t n_rows,
-                    const double *map, const oracle_fit_params *prm,
-                    double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto)
+/* Prediction: p, C (full 5x5) moved to the plane dx away, C <- F C F^T.
+ * Returns the status of the helix step (0 or 2). */
+static int32_t predict(double *p, double *C, double dx, const oracle_fit_params *prm)
 {
-    double xs[512], ys[512], zs[512];
-    *ndfo = 2 * n - 5;
+    double pp[5], F[25], FC[25], Ft[25];
+    int32_t st = oracle_propagate(p, dx, prm->bz, prm->max_sin, pp, F);
+    if (st) return st;
+    mat5_mul(F, C, FC);
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Ft[i * 5 + j] = F[j * 5 + i];
+    mat5_mul(FC, Ft, C);
+    for (int i = 0; i < 5; ++i) p[i] = pp[i];
+    return 0;
+}
+
+/* chi2 of the predicted residual of measurement (my, mz) against the state
+ * p with covariance C; NaN if the residual covariance is not positive. */
+static double resid_chi2(const double *p, const double *C, double my, double mz, double vy, double vz)
+{
+    double r0 = my - p[0], r1 = mz - p[1];
+    double S00 = C[0] + vy, S01 = C[1], S10 = C[5], S11 = C[6] + vz;
+    double det = S00 * S11 - S01 * S10;
+    if (!(det > 0.0)) return NAN;
+    double Si00 = S11 / det, Si01 = -S01 / det, Si10 = -S10 / det, Si11 = S00 / det;
+    return r0 * (Si00 * r0 + Si01 * r1) + r1 * (Si10 * r0 + Si11 * r1);
+}
+
+/* Kalman update of the predicted p, C with the measurement (my, mz), H = [I2 0]:
+ * r = m - (y, z), S = C_yz + diag(vy, vz), K = C H^T S^-1, p += K r,
+ * C -= K H C.  Adds r^T S^-1 r to *chi2.  Returns 0, or 3 if S is singular
+ * or the result is not finite. */
+static int32_t update(double *p, double *C, double my, double mz, double vy, double vz, double *chi2)
+{
+    double Cp[25];
+    for (int i = 0; i < 25; ++i) Cp[i] = C[i];
+    double r0 = my - p[0], r1 = mz - p[1];
+    double S00 = Cp[0] + vy, S01 = Cp[1], S10 = Cp[5], S11 = Cp[6] + vz;
+    double det = S00 * S11 - S01 * S10;
+    if (!(det > 0.0)) return 3;
+    double Si00 = S11 / det, Si01 = -S01 / det, Si10 = -S10 / det, Si11 = S00 / det;
+    double K[10];
+    for (int i = 0; i < 5; ++i) {
+        K[i * 2 + 0] = Cp[i * 5 + 0] * Si00 + Cp[i * 5 + 1] * Si10;
+        K[i * 2 + 1] = Cp[i * 5 + 0] * Si01 + Cp[i * 5 + 1] * Si11;
+    }
+    for (int i = 0; i < 5; ++i) p[i] = p[i] + K[i * 2 + 0] * r0 + K[i * 2 + 1] * r1;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j)
+            C[i * 5 + j] = Cp[i * 5 + j] - (K[i * 2 + 0] * Cp[0 * 5 + j] + K[i * 2 + 1] * Cp[1 * 5 + j]);
+    *chi2 += r0 * (Si00 * r0 + Si01 * r1) + r1 * (Si10 * r0 + Si11 * r1);
+    int finite = isfinite(*chi2);
+    for (int i = 0; i < 5; ++i) finite &= isfinite(p[i]);
+    return finite ? 0 : 3;
+}
+
+/* Inward fit of n points at planes xs (ascending), as described above: state
+ * p and full covariance C at xs[0] (or where the filter stopped), chi2, status. */
+static int32_t fit_points(int32_t n, const double *xs, const double *ys, const double *zs,
+                          const oracle_fit_params *prm, double *xo, double *p, double *C, double *chi2o)
+{
     *chi2o = 0.0;
     *xo = 0.0;
-    for (int i = 0; i < 5; ++i) po[i] = 0.0;
-    for (int i = 0; i < 15; ++i) co[i] = 0.0;
-    if (n < 3 || n > 512) { *sto = 1; return; }
-    for (int k = 0; k < n; ++k) {
-        int32_t r = row0 + k;
-        xs[k] = row_x[r];
-        ys[k] = y[hit[k]];
-        zs[k] = z[hit[k]];
-        if (map) {
-            ys[k] -= map[((size_t)sec * n_rows + r) * 2 + 0];
-            zs[k] -= map[((size_t)sec * n_rows + r) * 2 + 1];
-        }
-    }
+    for (int i = 0; i < 5; ++i) p[i] = 0.0;
+    for (int i = 0; i < 25; ++i) C[i] = 0.0;
+    if (n < 3) return 1;
     /* start */
     int a = n - 1, b = (n - 1) / 2, c = 0;
     double bcx = xs[b] - xs[c], bcy = ys[b] - ys[c];
@@ -343,14 +386,12 @@ static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
     int32_t st = 0;
     if (!(prod > 0.0) || !(fabs(ua) < 1.0) || !(fabs(uc) < 1.0)) st = 1;
     double phiA = atan2(aby, abx) + asin(st ? 0.0 : ua);
-    double p[5], C[25];
     p[0] = ys[a];
     p[1] = zs[a];
     p[2] = sin(phiA);
     p[3] = (zs[a] - zs[c]) / (lac * g_of(uc));
     p[4] = -kap0 / (C_LIGHT * prm->bz);
     if (!st && (!(cos(phiA) > 0.0) || !(fabs(p[2]) < prm->max_sin))) st = 1;
-    for (int i = 0; i < 25; ++i) C[i] = 0.0;
     C[0] = prm->sigma_y * prm->sigma_y;
     C[6] = prm->sigma_z * prm->sigma_z;
     C[12] = prm->var_sin0;
@@ -360,42 +401,50 @@ static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
     double chi2 = 0.0;
     double xcur = xs[a];
     for (int k = n - 2; k >= 0 && !st; --k) {
-        double pp[5], F[25], FC[25], Ft[25], Cp[25];
-        double dx = xs[k] - xs[k + 1];
-        if (oracle_propagate(p, dx, prm->bz, prm->max_sin, pp, F)) { st = 2; break; }
-        mat5_mul(F, C, FC);
-        for (int i = 0; i < 5; ++i)
-            for (int j = 0; j < 5; ++j) Ft[i * 5 + j] = F[j * 5 + i];
-        mat5_mul(FC, Ft, Cp);
+        if (predict(p, C, xs[k] - xs[k + 1], prm)) { st = 2; break; }
         xcur = xs[k];
-        /* update with m = (ys[k], zs[k]), H = [I2 0] */
-        double r0 = ys[k] - pp[0], r1 = zs[k] - pp[1];
-        double S00 = Cp[0] + vy, S01 = Cp[1], S10 = Cp[5], S11 = Cp[6] + vz;
-        double det = S00 * S11 - S01 * S10;
-        if (!(det > 0.0)) { st = 3; break; }
-        double Si00 = S11 / det, Si01 = -S01 / det, Si10 = -S10 / det, Si11 = S00 / det;
-        double K[10];
-        for (int i = 0; i < 5; ++i) {
-            K[i * 2 + 0] = Cp[i * 5 + 0] * Si00 + Cp[i * 5 + 1] * Si10;
-            K[i * 2 + 1] = Cp[i * 5 + 0] * Si01 + Cp[i * 5 + 1] * Si11;
-        }
-        for (int i = 0; i < 5; ++i) p[i] = pp[i] + K[i * 2 + 0] * r0 + K[i * 2 + 1] * r1;
-        for (int i = 0; i < 5; ++i)
-            for (int j = 0; j < 5; ++j)
-                C[i * 5 + j] = Cp[i * 5 + j] - (K[i * 2 + 0] * Cp[0 * 5 + j] + K[i * 2 + 1] * Cp[1 * 5 + j]);
-        chi2 += r0 * (Si00 * r0 + Si01 * r1) + r1 * (Si10 * r0 + Si11 * r1);
-        int finite = isfinite(chi2);
-        for (int i = 0; i < 5; ++i) finite &= isfinite(p[i]);
-        if (!finite) { st = 3; break; }
+        if (update(p, C, ys[k], zs[k], vy, vz, &chi2)) { st = 3; break; }
     }
     *xo = xcur;
-    for (int i = 0; i < 5; ++i) po[i] = p[i];
+    *chi2o = chi2;
+    return st;
+}
+
+static void pack_cov(const double *C, double *co)
+{
     /* packed lower triangle, row by row: (0,0) (1,0) (1,1) (2,0) ... */
     int q = 0;
     for (int i = 0; i < 5; ++i)
         for (int j = 0; j <= i; ++j) co[q++] = C[i * 5 + j];
-    *chi2o = chi2;
-    *sto = st;
+}
+
+static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
+                    const double *y, const double *z, const double *row_x, int32_t n_rows,
+                    const double *map, const oracle_fit_params *prm,
+                    double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto)
+{
+    double xs[512], ys[512], zs[512], C[25];
+    *ndfo = 2 * n - 5;
+    if (n < 3 || n > 512) {
+        *chi2o = 0.0;
+        *xo = 0.0;
+        for (int i = 0; i < 5; ++i) po[i] = 0.0;
+        for (int i = 0; i < 15; ++i) co[i] = 0.0;
+        *sto = 1;
+        return;
+    }
+    for (int k = 0; k < n; ++k) {
+        int32_t r = row0 + k;
+        xs[k] = row_x[r];
+        ys[k] = y[hit[k]];
+        zs[k] = z[hit[k]];
+        if (map) {
+            ys[k] -= map[((size_t)sec * n_rows + r) * 2 + 0];
+            zs[k] -= map[((size_t)sec * n_rows + r) * 2 + 1];
+        }
+    }
+    *sto = fit_points(n, xs, ys, zs, prm, xo, po, C, chi2o);
+    pack_cov(C, co);
 }
 
 void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
@@ -410,4 +459,216 @@ void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                 y, z, row_x, n_rows, map, prm, &x_out[i], &par[(size_t)i * 5],
                 &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i]);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Track following.  The paper does not describe it; this is a textbook      */
+/* prolongation with cluster pickup, per seed:                               */
+/*  0  fit the seed as above (state at its innermost hit)                    */
+/*  A  inwards, row by row below the innermost hit: predict to the row; stop */
+/*     if the step fails or |y| exceeds the row half-width x tan 10 deg (the */
+/*     track leaves the sector); among all clusters of that (frame, sector,  */
+/*     row) take the one of smallest predicted-residual chi2 (ties: smaller  */
+/*     id); if chi2 <= gate, update with it, else count a miss and stop      */
+/*     after more than max_miss consecutive misses                           */
+/*  B  outwards: restart at the innermost hit (its measured y, z, the other  */
+/*     parameters from A, the start covariance of the fit), update with      */
+/*     every hit above it up to the outermost, then prolong outwards above   */
+/*     the outermost hit as in A                                             */
+/*  C  refit all hits inwards exactly as the seed fit (three-point start at */
+/*     the outermost hit, middle hit (n-1)/2 in ascending row order)         */
+/* Then duplicates: each cluster belongs to the track with the smallest key  */
+/* (n_rows - n_hits, track index) among the successfully refitted tracks     */
+/* that hold it; a track owning fewer than half of its hits is marked 4.     */
+/* margin[t] is the smallest relative distance of any floating-point         */
+/* decision of A and B from its threshold (gate, tie, half-width, max_sin):  */
+/* a computation with different rounding may decide differently only where   */
+/* it is tiny.                                                               */
+/* ------------------------------------------------------------------------ */
+static double dmin(double a, double b) { return a < b ? a : b; }
+
+/* One row of prolongation: predict p, C to plane x_r; returns 1 to go on,
+ * 0 to stop.  *pick = chosen cluster or -1. */
+static int follow_row(double *p, double *C, double *xcur, double xr, int32_t c0, int32_t c1,
+                      const double *y, const double *z, const oracle_fit_params *prm,
+                      double gate, double tan10, int32_t *pick, double *margin)
+{
+    double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
+    *pick = -1;
+    if (predict(p, C, xr - *xcur, prm)) return 0;
+    *xcur = xr;
+    *margin = dmin(*margin, fabs(fabs(p[2]) - prm->max_sin));
+    double hw = xr * tan10;
+    *margin = dmin(*margin, fabs(fabs(p[0]) - hw) / hw);
+    if (!(fabs(p[0]) <= hw)) return 0;
+    double b1 = INFINITY, b2 = INFINITY;
+    int32_t best = -1;
+    for (int32_t c = c0; c < c1; ++c) {
+        double chi = resid_chi2(p, C, y[c], z[c], vy, vz);
+        if (!isfinite(chi)) continue;
+        *margin = dmin(*margin, fabs(chi - gate) / (gate + 1.0));
+        if (chi < b1) { b2 = b1; b1 = chi; best = c; }
+        else if (chi < b2) b2 = chi;
+    }
+    if (best >= 0 && b1 <= gate) {
+        if (b2 <= gate) *margin = dmin(*margin, (b2 - b1) / (b1 + 1.0));
+        double chi2 = 0.0;
+        if (update(p, C, y[best], z[best], vy, vz, &chi2)) return 0;
+        *pick = best;
+    }
+    return 1;
+}
+
+static void follow_one(int32_t i, int32_t n, const int32_t *hit, int32_t frame, int32_t sec,
+                       int32_t row0, const int32_t *row_offsets, int32_t n_sectors, int32_t n_rows,
+                       const double *y, const double *z, const double *row_x,
+                       const oracle_fit_params *prm, const oracle_follow_params *fp,
+                       int32_t *rows, double *xo, double *po, double *co, double *chi2o,
+                       int32_t *ndfo, int32_t *sto, double *margin)
+{
+    const double tan10 = tan(3.14159265358979323846 / 18.0);   /* sector half-opening 10 deg */
+    double xs[512], ys[512], zs[512], p[5], C[25];
+    (void)i;
+    *margin = INFINITY;
+    *ndfo = 2 * n - 5;
+    for (int32_t r = 0; r < n_rows; ++r) rows[r] = -1;
+    if (n < 3 || row0 < 0 || row0 + n > n_rows) {
+        *xo = 0.0;
+        *chi2o = 0.0;
+        for (int q = 0; q < 5; ++q) po[q] = 0.0;
+        for (int q = 0; q < 15; ++q) co[q] = 0.0;
+        *sto = 1;
+        return;
+    }
+    /* 0: the seed fit */
+    for (int32_t k = 0; k < n; ++k) {
+        rows[row0 + k] = hit[k];
+        xs[k] = row_x[row0 + k];
+        ys[k] = y[hit[k]];
+        zs[k] = z[hit[k]];
+    }
+    *sto = fit_points(n, xs, ys, zs, prm, xo, p, C, chi2o);
+    if (*sto) {
+        for (int q = 0; q < 5; ++q) po[q] = p[q];
+        pack_cov(C, co);
+        return;
+    }
+    const int32_t *seg_off = row_offsets + ((size_t)frame * n_sectors + sec) * n_rows;
+    /* A: inwards */
+    int32_t lo = row0, hi = row0 + n - 1;
+    double plo[5];
+    for (int q = 0; q < 5; ++q) plo[q] = p[q];
+    double xcur = row_x[row0];
+    int32_t miss = 0;
+    for (int32_t r = row0 - 1; r >= 0; --r) {
+        int32_t pick;
+        if (!follow_row(p, C, &xcur, row_x[r], seg_off[r], seg_off[r + 1], y, z, prm, fp->gate,
+                        tan10, &pick, margin))
+            break;
+        if (pick >= 0) {
+            rows[r] = pick;
+            lo = r;
+            miss = 0;
+            for (int q = 0; q < 5; ++q) plo[q] = p[q];
+        } else if (++miss > fp->max_miss) {
+            break;
+        }
+    }
+    /* B: outwards from the innermost hit */
+    for (int q = 0; q < 5; ++q) p[q] = plo[q];
+    p[0] = y[rows[lo]];
+    p[1] = z[rows[lo]];
+    for (int q = 0; q < 25; ++q) C[q] = 0.0;
+    C[0] = prm->sigma_y * prm->sigma_y;
+    C[6] = prm->sigma_z * prm->sigma_z;
+    C[12] = prm->var_sin0;
+    C[18] = prm->var_tgl0;
+    C[24] = prm->var_qpt0;
+    xcur = row_x[lo];
+    int ok = 1;
+    {
+        double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z, chi2 = 0.0;
+        for (int32_t r = lo + 1; r <= hi && ok; ++r) {
+            if (rows[r] < 0) continue;
+            if (predict(p, C, row_x[r] - xcur, prm)) { ok = 0; break; }
+            xcur = row_x[r];
+            *margin = dmin(*margin, fabs(fabs(p[2]) - prm->max_sin));
+            if (update(p, C, y[rows[r]], z[rows[r]], vy, vz, &chi2)) ok = 0;
+        }
+    }
+    if (ok) {
+        miss = 0;
+        for (int32_t r = hi + 1; r < n_rows; ++r) {
+            int32_t pick;
+            if (!follow_row(p, C, &xcur, row_x[r], seg_off[r], seg_off[r + 1], y, z, prm, fp->gate,
+                            tan10, &pick, margin))
+                break;
+            if (pick >= 0) {
+                rows[r] = pick;
+                hi = r;
+                miss = 0;
+            } else if (++miss > fp->max_miss) {
+                break;
+            }
+        }
+    }
+    /* C: refit of all hits */
+    int32_t m = 0;
+    for (int32_t r = lo; r <= hi; ++r) {
+        if (rows[r] < 0) continue;
+        xs[m] = row_x[r];
+        ys[m] = y[rows[r]];
+        zs[m] = z[rows[r]];
+        ++m;
+    }
+    *sto = fit_points(m, xs, ys, zs, prm, xo, p, C, chi2o);
+    for (int q = 0; q < 5; ++q) po[q] = p[q];
+    pack_cov(C, co);
+    *ndfo = 2 * m - 5;
+}
+
+void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                   const int32_t *frame, const int32_t *sector, const int32_t *first_row,
+                   const int32_t *row_offsets, int32_t n_sectors, int32_t n_rows,
+                   const double *y, const double *z, const double *row_x,
+                   const oracle_fit_params *prm, const oracle_follow_params *fp,
+                   int32_t *rows, double *x_out, double *par, double *cov, double *chi2,
+                   int32_t *ndf, int32_t *status, double *margin)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        follow_one(i, offsets[i + 1] - offsets[i], hits + offsets[i], frame[i], sector[i],
+                   first_row[i], row_offsets, n_sectors, n_rows, y, z, row_x, prm, fp,
+                   rows + (size_t)i * n_rows, &x_out[i], &par[(size_t)i * 5],
+                   &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i], &margin[i]);
+    }
+    /* duplicates */
+    int32_t N = 0;
+    for (int32_t i = 0; i < n_tracks; ++i)
+        for (int32_t r = 0; r < n_rows; ++r) {
+            int32_t c = rows[(size_t)i * n_rows + r];
+            if (c + 1 > N) N = c + 1;
+        }
+    uint64_t *owner = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(N > 0 ? N : 1));
+    for (int32_t c = 0; c < N; ++c) owner[c] = UINT64_MAX;
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        if (status[i]) continue;
+        uint64_t key = ((uint64_t)(uint32_t)(n_rows - (ndf[i] + 5) / 2) << 32) | (uint32_t)i;
+        for (int32_t r = 0; r < n_rows; ++r) {
+            int32_t c = rows[(size_t)i * n_rows + r];
+            if (c >= 0 && key < owner[c]) owner[c] = key;
+        }
+    }
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        if (status[i]) continue;
+        int32_t nh = (ndf[i] + 5) / 2;
+        uint64_t key = ((uint64_t)(uint32_t)(n_rows - nh) << 32) | (uint32_t)i;
+        int32_t owned = 0;
+        for (int32_t r = 0; r < n_rows; ++r) {
+            int32_t c = rows[(size_t)i * n_rows + r];
+            if (c >= 0 && owner[c] == key) ++owned;
+        }
+        if (2 * owned < nh) status[i] = 4;
+    }
+    free(owner);
 }

@@ -11,6 +11,11 @@ typedef struct oracle_fit_params {
     double var_sin0, var_tgl0, var_qpt0;   /* start covariance of s, t, w */
 } oracle_fit_params;
 
+typedef struct oracle_follow_params {
+    double gate;        /* pickup gate on the predicted-residual chi2 (2 dof) */
+    int32_t max_miss;   /* consecutive rows without pickup that are crossed */
+} oracle_follow_params;
+
 void oracle_set_threads(int n);
 int oracle_max_threads(void);
 
@@ -32,4 +37,12 @@ void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                 const double *y, const double *z, const double *row_x, int32_t n_rows,
                 const double *map, const oracle_fit_params *prm,
                 double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status);
+
+void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                   const int32_t *frame, const int32_t *sector, const int32_t *first_row,
+                   const int32_t *row_offsets, int32_t n_sectors, int32_t n_rows,
+                   const double *y, const double *z, const double *row_x,
+                   const oracle_fit_params *prm, const oracle_follow_params *fp,
+                   int32_t *rows, double *x_out, double *par, double *cov, double *chi2,
+                   int32_t *ndf, int32_t *status, double *margin);
 #endif

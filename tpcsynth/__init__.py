@@ -1,6 +1,6 @@
 """Seeded synthetic TPC time frames (inputs only; no reconstruction arithmetic)."""
 from .generator import (Frames, Tracks, make_frames, make_config, config_params, make_row_x,
-                        sector_alpha, sector_side, CONFIG_NAMES, C_LIGHT, TAN10)
+                        sector_alpha, sector_side, CONFIG_NAMES, C_LIGHT, TAN10, drop_clusters, add_clusters)
 
 __all__ = ["Frames", "Tracks", "make_frames", "make_config", "config_params", "make_row_x",
-           "sector_alpha", "sector_side", "CONFIG_NAMES", "C_LIGHT", "TAN10"]
+           "sector_alpha", "sector_side", "CONFIG_NAMES", "C_LIGHT", "TAN10", "drop_clusters", "add_clusters"]

@@ -294,7 +294,7 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
                 drift_window_us: float = 0.0, distortion_amp: float = 0.0, distortion_period: float = 38.0,
                 bz: float = 0.5, sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True,
                 shuffle: bool = True, max_turns: int = 3, keep_truth: bool = False,
-                tracks: Optional[Tracks] = None) -> Frames:
+                hit_eff: float = 1.0, tracks: Optional[Tracks] = None) -> Frames:
     """General generator; ``make_config`` fixes the parameters of the five workloads."""
     rng = np.random.Generator(np.random.PCG64(seed))
     row_x = make_row_x(n_rows)
@@ -312,6 +312,10 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
             parts.append(_draw_tracks(rng, nt, phi_range, looper_frac, trunc_frac, n_rows, f, t0))
         tracks = _concat_tracks(parts)
     cr = _crossings_parallel(tracks, row_x, n_sectors, bz, max_turns)
+    if hit_eff < 1.0:
+        # pad-row inefficiency: each crossing leaves a cluster with probability hit_eff
+        keep = rng.random(cr["track"].size) < hit_eff
+        cr = {k: v[keep] for k, v in cr.items()}
     n_sig = cr["track"].size
     y_true = cr["y"].copy()
     z_true = cr["z"].copy()
@@ -381,6 +385,43 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
     fr.meta = dict(n_tracks=len(tracks), n_signal=n_sig, n_noise=n_noise, seed=seed)
     fr.meta["tracks"] = tracks
     return fr
+
+
+def drop_clusters(fr: Frames, keep: np.ndarray) -> Frames:
+    """The clusters of ``fr`` where ``keep`` is true, in the same order, ids
+    renumbered; truth arrays follow.  Used to plant gaps in tracks."""
+    keep = np.asarray(keep, dtype=bool)
+    seg = np.repeat(np.arange(fr.row_offsets.size - 1), np.diff(fr.row_offsets))
+    counts = np.bincount(seg[keep], minlength=fr.row_offsets.size - 1)
+    offs = np.zeros(fr.row_offsets.size, dtype=np.int32)
+    np.cumsum(counts, out=offs[1:])
+    def cut(v):
+        return None if v is None else v[keep]
+    return Frames(fr.n_frames, fr.n_sectors, fr.n_rows, fr.row_x, offs, fr.y[keep], fr.z[keep],
+                  fr.bz, fr.sigma_y, fr.sigma_z, cut(fr.track_of), cut(fr.y_true), cut(fr.z_true),
+                  cut(fr.s_true), cut(fr.t_true), cut(fr.w_true), fr.distortion, dict(fr.meta))
+
+
+def add_clusters(fr: Frames, frame, sector, row, y, z, track_of=None) -> Frames:
+    """``fr`` with extra clusters appended at the end of their (frame, sector,
+    row); ids renumbered, truth of the new clusters unknown (NaN)."""
+    seg_new = (np.asarray(frame) * fr.n_sectors + np.asarray(sector)) * fr.n_rows + np.asarray(row)
+    seg_old = np.repeat(np.arange(fr.row_offsets.size - 1), np.diff(fr.row_offsets))
+    seg = np.concatenate([seg_old, seg_new])
+    order = np.argsort(seg, kind="stable")
+    counts = np.bincount(seg, minlength=fr.row_offsets.size - 1)
+    offs = np.zeros(fr.row_offsets.size, dtype=np.int32)
+    np.cumsum(counts, out=offs[1:])
+    k = seg_new.size
+    tof = np.full(k, -1, np.int32) if track_of is None else np.asarray(track_of, np.int32)
+    def cat(v, extra):
+        return None if v is None else np.concatenate([v, extra])[order]
+    nan = np.full(k, np.nan)
+    return Frames(fr.n_frames, fr.n_sectors, fr.n_rows, fr.row_x, offs,
+                  cat(fr.y, np.asarray(y, np.float32)), cat(fr.z, np.asarray(z, np.float32)),
+                  fr.bz, fr.sigma_y, fr.sigma_z, cat(fr.track_of, tof), cat(fr.y_true, nan),
+                  cat(fr.z_true, nan), cat(fr.s_true, nan), cat(fr.t_true, nan), cat(fr.w_true, nan),
+                  fr.distortion, dict(fr.meta))
 
 
 CONFIG_NAMES = (
