@@ -52,6 +52,7 @@ typedef int32_t tpc_status;
 #define TPC_FIT_INIT_FAIL    1   /* three-point start degenerate or |sin phi| >= max_sin */
 #define TPC_FIT_SIN_FAIL     2   /* propagation reached |sin phi| >= max_sin */
 #define TPC_FIT_NUM_FAIL     3   /* singular residual covariance or non-finite state */
+#define TPC_FOLLOW_DUPLICATE 4   /* tpc_track_follow: fewer than half of its clusters are its own */
 
 /* Reconstruction constants.  Copied at tpc_create(); the context is immutable. */
 typedef struct tpc_config {
@@ -111,7 +112,8 @@ void tpc_destroy(tpc_context *ctx);
 #define TPC_STAGE_FIT         4
 #define TPC_STAGE_ADJOINT     8
 #define TPC_STAGE_PERSISTENT 16
-#define TPC_STAGE_ALL        31
+#define TPC_STAGE_FOLLOW     32
+#define TPC_STAGE_ALL        63
 
 /* Workspace bytes needed by the stages in `stage_mask` for frames of this
  * shape (only n_frames and n_clusters are read; host call, no device work).
@@ -230,6 +232,45 @@ tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *frames, int
                            const tpc_tune *tune, int32_t *up, int32_t *dn, tpc_seeds *seeds,
                            tpc_tracks *tracks, int32_t *dev_status, void *ws, size_t ws_bytes,
                            void *stream);
+
+/* Track following: the step after the fit that the paper's reconstruction
+ * implies but does not describe (Sec. 4.2 names track reconstruction as the
+ * load of the farm's GPUs); this is a textbook prolongation with cluster
+ * pickup.  For every seed i (double precision throughout, no map):
+ *   0  the fit of tpc_kalman_fit (state at the innermost hit);
+ *   A  inwards, pad row by pad row below the innermost hit: helix step to the
+ *      row; stop if it fails or |y| > x tan 10 deg (the track leaves the
+ *      sector); take the cluster of that (frame, sector, row) with the
+ *      smallest chi2 of its predicted residual, r^T (C_yz + diag(sigma_y^2,
+ *      sigma_z^2))^-1 r, ties to the smaller id; if chi2 <= gate_chi2 update
+ *      the state with it, else count a miss, and stop after more than
+ *      max_miss consecutive misses;
+ *   B  outwards: restart at the innermost hit (its measured y, z, the other
+ *      parameters from A, the fit's start covariance), update with every hit
+ *      above it up to the outermost, then prolong outwards as in A;
+ *   C  refit all hits exactly as tpc_kalman_fit does a seed (three-point start
+ *      at the outermost, middle ((n-1)/2 in ascending row order) and
+ *      innermost hits; steps across empty rows go plane to plane).
+ * A cluster may be taken by several tracks.  Then duplicates: every cluster
+ * belongs to the track of smallest key (n_rows - n_hits, index) among the
+ * tracks with status TPC_FIT_OK holding it; a track owning fewer than half
+ * of its clusters gets status TPC_FOLLOW_DUPLICATE (broken pieces of one
+ * particle's chain grow into the same track and only one is kept).
+ * params: host pointer; gate_chi2 finite, >= 0; max_miss in 0..n_rows.
+ * rows: [cap_seeds][n_rows] device int32, written for i < *n_seeds: the
+ * cluster of track i in each pad row, -1 where it has none.
+ * tracks: as tpc_kalman_fit, for the refit (ndf = 2 n_hits - 5), status
+ * TPC_FIT_* of the seed fit or the refit, or TPC_FOLLOW_DUPLICATE.
+ * Seeds are read as tpc_ca_seed writes them (hit_yz is not used).
+ * ws: TPC_STAGE_FOLLOW workspace. */
+typedef struct tpc_follow_params {
+    float gate_chi2;
+    int32_t max_miss;
+} tpc_follow_params;
+tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
+                            const tpc_seeds *seeds, const tpc_follow_params *params,
+                            int32_t *rows, tpc_tracks *tracks, void *ws, size_t ws_bytes,
+                            void *stream);
 
 /* Workgroups the persistent kernel can keep resident on the context's device. */
 int32_t tpc_persistent_grid(const tpc_context *ctx);

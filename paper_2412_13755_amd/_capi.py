@@ -22,12 +22,14 @@ TPC_ERR_UNSUPPORTED = -4
 TPC_ERR_WORKSPACE = -5
 
 TPC_FIT_OK, TPC_FIT_INIT_FAIL, TPC_FIT_SIN_FAIL, TPC_FIT_NUM_FAIL = 0, 1, 2, 3
+TPC_FOLLOW_DUPLICATE = 4
 
 TPC_STAGE_NEIGHBOURS = 1
 TPC_STAGE_SEED = 2
 TPC_STAGE_FIT = 4
 TPC_STAGE_ADJOINT = 8
-TPC_STAGE_ALL = 31
+TPC_STAGE_FOLLOW = 32
+TPC_STAGE_ALL = 63
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32
@@ -57,6 +59,10 @@ class TracksC(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("grid", i32), ("sort_fit", i32)]
+
+
+class FollowParams(ctypes.Structure):
+    _fields_ = [("gate_chi2", f32), ("max_miss", i32)]
 
 
 TPC_MODE_STAGED = 0
@@ -91,6 +97,9 @@ SIGNATURES = {
     "tpc_reconstruct": (i32, [P, ctypes.POINTER(FramesC), i32, ctypes.POINTER(Tune), P, P,
                               ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), P, P, ctypes.c_size_t,
                               P]),
+    "tpc_track_follow": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
+                               ctypes.POINTER(FollowParams), P, ctypes.POINTER(TracksC), P,
+                               ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),

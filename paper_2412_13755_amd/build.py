@@ -27,6 +27,7 @@ SOURCES = {
     "tpc_fit.hip": [],
     "tpc_adjoint.hip": [],
     "tpc_persistent.hip": [],
+    "tpc_follow.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

@@ -76,6 +76,7 @@ size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
     if (mask & TPC_STAGE_ADJOINT) b = std::max(b, adjoint_bytes(ctx, fr, N > 0 ? N : 1, cs));
     if (mask & TPC_STAGE_PERSISTENT)
         b = std::max(b, persist_ws_layout(nullptr, N, NR, cs, N > 0 ? N : 1, nullptr));
+    if (mask & TPC_STAGE_FOLLOW) b = std::max(b, follow_ws_layout(nullptr, N, NR, nullptr));
     return b;
 }
 
@@ -314,6 +315,27 @@ tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *fr, int32_t
     const int sort_fit = tune ? tune->sort_fit : 1;
     hipError_t e = launch_persistent(ctx, fr, up, dn, sd, tr, dev_status, ws, grid, sort_fit, st);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "persistent kernel");
+}
+
+tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                            const tpc_follow_params *prm, int32_t *rows, tpc_tracks *tr, void *ws,
+                            size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if (!prm) return fail(TPC_ERR_ARG, "null follow parameters");
+    if (!(prm->gate_chi2 >= 0.f) || !isfinite(prm->gate_chi2)) return fail(TPC_ERR_ARG, "gate_chi2 must be finite and >= 0");
+    if (prm->max_miss < 0 || prm->max_miss > ctx->cfg.n_rows) return fail(TPC_ERR_ARG, "max_miss outside 0..n_rows");
+    if (sd->cap_seeds > 0 && !rows) return fail(TPC_ERR_ARG, "null rows");
+    if ((int64_t)sd->cap_seeds * ctx->cfg.n_rows >= ((int64_t)1 << 31))
+        return fail(TPC_ERR_ARG, "cap_seeds * n_rows must stay below 2^31");
+    if ((s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_FOLLOW)))) return s;
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_follow(ctx, fr, sd, (double)prm->gate_chi2, prm->max_miss, rows, tr, ws,
+                                 (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "follow kernels");
 }
 
 int32_t tpc_persistent_grid(const tpc_context *ctx) { return ctx ? ctx->persist_grid : 0; }

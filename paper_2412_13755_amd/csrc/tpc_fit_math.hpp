@@ -135,8 +135,10 @@ __host__ __device__ inline R asin_over_d_r(R u) {
 // conversions).  Returns false when |sin phi| reaches max_sin before or
 // after the step; the step is evaluated regardless (no early exit keeps the
 // filter loop free of branches), so p and J are then meaningless.
-template <class R>
-__host__ __device__ inline bool helix_step(R p[5], float dx, float kbz, float max_sin, StepJac &J) {
+// The plane distance dx and kbz = -c Bz come in precision K: single in the
+// fit (adjacent planes), double where steps cross several planes.
+template <class R, class K = float>
+__host__ __device__ inline bool helix_step(R p[5], K dx, K kbz, float max_sin, StepJac &J) {
     // kbz = -c Bz, so kappa = kbz * w
     const R s = p[2], t = p[3], w = p[4];
     const R kap = (R)kbz * w;
@@ -153,7 +155,7 @@ __host__ __device__ inline bool helix_step(R p[5], float dx, float kbz, float ma
     const R sq = sqrt_pos((R)1 + T * T, &isq);
     const R chord = adx * sq;
     const R u = (R)0.5 * kap * chord;
-    const R sgn = dx >= 0.0f ? (R)1 : (R)-1;
+    const R sgn = dx >= (K)0 ? (R)1 : (R)-1;
     const R arc = sgn * chord * asin_over_r(u);  // signed transverse path length
     // Jacobian
     const R iden2 = iden * iden;
@@ -323,9 +325,9 @@ __host__ __device__ inline R kalman_update(R p[5], SymT<R> &C, R my, R mz, R vy,
 // Exact circle through C (innermost), B, A (outermost): state at A, computed
 // in precision R.  Returns false if the points are degenerate or the
 // direction at A is not towards +x with |sin phi| < max_sin.
-template <class R>
+template <class R, class K = float>
 __host__ __device__ inline bool helix_start(R xa, R ya, R za, R xb, R yb, R xc, R yc, R zc,
-                                            float kbz, float max_sin, R p[5]) {
+                                            K kbz, float max_sin, R p[5]) {
     const R bcx = xb - xc, bcy = yb - yc;
     const R abx = xa - xb, aby = ya - yb;
     const R acx = xa - xc, acy = ya - yc;

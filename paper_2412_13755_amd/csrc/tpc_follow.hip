@@ -1,0 +1,416 @@
+// Track following (gfx950): every seed is fitted, prolonged inwards and
+// outwards with cluster pickup across up to max_miss empty pad rows, refitted
+// over all its hits, and tracks that share most of their clusters with a
+// longer one are marked as duplicates.
+//
+//  fl_index        workgroup per (frame, sector, row): the row's clusters in
+//                  y cells (about one cluster per cell, counting sort with
+//                  atomics in global memory); non-finite clusters are left out
+//                  (they can never pass the gate)
+//  fl_tracks       thread per seed, double precision throughout: seed fit,
+//                  inward prolongation, outward refit and prolongation,
+//                  final refit; the search in a row scans only the cells
+//                  covering the y extent of the gate ellipse
+//  fl_owner_init   owner key of every cluster := none
+//  fl_claim        thread per refitted track: 64-bit atomicMin of its key
+//                  (n_rows - n_hits, index) on each of its clusters
+//  fl_keep         thread per refitted track: duplicate if it owns fewer than
+//                  half of its clusters
+#include "tpc_fit_common.hpp"
+
+#define TPC_TAN10 0.17632698070846498   // tan 10 deg: a pad row spans |y| <= x tan 10 deg
+
+namespace {
+
+struct FlIndex {
+    float2 *grid;                 // [NR] (y0, cells per cm) of the segment's y cells
+    int32_t *cstart;              // [N + NR] cell starts of segment s at row_offsets[s] + s (n + 1 entries)
+    int32_t *cur;                 // [N + NR] scatter cursors
+    float2 *syz;                  // [N] (y, z) ordered by cell within each segment
+    int32_t *sid;                 // [N] their global ids
+    unsigned long long *owner;    // [N] smallest key of a track holding the cluster
+};
+
+struct FlArgs {
+    FitArgs F;                    // seeds, clusters, constants, outputs
+    const int32_t *row_offsets;
+    const int32_t *frame;         // [cap_seeds] frame of each seed
+    int32_t n_frames;
+    FlIndex X;
+    int32_t *rows;                // [cap_seeds][n_rows] cluster per pad row, -1 for none
+    double kbz;                   // -c Bz in double precision
+    double gate;
+    int32_t max_miss;
+};
+
+__device__ inline int ycell(float y, float y0, float iw, int n) {
+    float c = (y - y0) * iw;
+    c = fmaxf(c, 0.f);
+    c = fminf(c, (float)(n - 1));
+    return (int)c;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fl_index(const int32_t *__restrict__ off, const float *__restrict__ y, const float *__restrict__ z,
+         FlIndex X) {
+    __shared__ float red[2][TPC_BLOCK / TPC_WAVE];
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    __shared__ int carry;
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    const int a = off[seg], n = off[seg + 1] - a;
+    const int base = a + seg;
+    const int lane = threadIdx.x & (TPC_WAVE - 1), wid = threadIdx.x / TPC_WAVE;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int j = threadIdx.x; j < n; j += TPC_BLOCK) {
+        const float v = y[a + j], w = z[a + j];
+        if (isfinite(v) && isfinite(w)) {
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane == 0) {
+        red[0][wid] = lo;
+        red[1][wid] = hi;
+    }
+    for (int j = threadIdx.x; j <= n; j += TPC_BLOCK) X.cstart[base + j] = 0;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < TPC_BLOCK / TPC_WAVE; ++w) {
+        lo = fminf(lo, red[0][w]);
+        hi = fmaxf(hi, red[1][w]);
+    }
+    const float iw = hi > lo ? (float)n / (hi - lo) : 0.f;
+    const float y0 = hi >= lo ? lo : 0.f;
+    if (threadIdx.x == 0) X.grid[seg] = make_float2(y0, iw);
+    for (int j = threadIdx.x; j < n; j += TPC_BLOCK) {
+        const float v = y[a + j], w = z[a + j];
+        if (isfinite(v) && isfinite(w)) atomicAdd(&X.cstart[base + ycell(v, y0, iw, n)], 1);
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 <= n; c0 += TPC_BLOCK) {
+        const int j = c0 + threadIdx.x;
+        const int v = j <= n ? X.cstart[base + j] : 0;
+        int tot;
+        const int ex = block_exclusive_scan(v, sh, &tot);
+        const int cr = carry;
+        if (j <= n) {
+            X.cstart[base + j] = cr + ex;
+            X.cur[base + j] = cr + ex;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry = cr + tot;
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < n; j += TPC_BLOCK) {
+        const float v = y[a + j], w = z[a + j];
+        if (isfinite(v) && isfinite(w)) {
+            const int pos = atomicAdd(&X.cur[base + ycell(v, y0, iw, n)], 1);
+            X.syz[a + pos] = make_float2(v, w);
+            X.sid[a + pos] = a + j;
+        }
+    }
+}
+
+// Cluster of segment `seg` with the smallest predicted-residual chi2 against
+// (p, C), ties to the smaller id; -1 if none is within the gate.  Only the
+// cells covering the gate ellipse's y extent, sqrt(gate * S_yy), are read,
+// widened so that float rounding of the bounds cannot exclude a cluster.
+__device__ inline int pick_cluster(const FlArgs &A, int seg, const double p[5], const SymT<double> &C) {
+    const int a = A.row_offsets[seg], n = A.row_offsets[seg + 1] - a;
+    if (n <= 0) return -1;
+    const double S00 = C.c00 + A.F.vy, S01 = C.c10, S11 = C.c11 + A.F.vz;
+    const double det = S00 * S11 - S01 * S01;
+    if (!(det > 0.0)) return -1;
+    const double idet = 1.0 / det;
+    const double i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
+    const double hy = sqrt(A.gate * S00) * (1.0 + 1e-6) + 1e-5 * (1.0 + fabs(p[0]));
+    const float2 g = A.X.grid[seg];
+    const int c0 = ycell((float)(p[0] - hy), g.x, g.y, n);
+    const int c1 = ycell((float)(p[0] + hy), g.x, g.y, n);
+    const int base = a + seg;
+    const int j0 = A.X.cstart[base + c0], j1 = A.X.cstart[base + c1 + 1];
+    int best = -1;
+    double bchi = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const float2 c = A.X.syz[a + j];
+        const int id = A.X.sid[a + j];
+        const double r0 = (double)c.x - p[0], r1 = (double)c.y - p[1];
+        const double chi = r0 * (i00 * r0 + i01 * r1) + r1 * (i01 * r0 + i11 * r1);
+        if (chi <= A.gate && (best < 0 || chi < bchi || (chi == bchi && id < best))) {
+            best = id;
+            bchi = chi;
+        }
+    }
+    return best;
+}
+
+__device__ inline void start_cov(const FitArgs &F, SymT<double> &C) {
+    C = SymT<double>{};
+    C.c00 = F.vy;
+    C.c11 = F.vz;
+    C.c22 = F.var_s;
+    C.c33 = F.var_t;
+    C.c44 = F.var_w;
+}
+
+// One prolongation row: helix step to plane r, stop (false) if it fails or
+// leaves the row's width; *pick = cluster taken up (state updated) or -1.
+__device__ inline bool follow_row(const FlArgs &A, int seg0, int r, const float *xs, double p[5],
+                                  SymT<double> &C, double &xcur, int &pick) {
+    pick = -1;
+    StepJac J;
+    const double xr = (double)xs[r];
+    if (!helix_step<double, double>(p, xr - xcur, A.kbz, A.F.max_sin, J)) return false;
+    sym_transport<double, false>(C, J);
+    xcur = xr;
+    if (!(fabs(p[0]) <= xr * TPC_TAN10)) return false;
+    const int c = pick_cluster(A, seg0 + r, p, C);
+    if (c < 0) return true;
+    const double dchi = kalman_update<double>(p, C, (double)A.F.y[c], (double)A.F.z[c], A.F.vy, A.F.vz);
+    const double chk = dchi + p[0] + p[1] + p[2] + p[3] + p[4];
+    if (!(chk - chk == 0.0)) return false;
+    pick = c;
+    return true;
+}
+
+// Inward fit of the hits rw[lo..hi] (m of them, -1 = no hit): three-point
+// start at the outermost, middle ((m - 1) / 2 in ascending row order) and
+// innermost hits, then a helix step and Kalman update per hit.
+__device__ inline int fit_rows(const FlArgs &A, const int32_t *rw, int lo, int hi, int m,
+                               const float *xs, double p[5], SymT<double> &C, double &chi2,
+                               double &xcur) {
+    const FitArgs &F = A.F;
+    chi2 = 0.0;
+    xcur = (double)xs[hi];
+    start_cov(F, C);
+    for (int q = 0; q < 5; ++q) p[q] = 0.0;
+    if (m < 3) return TPC_FIT_INIT_FAIL;
+    int mid = lo;
+    for (int r = lo, k = 0, want = (m - 1) / 2; r <= hi; ++r) {
+        if (rw[r] < 0) continue;
+        if (k == want) {
+            mid = r;
+            break;
+        }
+        ++k;
+    }
+    const int ia = rw[hi], ib = rw[mid], ic = rw[lo];
+    if (!helix_start<double, double>((double)xs[hi], (double)F.y[ia], (double)F.z[ia], (double)xs[mid],
+                                     (double)F.y[ib], (double)xs[lo], (double)F.y[ic], (double)F.z[ic],
+                                     A.kbz, F.max_sin, p))
+        return TPC_FIT_INIT_FAIL;
+    for (int r = hi - 1; r >= lo; --r) {
+        const int id = rw[r];
+        if (id < 0) continue;
+        StepJac J;
+        const bool stepped = helix_step<double, double>(p, (double)xs[r] - xcur, A.kbz, F.max_sin, J);
+        sym_transport<double, false>(C, J);
+        const double dchi = kalman_update<double>(p, C, (double)F.y[id], (double)F.z[id], F.vy, F.vz);
+        chi2 += dchi;
+        const double chk = chi2 + p[0] + p[1] + p[2] + p[3] + p[4];
+        if (!stepped) return TPC_FIT_SIN_FAIL;
+        if (!(dchi >= 0.0) || !(chk - chk == 0.0)) return TPC_FIT_NUM_FAIL;
+        xcur = (double)xs[r];
+    }
+    return TPC_FIT_OK;
+}
+
+__device__ inline void follow_one(const FlArgs &A, int i, const float *xs) {
+    const FitArgs &F = A.F;
+    const SeedView sv = seed_view(F, i);
+    const int R = F.n_rows;
+    int32_t *rw = A.rows + (size_t)i * R;
+    for (int r = 0; r < R; ++r)
+        rw[r] = (sv.sane && r >= sv.row0 && r < sv.row0 + sv.n) ? sv.hh[r - sv.row0] : -1;
+    double p[5] = {0, 0, 0, 0, 0};
+    SymT<double> C = {};
+    double chi2 = 0.0, xcur = 0.0;
+    int status = TPC_FIT_INIT_FAIL, m = sv.n;
+    if (sv.sane) {
+        // a seed list not written by tpc_ca_seed may hold anything
+        if ((uint32_t)A.frame[i] >= (uint32_t)A.n_frames) m = 0;
+        for (int k = 0; k < sv.n; ++k)
+            if ((uint32_t)sv.hh[k] >= (uint32_t)F.n_clusters) rw[sv.row0 + k] = -1, m = 0;
+    }
+    if (sv.sane && m == sv.n) {
+        int lo = sv.row0, hi = sv.row0 + sv.n - 1;
+        status = fit_rows(A, rw, lo, hi, m, xs, p, C, chi2, xcur);
+        if (status == TPC_FIT_OK) {
+            const int seg0 = (A.frame[i] * F.n_sectors + sv.sec) * R;
+            // inwards from the innermost hit
+            double plo[5] = {p[0], p[1], p[2], p[3], p[4]};
+            int miss = 0;
+            for (int r = lo - 1; r >= 0; --r) {
+                int pick;
+                if (!follow_row(A, seg0, r, xs, p, C, xcur, pick)) break;
+                if (pick >= 0) {
+                    rw[r] = pick;
+                    lo = r;
+                    miss = 0;
+                    for (int q = 0; q < 5; ++q) plo[q] = p[q];
+                } else if (++miss > A.max_miss) {
+                    break;
+                }
+            }
+            // outwards: restart at the innermost hit, update with the hits above
+            for (int q = 2; q < 5; ++q) p[q] = plo[q];
+            p[0] = (double)F.y[rw[lo]];
+            p[1] = (double)F.z[rw[lo]];
+            start_cov(F, C);
+            xcur = (double)xs[lo];
+            bool ok = true;
+            for (int r = lo + 1; r <= hi; ++r) {
+                const int id = rw[r];
+                if (id < 0) continue;
+                StepJac J;
+                if (!helix_step<double, double>(p, (double)xs[r] - xcur, A.kbz, F.max_sin, J)) {
+                    ok = false;
+                    break;
+                }
+                sym_transport<double, false>(C, J);
+                xcur = (double)xs[r];
+                const double dchi = kalman_update<double>(p, C, (double)F.y[id], (double)F.z[id], F.vy, F.vz);
+                const double chk = dchi + p[0] + p[1] + p[2] + p[3] + p[4];
+                if (!(dchi >= 0.0) || !(chk - chk == 0.0)) {
+                    ok = false;
+                    break;
+                }
+            }
+            if (ok) {
+                miss = 0;
+                for (int r = hi + 1; r < R; ++r) {
+                    int pick;
+                    if (!follow_row(A, seg0, r, xs, p, C, xcur, pick)) break;
+                    if (pick >= 0) {
+                        rw[r] = pick;
+                        hi = r;
+                        miss = 0;
+                    } else if (++miss > A.max_miss) {
+                        break;
+                    }
+                }
+            }
+            // refit of all hits
+            m = 0;
+            for (int r = lo; r <= hi; ++r) m += rw[r] >= 0;
+            status = fit_rows(A, rw, lo, hi, m, xs, p, C, chi2, xcur);
+        }
+    }
+    F.out.x[i] = (float)xcur;
+    float *po = F.out.par + (size_t)i * 5;
+    for (int q = 0; q < 5; ++q) po[q] = (float)p[q];
+    float *co = F.out.cov + (size_t)i * 15;
+    const double cc[15] = {C.c00, C.c10, C.c11, C.c20, C.c21, C.c22, C.c30, C.c31,
+                           C.c32, C.c33, C.c40, C.c41, C.c42, C.c43, C.c44};
+    for (int q = 0; q < 15; ++q) co[q] = (float)cc[q];
+    F.out.chi2[i] = (float)chi2;
+    F.out.ndf[i] = 2 * m - 5;
+    F.out.status[i] = status;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fl_tracks(FlArgs A) {
+    __shared__ float xs[TPC_MAX_ROWS];
+    for (int r = threadIdx.x; r < A.F.n_rows; r += TPC_BLOCK) xs[r] = A.F.row_x[r];
+    __syncthreads();
+    int T = *A.F.n_seeds;
+    if (T > A.F.cap_seeds) T = A.F.cap_seeds;
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) follow_one(A, i, xs);
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fl_owner_init(unsigned long long *__restrict__ owner, int32_t N) {
+    for (int c = blockIdx.x * TPC_BLOCK + threadIdx.x; c < N; c += gridDim.x * TPC_BLOCK) owner[c] = ~0ull;
+}
+
+__device__ inline unsigned long long track_key(int n_rows, int ndf, int i) {
+    return ((unsigned long long)(uint32_t)(n_rows - (ndf + 5) / 2) << 32) | (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fl_claim(const int32_t *__restrict__ n_seeds, int32_t cap_seeds, int32_t n_rows,
+         const int32_t *__restrict__ rows, const int32_t *__restrict__ status,
+         const int32_t *__restrict__ ndf, unsigned long long *__restrict__ owner) {
+    int T = *n_seeds;
+    if (T > cap_seeds) T = cap_seeds;
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+        if (status[i] != TPC_FIT_OK) continue;
+        const unsigned long long key = track_key(n_rows, ndf[i], i);
+        const int32_t *rw = rows + (size_t)i * n_rows;
+        for (int r = 0; r < n_rows; ++r) {
+            const int c = rw[r];
+            if (c >= 0) atomicMin(&owner[c], key);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fl_keep(const int32_t *__restrict__ n_seeds, int32_t cap_seeds, int32_t n_rows,
+        const int32_t *__restrict__ rows, int32_t *__restrict__ status, const int32_t *__restrict__ ndf,
+        const unsigned long long *__restrict__ owner) {
+    int T = *n_seeds;
+    if (T > cap_seeds) T = cap_seeds;
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+        if (status[i] != TPC_FIT_OK) continue;
+        const unsigned long long key = track_key(n_rows, ndf[i], i);
+        const int32_t *rw = rows + (size_t)i * n_rows;
+        int owned = 0;
+        for (int r = 0; r < n_rows; ++r) {
+            const int c = rw[r];
+            if (c >= 0) owned += owner[c] == key;
+        }
+        if (2 * owned < (ndf[i] + 5) / 2) status[i] = TPC_FOLLOW_DUPLICATE;
+    }
+}
+
+int grid_for(int64_t items) {
+    int64_t b = (items + TPC_BLOCK - 1) / TPC_BLOCK;
+    if (b > 8192) b = 8192;
+    return b < 1 ? 1 : (int)b;
+}
+
+}  // namespace
+
+size_t follow_ws_layout(void *ws, int64_t N, int64_t NR, void *out) {
+    WsCarver w(ws);
+    FlIndex X;
+    X.grid = w.take<float2>(NR > 0 ? NR : 1);
+    X.cstart = w.take<int32_t>(N + NR + 1);
+    X.cur = w.take<int32_t>(N + NR + 1);
+    X.syz = w.take<float2>(N > 0 ? N : 1);
+    X.sid = w.take<int32_t>(N > 0 ? N : 1);
+    X.owner = w.take<unsigned long long>(N > 0 ? N : 1);
+    if (out) *static_cast<FlIndex *>(out) = X;
+    return (w.off + 255) & ~size_t(255);
+}
+
+hipError_t launch_follow(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                         double gate, int32_t max_miss, int32_t *rows, const tpc_tracks *tr,
+                         void *ws, hipStream_t st) {
+    const tpc_config &c = ctx->cfg;
+    const int64_t NR = (int64_t)fr->n_frames * c.n_sectors * c.n_rows;
+    FlArgs A;
+    A.F = make_fit_args(ctx, fr, sd, nullptr);
+    A.F.out = *tr;
+    A.row_offsets = fr->row_offsets;
+    A.frame = sd->frame;
+    A.n_frames = fr->n_frames;
+    follow_ws_layout(ws, fr->n_clusters, NR, &A.X);
+    A.rows = rows;
+    A.kbz = -0.00299792458 * (double)c.bz;
+    A.gate = gate;
+    A.max_miss = max_miss;
+    hipLaunchKernelGGL(fl_index, dim3((unsigned)NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, fr->y,
+                       fr->z, A.X);
+    hipLaunchKernelGGL(fl_tracks, dim3(grid_for(sd->cap_seeds)), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(fl_owner_init, dim3(grid_for(fr->n_clusters)), dim3(TPC_BLOCK), 0, st, A.X.owner,
+                       fr->n_clusters);
+    hipLaunchKernelGGL(fl_claim, dim3(grid_for(sd->cap_seeds)), dim3(TPC_BLOCK), 0, st, sd->n_seeds,
+                       sd->cap_seeds, c.n_rows, rows, tr->status, tr->ndf, A.X.owner);
+    hipLaunchKernelGGL(fl_keep, dim3(grid_for(sd->cap_seeds)), dim3(TPC_BLOCK), 0, st, sd->n_seeds,
+                       sd->cap_seeds, c.n_rows, rows, tr->status, tr->ndf, A.X.owner);
+    return hipGetLastError();
+}

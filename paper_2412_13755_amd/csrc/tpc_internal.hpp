@@ -82,6 +82,11 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
                              const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status,
                              void *ws, int grid, int sort_fit, hipStream_t st);
 
+size_t follow_ws_layout(void *ws, int64_t N, int64_t NR, void *index_out);
+hipError_t launch_follow(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                         double gate, int32_t max_miss, int32_t *rows, const tpc_tracks *tr,
+                         void *ws, hipStream_t st);
+
 // launchers (return hipError_t of the last launch)
 hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32_t *up,
                              int32_t *dn, const NbWs &ws, hipStream_t st);

@@ -236,6 +236,26 @@ class Reco:
                                        ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return tracks
 
+    def follow(self, frames: DeviceFrames, seeds: Seeds, gate_chi2: float, max_miss: int,
+               rows: Optional[torch.Tensor] = None, tracks: Optional[Tracks] = None, ws=None):
+        """Track following of every seed and duplicate removal (tpc_track_follow).
+
+        Returns (rows [cap_seeds, n_rows] int32, Tracks); rows and tracks are
+        valid for the first n_seeds entries.
+        """
+        T = seeds.frame.numel()
+        if rows is None:
+            rows = torch.empty(T, self.cfg.n_rows, dtype=torch.int32, device=self.device)
+        tracks = self.alloc_tracks(seeds) if tracks is None else tracks
+        ws = self.workspace(frames) if ws is None else ws
+        prm = C.FollowParams(float(gate_chi2), int(max_miss))
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_track_follow(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
+                                         ctypes.byref(prm), rows.data_ptr(), ctypes.byref(tc),
+                                         ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return rows, tracks
+
     def chi2_sum(self, seeds: Seeds, tracks: Tracks, loss: Optional[torch.Tensor] = None, ws=None):
         """Sum of chi2 over successfully fitted tracks (device float scalar)."""
         loss = torch.empty((), dtype=torch.float32, device=self.device) if loss is None else loss

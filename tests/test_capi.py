@@ -28,7 +28,7 @@ def test_header_declares_the_path():
     names = declared_functions()
     for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
               "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
-              "tpc_status_string", "tpc_last_error"):
+              "tpc_track_follow", "tpc_status_string", "tpc_last_error"):
         assert n in names
 
 
@@ -92,6 +92,9 @@ def test_calls_reject_null_context_and_frames(capi):
                              0, None, None, None, 0, None) == capi.TPC_ERR_ARG
     assert L.tpc_chi2_sum(None, ctypes.byref(sd), ctypes.byref(tr), None, None, 0,
                           None) == capi.TPC_ERR_ARG
+    fp = capi.FollowParams(25.0, 3)
+    assert L.tpc_track_follow(None, ctypes.byref(fr), ctypes.byref(sd), ctypes.byref(fp), None,
+                              ctypes.byref(tr), None, 0, None) == capi.TPC_ERR_ARG
     n = ctypes.c_size_t()
     assert L.tpc_ckpt_bytes(None, ctypes.byref(sd), ctypes.byref(n)) == capi.TPC_ERR_ARG
     n = ctypes.c_size_t()

@@ -1,0 +1,163 @@
+"""GPU parity of track following (tpc_track_follow through the C-ABI) against
+the CPU oracle on the oracle's own seeds (the GPU seeds are checked to be the
+same, bit for bit).
+
+Every pickup and stop is a floating-point decision; the oracle reports for
+each track the smallest relative distance of any of them from its threshold
+(margin).  Tracks with margin >= 1e-6 must take exactly the oracle's clusters
+(rounding differences between the two are ~1e-12 relative); the few below may
+differ, and so may the duplicate flags of tracks sharing clusters with them.
+On the rest: duplicate flags equal, refit within the fit tolerances (1e-4 on
+parameters, 1e-3 on covariance and chi2).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import NB, MIN_HITS, FIT
+from tests import parity
+from tpcsynth import make_config, make_frames
+
+pytestmark = pytest.mark.gpu
+
+GATE = 25.0
+MAX_MISS = 3
+MARGIN = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu(fr, gate=GATE, max_miss=MAX_MISS, repeat=1):
+    import torch
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT),
+                "cuda:0")
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    outs = []
+    for _ in range(repeat):
+        rows, tr = reco.follow(dfr, seeds, gate, max_miss)
+        torch.cuda.synchronize()
+        T = int(seeds.n_seeds.item())
+        outs.append(dict(rows=rows[:T].cpu().numpy(), x=tr.x[:T].cpu().numpy(),
+                         par=tr.par[:T].cpu().numpy(), cov=tr.cov[:T].cpu().numpy(),
+                         chi2=tr.chi2[:T].cpu().numpy(), ndf=tr.ndf[:T].cpu().numpy(),
+                         status=tr.status[:T].cpu().numpy()))
+    assert int(seeds.status.item()) == 0
+    return seeds.to_numpy(), outs
+
+
+def _oracle(fr, gate=GATE, max_miss=MAX_MISS):
+    up, dn = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    sd = oracle.ca_seed(fr.row_offsets, up, dn, fr.n_sectors, fr.n_rows, MIN_HITS)
+    out = oracle.follow(sd, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows,
+                        gate=gate, max_miss=max_miss, **FIT)
+    return sd, out
+
+
+def compare_follow(g, r):
+    T = len(r["status"])
+    assert g["rows"].shape == r["rows"].shape
+    fragile = r["margin"] < MARGIN
+    same = np.all(g["rows"] == r["rows"], axis=1)
+    bad = ~same & ~fragile
+    assert not bad.any(), "%d tracks with robust decisions took other clusters (first %d)" % (
+        bad.sum(), np.nonzero(bad)[0][0])
+    assert fragile.sum() <= max(2, int(1e-3 * T)), "too many near-threshold tracks: %d" % fragile.sum()
+    # clusters of tracks whose decisions may differ: ownership around them may too
+    odd = np.nonzero(~same | fragile)[0]
+    touched = np.unique(np.concatenate([g["rows"][odd].ravel(), r["rows"][odd].ravel(), [-1]]))
+    touched = touched[touched >= 0]
+    affected = np.isin(g["rows"], touched).any(axis=1) | np.isin(r["rows"], touched).any(axis=1)
+    clean = same & ~fragile & ~affected
+    sg, sr = g["status"][clean], r["status"][clean]
+    # duplicate flags are integer decisions on identical cluster lists: exact
+    np.testing.assert_array_equal(sg == 4, sr == 4)
+    sub = lambda d: {k: np.asarray(v)[clean] for k, v in d.items() if k in parity_keys}
+    gg, rr = sub(g), sub(r)
+    gg["status"] = np.where(sg == 4, 0, sg)
+    rr["status"] = np.where(sr == 4, 0, sr)
+    st = parity.compare_fit(gg, rr)
+    st.update(tracks=T, fragile=int(fragile.sum()), affected=int((~clean).sum()),
+              kept=int((r["status"] == 0).sum()), duplicates=int((r["status"] == 4).sum()),
+              hits_kept=int((r["rows"][r["status"] == 0] >= 0).sum()))
+    return st
+
+
+parity_keys = ("x", "par", "cov", "chi2", "ndf", "status")
+
+
+def check(fr, label, **kw):
+    print("[follow] %s: N=%d" % (label, fr.n_clusters), flush=True)
+    gs, (g,) = _gpu(fr, **kw)
+    rs, r = _oracle(fr, **kw)
+    parity.assert_seeds_equal(gs, rs)
+    st = compare_follow(g, r)
+    print("[follow] %s: %s" % (label, st), flush=True)
+    return st
+
+
+def test_follow_full_tpc_event(torch_dev):
+    st = check(make_config(1), "full-tpc-event-1e4")
+    assert st["duplicates"] > 1000 and st["kept"] > 10000
+
+
+def test_follow_uneven_frames_with_inefficiency(torch_dev):
+    st = check(make_config(3, scale=0.02, hit_eff=0.97), "batched-64-uneven x0.02, 3% missing")
+    assert st["duplicates"] > st["kept"] // 2
+
+
+def test_follow_single_sector_and_dense_rows(torch_dev):
+    check(make_config(0, hit_eff=0.9), "single-sector-200, 10% missing")
+    fr = make_frames(n_sectors=36, n_rows=48, tracks_per_frame=(6500,), seed=7,
+                     phi_range=(0.03, 0.32), looper_frac=0.05, trunc_frac=0.3, noise_frac=0.1)
+    counts = np.diff(fr.row_offsets)
+    assert counts.max() > 1024, "a row with several scan chunks in the cell index"
+    check(fr, "dense rows")
+
+
+def test_follow_zero_gate_and_no_gaps(torch_dev):
+    fr = make_config(0)
+    st = check(fr, "gate 0", gate=0.0, max_miss=0)
+    assert st["duplicates"] == 0
+    check(fr, "max_miss 0", max_miss=0)
+
+
+def test_follow_non_finite_clusters(torch_dev):
+    fr = make_config(0, hit_eff=0.95)
+    y, z = fr.y.copy(), fr.z.copy()
+    rng = np.random.default_rng(3)
+    bad = rng.choice(fr.n_clusters, 40, replace=False)
+    y[bad[:15]] = np.nan
+    z[bad[15:30]] = np.inf
+    y[bad[30:]] = -np.inf
+    fr.y, fr.z = y, z
+    check(fr, "non-finite clusters")
+
+
+def test_follow_repeat_is_bit_identical(torch_dev):
+    fr = make_config(1, scale=0.2, hit_eff=0.97)
+    _, (a, b) = _gpu(fr, repeat=2)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_follow_without_seeds(torch_dev):
+    import torch
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    fr = make_frames(n_sectors=1, tracks_per_frame=(1,), seed=1, phi_range=(2.0, 2.1))
+    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=1, min_hits=MIN_HITS, **NB, **FIT), "cuda:0")
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    rows = torch.full((seeds.frame.numel(), fr.n_rows), -7, dtype=torch.int32, device="cuda:0")
+    reco.follow(dfr, seeds, GATE, MAX_MISS, rows=rows)
+    torch.cuda.synchronize()
+    assert int(seeds.n_seeds.item()) == 0
+    assert bool((rows == -7).all())
