@@ -16,6 +16,10 @@ Extra legs, reported beside the headline value:
            replayed as a graph
   adjoint  10^5 tracks with an injected distortion map: full gradient
            evaluations per second (fit with checkpoints + chi2 sum + adjoint)
+  follow   track following after the fit on the headline workload: every seed
+           prolonged with chi2-gated cluster pickup (gate 25, up to 3 empty
+           rows crossed), refitted, duplicates removed; the oracle is timed
+           on the same seeds
   copy     a 1 GiB device copy (reference for the HBM traffic counters; run
            alone with --legs copy)
   stages   the three stage calls on the headline workload, --steps times,
@@ -54,6 +58,7 @@ B_SEED_PER_SEED = 16           # write offset, frame, sector, first row
 B_FIT_PER_HIT = 8              # read the hit's y, z
 B_FIT_PER_TRACK = 24 + 96      # read seed record; write 24 words
 FLOP_FIT_PER_HIT = 300         # helix step ~35, Jacobian ~30, F C F^T ~110, update ~125
+FOLLOW_GATE, FOLLOW_MAX_MISS = 25.0, 3
 
 
 def parse():
@@ -61,7 +66,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint")
+    ap.add_argument("--legs", default="main,batched,adjoint,follow")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--stages-workload", type=int, default=1,
@@ -280,6 +285,66 @@ def leg_adjoint(args):
             "tracks_per_s": round(T / ms * 1e3, 1), "ckpt_rows": reco.cfg.ckpt_rows}
 
 
+def leg_follow(args, with_cpu=True):
+    """tpc_track_follow on the headline workload's seeds, timed with HIP events
+    on the launch stream; the oracle's following timed on the same seeds."""
+    import torch
+    from tpcsynth import make_config
+    fr = make_config(1)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    ws = reco.workspace(dfr)
+    up, dn = reco.neighbours(dfr, ws=ws)
+    seeds = reco.seed(dfr, up, dn, ws=ws)
+    rows, tr = reco.follow(dfr, seeds, FOLLOW_GATE, FOLLOW_MAX_MISS, ws=ws)
+    torch.cuda.synchronize()
+    T, H = int(seeds.n_seeds.item()), int(seeds.n_hits.item())
+    stream = torch.cuda.current_stream()
+    steps = max(5, args.steps)
+    for _ in range(2):
+        reco.follow(dfr, seeds, FOLLOW_GATE, FOLLOW_MAX_MISS, rows, tr, ws)
+    evs = []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        reco.follow(dfr, seeds, FOLLOW_GATE, FOLLOW_MAX_MISS, rows, tr, ws)
+        e[1].record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    st = tr.status[:T].cpu().numpy()
+    rw = rows[:T].cpu().numpy()
+    final_hits = int((rw >= 0).sum())
+    kept_hits = int((rw[st == 0] >= 0).sum())
+    # seed fit over the seed hits, outward pass and refit over the final hits
+    flops = FLOP_FIT_PER_HIT * (H + 2 * final_hits)
+    achieved = flops / (ms * 1e-3) / 1e12
+    res = {"workload": fr.meta["name"], "clusters": dfr.n_clusters, "seeds": T, "seed_hits": H,
+           "gate_chi2": FOLLOW_GATE, "max_miss": FOLLOW_MAX_MISS,
+           "kept": int((st == 0).sum()), "duplicates": int((st == 4).sum()),
+           "hits_kept": kept_hits, "ms": round(ms, 5), "seeds_per_s": round(T / ms * 1e3, 1),
+           "M_clusters_per_s": round(dfr.n_clusters / ms / 1e3, 3),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
+                        "algorithmic_flops": int(flops),
+                        "calls": "fl_index, fl_tracks, fl_owner_init, fl_claim, fl_keep"}}
+    if with_cpu:
+        import oracle
+        oracle.set_threads(len(os.sched_getaffinity(0)))
+        up_r, dn_r = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+        sd = oracle.ca_seed(fr.row_offsets, up_r, dn_r, fr.n_sectors, fr.n_rows, MIN_HITS)
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            oracle.follow(sd, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows,
+                          gate=FOLLOW_GATE, max_miss=FOLLOW_MAX_MISS, **FIT)
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
+        res["cpu_oracle"] = {"ms": round(t * 1e3, 3), "cores": int(oracle.max_threads()),
+                             "seeds_per_s": round(T / t, 1)}
+    return res
+
+
 def leg_copy(args):
     """A plain device copy of known size (calibrates the HBM traffic counters)."""
     import torch
@@ -335,6 +400,9 @@ def main():
     if legs == {"stages"}:
         print(json.dumps({"stages": leg_stages(args)}), flush=True)
         return
+    if legs == {"follow"}:
+        print(json.dumps({"follow": leg_follow(args, not args.no_cpu)}), flush=True)
+        return
     main_res, fr = leg_main(args)
     out = {
         "metric": "M clusters/s through CA seed+Kalman fit (plain vs batched); adjoint grads/s",
@@ -348,6 +416,8 @@ def main():
         out["batched"] = leg_batched(args)
     if "adjoint" in legs:
         out["adjoint"] = leg_adjoint(args)
+    if "follow" in legs:
+        out["follow"] = leg_follow(args, not args.no_cpu)
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:
