@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpc_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "rans_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
     """Compile ``liboracle.so`` with gcc (no fused multiply-add contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *GCC_FLAGS, *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -50,7 +51,7 @@ class FollowParams(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
@@ -69,6 +70,15 @@ def lib():
                                     ctypes.POINTER(FitParams), ctypes.POINTER(FollowParams),
                                     P, P, P, P, P, P, P, P]
         L.oracle_follow.restype = None
+        u32, i64, sz = ctypes.c_uint32, ctypes.c_int64, ctypes.c_size_t
+        L.oracle_rans_freqs.argtypes = [P, u32, ctypes.c_uint64, u32, P]
+        L.oracle_rans_freqs.restype = i64
+        L.oracle_rans_bound.argtypes = [i64, u32, u32]
+        L.oracle_rans_bound.restype = sz
+        L.oracle_rans_encode.argtypes = [P, i64, u32, u32, u32, P, sz, ctypes.POINTER(sz)]
+        L.oracle_rans_encode.restype = i32
+        L.oracle_rans_decode.argtypes = [P, sz, P, i64, ctypes.POINTER(i64)]
+        L.oracle_rans_decode.restype = i32
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -187,6 +197,43 @@ def follow(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, gate, ma
                         _p(out["x"]), _p(out["par"]), _p(out["cov"]), _p(out["chi2"]),
                         _p(out["ndf"]), _p(out["status"]), _p(out["margin"]))
     return out
+
+
+RANS_MAX_RANGE = 1 << 20
+
+
+def rans_freqs(counts, n, L):
+    """Scaled frequencies (sum 2^L) of a symbol histogram; None if more than 2^L symbols occur."""
+    c = np.ascontiguousarray(counts, dtype=np.uint32)
+    f = np.empty_like(c)
+    d = lib().oracle_rans_freqs(_p(c), c.size, int(n), int(L), _p(f))
+    return None if d < 0 else f
+
+
+def rans_encode(sym, L, B, max_range=RANS_MAX_RANGE) -> bytes:
+    """rANS stream of an int32 array (64 interleaved coders per block of B symbols)."""
+    s = np.ascontiguousarray(sym, dtype=np.int32)
+    lo, hi = (int(s.min()), int(s.max())) if s.size else (0, -1)
+    R = hi - lo + 1 if s.size else 0
+    cap = int(lib().oracle_rans_bound(s.size, min(max(R, 0), max_range), int(B))) if R <= max_range else 64
+    out = np.empty(max(cap, 64), np.uint8)
+    size = ctypes.c_size_t()
+    st = lib().oracle_rans_encode(_p(s), s.size, int(L), int(B), int(max_range), _p(out), out.size,
+                                  ctypes.byref(size))
+    if st != 0:
+        raise ValueError("oracle rANS encode failed (%d)" % st)
+    return out[:size.value].tobytes()
+
+
+def rans_decode(stream: bytes) -> np.ndarray:
+    buf = np.frombuffer(stream, dtype=np.uint8)
+    n = ctypes.c_int64()
+    lib().oracle_rans_decode(_p(np.ascontiguousarray(buf)), buf.size, None, 0, ctypes.byref(n))
+    out = np.empty(max(n.value, 1), np.int32)
+    st = lib().oracle_rans_decode(_p(np.ascontiguousarray(buf)), buf.size, _p(out), out.size, ctypes.byref(n))
+    if st != 0:
+        raise ValueError("oracle rANS decode failed")
+    return out[:n.value].copy()
 
 
 def unpack_cov(c15: np.ndarray) -> np.ndarray:

@@ -45,4 +45,12 @@ void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits
                    const oracle_fit_params *prm, const oracle_follow_params *fp,
                    int32_t *rows, double *x_out, double *par, double *cov, double *chi2,
                    int32_t *ndf, int32_t *status, double *margin);
+
+/* rANS coder of integer arrays (rans_oracle.c) */
+#include <stddef.h>
+int64_t oracle_rans_freqs(const uint32_t *c, uint32_t R, uint64_t n, uint32_t L, uint32_t *f);
+size_t oracle_rans_bound(int64_t n, uint32_t R, uint32_t B);
+int32_t oracle_rans_encode(const int32_t *sym, int64_t n, uint32_t L, uint32_t B, uint32_t max_range,
+                           uint8_t *out, size_t cap, size_t *size);
+int32_t oracle_rans_decode(const uint8_t *in, size_t size, int32_t *out, int64_t cap, int64_t *n_out);
 #endif
