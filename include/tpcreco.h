@@ -272,6 +272,52 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
                             int32_t *rows, tpc_tracks *tracks, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* Entropy coding of a time frame's integer arrays (Sec. 4.3: every flat
+ * integer array is coded on its own with range asymmetric numeral systems,
+ * the symbol distribution counted for each frame, several coders
+ * interleaved on one stream).  This library's coder:
+ *   frequencies  counts c_s over the array's range [lo, hi] (R = hi - lo + 1
+ *                <= 2^20 entries, D symbols present, D <= 2^L), scaled to
+ *                M = 2^L: f_s = floor(c_s (M - D) / n) + 1 where c_s > 0,
+ *                else 0; the shortfall M - sum f goes to the most frequent
+ *                symbol (the smallest on ties);
+ *   coder        32-bit state in [2^16, 2^32), 16-bit words: to code s, if
+ *                x >= f_s 2^(32-L) emit x mod 2^16 and shift x right by 16,
+ *                then x <- floor(x / f_s) 2^L + (x mod f_s) + cum_s;
+ *   interleaving blocks of B symbols; symbol 64 j + k of a block belongs to
+ *                coder k (64 coders starting at 2^16); a block is coded
+ *                backwards (j, then k, descending) onto one word stack;
+ *   stream       little-endian: u32 magic 0x534E4152, u32 version 1, u64 n,
+ *                i32 lo, u32 R, u32 L, u32 B, u32 blocks, u32 0; u32 f[R];
+ *                u32 word_start[blocks + 1] (in words); u32 state[blocks][64];
+ *                u16 words, each block's stack last pushed first.
+ * A decoder runs each block forwards: slot = x mod 2^L, s with
+ * cum_s <= slot < cum_s + f_s, x <- f_s (x >> L) + slot - cum_s, and while
+ * x < 2^16, x <- x 2^16 + next word. */
+#define TPC_RANS_LANES 64
+typedef struct tpc_rans_params {
+    int32_t scale_bits;       /* L, 1..16 */
+    int32_t block_symbols;    /* B, a multiple of 64, 64..2^24 */
+} tpc_rans_params;
+
+/* Workspace bytes of tpc_rans_encode for n symbols (host call). */
+tpc_status tpc_rans_workspace_bytes(int64_t n, const tpc_rans_params *params, size_t *bytes);
+
+/* Largest stream for n symbols whose range is at most `range` (host call):
+ * 40 + 4 range + 4 (blocks + 1) + 256 blocks + 2 n bytes. */
+tpc_status tpc_rans_max_bytes(int64_t n, int64_t range, const tpc_rans_params *params, size_t *bytes);
+
+/* Codes symbols[0..n) (device int32, 0 <= n < 2^31) into out (device, 4-byte
+ * aligned, out_cap bytes).  *out_size (device u64) receives the stream's
+ * exact size.  *dev_status (device int32) receives TPC_OK, TPC_ERR_ARG (range
+ * wider than 2^20 or more than 2^L distinct symbols; nothing written) or
+ * TPC_ERR_CAPACITY (the stream is larger than out_cap; nothing written,
+ * *out_size says how large).  The output is identical for identical input
+ * (integer arithmetic throughout).  ws: tpc_rans_workspace_bytes() bytes. */
+tpc_status tpc_rans_encode(const int32_t *symbols, int64_t n, const tpc_rans_params *params,
+                           void *out, size_t out_cap, uint64_t *out_size, int32_t *dev_status,
+                           void *ws, size_t ws_bytes, void *stream);
+
 /* Workgroups the persistent kernel can keep resident on the context's device. */
 int32_t tpc_persistent_grid(const tpc_context *ctx);
 

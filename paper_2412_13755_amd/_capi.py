@@ -65,6 +65,10 @@ class FollowParams(ctypes.Structure):
     _fields_ = [("gate_chi2", f32), ("max_miss", i32)]
 
 
+class RansParams(ctypes.Structure):
+    _fields_ = [("scale_bits", i32), ("block_symbols", i32)]
+
+
 TPC_MODE_STAGED = 0
 TPC_MODE_PERSISTENT = 1
 TPC_STAGE_PERSISTENT = 16
@@ -100,6 +104,12 @@ SIGNATURES = {
     "tpc_track_follow": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
                                ctypes.POINTER(FollowParams), P, ctypes.POINTER(TracksC), P,
                                ctypes.c_size_t, P]),
+    "tpc_rans_workspace_bytes": (i32, [ctypes.c_int64, ctypes.POINTER(RansParams),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "tpc_rans_max_bytes": (i32, [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(RansParams),
+                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "tpc_rans_encode": (i32, [P, ctypes.c_int64, ctypes.POINTER(RansParams), P, ctypes.c_size_t, P, P, P,
+                              ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),

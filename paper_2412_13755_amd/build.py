@@ -28,6 +28,7 @@ SOURCES = {
     "tpc_adjoint.hip": [],
     "tpc_persistent.hip": [],
     "tpc_follow.hip": [],
+    "tpc_rans.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

@@ -338,6 +338,54 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *fr, const 
     return e == hipSuccess ? TPC_OK : hip_fail(e, "follow kernels");
 }
 
+static tpc_status check_rans_params(const tpc_rans_params *p) {
+    if (!p) return fail(TPC_ERR_ARG, "null rANS parameters");
+    if (p->scale_bits < 1 || p->scale_bits > 16) return fail(TPC_ERR_ARG, "scale_bits outside 1..16");
+    if (p->block_symbols < TPC_RANS_LANES || p->block_symbols % TPC_RANS_LANES || p->block_symbols > (1 << 24))
+        return fail(TPC_ERR_ARG, "block_symbols must be a multiple of 64 in 64..2^24");
+    return TPC_OK;
+}
+
+tpc_status tpc_rans_workspace_bytes(int64_t n, const tpc_rans_params *p, size_t *bytes) {
+    g_err[0] = 0;
+    tpc_status s = check_rans_params(p);
+    if (s) return s;
+    if (!bytes) return fail(TPC_ERR_ARG, "null bytes");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(TPC_ERR_ARG, "n outside 0..2^31-1");
+    *bytes = rans_ws_layout(nullptr, n, p->block_symbols, nullptr);
+    return TPC_OK;
+}
+
+tpc_status tpc_rans_max_bytes(int64_t n, int64_t range, const tpc_rans_params *p, size_t *bytes) {
+    g_err[0] = 0;
+    tpc_status s = check_rans_params(p);
+    if (s) return s;
+    if (!bytes) return fail(TPC_ERR_ARG, "null bytes");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(TPC_ERR_ARG, "n outside 0..2^31-1");
+    if (range < 0 || range > TPC_RANS_MAX_RANGE) return fail(TPC_ERR_ARG, "range outside 0..2^20");
+    const int64_t nb = n > 0 ? (n + p->block_symbols - 1) / p->block_symbols : 0;
+    *bytes = (size_t)(40 + 4 * (n > 0 ? range : 0) + 4 * (nb + 1) + 4 * TPC_RANS_LANES * nb + 2 * n);
+    return TPC_OK;
+}
+
+tpc_status tpc_rans_encode(const int32_t *sym, int64_t n, const tpc_rans_params *p, void *out,
+                           size_t out_cap, uint64_t *out_size, int32_t *dev_status, void *ws,
+                           size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_rans_params(p);
+    if (s) return s;
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(TPC_ERR_ARG, "n outside 0..2^31-1");
+    if (n > 0 && !sym) return fail(TPC_ERR_ARG, "null symbols");
+    if (!out || !out_size || !dev_status) return fail(TPC_ERR_ARG, "null output, size or status");
+    if (((uintptr_t)out & 3) != 0) return fail(TPC_ERR_ARG, "output not 4-byte aligned");
+    if ((s = check_ws(ws, ws_bytes, rans_ws_layout(nullptr, n, p->block_symbols, nullptr)))) return s;
+    RansWs W;
+    rans_ws_layout(ws, n, p->block_symbols, &W);
+    hipError_t e = launch_rans_encode(sym, n, p->scale_bits, p->block_symbols, (uint8_t *)out,
+                                      (uint64_t)out_cap, out_size, dev_status, W, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "rANS kernels");
+}
+
 int32_t tpc_persistent_grid(const tpc_context *ctx) { return ctx ? ctx->persist_grid : 0; }
 
 }  // extern "C"

@@ -83,6 +83,20 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
                              void *ws, int grid, int sort_fit, hipStream_t st);
 
 size_t follow_ws_layout(void *ws, int64_t N, int64_t NR, void *index_out);
+
+#define TPC_RANS_MAX_RANGE (1 << 20)   // widest symbol range max - min + 1 of one array
+struct RansWs {
+    int32_t *mm;                 // min, max, status
+    uint32_t *counts;            // [TPC_RANS_MAX_RANGE] histogram
+    uint2 *fc;                   // [TPC_RANS_MAX_RANGE] (frequency, cumulative frequency)
+    uint32_t *wcount, *wstart;   // [nb], [nb + 1] words per coding block, their prefix
+    uint32_t *states;            // [nb][64] final coder states
+    uint16_t *scratch;           // [nb][B] word stack of each block
+};
+size_t rans_ws_layout(void *ws, int64_t n, int32_t B, RansWs *out);
+hipError_t launch_rans_encode(const int32_t *sym, int64_t n, int32_t L, int32_t B, uint8_t *out,
+                              uint64_t cap, uint64_t *out_size, int32_t *dev_status, const RansWs &W,
+                              hipStream_t st);
 hipError_t launch_follow(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
                          double gate, int32_t max_miss, int32_t *rows, const tpc_tracks *tr,
                          void *ws, hipStream_t st);

@@ -1,0 +1,361 @@
+// rANS entropy coding of an array of 32-bit integers (gfx950): the
+// compression stage of a time frame, where every flat integer array is coded
+// on its own with frequencies counted for that frame (Sec. 4.3).
+//
+//  rs_init      min / max / status words
+//  rs_minmax    grid reduction of the symbol range
+//  rs_clear     zero the histogram over the range (fails if wider than 2^20)
+//  rs_hist      histogram: LDS-private per workgroup when the range fits
+//               (8192 bins), global atomics otherwise
+//  rs_freq      one workgroup: number of symbols present, most frequent
+//               symbol, scaled frequencies (integer arithmetic, exactly the
+//               stated rule), their exclusive scan
+//  rs_encode    one wavefront per block of B symbols, lane k = coder k; the
+//               block is coded backwards round by round; the words a round
+//               emits are placed by ballot and prefix popcount in the order
+//               coders 63 .. 0 push them, into a per-block scratch stack
+//  rs_scan      exclusive scan of the blocks' word counts
+//  rs_pack      the stream: header, frequency table, block word offsets,
+//               final coder states, every block's stack reversed; nothing is
+//               written and the status says TPC_ERR_CAPACITY when the
+//               stream (its exact size is reported) does not fit
+#include "tpc_internal.hpp"
+
+#define RS_LANES 64
+#define RS_HEAD 40
+#define RS_LDS_BINS 8192
+#define RS_MAGIC 0x534E4152u
+
+namespace {
+
+struct RsArgs {
+    const int32_t *sym;
+    int64_t n;
+    int32_t L, B, nb;
+    int32_t *mm;           // [0] min, [1] max, [2] status (device)
+    uint32_t *counts;      // [TPC_RANS_MAX_RANGE]
+    uint2 *fc;             // [TPC_RANS_MAX_RANGE] (frequency, cumulative)
+    uint32_t *wcount;      // [nb] words of each block
+    uint32_t *wstart;      // [nb + 1]
+    uint32_t *states;      // [nb][64]
+    uint16_t *scratch;     // [nb][B] each block's word stack, push order
+    uint8_t *out;
+    uint64_t cap;
+    uint64_t *out_size;
+    int32_t *dev_status;
+};
+
+// Range R = max - min + 1 (0 for no symbols).
+__device__ inline int64_t rs_range(const RsArgs &A) {
+    return A.n > 0 ? (int64_t)A.mm[1] - (int64_t)A.mm[0] + 1 : 0;
+}
+
+__global__ void rs_init(RsArgs A) {
+    if (threadIdx.x == 0) {
+        A.mm[0] = 0x7fffffff;
+        A.mm[1] = (int32_t)0x80000000;
+        A.mm[2] = TPC_OK;
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsArgs A) {
+    __shared__ int sh[2][TPC_BLOCK / TPC_WAVE];
+    int lo = 0x7fffffff, hi = (int)0x80000000;
+    for (int64_t i = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * TPC_BLOCK) {
+        const int v = A.sym[i];
+        lo = v < lo ? v : lo;
+        hi = v > hi ? v : hi;
+    }
+#pragma unroll
+    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) {
+        const int a = __shfl_xor(lo, d, TPC_WAVE), b = __shfl_xor(hi, d, TPC_WAVE);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    const int wid = threadIdx.x / TPC_WAVE;
+    if ((threadIdx.x & (TPC_WAVE - 1)) == 0) {
+        sh[0][wid] = lo;
+        sh[1][wid] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w) {
+            lo = sh[0][w] < lo ? sh[0][w] : lo;
+            hi = sh[1][w] > hi ? sh[1][w] : hi;
+        }
+        atomicMin(&A.mm[0], lo);
+        atomicMax(&A.mm[1], hi);
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_clear(RsArgs A) {
+    const int64_t R = rs_range(A);
+    if (R > TPC_RANS_MAX_RANGE) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) A.mm[2] = TPC_ERR_ARG;
+        return;
+    }
+    for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < R; s += (int64_t)gridDim.x * TPC_BLOCK)
+        A.counts[s] = 0;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_hist(RsArgs A) {
+    __shared__ uint32_t h[RS_LDS_BINS];
+    const int64_t R = rs_range(A);
+    if (R > TPC_RANS_MAX_RANGE) return;
+    const int lo = A.mm[0];
+    const bool local = R <= RS_LDS_BINS;
+    if (local) {
+        for (int s = threadIdx.x; s < R; s += TPC_BLOCK) h[s] = 0;
+        __syncthreads();
+    }
+    for (int64_t i = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * TPC_BLOCK) {
+        const uint32_t s = (uint32_t)((int64_t)A.sym[i] - lo);
+        if (local) atomicAdd(&h[s], 1u);
+        else atomicAdd(&A.counts[s], 1u);
+    }
+    if (local) {
+        __syncthreads();
+        for (int s = threadIdx.x; s < R; s += TPC_BLOCK)
+            if (h[s]) atomicAdd(&A.counts[s], h[s]);
+    }
+}
+
+// Block-wide reductions for the 1024-thread frequency kernel.
+#define RS_FREQ_THREADS 1024
+__device__ inline long long rs_block_sum(long long v, long long *sh) {
+#pragma unroll
+    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, TPC_WAVE);
+    const int wid = threadIdx.x / TPC_WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (TPC_WAVE - 1)) == 0) sh[wid] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int w = 0; w < RS_FREQ_THREADS / TPC_WAVE; ++w) t += sh[w];
+    return t;
+}
+
+// key = count << 32 | (2^32 - 1 - s): the largest key is the most frequent
+// symbol, the smallest s among equals
+__device__ inline unsigned long long rs_block_max(unsigned long long v, unsigned long long *sh) {
+#pragma unroll
+    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) {
+        const unsigned long long o = __shfl_xor(v, d, TPC_WAVE);
+        v = o > v ? o : v;
+    }
+    const int wid = threadIdx.x / TPC_WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (TPC_WAVE - 1)) == 0) sh[wid] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < RS_FREQ_THREADS / TPC_WAVE; ++w) t = sh[w] > t ? sh[w] : t;
+    return t;
+}
+
+__global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsArgs A) {
+    __shared__ long long sh[RS_FREQ_THREADS / TPC_WAVE];
+    __shared__ unsigned long long shk[RS_FREQ_THREADS / TPC_WAVE];
+    __shared__ int scan_sh[RS_FREQ_THREADS / TPC_WAVE];
+    if (A.mm[2] != TPC_OK) return;
+    const int64_t R = rs_range(A);
+    if (R == 0) return;
+    const uint64_t M = 1ull << A.L;
+    long long d = 0;
+    unsigned long long best = 0;
+    for (int64_t s = threadIdx.x; s < R; s += RS_FREQ_THREADS) {
+        const uint32_t c = A.counts[s];
+        d += c > 0;
+        const unsigned long long key = ((unsigned long long)c << 32) | (0xffffffffull - (uint64_t)s);
+        best = key > best ? key : best;
+    }
+    const long long D = rs_block_sum(d, sh);
+    best = rs_block_max(best, shk);
+    if ((uint64_t)D > M) {
+        if (threadIdx.x == 0) A.mm[2] = TPC_ERR_ARG;
+        return;
+    }
+    const int64_t sbest = (int64_t)(0xffffffffull - (best & 0xffffffffull));
+    long long part = 0;
+    for (int64_t s = threadIdx.x; s < R; s += RS_FREQ_THREADS) {
+        const uint32_t c = A.counts[s];
+        const uint32_t f = c ? (uint32_t)((uint64_t)c * (M - (uint64_t)D) / (uint64_t)A.n + 1) : 0u;
+        A.fc[s].x = f;
+        part += f;
+    }
+    const long long sum = rs_block_sum(part, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) A.fc[sbest].x += (uint32_t)((long long)M - sum);
+    __threadfence_block();
+    __syncthreads();
+    // exclusive scan of the frequencies in chunks of the workgroup
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < R; c0 += RS_FREQ_THREADS) {
+        const int64_t s = c0 + threadIdx.x;
+        const int f = s < R ? (int)A.fc[s].x : 0;
+        // block_exclusive_scan covers TPC_BLOCK threads: scan four quarters
+        const int lane = threadIdx.x & (TPC_WAVE - 1), wid = threadIdx.x / TPC_WAVE;
+        int inc = wave_inclusive_scan(f);
+        if (lane == TPC_WAVE - 1) scan_sh[wid] = inc;
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int w = 0; w < RS_FREQ_THREADS / TPC_WAVE; ++w) {
+            const int v = scan_sh[w];
+            before += w < wid ? v : 0;
+            tot += v;
+        }
+        __syncthreads();
+        if (s < R) A.fc[s].y = carry + (uint32_t)(before + inc - f);
+        carry += (uint32_t)tot;
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_encode(RsArgs A) {
+    if (A.mm[2] != TPC_OK) return;
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    const int b = blockIdx.x * (TPC_BLOCK / TPC_WAVE) + threadIdx.x / TPC_WAVE;
+    if (b >= A.nb) return;
+    const int lo = A.mm[0];
+    const int L = A.L;
+    const int64_t i0 = (int64_t)b * A.B;
+    const int64_t i1 = i0 + A.B < A.n ? i0 + A.B : A.n;
+    const int rounds = (int)((i1 - i0 + RS_LANES - 1) / RS_LANES);
+    uint16_t *stack = A.scratch + (size_t)b * A.B;
+    uint32_t x = 1u << 16;
+    uint32_t top = 0;
+    for (int j = rounds - 1; j >= 0; --j) {
+        const int64_t i = i0 + (int64_t)j * RS_LANES + lane;
+        const bool active = i < i1;
+        const uint32_t s = active ? (uint32_t)((int64_t)A.sym[i] - lo) : 0u;
+        const uint2 fc = active ? A.fc[s] : make_uint2(1u, 0u);
+        const bool emit = active && (uint64_t)x >= ((uint64_t)fc.x << (32 - L));
+        const unsigned long long mask = __ballot(emit);
+        if (emit) {
+            // coders above this one push first
+            const int rank = __popcll(lane == 63 ? 0ull : mask >> (lane + 1));
+            stack[top + rank] = (uint16_t)(x & 0xffffu);
+            x >>= 16;
+        }
+        top += (uint32_t)__popcll(mask);
+        if (active) {
+            const uint32_t q = x / fc.x;
+            x = (q << L) + (x - q * fc.x) + fc.y;
+        }
+    }
+    A.states[(size_t)b * RS_LANES + lane] = x;
+    if (lane == 0) A.wcount[b] = top;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_scan(RsArgs A) {
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < A.nb; c0 += TPC_BLOCK) {
+        const int b = c0 + threadIdx.x;
+        const int v = (b < A.nb && A.mm[2] == TPC_OK) ? (int)A.wcount[b] : 0;
+        int tot;
+        const int ex = block_exclusive_scan(v, sh, &tot);
+        if (b < A.nb) A.wstart[b] = carry + (uint32_t)ex;
+        carry += (uint32_t)tot;
+    }
+    if (threadIdx.x == 0) A.wstart[A.nb] = carry;
+}
+
+__device__ inline void put32(uint8_t *p, uint32_t v) { *reinterpret_cast<uint32_t *>(p) = v; }
+
+// Grid: one workgroup per coding block (at least one).
+__global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsArgs A) {
+    const int st0 = A.mm[2];
+    const int64_t R = st0 == TPC_OK ? rs_range(A) : 0;
+    const uint64_t words = A.wstart[A.nb];
+    const uint64_t head = RS_HEAD + 4ull * R + 4ull * (A.nb + 1) + 4ull * RS_LANES * A.nb;
+    const uint64_t total = head + 2ull * words;
+    const bool fits = st0 == TPC_OK && total <= A.cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *A.out_size = st0 == TPC_OK ? total : 0ull;
+        *A.dev_status = st0 != TPC_OK ? st0 : (fits ? TPC_OK : TPC_ERR_CAPACITY);
+    }
+    if (!fits) return;
+    uint8_t *o = A.out;
+    const int G = gridDim.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        put32(o, RS_MAGIC);
+        put32(o + 4, 1u);
+        put32(o + 8, (uint32_t)((uint64_t)A.n & 0xffffffffu));
+        put32(o + 12, (uint32_t)((uint64_t)A.n >> 32));
+        put32(o + 16, (uint32_t)(A.n > 0 ? A.mm[0] : 0));
+        put32(o + 20, (uint32_t)R);
+        put32(o + 24, (uint32_t)A.L);
+        put32(o + 28, (uint32_t)A.B);
+        put32(o + 32, (uint32_t)A.nb);
+        put32(o + 36, 0u);
+    }
+    // frequency table, word offsets, states: spread over the grid
+    uint32_t *ft = reinterpret_cast<uint32_t *>(o + RS_HEAD);
+    for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < R; s += (int64_t)G * TPC_BLOCK) ft[s] = A.fc[s].x;
+    uint32_t *ws = ft + R;
+    for (int64_t b = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; b <= A.nb; b += (int64_t)G * TPC_BLOCK) ws[b] = A.wstart[b];
+    uint32_t *sts = ws + A.nb + 1;
+    for (int64_t q = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; q < (int64_t)A.nb * RS_LANES; q += (int64_t)G * TPC_BLOCK)
+        sts[q] = A.states[q];
+    // each block's stack, last pushed first
+    uint16_t *wo = reinterpret_cast<uint16_t *>(o + head);
+    for (int b = blockIdx.x; b < A.nb; b += G) {
+        const uint32_t top = A.wcount[b], base = A.wstart[b];
+        const uint16_t *stack = A.scratch + (size_t)b * A.B;
+        for (uint32_t w = threadIdx.x; w < top; w += TPC_BLOCK) wo[base + w] = stack[top - 1 - w];
+    }
+}
+
+int grid_over(int64_t items, int cap) {
+    int64_t b = (items + TPC_BLOCK - 1) / TPC_BLOCK;
+    if (b > cap) b = cap;
+    return b < 1 ? 1 : (int)b;
+}
+
+}  // namespace
+
+size_t rans_ws_layout(void *ws, int64_t n, int32_t B, RansWs *out) {
+    WsCarver w(ws);
+    const int64_t nb = n > 0 ? (n + B - 1) / B : 0;
+    RansWs r;
+    r.mm = w.take<int32_t>(4);
+    r.counts = w.take<uint32_t>(TPC_RANS_MAX_RANGE);
+    r.fc = w.take<uint2>(TPC_RANS_MAX_RANGE);
+    r.wcount = w.take<uint32_t>(nb > 0 ? nb : 1);
+    r.wstart = w.take<uint32_t>(nb + 1);
+    r.states = w.take<uint32_t>((nb > 0 ? nb : 1) * RS_LANES);
+    r.scratch = w.take<uint16_t>((size_t)(nb > 0 ? nb : 1) * B);
+    if (out) *out = r;
+    return (w.off + 255) & ~size_t(255);
+}
+
+hipError_t launch_rans_encode(const int32_t *sym, int64_t n, int32_t L, int32_t B, uint8_t *out,
+                              uint64_t cap, uint64_t *out_size, int32_t *dev_status, const RansWs &W,
+                              hipStream_t st) {
+    RsArgs A;
+    A.sym = sym;
+    A.n = n;
+    A.L = L;
+    A.B = B;
+    A.nb = (int32_t)(n > 0 ? (n + B - 1) / B : 0);
+    A.mm = W.mm;
+    A.counts = W.counts;
+    A.fc = W.fc;
+    A.wcount = W.wcount;
+    A.wstart = W.wstart;
+    A.states = W.states;
+    A.scratch = W.scratch;
+    A.out = out;
+    A.cap = cap;
+    A.out_size = out_size;
+    A.dev_status = dev_status;
+    const int gs = grid_over(n, 2048);
+    hipLaunchKernelGGL(rs_init, dim3(1), dim3(TPC_WAVE), 0, st, A);
+    hipLaunchKernelGGL(rs_minmax, dim3(gs), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rs_clear, dim3(grid_over(TPC_RANS_MAX_RANGE, 1024)), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rs_hist, dim3(gs), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rs_freq, dim3(1), dim3(RS_FREQ_THREADS), 0, st, A);
+    const int eb = (A.nb + TPC_BLOCK / TPC_WAVE - 1) / (TPC_BLOCK / TPC_WAVE);
+    if (eb > 0) hipLaunchKernelGGL(rs_encode, dim3(eb), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rs_scan, dim3(1), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rs_pack, dim3(A.nb > 0 ? (A.nb < 4096 ? A.nb : 4096) : 1), dim3(TPC_BLOCK), 0, st, A);
+    return hipGetLastError();
+}

@@ -345,6 +345,42 @@ class ReconstructGraph:
         return self.up, self.dn, self.seeds, self.tracks
 
 
+def rans_workspace(n: int, scale_bits: int, block_symbols: int, device="cuda:0") -> torch.Tensor:
+    prm = C.RansParams(int(scale_bits), int(block_symbols))
+    b = ctypes.c_size_t()
+    C.check(C.lib().tpc_rans_workspace_bytes(int(n), ctypes.byref(prm), ctypes.byref(b)))
+    return torch.empty(max(int(b.value), 1), dtype=torch.uint8, device=device)
+
+
+def rans_max_bytes(n: int, value_range: int, scale_bits: int, block_symbols: int) -> int:
+    prm = C.RansParams(int(scale_bits), int(block_symbols))
+    b = ctypes.c_size_t()
+    C.check(C.lib().tpc_rans_max_bytes(int(n), int(value_range), ctypes.byref(prm), ctypes.byref(b)))
+    return int(b.value)
+
+
+def rans_encode(symbols: torch.Tensor, scale_bits: int, block_symbols: int, out=None, ws=None,
+                out_size=None, status=None):
+    """tpc_rans_encode of a contiguous int32 device tensor.  Returns (out,
+    out_size, status): the uint8 stream buffer, the stream's size and the
+    device status (device tensors; nothing is synchronised)."""
+    if symbols.dtype != torch.int32 or not symbols.is_contiguous() or symbols.device.type != "cuda":
+        raise ValueError("symbols must be a contiguous int32 device tensor")
+    n = symbols.numel()
+    d = symbols.device
+    if out is None:
+        out = torch.empty(rans_max_bytes(n, 1 << 20, scale_bits, block_symbols), dtype=torch.uint8, device=d)
+    ws = rans_workspace(n, scale_bits, block_symbols, d) if ws is None else ws
+    out_size = torch.zeros(1, dtype=torch.int64, device=d) if out_size is None else out_size
+    status = torch.zeros(1, dtype=torch.int32, device=d) if status is None else status
+    prm = C.RansParams(int(scale_bits), int(block_symbols))
+    C.check(C.lib().tpc_rans_encode(symbols.data_ptr() if n else None, n, ctypes.byref(prm),
+                                    out.data_ptr(), out.numel(), out_size.data_ptr(),
+                                    status.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream_handle(d)))
+    return out, out_size, status
+
+
 class KalmanChi2(torch.autograd.Function):
     """loss = sum of fit chi2 over the (fixed) seeds, as a function of the
     [n_sectors, n_rows, 2] cluster correction map; backward runs the

@@ -28,7 +28,8 @@ def test_header_declares_the_path():
     names = declared_functions()
     for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
               "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
-              "tpc_track_follow", "tpc_status_string", "tpc_last_error"):
+              "tpc_track_follow", "tpc_rans_encode", "tpc_rans_workspace_bytes",
+              "tpc_rans_max_bytes", "tpc_status_string", "tpc_last_error"):
         assert n in names
 
 
@@ -99,6 +100,21 @@ def test_calls_reject_null_context_and_frames(capi):
     assert L.tpc_ckpt_bytes(None, ctypes.byref(sd), ctypes.byref(n)) == capi.TPC_ERR_ARG
     n = ctypes.c_size_t()
     assert L.tpc_workspace_bytes(None, ctypes.byref(fr), 1, ctypes.byref(n)) == capi.TPC_ERR_ARG
+
+
+def test_rans_host_checks(capi):
+    L = capi.lib()
+    n = ctypes.c_size_t()
+    for bits, blk in ((0, 64), (17, 64), (12, 100), (12, 0)):
+        p = capi.RansParams(bits, blk)
+        assert L.tpc_rans_workspace_bytes(1000, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
+    p = capi.RansParams(12, 4096)
+    assert L.tpc_rans_workspace_bytes(-1, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
+    assert L.tpc_rans_max_bytes(1000, 50, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_OK
+    assert n.value == 40 + 4 * 50 + 4 * 2 + 256 + 2 * 1000
+    assert L.tpc_rans_max_bytes(1000, (1 << 20) + 1, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
+    assert L.tpc_rans_encode(None, 10, ctypes.byref(p), None, 0, None, None, None, 0,
+                             None) == capi.TPC_ERR_ARG
 
 
 def test_status_strings(capi):

@@ -1,0 +1,92 @@
+"""GPU parity of the rANS coder (tpc_rans_encode through the C-ABI): the
+stream must be byte-identical to the oracle's for the same array and
+parameters (integer arithmetic on both sides), and the oracle's decoder must
+give the array back."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu(x, L, B, cap=None):
+    import torch
+    from paper_2412_13755_amd.reco import rans_encode
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+    out = None if cap is None else torch.empty(cap, dtype=torch.uint8, device="cuda")
+    out, size, status = rans_encode(t, L, B, out=out)
+    torch.cuda.synchronize()
+    n = int(size.item())
+    st = int(status.item())
+    return (out[:n].cpu().numpy().tobytes() if st == 0 else None), n, st
+
+
+def _check(x, L, B, label):
+    print("[rans] %s: n=%d L=%d B=%d" % (label, len(x), L, B), flush=True)
+    g, n, st = _gpu(x, L, B)
+    assert st == 0, st
+    r = oracle.rans_encode(x, L, B)
+    assert len(g) == len(r), (len(g), len(r))
+    assert g == r, "streams differ at byte %d" % next(i for i in range(len(r)) if g[i] != r[i])
+    np.testing.assert_array_equal(oracle.rans_decode(g), x)
+    return len(g)
+
+
+@pytest.mark.parametrize("L,B", [(16, 64), (12, 4096), (11, 32768), (16, 1 << 20)])
+def test_geometric_symbols(torch_dev, L, B):
+    rng = np.random.default_rng(L * 7 + B)
+    x = (rng.geometric(0.05, 1_000_003) - 20).astype(np.int32)
+    size = _check(x, L, B, "geometric")
+    if B >= 4096:                      # 256 bytes of coder states per block
+        assert size < 2 * len(x)
+
+
+def test_ragged_small_and_degenerate(torch_dev):
+    rng = np.random.default_rng(3)
+    for n in (0, 1, 2, 63, 64, 65, 64 * 37 + 13):
+        _check(rng.integers(-3, 9, n).astype(np.int32), 12, 128, "ragged %d" % n)
+    _check(np.full(10_000, -7, np.int32), 12, 1024, "one symbol")
+    _check((np.int32(-2**31) + rng.integers(0, 5, 5000)).astype(np.int32), 16, 256, "int32 minimum")
+    _check(np.array([7], np.int32), 16, 64, "single value")
+
+
+def test_wide_range_uses_global_histogram(torch_dev):
+    rng = np.random.default_rng(4)
+    x = rng.integers(0, 16000, 500_000).astype(np.int32)        # range above the LDS histogram
+    _check(x, 16, 8192, "wide")
+    y = np.concatenate([rng.integers(0, 50, 100_000), [1 << 19]]).astype(np.int32)   # sparse wide range
+    _check(y, 12, 4096, "sparse range")
+
+
+def test_errors_and_capacity(torch_dev):
+    _, _, st = _gpu(np.arange(300, dtype=np.int32), 8, 64)             # 300 symbols, M = 256
+    assert st == -1
+    _, _, st = _gpu(np.array([0, 1 << 21], np.int32), 16, 64)           # range beyond 2^20
+    assert st == -1
+    x = np.random.default_rng(6).integers(0, 40, 50_000).astype(np.int32)
+    want = len(oracle.rans_encode(x, 12, 4096))
+    g, n, st = _gpu(x, 12, 4096, cap=want - 1)
+    assert st == -2 and n == want
+    g, n, st = _gpu(x, 12, 4096, cap=want)
+    assert st == 0 and n == want
+
+
+def test_large_array(torch_dev):
+    rng = np.random.default_rng(9)
+    x = np.round(rng.normal(0.0, 12.0, 1 << 24)).astype(np.int32)
+    _check(x, 14, 1 << 15, "2^24 normal")
+
+
+def test_repeat_is_identical(torch_dev):
+    x = np.random.default_rng(10).integers(-100, 100, 300_000).astype(np.int32)
+    a, _, _ = _gpu(x, 12, 4096)
+    b, _, _ = _gpu(x, 12, 4096)
+    assert a == b
