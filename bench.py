@@ -20,6 +20,11 @@ Extra legs, reported beside the headline value:
            prolonged with chi2-gated cluster pickup (gate 25, up to 3 empty
            rows crossed), refitted, duplicates removed; the oracle is timed
            on the same seeds
+  rans     rANS coding of a 2^28-symbol int32 array (rounded normal, sigma 12,
+           about 5.6 bits of entropy per symbol; scale 2^14, blocks of 2^15
+           symbols): symbols/s of tpc_rans_encode with the array resident in
+           HBM, against the paper's CPU figure of 10^9 symbols/s; the oracle
+           coder is timed on 2^24 of the symbols
   copy     a 1 GiB device copy (reference for the HBM traffic counters; run
            alone with --legs copy)
   stages   the three stage calls on the headline workload, --steps times,
@@ -66,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint,follow")
+    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--stages-workload", type=int, default=1,
@@ -345,6 +350,62 @@ def leg_follow(args, with_cpu=True):
     return res
 
 
+RANS_L, RANS_B, RANS_N = 14, 1 << 15, 1 << 28
+RANS_PAPER_SYMBOLS_PER_S = 1e9      # the paper's AVX2 coder, 16 interleaved encoders
+
+
+def leg_rans(args, with_cpu=True):
+    """tpc_rans_encode of a large resident array, HIP events on the launch stream."""
+    import torch
+    from paper_2412_13755_amd.reco import rans_encode, rans_max_bytes, rans_workspace
+    g = torch.Generator(device="cuda").manual_seed(28)
+    x = torch.round(torch.randn(RANS_N, device="cuda", generator=g) * 12.0).to(torch.int32)
+    out = torch.empty(rans_max_bytes(RANS_N, 1 << 20, RANS_L, RANS_B), dtype=torch.uint8, device="cuda")
+    ws = rans_workspace(RANS_N, RANS_L, RANS_B)
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        rans_encode(x, RANS_L, RANS_B, out, ws, size, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    stream = torch.cuda.current_stream()
+    steps = max(3, args.steps // 5)
+    evs = []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        rans_encode(x, RANS_L, RANS_B, out, ws, size, status)
+        e[1].record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    nbytes = int(size.item())
+    sps = RANS_N / (ms * 1e-3)
+    alg = 4 * RANS_N + nbytes                      # read the symbols, write the stream
+    res = {"workload": "normal-sigma12-2^28", "symbols": RANS_N, "scale_bits": RANS_L,
+           "block_symbols": RANS_B, "stream_bytes": nbytes,
+           "bits_per_symbol": round(8.0 * nbytes / RANS_N, 4), "ms": round(ms, 4),
+           "G_symbols_per_s": round(sps / 1e9, 3),
+           "vs_paper_cpu": round(sps / RANS_PAPER_SYMBOLS_PER_S, 2),
+           "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes": alg,
+                        "calls": "rs_init, rs_minmax, rs_clear, rs_hist, rs_freq, rs_encode, rs_scan, rs_pack"}}
+    if with_cpu:
+        import oracle
+        xs = x[:1 << 24].cpu().numpy()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.rans_encode(xs, RANS_L, RANS_B)
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
+        res["cpu_oracle"] = {"symbols": int(xs.size), "ms": round(t * 1e3, 2), "cores": 1,
+                             "G_symbols_per_s": round(xs.size / t / 1e9, 4)}
+    return res
+
+
 def leg_copy(args):
     """A plain device copy of known size (calibrates the HBM traffic counters)."""
     import torch
@@ -403,6 +464,9 @@ def main():
     if legs == {"follow"}:
         print(json.dumps({"follow": leg_follow(args, not args.no_cpu)}), flush=True)
         return
+    if legs == {"rans"}:
+        print(json.dumps({"rans": leg_rans(args, not args.no_cpu)}), flush=True)
+        return
     main_res, fr = leg_main(args)
     out = {
         "metric": "M clusters/s through CA seed+Kalman fit (plain vs batched); adjoint grads/s",
@@ -418,6 +482,8 @@ def main():
         out["adjoint"] = leg_adjoint(args)
     if "follow" in legs:
         out["follow"] = leg_follow(args, not args.no_cpu)
+    if "rans" in legs:
+        out["rans"] = leg_rans(args, not args.no_cpu)
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:

@@ -88,7 +88,7 @@ size_t follow_ws_layout(void *ws, int64_t N, int64_t NR, void *index_out);
 struct RansWs {
     int32_t *mm;                 // min, max, status
     uint32_t *counts;            // [TPC_RANS_MAX_RANGE] histogram
-    uint2 *fc;                   // [TPC_RANS_MAX_RANGE] (frequency, cumulative frequency)
+    uint4 *fc;                   // [TPC_RANS_MAX_RANGE] (frequency, cumulative frequency, reciprocal, shifts)
     uint32_t *wcount, *wstart;   // [nb], [nb + 1] words per coding block, their prefix
     uint32_t *states;            // [nb][64] final coder states
     uint16_t *scratch;           // [nb][B] word stack of each block

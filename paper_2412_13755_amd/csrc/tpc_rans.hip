@@ -6,14 +6,18 @@
 //  rs_minmax    grid reduction of the symbol range
 //  rs_clear     zero the histogram over the range (fails if wider than 2^20)
 //  rs_hist      histogram: LDS-private per workgroup when the range fits
-//               (8192 bins), global atomics otherwise
+//               (8192 bins; eight copies of each bin up to 1024), global
+//               atomics otherwise; 16-byte symbol loads
 //  rs_freq      one workgroup: number of symbols present, most frequent
 //               symbol, scaled frequencies (integer arithmetic, exactly the
 //               stated rule), their exclusive scan
 //  rs_encode    one wavefront per block of B symbols, lane k = coder k; the
-//               block is coded backwards round by round; the words a round
-//               emits are placed by ballot and prefix popcount in the order
-//               coders 63 .. 0 push them, into a per-block scratch stack
+//               block is coded backwards round by round (symbols loaded eight
+//               rounds at a time, the coding table in LDS for ranges up to
+//               2048, division by the frequency as a multiply-high with a
+//               precomputed reciprocal); the words a round emits are placed
+//               by ballot and prefix popcount in the order coders 63 .. 0
+//               push them, into a per-block scratch stack
 //  rs_scan      exclusive scan of the blocks' word counts
 //  rs_pack      the stream: header, frequency table, block word offsets,
 //               final coder states, every block's stack reversed; nothing is
@@ -25,6 +29,8 @@
 #define RS_HEAD 40
 #define RS_LDS_BINS 8192
 #define RS_MAGIC 0x534E4152u
+#define RS_TAB_LDS 2048     // coding table in LDS up to this range (32 KB)
+#define RS_CHUNK 8          // rounds whose symbols are loaded at once
 
 namespace {
 
@@ -34,7 +40,7 @@ struct RsArgs {
     int32_t L, B, nb;
     int32_t *mm;           // [0] min, [1] max, [2] status (device)
     uint32_t *counts;      // [TPC_RANS_MAX_RANGE]
-    uint2 *fc;             // [TPC_RANS_MAX_RANGE] (frequency, cumulative)
+    uint4 *fc;             // [TPC_RANS_MAX_RANGE] (frequency, cumulative, reciprocal, shifts)
     uint32_t *wcount;      // [nb] words of each block
     uint32_t *wstart;      // [nb + 1]
     uint32_t *states;      // [nb][64]
@@ -58,19 +64,41 @@ __global__ void rs_init(RsArgs A) {
     }
 }
 
+// The symbols as 16-byte vectors where aligned: head (scalar), body (int4),
+// tail (scalar).
+struct Vec4Split {
+    int64_t head, nv;        // scalars before the first aligned vector, vectors
+};
+__device__ inline Vec4Split vec4_split(const int32_t *p, int64_t n) {
+    Vec4Split v;
+    const int64_t mis = (int64_t)(((uintptr_t)p >> 2) & 3);
+    v.head = mis ? 4 - mis : 0;
+    if (v.head > n) v.head = n;
+    v.nv = (n - v.head) / 4;
+    return v;
+}
+
 __global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsArgs A) {
     __shared__ int sh[2][TPC_BLOCK / TPC_WAVE];
     int lo = 0x7fffffff, hi = (int)0x80000000;
-    for (int64_t i = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * TPC_BLOCK) {
-        const int v = A.sym[i];
-        lo = v < lo ? v : lo;
-        hi = v > hi ? v : hi;
+    const Vec4Split V = vec4_split(A.sym, A.n);
+    const int4 *v4 = reinterpret_cast<const int4 *>(A.sym + V.head);
+    const int64_t gtid = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x, G = (int64_t)gridDim.x * TPC_BLOCK;
+    for (int64_t q = gtid; q < V.nv; q += G) {
+        const int4 v = v4[q];
+        lo = min(lo, min(min(v.x, v.y), min(v.z, v.w)));
+        hi = max(hi, max(max(v.x, v.y), max(v.z, v.w)));
+    }
+    for (int64_t i = gtid; i < V.head + (A.n - V.head - 4 * V.nv); i += G) {
+        const int64_t j = i < V.head ? i : V.head + 4 * V.nv + (i - V.head);
+        const int v = A.sym[j];
+        lo = min(lo, v);
+        hi = max(hi, v);
     }
 #pragma unroll
     for (int d = TPC_WAVE / 2; d > 0; d >>= 1) {
-        const int a = __shfl_xor(lo, d, TPC_WAVE), b = __shfl_xor(hi, d, TPC_WAVE);
-        lo = a < lo ? a : lo;
-        hi = b > hi ? b : hi;
+        lo = min(lo, __shfl_xor(lo, d, TPC_WAVE));
+        hi = max(hi, __shfl_xor(hi, d, TPC_WAVE));
     }
     const int wid = threadIdx.x / TPC_WAVE;
     if ((threadIdx.x & (TPC_WAVE - 1)) == 0) {
@@ -80,8 +108,8 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsArgs A) {
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w) {
-            lo = sh[0][w] < lo ? sh[0][w] : lo;
-            hi = sh[1][w] > hi ? sh[1][w] : hi;
+            lo = min(lo, sh[0][w]);
+            hi = max(hi, sh[1][w]);
         }
         atomicMin(&A.mm[0], lo);
         atomicMax(&A.mm[1], hi);
@@ -98,25 +126,48 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_clear(RsArgs A) {
         A.counts[s] = 0;
 }
 
+// Up to RS_COPY_BINS symbols, each bin has RS_COPIES copies side by side in
+// LDS and lane k counts into copy k mod RS_COPIES: a peaked distribution
+// sends most lanes of an instruction to a few bins, and the copies spread
+// those atomics over banks.
+#define RS_COPIES 8
+#define RS_COPY_BINS (RS_LDS_BINS / RS_COPIES)
 __global__ void __launch_bounds__(TPC_BLOCK) rs_hist(RsArgs A) {
     __shared__ uint32_t h[RS_LDS_BINS];
     const int64_t R = rs_range(A);
     if (R > TPC_RANS_MAX_RANGE) return;
     const int lo = A.mm[0];
-    const bool local = R <= RS_LDS_BINS;
-    if (local) {
-        for (int s = threadIdx.x; s < R; s += TPC_BLOCK) h[s] = 0;
+    const int mode = R <= RS_COPY_BINS ? 2 : (R <= RS_LDS_BINS ? 1 : 0);
+    const int cp = mode == 2 ? (threadIdx.x & (RS_COPIES - 1)) : 0;
+    const int stride = mode == 2 ? RS_COPIES : 1;
+    if (mode) {
+        for (int s = threadIdx.x; s < RS_LDS_BINS; s += TPC_BLOCK) h[s] = 0;
         __syncthreads();
     }
-    for (int64_t i = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * TPC_BLOCK) {
-        const uint32_t s = (uint32_t)((int64_t)A.sym[i] - lo);
-        if (local) atomicAdd(&h[s], 1u);
+    const Vec4Split V = vec4_split(A.sym, A.n);
+    const int4 *v4 = reinterpret_cast<const int4 *>(A.sym + V.head);
+    const int64_t gtid = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x, G = (int64_t)gridDim.x * TPC_BLOCK;
+    auto add = [&](int v) {
+        const uint32_t s = (uint32_t)((int64_t)v - lo);
+        if (mode) atomicAdd(&h[s * stride + cp], 1u);
         else atomicAdd(&A.counts[s], 1u);
+    };
+    for (int64_t q = gtid; q < V.nv; q += G) {
+        const int4 v = v4[q];
+        add(v.x);
+        add(v.y);
+        add(v.z);
+        add(v.w);
     }
-    if (local) {
+    for (int64_t i = gtid; i < V.head + (A.n - V.head - 4 * V.nv); i += G)
+        add(A.sym[i < V.head ? i : V.head + 4 * V.nv + (i - V.head)]);
+    if (mode) {
         __syncthreads();
-        for (int s = threadIdx.x; s < R; s += TPC_BLOCK)
-            if (h[s]) atomicAdd(&A.counts[s], h[s]);
+        for (int s = threadIdx.x; s < R; s += TPC_BLOCK) {
+            uint32_t c = 0;
+            for (int k = 0; k < stride; ++k) c += h[s * stride + k];
+            if (c) atomicAdd(&A.counts[s], c);
+        }
     }
 }
 
@@ -203,45 +254,96 @@ __global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsArgs A) {
             tot += v;
         }
         __syncthreads();
-        if (s < R) A.fc[s].y = carry + (uint32_t)(before + inc - f);
+        if (s < R) {
+            A.fc[s].y = carry + (uint32_t)(before + inc - f);
+            // floor(x / f) = (t + ((x - t) >> s1)) >> s2, t = mulhi(x, m), for
+            // every 32-bit x (division by an invariant integer, Granlund and
+            // Montgomery 1994): l = ceil(log2 f), m = floor(2^32 (2^l - f) / f) + 1,
+            // s1 = 1, s2 = l - 1; for f = 1, m = 0, s1 = s2 = 0
+            uint32_t m = 0, sh = 0;
+            if (f > 1) {
+                const int l = 32 - __clz(f - 1);
+                m = (uint32_t)(((((uint64_t)1 << l) - (uint64_t)f) << 32) / (uint64_t)f + 1);
+                sh = 1u | ((uint32_t)(l - 1) << 8);
+            }
+            A.fc[s].z = m;
+            A.fc[s].w = sh;
+        }
         carry += (uint32_t)tot;
     }
 }
 
-__global__ void __launch_bounds__(TPC_BLOCK) rs_encode(RsArgs A) {
-    if (A.mm[2] != TPC_OK) return;
-    const int lane = threadIdx.x & (TPC_WAVE - 1);
-    const int b = blockIdx.x * (TPC_BLOCK / TPC_WAVE) + threadIdx.x / TPC_WAVE;
-    if (b >= A.nb) return;
+// One block of symbols by one wavefront; T is the coding table (LDS or
+// global memory, a separate instantiation each so that the loads are not
+// generic).
+template <class Tab>
+__device__ inline void encode_block(const RsArgs &A, Tab T, int b, int lane) {
     const int lo = A.mm[0];
     const int L = A.L;
     const int64_t i0 = (int64_t)b * A.B;
-    const int64_t i1 = i0 + A.B < A.n ? i0 + A.B : A.n;
-    const int rounds = (int)((i1 - i0 + RS_LANES - 1) / RS_LANES);
+    const int nloc = (int)((i0 + A.B < A.n ? i0 + A.B : A.n) - i0);
+    const int32_t *src = A.sym + i0;
+    const int rounds = (nloc + RS_LANES - 1) / RS_LANES;
     uint16_t *stack = A.scratch + (size_t)b * A.B;
     uint32_t x = 1u << 16;
     uint32_t top = 0;
-    for (int j = rounds - 1; j >= 0; --j) {
-        const int64_t i = i0 + (int64_t)j * RS_LANES + lane;
-        const bool active = i < i1;
-        const uint32_t s = active ? (uint32_t)((int64_t)A.sym[i] - lo) : 0u;
-        const uint2 fc = active ? A.fc[s] : make_uint2(1u, 0u);
-        const bool emit = active && (uint64_t)x >= ((uint64_t)fc.x << (32 - L));
-        const unsigned long long mask = __ballot(emit);
-        if (emit) {
-            // coders above this one push first
-            const int rank = __popcll(lane == 63 ? 0ull : mask >> (lane + 1));
-            stack[top + rank] = (uint16_t)(x & 0xffffu);
-            x >>= 16;
+    for (int jc = rounds - 1; jc >= 0; jc -= RS_CHUNK) {
+        // the symbols of the next RS_CHUNK rounds (coded backwards), loaded together
+        int32_t sv[RS_CHUNK];
+#pragma unroll
+        for (int u = 0; u < RS_CHUNK; ++u) {
+            const int k = (jc - u) * RS_LANES + lane;
+            sv[u] = (jc - u >= 0 && k < nloc) ? src[k] : lo;
         }
-        top += (uint32_t)__popcll(mask);
-        if (active) {
-            const uint32_t q = x / fc.x;
-            x = (q << L) + (x - q * fc.x) + fc.y;
+#pragma unroll
+        for (int u = 0; u < RS_CHUNK; ++u) {
+            const int j = jc - u;
+            if (j < 0) break;
+            const bool act = j * RS_LANES + lane < nloc;
+            const uint4 e = T(act ? (uint32_t)(sv[u] - lo) : 0u);
+            const bool emit = act && (uint64_t)x >= ((uint64_t)e.x << (32 - L));
+            const unsigned long long mask = __ballot(emit);
+            if (emit) {
+                // coders above this one push first
+                const int rank = __popcll(lane == 63 ? 0ull : mask >> (lane + 1));
+                stack[top + rank] = (uint16_t)(x & 0xffffu);
+                x >>= 16;
+            }
+            top += (uint32_t)__popcll(mask);
+            if (act) {
+                const uint32_t t = __umulhi(x, e.z);
+                const uint32_t q = (t + ((x - t) >> (e.w & 0xffu))) >> (e.w >> 8);
+                x = (q << L) + (x - q * e.x) + e.y;
+            }
         }
     }
     A.states[(size_t)b * RS_LANES + lane] = x;
     if (lane == 0) A.wcount[b] = top;
+}
+
+struct LdsTab {
+    const uint4 *t;
+    __device__ uint4 operator()(uint32_t s) const { return t[s]; }
+};
+struct GlobalTab {
+    const uint4 *__restrict__ t;
+    __device__ uint4 operator()(uint32_t s) const { return t[s]; }
+};
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_encode(RsArgs A) {
+    __shared__ uint4 tab[RS_TAB_LDS];
+    if (A.mm[2] != TPC_OK) return;                  // uniform over the grid
+    const int64_t R = rs_range(A);
+    const bool in_lds = R <= RS_TAB_LDS;
+    if (in_lds) {
+        for (int s = threadIdx.x; s < R; s += TPC_BLOCK) tab[s] = A.fc[s];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    const int b = blockIdx.x * (TPC_BLOCK / TPC_WAVE) + threadIdx.x / TPC_WAVE;
+    if (b >= A.nb) return;                          // after the only barrier
+    if (in_lds) encode_block(A, LdsTab{tab}, b, lane);
+    else encode_block(A, GlobalTab{A.fc}, b, lane);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK) rs_scan(RsArgs A) {
@@ -318,7 +420,7 @@ size_t rans_ws_layout(void *ws, int64_t n, int32_t B, RansWs *out) {
     RansWs r;
     r.mm = w.take<int32_t>(4);
     r.counts = w.take<uint32_t>(TPC_RANS_MAX_RANGE);
-    r.fc = w.take<uint2>(TPC_RANS_MAX_RANGE);
+    r.fc = w.take<uint4>(TPC_RANS_MAX_RANGE);
     r.wcount = w.take<uint32_t>(nb > 0 ? nb : 1);
     r.wstart = w.take<uint32_t>(nb + 1);
     r.states = w.take<uint32_t>((nb > 0 ? nb : 1) * RS_LANES);
