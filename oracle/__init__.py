@@ -79,6 +79,9 @@ def lib():
         L.oracle_rans_encode.restype = i32
         L.oracle_rans_decode.argtypes = [P, sz, P, i64, ctypes.POINTER(i64)]
         L.oracle_rans_decode.restype = i32
+        L.oracle_ctf_build.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, ctypes.c_float,
+                                       ctypes.c_float, P, P]
+        L.oracle_ctf_build.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -234,6 +237,32 @@ def rans_decode(stream: bytes) -> np.ndarray:
     if st != 0:
         raise ValueError("oracle rANS decode failed")
     return out[:n.value].copy()
+
+
+CTF_ARRAYS = ("trk_seg", "trk_n", "trk_row0", "trk_y0h", "trk_y0l", "trk_z0h", "trk_z0l", "trk_dy1",
+              "trk_dz1", "hit_drow", "hit_ry", "hit_rz", "seg_nfree", "free_yh", "free_yl", "free_zh",
+              "free_zl")
+
+
+def ctf_build(row_offsets, y, z, n_sectors, n_rows, rows, status, frame, sector, qy, qz) -> dict:
+    """Track-model residual arrays of a frame (see rans_oracle.c), name -> int32 array."""
+    off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    st = np.ascontiguousarray(status, dtype=np.int32)
+    fr = np.ascontiguousarray(frame, dtype=np.int32)
+    se = np.ascontiguousarray(sector, dtype=np.int32)
+    T = st.size
+    N = int(off[-1])
+    NR = off.size - 1
+    caps = [max(T, 1)] * 9 + [max(N, 1)] * 3 + [max(NR, 1)] + [max(N, 1)] * 4
+    bufs = [np.zeros(c, np.int32) for c in caps]
+    ptrs = (ctypes.c_void_p * 17)(*[b.ctypes.data for b in bufs])
+    cnt = np.zeros(17, np.int64)
+    lib().oracle_ctf_build(T, n_rows, n_sectors, NR, _p(off), _p(y), _p(z), _p(rows), _p(st), _p(fr),
+                           _p(se), float(qy), float(qz), ptrs, _p(cnt))
+    return {k: bufs[i][:cnt[i]].copy() for i, k in enumerate(CTF_ARRAYS)}
 
 
 def unpack_cov(c15: np.ndarray) -> np.ndarray:

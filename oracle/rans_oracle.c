@@ -31,6 +31,7 @@
  * s = the symbol with cum_s <= slot < cum_s + f_s, x <- f_s (x >> L) + slot -
  * cum_s, and if x < 2^16, x <- (x << 16) | next word.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -198,4 +199,87 @@ int32_t oracle_rans_decode(const uint8_t *in, size_t size, int32_t *out, int64_t
     }
     free(f); free(cum); free(slot_sym);
     return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Track-model residual transform of a time frame's clusters into flat        */
+/* integer arrays (the input of the entropy coder above).                     */
+/*  Q(v)        rint(v * (1/q)) in single precision (1/q rounded to float),   */
+/*              0 when not finite or beyond +-2^30                            */
+/*  owner       a cluster belongs to the lowest-index kept track (status 0)   */
+/*              holding it; clusters of no kept track are free                */
+/*  per kept    seg (frame*S + sector), n (its own clusters), row0, Q(y0)     */
+/*  track       and Q(z0) split as v >> 8 and v & 255, Q(y1) - Q(y0),         */
+/*              Q(z1) - Q(z0) (0 where the track has fewer clusters)          */
+/*  per own     for k >= 1 the row step r_k - r_(k-1) - 1; for k >= 2 the     */
+/*  cluster k   second differences Q_k - 2 Q_(k-1) + Q_(k-2) in y and in z    */
+/*  per segment the number of free clusters, then their Q(y), Q(z) split as   */
+/*              above, in id order                                            */
+/* Arrays in order: 0 trk_seg 1 trk_n 2 trk_row0 3 trk_y0h 4 trk_y0l          */
+/* 5 trk_z0h 6 trk_z0l 7 trk_dy1 8 trk_dz1 9 hit_drow 10 hit_ry 11 hit_rz     */
+/* 12 seg_nfree 13 free_yh 14 free_yl 15 free_zh 16 free_zl.                  */
+/* ------------------------------------------------------------------------ */
+static int32_t quant(float v, float inv)
+{
+    float s = v * inv;
+    if (!(s > -1073741824.0f && s < 1073741824.0f)) return 0;
+    return (int32_t)rintf(s);
+}
+
+void oracle_ctf_build(int32_t n_tracks, int32_t n_rows, int32_t n_sectors, int32_t n_segments,
+                      const int32_t *row_offsets, const float *y, const float *z,
+                      const int32_t *rows, const int32_t *status, const int32_t *frame,
+                      const int32_t *sector, float qy, float qz, int32_t **arr, int64_t *count)
+{
+    int32_t N = row_offsets[n_segments];
+    float iy = 1.0f / qy, iz = 1.0f / qz;
+    int32_t *own = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+    for (int32_t c = 0; c < N; ++c) own[c] = -1;
+    for (int32_t t = n_tracks - 1; t >= 0; --t) {
+        if (status[t]) continue;
+        for (int32_t r = 0; r < n_rows; ++r) {
+            int32_t c = rows[(size_t)t * n_rows + r];
+            if (c >= 0) own[c] = t;
+        }
+    }
+    for (int k = 0; k < 17; ++k) count[k] = 0;
+    for (int32_t t = 0; t < n_tracks; ++t) {
+        if (status[t]) continue;
+        int32_t m = 0, r0 = 0, rp = 0, qy0 = 0, qz0 = 0, qy1 = 0, qz1 = 0, py1 = 0, pz1 = 0, py2 = 0, pz2 = 0;
+        for (int32_t r = 0; r < n_rows; ++r) {
+            int32_t c = rows[(size_t)t * n_rows + r];
+            if (c < 0 || own[c] != t) continue;
+            int32_t a = quant(y[c], iy), b = quant(z[c], iz);
+            if (m == 0) { r0 = r; qy0 = a; qz0 = b; }
+            else {
+                arr[9][count[9]++] = r - rp - 1;
+                if (m == 1) { qy1 = a; qz1 = b; }
+                else {
+                    arr[10][count[10]++] = a - 2 * py1 + py2;
+                    arr[11][count[11]++] = b - 2 * pz1 + pz2;
+                }
+            }
+            py2 = py1; pz2 = pz1; py1 = a; pz1 = b;
+            rp = r;
+            ++m;
+        }
+        int32_t seg = (frame[t] * n_sectors + sector[t]);
+        int32_t v[9] = {seg, m, r0, qy0 >> 8, qy0 & 255, qz0 >> 8, qz0 & 255,
+                        m >= 2 ? qy1 - qy0 : 0, m >= 2 ? qz1 - qz0 : 0};
+        for (int k = 0; k < 9; ++k) arr[k][count[k]++] = v[k];
+    }
+    for (int32_t s = 0; s < n_segments; ++s) {
+        int32_t nf = 0;
+        for (int32_t c = row_offsets[s]; c < row_offsets[s + 1]; ++c) {
+            if (own[c] >= 0) continue;
+            int32_t a = quant(y[c], iy), b = quant(z[c], iz);
+            arr[13][count[13]++] = a >> 8;
+            arr[14][count[14]++] = a & 255;
+            arr[15][count[15]++] = b >> 8;
+            arr[16][count[16]++] = b & 255;
+            ++nf;
+        }
+        arr[12][count[12]++] = nf;
+    }
+    free(own);
 }

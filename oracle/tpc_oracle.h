@@ -53,4 +53,8 @@ size_t oracle_rans_bound(int64_t n, uint32_t R, uint32_t B);
 int32_t oracle_rans_encode(const int32_t *sym, int64_t n, uint32_t L, uint32_t B, uint32_t max_range,
                            uint8_t *out, size_t cap, size_t *size);
 int32_t oracle_rans_decode(const uint8_t *in, size_t size, int32_t *out, int64_t cap, int64_t *n_out);
+void oracle_ctf_build(int32_t n_tracks, int32_t n_rows, int32_t n_sectors, int32_t n_segments,
+                      const int32_t *row_offsets, const float *y, const float *z,
+                      const int32_t *rows, const int32_t *status, const int32_t *frame,
+                      const int32_t *sector, float qy, float qz, int32_t **arr, int64_t *count);
 #endif
