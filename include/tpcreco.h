@@ -113,7 +113,8 @@ void tpc_destroy(tpc_context *ctx);
 #define TPC_STAGE_ADJOINT     8
 #define TPC_STAGE_PERSISTENT 16
 #define TPC_STAGE_FOLLOW     32
-#define TPC_STAGE_ALL        63
+#define TPC_STAGE_CTF        64
+#define TPC_STAGE_ALL       127
 
 /* Workspace bytes needed by the stages in `stage_mask` for frames of this
  * shape (only n_frames and n_clusters are read; host call, no device work).
@@ -317,6 +318,40 @@ tpc_status tpc_rans_max_bytes(int64_t n, int64_t range, const tpc_rans_params *p
 tpc_status tpc_rans_encode(const int32_t *symbols, int64_t n, const tpc_rans_params *params,
                            void *out, size_t out_cap, uint64_t *out_size, int32_t *dev_status,
                            void *ws, size_t ws_bytes, void *stream);
+
+/* Track-model residual transform: a frame's clusters as flat integer
+ * arrays for the entropy coder (Sec. 4.3 reduces every detector's time
+ * frame to integer arrays and codes each on its own; the arrays below are
+ * this library's reading for the TPC).  Q(v) = rint(v * (1/q)) in single
+ * precision (1/q rounded to float), 0 when not finite or beyond +-2^30.
+ * Each cluster belongs to the lowest-index track with status TPC_FIT_OK
+ * (after tpc_track_follow) holding it, else it is free.  Per such track, in
+ * index order: trk_seg = frame * n_sectors + sector, trk_n = its own
+ * clusters, trk_row0 = the first one's pad row, Q(y0), Q(z0) split into
+ * v >> 8 (trk_y0h, trk_z0h) and v & 255 (trk_y0l, trk_z0l), trk_dy1 =
+ * Q(y1) - Q(y0), trk_dz1 likewise (0 for fewer clusters); per own cluster
+ * k >= 1 in row order, hit_drow = r_k - r_(k-1) - 1; per k >= 2, hit_ry =
+ * Q(y_k) - 2 Q(y_(k-1)) + Q(y_(k-2)), hit_rz likewise.  Per segment (frame,
+ * sector, row): seg_nfree = its free clusters, whose Q(y), Q(z) follow in
+ * id order split the same way (free_yh, free_yl, free_zh, free_zl).
+ * rows, tracks: the output of tpc_track_follow for these seeds.  q_y, q_z:
+ * host floats > 0.  out: device arrays of cap_seeds (trk_*), n_clusters
+ * (hit_*, free_*) and n_frames*n_sectors*n_rows (seg_nfree) entries;
+ * out->counts (device int64[TPC_CTF_ARRAYS]) receives the number of entries
+ * written to each array, in the order of the struct.  ws: TPC_STAGE_CTF
+ * workspace (sized for the default seed capacity N / min_hits + 1; larger
+ * capacities need more, reported as TPC_ERR_WORKSPACE). */
+#define TPC_CTF_ARRAYS 17
+typedef struct tpc_ctf_arrays {
+    int32_t *trk_seg, *trk_n, *trk_row0, *trk_y0h, *trk_y0l, *trk_z0h, *trk_z0l, *trk_dy1, *trk_dz1;
+    int32_t *hit_drow, *hit_ry, *hit_rz;
+    int32_t *seg_nfree;
+    int32_t *free_yh, *free_yl, *free_zh, *free_zl;
+    int64_t *counts;
+} tpc_ctf_arrays;
+tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *frames, const tpc_seeds *seeds,
+                         const int32_t *rows, const tpc_tracks *tracks, float q_y, float q_z,
+                         const tpc_ctf_arrays *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Workgroups the persistent kernel can keep resident on the context's device. */
 int32_t tpc_persistent_grid(const tpc_context *ctx);

@@ -29,7 +29,8 @@ TPC_STAGE_SEED = 2
 TPC_STAGE_FIT = 4
 TPC_STAGE_ADJOINT = 8
 TPC_STAGE_FOLLOW = 32
-TPC_STAGE_ALL = 63
+TPC_STAGE_CTF = 64
+TPC_STAGE_ALL = 127
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32
@@ -67,6 +68,15 @@ class FollowParams(ctypes.Structure):
 
 class RansParams(ctypes.Structure):
     _fields_ = [("scale_bits", i32), ("block_symbols", i32)]
+
+
+CTF_ARRAYS = ("trk_seg", "trk_n", "trk_row0", "trk_y0h", "trk_y0l", "trk_z0h", "trk_z0l", "trk_dy1",
+              "trk_dz1", "hit_drow", "hit_ry", "hit_rz", "seg_nfree", "free_yh", "free_yl", "free_zh",
+              "free_zl")
+
+
+class CtfArraysC(ctypes.Structure):
+    _fields_ = [(k, P) for k in CTF_ARRAYS] + [("counts", P)]
 
 
 TPC_MODE_STAGED = 0
@@ -110,6 +120,8 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_size_t)]),
     "tpc_rans_encode": (i32, [P, ctypes.c_int64, ctypes.POINTER(RansParams), P, ctypes.c_size_t, P, P, P,
                               ctypes.c_size_t, P]),
+    "tpc_ctf_build": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P, ctypes.POINTER(TracksC),
+                            f32, f32, ctypes.POINTER(CtfArraysC), P, ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),

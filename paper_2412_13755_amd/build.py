@@ -29,6 +29,7 @@ SOURCES = {
     "tpc_persistent.hip": [],
     "tpc_follow.hip": [],
     "tpc_rans.hip": [],
+    "tpc_ctf.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

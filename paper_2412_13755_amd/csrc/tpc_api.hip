@@ -77,6 +77,7 @@ size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
     if (mask & TPC_STAGE_PERSISTENT)
         b = std::max(b, persist_ws_layout(nullptr, N, NR, cs, N > 0 ? N : 1, nullptr));
     if (mask & TPC_STAGE_FOLLOW) b = std::max(b, follow_ws_layout(nullptr, N, NR, nullptr));
+    if (mask & TPC_STAGE_CTF) b = std::max(b, ctf_ws_layout(nullptr, N, NR, cs, nullptr));
     return b;
 }
 
@@ -336,6 +337,28 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *fr, const 
     hipError_t e = launch_follow(ctx, fr, sd, (double)prm->gate_chi2, prm->max_miss, rows, tr, ws,
                                  (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "follow kernels");
+}
+
+tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                         const int32_t *rows, const tpc_tracks *tr, float qy, float qz,
+                         const tpc_ctf_arrays *out, void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if (!tr || (sd->cap_seeds > 0 && !tr->status)) return fail(TPC_ERR_ARG, "null track status");
+    if (sd->cap_seeds > 0 && !rows) return fail(TPC_ERR_ARG, "null rows");
+    if (!(qy > 0.f) || !(qz > 0.f) || !isfinite(qy) || !isfinite(qz))
+        return fail(TPC_ERR_ARG, "quantisation steps must be finite and > 0");
+    if (!out || !out->counts) return fail(TPC_ERR_ARG, "null output arrays or counts");
+    int32_t *const *a = &out->trk_seg;
+    for (int k = 0; k < TPC_CTF_ARRAYS; ++k)
+        if (!a[k]) return fail(TPC_ERR_ARG, "null output array %d", k);
+    const int64_t NR = n_segments(ctx, fr);
+    if ((s = check_ws(ws, ws_bytes, ctf_ws_layout(nullptr, fr->n_clusters, NR, sd->cap_seeds, nullptr))))
+        return s;
+    hipError_t e = launch_ctf_build(ctx, fr, sd, rows, tr, qy, qz, out, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "transform kernels");
 }
 
 static tpc_status check_rans_params(const tpc_rans_params *p) {

@@ -84,6 +84,11 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
 
 size_t follow_ws_layout(void *ws, int64_t N, int64_t NR, void *index_out);
 
+size_t ctf_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, void *out);
+hipError_t launch_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                            const int32_t *rows, const tpc_tracks *tr, float qy, float qz,
+                            const tpc_ctf_arrays *out, void *ws, hipStream_t st);
+
 #define TPC_RANS_MAX_RANGE (1 << 20)   // widest symbol range max - min + 1 of one array
 struct RansWs {
     int32_t *mm;                 // min, max, status

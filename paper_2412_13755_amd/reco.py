@@ -256,6 +256,28 @@ class Reco:
                                          ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return rows, tracks
 
+    def alloc_ctf(self, frames: DeviceFrames, seeds: Seeds) -> dict:
+        T, N = seeds.frame.numel(), max(frames.n_clusters, 1)
+        NR = frames.n_frames * self.cfg.n_sectors * self.cfg.n_rows
+        caps = [T] * 9 + [N] * 3 + [NR] + [N] * 4
+        d = {k: torch.empty(c, dtype=torch.int32, device=self.device) for k, c in zip(C.CTF_ARRAYS, caps)}
+        d["counts"] = torch.zeros(len(C.CTF_ARRAYS), dtype=torch.int64, device=self.device)
+        return d
+
+    def ctf_build(self, frames: DeviceFrames, seeds: Seeds, rows: torch.Tensor, tracks: Tracks,
+                  q_y: float, q_z: float, out: Optional[dict] = None, ws=None) -> dict:
+        """tpc_ctf_build: the frame's track-model residual arrays (device tensors,
+        valid up to out["counts"][k] entries each)."""
+        out = self.alloc_ctf(frames, seeds) if out is None else out
+        ws = self.workspace(frames) if ws is None else ws
+        oc = C.CtfArraysC(*[out[k].data_ptr() for k in C.CTF_ARRAYS], out["counts"].data_ptr())
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_ctf_build(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc), rows.data_ptr(),
+                                      ctypes.byref(tc), float(q_y), float(q_z), ctypes.byref(oc),
+                                      ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return out
+
     def chi2_sum(self, seeds: Seeds, tracks: Tracks, loss: Optional[torch.Tensor] = None, ws=None):
         """Sum of chi2 over successfully fitted tracks (device float scalar)."""
         loss = torch.empty((), dtype=torch.float32, device=self.device) if loss is None else loss

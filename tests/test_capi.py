@@ -29,7 +29,7 @@ def test_header_declares_the_path():
     for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
               "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
               "tpc_track_follow", "tpc_rans_encode", "tpc_rans_workspace_bytes",
-              "tpc_rans_max_bytes", "tpc_status_string", "tpc_last_error"):
+              "tpc_rans_max_bytes", "tpc_ctf_build", "tpc_status_string", "tpc_last_error"):
         assert n in names
 
 
