@@ -25,6 +25,11 @@ Extra legs, reported beside the headline value:
            symbols): symbols/s of tpc_rans_encode with the array resident in
            HBM, against the paper's CPU figure of 10^9 symbols/s; the oracle
            coder is timed on 2^24 of the symbols
+  ctf      compression of the headline frame: track following, then (timed)
+           the track-model residual transform into 17 integer arrays and the
+           rANS coding of all of them in one batch (scale 2^14, blocks of
+           2^13, counts read on the device), eagerly and as a graph;
+           clusters/s and bits per cluster
   copy     a 1 GiB device copy (reference for the HBM traffic counters; run
            alone with --legs copy)
   stages   the three stage calls on the headline workload, --steps times,
@@ -71,7 +76,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans")
+    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--stages-workload", type=int, default=1,
@@ -406,6 +411,71 @@ def leg_rans(args, with_cpu=True):
     return res
 
 
+CTF_Q = 0.01                      # quantisation step of y and z, cm
+CTF_B = 1 << 13                   # coding block of the frame's arrays
+
+
+def leg_ctf(args):
+    """Transform + coding of every array of the headline frame's CTF."""
+    import torch
+    from paper_2412_13755_amd import _capi as C
+    from paper_2412_13755_amd.reco import rans_encode_batch, rans_batch_workspace
+    from tpcsynth import make_config
+    fr = make_config(1)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    ws = reco.workspace(dfr)
+    up, dn = reco.neighbours(dfr, ws=ws)
+    seeds = reco.seed(dfr, up, dn, ws=ws)
+    rows, tr = reco.follow(dfr, seeds, FOLLOW_GATE, FOLLOW_MAX_MISS, ws=ws)
+    arr = reco.ctf_build(dfr, seeds, rows, tr, CTF_Q, CTF_Q, ws=ws)
+    torch.cuda.synchronize()
+    counts = [int(v) for v in arr["counts"].cpu()]
+    # all 17 arrays coded by one batch; counts read on the device (no host sync)
+    jobs = [{"symbols": arr[k], "n_device": arr["counts"][i:i + 1]} for i, k in enumerate(C.CTF_ARRAYS)]
+    rans_encode_batch(jobs, RANS_L, CTF_B)
+    rws = rans_batch_workspace(jobs, RANS_L, CTF_B)
+
+    def step():
+        reco.ctf_build(dfr, seeds, rows, tr, CTF_Q, CTF_Q, out=arr, ws=ws)
+        rans_encode_batch(jobs, RANS_L, CTF_B, rws)
+    step()
+    torch.cuda.synchronize()
+    assert all(int(j["status"].item()) == 0 for j in jobs)
+    total = sum(int(j["out_size"].item()) for j in jobs)
+    stream = torch.cuda.current_stream()
+    steps = max(5, args.steps // 2)
+
+    def event_ms(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+    ms_eager = event_ms(step)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    ms_graph = event_ms(g.replay)
+    torch.cuda.synchronize()
+    assert sum(int(j["out_size"].item()) for j in jobs) == total
+    ms = min(ms_eager, ms_graph)
+    N = dfr.n_clusters
+    return {"workload": fr.meta["name"], "clusters": N, "q_cm": CTF_Q, "arrays": len(counts),
+            "scale_bits": RANS_L, "block_symbols": CTF_B,
+            "symbols": int(sum(counts)), "stream_bytes": total,
+            "bits_per_cluster": round(8.0 * total / N, 3),
+            "ratio_vs_float_yz": round(8.0 * N / total, 3),
+            "ms_eager": round(ms_eager, 4), "ms_graph": round(ms_graph, 4),
+            "M_clusters_per_s": round(N / ms / 1e3, 2),
+            "G_symbols_per_s": round(sum(counts) / ms / 1e6, 3)}
+
+
 def leg_copy(args):
     """A plain device copy of known size (calibrates the HBM traffic counters)."""
     import torch
@@ -464,6 +534,9 @@ def main():
     if legs == {"follow"}:
         print(json.dumps({"follow": leg_follow(args, not args.no_cpu)}), flush=True)
         return
+    if legs == {"ctf"}:
+        print(json.dumps({"ctf": leg_ctf(args)}), flush=True)
+        return
     if legs == {"rans"}:
         print(json.dumps({"rans": leg_rans(args, not args.no_cpu)}), flush=True)
         return
@@ -484,6 +557,8 @@ def main():
         out["follow"] = leg_follow(args, not args.no_cpu)
     if "rans" in legs:
         out["rans"] = leg_rans(args, not args.no_cpu)
+    if "ctf" in legs:
+        out["ctf"] = leg_ctf(args)
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:

@@ -353,6 +353,28 @@ tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *frames, const
                          const int32_t *rows, const tpc_tracks *tracks, float q_y, float q_z,
                          const tpc_ctf_arrays *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Several arrays (1..TPC_RANS_BATCH_MAX) coded by one set of launches, each
+ * exactly as tpc_rans_encode would (same parameters for all).  An array's
+ * symbol count is n, or, when n_device is not NULL, the device int64 it
+ * points to clamped to 0..n (n is then the capacity; the counts of
+ * tpc_ctf_build can be passed without a host synchronisation).  Each job
+ * has its own output, size and status as in tpc_rans_encode.
+ * ws: tpc_rans_batch_workspace_bytes() bytes (which reads n only). */
+#define TPC_RANS_BATCH_MAX 24
+typedef struct tpc_rans_job {
+    const int32_t *symbols;
+    int64_t n;
+    const int64_t *n_device;
+    void *out;
+    size_t out_cap;
+    uint64_t *out_size;
+    int32_t *dev_status;
+} tpc_rans_job;
+tpc_status tpc_rans_batch_workspace_bytes(int32_t count, const tpc_rans_job *jobs,
+                                          const tpc_rans_params *params, size_t *bytes);
+tpc_status tpc_rans_encode_batch(int32_t count, const tpc_rans_job *jobs, const tpc_rans_params *params,
+                                 void *ws, size_t ws_bytes, void *stream);
+
 /* Workgroups the persistent kernel can keep resident on the context's device. */
 int32_t tpc_persistent_grid(const tpc_context *ctx);
 

@@ -79,6 +79,12 @@ class CtfArraysC(ctypes.Structure):
     _fields_ = [(k, P) for k in CTF_ARRAYS] + [("counts", P)]
 
 
+class RansJobC(ctypes.Structure):
+    _fields_ = [("symbols", P), ("n", ctypes.c_int64), ("n_device", P), ("out", P), ("out_cap", ctypes.c_size_t),
+                ("out_size", P), ("dev_status", P)]
+
+
+TPC_RANS_BATCH_MAX = 24
 TPC_MODE_STAGED = 0
 TPC_MODE_PERSISTENT = 1
 TPC_STAGE_PERSISTENT = 16
@@ -122,6 +128,8 @@ SIGNATURES = {
                               ctypes.c_size_t, P]),
     "tpc_ctf_build": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P, ctypes.POINTER(TracksC),
                             f32, f32, ctypes.POINTER(CtfArraysC), P, ctypes.c_size_t, P]),
+    "tpc_rans_batch_workspace_bytes": (i32, [i32, P, ctypes.POINTER(RansParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "tpc_rans_encode_batch": (i32, [i32, P, ctypes.POINTER(RansParams), P, ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),

@@ -402,10 +402,54 @@ tpc_status tpc_rans_encode(const int32_t *sym, int64_t n, const tpc_rans_params 
     if (!out || !out_size || !dev_status) return fail(TPC_ERR_ARG, "null output, size or status");
     if (((uintptr_t)out & 3) != 0) return fail(TPC_ERR_ARG, "output not 4-byte aligned");
     if ((s = check_ws(ws, ws_bytes, rans_ws_layout(nullptr, n, p->block_symbols, nullptr)))) return s;
-    RansWs W;
-    rans_ws_layout(ws, n, p->block_symbols, &W);
-    hipError_t e = launch_rans_encode(sym, n, p->scale_bits, p->block_symbols, (uint8_t *)out,
-                                      (uint64_t)out_cap, out_size, dev_status, W, (hipStream_t)stream);
+    RansJob J{sym, n, nullptr, (uint8_t *)out, (uint64_t)out_cap, out_size, dev_status};
+    hipError_t e = launch_rans_batch(1, &J, p->scale_bits, p->block_symbols, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "rANS kernels");
+}
+
+static tpc_status check_rans_jobs(int32_t count, const tpc_rans_job *jobs, bool outputs) {
+    if (count < 1 || count > TPC_RANS_BATCH_MAX) return fail(TPC_ERR_ARG, "count outside 1..%d", TPC_RANS_BATCH_MAX);
+    if (!jobs) return fail(TPC_ERR_ARG, "null jobs");
+    for (int k = 0; k < count; ++k) {
+        const tpc_rans_job &J = jobs[k];
+        if (J.n < 0 || J.n >= ((int64_t)1 << 31)) return fail(TPC_ERR_ARG, "job %d: n outside 0..2^31-1", k);
+        if (!outputs) continue;
+        if (J.n > 0 && !J.symbols) return fail(TPC_ERR_ARG, "job %d: null symbols", k);
+        if (!J.out || !J.out_size || !J.dev_status) return fail(TPC_ERR_ARG, "job %d: null output, size or status", k);
+        if (((uintptr_t)J.out & 3) != 0) return fail(TPC_ERR_ARG, "job %d: output not 4-byte aligned", k);
+    }
+    return TPC_OK;
+}
+
+static void rans_jobs(int32_t count, const tpc_rans_job *jobs, RansJob *J) {
+    for (int k = 0; k < count; ++k)
+        J[k] = RansJob{jobs[k].symbols, jobs[k].n, jobs[k].n_device, (uint8_t *)jobs[k].out,
+                       (uint64_t)jobs[k].out_cap, jobs[k].out_size, jobs[k].dev_status};
+}
+
+tpc_status tpc_rans_batch_workspace_bytes(int32_t count, const tpc_rans_job *jobs, const tpc_rans_params *p,
+                                          size_t *bytes) {
+    g_err[0] = 0;
+    tpc_status s = check_rans_params(p);
+    if (s) return s;
+    if (!bytes) return fail(TPC_ERR_ARG, "null bytes");
+    if ((s = check_rans_jobs(count, jobs, false))) return s;
+    RansJob J[TPC_RANS_BATCH_MAX];
+    rans_jobs(count, jobs, J);
+    *bytes = rans_batch_ws_bytes(count, J, p->block_symbols);
+    return TPC_OK;
+}
+
+tpc_status tpc_rans_encode_batch(int32_t count, const tpc_rans_job *jobs, const tpc_rans_params *p, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_rans_params(p);
+    if (s) return s;
+    if ((s = check_rans_jobs(count, jobs, true))) return s;
+    RansJob J[TPC_RANS_BATCH_MAX];
+    rans_jobs(count, jobs, J);
+    if ((s = check_ws(ws, ws_bytes, rans_batch_ws_bytes(count, J, p->block_symbols)))) return s;
+    hipError_t e = launch_rans_batch(count, J, p->scale_bits, p->block_symbols, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "rANS kernels");
 }
 

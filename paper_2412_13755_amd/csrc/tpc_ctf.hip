@@ -5,15 +5,17 @@
 //  ct_own          wavefront per kept track: 32-bit atomicMin of the track
 //                  index on each of its clusters (lowest index owns)
 //  ct_count        wavefront per track: its own clusters, counted by ballot
-//  ct_scan_tracks  one workgroup: prefixes of kept tracks, row steps and
-//                  second differences over the tracks
+//  ct_tsum/tscan/tapply  prefixes of kept tracks, row steps and second
+//                  differences over the tracks (workgroup sums, their scan,
+//                  each workgroup's scan)
 //  ct_free         workgroup per segment: free clusters compacted in id order
 //                  (block scan), their split quantised values; the segment's
 //                  count
 //  ct_scan_segs    one workgroup: prefix of free clusters over segments (run
 //                  between two ct_free passes: count, then emit)
-//  ct_emit         thread per kept track: one walk up its rows, emitting the
-//                  track record and the residuals of its own clusters
+//  ct_emit         workgroup per kept track: its own clusters compacted in row
+//                  order (block scan into LDS), then each thread writes the
+//                  row step and residuals of one cluster; the track record
 #include "tpc_internal.hpp"
 
 namespace {
@@ -30,6 +32,7 @@ struct CtArgs {
     int32_t *m;                   // [cap_seeds] own clusters of each kept track
     int32_t *kp, *dp, *rp;        // [cap_seeds + 1] prefixes: kept, row steps, residuals
     int32_t *fp;                  // [NR + 1] prefix of free clusters
+    int32_t *bsum;                // [3 per workgroup of tracks] sums, then their prefixes
     tpc_ctf_arrays out;
 };
 
@@ -80,37 +83,69 @@ __global__ void __launch_bounds__(TPC_BLOCK) ct_count(CtArgs A) {
     }
 }
 
-// Exclusive scans of three per-track counts in one workgroup.
-__global__ void __launch_bounds__(TPC_BLOCK) ct_scan_tracks(CtArgs A) {
+// Exclusive scans of three per-track counts (kept, row steps, residuals):
+// per-workgroup sums, one workgroup over those, then each workgroup's scan.
+__device__ inline void track_vals(const CtArgs &A, int t, int T, int v[3]) {
+    const bool kept = t < T && A.status[t] == TPC_FIT_OK;
+    const int mt = kept ? A.m[t] : 0;
+    v[0] = kept ? 1 : 0;
+    v[1] = mt > 1 ? mt - 1 : 0;
+    v[2] = mt > 2 ? mt - 2 : 0;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) ct_tsum(CtArgs A) {
     __shared__ int sh[3][TPC_BLOCK / TPC_WAVE];
     const int T = n_tracks(A);
-    int c0 = 0, c1 = 0, c2 = 0;
-    for (int b = 0; b < T; b += TPC_BLOCK) {
-        const int t = b + threadIdx.x;
-        const bool kept = t < T && A.status[t] == TPC_FIT_OK;
-        const int mt = kept ? A.m[t] : 0;
-        const int v[3] = {kept ? 1 : 0, mt > 1 ? mt - 1 : 0, mt > 2 ? mt - 2 : 0};
-        int tot[3], ex[3];
+    if ((int)blockIdx.x * TPC_BLOCK >= T) return;
+    int v[3], tot[3];
+    track_vals(A, blockIdx.x * TPC_BLOCK + threadIdx.x, T, v);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ex[k] = block_exclusive_scan(v[k], sh[k], &tot[k]);
-        if (t < T) {
-            A.kp[t] = c0 + ex[0];
-            A.dp[t] = c1 + ex[1];
-            A.rp[t] = c2 + ex[2];
+    for (int k = 0; k < 3; ++k) block_exclusive_scan(v[k], sh[k], &tot[k]);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) A.bsum[blockIdx.x * 3 + k] = tot[k];
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) ct_tscan(CtArgs A) {
+    __shared__ int sh[3][TPC_BLOCK / TPC_WAVE];
+    const int T = n_tracks(A);
+    const int nb = (T + TPC_BLOCK - 1) / TPC_BLOCK;
+    int c[3] = {0, 0, 0};
+    for (int b0 = 0; b0 < nb; b0 += TPC_BLOCK) {
+        const int b = b0 + threadIdx.x;
+        int tot[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int v = b < nb ? A.bsum[b * 3 + k] : 0;
+            const int ex = block_exclusive_scan(v, sh[k], &tot[k]);
+            if (b < nb) A.bsum[b * 3 + k] = c[k] + ex;
+            c[k] += tot[k];
         }
-        c0 += tot[0];
-        c1 += tot[1];
-        c2 += tot[2];
     }
     if (threadIdx.x == 0) {
-        A.kp[T] = c0;
-        A.dp[T] = c1;
-        A.rp[T] = c2;
-        for (int k = 0; k < 9; ++k) A.out.counts[k] = c0;
-        A.out.counts[9] = c1;
-        A.out.counts[10] = c2;
-        A.out.counts[11] = c2;
+        A.kp[T] = c[0];
+        A.dp[T] = c[1];
+        A.rp[T] = c[2];
+        for (int k = 0; k < 9; ++k) A.out.counts[k] = c[0];
+        A.out.counts[9] = c[1];
+        A.out.counts[10] = c[2];
+        A.out.counts[11] = c[2];
         A.out.counts[12] = A.NR;
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) ct_tapply(CtArgs A) {
+    __shared__ int sh[3][TPC_BLOCK / TPC_WAVE];
+    const int T = n_tracks(A);
+    if ((int)blockIdx.x * TPC_BLOCK >= T) return;
+    const int t = blockIdx.x * TPC_BLOCK + threadIdx.x;
+    int v[3], tot[3], ex[3];
+    track_vals(A, t, T, v);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ex[k] = block_exclusive_scan(v[k], sh[k], &tot[k]);
+    if (t < T) {
+        A.kp[t] = A.bsum[blockIdx.x * 3] + ex[0];
+        A.dp[t] = A.bsum[blockIdx.x * 3 + 1] + ex[1];
+        A.rp[t] = A.bsum[blockIdx.x * 3 + 2] + ex[2];
     }
 }
 
@@ -159,49 +194,53 @@ __global__ void __launch_bounds__(TPC_BLOCK) ct_scan_segs(CtArgs A) {
     }
 }
 
+// Workgroup per kept track (TPC_BLOCK >= n_rows threads, thread r on row r):
+// its own clusters compacted in row order by a block scan into LDS, then
+// thread k writes what cluster k contributes.
 __global__ void __launch_bounds__(TPC_BLOCK) ct_emit(CtArgs A) {
+    __shared__ int sy[TPC_MAX_ROWS], sz[TPC_MAX_ROWS], sr[TPC_MAX_ROWS];
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     const int T = n_tracks(A);
-    for (int t = blockIdx.x * TPC_BLOCK + threadIdx.x; t < T; t += gridDim.x * TPC_BLOCK) {
-        if (A.status[t] != TPC_FIT_OK) continue;
+    for (int t = blockIdx.x; t < T; t += gridDim.x) {
+        if (A.status[t] != TPC_FIT_OK) continue;        // uniform over the workgroup
         const int32_t *rw = A.rows + (size_t)t * A.R;
-        int d = A.dp[t], g = A.rp[t];
-        int m = 0, r0 = 0, rp = 0, qy0 = 0, qz0 = 0, qy1 = 0, qz1 = 0, py1 = 0, pz1 = 0, py2 = 0, pz2 = 0;
-        for (int r = 0; r < A.R; ++r) {
-            const int c = rw[r];
-            if ((uint32_t)c >= (uint32_t)A.N || A.own[c] != t) continue;
-            const int32_t a = quant(A.y[c], A.iy), b = quant(A.z[c], A.iz);
-            if (m == 0) {
-                r0 = r;
-                qy0 = a;
-                qz0 = b;
-            } else {
-                A.out.hit_drow[d++] = r - rp - 1;
-                if (m == 1) {
-                    qy1 = a;
-                    qz1 = b;
-                } else {
-                    A.out.hit_ry[g] = a - 2 * py1 + py2;
-                    A.out.hit_rz[g] = b - 2 * pz1 + pz2;
-                    ++g;
-                }
+        int m = 0;
+        for (int r0 = 0; r0 < A.R; r0 += TPC_BLOCK) {
+            const int r = r0 + threadIdx.x;
+            const int c = r < A.R ? rw[r] : -1;
+            const bool mine = (uint32_t)c < (uint32_t)A.N && A.own[c] == t;
+            int tot;
+            const int k = m + block_exclusive_scan(mine ? 1 : 0, sh, &tot);
+            if (mine) {
+                sy[k] = quant(A.y[c], A.iy);
+                sz[k] = quant(A.z[c], A.iz);
+                sr[k] = r;
             }
-            py2 = py1;
-            pz2 = pz1;
-            py1 = a;
-            pz1 = b;
-            rp = r;
-            ++m;
+            m += tot;
         }
-        const int k = A.kp[t];
-        A.out.trk_seg[k] = A.frame[t] * A.S + A.sector[t];
-        A.out.trk_n[k] = m;
-        A.out.trk_row0[k] = r0;
-        A.out.trk_y0h[k] = qy0 >> 8;
-        A.out.trk_y0l[k] = qy0 & 255;
-        A.out.trk_z0h[k] = qz0 >> 8;
-        A.out.trk_z0l[k] = qz0 & 255;
-        A.out.trk_dy1[k] = m >= 2 ? qy1 - qy0 : 0;
-        A.out.trk_dz1[k] = m >= 2 ? qz1 - qz0 : 0;
+        __syncthreads();
+        const int d = A.dp[t], g = A.rp[t];
+        for (int k = threadIdx.x; k < m; k += TPC_BLOCK) {
+            if (k >= 1) A.out.hit_drow[d + k - 1] = sr[k] - sr[k - 1] - 1;
+            if (k >= 2) {
+                A.out.hit_ry[g + k - 2] = sy[k] - 2 * sy[k - 1] + sy[k - 2];
+                A.out.hit_rz[g + k - 2] = sz[k] - 2 * sz[k - 1] + sz[k - 2];
+            }
+        }
+        if (threadIdx.x == 0) {
+            const int k = A.kp[t];
+            const int qy0 = m ? sy[0] : 0, qz0 = m ? sz[0] : 0;
+            A.out.trk_seg[k] = A.frame[t] * A.S + A.sector[t];
+            A.out.trk_n[k] = m;
+            A.out.trk_row0[k] = m ? sr[0] : 0;
+            A.out.trk_y0h[k] = qy0 >> 8;
+            A.out.trk_y0l[k] = qy0 & 255;
+            A.out.trk_z0h[k] = qz0 >> 8;
+            A.out.trk_z0l[k] = qz0 & 255;
+            A.out.trk_dy1[k] = m >= 2 ? sy[1] - qy0 : 0;
+            A.out.trk_dz1[k] = m >= 2 ? sz[1] - qz0 : 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -221,9 +260,10 @@ size_t ctf_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, void *o
     int32_t *dp = w.take<int32_t>(cap_seeds + 1);
     int32_t *rp = w.take<int32_t>(cap_seeds + 1);
     int32_t *fp = w.take<int32_t>(NR + 1);
+    int32_t *bs = w.take<int32_t>(3 * ((cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK + 1));
     if (out) {
         int32_t **p = static_cast<int32_t **>(out);
-        p[0] = own; p[1] = m; p[2] = kp; p[3] = dp; p[4] = rp; p[5] = fp;
+        p[0] = own; p[1] = m; p[2] = kp; p[3] = dp; p[4] = rp; p[5] = fp; p[6] = bs;
     }
     return (w.off + 255) & ~size_t(255);
 }
@@ -248,7 +288,7 @@ hipError_t launch_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const 
     A.status = tr->status;
     A.iy = 1.0f / qy;
     A.iz = 1.0f / qz;
-    int32_t *p[6];
+    int32_t *p[7];
     ctf_ws_layout(ws, A.N, A.NR, A.cap_seeds, p);
     A.own = p[0];
     A.m = p[1];
@@ -256,15 +296,19 @@ hipError_t launch_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const 
     A.dp = p[3];
     A.rp = p[4];
     A.fp = p[5];
+    A.bsum = p[6];
     A.out = *out;
     const int wb = grid_for((int64_t)A.cap_seeds * TPC_WAVE);
     hipLaunchKernelGGL(ct_own_init, dim3(grid_for(A.N)), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(ct_own, dim3(wb), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(ct_count, dim3(wb), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(ct_scan_tracks, dim3(1), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(ct_tsum, dim3((A.cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(ct_tscan, dim3(1), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(ct_tapply, dim3((A.cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(ct_free, dim3(A.NR), dim3(TPC_BLOCK), 0, st, A, 0);
     hipLaunchKernelGGL(ct_scan_segs, dim3(1), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(ct_free, dim3(A.NR), dim3(TPC_BLOCK), 0, st, A, 1);
-    hipLaunchKernelGGL(ct_emit, dim3(grid_for(A.cap_seeds)), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(ct_emit, dim3(A.cap_seeds < 32768 ? (A.cap_seeds > 0 ? A.cap_seeds : 1) : 32768),
+                       dim3(TPC_BLOCK), 0, st, A);
     return hipGetLastError();
 }

@@ -99,9 +99,18 @@ struct RansWs {
     uint16_t *scratch;           // [nb][B] word stack of each block
 };
 size_t rans_ws_layout(void *ws, int64_t n, int32_t B, RansWs *out);
-hipError_t launch_rans_encode(const int32_t *sym, int64_t n, int32_t L, int32_t B, uint8_t *out,
-                              uint64_t cap, uint64_t *out_size, int32_t *dev_status, const RansWs &W,
-                              hipStream_t st);
+struct RansJob {
+    const int32_t *sym;
+    int64_t n;                 // symbols, or their upper bound when n_dev is given
+    const int64_t *n_dev;      // optional device count
+    uint8_t *out;
+    uint64_t cap;
+    uint64_t *out_size;
+    int32_t *dev_status;
+};
+size_t rans_batch_ws_bytes(int count, const RansJob *jobs, int32_t B);
+hipError_t launch_rans_batch(int count, const RansJob *jobs, int32_t L, int32_t B, void *ws,
+                             hipStream_t st);
 hipError_t launch_follow(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
                          double gate, int32_t max_miss, int32_t *rows, const tpc_tracks *tr,
                          void *ws, hipStream_t st);

@@ -2,6 +2,8 @@
 // compression stage of a time frame, where every flat integer array is coded
 // on its own with frequencies counted for that frame (Sec. 4.3).
 //
+//  Every kernel codes a batch of arrays: grid dimension y selects the
+//  array; an array's symbol count may come from device memory.
 //  rs_init      min / max / status words
 //  rs_minmax    grid reduction of the symbol range
 //  rs_clear     zero the histogram over the range (fails if wider than 2^20)
@@ -36,7 +38,9 @@ namespace {
 
 struct RsArgs {
     const int32_t *sym;
-    int64_t n;
+    int64_t n;             // resolved on the device: min(*n_dev, n_cap), or n_cap
+    const int64_t *n_dev;  // optional device symbol count
+    int64_t n_cap;
     int32_t L, B, nb;
     int32_t *mm;           // [0] min, [1] max, [2] status (device)
     uint32_t *counts;      // [TPC_RANS_MAX_RANGE]
@@ -51,12 +55,30 @@ struct RsArgs {
     int32_t *dev_status;
 };
 
+// Arrays coded together: grid dimension y selects the array.
+struct RsBatch {
+    RsArgs a[TPC_RANS_BATCH_MAX];
+};
+
+__device__ inline RsArgs rs_job(const RsBatch &Bt) {
+    RsArgs A = Bt.a[blockIdx.y];
+    if (A.n_dev) {
+        const int64_t v = *A.n_dev;
+        A.n = v < 0 ? 0 : (v < A.n_cap ? v : A.n_cap);
+    } else {
+        A.n = A.n_cap;
+    }
+    A.nb = (int32_t)(A.n > 0 ? (A.n + A.B - 1) / A.B : 0);
+    return A;
+}
+
 // Range R = max - min + 1 (0 for no symbols).
 __device__ inline int64_t rs_range(const RsArgs &A) {
     return A.n > 0 ? (int64_t)A.mm[1] - (int64_t)A.mm[0] + 1 : 0;
 }
 
-__global__ void rs_init(RsArgs A) {
+__global__ void rs_init(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     if (threadIdx.x == 0) {
         A.mm[0] = 0x7fffffff;
         A.mm[1] = (int32_t)0x80000000;
@@ -78,7 +100,8 @@ __device__ inline Vec4Split vec4_split(const int32_t *p, int64_t n) {
     return v;
 }
 
-__global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsArgs A) {
+__global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     __shared__ int sh[2][TPC_BLOCK / TPC_WAVE];
     int lo = 0x7fffffff, hi = (int)0x80000000;
     const Vec4Split V = vec4_split(A.sym, A.n);
@@ -111,12 +134,15 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsArgs A) {
             lo = min(lo, sh[0][w]);
             hi = max(hi, sh[1][w]);
         }
-        atomicMin(&A.mm[0], lo);
-        atomicMax(&A.mm[1], hi);
+        if (lo <= hi) {                     // a workgroup that saw no symbol adds nothing
+            atomicMin(&A.mm[0], lo);
+            atomicMax(&A.mm[1], hi);
+        }
     }
 }
 
-__global__ void __launch_bounds__(TPC_BLOCK) rs_clear(RsArgs A) {
+__global__ void __launch_bounds__(TPC_BLOCK) rs_clear(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     const int64_t R = rs_range(A);
     if (R > TPC_RANS_MAX_RANGE) {
         if (blockIdx.x == 0 && threadIdx.x == 0) A.mm[2] = TPC_ERR_ARG;
@@ -132,10 +158,12 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_clear(RsArgs A) {
 // those atomics over banks.
 #define RS_COPIES 8
 #define RS_COPY_BINS (RS_LDS_BINS / RS_COPIES)
-__global__ void __launch_bounds__(TPC_BLOCK) rs_hist(RsArgs A) {
+__global__ void __launch_bounds__(TPC_BLOCK) rs_hist(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     __shared__ uint32_t h[RS_LDS_BINS];
     const int64_t R = rs_range(A);
     if (R > TPC_RANS_MAX_RANGE) return;
+    if ((int64_t)blockIdx.x * TPC_BLOCK * 4 >= A.n) return;     // no symbols for this workgroup
     const int lo = A.mm[0];
     const int mode = R <= RS_COPY_BINS ? 2 : (R <= RS_LDS_BINS ? 1 : 0);
     const int cp = mode == 2 ? (threadIdx.x & (RS_COPIES - 1)) : 0;
@@ -202,7 +230,8 @@ __device__ inline unsigned long long rs_block_max(unsigned long long v, unsigned
     return t;
 }
 
-__global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsArgs A) {
+__global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     __shared__ long long sh[RS_FREQ_THREADS / TPC_WAVE];
     __shared__ unsigned long long shk[RS_FREQ_THREADS / TPC_WAVE];
     __shared__ int scan_sh[RS_FREQ_THREADS / TPC_WAVE];
@@ -330,7 +359,8 @@ struct GlobalTab {
     __device__ uint4 operator()(uint32_t s) const { return t[s]; }
 };
 
-__global__ void __launch_bounds__(TPC_BLOCK) rs_encode(RsArgs A) {
+__global__ void __launch_bounds__(TPC_BLOCK) rs_encode(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     __shared__ uint4 tab[RS_TAB_LDS];
     if (A.mm[2] != TPC_OK) return;                  // uniform over the grid
     const int64_t R = rs_range(A);
@@ -346,7 +376,8 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_encode(RsArgs A) {
     else encode_block(A, GlobalTab{A.fc}, b, lane);
 }
 
-__global__ void __launch_bounds__(TPC_BLOCK) rs_scan(RsArgs A) {
+__global__ void __launch_bounds__(TPC_BLOCK) rs_scan(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     uint32_t carry = 0;
     for (int c0 = 0; c0 < A.nb; c0 += TPC_BLOCK) {
@@ -363,7 +394,8 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_scan(RsArgs A) {
 __device__ inline void put32(uint8_t *p, uint32_t v) { *reinterpret_cast<uint32_t *>(p) = v; }
 
 // Grid: one workgroup per coding block (at least one).
-__global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsArgs A) {
+__global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
     const int st0 = A.mm[2];
     const int64_t R = st0 == TPC_OK ? rs_range(A) : 0;
     const uint64_t words = A.wstart[A.nb];
@@ -429,35 +461,56 @@ size_t rans_ws_layout(void *ws, int64_t n, int32_t B, RansWs *out) {
     return (w.off + 255) & ~size_t(255);
 }
 
-hipError_t launch_rans_encode(const int32_t *sym, int64_t n, int32_t L, int32_t B, uint8_t *out,
-                              uint64_t cap, uint64_t *out_size, int32_t *dev_status, const RansWs &W,
-                              hipStream_t st) {
-    RsArgs A;
-    A.sym = sym;
-    A.n = n;
-    A.L = L;
-    A.B = B;
-    A.nb = (int32_t)(n > 0 ? (n + B - 1) / B : 0);
-    A.mm = W.mm;
-    A.counts = W.counts;
-    A.fc = W.fc;
-    A.wcount = W.wcount;
-    A.wstart = W.wstart;
-    A.states = W.states;
-    A.scratch = W.scratch;
-    A.out = out;
-    A.cap = cap;
-    A.out_size = out_size;
-    A.dev_status = dev_status;
-    const int gs = grid_over(n, 2048);
-    hipLaunchKernelGGL(rs_init, dim3(1), dim3(TPC_WAVE), 0, st, A);
-    hipLaunchKernelGGL(rs_minmax, dim3(gs), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(rs_clear, dim3(grid_over(TPC_RANS_MAX_RANGE, 1024)), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(rs_hist, dim3(gs), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(rs_freq, dim3(1), dim3(RS_FREQ_THREADS), 0, st, A);
-    const int eb = (A.nb + TPC_BLOCK / TPC_WAVE - 1) / (TPC_BLOCK / TPC_WAVE);
-    if (eb > 0) hipLaunchKernelGGL(rs_encode, dim3(eb), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(rs_scan, dim3(1), dim3(TPC_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(rs_pack, dim3(A.nb > 0 ? (A.nb < 4096 ? A.nb : 4096) : 1), dim3(TPC_BLOCK), 0, st, A);
+hipError_t launch_rans_batch(int count, const RansJob *jobs, int32_t L, int32_t B, void *ws,
+                             hipStream_t st) {
+    RsBatch Bt;
+    int64_t ncap = 0;
+    int nb_cap = 0;
+    size_t off = 0;
+    for (int k = 0; k < count; ++k) {
+        const RansJob &J = jobs[k];
+        RansWs W;
+        off += rans_ws_layout(ws ? (char *)ws + off : nullptr, J.n, B, &W);
+        RsArgs &A = Bt.a[k];
+        A.sym = J.sym;
+        A.n = J.n;
+        A.n_dev = J.n_dev;
+        A.n_cap = J.n;
+        A.L = L;
+        A.B = B;
+        A.nb = (int32_t)(J.n > 0 ? (J.n + B - 1) / B : 0);
+        A.mm = W.mm;
+        A.counts = W.counts;
+        A.fc = W.fc;
+        A.wcount = W.wcount;
+        A.wstart = W.wstart;
+        A.states = W.states;
+        A.scratch = W.scratch;
+        A.out = J.out;
+        A.cap = J.cap;
+        A.out_size = J.out_size;
+        A.dev_status = J.dev_status;
+        ncap = J.n > ncap ? J.n : ncap;
+        nb_cap = A.nb > nb_cap ? A.nb : nb_cap;
+    }
+    // about 16 symbols per thread, at most 2048 workgroups per array
+    const int gs = grid_over((ncap + 15) / 16, 2048);
+    const dim3 one(1, count);
+    hipLaunchKernelGGL(rs_init, one, dim3(TPC_WAVE), 0, st, Bt);
+    hipLaunchKernelGGL(rs_minmax, dim3(gs, count), dim3(TPC_BLOCK), 0, st, Bt);
+    hipLaunchKernelGGL(rs_clear, dim3(grid_over(TPC_RANS_MAX_RANGE, 1024), count), dim3(TPC_BLOCK), 0, st, Bt);
+    hipLaunchKernelGGL(rs_hist, dim3(gs, count), dim3(TPC_BLOCK), 0, st, Bt);
+    hipLaunchKernelGGL(rs_freq, one, dim3(RS_FREQ_THREADS), 0, st, Bt);
+    const int eb = (nb_cap + TPC_BLOCK / TPC_WAVE - 1) / (TPC_BLOCK / TPC_WAVE);
+    if (eb > 0) hipLaunchKernelGGL(rs_encode, dim3(eb, count), dim3(TPC_BLOCK), 0, st, Bt);
+    hipLaunchKernelGGL(rs_scan, one, dim3(TPC_BLOCK), 0, st, Bt);
+    hipLaunchKernelGGL(rs_pack, dim3(nb_cap > 0 ? (nb_cap < 4096 ? nb_cap : 4096) : 1, count), dim3(TPC_BLOCK), 0,
+                       st, Bt);
     return hipGetLastError();
+}
+
+size_t rans_batch_ws_bytes(int count, const RansJob *jobs, int32_t B) {
+    size_t off = 0;
+    for (int k = 0; k < count; ++k) off += rans_ws_layout(nullptr, jobs[k].n, B, nullptr);
+    return off;
 }

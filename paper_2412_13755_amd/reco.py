@@ -403,6 +403,51 @@ def rans_encode(symbols: torch.Tensor, scale_bits: int, block_symbols: int, out=
     return out, out_size, status
 
 
+def _rans_jobs(jobs):
+    arr = (C.RansJobC * len(jobs))()
+    for k, j in enumerate(jobs):
+        sym = j["symbols"]
+        if sym.dtype != torch.int32 or not sym.is_contiguous() or sym.device.type != "cuda":
+            raise ValueError("symbols must be contiguous int32 device tensors")
+        nd = j.get("n_device")
+        arr[k] = C.RansJobC(sym.data_ptr() if sym.numel() else None, sym.numel(),
+                            None if nd is None else nd.data_ptr(),
+                            None if j.get("out") is None else j["out"].data_ptr(),
+                            0 if j.get("out") is None else j["out"].numel(),
+                            None if j.get("out_size") is None else j["out_size"].data_ptr(),
+                            None if j.get("status") is None else j["status"].data_ptr())
+    return arr
+
+
+def rans_batch_workspace(jobs, scale_bits: int, block_symbols: int, device="cuda:0") -> torch.Tensor:
+    prm = C.RansParams(int(scale_bits), int(block_symbols))
+    b = ctypes.c_size_t()
+    arr = _rans_jobs(jobs)
+    C.check(C.lib().tpc_rans_batch_workspace_bytes(len(jobs), arr, ctypes.byref(prm), ctypes.byref(b)))
+    return torch.empty(max(int(b.value), 1), dtype=torch.uint8, device=device)
+
+
+def rans_encode_batch(jobs, scale_bits: int, block_symbols: int, ws=None):
+    """tpc_rans_encode_batch.  jobs: dicts with "symbols" (int32 device tensor,
+    its length the capacity), optional "n_device" (int64 device element with
+    the count), "out" (uint8), "out_size" (int64 element), "status" (int32
+    element); missing outputs are allocated.  Returns the jobs."""
+    for j in jobs:
+        d = j["symbols"].device
+        if j.get("out") is None:
+            j["out"] = torch.empty(rans_max_bytes(j["symbols"].numel(), 1 << 20, scale_bits, block_symbols),
+                                   dtype=torch.uint8, device=d)
+        if j.get("out_size") is None:
+            j["out_size"] = torch.zeros(1, dtype=torch.int64, device=d)
+        if j.get("status") is None:
+            j["status"] = torch.zeros(1, dtype=torch.int32, device=d)
+    ws = rans_batch_workspace(jobs, scale_bits, block_symbols, jobs[0]["symbols"].device) if ws is None else ws
+    prm = C.RansParams(int(scale_bits), int(block_symbols))
+    C.check(C.lib().tpc_rans_encode_batch(len(jobs), _rans_jobs(jobs), ctypes.byref(prm), ws.data_ptr(),
+                                          ws.numel(), _stream_handle(jobs[0]["symbols"].device)))
+    return jobs
+
+
 class KalmanChi2(torch.autograd.Function):
     """loss = sum of fit chi2 over the (fixed) seeds, as a function of the
     [n_sectors, n_rows, 2] cluster correction map; backward runs the

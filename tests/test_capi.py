@@ -29,7 +29,8 @@ def test_header_declares_the_path():
     for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
               "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
               "tpc_track_follow", "tpc_rans_encode", "tpc_rans_workspace_bytes",
-              "tpc_rans_max_bytes", "tpc_ctf_build", "tpc_status_string", "tpc_last_error"):
+              "tpc_rans_max_bytes", "tpc_ctf_build", "tpc_rans_encode_batch",
+              "tpc_rans_batch_workspace_bytes", "tpc_status_string", "tpc_last_error"):
         assert n in names
 
 
@@ -115,6 +116,14 @@ def test_rans_host_checks(capi):
     assert L.tpc_rans_max_bytes(1000, (1 << 20) + 1, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
     assert L.tpc_rans_encode(None, 10, ctypes.byref(p), None, 0, None, None, None, 0,
                              None) == capi.TPC_ERR_ARG
+    jobs = (capi.RansJobC * 2)()
+    jobs[0].n, jobs[1].n = 100, 1 << 31
+    assert L.tpc_rans_batch_workspace_bytes(2, jobs, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
+    assert L.tpc_rans_batch_workspace_bytes(0, jobs, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
+    assert L.tpc_rans_batch_workspace_bytes(25, jobs, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_ERR_ARG
+    jobs[1].n = 50
+    assert L.tpc_rans_batch_workspace_bytes(2, jobs, ctypes.byref(p), ctypes.byref(n)) == capi.TPC_OK
+    assert L.tpc_rans_encode_batch(2, jobs, ctypes.byref(p), None, 0, None) == capi.TPC_ERR_ARG
 
 
 def test_status_strings(capi):

@@ -90,3 +90,22 @@ def test_repeat_is_identical(torch_dev):
     a, _, _ = _gpu(x, 12, 4096)
     b, _, _ = _gpu(x, 12, 4096)
     assert a == b
+
+
+def test_batch_equals_single_calls_and_device_counts(torch_dev):
+    import torch
+    from paper_2412_13755_amd.reco import rans_encode_batch
+    rng = np.random.default_rng(11)
+    xs = [rng.integers(-5, 30, n).astype(np.int32) for n in (0, 1, 63, 5000, 70_000, 300_001)]
+    xs.append(rng.integers(0, 15000, 100_000).astype(np.int32))          # global histogram path
+    jobs = []
+    for x in xs:
+        cap = np.concatenate([x, rng.integers(-9, 9, 77).astype(np.int32)])   # spare entries past n
+        t = torch.from_numpy(cap).cuda()
+        jobs.append({"symbols": t, "n_device": torch.tensor([len(x)], dtype=torch.int64, device="cuda")})
+    rans_encode_batch(jobs, 16, 4096)
+    torch.cuda.synchronize()
+    for x, j in zip(xs, jobs):
+        assert int(j["status"].item()) == 0
+        got = j["out"][:int(j["out_size"].item())].cpu().numpy().tobytes()
+        assert got == oracle.rans_encode(x, 16, 4096)
