@@ -44,6 +44,10 @@ class FitParams(ctypes.Structure):
                 ("var_qpt0", ctypes.c_double)]
 
 
+class Material(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("mass", ctypes.c_double), ("chi2_cut", ctypes.c_double)]
+
+
 class FollowParams(ctypes.Structure):
     _fields_ = [("gate", ctypes.c_double), ("max_miss", ctypes.c_int32)]
 
@@ -82,6 +86,9 @@ def lib():
         L.oracle_ctf_build.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, ctypes.c_float,
                                        ctypes.c_float, P, P]
         L.oracle_ctf_build.restype = None
+        L.oracle_fit_material.argtypes = [i32, P, P, P, P, P, P, ctypes.POINTER(FitParams),
+                                           ctypes.POINTER(Material), P, P, P, P, P, P, P, P]
+        L.oracle_fit_material.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -170,6 +177,31 @@ def fit(seeds: dict, y, z, row_x, n_rows, *, bz, sigma_y, sigma_z, max_sin, var_
                      None if mp is None else _p(mp), ctypes.byref(prm), _p(out["x"]),
                      _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndf"]),
                      _p(out["status"]))
+    return out
+
+
+def fit_material(seeds: dict, y, z, row_x, *, x0, mass, chi2_cut, bz, sigma_y, sigma_z, max_sin,
+                 var_sin0, var_tgl0, var_qpt0):
+    """Fit with multiple scattering (radiation length x0 cm, mass GeV) and
+    rejection of hits above chi2_cut.  Returns the fit's dict plus
+    rejected (uint8 per seed hit) and margin per track."""
+    offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
+    hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
+    fr = np.ascontiguousarray(seeds["first_row"], dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    rx = np.ascontiguousarray(row_x, dtype=np.float64)
+    T = len(offsets) - 1
+    prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
+    mat = Material(float(x0), float(mass), float(chi2_cut))
+    out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
+               ndf=np.empty(T, np.int32), status=np.empty(T, np.int32),
+               rejected=np.zeros(max(hits.size, 1), np.uint8), margin=np.empty(T))
+    lib().oracle_fit_material(T, _p(offsets), _p(hits), _p(fr), _p(y), _p(z), _p(rx), ctypes.byref(prm),
+                              ctypes.byref(mat), _p(out["x"]), _p(out["par"]), _p(out["cov"]),
+                              _p(out["chi2"]), _p(out["ndf"]), _p(out["status"]), _p(out["rejected"]),
+                              _p(out["margin"]))
+    out["rejected"] = out["rejected"][:hits.size]
     return out
 
 

@@ -361,17 +361,12 @@ static int32_t update(double *p, double *C, double my, double mz, double vy, dou
     return finite ? 0 : 3;
 }
 
-/* Inward fit of n points at planes xs (ascending), as described above: state
- * p and full covariance C at xs[0] (or where the filter stopped), chi2, status. */
-static int32_t fit_points(int32_t n, const double *xs, const double *ys, const double *zs,
-                          const oracle_fit_params *prm, double *xo, double *p, double *C, double *chi2o)
+/* Exact circle through hits n-1 (outermost), (n-1)/2 and 0: the state at
+ * x of hit n-1 and the start covariance; returns 0 or 1 (degenerate points,
+ * or a direction at the start not towards +x or with |sin phi| >= max_sin). */
+static int32_t start_points(int32_t n, const double *xs, const double *ys, const double *zs,
+                            const oracle_fit_params *prm, double *p, double *C)
 {
-    *chi2o = 0.0;
-    *xo = 0.0;
-    for (int i = 0; i < 5; ++i) p[i] = 0.0;
-    for (int i = 0; i < 25; ++i) C[i] = 0.0;
-    if (n < 3) return 1;
-    /* start */
     int a = n - 1, b = (n - 1) / 2, c = 0;
     double bcx = xs[b] - xs[c], bcy = ys[b] - ys[c];
     double abx = xs[a] - xs[b], aby = ys[a] - ys[b];
@@ -392,11 +387,27 @@ static int32_t fit_points(int32_t n, const double *xs, const double *ys, const d
     p[3] = (zs[a] - zs[c]) / (lac * g_of(uc));
     p[4] = -kap0 / (C_LIGHT * prm->bz);
     if (!st && (!(cos(phiA) > 0.0) || !(fabs(p[2]) < prm->max_sin))) st = 1;
+    for (int i = 0; i < 25; ++i) C[i] = 0.0;
     C[0] = prm->sigma_y * prm->sigma_y;
     C[6] = prm->sigma_z * prm->sigma_z;
     C[12] = prm->var_sin0;
     C[18] = prm->var_tgl0;
     C[24] = prm->var_qpt0;
+    return st;
+}
+
+/* Inward fit of n points at planes xs (ascending), as described above: state
+ * p and full covariance C at xs[0] (or where the filter stopped), chi2, status. */
+static int32_t fit_points(int32_t n, const double *xs, const double *ys, const double *zs,
+                          const oracle_fit_params *prm, double *xo, double *p, double *C, double *chi2o)
+{
+    *chi2o = 0.0;
+    *xo = 0.0;
+    for (int i = 0; i < 5; ++i) p[i] = 0.0;
+    for (int i = 0; i < 25; ++i) C[i] = 0.0;
+    if (n < 3) return 1;
+    int32_t st = start_points(n, xs, ys, zs, prm, p, C);
+    int a = n - 1;
     double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
     double chi2 = 0.0;
     double xcur = xs[a];
@@ -671,4 +682,94 @@ void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits
         if (2 * owned < nh) status[i] = 4;
     }
     free(owner);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fit with material: the fit above plus multiple scattering in the gas and  */
+/* rejection of outlying hits.  Before each inward step from plane a to      */
+/* plane b (state at a, after its update), the scattering of the segment     */
+/* between them enters the covariance: path ds = |dx| sqrt(1+t^2) /          */
+/* sqrt(1-s^2), momentum p = sqrt(1+t^2)/|w|, beta = p / sqrt(p^2 + m^2),     */
+/* theta0 = 0.0136/(beta p) sqrt(ds/X0) (1 + 0.038 ln(ds/X0)) (Highland), and */
+/* with the two projected angles independent (phi changes by theta/cos       */
+/* lambda, lambda by theta):                                                 */
+/*   C_ss += th2 (1-s^2)(1+t^2), C_tt += th2 (1+t^2)^2,                     */
+/*   C_tw += th2 t w (1+t^2),    C_ww += th2 t^2 w^2     (th2 = theta0^2)    */
+/* (no noise for X0 infinite or w = 0).  After the step, a hit whose         */
+/* predicted-residual chi2 exceeds chi2_cut is not used (flagged; the state  */
+/* goes on from the prediction).  chi2 sums the used hits, ndf = 2 used - 5  */
+/* with the outermost (start) hit counted as used.  margin = smallest        */
+/* |chi2 - cut| / (cut + 1) over the hits' decisions.                        */
+/* ------------------------------------------------------------------------ */
+static void add_scattering(const double *p, double dx, const oracle_material *m, double *C)
+{
+    double s = p[2], t = p[3], w = p[4];
+    if (!(m->x0 < INFINITY) || w == 0.0) return;
+    double t2 = 1.0 + t * t;
+    double ds = fabs(dx) * sqrt(t2) / sqrt(1.0 - s * s);
+    double pm = sqrt(t2) / fabs(w);
+    double beta = pm / sqrt(pm * pm + m->mass * m->mass);
+    double xr = ds / m->x0;
+    double th = 0.0136 / (beta * pm) * sqrt(xr) * (1.0 + 0.038 * log(xr));
+    double th2 = th * th;
+    C[2 * 5 + 2] += th2 * (1.0 - s * s) * t2;
+    C[3 * 5 + 3] += th2 * t2 * t2;
+    C[3 * 5 + 4] += th2 * t * w * t2;
+    C[4 * 5 + 3] += th2 * t * w * t2;
+    C[4 * 5 + 4] += th2 * t * t * w * w;
+}
+
+static void fit_one_material(int32_t n, const int32_t *hit, int32_t row0, const double *y, const double *z,
+                             const double *row_x, const oracle_fit_params *prm, const oracle_material *mat,
+                             double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto,
+                             uint8_t *rej, double *margin)
+{
+    double xs[512], ys[512], zs[512], C[25], p[5];
+    *margin = INFINITY;
+    for (int k = 0; k < n && k < 512; ++k) rej[k] = 0;
+    *ndfo = 2 * n - 5;
+    *chi2o = 0.0;
+    *xo = 0.0;
+    for (int i = 0; i < 5; ++i) po[i] = 0.0;
+    for (int i = 0; i < 15; ++i) co[i] = 0.0;
+    if (n < 3 || n > 512) { *sto = 1; return; }
+    for (int k = 0; k < n; ++k) { xs[k] = row_x[row0 + k]; ys[k] = y[hit[k]]; zs[k] = z[hit[k]]; }
+    int32_t st = start_points(n, xs, ys, zs, prm, p, C);
+    double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
+    double chi2 = 0.0, xcur = xs[n - 1];
+    int32_t used = 1;
+    for (int k = n - 2; k >= 0 && !st; --k) {
+        double dx = xs[k] - xs[k + 1];
+        add_scattering(p, dx, mat, C);
+        if (predict(p, C, dx, prm)) { st = 2; break; }
+        xcur = xs[k];
+        double chi = resid_chi2(p, C, ys[k], zs[k], vy, vz);
+        if (isfinite(chi)) {
+            double mg = fabs(chi - mat->chi2_cut) / (mat->chi2_cut + 1.0);
+            if (mg < *margin) *margin = mg;
+        }
+        if (chi > mat->chi2_cut) { rej[k] = 1; continue; }
+        if (update(p, C, ys[k], zs[k], vy, vz, &chi2)) { st = 3; break; }
+        ++used;
+    }
+    *xo = xcur;
+    for (int i = 0; i < 5; ++i) po[i] = p[i];
+    pack_cov(C, co);
+    *chi2o = chi2;
+    *ndfo = 2 * used - 5;
+    *sto = st;
+}
+
+void oracle_fit_material(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                         const int32_t *first_row, const double *y, const double *z, const double *row_x,
+                         const oracle_fit_params *prm, const oracle_material *mat,
+                         double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
+                         uint8_t *rejected, double *margin)
+{
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        fit_one_material(offsets[i + 1] - offsets[i], hits + offsets[i], first_row[i], y, z, row_x, prm, mat,
+                         &x_out[i], &par[(size_t)i * 5], &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i],
+                         rejected + offsets[i], &margin[i]);
+    }
 }

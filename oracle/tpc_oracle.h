@@ -16,6 +16,12 @@ typedef struct oracle_follow_params {
     int32_t max_miss;   /* consecutive rows without pickup that are crossed */
 } oracle_follow_params;
 
+typedef struct oracle_material {
+    double x0;          /* radiation length of the gas, cm (infinite: no scattering) */
+    double mass;        /* mass hypothesis, GeV */
+    double chi2_cut;    /* a hit whose predicted-residual chi2 exceeds this is not used */
+} oracle_material;
+
 void oracle_set_threads(int n);
 int oracle_max_threads(void);
 
@@ -45,6 +51,12 @@ void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits
                    const oracle_fit_params *prm, const oracle_follow_params *fp,
                    int32_t *rows, double *x_out, double *par, double *cov, double *chi2,
                    int32_t *ndf, int32_t *status, double *margin);
+
+void oracle_fit_material(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                         const int32_t *first_row, const double *y, const double *z, const double *row_x,
+                         const oracle_fit_params *prm, const oracle_material *mat,
+                         double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
+                         uint8_t *rejected, double *margin);
 
 /* rANS coder of integer arrays (rans_oracle.c) */
 #include <stddef.h>

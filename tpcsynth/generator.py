@@ -465,3 +465,110 @@ def make_config(k: int, scale: float = 1.0, keep_truth: bool = False, **over) ->
     fr.meta["name"] = CONFIG_NAMES[k]
     fr.meta["scale"] = scale
     return fr
+
+
+HIGHLAND = 0.0136                 # GeV, multiple-scattering constant
+PION_MASS = 0.13957               # GeV
+
+
+def highland_theta0(p, beta, x_over_x0):
+    """Width of the projected scattering angle (Highland): 13.6 MeV / (beta p) sqrt(x/X0) (1 + 0.038 ln(x/X0))."""
+    return HIGHLAND / (beta * p) * np.sqrt(x_over_x0) * (1.0 + 0.038 * np.log(x_over_x0))
+
+
+def make_scattering_frame(*, n_tracks: int = 200, seed: int = 0, x0_cm: float = 300.0,
+                          mass: float = PION_MASS, inv_pt=(0.5, 3.0), phi_range=(-0.06, 0.06),
+                          tgl_range=(-0.8, 0.8), n_rows: int = 152, bz: float = 0.5,
+                          sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True) -> Frames:
+    """One sector (alpha = 0) of tracks stepped plane by plane with multiple scattering.
+
+    Each track starts at the origin; from one pad-row plane to the next its
+    exact helix in global coordinates (circle in x-y, straight in z against
+    the transverse path) is intersected with the plane; after every crossing
+    but the first, the direction receives two independent Gaussian kicks of
+    width theta0 (Highland, with the 3-D path of the segment just traversed
+    and the momentum and velocity for the given mass): one in the bending
+    plane (phi changes by theta1 / cos(lambda)) and one in lambda; the total
+    momentum is kept, so pT and the curvature follow lambda.  A track stops
+    when it misses the next plane or leaves the row width.  Truth at every
+    cluster: y, z and the direction (s, t, w) of the segment leaving it.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    row_x = make_row_x(n_rows).astype(np.float64)
+    n = n_tracks
+    q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    ipt = rng.uniform(inv_pt[0], inv_pt[1], n)
+    phi = rng.uniform(phi_range[0], phi_range[1], n)
+    lam = np.arctan(rng.uniform(tgl_range[0], tgl_range[1], n))
+    p = 1.0 / (ipt * np.cos(lam))                      # total momentum, kept
+    X = np.zeros(n)
+    Y = np.zeros(n)
+    Z = np.zeros(n)
+    alive = np.ones(n, bool)
+    recs = []
+    for k in range(n_rows):
+        xk = row_x[k]
+        pt = p * np.cos(lam)
+        kap = -C_LIGHT * bz * q / pt                 # signed curvature, ccw > 0
+        cx = X - np.sin(phi) / kap
+        cy = Y + np.cos(phi) / kap
+        R = 1.0 / np.abs(kap)
+        h2 = R * R - (xk - cx) ** 2
+        ok = alive & (h2 > 0)
+        h = np.sqrt(np.where(ok, h2, 0.0))
+        # the crossing reached first along the motion: smallest positive turn
+        th0 = np.arctan2(Y - cy, X - cx)
+        best_turn = np.full(n, np.inf)
+        best_y = np.zeros(n)
+        for sg in (1.0, -1.0):
+            yc = cy + sg * h
+            th = np.arctan2(yc - cy, xk - cx)
+            turn = np.where(kap > 0, th - th0, th0 - th)
+            turn = np.mod(turn, 2 * math.pi)
+            better = ok & (turn > 1e-12) & (turn < best_turn)
+            best_turn = np.where(better, turn, best_turn)
+            best_y = np.where(better, yc, best_y)
+        ok &= np.isfinite(best_turn) & (best_turn < math.pi / 2)
+        sxy = np.where(ok, R * best_turn, 0.0)
+        Xn, Yn = np.full(n, xk), best_y
+        Zn = Z + np.tan(lam) * sxy
+        phin = phi + kap * sxy
+        ok &= np.abs(Yn) <= xk * TAN10
+        ok &= np.abs(Zn) <= DRIFT_LENGTH
+        alive = ok
+        if not alive.any():
+            break
+        # direction leaving this plane: kicked after every crossing but the first
+        lamn = lam.copy()
+        if k > 0:
+            path = sxy * np.sqrt(1.0 + np.tan(lam) ** 2)
+            beta = p / np.sqrt(p * p + mass * mass)
+            th0s = highland_theta0(p, beta, np.maximum(path, 1e-12) / x0_cm)
+            k1 = rng.normal(0.0, 1.0, n) * th0s
+            k2 = rng.normal(0.0, 1.0, n) * th0s
+            phin = phin + np.where(alive, k1 / np.cos(lam), 0.0)
+            lamn = lam + np.where(alive, k2, 0.0)
+        idx = np.nonzero(alive)[0]
+        recs.append((idx, np.full(idx.size, k), Yn[idx], Zn[idx], np.sin(phin[idx]), np.tan(lamn[idx]),
+                     q[idx] / (p[idx] * np.cos(lamn[idx]))))
+        X, Y, Z, phi, lam = Xn, np.where(alive, Yn, Y), np.where(alive, Zn, Z), phin, lamn
+    tid = np.concatenate([r[0] for r in recs])
+    row = np.concatenate([r[1] for r in recs])
+    yt = np.concatenate([r[2] for r in recs])
+    zt = np.concatenate([r[3] for r in recs])
+    st_ = np.concatenate([r[4] for r in recs])
+    tt_ = np.concatenate([r[5] for r in recs])
+    wt_ = np.concatenate([r[6] for r in recs])
+    ym = yt + (rng.normal(0.0, sigma_y, yt.size) if smear else 0.0)
+    zm = zt + (rng.normal(0.0, sigma_z, zt.size) if smear else 0.0)
+    order = np.lexsort((tid, row))
+    counts = np.bincount(row, minlength=n_rows)
+    offs = np.zeros(n_rows + 1, dtype=np.int32)
+    np.cumsum(counts, out=offs[1:])
+    fr = Frames(1, 1, n_rows, row_x.astype(np.float32), offs, ym[order].astype(np.float32),
+                zm[order].astype(np.float32), bz, sigma_y, sigma_z)
+    fr.track_of = tid[order].astype(np.int32)
+    fr.y_true, fr.z_true = yt[order], zt[order]
+    fr.s_true, fr.t_true, fr.w_true = st_[order], tt_[order], wt_[order]
+    fr.meta = dict(n_tracks=n, seed=seed, x0_cm=x0_cm, mass=mass)
+    return fr
