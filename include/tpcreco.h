@@ -177,6 +177,34 @@ tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *frames,
                           const tpc_seeds *seeds, const float *map, tpc_tracks *tracks,
                           void *ckpt, size_t ckpt_bytes, void *ws, size_t ws_bytes, void *stream);
 
+/* Fit with material: tpc_kalman_fit (no map, no checkpoints) plus multiple
+ * scattering in the gas as process noise and the rejection of outlying
+ * hits -- a variant of the fit the paper's reconstruction implies but does
+ * not describe.  Before each inward step from plane a to plane b (state p at
+ * a), the scattering of that segment enters the covariance: path
+ * ds = |x_b - x_a| sqrt(1 + t^2) / sqrt(1 - s^2), momentum P = sqrt(1 + t^2)/|w|,
+ * beta = P / sqrt(P^2 + mass^2), theta0 = 0.0136 / (beta P) sqrt(ds/x0)
+ * (1 + 0.038 ln(ds/x0)) (Highland), th2 = theta0^2:
+ *   C_ss += th2 (1 - s^2)(1 + t^2), C_tt += th2 (1 + t^2)^2,
+ *   C_tw += th2 t w (1 + t^2), C_ww += th2 t^2 w^2
+ * (none for x0 infinite or w = 0).  After the helix step, a hit whose
+ * predicted-residual chi2 exceeds chi2_cut is not used: the filter goes on
+ * from the prediction and rejected[seed hit] = 1 (else 0).  chi2 sums the
+ * used hits; ndf = 2 (used hits + 1) - 5, the outermost (start) hit
+ * counted.  Double precision throughout.  mat: host pointer; x0 > 0 (cm,
+ * infinity = no scattering), mass >= 0 (GeV), chi2_cut > 0 (infinity = keep
+ * all).  rejected: optional device uint8 [cap_hits].  ws: TPC_STAGE_FIT
+ * workspace. */
+typedef struct tpc_material {
+    float x0;
+    float mass;
+    float chi2_cut;
+} tpc_material;
+tpc_status tpc_kalman_fit_material(const tpc_context *ctx, const tpc_frames *frames,
+                                   const tpc_seeds *seeds, const tpc_material *mat,
+                                   tpc_tracks *tracks, uint8_t *rejected, void *ws, size_t ws_bytes,
+                                   void *stream);
+
 /* Checkpoint-buffer bytes for seeds of these capacities (host call). */
 tpc_status tpc_ckpt_bytes(const tpc_context *ctx, const tpc_seeds *seeds, size_t *bytes);
 

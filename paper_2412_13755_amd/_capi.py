@@ -62,6 +62,10 @@ class Tune(ctypes.Structure):
     _fields_ = [("grid", i32), ("sort_fit", i32)]
 
 
+class Material(ctypes.Structure):
+    _fields_ = [("x0", f32), ("mass", f32), ("chi2_cut", f32)]
+
+
 class FollowParams(ctypes.Structure):
     _fields_ = [("gate_chi2", f32), ("max_miss", i32)]
 
@@ -130,6 +134,9 @@ SIGNATURES = {
                             f32, f32, ctypes.POINTER(CtfArraysC), P, ctypes.c_size_t, P]),
     "tpc_rans_batch_workspace_bytes": (i32, [i32, P, ctypes.POINTER(RansParams), ctypes.POINTER(ctypes.c_size_t)]),
     "tpc_rans_encode_batch": (i32, [i32, P, ctypes.POINTER(RansParams), P, ctypes.c_size_t, P]),
+    "tpc_kalman_fit_material": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
+                                      ctypes.POINTER(Material), ctypes.POINTER(TracksC), P, P,
+                                      ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),

@@ -30,6 +30,7 @@ SOURCES = {
     "tpc_follow.hip": [],
     "tpc_rans.hip": [],
     "tpc_ctf.hip": [],
+    "tpc_fit_ms.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

@@ -10,6 +10,7 @@
 #include <new>
 
 #include "tpc_internal.hpp"
+#include "tpc_fit_ms.hpp"
 
 namespace {
 
@@ -247,6 +248,24 @@ tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *fr, const tp
     if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds, sd->cap_hits)))) return s;
     if (sd->cap_seeds == 0) return TPC_OK;
     hipError_t e = launch_fit(ctx, fr, sd, map, tr, (double *)ckpt, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
+}
+
+tpc_status tpc_kalman_fit_material(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                                   const tpc_material *mat, tpc_tracks *tr, uint8_t *rejected, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if (!mat) return fail(TPC_ERR_ARG, "null material");
+    if (!(mat->x0 > 0.f)) return fail(TPC_ERR_ARG, "x0 must be > 0");
+    if (!(mat->mass >= 0.f) || !isfinite(mat->mass)) return fail(TPC_ERR_ARG, "mass must be finite and >= 0");
+    if (!(mat->chi2_cut > 0.f)) return fail(TPC_ERR_ARG, "chi2_cut must be > 0");
+    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds, sd->cap_hits)))) return s;
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_fit_material(ctx, fr, sd, mat, tr, rejected, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
 }
 

@@ -236,6 +236,21 @@ class Reco:
                                        ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return tracks
 
+    def fit_material(self, frames: DeviceFrames, seeds: Seeds, x0: float, mass: float, chi2_cut: float,
+                     tracks: Optional[Tracks] = None, rejected: Optional[torch.Tensor] = None, ws=None):
+        """tpc_kalman_fit_material: returns (Tracks, rejected uint8 per seed hit)."""
+        tracks = self.alloc_tracks(seeds) if tracks is None else tracks
+        if rejected is None:
+            rejected = torch.zeros(max(seeds.hits.numel(), 1), dtype=torch.uint8, device=self.device)
+        ws = self.workspace(frames) if ws is None else ws
+        mat = C.Material(float(x0), float(mass), float(chi2_cut))
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_kalman_fit_material(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
+                                                ctypes.byref(mat), ctypes.byref(tc), rejected.data_ptr(),
+                                                ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return tracks, rejected
+
     def follow(self, frames: DeviceFrames, seeds: Seeds, gate_chi2: float, max_miss: int,
                rows: Optional[torch.Tensor] = None, tracks: Optional[Tracks] = None, ws=None):
         """Track following of every seed and duplicate removal (tpc_track_follow).

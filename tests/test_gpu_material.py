@@ -1,0 +1,88 @@
+"""GPU parity of the fit with material (tpc_kalman_fit_material through the
+C-ABI) against the oracle on the oracle's seeds (the GPU's are checked to be
+the same first).  Rejection flags must equal the oracle's for every track
+whose hits' chi2 all lie farther than 1e-6 (relative) from the cut; the
+refits are held to the fit tolerances (1e-4 parameters, 1e-3 covariance and
+chi2)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import NB, MIN_HITS, FIT
+from tests import parity
+from tpcsynth import make_config, make_scattering_frame, PION_MASS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def check(fr, x0, cut, label, displace=None):
+    import torch
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    print("[material] %s: N=%d x0=%g cut=%g" % (label, fr.n_clusters, x0, cut), flush=True)
+    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT), "cuda:0")
+    ru, rd = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    rs = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, MIN_HITS)
+    y = fr.y
+    if displace is not None:
+        y = fr.y.copy()
+        y[rs["hits"][displace]] += np.float32(12 * fr.sigma_y)
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    torch.cuda.synchronize()
+    parity.assert_seeds_equal(seeds.to_numpy(), rs)
+    if displace is not None:        # fit the displaced clusters with the same seeds
+        fr2 = type(fr)(**{**fr.__dict__, "y": y})
+        dfr = reco.upload(fr2)
+        seeds.hit_yz = None
+    tr, rej = reco.fit_material(dfr, seeds, x0, PION_MASS, cut)
+    torch.cuda.synchronize()
+    T = len(rs["offsets"]) - 1
+    H = rs["hits"].size
+    g = {k: getattr(tr, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "chi2", "ndf", "status")}
+    grej = rej[:H].cpu().numpy()
+    r = oracle.fit_material(rs, y, fr.z, fr.row_x, x0=x0, mass=PION_MASS, chi2_cut=cut, **FIT)
+    robust = r["margin"] >= 1e-6
+    assert (~robust).sum() <= max(2, T // 1000), (~robust).sum()
+    seg = np.repeat(np.arange(T), np.diff(rs["offsets"]))
+    np.testing.assert_array_equal(grej[robust[seg]], r["rejected"][robust[seg]])
+    sub = lambda d: {k: np.asarray(v)[robust] for k, v in d.items() if k in ("x", "par", "cov", "chi2", "ndf", "status")}
+    st = parity.compare_fit(sub(g), sub(r))
+    st.update(rejected=int(r["rejected"].sum()), fragile=int((~robust).sum()))
+    print("[material] %s: %s" % (label, st), flush=True)
+    return st, r
+
+
+@pytest.mark.parametrize("x0", [50.0, 300.0])
+def test_scattering_frames(torch_dev, x0):
+    fr = make_scattering_frame(n_tracks=400, seed=21, x0_cm=x0, inv_pt=(0.5, 5.0))
+    check(fr, x0, 30.0, "stepped tracks")
+
+
+def test_headline_frame_gas_radiation_length(torch_dev):
+    st, r = check(make_config(1), 2870.0, 30.0, "full-tpc-event-1e4")
+    assert st["compared"] > 20000
+
+
+def test_displaced_hits(torch_dev):
+    fr = make_scattering_frame(n_tracks=300, seed=5, x0_cm=300.0)
+    up, dn = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    sd = oracle.ca_seed(fr.row_offsets, up, dn, 1, fr.n_rows, MIN_HITS)
+    rng = np.random.default_rng(6)
+    off = sd["offsets"]
+    planted = np.array([off[i] + int(rng.integers(1, (off[i + 1] - off[i]) // 2 - 1))
+                        for i in range(len(off) - 1) if off[i + 1] - off[i] >= 20])
+    st, r = check(fr, 300.0, 30.0, "displaced", displace=planted)
+    assert r["rejected"][planted].mean() > 0.95
+
+
+def test_no_material_is_the_plain_fit(torch_dev):
+    fr = make_config(0)
+    check(fr, float("inf"), float("inf"), "no material")
