@@ -30,6 +30,8 @@ Extra legs, reported beside the headline value:
            rANS coding of all of them in one batch (scale 2^14, blocks of
            2^13, counts read on the device), eagerly and as a graph;
            clusters/s and bits per cluster
+  material the fit with multiple scattering (radiation length 2870 cm, pion
+           mass) and outlier rejection (chi2 > 30) on the headline seeds
   copy     a 1 GiB device copy (reference for the HBM traffic counters; run
            alone with --legs copy)
   stages   the three stage calls on the headline workload, --steps times,
@@ -76,7 +78,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf")
+    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf,material")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--stages-workload", type=int, default=1,
@@ -476,6 +478,45 @@ def leg_ctf(args):
             "G_symbols_per_s": round(sum(counts) / ms / 1e6, 3)}
 
 
+MAT_X0, MAT_CUT = 2870.0, 30.0
+
+
+def leg_material(args):
+    """tpc_kalman_fit_material on the headline seeds, HIP events on the launch stream."""
+    import torch
+    from tpcsynth import make_config, PION_MASS
+    fr = make_config(1)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    ws = reco.workspace(dfr)
+    up, dn = reco.neighbours(dfr, ws=ws)
+    seeds = reco.seed(dfr, up, dn, ws=ws)
+    tr, rej = reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, ws=ws)
+    torch.cuda.synchronize()
+    T, H = int(seeds.n_seeds.item()), int(seeds.n_hits.item())
+    stream = torch.cuda.current_stream()
+    steps = max(5, args.steps)
+    for _ in range(2):
+        reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, tr, rej, ws)
+    evs = []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, tr, rej, ws)
+        e[1].record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    flops = (FLOP_FIT_PER_HIT + 40) * H            # the fit's step and update, plus the noise term
+    return {"workload": fr.meta["name"], "seeds": T, "seed_hits": H, "x0_cm": MAT_X0, "chi2_cut": MAT_CUT,
+            "rejected_hits": int(rej[:H].sum()), "ms": round(ms, 5),
+            "tracks_per_s": round(T / ms * 1e3, 1),
+            "roofline": {"bound": "alu", "achieved": round(flops / (ms * 1e-3) / 1e12, 4),
+                         "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(flops / (ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS, 5),
+                         "kernel": "fit_ms_tracks", "algorithmic_flops": int(flops)}}
+
+
 def leg_copy(args):
     """A plain device copy of known size (calibrates the HBM traffic counters)."""
     import torch
@@ -534,6 +575,9 @@ def main():
     if legs == {"follow"}:
         print(json.dumps({"follow": leg_follow(args, not args.no_cpu)}), flush=True)
         return
+    if legs == {"material"}:
+        print(json.dumps({"material": leg_material(args)}), flush=True)
+        return
     if legs == {"ctf"}:
         print(json.dumps({"ctf": leg_ctf(args)}), flush=True)
         return
@@ -559,6 +603,8 @@ def main():
         out["rans"] = leg_rans(args, not args.no_cpu)
     if "ctf" in legs:
         out["ctf"] = leg_ctf(args)
+    if "material" in legs:
+        out["material"] = leg_material(args)
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:
