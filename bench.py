@@ -388,12 +388,30 @@ def leg_rans(args, with_cpu=True):
     ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     nbytes = int(size.item())
     sps = RANS_N / (ms * 1e-3)
+    # the decoder on the same stream
+    from paper_2412_13755_amd.reco import rans_decode
+    dec = torch.empty(RANS_N, dtype=torch.int32, device="cuda")
+    dws = None
+    for _ in range(2):
+        _, dn, dst = rans_decode(out, nbytes, RANS_N, out=dec, ws=dws)
+    torch.cuda.synchronize()
+    assert int(dst.item()) == 0 and int(dn.item()) == RANS_N and bool(torch.equal(dec, x))
+    devs = []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        rans_decode(out, nbytes, RANS_N, out=dec, ws=dws)
+        e[1].record(stream)
+        devs.append(e)
+    torch.cuda.synchronize()
+    ms_dec = float(np.mean([e[0].elapsed_time(e[1]) for e in devs]))
     alg = 4 * RANS_N + nbytes                      # read the symbols, write the stream
     res = {"workload": "normal-sigma12-2^28", "symbols": RANS_N, "scale_bits": RANS_L,
            "block_symbols": RANS_B, "stream_bytes": nbytes,
            "bits_per_symbol": round(8.0 * nbytes / RANS_N, 4), "ms": round(ms, 4),
            "G_symbols_per_s": round(sps / 1e9, 3),
            "vs_paper_cpu": round(sps / RANS_PAPER_SYMBOLS_PER_S, 2),
+           "decode_ms": round(ms_dec, 4), "decode_G_symbols_per_s": round(RANS_N / ms_dec / 1e6, 3),
            "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -381,6 +381,18 @@ tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *frames, const
                          const int32_t *rows, const tpc_tracks *tracks, float q_y, float q_z,
                          const tpc_ctf_arrays *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Decodes a stream of tpc_rans_encode (device, 4-byte aligned, `size`
+ * bytes) into symbols (device int32, capacity `cap` < 2^31).  *n_out (device
+ * int64) receives the stream's symbol count; *dev_status (device int32)
+ * TPC_OK, TPC_ERR_CAPACITY (more symbols than cap; nothing written) or
+ * TPC_ERR_ARG (malformed: bad header, frequencies not summing to 2^L, a
+ * block not returning its coders to 2^16 or not using exactly its words;
+ * the symbols written are then meaningless).  Every read is bounds-checked
+ * against `size`.  ws: tpc_rans_decode_workspace_bytes() bytes. */
+tpc_status tpc_rans_decode_workspace_bytes(size_t *bytes);
+tpc_status tpc_rans_decode(const void *in, size_t size, int32_t *symbols, int64_t cap, int64_t *n_out,
+                           int32_t *dev_status, void *ws, size_t ws_bytes, void *stream);
+
 /* Several arrays (1..TPC_RANS_BATCH_MAX) coded by one set of launches, each
  * exactly as tpc_rans_encode would (same parameters for all).  An array's
  * symbol count is n, or, when n_device is not NULL, the device int64 it

@@ -137,6 +137,8 @@ SIGNATURES = {
     "tpc_kalman_fit_material": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
                                       ctypes.POINTER(Material), ctypes.POINTER(TracksC), P, P,
                                       ctypes.c_size_t, P]),
+    "tpc_rans_decode_workspace_bytes": (i32, [ctypes.POINTER(ctypes.c_size_t)]),
+    "tpc_rans_decode": (i32, [P, ctypes.c_size_t, P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),
     "tpc_status_string": (ctypes.c_char_p, [i32]),
     "tpc_last_error": (ctypes.c_char_p, []),

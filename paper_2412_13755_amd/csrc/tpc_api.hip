@@ -11,6 +11,7 @@
 
 #include "tpc_internal.hpp"
 #include "tpc_fit_ms.hpp"
+#include "tpc_rans_dec.hpp"
 
 namespace {
 
@@ -470,6 +471,26 @@ tpc_status tpc_rans_encode_batch(int32_t count, const tpc_rans_job *jobs, const 
     if ((s = check_ws(ws, ws_bytes, rans_batch_ws_bytes(count, J, p->block_symbols)))) return s;
     hipError_t e = launch_rans_batch(count, J, p->scale_bits, p->block_symbols, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "rANS kernels");
+}
+
+tpc_status tpc_rans_decode_workspace_bytes(size_t *bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(TPC_ERR_ARG, "null bytes");
+    *bytes = rans_decode_ws_bytes();
+    return TPC_OK;
+}
+
+tpc_status tpc_rans_decode(const void *in, size_t size, int32_t *symbols, int64_t cap, int64_t *n_out,
+                           int32_t *dev_status, void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!in || !n_out || !dev_status) return fail(TPC_ERR_ARG, "null stream, count or status");
+    if (((uintptr_t)in & 3) != 0) return fail(TPC_ERR_ARG, "stream not 4-byte aligned");
+    if (cap < 0 || cap >= ((int64_t)1 << 31)) return fail(TPC_ERR_ARG, "cap outside 0..2^31-1");
+    if (cap > 0 && !symbols) return fail(TPC_ERR_ARG, "null symbols");
+    tpc_status s = check_ws(ws, ws_bytes, rans_decode_ws_bytes());
+    if (s) return s;
+    hipError_t e = launch_rans_decode(in, (uint64_t)size, symbols, cap, n_out, dev_status, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "rANS decoder kernels");
 }
 
 int32_t tpc_persistent_grid(const tpc_context *ctx) { return ctx ? ctx->persist_grid : 0; }

@@ -21,11 +21,13 @@
 //               by ballot and prefix popcount in the order coders 63 .. 0
 //               push them, into a per-block scratch stack
 //  rs_scan      exclusive scan of the blocks' word counts
+//  rd_*         the decoder (see below)
 //  rs_pack      the stream: header, frequency table, block word offsets,
 //               final coder states, every block's stack reversed; nothing is
 //               written and the status says TPC_ERR_CAPACITY when the
 //               stream (its exact size is reported) does not fit
 #include "tpc_internal.hpp"
+#include "tpc_rans_dec.hpp"
 
 #define RS_LANES 64
 #define RS_HEAD 40
@@ -438,6 +440,149 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsBatch Bt) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Decoder.  rd_head parses and checks the header, rd_table builds the
+// cumulative frequencies and a per-slot table (symbol, frequency, slot minus
+// the symbol's cumulative start), rd_decode runs each block forwards with one
+// wavefront: the lanes whose state drops below 2^16 take the next words in
+// lane order (ballot rank), which is the order the encoder stored them.
+
+struct RdArgs {
+    const uint8_t *in;
+    uint64_t size;
+    int32_t *out;
+    int64_t cap;
+    int64_t *n_out;
+    int32_t *dev_status;
+    int64_t *hd;          // parsed header: n, lo, R, L, B, nb, word area offset, status
+    uint32_t *cum;        // [TPC_RANS_MAX_RANGE + 1]
+    uint4 *slot;          // [2^16]
+};
+
+__device__ inline uint32_t get32(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
+
+__global__ void rd_head(RdArgs A) {
+    if (threadIdx.x != 0) return;
+    int st = TPC_OK;
+    int64_t n = 0, lo = 0, R = 0, L = 0, B = 0, nb = 0, head = 0;
+    if (A.size < RS_HEAD || get32(A.in) != RS_MAGIC || get32(A.in + 4) != 1u) {
+        st = TPC_ERR_ARG;
+    } else {
+        n = (int64_t)((uint64_t)get32(A.in + 8) | ((uint64_t)get32(A.in + 12) << 32));
+        lo = (int32_t)get32(A.in + 16);
+        R = get32(A.in + 20);
+        L = get32(A.in + 24);
+        B = get32(A.in + 28);
+        nb = get32(A.in + 32);
+        head = RS_HEAD + 4 * R + 4 * (nb + 1) + 4 * (int64_t)RS_LANES * nb;
+        if (n < 0 || n >= ((int64_t)1 << 31) || L < 1 || L > 16 || B < RS_LANES || B % RS_LANES ||
+            R > TPC_RANS_MAX_RANGE || nb != (n > 0 ? (n + B - 1) / B : 0) || (n > 0 && R < 1) ||
+            (uint64_t)head > A.size)
+            st = TPC_ERR_ARG;
+        else if (n > A.cap)
+            st = TPC_ERR_CAPACITY;
+    }
+    int64_t *h = A.hd;
+    h[0] = n; h[1] = lo; h[2] = R; h[3] = L; h[4] = B; h[5] = nb; h[6] = head; h[7] = st;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rd_table(RdArgs A) {
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    __shared__ int bad;
+    if (A.hd[7] != TPC_OK) return;
+    const int64_t R = A.hd[2], L = A.hd[3];
+    const uint32_t M = 1u << L;
+    const uint32_t *f = reinterpret_cast<const uint32_t *>(A.in + RS_HEAD);
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    // 64-bit running sum: a table summing past M (however it would wrap) is refused
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < R; c0 += TPC_BLOCK) {
+        const int64_t s = c0 + threadIdx.x;
+        const uint32_t v = s < R ? f[s] : 0u;
+        if (v > M) bad = 1;
+        int tot;
+        const int ex = block_exclusive_scan((int)(v > M ? 0 : v), sh, &tot);
+        const uint64_t c = carry + (uint64_t)ex;
+        if (s < R) A.cum[s] = c <= M ? (uint32_t)c : M;
+        carry += (uint64_t)tot;
+        if (carry > M && threadIdx.x == 0) bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A.cum[R] = carry <= M ? (uint32_t)carry : M;
+        if (bad || (A.hd[0] > 0 && carry != M)) A.hd[7] = TPC_ERR_ARG;
+    }
+}
+
+// Slot table: grid over symbols, each thread fills its symbol's slots.
+__global__ void __launch_bounds__(TPC_BLOCK) rd_slots(RdArgs A) {
+    if (A.hd[7] != TPC_OK) return;
+    const int64_t R = A.hd[2];
+    const uint32_t *f = reinterpret_cast<const uint32_t *>(A.in + RS_HEAD);
+    for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < R; s += (int64_t)gridDim.x * TPC_BLOCK) {
+        const uint32_t c = A.cum[s], fs = f[s];
+        for (uint32_t q = 0; q < fs && c + q < (1u << 16); ++q) A.slot[c + q] = make_uint4((uint32_t)s, fs, q, 0u);
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rd_decode(RdArgs A) {
+    __shared__ int failed;
+    if (A.hd[7] != TPC_OK) return;                         // uniform over the grid
+    const int64_t n = A.hd[0], lo = A.hd[1], R = A.hd[2], B = A.hd[4], nb = A.hd[5], head = A.hd[6];
+    const int L = (int)A.hd[3];
+    const uint32_t mask_M = (1u << L) - 1u;
+    const uint8_t *base = A.in + RS_HEAD + 4 * R;
+    const uint32_t *ws = reinterpret_cast<const uint32_t *>(base);
+    const uint32_t *sts = ws + nb + 1;
+    const uint16_t *words = reinterpret_cast<const uint16_t *>(A.in + head);
+    const uint64_t n_words = (A.size - (uint64_t)head) / 2;
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    if (threadIdx.x == 0) failed = 0;
+    __syncthreads();
+    const int64_t W = (int64_t)gridDim.x * (TPC_BLOCK / TPC_WAVE);
+    for (int64_t b = (int64_t)blockIdx.x * (TPC_BLOCK / TPC_WAVE) + threadIdx.x / TPC_WAVE; b < nb; b += W) {
+        const int64_t i0 = b * B, i1 = i0 + B < n ? i0 + B : n;
+        uint32_t x = sts[b * RS_LANES + lane];
+        uint64_t w = ws[b], w_end = ws[b + 1];
+        bool ok = w <= w_end && w_end <= n_words;
+        const int64_t rounds = (i1 - i0 + RS_LANES - 1) / RS_LANES;
+        for (int64_t j = 0; j < rounds && ok; ++j) {
+            const int64_t i = i0 + j * RS_LANES + lane;
+            const bool act = i < i1;
+            const uint32_t sl = x & mask_M;
+            const uint4 e = act ? A.slot[sl] : make_uint4(0u, 1u, 0u, 0u);
+            if (act) {
+                A.out[i] = (int32_t)(lo + (int64_t)e.x);
+                x = e.y * (x >> L) + e.z;
+            }
+            const bool need = act && x < (1u << 16);
+            const unsigned long long m = __ballot(need);
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            if (w + cnt > w_end) {
+                ok = false;
+                break;
+            }
+            if (need) {
+                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                x = (x << 16) | words[w + rank];
+            }
+            w += cnt;
+        }
+        // a block decodes back to the coders' start states, using all its words
+        if (!ok || w != w_end || __ballot(x != (1u << 16)) != 0ull) failed = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && failed) A.hd[7] = TPC_ERR_ARG;
+}
+
+__global__ void rd_done(RdArgs A) {
+    if (threadIdx.x == 0) {
+        *A.n_out = A.hd[0];
+        *A.dev_status = (int32_t)A.hd[7];
+    }
+}
+
 int grid_over(int64_t items, int cap) {
     int64_t b = (items + TPC_BLOCK - 1) / TPC_BLOCK;
     if (b > cap) b = cap;
@@ -513,4 +658,36 @@ size_t rans_batch_ws_bytes(int count, const RansJob *jobs, int32_t B) {
     size_t off = 0;
     for (int k = 0; k < count; ++k) off += rans_ws_layout(nullptr, jobs[k].n, B, nullptr);
     return off;
+}
+
+size_t rans_decode_ws_bytes() {
+    WsCarver w(nullptr);
+    w.take<int64_t>(8);
+    w.take<uint32_t>(TPC_RANS_MAX_RANGE + 1);
+    w.take<uint4>(1 << 16);
+    return (w.off + 255) & ~size_t(255);
+}
+
+hipError_t launch_rans_decode(const void *in, uint64_t size, int32_t *out, int64_t cap, int64_t *n_out,
+                              int32_t *dev_status, void *ws, hipStream_t st) {
+    RdArgs A;
+    WsCarver w(ws);
+    A.in = static_cast<const uint8_t *>(in);
+    A.size = size;
+    A.out = out;
+    A.cap = cap;
+    A.n_out = n_out;
+    A.dev_status = dev_status;
+    A.hd = w.take<int64_t>(8);
+    A.cum = w.take<uint32_t>(TPC_RANS_MAX_RANGE + 1);
+    A.slot = w.take<uint4>(1 << 16);
+    hipLaunchKernelGGL(rd_head, dim3(1), dim3(TPC_WAVE), 0, st, A);
+    hipLaunchKernelGGL(rd_table, dim3(1), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rd_slots, dim3(64), dim3(TPC_BLOCK), 0, st, A);
+    const int64_t blocks_max = cap > 0 ? (cap + RS_LANES - 1) / RS_LANES : 1;
+    int g = (int)((blocks_max + TPC_BLOCK / TPC_WAVE - 1) / (TPC_BLOCK / TPC_WAVE));
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL(rd_decode, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(rd_done, dim3(1), dim3(TPC_WAVE), 0, st, A);
+    return hipGetLastError();
 }

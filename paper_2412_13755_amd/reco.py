@@ -418,6 +418,24 @@ def rans_encode(symbols: torch.Tensor, scale_bits: int, block_symbols: int, out=
     return out, out_size, status
 
 
+def rans_decode(stream: torch.Tensor, size: int, cap: int, out=None, ws=None):
+    """tpc_rans_decode of the first `size` bytes of a uint8 device tensor.
+    Returns (symbols int32 [cap], n int64 [1], status int32 [1]) device tensors."""
+    if stream.dtype != torch.uint8 or stream.device.type != "cuda" or not stream.is_contiguous():
+        raise ValueError("stream must be a contiguous uint8 device tensor")
+    d = stream.device
+    out = torch.empty(max(int(cap), 1), dtype=torch.int32, device=d) if out is None else out
+    if ws is None:
+        b = ctypes.c_size_t()
+        C.check(C.lib().tpc_rans_decode_workspace_bytes(ctypes.byref(b)))
+        ws = torch.empty(int(b.value), dtype=torch.uint8, device=d)
+    n = torch.zeros(1, dtype=torch.int64, device=d)
+    st = torch.zeros(1, dtype=torch.int32, device=d)
+    C.check(C.lib().tpc_rans_decode(stream.data_ptr(), int(size), out.data_ptr(), int(cap), n.data_ptr(),
+                                    st.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(d)))
+    return out, n, st
+
+
 def _rans_jobs(jobs):
     arr = (C.RansJobC * len(jobs))()
     for k, j in enumerate(jobs):

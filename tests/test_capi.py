@@ -30,7 +30,8 @@ def test_header_declares_the_path():
               "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
               "tpc_track_follow", "tpc_rans_encode", "tpc_rans_workspace_bytes",
               "tpc_rans_max_bytes", "tpc_ctf_build", "tpc_rans_encode_batch",
-              "tpc_rans_batch_workspace_bytes", "tpc_kalman_fit_material", "tpc_status_string",
+              "tpc_rans_batch_workspace_bytes", "tpc_kalman_fit_material", "tpc_rans_decode",
+              "tpc_rans_decode_workspace_bytes", "tpc_status_string",
               "tpc_last_error"):
         assert n in names
 

@@ -109,3 +109,49 @@ def test_batch_equals_single_calls_and_device_counts(torch_dev):
         assert int(j["status"].item()) == 0
         got = j["out"][:int(j["out_size"].item())].cpu().numpy().tobytes()
         assert got == oracle.rans_encode(x, 16, 4096)
+
+
+def _decode(stream: bytes, cap):
+    import torch
+    from paper_2412_13755_amd.reco import rans_decode
+    buf = torch.from_numpy(np.frombuffer(stream, dtype=np.uint8).copy()).cuda()
+    out, n, st = rans_decode(buf, len(stream), cap)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(n.item()), int(st.item())
+
+
+def test_decoder_round_trips(torch_dev):
+    rng = np.random.default_rng(21)
+    cases = [(np.zeros(0, np.int32), 12, 64), (np.array([5], np.int32), 16, 64),
+             (rng.integers(-3, 9, 64 * 37 + 13).astype(np.int32), 12, 128),
+             (np.full(10_000, -7, np.int32), 12, 1024),
+             (rng.integers(0, 16000, 200_000).astype(np.int32), 16, 8192),
+             ((rng.geometric(0.05, 1_000_003) - 20).astype(np.int32), 11, 32768),
+             ((np.int32(-2**31) + rng.integers(0, 5, 5000)).astype(np.int32), 16, 256)]
+    for x, L, B in cases:
+        s = oracle.rans_encode(x, L, B)
+        got, n, st = _decode(s, len(x) + 7)
+        assert st == 0 and n == len(x)
+        np.testing.assert_array_equal(got[:n], x)
+    x = np.round(np.random.default_rng(9).normal(0.0, 12.0, 1 << 22)).astype(np.int32)
+    g, _, _ = _gpu(x, 14, 1 << 15)                      # GPU-coded stream
+    got, n, st = _decode(g, len(x))
+    assert st == 0 and n == len(x)
+    np.testing.assert_array_equal(got, x)
+
+
+def test_decoder_refuses_bad_streams(torch_dev):
+    x = np.random.default_rng(22).integers(0, 40, 50_000).astype(np.int32)
+    s = oracle.rans_encode(x, 12, 4096)
+    _, n, st = _decode(s, len(x) - 1)
+    assert st == -2 and n == len(x)                      # capacity
+    bad = bytearray(s); bad[0] ^= 1
+    assert _decode(bytes(bad), len(x))[2] == -1          # magic
+    assert _decode(s[:-10], len(x))[2] == -1             # truncated words
+    assert _decode(s[:100], len(x))[2] == -1             # truncated tables
+    bad = bytearray(s); bad[-101] ^= 0x40
+    assert _decode(bytes(bad), len(x))[2] == -1          # a flipped word
+    bad = bytearray(s); bad[40:44] = (0xFFFFFFF0).to_bytes(4, "little")
+    assert _decode(bytes(bad), len(x))[2] == -1          # frequencies summing past 2^L
+    bad = bytearray(s); bad[40:44] = (1 << 31).to_bytes(4, "little"); bad[44:48] = (1 << 31).to_bytes(4, "little")
+    assert _decode(bytes(bad), len(x))[2] == -1          # a sum that wraps in 32 bits
