@@ -89,6 +89,12 @@ def lib():
         L.oracle_fit_material.argtypes = [i32, P, P, P, P, P, P, ctypes.POINTER(FitParams),
                                            ctypes.POINTER(Material), P, P, P, P, P, P, P, P]
         L.oracle_fit_material.restype = None
+        L.oracle_neighbours_skip.argtypes = [i32, i32, P, P, P, f32, f32, f32, f32, P, P]
+        L.oracle_neighbours_skip.restype = None
+        L.oracle_fit_rows.argtypes = [i32, P, P, P, P, P, i32, i32, i32, P, P, P, P,
+                                      ctypes.POINTER(FitParams), ctypes.POINTER(Material),
+                                      P, P, P, P, P, P, P, P]
+        L.oracle_fit_rows.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -117,6 +123,20 @@ def neighbours(row_offsets, y, z, n_rows, win_y, win_z, cut_y, cut_z):
     dn = np.empty(n, np.int32)
     lib().oracle_neighbours(len(off) - 1, n_rows, _p(off), _p(y), _p(z), win_y, win_z,
                             cut_y, cut_z, _p(up), _p(dn))
+    return up, dn
+
+
+def neighbours_skip(row_offsets, y, z, n_rows, win_y, win_z, cut_y, cut_z):
+    """Returns (up, dn): best triplet partners per cluster, one or two rows
+    away (a triplet spanning fewer rows always wins)."""
+    off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    n = int(off[-1])
+    up = np.empty(n, np.int32)
+    dn = np.empty(n, np.int32)
+    lib().oracle_neighbours_skip(len(off) - 1, n_rows, _p(off), _p(y), _p(z), win_y, win_z,
+                                 cut_y, cut_z, _p(up), _p(dn))
     return up, dn
 
 
@@ -201,6 +221,40 @@ def fit_material(seeds: dict, y, z, row_x, *, x0, mass, chi2_cut, bz, sigma_y, s
                               ctypes.byref(mat), _p(out["x"]), _p(out["par"]), _p(out["cov"]),
                               _p(out["chi2"]), _p(out["ndf"]), _p(out["status"]), _p(out["rejected"]),
                               _p(out["margin"]))
+    out["rejected"] = out["rejected"][:hits.size]
+    return out
+
+
+def fit_rows(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, err, x0, mass, chi2_cut,
+             bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0):
+    """Fit of seeds whose hits may skip pad rows (each hit's row is looked up
+    in ``row_offsets``), with per-cluster errors ``err`` ([N, 2] float32
+    sigma_y, sigma_z; None: the constants) and material as in fit_material
+    (x0=inf, chi2_cut=inf: none).  Returns fit_material's dict."""
+    offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
+    hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
+    frm = np.ascontiguousarray(seeds["frame"], dtype=np.int32)
+    sec = np.ascontiguousarray(seeds["sector"], dtype=np.int32)
+    off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    rx = np.ascontiguousarray(row_x, dtype=np.float64)
+    ev = None
+    if err is not None:
+        ev = np.ascontiguousarray(err, dtype=np.float32)
+        if ev.shape != (y.size, 2):
+            raise ValueError("err must be [n_clusters, 2]")
+    T = len(offsets) - 1
+    n_frames = (off.size - 1) // (n_sectors * n_rows)
+    prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
+    mat = Material(float(x0), float(mass), float(chi2_cut))
+    out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
+               ndf=np.empty(T, np.int32), status=np.empty(T, np.int32),
+               rejected=np.zeros(max(hits.size, 1), np.uint8), margin=np.empty(T))
+    lib().oracle_fit_rows(T, _p(offsets), _p(hits), _p(frm), _p(sec), _p(off), n_frames, n_sectors, n_rows,
+                          _p(y), _p(z), _p(rx), None if ev is None else _p(ev), ctypes.byref(prm),
+                          ctypes.byref(mat), _p(out["x"]), _p(out["par"]), _p(out["cov"]), _p(out["chi2"]),
+                          _p(out["ndf"]), _p(out["status"]), _p(out["rejected"]), _p(out["margin"]))
     out["rejected"] = out["rejected"][:hits.size]
     return out
 

@@ -15,6 +15,8 @@
  *   ca_seed         mutual links -> maximal chains -> end claims -> seeds
  *   fit             exact three-point helix start + extended Kalman filter
  *                   through the hits inwards, double precision throughout
+ *   neighbours_skip partners up to two rows away where adjacent rows give none
+ *   fit_rows        the fit over seeds that skip rows, per-cluster errors
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
  */
@@ -89,6 +91,73 @@ void oracle_neighbours(int32_t n_segments, int32_t n_rows, const int32_t *row_of
                     /* u and d ascend, so strict '<' keeps the smallest (q, u, d) */
                     if (!found || q < best_q) {
                         found = 1; best_q = q; best_u = u; best_d = d;
+                    }
+                }
+            }
+            up[h] = best_u;
+            dn[h] = best_d;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbours across a missing pad row.  The partners of h (row r, 1 <= r <=  */
+/* R-2) may lie one or two rows away: d in row r-a, u in row r+b, a and b in  */
+/* {1, 2}, both rows inside the sector.  With A = y_u - y_h, B = y_h - y_d    */
+/* (z likewise) a triplet passes if                                           */
+/*   |A| <= b win, |B| <= a win (y and z with their windows) and              */
+/*   |D| <= cut,  D = g (A/b - B/a),  g = 2/(a+b):                            */
+/* D is the divided second difference scaled to unit row pitch -- zero on a   */
+/* straight line, and on a parabola the same value for every (a, b) -- and    */
+/* at a = b = 1 it is the adjacent-row dy above.  A triplet that spans fewer  */
+/* rows always wins (a+b = 2, then 3, then 4), so h keeps its adjacent-row    */
+/* result whenever it has one.  Within a span: smallest q = Dy^2 + Dz^2, then */
+/* smaller u id, then smaller d id.  Single precision, one rounding per       */
+/* operation: b win, A/b and B/a are exact (a, b powers of two) and g is      */
+/* 2/(a+b) rounded once.                                                      */
+/* ------------------------------------------------------------------------ */
+void oracle_neighbours_skip(int32_t n_segments, int32_t n_rows, const int32_t *row_offsets,
+                            const float *y, const float *z, float win_y, float win_z,
+                            float cut_y, float cut_z, int32_t *up, int32_t *dn)
+{
+    int32_t n = row_offsets[n_segments];
+    for (int32_t i = 0; i < n; ++i) { up[i] = -1; dn[i] = -1; }
+
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t seg = 0; seg < n_segments; ++seg) {
+        int32_t r = seg % n_rows;
+        if (r == 0 || r == n_rows - 1) continue;
+        for (int32_t h = row_offsets[seg]; h < row_offsets[seg + 1]; ++h) {
+            int found = 0;
+            float best_q = 0.0f;
+            int32_t best_u = -1, best_d = -1;
+            for (int span = 2; span <= 4 && !found; ++span) {
+                for (int a = 1; a <= 2; ++a) {
+                    int b = span - a;
+                    if (b < 1 || b > 2 || r - a < 0 || r + b > n_rows - 1) continue;
+                    float fa = (float)a, fb = (float)b;
+                    float g = 2.0f / (float)span;
+                    int32_t su = seg + b, sd = seg - a;
+                    for (int32_t u = row_offsets[su]; u < row_offsets[su + 1]; ++u) {
+                        float Ay = y[u] - y[h];
+                        float Az = z[u] - z[h];
+                        if (!(fabsf(Ay) <= fb * win_y && fabsf(Az) <= fb * win_z)) continue;
+                        for (int32_t d = row_offsets[sd]; d < row_offsets[sd + 1]; ++d) {
+                            float By = y[h] - y[d];
+                            float Bz = z[h] - z[d];
+                            if (!(fabsf(By) <= fa * win_y && fabsf(Bz) <= fa * win_z)) continue;
+                            float ty = Ay / fb, sy = By / fa;
+                            float tz = Az / fb, sz = Bz / fa;
+                            float ey = ty - sy, ez = tz - sz;
+                            float Dy = g * ey, Dz = g * ez;
+                            if (!(fabsf(Dy) <= cut_y && fabsf(Dz) <= cut_z)) continue;
+                            float qy = Dy * Dy;
+                            float qz = Dz * Dz;
+                            float q = qy + qz;
+                            int better = !found || q < best_q ||
+                                         (q == best_q && (u < best_u || (u == best_u && d < best_d)));
+                            if (better) { found = 1; best_q = q; best_u = u; best_d = d; }
+                        }
                     }
                 }
             }
@@ -719,23 +788,18 @@ static void add_scattering(const double *p, double dx, const oracle_material *m,
     C[4 * 5 + 4] += th2 * t * t * w * w;
 }
 
-static void fit_one_material(int32_t n, const int32_t *hit, int32_t row0, const double *y, const double *z,
-                             const double *row_x, const oracle_fit_params *prm, const oracle_material *mat,
-                             double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto,
-                             uint8_t *rej, double *margin)
+/* Fit with material of n points at planes xs (ascending), point k with the
+ * measurement variances vys[k], vzs[k] (the outermost point's are also the
+ * start covariance of y and z). */
+static void fit_material_points(int32_t n, const double *xs, const double *ys, const double *zs,
+                                const double *vys, const double *vzs, const oracle_fit_params *prm,
+                                const oracle_material *mat, double *xo, double *po, double *co,
+                                double *chi2o, int32_t *ndfo, int32_t *sto, uint8_t *rej, double *margin)
 {
-    double xs[512], ys[512], zs[512], C[25], p[5];
-    *margin = INFINITY;
-    for (int k = 0; k < n && k < 512; ++k) rej[k] = 0;
-    *ndfo = 2 * n - 5;
-    *chi2o = 0.0;
-    *xo = 0.0;
-    for (int i = 0; i < 5; ++i) po[i] = 0.0;
-    for (int i = 0; i < 15; ++i) co[i] = 0.0;
-    if (n < 3 || n > 512) { *sto = 1; return; }
-    for (int k = 0; k < n; ++k) { xs[k] = row_x[row0 + k]; ys[k] = y[hit[k]]; zs[k] = z[hit[k]]; }
+    double C[25], p[5];
     int32_t st = start_points(n, xs, ys, zs, prm, p, C);
-    double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
+    C[0] = vys[n - 1];
+    C[6] = vzs[n - 1];
     double chi2 = 0.0, xcur = xs[n - 1];
     int32_t used = 1;
     for (int k = n - 2; k >= 0 && !st; --k) {
@@ -743,13 +807,13 @@ static void fit_one_material(int32_t n, const int32_t *hit, int32_t row0, const 
         add_scattering(p, dx, mat, C);
         if (predict(p, C, dx, prm)) { st = 2; break; }
         xcur = xs[k];
-        double chi = resid_chi2(p, C, ys[k], zs[k], vy, vz);
+        double chi = resid_chi2(p, C, ys[k], zs[k], vys[k], vzs[k]);
         if (isfinite(chi)) {
             double mg = fabs(chi - mat->chi2_cut) / (mat->chi2_cut + 1.0);
             if (mg < *margin) *margin = mg;
         }
         if (chi > mat->chi2_cut) { rej[k] = 1; continue; }
-        if (update(p, C, ys[k], zs[k], vy, vz, &chi2)) { st = 3; break; }
+        if (update(p, C, ys[k], zs[k], vys[k], vzs[k], &chi2)) { st = 3; break; }
         ++used;
     }
     *xo = xcur;
@@ -758,6 +822,39 @@ static void fit_one_material(int32_t n, const int32_t *hit, int32_t row0, const 
     *chi2o = chi2;
     *ndfo = 2 * used - 5;
     *sto = st;
+}
+
+/* Outputs of a refused seed (status 1). */
+static void refuse(int32_t n, double *xo, double *po, double *co, double *chi2o, int32_t *ndfo,
+                   int32_t *sto, uint8_t *rej, double *margin)
+{
+    *margin = INFINITY;
+    for (int k = 0; k < n && k < 512; ++k) rej[k] = 0;
+    *ndfo = 2 * n - 5;
+    *chi2o = 0.0;
+    *xo = 0.0;
+    for (int i = 0; i < 5; ++i) po[i] = 0.0;
+    for (int i = 0; i < 15; ++i) co[i] = 0.0;
+    *sto = 1;
+}
+
+static void fit_one_material(int32_t n, const int32_t *hit, int32_t row0, const double *y, const double *z,
+                             const double *row_x, const oracle_fit_params *prm, const oracle_material *mat,
+                             double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto,
+                             uint8_t *rej, double *margin)
+{
+    double xs[512], ys[512], zs[512], vys[512], vzs[512];
+    refuse(n, xo, po, co, chi2o, ndfo, sto, rej, margin);
+    if (n < 3 || n > 512) return;
+    double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
+    for (int k = 0; k < n; ++k) {
+        xs[k] = row_x[row0 + k];
+        ys[k] = y[hit[k]];
+        zs[k] = z[hit[k]];
+        vys[k] = vy;
+        vzs[k] = vz;
+    }
+    fit_material_points(n, xs, ys, zs, vys, vzs, prm, mat, xo, po, co, chi2o, ndfo, sto, rej, margin);
 }
 
 void oracle_fit_material(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
@@ -771,5 +868,77 @@ void oracle_fit_material(int32_t n_tracks, const int32_t *offsets, const int32_t
         fit_one_material(offsets[i + 1] - offsets[i], hits + offsets[i], first_row[i], y, z, row_x, prm, mat,
                          &x_out[i], &par[(size_t)i * 5], &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i],
                          rejected + offsets[i], &margin[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fit of seeds whose hits may skip pad rows, with per-cluster errors.        */
+/* The row of a hit is the pad row of the seed's (frame, sector) whose id     */
+/* range holds it; a seed with a hit outside that (frame, sector), or whose   */
+/* rows do not rise strictly with the hit index, is refused (status 1).  Hit  */
+/* h is measured with variances err[h][0]^2, err[h][1]^2 (err null: sigma_y^2 */
+/* and sigma_z^2 for every hit), which also enter the start covariance at     */
+/* the outermost hit.  Otherwise this is the fit with material above, and     */
+/* with an infinite radiation length and no cut the plain fit.               */
+/* ------------------------------------------------------------------------ */
+
+/* Pad row of cluster id among the rows [base, base + n_rows) of one
+ * (frame, sector), or -1 if the id lies in none of them. */
+static int32_t row_of(const int32_t *row_offsets, int32_t base, int32_t n_rows, int32_t id)
+{
+    if (id < row_offsets[base] || id >= row_offsets[base + n_rows]) return -1;
+    int32_t lo = 0, hi = n_rows - 1;          /* off[base+lo] <= id < off[base+hi+1] */
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) / 2;
+        if (row_offsets[base + mid] <= id) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+static void fit_one_rows(int32_t n, const int32_t *hit, int32_t frame, int32_t sec,
+                         const int32_t *row_offsets, int32_t n_frames, int32_t n_sectors, int32_t n_rows,
+                         const double *y, const double *z, const double *row_x, const float *err,
+                         const oracle_fit_params *prm, const oracle_material *mat,
+                         double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto,
+                         uint8_t *rej, double *margin)
+{
+    double xs[512], ys[512], zs[512], vys[512], vzs[512];
+    refuse(n, xo, po, co, chi2o, ndfo, sto, rej, margin);
+    if (n < 3 || n > 512 || frame < 0 || frame >= n_frames || sec < 0 || sec >= n_sectors) return;
+    int32_t base = (frame * n_sectors + sec) * n_rows;
+    int32_t prev = -1;
+    for (int k = 0; k < n; ++k) {
+        int32_t r = row_of(row_offsets, base, n_rows, hit[k]);
+        if (r < 0 || r <= prev) return;
+        prev = r;
+        xs[k] = row_x[r];
+        ys[k] = y[hit[k]];
+        zs[k] = z[hit[k]];
+        if (err) {
+            double ey = (double)err[(size_t)hit[k] * 2], ez = (double)err[(size_t)hit[k] * 2 + 1];
+            vys[k] = ey * ey;
+            vzs[k] = ez * ez;
+        } else {
+            vys[k] = prm->sigma_y * prm->sigma_y;
+            vzs[k] = prm->sigma_z * prm->sigma_z;
+        }
+    }
+    fit_material_points(n, xs, ys, zs, vys, vzs, prm, mat, xo, po, co, chi2o, ndfo, sto, rej, margin);
+}
+
+void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                     const int32_t *frame, const int32_t *sector, const int32_t *row_offsets,
+                     int32_t n_frames, int32_t n_sectors, int32_t n_rows,
+                     const double *y, const double *z, const double *row_x, const float *err,
+                     const oracle_fit_params *prm, const oracle_material *mat,
+                     double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
+                     uint8_t *rejected, double *margin)
+{
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        fit_one_rows(offsets[i + 1] - offsets[i], hits + offsets[i], frame[i], sector[i], row_offsets,
+                     n_frames, n_sectors, n_rows, y, z, row_x, err, prm, mat, &x_out[i], &par[(size_t)i * 5],
+                     &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i], rejected + offsets[i], &margin[i]);
     }
 }

@@ -58,6 +58,18 @@ void oracle_fit_material(int32_t n_tracks, const int32_t *offsets, const int32_t
                          double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
                          uint8_t *rejected, double *margin);
 
+void oracle_neighbours_skip(int32_t n_segments, int32_t n_rows, const int32_t *row_offsets,
+                            const float *y, const float *z, float win_y, float win_z,
+                            float cut_y, float cut_z, int32_t *up, int32_t *dn);
+
+void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                     const int32_t *frame, const int32_t *sector, const int32_t *row_offsets,
+                     int32_t n_frames, int32_t n_sectors, int32_t n_rows,
+                     const double *y, const double *z, const double *row_x, const float *err,
+                     const oracle_fit_params *prm, const oracle_material *mat,
+                     double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
+                     uint8_t *rejected, double *margin);
+
 /* rANS coder of integer arrays (rans_oracle.c) */
 #include <stddef.h>
 int64_t oracle_rans_freqs(const uint32_t *c, uint32_t R, uint64_t n, uint32_t L, uint32_t *f);

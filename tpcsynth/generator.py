@@ -81,6 +81,7 @@ class Frames:
     w_true: Optional[np.ndarray] = None       # q/pT in the +x orientation
     distortion: Optional[np.ndarray] = None   # float32 [S, R, 2] (dy, dz) added to the clusters
     meta: dict = dataclasses.field(default_factory=dict)
+    err: Optional[np.ndarray] = None          # float32 [N, 2] per-cluster (sigma_y, sigma_z), if drawn
 
     @property
     def n_clusters(self) -> int:
@@ -101,7 +102,8 @@ class Frames:
         return Frames(1, self.n_sectors, self.n_rows, self.row_x, (off - a).astype(np.int32),
                       self.y[sl], self.z[sl], self.bz, self.sigma_y, self.sigma_z,
                       cut(self.track_of), cut(self.y_true), cut(self.z_true), cut(self.s_true),
-                      cut(self.t_true), cut(self.w_true), self.distortion, dict(self.meta))
+                      cut(self.t_true), cut(self.w_true), self.distortion, dict(self.meta),
+                      cut(self.err))
 
 
 # ----------------------------------------------------------------------------
@@ -294,8 +296,13 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
                 drift_window_us: float = 0.0, distortion_amp: float = 0.0, distortion_period: float = 38.0,
                 bz: float = 0.5, sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True,
                 shuffle: bool = True, max_turns: int = 3, keep_truth: bool = False,
-                hit_eff: float = 1.0, tracks: Optional[Tracks] = None) -> Frames:
-    """General generator; ``make_config`` fixes the parameters of the five workloads."""
+                hit_eff: float = 1.0, tracks: Optional[Tracks] = None,
+                err_scale: Optional[Sequence[float]] = None) -> Frames:
+    """General generator; ``make_config`` fixes the parameters of the five workloads.
+
+    ``err_scale=(lo, hi)`` gives every track cluster its own resolution: the
+    nominal sigma_y and sigma_z times two independent factors drawn uniformly
+    in [lo, hi], stored in ``err`` (noise clusters get the nominal values)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     row_x = make_row_x(n_rows)
     F = len(tracks_per_frame)
@@ -334,9 +341,10 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
         dist = dist.astype(np.float32)
         y_true = y_true + dist[cr["sector"], cr["row"], 0].astype(np.float64)
         z_true = z_true + dist[cr["sector"], cr["row"], 1].astype(np.float64)
+    fac = rng.uniform(err_scale[0], err_scale[1], (n_sig, 2)) if err_scale is not None else np.ones((n_sig, 2))
     if smear:
-        ym = y_true + rng.normal(0.0, sigma_y, n_sig)
-        zm = z_true + rng.normal(0.0, sigma_z, n_sig)
+        ym = y_true + rng.normal(0.0, sigma_y * fac[:, 0], n_sig)
+        zm = z_true + rng.normal(0.0, sigma_z * fac[:, 1], n_sig)
     else:
         ym, zm = y_true.copy(), z_true.copy()
     sec = cr["sector"]
@@ -360,6 +368,7 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
         tid = np.concatenate([tid, np.full(n_noise, -1)])
         ym = np.concatenate([ym, ny])
         zm = np.concatenate([zm, nz])
+        fac = np.concatenate([fac, np.ones((n_noise, 2))])
         nanv = np.full(n_noise, np.nan)
         y_true = np.concatenate([y_true, nanv])
         z_true = np.concatenate([z_true, nanv])
@@ -382,6 +391,9 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
         fr.y_true, fr.z_true = y_true[order], z_true[order]
         fr.s_true, fr.t_true, fr.w_true = st[order], tt[order], wt[order]
     fr.distortion = dist
+    if err_scale is not None:
+        sig = np.stack([sigma_y * fac[order, 0], sigma_z * fac[order, 1]], 1)
+        fr.err = np.ascontiguousarray(sig, dtype=np.float32)
     fr.meta = dict(n_tracks=len(tracks), n_signal=n_sig, n_noise=n_noise, seed=seed)
     fr.meta["tracks"] = tracks
     return fr
@@ -399,7 +411,8 @@ def drop_clusters(fr: Frames, keep: np.ndarray) -> Frames:
         return None if v is None else v[keep]
     return Frames(fr.n_frames, fr.n_sectors, fr.n_rows, fr.row_x, offs, fr.y[keep], fr.z[keep],
                   fr.bz, fr.sigma_y, fr.sigma_z, cut(fr.track_of), cut(fr.y_true), cut(fr.z_true),
-                  cut(fr.s_true), cut(fr.t_true), cut(fr.w_true), fr.distortion, dict(fr.meta))
+                  cut(fr.s_true), cut(fr.t_true), cut(fr.w_true), fr.distortion, dict(fr.meta),
+                  cut(fr.err))
 
 
 def add_clusters(fr: Frames, frame, sector, row, y, z, track_of=None) -> Frames:
@@ -421,7 +434,9 @@ def add_clusters(fr: Frames, frame, sector, row, y, z, track_of=None) -> Frames:
                   cat(fr.y, np.asarray(y, np.float32)), cat(fr.z, np.asarray(z, np.float32)),
                   fr.bz, fr.sigma_y, fr.sigma_z, cat(fr.track_of, tof), cat(fr.y_true, nan),
                   cat(fr.z_true, nan), cat(fr.s_true, nan), cat(fr.t_true, nan), cat(fr.w_true, nan),
-                  fr.distortion, dict(fr.meta))
+                  fr.distortion, dict(fr.meta),
+                  None if fr.err is None else np.concatenate(
+                      [fr.err, np.tile(np.float32([fr.sigma_y, fr.sigma_z]), (k, 1))])[order])
 
 
 CONFIG_NAMES = (
