@@ -136,6 +136,24 @@ tpc_status tpc_workspace_bytes(const tpc_context *ctx, const tpc_frames *frames,
 tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *frames,
                           int32_t *up, int32_t *dn, void *ws, size_t ws_bytes, void *stream);
 
+/* Neighbour finding across one missing pad row (pad-row inefficiency, dead
+ * rows) -- a variant of the search above that the paper does not describe.
+ * Partners may lie one or two rows away: d in row r-a, u in row r+b, a and b
+ * in {1, 2}, both rows inside the sector.  With A = y_u - y_h, B = y_h - y_d
+ * (z likewise) a triplet passes if |A| <= b win, |B| <= a win (y and z with
+ * their windows) and |D| <= cut for D = g (A/b - B/a), g = 2/(a+b): the
+ * divided second difference at unit row pitch, 0 on a straight line, the
+ * same on a parabola for every (a, b), and the dy above at a = b = 1.  The
+ * triplet spanning the fewest rows wins (a+b = 2, then 3, then 4), then the
+ * smallest q = Dy^2 + Dz^2, then the smaller u id, then the smaller d id;
+ * so a cluster keeps its adjacent-row result whenever it has one.  One IEEE
+ * single-precision rounding per operation (A/b, B/a and b win exact, g =
+ * 2/3 rounded once).  Output and workspace as tpc_neighbours; the links feed
+ * tpc_ca_seed unchanged, and its seeds then skip rows: fit them with
+ * tpc_kalman_fit_rows (tpc_kalman_fit assumes consecutive rows). */
+tpc_status tpc_neighbours_skip(const tpc_context *ctx, const tpc_frames *frames,
+                               int32_t *up, int32_t *dn, void *ws, size_t ws_bytes, void *stream);
+
 /* Cellular-automaton seeding from the neighbour links.
  *   links   h -> up[h] is kept if dn[up[h]] == h (and symmetrically);
  *   chains  maximal runs of kept links, bottom b to top t, m >= 2 clusters;
@@ -204,6 +222,23 @@ tpc_status tpc_kalman_fit_material(const tpc_context *ctx, const tpc_frames *fra
                                    const tpc_seeds *seeds, const tpc_material *mat,
                                    tpc_tracks *tracks, uint8_t *rejected, void *ws, size_t ws_bytes,
                                    void *stream);
+
+/* Fit of seeds whose hits may skip pad rows, with per-cluster errors.  The
+ * pad row of each hit is the row of the seed's (frame, sector) whose id
+ * range holds it (seeds->first_row is not read); a seed with a hit outside
+ * that (frame, sector), or whose rows do not rise strictly with the hit
+ * index, gets status TPC_FIT_INIT_FAIL and zero outputs.  Hit h is
+ * measured with variances cluster_err[2h]^2, cluster_err[2h+1]^2 (its
+ * sigma_y, sigma_z in cm, also the start covariance at the outermost hit);
+ * cluster_err NULL: the configured sigma_y, sigma_z for every hit.  mat as
+ * for tpc_kalman_fit_material, NULL for no scattering and no rejection (the
+ * plain fit over the hits' own rows).  Otherwise as tpc_kalman_fit_material.
+ * cluster_err: optional device float [n_clusters][2], 8-byte aligned.
+ * rejected: optional device uint8 [cap_hits].  ws: TPC_STAGE_FIT workspace. */
+tpc_status tpc_kalman_fit_rows(const tpc_context *ctx, const tpc_frames *frames,
+                               const tpc_seeds *seeds, const float *cluster_err,
+                               const tpc_material *mat, tpc_tracks *tracks, uint8_t *rejected,
+                               void *ws, size_t ws_bytes, void *stream);
 
 /* Checkpoint-buffer bytes for seeds of these capacities (host call). */
 tpc_status tpc_ckpt_bytes(const tpc_context *ctx, const tpc_seeds *seeds, size_t *bytes);

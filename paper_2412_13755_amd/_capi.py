@@ -108,6 +108,7 @@ SIGNATURES = {
     "tpc_destroy": (None, [P]),
     "tpc_workspace_bytes": (i32, [P, ctypes.POINTER(FramesC), i32, ctypes.POINTER(ctypes.c_size_t)]),
     "tpc_neighbours": (i32, [P, ctypes.POINTER(FramesC), P, P, P, ctypes.c_size_t, P]),
+    "tpc_neighbours_skip": (i32, [P, ctypes.POINTER(FramesC), P, P, P, ctypes.c_size_t, P]),
     "tpc_ca_seed": (i32, [P, ctypes.POINTER(FramesC), P, P, ctypes.POINTER(SeedsC), P, P,
                           ctypes.c_size_t, P]),
     "tpc_kalman_fit": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
@@ -137,6 +138,9 @@ SIGNATURES = {
     "tpc_kalman_fit_material": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
                                       ctypes.POINTER(Material), ctypes.POINTER(TracksC), P, P,
                                       ctypes.c_size_t, P]),
+    "tpc_kalman_fit_rows": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
+                                  ctypes.POINTER(Material), ctypes.POINTER(TracksC), P, P,
+                                  ctypes.c_size_t, P]),
     "tpc_rans_decode_workspace_bytes": (i32, [ctypes.POINTER(ctypes.c_size_t)]),
     "tpc_rans_decode": (i32, [P, ctypes.c_size_t, P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),

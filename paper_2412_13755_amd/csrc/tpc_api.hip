@@ -11,6 +11,7 @@
 
 #include "tpc_internal.hpp"
 #include "tpc_fit_ms.hpp"
+#include "tpc_nb_skip.hpp"
 #include "tpc_rans_dec.hpp"
 
 namespace {
@@ -102,6 +103,15 @@ tpc_status check_tracks(const tpc_seeds *sd, const tpc_tracks *tr) {
     if (!tr) return fail(TPC_ERR_ARG, "null tracks");
     if (sd->cap_seeds > 0 && (!tr->x || !tr->par || !tr->cov || !tr->chi2 || !tr->ndf || !tr->status))
         return fail(TPC_ERR_ARG, "null track arrays");
+    return TPC_OK;
+}
+
+// Material parameters, when given (NULL is accepted here).
+tpc_status check_material(const tpc_material *mat) {
+    if (!mat) return TPC_OK;
+    if (!(mat->x0 > 0.f)) return fail(TPC_ERR_ARG, "x0 must be > 0");
+    if (!(mat->mass >= 0.f) || !isfinite(mat->mass)) return fail(TPC_ERR_ARG, "mass must be finite and >= 0");
+    if (!(mat->chi2_cut > 0.f)) return fail(TPC_ERR_ARG, "chi2_cut must be > 0");
     return TPC_OK;
 }
 
@@ -202,6 +212,21 @@ tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32_t 
     return e == hipSuccess ? TPC_OK : hip_fail(e, "neighbour kernels");
 }
 
+tpc_status tpc_neighbours_skip(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
+                               void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
+    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_NEIGHBOURS));
+    if (s) return s;
+    if (fr->n_clusters == 0) return TPC_OK;
+    NbWs l;
+    nb_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
+    hipError_t e = launch_neighbours_skip(ctx, fr, up, dn, l, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "neighbour kernels");
+}
+
 tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const int32_t *up,
                        const int32_t *dn, tpc_seeds *sd, int32_t *dev_status, void *ws,
                        size_t ws_bytes, void *stream) {
@@ -261,12 +286,26 @@ tpc_status tpc_kalman_fit_material(const tpc_context *ctx, const tpc_frames *fr,
     if ((s = check_seeds_for_fit(sd))) return s;
     if ((s = check_tracks(sd, tr))) return s;
     if (!mat) return fail(TPC_ERR_ARG, "null material");
-    if (!(mat->x0 > 0.f)) return fail(TPC_ERR_ARG, "x0 must be > 0");
-    if (!(mat->mass >= 0.f) || !isfinite(mat->mass)) return fail(TPC_ERR_ARG, "mass must be finite and >= 0");
-    if (!(mat->chi2_cut > 0.f)) return fail(TPC_ERR_ARG, "chi2_cut must be > 0");
+    if ((s = check_material(mat))) return s;
     if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds, sd->cap_hits)))) return s;
     if (sd->cap_seeds == 0) return TPC_OK;
     hipError_t e = launch_fit_material(ctx, fr, sd, mat, tr, rejected, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
+}
+
+tpc_status tpc_kalman_fit_rows(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                               const float *cluster_err, const tpc_material *mat, tpc_tracks *tr,
+                               uint8_t *rejected, void *ws, size_t ws_bytes, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if ((s = check_material(mat))) return s;
+    if (((uintptr_t)cluster_err & 7) != 0) return fail(TPC_ERR_ARG, "cluster_err not 8-byte aligned");
+    if ((s = check_ws(ws, ws_bytes, fit_bytes(sd->cap_seeds, sd->cap_hits)))) return s;
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_fit_rows(ctx, fr, sd, cluster_err, mat, tr, rejected, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
 }
 

@@ -196,72 +196,90 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
 // UZ, UI, UCS, gu) and down row (D...).  UCS[c] indexes the first cluster of
 // cell c in UY/UZ/UI; a stored id k stands for cluster ubase + k (dbase + k
 // in the down row).  Every operation is one single-precision rounding, and
-// the predicates are evaluated on exactly the operands of the definition:
-// ay = y_u - y_h, by = y_h - y_d, dy = ay - by (z likewise).
+// the predicates are evaluated on exactly the operands of the definition.
+// The down row lies A rows below h and the up row B rows above (A, B in
+// {1, 2}): with ay = y_u - y_h and by = y_h - y_d (z likewise) a pair passes
+// |ay| <= B win, |by| <= A win and |dy| <= cut for the second difference
+// dy = g (ay / B - by / A), g = 2 / (A + B), scored by q = dy*dy + dz*dz.
+// At A = B = 1 every scale factor is exactly 1 and dy = ay - by, the
+// adjacent-row definition; B win, ay / B and by / A are exact for the other
+// distances (powers of two) and g = 2/3 is the rounded constant.
 //
 // Enumeration: the down-row clusters in h's window are collected first (up
 // to TPC_NB_DLIST in registers); then every up-row cluster in the window is
 // paired with that list.  If more down clusters are in the window, each up
 // candidate instead scans the down-row cells that overlap the cut interval
-// around its straight-line prediction c = h - (u - h).  Cells scanned are
-// those overlapping [h - win - m, h + win + m] (or [c - cut - m, c + cut + m])
-// with a margin m far above the rounding of the predicates and of c; as
-// cell_coord is monotonic, every cluster that can pass the exact predicates
-// is visited.  A cluster h with a non-finite coordinate fails every window,
-// so it is skipped.
+// around its straight-line prediction c = h - (A / B)(u - h), of half-width
+// A (A + B) / 2 cut.  Cells scanned are those overlapping the window (or
+// cut) interval widened by a margin m far above the rounding of the
+// predicates and of c; as cell_coord is monotonic, every cluster that can
+// pass the exact predicates is visited.  A cluster h with a non-finite
+// coordinate fails every window, so it is skipped.
 #define TPC_NB_DLIST 8
 
-template <class FP, class IP, class CP>
+template <int A = 1, int B = 1, class FP, class IP, class CP>
 __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS, const SegGrid &gu,
                                  int32_t ubase, FP DY, FP DZ, IP DI, CP DCS, const SegGrid &gd,
                                  int32_t dbase, float win_y, float win_z, float cut_y, float cut_z) {
 #pragma clang fp contract(off)
+    static_assert(A >= 1 && A <= 2 && B >= 1 && B <= 2, "partners one or two rows away");
+    constexpr float fa = (float)A, fb = (float)B;
+    constexpr float g = 2.0f / (float)(A + B);
+    constexpr float kw = A > B ? fa : fb;              // widest window, in windows
+    constexpr float kc = (float)(A * (A + B)) / 2.0f;  // cut interval of the down row, in cuts
+    constexpr float rab = fa / fb;                     // prediction slope of the down row
     Best best = {0.f, -1, -1};
     if (gu.ny <= 0 || gd.ny <= 0 || !isfinite(yh) || !isfinite(zh)) return best;
-    const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
-    const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
-    const float wy = win_y + my, wz = win_z + mz, ky = cut_y + my, kz = cut_z + mz;
-    // down clusters in the window
+    const float my = 1e-5f * (fabsf(yh) + kw * win_y + kc * cut_y) + 1e-6f;
+    const float mz = 1e-5f * (fabsf(zh) + kw * win_z + kc * cut_z) + 1e-6f;
+    const float wdy = fa * win_y + my, wdz = fa * win_z + mz;
+    const float wuy = fb * win_y + my, wuz = fb * win_z + mz;
+    const float ky = kc * cut_y + my, kz = kc * cut_z + mz;
+    // down clusters in the window (by / A kept)
     float lb[TPC_NB_DLIST][2];
     int32_t ld[TPC_NB_DLIST];
 #pragma unroll
     for (int j = 0; j < TPC_NB_DLIST; ++j) { lb[j][0] = 0.f; lb[j][1] = 0.f; ld[j] = -1; }
     int nd = 0;
     {
-        const int y0 = cell_coord(yh - wy, gd.y0, gd.iwy, gd.ny), y1 = cell_coord(yh + wy, gd.y0, gd.iwy, gd.ny);
-        const int z0 = cell_coord(zh - wz, gd.z0, gd.iwz, gd.nz), z1 = cell_coord(zh + wz, gd.z0, gd.iwz, gd.nz);
+        const int y0 = cell_coord(yh - wdy, gd.y0, gd.iwy, gd.ny), y1 = cell_coord(yh + wdy, gd.y0, gd.iwy, gd.ny);
+        const int z0 = cell_coord(zh - wdz, gd.z0, gd.iwz, gd.nz), z1 = cell_coord(zh + wdz, gd.z0, gd.iwz, gd.nz);
         for (int iy = y0; iy <= y1; ++iy) {
             const int e0 = DCS[iy * gd.nz + z0];
             const int e1 = DCS[iy * gd.nz + z1 + 1];
             for (int kd = e0; kd < e1; ++kd) {
                 const float by = yh - DY[kd];
                 const float bz = zh - DZ[kd];
-                if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
+                if (!(fabsf(by) <= fa * win_y && fabsf(bz) <= fa * win_z)) continue;
                 const int32_t d = dbase + (int32_t)DI[kd];
+                const float sy = by / fa, sz = bz / fa;
 #pragma unroll
                 for (int j = 0; j < TPC_NB_DLIST; ++j)
-                    if (nd == j) { lb[j][0] = by; lb[j][1] = bz; ld[j] = d; }
+                    if (nd == j) { lb[j][0] = sy; lb[j][1] = sz; ld[j] = d; }
                 ++nd;
             }
         }
     }
     if (nd == 0) return best;
     const bool listed = nd <= TPC_NB_DLIST;
-    const int yu0 = cell_coord(yh - wy, gu.y0, gu.iwy, gu.ny), yu1 = cell_coord(yh + wy, gu.y0, gu.iwy, gu.ny);
-    const int zu0 = cell_coord(zh - wz, gu.z0, gu.iwz, gu.nz), zu1 = cell_coord(zh + wz, gu.z0, gu.iwz, gu.nz);
+    const int yu0 = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny), yu1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
+    const int zu0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz), zu1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
     for (int iyu = yu0; iyu <= yu1; ++iyu) {
         const int ue0 = UCS[iyu * gu.nz + zu0];
         const int ue1 = UCS[iyu * gu.nz + zu1 + 1];
         for (int ku = ue0; ku < ue1; ++ku) {
             const float ay = UY[ku] - yh;
             const float az = UZ[ku] - zh;
-            if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
+            if (!(fabsf(ay) <= fb * win_y && fabsf(az) <= fb * win_z)) continue;
             const int32_t u = ubase + (int32_t)UI[ku];
+            const float ty = ay / fb, tz = az / fb;
             if (listed) {
 #pragma unroll
                 for (int j = 0; j < TPC_NB_DLIST; ++j) {
-                    const float dy = ay - lb[j][0];
-                    const float dz = az - lb[j][1];
+                    const float ey = ty - lb[j][0];
+                    const float ez = tz - lb[j][1];
+                    const float dy = g * ey;
+                    const float dz = g * ez;
                     if (j < nd && fabsf(dy) <= cut_y && fabsf(dz) <= cut_z) {
                         const float qy = dy * dy;
                         const float qz = dz * dz;
@@ -271,7 +289,7 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
                 }
                 continue;
             }
-            const float cy = yh - ay, cz = zh - az;
+            const float cy = yh - rab * ay, cz = zh - rab * az;
             const int yd0 = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
             const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
             const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
@@ -282,9 +300,11 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
                 for (int kd = de0; kd < de1; ++kd) {
                     const float by = yh - DY[kd];
                     const float bz = zh - DZ[kd];
-                    if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
-                    const float dy = ay - by;
-                    const float dz = az - bz;
+                    if (!(fabsf(by) <= fa * win_y && fabsf(bz) <= fa * win_z)) continue;
+                    const float ey = ty - by / fa;
+                    const float ez = tz - bz / fa;
+                    const float dy = g * ey;
+                    const float dz = g * ez;
                     if (!(fabsf(dy) <= cut_y && fabsf(dz) <= cut_z)) continue;
                     const float qy = dy * dy;
                     const float qz = dz * dz;

@@ -177,6 +177,17 @@ class Reco:
                                        ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return up, dn
 
+    def neighbours_skip(self, frames: DeviceFrames, up=None, dn=None, ws=None):
+        """tpc_neighbours_skip: partners up to two rows away where the
+        adjacent rows give none."""
+        N = frames.n_clusters
+        up = torch.empty(N, dtype=torch.int32, device=self.device) if up is None else up
+        dn = torch.empty(N, dtype=torch.int32, device=self.device) if dn is None else dn
+        ws = self.workspace(frames) if ws is None else ws
+        C.check(C.lib().tpc_neighbours_skip(self._ctx, ctypes.byref(frames.c), up.data_ptr(), dn.data_ptr(),
+                                            ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return up, dn
+
     def alloc_seeds(self, frames: DeviceFrames, cap_seeds=None, cap_hits=None, hit_yz=True) -> Seeds:
         """Seed buffers; with hit_yz the seeding also stores the coordinates of
         every seed hit, which the fit and the adjoint then read directly."""
@@ -249,6 +260,30 @@ class Reco:
         C.check(C.lib().tpc_kalman_fit_material(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
                                                 ctypes.byref(mat), ctypes.byref(tc), rejected.data_ptr(),
                                                 ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
+        return tracks, rejected
+
+    def fit_rows(self, frames: DeviceFrames, seeds: Seeds, cluster_err: Optional[torch.Tensor] = None,
+                 material: Optional[tuple] = None, tracks: Optional[Tracks] = None,
+                 rejected: Optional[torch.Tensor] = None, ws=None):
+        """tpc_kalman_fit_rows: seeds whose hits may skip pad rows, optional
+        per-cluster errors ([N, 2] float32 sigma_y, sigma_z on the device) and
+        material (x0, mass, chi2_cut).  Returns (Tracks, rejected)."""
+        tracks = self.alloc_tracks(seeds) if tracks is None else tracks
+        if rejected is None:
+            rejected = torch.zeros(max(seeds.hits.numel(), 1), dtype=torch.uint8, device=self.device)
+        ws = self.workspace(frames) if ws is None else ws
+        err = 0
+        if cluster_err is not None:
+            if (cluster_err.dtype != torch.float32 or cluster_err.device.type != self.device.type
+                    or tuple(cluster_err.shape) != (frames.n_clusters, 2) or not cluster_err.is_contiguous()):
+                raise ValueError("cluster_err must be a contiguous float32 [n_clusters, 2] tensor on the device")
+            err = cluster_err.data_ptr()
+        mat = None if material is None else ctypes.byref(C.Material(*(float(v) for v in material)))
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_kalman_fit_rows(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc), err, mat,
+                                            ctypes.byref(tc), rejected.data_ptr(), ws.data_ptr(), ws.numel(),
+                                            _stream_handle(self.device)))
         return tracks, rejected
 
     def follow(self, frames: DeviceFrames, seeds: Seeds, gate_chi2: float, max_miss: int,
