@@ -32,6 +32,11 @@ Extra legs, reported beside the headline value:
            clusters/s and bits per cluster
   material the fit with multiple scattering (radiation length 2870 cm, pion
            mass) and outlier rejection (chi2 > 30) on the headline seeds
+  skip     the headline event with 10% pad-row inefficiency: neighbours across
+           one missing row + seeding + the fit over the hits' own rows, against
+           the adjacent-row path on the same frame (times per call, seed
+           lengths, track pieces found in one seed); the oracle chain is
+           timed on the same frame
   copy     a 1 GiB device copy (reference for the HBM traffic counters; run
            alone with --legs copy)
   stages   the three stage calls on the headline workload, --steps times,
@@ -78,7 +83,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf,material")
+    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf,material,skip")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--stages-workload", type=int, default=1,
@@ -535,6 +540,114 @@ def leg_material(args):
                          "kernel": "fit_ms_tracks", "algorithmic_flops": int(flops)}}
 
 
+SKIP_EFF = 0.9                 # pad-row efficiency of the row-skipping workload
+
+
+def _one_seed_coverage(fr, sd, min_clusters=20, frac=0.8):
+    """Fraction of (track, sector) pieces with >= min_clusters clusters of
+    which at least frac land in a single seed."""
+    t = fr.track_of
+    seg = np.repeat(np.arange(fr.row_offsets.size - 1), np.diff(fr.row_offsets))
+    sec = seg // fr.n_rows
+    sig = t >= 0
+    piece = t.astype(np.int64) * 4096 + sec
+    pk, pn = np.unique(piece[sig], return_counts=True)
+    big = pk[pn >= min_clusters]
+    nbig = pn[pn >= min_clusters]
+    h = sd["hits"]
+    sid = np.repeat(np.arange(len(sd["offsets"]) - 1), np.diff(sd["offsets"]))
+    ok = t[h] >= 0
+    key = sid[ok].astype(np.int64) * (1 << 40) + piece[h[ok]]
+    uk, un = np.unique(key, return_counts=True)
+    upiece = uk % (1 << 40)
+    best = {}
+    for p_, n_ in zip(upiece.tolist(), un.tolist()):
+        if n_ > best.get(p_, 0):
+            best[p_] = n_
+    got = np.array([best.get(p_, 0) for p_ in big.tolist()])
+    return float(np.mean(got >= frac * nbig)) if big.size else 0.0
+
+
+def leg_skip(args, with_cpu=True):
+    """Row-skipping path on the headline frame with 10% pad-row inefficiency
+    (neighbours across a missing row, seeding, the fit over the hits' rows)
+    against the adjacent-row path on the same frame; HIP events per call on
+    the launch stream."""
+    import torch
+    from tpcsynth import make_config
+    fr = make_config(1, hit_eff=SKIP_EFF)
+    N = fr.n_clusters
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    ws = reco.workspace(dfr)
+    up, dn = reco.neighbours_skip(dfr, ws=ws)
+    seeds = reco.seed(dfr, up, dn, ws=ws)
+    tr, rej = reco.fit_rows(dfr, seeds, ws=ws)
+    up0, dn0 = reco.neighbours(dfr, ws=ws)
+    seeds0 = reco.seed(dfr, up0, dn0, ws=ws)
+    tr0 = reco.fit(dfr, seeds0, ws=ws)
+    torch.cuda.synchronize()
+    assert int(seeds.status.item()) == 0 and int(seeds0.status.item()) == 0
+    stream = torch.cuda.current_stream()
+    steps = max(5, args.steps)
+
+    def run(calls):
+        for _ in range(2):
+            for c in calls:
+                c()
+        ev = []
+        for _ in range(steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+            e[0].record(stream)
+            for k, c in enumerate(calls):
+                c()
+                e[k + 1].record(stream)
+            ev.append(e)
+        torch.cuda.synchronize()
+        t = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(len(calls))] for e in ev]).mean(0)
+        return [round(float(v), 5) for v in t]
+
+    ts = run([lambda: reco.neighbours_skip(dfr, up, dn, ws), lambda: reco.seed(dfr, up, dn, seeds, ws),
+              lambda: reco.fit_rows(dfr, seeds, tracks=tr, rejected=rej, ws=ws)])
+    ta = run([lambda: reco.neighbours(dfr, up0, dn0, ws), lambda: reco.seed(dfr, up0, dn0, seeds0, ws),
+              lambda: reco.fit(dfr, seeds0, tracks=tr0, ws=ws)])
+    sd, sd0 = seeds.to_numpy(), seeds0.to_numpy()
+    T, H = len(sd["offsets"]) - 1, sd["hits"].size
+    ms = sum(ts)
+    flops = FLOP_FIT_PER_HIT * H
+    res = {"workload": fr.meta["name"] + " with 10% pad-row inefficiency", "clusters": N,
+           "hit_efficiency": SKIP_EFF,
+           "skip": {"ms": round(ms, 5), "M_clusters_per_s": round(N / ms / 1e3, 3),
+                    "stage_ms": dict(zip(("tpc_neighbours_skip", "tpc_ca_seed", "tpc_kalman_fit_rows"), ts)),
+                    "linked_frac": round(float((up >= 0).float().mean().item()), 4),
+                    "seeds": T, "seed_hits": H, "mean_seed_hits": round(H / max(T, 1), 2),
+                    "pieces_80pct_in_one_seed": round(_one_seed_coverage(fr, sd), 4)},
+           "adjacent": {"ms": round(sum(ta), 5), "M_clusters_per_s": round(N / sum(ta) / 1e3, 3),
+                        "stage_ms": dict(zip(("tpc_neighbours", "tpc_ca_seed", "tpc_kalman_fit"), ta)),
+                        "linked_frac": round(float((up0 >= 0).float().mean().item()), 4),
+                        "seeds": len(sd0["offsets"]) - 1, "seed_hits": int(sd0["hits"].size),
+                        "mean_seed_hits": round(sd0["hits"].size / max(len(sd0["offsets"]) - 1, 1), 2),
+                        "pieces_80pct_in_one_seed": round(_one_seed_coverage(fr, sd0), 4)},
+           "skip_pass_ms": round(ts[0] - ta[0], 5),
+           "roofline": {"bound": "alu", "kernel": "fit_ms_tracks (rows)", "avg_ms": ts[2],
+                        "achieved": round(flops / (ts[2] * 1e-3) / 1e12, 4), "peak": VALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(flops / (ts[2] * 1e-3) / 1e12 / VALU_PEAK_TFLOPS, 5),
+                        "algorithmic_flops": int(flops)}}
+    if with_cpu:
+        import oracle
+        oracle.set_threads(len(os.sched_getaffinity(0)))
+        inf = float("inf")
+        t0 = time.perf_counter()
+        u, d = oracle.neighbours_skip(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+        s = oracle.ca_seed(fr.row_offsets, u, d, fr.n_sectors, fr.n_rows, MIN_HITS)
+        oracle.fit_rows(s, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows, err=None,
+                        x0=inf, mass=0.0, chi2_cut=inf, **FIT)
+        t = time.perf_counter() - t0
+        res["cpu_oracle"] = {"ms": round(t * 1e3, 3), "cores": int(oracle.max_threads()),
+                             "M_clusters_per_s": round(N / t / 1e6, 3)}
+    return res
+
+
 def leg_copy(args):
     """A plain device copy of known size (calibrates the HBM traffic counters)."""
     import torch
@@ -599,6 +712,9 @@ def main():
     if legs == {"ctf"}:
         print(json.dumps({"ctf": leg_ctf(args)}), flush=True)
         return
+    if legs == {"skip"}:
+        print(json.dumps({"skip": leg_skip(args, not args.no_cpu)}), flush=True)
+        return
     if legs == {"rans"}:
         print(json.dumps({"rans": leg_rans(args, not args.no_cpu)}), flush=True)
         return
@@ -623,6 +739,8 @@ def main():
         out["ctf"] = leg_ctf(args)
     if "material" in legs:
         out["material"] = leg_material(args)
+    if "skip" in legs:
+        out["skip"] = leg_skip(args, not args.no_cpu)
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:

@@ -114,7 +114,8 @@ void tpc_destroy(tpc_context *ctx);
 #define TPC_STAGE_PERSISTENT 16
 #define TPC_STAGE_FOLLOW     32
 #define TPC_STAGE_CTF        64
-#define TPC_STAGE_ALL       127
+#define TPC_STAGE_SKIP      128
+#define TPC_STAGE_ALL       255
 
 /* Workspace bytes needed by the stages in `stage_mask` for frames of this
  * shape (only n_frames and n_clusters are read; host call, no device work).
@@ -148,9 +149,10 @@ tpc_status tpc_neighbours(const tpc_context *ctx, const tpc_frames *frames,
  * smallest q = Dy^2 + Dz^2, then the smaller u id, then the smaller d id;
  * so a cluster keeps its adjacent-row result whenever it has one.  One IEEE
  * single-precision rounding per operation (A/b, B/a and b win exact, g =
- * 2/3 rounded once).  Output and workspace as tpc_neighbours; the links feed
- * tpc_ca_seed unchanged, and its seeds then skip rows: fit them with
- * tpc_kalman_fit_rows (tpc_kalman_fit assumes consecutive rows). */
+ * 2/3 rounded once).  Output as tpc_neighbours.  ws: TPC_STAGE_SKIP
+ * workspace (the neighbour workspace plus a list of queried clusters).  The
+ * links feed tpc_ca_seed unchanged, and its seeds then skip rows: fit them
+ * with tpc_kalman_fit_rows (tpc_kalman_fit assumes consecutive rows). */
 tpc_status tpc_neighbours_skip(const tpc_context *ctx, const tpc_frames *frames,
                                int32_t *up, int32_t *dn, void *ws, size_t ws_bytes, void *stream);
 

@@ -30,7 +30,8 @@ TPC_STAGE_FIT = 4
 TPC_STAGE_ADJOINT = 8
 TPC_STAGE_FOLLOW = 32
 TPC_STAGE_CTF = 64
-TPC_STAGE_ALL = 127
+TPC_STAGE_SKIP = 128
+TPC_STAGE_ALL = 255
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32

@@ -81,6 +81,7 @@ size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
         b = std::max(b, persist_ws_layout(nullptr, N, NR, cs, N > 0 ? N : 1, nullptr));
     if (mask & TPC_STAGE_FOLLOW) b = std::max(b, follow_ws_layout(nullptr, N, NR, nullptr));
     if (mask & TPC_STAGE_CTF) b = std::max(b, ctf_ws_layout(nullptr, N, NR, cs, nullptr));
+    if (mask & TPC_STAGE_SKIP) b = std::max(b, skip_ws_layout(nullptr, N, NR, nullptr));
     return b;
 }
 
@@ -218,11 +219,11 @@ tpc_status tpc_neighbours_skip(const tpc_context *ctx, const tpc_frames *fr, int
     tpc_status s = check_frames(ctx, fr);
     if (s) return s;
     if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
-    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_NEIGHBOURS));
+    s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_SKIP));
     if (s) return s;
     if (fr->n_clusters == 0) return TPC_OK;
-    NbWs l;
-    nb_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
+    SkipWs l;
+    skip_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
     hipError_t e = launch_neighbours_skip(ctx, fr, up, dn, l, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "neighbour kernels");
 }
