@@ -93,7 +93,7 @@ def lib():
         L.oracle_neighbours_skip.restype = None
         L.oracle_fit_rows.argtypes = [i32, P, P, P, P, P, i32, i32, i32, P, P, P, P,
                                       ctypes.POINTER(FitParams), ctypes.POINTER(Material),
-                                      P, P, P, P, P, P, P, P]
+                                      P, P, P, P, P, P, P, P, P, P]
         L.oracle_fit_rows.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
@@ -226,11 +226,13 @@ def fit_material(seeds: dict, y, z, row_x, *, x0, mass, chi2_cut, bz, sigma_y, s
 
 
 def fit_rows(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, err, x0, mass, chi2_cut,
-             bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0):
+             bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0, smooth=False):
     """Fit of seeds whose hits may skip pad rows (each hit's row is looked up
     in ``row_offsets``), with per-cluster errors ``err`` ([N, 2] float32
     sigma_y, sigma_z; None: the constants) and material as in fit_material
-    (x0=inf, chi2_cut=inf: none).  Returns fit_material's dict."""
+    (x0=inf, chi2_cut=inf: none).  Returns fit_material's dict; with
+    ``smooth`` also hit_par [H, 5] and hit_cov [H, 15] (packed), the
+    smoothed state at every seed hit's plane."""
     offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
     hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
     frm = np.ascontiguousarray(seeds["frame"], dtype=np.int32)
@@ -251,11 +253,19 @@ def fit_rows(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, err, x
     out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
                ndf=np.empty(T, np.int32), status=np.empty(T, np.int32),
                rejected=np.zeros(max(hits.size, 1), np.uint8), margin=np.empty(T))
+    hp = hc = None
+    if smooth:
+        out["hit_par"] = hp = np.zeros((max(hits.size, 1), 5))
+        out["hit_cov"] = hc = np.zeros((max(hits.size, 1), 15))
     lib().oracle_fit_rows(T, _p(offsets), _p(hits), _p(frm), _p(sec), _p(off), n_frames, n_sectors, n_rows,
                           _p(y), _p(z), _p(rx), None if ev is None else _p(ev), ctypes.byref(prm),
                           ctypes.byref(mat), _p(out["x"]), _p(out["par"]), _p(out["cov"]), _p(out["chi2"]),
-                          _p(out["ndf"]), _p(out["status"]), _p(out["rejected"]), _p(out["margin"]))
+                          _p(out["ndf"]), _p(out["status"]), _p(out["rejected"]), _p(out["margin"]),
+                          None if hp is None else _p(hp), None if hc is None else _p(hc))
     out["rejected"] = out["rejected"][:hits.size]
+    if smooth:
+        out["hit_par"] = hp[:hits.size]
+        out["hit_cov"] = hc[:hits.size]
     return out
 
 

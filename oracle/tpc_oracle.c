@@ -812,9 +812,12 @@ static void fit_material_points(int32_t n, const double *xs, const double *ys, c
             double mg = fabs(chi - mat->chi2_cut) / (mat->chi2_cut + 1.0);
             if (mg < *margin) *margin = mg;
         }
-        if (chi > mat->chi2_cut) { rej[k] = 1; continue; }
-        if (update(p, C, ys[k], zs[k], vys[k], vzs[k], &chi2)) { st = 3; break; }
-        ++used;
+        if (chi > mat->chi2_cut) {
+            rej[k] = 1;
+        } else {
+            if (update(p, C, ys[k], zs[k], vys[k], vzs[k], &chi2)) { st = 3; break; }
+            ++used;
+        }
     }
     *xo = xcur;
     for (int i = 0; i < 5; ++i) po[i] = p[i];
@@ -879,7 +882,10 @@ void oracle_fit_material(int32_t n_tracks, const int32_t *offsets, const int32_t
 /* h is measured with variances err[h][0]^2, err[h][1]^2 (err null: sigma_y^2 */
 /* and sigma_z^2 for every hit), which also enter the start covariance at     */
 /* the outermost hit.  Otherwise this is the fit with material above, and     */
-/* with an infinite radiation length and no cut the plain fit.               */
+/* with an infinite radiation length and no cut the plain fit.  When asked,  */
+/* the smoother about the fit's trajectory (smooth_reference) then gives the */
+/* state at every hit's plane from all hits; a failing smoother step sets    */
+/* status 2 or 3 and zero smoothed states.                                   */
 /* ------------------------------------------------------------------------ */
 
 /* Pad row of cluster id among the rows [base, base + n_rows) of one
@@ -896,15 +902,167 @@ static int32_t row_of(const int32_t *row_offsets, int32_t base, int32_t n_rows, 
     return lo;
 }
 
+/* Inverse of a 5x5 matrix by Gauss-Jordan elimination with partial
+ * pivoting; returns 0, or 1 if a pivot vanishes. */
+static int inv5(const double *A, double *X)
+{
+    double M[5][10];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 10; ++j) M[i][j] = j < 5 ? A[i * 5 + j] : (j - 5 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 5; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 5; ++i)
+            if (fabs(M[i][c]) > fabs(M[piv][c])) piv = i;
+        if (!(fabs(M[piv][c]) > 0.0)) return 1;
+        if (piv != c)
+            for (int j = 0; j < 10; ++j) { double t = M[c][j]; M[c][j] = M[piv][j]; M[piv][j] = t; }
+        double d = M[c][c];
+        for (int j = 0; j < 10; ++j) M[c][j] /= d;
+        for (int i = 0; i < 5; ++i) {
+            if (i == c) continue;
+            double f = M[i][c];
+            for (int j = 0; j < 10; ++j) M[i][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) X[i * 5 + j] = M[i][j + 5];
+    return 0;
+}
+
+/* Smoother about a reference trajectory.  The reference is the fit's final
+ * state carried by the exact helix step to every plane (r_k; a step that
+ * fails ends the smoothing with status 2).  About it the problem is linear
+ * in the deviation d = state - r: the step from plane k to plane k-1 maps d
+ * by its Jacobian F_k (taken on the reference), the scattering of that
+ * segment adds Q_k (from r_k) before the step, and a hit measures
+ * (y, z) of r + d.  A Kalman filter of d runs inwards from plane n-1 (d = 0,
+ * variances (100 sigma)^2 on y and z and the start variances on the other
+ * three), taking the hits the fit used (none it rejected); then the
+ * Rauch-Tung-Striebel pass outwards:
+ *   G = C_k F_k^T P^-1,  P = F_k (C_k + Q_k) F_k^T,
+ *   d_s(k) = d_k + G (d_s(k-1) - F_k d_k),
+ *   C_s(k) = C_k + G (C_s(k-1) - P) G^T,
+ * starting from the filtered d at plane 0.  The smoothed state is r_k +
+ * d_s(k), written to sp[n][5], sc[n][15] (packed).  Returns 0, 2 or 3. */
+static int32_t smooth_reference(int32_t n, const double *xs, const double *ys, const double *zs,
+                                const double *vys, const double *vzs, const uint8_t *rej, const double *pfin,
+                                const oracle_fit_params *prm, const oracle_material *mat,
+                                double *sp, double *sc)
+{
+    /* per plane: reference state (5), Jacobian of the step inwards from it
+     * (25), scattering covariance of that segment (25), filtered d (5) and
+     * covariance (25) */
+    double *w = (double *)malloc(sizeof(double) * (size_t)n * 85);
+    double *R = w, *FJ = w + (size_t)n * 5, *QS = w + (size_t)n * 30, *D = w + (size_t)n * 55,
+           *CD = w + (size_t)n * 60;
+    int32_t st = 0;
+    memcpy(R, pfin, sizeof(double) * 5);
+    for (int k = 1; k < n && !st; ++k) {       /* the reference, outwards */
+        double F[25];
+        if (oracle_propagate(pfin, xs[k] - xs[0], prm->bz, prm->max_sin, R + (size_t)k * 5, F)) st = 2;
+    }
+    for (int k = 1; k < n && !st; ++k) {       /* steps inwards along it */
+        double pp[5];
+        double dx = xs[k - 1] - xs[k];
+        if (oracle_propagate(R + (size_t)k * 5, dx, prm->bz, prm->max_sin, pp, FJ + (size_t)k * 25)) st = 2;
+        double *Q = QS + (size_t)k * 25;
+        for (int i = 0; i < 25; ++i) Q[i] = 0.0;
+        add_scattering(R + (size_t)k * 5, dx, mat, Q);
+    }
+    /* inward filter of the deviation */
+    double d[5] = {0, 0, 0, 0, 0}, C[25], chi2 = 0.0;
+    for (int i = 0; i < 25; ++i) C[i] = 0.0;
+    C[0] = 1e4 * vys[n - 1];
+    C[6] = 1e4 * vzs[n - 1];
+    C[12] = prm->var_sin0;
+    C[18] = prm->var_tgl0;
+    C[24] = prm->var_qpt0;
+    for (int k = n - 1; k >= 0 && !st; --k) {
+        if (k < n - 1) {
+            const double *F = FJ + (size_t)(k + 1) * 25, *Q = QS + (size_t)(k + 1) * 25;
+            double Ft[25], T[25], nd[5];
+            for (int i = 0; i < 25; ++i) C[i] += Q[i];
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j < 5; ++j) Ft[i * 5 + j] = F[j * 5 + i];
+            mat5_mul(F, C, T);
+            mat5_mul(T, Ft, C);
+            for (int i = 0; i < 5; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < 5; ++j) acc += F[i * 5 + j] * d[j];
+                nd[i] = acc;
+            }
+            memcpy(d, nd, sizeof d);
+        }
+        if (!rej[k]) {
+            /* the hit measures r + d: update d with the residual about r */
+            const double *r = R + (size_t)k * 5;
+            double md[5];
+            memcpy(md, d, sizeof md);
+            if (update(md, C, ys[k] - r[0], zs[k] - r[1], vys[k], vzs[k], &chi2)) st = 3;
+            memcpy(d, md, sizeof d);
+        }
+        memcpy(D + (size_t)k * 5, d, sizeof d);
+        memcpy(CD + (size_t)k * 25, C, sizeof C);
+    }
+    if (!st) {
+        /* outwards: Rauch-Tung-Striebel */
+        double ds[5], Cs[25];
+        memcpy(ds, D, sizeof ds);
+        memcpy(Cs, CD, sizeof Cs);
+        for (int i = 0; i < 5; ++i) sp[i] = R[i] + ds[i];
+        pack_cov(Cs, sc);
+        for (int k = 1; k < n && !st; ++k) {
+            const double *F = FJ + (size_t)k * 25, *Q = QS + (size_t)k * 25;
+            const double *dk = D + (size_t)k * 5, *Ck = CD + (size_t)k * 25;
+            double Cq[25], Ft[25], T[25], P[25], Pi[25], G[25], Gt[25], E[25], GE[25], pd[5];
+            for (int i = 0; i < 25; ++i) Cq[i] = Ck[i] + Q[i];
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j < 5; ++j) Ft[i * 5 + j] = F[j * 5 + i];
+            mat5_mul(F, Cq, T);
+            mat5_mul(T, Ft, P);
+            if (inv5(P, Pi)) { st = 3; break; }
+            mat5_mul(Ck, Ft, T);
+            mat5_mul(T, Pi, G);
+            for (int i = 0; i < 5; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < 5; ++j) acc += F[i * 5 + j] * dk[j];
+                pd[i] = acc;
+            }
+            double nds[5];
+            for (int i = 0; i < 5; ++i) {
+                double acc = dk[i];
+                for (int j = 0; j < 5; ++j) acc += G[i * 5 + j] * (ds[j] - pd[j]);
+                nds[i] = acc;
+            }
+            for (int i = 0; i < 25; ++i) E[i] = Cs[i] - P[i];
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j < 5; ++j) Gt[i * 5 + j] = G[j * 5 + i];
+            mat5_mul(G, E, T);
+            mat5_mul(T, Gt, GE);
+            for (int i = 0; i < 25; ++i) Cs[i] = Ck[i] + GE[i];
+            memcpy(ds, nds, sizeof ds);
+            for (int i = 0; i < 5; ++i) sp[(size_t)k * 5 + i] = R[(size_t)k * 5 + i] + ds[i];
+            pack_cov(Cs, sc + (size_t)k * 15);
+        }
+    }
+    free(w);
+    return st;
+}
+
 static void fit_one_rows(int32_t n, const int32_t *hit, int32_t frame, int32_t sec,
                          const int32_t *row_offsets, int32_t n_frames, int32_t n_sectors, int32_t n_rows,
                          const double *y, const double *z, const double *row_x, const float *err,
                          const oracle_fit_params *prm, const oracle_material *mat,
                          double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto,
-                         uint8_t *rej, double *margin)
+                         uint8_t *rej, double *margin, double *sp, double *sc)
 {
     double xs[512], ys[512], zs[512], vys[512], vzs[512];
     refuse(n, xo, po, co, chi2o, ndfo, sto, rej, margin);
+    if (sp)
+        for (int k = 0; k < n && k < 512; ++k) {
+            for (int i = 0; i < 5; ++i) sp[(size_t)k * 5 + i] = 0.0;
+            for (int i = 0; i < 15; ++i) sc[(size_t)k * 15 + i] = 0.0;
+        }
     if (n < 3 || n > 512 || frame < 0 || frame >= n_frames || sec < 0 || sec >= n_sectors) return;
     int32_t base = (frame * n_sectors + sec) * n_rows;
     int32_t prev = -1;
@@ -924,7 +1082,21 @@ static void fit_one_rows(int32_t n, const int32_t *hit, int32_t frame, int32_t s
             vzs[k] = prm->sigma_z * prm->sigma_z;
         }
     }
+    if (!sp) {
+        fit_material_points(n, xs, ys, zs, vys, vzs, prm, mat, xo, po, co, chi2o, ndfo, sto, rej, margin);
+        return;
+    }
     fit_material_points(n, xs, ys, zs, vys, vzs, prm, mat, xo, po, co, chi2o, ndfo, sto, rej, margin);
+    if (*sto == 0) {
+        int32_t s2 = smooth_reference(n, xs, ys, zs, vys, vzs, rej, po, prm, mat, sp, sc);
+        if (s2) {
+            *sto = s2;
+            for (int k = 0; k < n; ++k) {
+                for (int i = 0; i < 5; ++i) sp[(size_t)k * 5 + i] = 0.0;
+                for (int i = 0; i < 15; ++i) sc[(size_t)k * 15 + i] = 0.0;
+            }
+        }
+    }
 }
 
 void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
@@ -933,12 +1105,14 @@ void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hi
                      const double *y, const double *z, const double *row_x, const float *err,
                      const oracle_fit_params *prm, const oracle_material *mat,
                      double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
-                     uint8_t *rejected, double *margin)
+                     uint8_t *rejected, double *margin, double *hit_par, double *hit_cov)
 {
     #pragma omp parallel for schedule(dynamic, 64)
     for (int32_t i = 0; i < n_tracks; ++i) {
         fit_one_rows(offsets[i + 1] - offsets[i], hits + offsets[i], frame[i], sector[i], row_offsets,
                      n_frames, n_sectors, n_rows, y, z, row_x, err, prm, mat, &x_out[i], &par[(size_t)i * 5],
-                     &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i], rejected + offsets[i], &margin[i]);
+                     &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i], rejected + offsets[i], &margin[i],
+                     hit_par ? hit_par + (size_t)offsets[i] * 5 : NULL,
+                     hit_cov ? hit_cov + (size_t)offsets[i] * 15 : NULL);
     }
 }

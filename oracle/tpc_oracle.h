@@ -68,7 +68,7 @@ void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hi
                      const double *y, const double *z, const double *row_x, const float *err,
                      const oracle_fit_params *prm, const oracle_material *mat,
                      double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
-                     uint8_t *rejected, double *margin);
+                     uint8_t *rejected, double *margin, double *hit_par, double *hit_cov);
 
 /* rANS coder of integer arrays (rans_oracle.c) */
 #include <stddef.h>
