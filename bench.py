@@ -31,7 +31,8 @@ Extra legs, reported beside the headline value:
            2^13, counts read on the device), eagerly and as a graph;
            clusters/s and bits per cluster
   material the fit with multiple scattering (radiation length 2870 cm, pion
-           mass) and outlier rejection (chi2 > 30) on the headline seeds
+           mass) and outlier rejection (chi2 > 30) on the headline seeds, and
+           the same fit over rows followed by the smoother (tpc_kalman_smooth)
   skip     the headline event with 10% pad-row inefficiency: neighbours across
            one missing row + seeding + the fit over the hits' own rows, against
            the adjacent-row path on the same frame (times per call, seed
@@ -531,9 +532,23 @@ def leg_material(args):
     torch.cuda.synchronize()
     ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     flops = (FLOP_FIT_PER_HIT + 40) * H            # the fit's step and update, plus the noise term
+    # the fit over rows followed by the smoother, same seeds and material
+    mat = (MAT_X0, PION_MASS, MAT_CUT)
+    out = reco.smooth(dfr, seeds, material=mat, ws=ws)
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        out = reco.smooth(dfr, seeds, material=mat, tracks=out[0], ws=ws)
+        e[1].record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms_s = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     return {"workload": fr.meta["name"], "seeds": T, "seed_hits": H, "x0_cm": MAT_X0, "chi2_cut": MAT_CUT,
             "rejected_hits": int(rej[:H].sum()), "ms": round(ms, 5),
             "tracks_per_s": round(T / ms * 1e3, 1),
+            "fit_and_smoother_ms": round(ms_s, 5), "smoothed_hits_per_s": round(H / ms_s * 1e3, 1),
             "roofline": {"bound": "alu", "achieved": round(flops / (ms * 1e-3) / 1e12, 4),
                          "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(flops / (ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS, 5),

@@ -115,7 +115,8 @@ void tpc_destroy(tpc_context *ctx);
 #define TPC_STAGE_FOLLOW     32
 #define TPC_STAGE_CTF        64
 #define TPC_STAGE_SKIP      128
-#define TPC_STAGE_ALL       255
+#define TPC_STAGE_SMOOTH    256
+#define TPC_STAGE_ALL       511
 
 /* Workspace bytes needed by the stages in `stage_mask` for frames of this
  * shape (only n_frames and n_clusters are read; host call, no device work).
@@ -241,6 +242,31 @@ tpc_status tpc_kalman_fit_rows(const tpc_context *ctx, const tpc_frames *frames,
                                const tpc_seeds *seeds, const float *cluster_err,
                                const tpc_material *mat, tpc_tracks *tracks, uint8_t *rejected,
                                void *ws, size_t ws_bytes, void *stream);
+
+/* The fit over rows (tpc_kalman_fit_rows, same arguments and outputs), then
+ * a smoother giving the state at every seed hit's plane from all hits --
+ * part of the two-pass fitting that the paper's reconstruction implies but
+ * does not describe.  Reference: the fit's final state carried by exact
+ * helix steps to every plane.  About it the problem is linear in the
+ * deviation d = state - reference: a Kalman filter of d runs inwards from
+ * the outermost hit (d = 0, variances (100 sigma)^2 on y and z and var_sin0,
+ * var_tgl0, var_qpt0), with the step Jacobians and the scattering noise of
+ * mat taken on the reference and the hits the fit used (not those it
+ * rejected); then the Rauch-Tung-Striebel pass outwards,
+ *   G = C_k F^T P^-1,  P = F (C_k + Q) F^T,
+ *   d_s(k) = d_k + G (d_s(k-1) - F d_k),  C_s(k) = C_k + G (C_s(k-1) - P) G^T.
+ * hit_par[h][5] and hit_cov[h][15] (packed like tracks->cov) receive the
+ * smoothed state reference + d_s and its covariance at seed hit h's plane,
+ * in seed-hit order; zeros for seeds whose fit failed.  A failing smoother
+ * step sets the track's status to TPC_FIT_SIN_FAIL or TPC_FIT_NUM_FAIL.
+ * Double precision throughout, single-precision outputs.
+ * rejected, hit_par, hit_cov: device, [cap_hits], [cap_hits][5],
+ * [cap_hits][15], required.  ws: TPC_STAGE_SMOOTH workspace (the fit's,
+ * plus 5 doubles per seed and 20 doubles + 2 bytes per seed hit). */
+tpc_status tpc_kalman_smooth(const tpc_context *ctx, const tpc_frames *frames,
+                             const tpc_seeds *seeds, const float *cluster_err,
+                             const tpc_material *mat, tpc_tracks *tracks, uint8_t *rejected,
+                             float *hit_par, float *hit_cov, void *ws, size_t ws_bytes, void *stream);
 
 /* Checkpoint-buffer bytes for seeds of these capacities (host call). */
 tpc_status tpc_ckpt_bytes(const tpc_context *ctx, const tpc_seeds *seeds, size_t *bytes);

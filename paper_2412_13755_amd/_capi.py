@@ -31,7 +31,8 @@ TPC_STAGE_ADJOINT = 8
 TPC_STAGE_FOLLOW = 32
 TPC_STAGE_CTF = 64
 TPC_STAGE_SKIP = 128
-TPC_STAGE_ALL = 255
+TPC_STAGE_SMOOTH = 256
+TPC_STAGE_ALL = 511
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32
@@ -142,6 +143,9 @@ SIGNATURES = {
     "tpc_kalman_fit_rows": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
                                   ctypes.POINTER(Material), ctypes.POINTER(TracksC), P, P,
                                   ctypes.c_size_t, P]),
+    "tpc_kalman_smooth": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
+                                ctypes.POINTER(Material), ctypes.POINTER(TracksC), P, P, P, P,
+                                ctypes.c_size_t, P]),
     "tpc_rans_decode_workspace_bytes": (i32, [ctypes.POINTER(ctypes.c_size_t)]),
     "tpc_rans_decode": (i32, [P, ctypes.c_size_t, P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]),
     "tpc_persistent_grid": (i32, [P]),

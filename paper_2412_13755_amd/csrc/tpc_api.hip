@@ -82,6 +82,7 @@ size_t stage_bytes(const tpc_context *ctx, const tpc_frames *fr, int32_t mask) {
     if (mask & TPC_STAGE_FOLLOW) b = std::max(b, follow_ws_layout(nullptr, N, NR, nullptr));
     if (mask & TPC_STAGE_CTF) b = std::max(b, ctf_ws_layout(nullptr, N, NR, cs, nullptr));
     if (mask & TPC_STAGE_SKIP) b = std::max(b, skip_ws_layout(nullptr, N, NR, nullptr));
+    if (mask & TPC_STAGE_SMOOTH) b = std::max(b, smooth_ws_layout(nullptr, cs, N > 0 ? N : 1, nullptr));
     return b;
 }
 
@@ -308,6 +309,26 @@ tpc_status tpc_kalman_fit_rows(const tpc_context *ctx, const tpc_frames *fr, con
     if (sd->cap_seeds == 0) return TPC_OK;
     hipError_t e = launch_fit_rows(ctx, fr, sd, cluster_err, mat, tr, rejected, ws, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernel");
+}
+
+tpc_status tpc_kalman_smooth(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                             const float *cluster_err, const tpc_material *mat, tpc_tracks *tr,
+                             uint8_t *rejected, float *hit_par, float *hit_cov, void *ws, size_t ws_bytes,
+                             void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if ((s = check_material(mat))) return s;
+    if (((uintptr_t)cluster_err & 7) != 0) return fail(TPC_ERR_ARG, "cluster_err not 8-byte aligned");
+    if (sd->cap_hits > 0 && (!rejected || !hit_par || !hit_cov))
+        return fail(TPC_ERR_ARG, "null rejected, hit_par or hit_cov");
+    if ((s = check_ws(ws, ws_bytes, smooth_ws_layout(nullptr, sd->cap_seeds, sd->cap_hits, nullptr)))) return s;
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_smooth(ctx, fr, sd, cluster_err, mat, tr, rejected, hit_par, hit_cov, ws,
+                                 (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "fit and smoother kernels");
 }
 
 tpc_status tpc_chi2_sum(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr,

@@ -18,6 +18,17 @@
 //                 a seed whose rows do not rise strictly, or with a hit
 //                 outside its (frame, sector), is refused before the fit.
 //                 ERRS: hit h is measured with variances err[h]^2.
+//  smooth_tracks  thread per seed, after the fit over rows: the state at
+//                 every hit's plane from all hits.  The reference is the
+//                 fit's final state (FP64, from the fit kernel) carried by
+//                 exact helix steps to every plane; about it a Kalman filter
+//                 of the deviation runs inwards (Jacobians and scattering
+//                 noise taken on the reference, diffuse start, the hits the
+//                 fit used), storing the filtered deviation and covariance
+//                 of each hit (20 doubles) and its row; then the
+//                 Rauch-Tung-Striebel pass outwards recomputes the reference
+//                 steps and solves with P = F (C + Q) F^T by a Cholesky
+//                 factorisation.
 #include "tpc_fit_common.hpp"
 #include "tpc_fit_ms.hpp"
 
@@ -34,6 +45,7 @@ struct MsArgs {
     const int32_t *frame;         // frame of each seed
     int32_t n_frames;
     const float2 *err;            // per-cluster (sigma_y, sigma_z), cm
+    double *pfin;                 // [cap_seeds][5] final state in FP64, or null
 };
 
 // Adds the scattering of a segment of plane distance dx to C (state p at
@@ -194,6 +206,8 @@ __device__ inline void fit_ms_one(const MsArgs &A, int i, const float *xs) {
             ++used;
         }
     }
+    if (A.pfin)
+        for (int q = 0; q < 5; ++q) A.pfin[(size_t)i * 5 + q] = p[q];
     F.out.x[i] = (float)xcur;
     float *po = F.out.par + (size_t)i * 5;
     for (int q = 0; q < 5; ++q) po[q] = (float)p[q];
@@ -215,6 +229,271 @@ __global__ void __launch_bounds__(TPC_BLOCK) fit_ms_tracks(MsArgs A) {
     if (T > A.F.cap_seeds) T = A.F.cap_seeds;
     for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK)
         fit_ms_one<ROWS, ERRS>(A, i, xs);
+}
+
+struct SmArgs {
+    MsArgs M;
+    SmWs w;
+    const uint8_t *rej;
+    float *hit_par, *hit_cov;
+};
+
+__device__ inline void sym_add(SymT<double> &C, const SymT<double> &Q) {
+    C.c00 += Q.c00; C.c10 += Q.c10; C.c11 += Q.c11; C.c20 += Q.c20; C.c21 += Q.c21;
+    C.c22 += Q.c22; C.c30 += Q.c30; C.c31 += Q.c31; C.c32 += Q.c32; C.c33 += Q.c33;
+    C.c40 += Q.c40; C.c41 += Q.c41; C.c42 += Q.c42; C.c43 += Q.c43; C.c44 += Q.c44;
+}
+
+__device__ inline void sym_dense(const SymT<double> &C, double M[5][5]) {
+    const double v[15] = {C.c00, C.c10, C.c11, C.c20, C.c21, C.c22, C.c30, C.c31,
+                          C.c32, C.c33, C.c40, C.c41, C.c42, C.c43, C.c44};
+    int q = 0;
+    for (int r = 0; r < 5; ++r)
+        for (int c = 0; c <= r; ++c, ++q) M[r][c] = M[c][r] = v[q];
+}
+
+__device__ inline SymT<double> sym_packed(const double M[5][5]) {
+    SymT<double> C;
+    C.c00 = M[0][0]; C.c10 = M[1][0]; C.c11 = M[1][1]; C.c20 = M[2][0]; C.c21 = M[2][1];
+    C.c22 = M[2][2]; C.c30 = M[3][0]; C.c31 = M[3][1]; C.c32 = M[3][2]; C.c33 = M[3][3];
+    C.c40 = M[4][0]; C.c41 = M[4][1]; C.c42 = M[4][2]; C.c43 = M[4][3]; C.c44 = M[4][4];
+    return C;
+}
+
+// d <- F d for the step Jacobian (identity plus the six off-diagonal terms).
+__device__ inline void jac_apply(const StepJac &J, const double d[5], double o[5]) {
+    o[0] = d[0] + J.f02 * d[2] + J.f04 * d[4];
+    o[1] = d[1] + J.f12 * d[2] + J.f13 * d[3] + J.f14 * d[4];
+    o[2] = d[2] + J.f24 * d[4];
+    o[3] = d[3];
+    o[4] = d[4];
+}
+
+// A = F C (dense) for the step Jacobian.
+__device__ inline void jac_times(const StepJac &J, const double C[5][5], double A[5][5]) {
+    for (int c = 0; c < 5; ++c) {
+        A[0][c] = C[0][c] + J.f02 * C[2][c] + J.f04 * C[4][c];
+        A[1][c] = C[1][c] + J.f12 * C[2][c] + J.f13 * C[3][c] + J.f14 * C[4][c];
+        A[2][c] = C[2][c] + J.f24 * C[4][c];
+        A[3][c] = C[3][c];
+        A[4][c] = C[4][c];
+    }
+}
+
+// Solves P X = A (P symmetric positive definite, 5x5) in place of A by a
+// Cholesky factorisation; false if a pivot is not positive.
+__device__ inline bool chol_solve(double P[5][5], double A[5][5]) {
+    for (int j = 0; j < 5; ++j) {
+        double s = P[j][j];
+        for (int k = 0; k < j; ++k) s -= P[j][k] * P[j][k];
+        if (!(s > 0.0)) return false;
+        const double l = sqrt(s);
+        P[j][j] = l;
+        for (int r = j + 1; r < 5; ++r) {
+            double t = P[r][j];
+            for (int k = 0; k < j; ++k) t -= P[r][k] * P[j][k];
+            P[r][j] = t / l;
+        }
+    }
+    for (int c = 0; c < 5; ++c) {
+        for (int r = 0; r < 5; ++r) {           // L y = a
+            double t = A[r][c];
+            for (int k = 0; k < r; ++k) t -= P[r][k] * A[k][c];
+            A[r][c] = t / P[r][r];
+        }
+        for (int r = 4; r >= 0; --r) {          // L^T x = y
+            double t = A[r][c];
+            for (int k = r + 1; k < 5; ++k) t -= P[k][r] * A[k][c];
+            A[r][c] = t / P[r][r];
+        }
+    }
+    return true;
+}
+
+template <bool ERRS>
+__device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
+    const MsArgs &A = S.M;
+    const FitArgs &F = A.F;
+    const SeedView sv = seed_view(F, i);
+    const int n = sv.n;
+    if (!(n >= 3 && sv.o0 >= 0 && sv.o0 <= F.cap_hits - n)) return;
+    float *hp = S.hit_par + (size_t)sv.o0 * 5;
+    float *hc = S.hit_cov + (size_t)sv.o0 * 15;
+    int status = F.out.status[i];
+    if (status == TPC_FIT_OK) {
+        // the fit accepted the seed, so its rows are valid
+        const int32_t *ro = A.row_offsets + ((size_t)A.frame[i] * F.n_sectors + sv.sec) * F.n_rows;
+        int ra, rb, rc;
+        seed_rows(ro, F.n_rows, sv, ra, rb, rc);
+        const double *pf = S.w.pfin + (size_t)i * 5;
+        double *wd = S.w.wd + (size_t)sv.o0 * 20;
+        int16_t *wr = S.w.wrow + sv.o0;
+        const uint8_t *rej = S.rej + sv.o0;
+        // inwards: reference at the outermost plane, then steps along it
+        double R[5];
+        for (int q = 0; q < 5; ++q) R[q] = pf[q];
+        StepJac J;
+        if (!helix_step<double, double>(R, (double)xs[ra] - (double)xs[rc], A.kbz, F.max_sin, J))
+            status = TPC_FIT_SIN_FAIL;
+        double vy = F.vy, vz = F.vz;
+        if (ERRS) {
+            const float2 e = A.err[sv.hh[n - 1]];
+            vy = (double)e.x * (double)e.x;
+            vz = (double)e.y * (double)e.y;
+        }
+        double d[5] = {0, 0, 0, 0, 0};
+        SymT<double> C = {};
+        C.c00 = 1e4 * vy;
+        C.c11 = 1e4 * vz;
+        C.c22 = F.var_s;
+        C.c33 = F.var_t;
+        C.c44 = F.var_w;
+        int rk = ra;
+        for (int k = n - 1; k >= 0 && status == TPC_FIT_OK; --k) {
+            if (k < n - 1) {
+                const int rn = walk_row(ro, rk - 1, sv.hh[k]);
+                const double dx = (double)xs[rn] - (double)xs[rk];
+                SymT<double> Q = {};
+                add_scattering(A, R, dx, Q);
+                sym_add(C, Q);
+                if (!helix_step<double, double>(R, dx, A.kbz, F.max_sin, J)) {
+                    status = TPC_FIT_SIN_FAIL;
+                    break;
+                }
+                double nd[5];
+                jac_apply(J, d, nd);
+                for (int q = 0; q < 5; ++q) d[q] = nd[q];
+                sym_transport<double, false>(C, J);
+                rk = rn;
+                if (ERRS) {
+                    const float2 e = A.err[sv.hh[k]];
+                    vy = (double)e.x * (double)e.x;
+                    vz = (double)e.y * (double)e.y;
+                }
+            }
+            if (!rej[k]) {
+                double my, mz;
+                hit_meas(F, sv, k, F.hyz ? 0 : sv.hh[k], my, mz);
+                const double dchi = kalman_update<double>(d, C, my - R[0], mz - R[1], vy, vz);
+                const double chk = dchi + d[0] + d[1] + d[2] + d[3] + d[4];
+                if (!(chk - chk == 0.0)) {
+                    status = TPC_FIT_NUM_FAIL;
+                    break;
+                }
+            }
+            double *w = wd + (size_t)k * 20;
+            for (int q = 0; q < 5; ++q) w[q] = d[q];
+            const double cc[15] = {C.c00, C.c10, C.c11, C.c20, C.c21, C.c22, C.c30, C.c31,
+                                   C.c32, C.c33, C.c40, C.c41, C.c42, C.c43, C.c44};
+            for (int q = 0; q < 15; ++q) w[5 + q] = cc[q];
+            wr[k] = (int16_t)rk;
+        }
+        // outwards: Rauch-Tung-Striebel
+        if (status == TPC_FIT_OK) {
+            double ds[5], Cs[5][5];
+            for (int q = 0; q < 5; ++q) { R[q] = pf[q]; ds[q] = wd[q]; }
+            {
+                SymT<double> C0;
+                const double *w = wd;
+                C0.c00 = w[5]; C0.c10 = w[6]; C0.c11 = w[7]; C0.c20 = w[8]; C0.c21 = w[9];
+                C0.c22 = w[10]; C0.c30 = w[11]; C0.c31 = w[12]; C0.c32 = w[13]; C0.c33 = w[14];
+                C0.c40 = w[15]; C0.c41 = w[16]; C0.c42 = w[17]; C0.c43 = w[18]; C0.c44 = w[19];
+                sym_dense(C0, Cs);
+            }
+            for (int q = 0; q < 5; ++q) hp[q] = (float)(R[q] + ds[q]);
+            {
+                const SymT<double> P0 = sym_packed(Cs);
+                const double cc[15] = {P0.c00, P0.c10, P0.c11, P0.c20, P0.c21, P0.c22, P0.c30, P0.c31,
+                                       P0.c32, P0.c33, P0.c40, P0.c41, P0.c42, P0.c43, P0.c44};
+                for (int q = 0; q < 15; ++q) hc[q] = (float)cc[q];
+            }
+            int rprev = wr[0];
+            for (int k = 1; k < n; ++k) {
+                const int r = wr[k];
+                // the reference at plane k, and the step from it back inwards
+                if (!helix_step<double, double>(R, (double)xs[r] - (double)xs[rprev], A.kbz, F.max_sin, J)) {
+                    status = TPC_FIT_SIN_FAIL;
+                    break;
+                }
+                double Rt[5] = {R[0], R[1], R[2], R[3], R[4]};
+                const double dxi = (double)xs[rprev] - (double)xs[r];
+                StepJac Jk;
+                if (!helix_step<double, double>(Rt, dxi, A.kbz, F.max_sin, Jk)) {
+                    status = TPC_FIT_SIN_FAIL;
+                    break;
+                }
+                SymT<double> Ck;
+                const double *w = wd + (size_t)k * 20;
+                const double dk[5] = {w[0], w[1], w[2], w[3], w[4]};
+                Ck.c00 = w[5]; Ck.c10 = w[6]; Ck.c11 = w[7]; Ck.c20 = w[8]; Ck.c21 = w[9];
+                Ck.c22 = w[10]; Ck.c30 = w[11]; Ck.c31 = w[12]; Ck.c32 = w[13]; Ck.c33 = w[14];
+                Ck.c40 = w[15]; Ck.c41 = w[16]; Ck.c42 = w[17]; Ck.c43 = w[18]; Ck.c44 = w[19];
+                SymT<double> Pq = Ck, Q = {};
+                add_scattering(A, R, dxi, Q);
+                sym_add(Pq, Q);
+                sym_transport<double, false>(Pq, Jk);       // P = F (C_k + Q) F^T
+                double P[5][5], Pd[5][5], Cd[5][5], X[5][5];
+                sym_dense(Pq, P);
+                sym_dense(Pq, Pd);
+                sym_dense(Ck, Cd);
+                jac_times(Jk, Cd, X);                        // F C_k
+                if (!chol_solve(P, X)) {                     // X = P^-1 F C_k = G^T
+                    status = TPC_FIT_NUM_FAIL;
+                    break;
+                }
+                double pd[5], e[5], nds[5];
+                jac_apply(Jk, dk, pd);
+                for (int q = 0; q < 5; ++q) e[q] = ds[q] - pd[q];
+                for (int a = 0; a < 5; ++a) {
+                    double acc = dk[a];
+                    for (int b = 0; b < 5; ++b) acc += X[b][a] * e[b];
+                    nds[a] = acc;
+                }
+                // Cs <- C_k + G (Cs - P) G^T
+                double D[5][5], T[5][5];
+                for (int a = 0; a < 5; ++a)
+                    for (int b = 0; b < 5; ++b) D[a][b] = Cs[a][b] - Pd[a][b];
+                for (int a = 0; a < 5; ++a)
+                    for (int b = 0; b < 5; ++b) {
+                        double acc = 0.0;
+                        for (int c = 0; c < 5; ++c) acc += X[c][a] * D[c][b];
+                        T[a][b] = acc;
+                    }
+                for (int a = 0; a < 5; ++a)
+                    for (int b = 0; b <= a; ++b) {
+                        double acc = 0.0;
+                        for (int c = 0; c < 5; ++c) acc += T[a][c] * X[c][b];
+                        Cs[a][b] = Cs[b][a] = Cd[a][b] + acc;
+                    }
+                for (int q = 0; q < 5; ++q) ds[q] = nds[q];
+                float *o = hp + (size_t)k * 5;
+                for (int q = 0; q < 5; ++q) o[q] = (float)(R[q] + ds[q]);
+                float *oc = hc + (size_t)k * 15;
+                int q = 0;
+                for (int a = 0; a < 5; ++a)
+                    for (int b = 0; b <= a; ++b, ++q) oc[q] = (float)Cs[a][b];
+                rprev = r;
+            }
+        }
+        if (status != TPC_FIT_OK) F.out.status[i] = status;
+    }
+    if (status != TPC_FIT_OK) {
+        for (int k = 0; k < n; ++k) {
+            for (int q = 0; q < 5; ++q) hp[(size_t)k * 5 + q] = 0.f;
+            for (int q = 0; q < 15; ++q) hc[(size_t)k * 15 + q] = 0.f;
+        }
+    }
+}
+
+template <bool ERRS>
+__global__ void __launch_bounds__(TPC_BLOCK) smooth_tracks(SmArgs S) {
+    __shared__ float xs[TPC_MAX_ROWS];
+    for (int r = threadIdx.x; r < S.M.F.n_rows; r += TPC_BLOCK) xs[r] = S.M.F.row_x[r];
+    __syncthreads();
+    int T = *S.M.F.n_seeds;
+    if (T > S.M.F.cap_seeds) T = S.M.F.cap_seeds;
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK)
+        smooth_one<ERRS>(S, i, xs);
 }
 
 MsArgs make_ms_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd, const tpc_material *mat,
@@ -240,6 +519,7 @@ MsArgs make_ms_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seed
     A.frame = sd->frame;
     A.n_frames = fr->n_frames;
     A.err = nullptr;
+    A.pfin = nullptr;
     return A;
 }
 
@@ -269,5 +549,37 @@ hipError_t launch_fit_rows(const tpc_context *ctx, const tpc_frames *fr, const t
         hipLaunchKernelGGL((fit_ms_tracks<true, true>), dim3(fit_blocks(sd)), dim3(TPC_BLOCK), 0, st, A);
     else
         hipLaunchKernelGGL((fit_ms_tracks<true, false>), dim3(fit_blocks(sd)), dim3(TPC_BLOCK), 0, st, A);
+    return hipGetLastError();
+}
+
+size_t smooth_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, SmWs *out) {
+    const size_t fb = fit_ws_layout(nullptr, cap_seeds, cap_hits, nullptr, nullptr);
+    WsCarver w(ws ? (void *)((char *)ws + fb) : nullptr);
+    double *pfin = w.take<double>((size_t)(cap_seeds > 0 ? cap_seeds : 1) * 5);
+    double *wd = w.take<double>((size_t)(cap_hits > 0 ? cap_hits : 1) * 20);
+    int16_t *wrow = w.take<int16_t>((size_t)(cap_hits > 0 ? cap_hits : 1));
+    if (out) *out = SmWs{pfin, wd, wrow};
+    return fb + ((w.off + 255) & ~size_t(255));
+}
+
+hipError_t launch_smooth(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd, const float *err,
+                         const tpc_material *mat, const tpc_tracks *tr, uint8_t *rejected, float *hit_par,
+                         float *hit_cov, void *ws, hipStream_t st) {
+    SmArgs S;
+    S.M = make_ms_args(ctx, fr, sd, mat, tr, rejected, ws, st);
+    S.M.err = reinterpret_cast<const float2 *>(err);
+    smooth_ws_layout(ws, sd->cap_seeds, sd->cap_hits, &S.w);
+    S.M.pfin = S.w.pfin;
+    S.rej = rejected;
+    S.hit_par = hit_par;
+    S.hit_cov = hit_cov;
+    const int blocks = fit_blocks(sd);
+    if (err) {
+        hipLaunchKernelGGL((fit_ms_tracks<true, true>), dim3(blocks), dim3(TPC_BLOCK), 0, st, S.M);
+        hipLaunchKernelGGL((smooth_tracks<true>), dim3(blocks), dim3(TPC_BLOCK), 0, st, S);
+    } else {
+        hipLaunchKernelGGL((fit_ms_tracks<true, false>), dim3(blocks), dim3(TPC_BLOCK), 0, st, S.M);
+        hipLaunchKernelGGL((smooth_tracks<false>), dim3(blocks), dim3(TPC_BLOCK), 0, st, S);
+    }
     return hipGetLastError();
 }

@@ -286,6 +286,32 @@ class Reco:
                                             _stream_handle(self.device)))
         return tracks, rejected
 
+    def smooth(self, frames: DeviceFrames, seeds: Seeds, cluster_err: Optional[torch.Tensor] = None,
+               material: Optional[tuple] = None, tracks: Optional[Tracks] = None, ws=None):
+        """tpc_kalman_smooth: the fit over rows, then the state at every seed
+        hit's plane.  Returns (Tracks, rejected, hit_par [cap_hits, 5],
+        hit_cov [cap_hits, 15])."""
+        tracks = self.alloc_tracks(seeds) if tracks is None else tracks
+        H = max(seeds.hits.numel(), 1)
+        rejected = torch.zeros(H, dtype=torch.uint8, device=self.device)
+        hit_par = torch.empty(H, 5, dtype=torch.float32, device=self.device)
+        hit_cov = torch.empty(H, 15, dtype=torch.float32, device=self.device)
+        ws = self.workspace(frames) if ws is None else ws
+        err = 0
+        if cluster_err is not None:
+            if (cluster_err.dtype != torch.float32 or cluster_err.device.type != self.device.type
+                    or tuple(cluster_err.shape) != (frames.n_clusters, 2) or not cluster_err.is_contiguous()):
+                raise ValueError("cluster_err must be a contiguous float32 [n_clusters, 2] tensor on the device")
+            err = cluster_err.data_ptr()
+        mat = None if material is None else ctypes.byref(C.Material(*(float(v) for v in material)))
+        sc = seeds.c()
+        tc = tracks.c()
+        C.check(C.lib().tpc_kalman_smooth(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc), err, mat,
+                                          ctypes.byref(tc), rejected.data_ptr(), hit_par.data_ptr(),
+                                          hit_cov.data_ptr(), ws.data_ptr(), ws.numel(),
+                                          _stream_handle(self.device)))
+        return tracks, rejected, hit_par, hit_cov
+
     def follow(self, frames: DeviceFrames, seeds: Seeds, gate_chi2: float, max_miss: int,
                rows: Optional[torch.Tensor] = None, tracks: Optional[Tracks] = None, ws=None):
         """Track following of every seed and duplicate removal (tpc_track_follow).

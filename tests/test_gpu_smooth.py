@@ -1,0 +1,88 @@
+"""GPU parity of the smoother (tpc_kalman_smooth through the C-ABI) against
+the oracle on the same seeds: the fit outputs to the fit tolerances, and the
+smoothed state at every seed hit's plane to the same tolerances (1e-4
+relative on parameters with the fit's floors, 1e-3 on the covariance
+relative to the product of standard deviations).  Tracks whose rejection
+decisions lie within 1e-6 (relative) of the cut are left out (the oracle
+reports that margin)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import NB, FIT, MIN_HITS
+from tests import parity
+from tpcsynth import make_config, make_scattering_frame, PION_MASS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def check(fr, label, skip=False, err=None, material=None):
+    import torch
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    print("[smooth] %s: N=%d" % (label, fr.n_clusters), flush=True)
+    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT), "cuda:0")
+    dfr = reco.upload(fr)
+    up, dn = (reco.neighbours_skip if skip else reco.neighbours)(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    derr = None if err is None else torch.from_numpy(np.ascontiguousarray(err, np.float32)).cuda()
+    tr, rej, hp, hc = reco.smooth(dfr, seeds, cluster_err=derr, material=material)
+    torch.cuda.synchronize()
+    nb = oracle.neighbours_skip if skip else oracle.neighbours
+    ru, rd = nb(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    rs = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, MIN_HITS)
+    parity.assert_seeds_equal(seeds.to_numpy(), rs)
+    x0, mass, cut = material if material is not None else (np.inf, PION_MASS, np.inf)
+    r = oracle.fit_rows(rs, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows, err=err,
+                        x0=x0, mass=mass, chi2_cut=cut, smooth=True, **FIT)
+    T, H = len(rs["offsets"]) - 1, rs["hits"].size
+    g = {k: getattr(tr, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "chi2", "ndf", "status")}
+    robust = r["margin"] >= 1e-6
+    assert (~robust).sum() <= max(2, T // 1000)
+    sub = lambda d: {k: np.asarray(d[k])[robust] for k in ("x", "par", "cov", "chi2", "ndf", "status")}
+    st = parity.compare_fit(sub(g), sub(r))
+    # smoothed states of the tracks both sides fitted
+    ok = robust & (g["status"] == 0) & (r["status"] == 0)
+    seg = np.repeat(np.arange(T), np.diff(rs["offsets"]))
+    m = ok[seg]
+    gp = hp[:H].cpu().numpy().astype(np.float64)[m]
+    gc = hc[:H].cpu().numpy().astype(np.float64)[m]
+    pr, cr = r["hit_par"][m], r["hit_cov"][m]
+    tol = parity.PAR_RTOL * np.maximum(np.abs(pr), parity.PAR_FLOOR)
+    dpar = np.abs(gp - pr) / np.maximum(np.abs(pr), parity.PAR_FLOOR)
+    assert not (np.abs(gp - pr) > tol).any(), "smoothed parameters: worst rel %.3g" % dpar.max()
+    C1, C2 = oracle.unpack_cov(gc), oracle.unpack_cov(cr)
+    sd_ = np.sqrt(np.einsum("tii->ti", C2))
+    dcov = np.abs(C1 - C2) / (sd_[:, :, None] * sd_[:, None, :])
+    assert dcov.max() <= parity.COV_RTOL, "smoothed covariance: worst %.3g" % dcov.max()
+    # failed tracks carry zeros
+    bad = (g["status"] != 0)[seg]
+    assert not hp[:H].cpu().numpy()[bad].any()
+    st.update(hits=int(m.sum()), worst_smooth_par=float(dpar.max()), worst_smooth_cov=float(dcov.max()))
+    print("[smooth] %s: %s" % (label, st), flush=True)
+    return st
+
+
+def test_single_sector_no_material(torch_dev):
+    check(make_config(0), "single sector")
+
+
+def test_stepped_scattering(torch_dev):
+    check(make_scattering_frame(n_tracks=400, seed=11, x0_cm=50.0, inv_pt=(0.5, 5.0)), "scattering x0 50",
+          material=(50.0, PION_MASS, 1e30))
+
+
+def test_headline_frame(torch_dev):
+    st = check(make_config(1), "full-tpc-event-1e4", material=(2870.0, PION_MASS, 30.0))
+    assert st["hits"] > 900000
+
+
+def test_skip_seeds_errors_and_rejection(torch_dev):
+    fr = make_config(1, scale=0.2, err_scale=(0.5, 2.0), hit_eff=0.9)
+    check(fr, "skip seeds, per-cluster errors, cut", skip=True, err=fr.err, material=(300.0, PION_MASS, 30.0))
