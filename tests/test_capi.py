@@ -31,8 +31,8 @@ def test_header_declares_the_path():
               "tpc_track_follow", "tpc_rans_encode", "tpc_rans_workspace_bytes",
               "tpc_rans_max_bytes", "tpc_ctf_build", "tpc_rans_encode_batch",
               "tpc_rans_batch_workspace_bytes", "tpc_kalman_fit_material", "tpc_rans_decode",
-              "tpc_rans_decode_workspace_bytes", "tpc_status_string",
-              "tpc_last_error"):
+              "tpc_rans_decode_workspace_bytes", "tpc_neighbours_skip", "tpc_kalman_fit_rows",
+              "tpc_kalman_smooth", "tpc_status_string", "tpc_last_error"):
         assert n in names
 
 
@@ -99,6 +99,12 @@ def test_calls_reject_null_context_and_frames(capi):
     fp = capi.FollowParams(25.0, 3)
     assert L.tpc_track_follow(None, ctypes.byref(fr), ctypes.byref(sd), ctypes.byref(fp), None,
                               ctypes.byref(tr), None, 0, None) == capi.TPC_ERR_ARG
+    assert L.tpc_neighbours_skip(None, ctypes.byref(fr), None, None, None, 0, None) == capi.TPC_ERR_ARG
+    assert L.tpc_kalman_fit_rows(None, ctypes.byref(fr), ctypes.byref(sd), None, None, ctypes.byref(tr),
+                                 None, None, 0, None) == capi.TPC_ERR_ARG
+    assert L.tpc_kalman_smooth(None, ctypes.byref(fr), ctypes.byref(sd), None, None, ctypes.byref(tr),
+                               None, None, None, None, 0, None) == capi.TPC_ERR_ARG
+    assert "context" in L.tpc_last_error().decode()
     n = ctypes.c_size_t()
     assert L.tpc_ckpt_bytes(None, ctypes.byref(sd), ctypes.byref(n)) == capi.TPC_ERR_ARG
     n = ctypes.c_size_t()
