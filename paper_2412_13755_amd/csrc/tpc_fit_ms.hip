@@ -24,8 +24,9 @@
 //                 exact helix steps to every plane; about it a Kalman filter
 //                 of the deviation runs inwards (Jacobians and scattering
 //                 noise taken on the reference, diffuse start, the hits the
-//                 fit used), storing the filtered deviation and covariance
-//                 of each hit (20 doubles) and its row; then the
+//                 fit used; rows as the fit stored them), storing the
+//                 filtered deviation and covariance of each hit (20
+//                 doubles); then the
 //                 Rauch-Tung-Striebel pass outwards recomputes the reference
 //                 steps and solves with P = F (C + Q) F^T by a Cholesky
 //                 factorisation.
@@ -46,6 +47,7 @@ struct MsArgs {
     int32_t n_frames;
     const float2 *err;            // per-cluster (sigma_y, sigma_z), cm
     double *pfin;                 // [cap_seeds][5] final state in FP64, or null
+    int16_t *rows_out;            // [cap_hits] row of every seed hit (ROWS), or null
 };
 
 // Adds the scattering of a segment of plane distance dx to C (state p at
@@ -162,12 +164,25 @@ __device__ inline void fit_ms_one(const MsArgs &A, int i, const float *xs) {
     if (status == TPC_FIT_OK) {
         float2 raw = hit_raw(F, sv, sv.n - 2, F.hyz ? 0 : sv.hh[sv.n - 2]);
         int rk = ra;
+        // ROWS: the row of the next hit is resolved a step ahead -- the row
+        // starts one and two rows below are loaded at the top of a step and
+        // compared after its helix step (a longer gap walks on); equal to
+        // walk_row, as seed_rows has checked every row
+        int rnext = ROWS ? walk_row(ro, ra - 1, sv.hh[sv.n - 2]) : 0;
+        if (ROWS && A.rows_out) A.rows_out[sv.o0 + sv.n - 1] = (int16_t)ra;
         for (int k = sv.n - 2; k >= 0; --k) {
             double my, mz;
             hit_fix(F, sv, k, raw, my, mz);
             if (k > 0) raw = hit_raw(F, sv, k - 1, F.hyz ? 0 : sv.hh[k - 1]);
+            int32_t nid = 0, v1 = INT32_MAX, v2 = INT32_MAX;
             if (ROWS) {
-                rk = walk_row(ro, rk - 1, sv.hh[k]);     // valid: checked by seed_rows
+                rk = rnext;
+                if (A.rows_out) A.rows_out[sv.o0 + k] = (int16_t)rk;
+                if (k > 0) {
+                    nid = sv.hh[k - 1];
+                    if (rk >= 1) v1 = ro[rk - 1];
+                    if (rk >= 2) v2 = ro[rk - 2];
+                }
             } else {
                 rk = sv.row0 + k;
             }
@@ -186,6 +201,7 @@ __device__ inline void fit_ms_one(const MsArgs &A, int i, const float *xs) {
             }
             sym_transport<double, false>(C, J);
             xcur = xk;
+            if (ROWS && k > 0) rnext = nid >= v1 ? rk - 1 : (nid >= v2 ? rk - 2 : walk_row(ro, rk - 3, nid));
             // predicted-residual chi2 of the hit
             const double r0 = my - p[0], r1 = mz - p[1];
             const double S00 = C.c00 + vy, S01 = C.c10, S11 = C.c11 + vz;
@@ -321,13 +337,11 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
     float *hc = S.hit_cov + (size_t)sv.o0 * 15;
     int status = F.out.status[i];
     if (status == TPC_FIT_OK) {
-        // the fit accepted the seed, so its rows are valid
-        const int32_t *ro = A.row_offsets + ((size_t)A.frame[i] * F.n_sectors + sv.sec) * F.n_rows;
-        int ra, rb, rc;
-        seed_rows(ro, F.n_rows, sv, ra, rb, rc);
+        // the fit accepted the seed and stored the row of every hit
         const double *pf = S.w.pfin + (size_t)i * 5;
         double *wd = S.w.wd + (size_t)sv.o0 * 20;
-        int16_t *wr = S.w.wrow + sv.o0;
+        const int16_t *wr = S.w.wrow + sv.o0;
+        const int ra = wr[n - 1], rc = wr[0];
         const uint8_t *rej = S.rej + sv.o0;
         // inwards: reference at the outermost plane, then steps along it
         double R[5];
@@ -349,10 +363,12 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
         C.c33 = F.var_t;
         C.c44 = F.var_w;
         int rk = ra;
+        int rn = wr[n - 2];                 // loaded a step ahead
         for (int k = n - 1; k >= 0 && status == TPC_FIT_OK; --k) {
             if (k < n - 1) {
-                const int rn = walk_row(ro, rk - 1, sv.hh[k]);
-                const double dx = (double)xs[rn] - (double)xs[rk];
+                const int rcur = rn;
+                if (k > 0) rn = wr[k - 1];
+                const double dx = (double)xs[rcur] - (double)xs[rk];
                 SymT<double> Q = {};
                 add_scattering(A, R, dx, Q);
                 sym_add(C, Q);
@@ -364,7 +380,7 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                 jac_apply(J, d, nd);
                 for (int q = 0; q < 5; ++q) d[q] = nd[q];
                 sym_transport<double, false>(C, J);
-                rk = rn;
+                rk = rcur;
                 if (ERRS) {
                     const float2 e = A.err[sv.hh[k]];
                     vy = (double)e.x * (double)e.x;
@@ -386,7 +402,6 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
             const double cc[15] = {C.c00, C.c10, C.c11, C.c20, C.c21, C.c22, C.c30, C.c31,
                                    C.c32, C.c33, C.c40, C.c41, C.c42, C.c43, C.c44};
             for (int q = 0; q < 15; ++q) w[5 + q] = cc[q];
-            wr[k] = (int16_t)rk;
         }
         // outwards: Rauch-Tung-Striebel
         if (status == TPC_FIT_OK) {
@@ -520,6 +535,7 @@ MsArgs make_ms_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seed
     A.n_frames = fr->n_frames;
     A.err = nullptr;
     A.pfin = nullptr;
+    A.rows_out = nullptr;
     return A;
 }
 
@@ -570,6 +586,7 @@ hipError_t launch_smooth(const tpc_context *ctx, const tpc_frames *fr, const tpc
     S.M.err = reinterpret_cast<const float2 *>(err);
     smooth_ws_layout(ws, sd->cap_seeds, sd->cap_hits, &S.w);
     S.M.pfin = S.w.pfin;
+    S.M.rows_out = S.w.wrow;
     S.rej = rejected;
     S.hit_par = hit_par;
     S.hit_cov = hit_cov;
