@@ -16,7 +16,8 @@
 //                 row above for each next one (at most R + n reads of the
 //                 row offsets per seed, all within the seed's R + 1) -- and
 //                 a seed whose rows do not rise strictly, or with a hit
-//                 outside its (frame, sector), is refused before the fit.
+//                 outside its (frame, sector), is refused before the fit;
+//                 during the fit each next row is resolved a step ahead.
 //                 ERRS: hit h is measured with variances err[h]^2.
 //  smooth_tracks  thread per seed, after the fit over rows: the state at
 //                 every hit's plane from all hits.  The reference is the
@@ -26,10 +27,9 @@
 //                 noise taken on the reference, diffuse start, the hits the
 //                 fit used; rows as the fit stored them), storing the
 //                 filtered deviation and covariance of each hit (20
-//                 doubles); then the
-//                 Rauch-Tung-Striebel pass outwards recomputes the reference
-//                 steps and solves with P = F (C + Q) F^T by a Cholesky
-//                 factorisation.
+//                 doubles); then the Rauch-Tung-Striebel pass outwards
+//                 recomputes the reference steps and solves with
+//                 P = F (C + Q) F^T by a Cholesky factorisation.
 #include "tpc_fit_common.hpp"
 #include "tpc_fit_ms.hpp"
 

@@ -11,20 +11,19 @@
 //              SKIP_ROW_MAX clusters each, taking the row's clusters in
 //              chunks of SKIP_Q; rows in ascending order over all sectors,
 //              so that the inner rows, which hold the most clusters, do not
-//              trail.  A chunk's
-//              unlinked clusters with finite coordinates (the others cannot
-//              link) go to LDS, ranked by y; every thread streams clusters
-//              of the four partner rows (coalesced) and finds the queries
-//              in its window by a binary search over the ranked y -- exact,
-//              since rounding is monotonic, so the y predicate
-//              |fl(y_h - y_c)| <= w holds on a contiguous run of ranks --
-//              once to count each query's candidates per row, once more to
-//              store them (row position and coordinates) in exact-size lists
-//              carved from an LDS pool by a prefix sum; then a thread per
-//              query scores the (down, up) pairs of its lists, from LDS
-//              only, with the exact arithmetic of best_pair.  A chunk whose
-//              lists exceed the pool (far beyond any TPC occupancy) scans
-//              the two rows per query instead.
+//              trail.  A chunk's unlinked clusters with finite coordinates
+//              (the others cannot link) go to LDS, ranked by y; every thread
+//              streams clusters of the four partner rows (coalesced) and
+//              finds the queries in its window by a binary search over the
+//              ranked y -- exact, since rounding is monotonic, so the y
+//              predicate |fl(y_h - y_c)| <= w holds on a contiguous run of
+//              ranks -- once to count each query's candidates per row, once
+//              more to store them (row position and coordinates) in
+//              exact-size lists carved from an LDS pool by a prefix sum;
+//              then a thread per query scores the (down, up) pairs of its
+//              lists, from LDS only, with the exact arithmetic of best_pair.
+//              A chunk whose lists exceed the pool (far beyond any TPC
+//              occupancy) scans the two rows per query instead.
 //  skip_zero, skip_prep, skip_query
 //              the h-rows with a larger partner row: global cell-sorted
 //              copies of the rows they need, their unlinked clusters in one
