@@ -70,7 +70,7 @@ def lib():
         L.oracle_fit.argtypes = [i32, P, P, P, P, P, P, P, i32, P, ctypes.POINTER(FitParams),
                                  P, P, P, P, P, P]
         L.oracle_fit.restype = None
-        L.oracle_follow.argtypes = [i32, P, P, P, P, P, P, i32, i32, P, P, P,
+        L.oracle_follow.argtypes = [i32, P, P, P, P, P, P, i32, i32, i32, P, P, P,
                                     ctypes.POINTER(FitParams), ctypes.POINTER(FollowParams),
                                     P, P, P, P, P, P, P, P]
         L.oracle_follow.restype = None
@@ -291,7 +291,8 @@ def follow(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, gate, ma
     out = dict(rows=np.empty((T, n_rows), np.int32), x=np.empty(T), par=np.empty((T, 5)),
                cov=np.empty((T, 15)), chi2=np.empty(T), ndf=np.empty(T, np.int32),
                status=np.empty(T, np.int32), margin=np.empty(T))
-    lib().oracle_follow(T, _p(offsets), _p(hits), _p(frm), _p(sec), _p(fr), _p(off), n_sectors, n_rows,
+    n_frames = (off.size - 1) // (n_sectors * n_rows)
+    lib().oracle_follow(T, _p(offsets), _p(hits), _p(frm), _p(sec), _p(fr), _p(off), n_frames, n_sectors, n_rows,
                         _p(y), _p(z), _p(rx), ctypes.byref(prm), ctypes.byref(fp), _p(out["rows"]),
                         _p(out["x"]), _p(out["par"]), _p(out["cov"]), _p(out["chi2"]),
                         _p(out["ndf"]), _p(out["status"]), _p(out["margin"]))

@@ -544,7 +544,10 @@ void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
 /* ------------------------------------------------------------------------ */
 /* Track following.  The paper does not describe it; this is a textbook      */
 /* prolongation with cluster pickup, per seed:                               */
-/*  0  fit the seed as above (state at its innermost hit)                    */
+/*  0  fit the seed as above (state at its innermost hit), each hit at the   */
+/*     row of its (frame, sector) holding it, so seeds may skip rows; a seed */
+/*     with a hit outside that (frame, sector) or rows not rising strictly  */
+/*     is refused (status 1)                                                 */
 /*  A  inwards, row by row below the innermost hit: predict to the row; stop */
 /*     if the step fails or |y| exceeds the row half-width x tan 10 deg (the */
 /*     track leaves the sector); among all clusters of that (frame, sector,  */
@@ -599,8 +602,11 @@ static int follow_row(double *p, double *C, double *xcur, double xr, int32_t c0,
     return 1;
 }
 
+static int32_t row_of(const int32_t *row_offsets, int32_t base, int32_t n_rows, int32_t id);
+
 static void follow_one(int32_t i, int32_t n, const int32_t *hit, int32_t frame, int32_t sec,
-                       int32_t row0, const int32_t *row_offsets, int32_t n_sectors, int32_t n_rows,
+                       int32_t row0, const int32_t *row_offsets, int32_t n_frames, int32_t n_sectors,
+                       int32_t n_rows,
                        const double *y, const double *z, const double *row_x,
                        const oracle_fit_params *prm, const oracle_follow_params *fp,
                        int32_t *rows, double *xo, double *po, double *co, double *chi2o,
@@ -612,7 +618,23 @@ static void follow_one(int32_t i, int32_t n, const int32_t *hit, int32_t frame, 
     *margin = INFINITY;
     *ndfo = 2 * n - 5;
     for (int32_t r = 0; r < n_rows; ++r) rows[r] = -1;
-    if (n < 3 || row0 < 0 || row0 + n > n_rows) {
+    /* 0: the seed fit, each hit at the row of the (frame, sector) holding it
+     * (seeds from links across a missing row skip rows); a seed with a hit
+     * outside its (frame, sector) or rows not rising strictly is refused */
+    int refused = n < 3 || n > 512 || sec < 0 || sec >= n_sectors || frame < 0 || frame >= n_frames;
+    int32_t prev = -1, base = (frame * n_sectors + sec) * n_rows;
+    for (int32_t k = 0; k < n && !refused; ++k) {
+        int32_t r = row_of(row_offsets, base, n_rows, hit[k]);
+        if (r < 0 || r <= prev) { refused = 1; break; }
+        prev = r;
+        rows[r] = hit[k];
+        xs[k] = row_x[r];
+        ys[k] = y[hit[k]];
+        zs[k] = z[hit[k]];
+    }
+    (void)row0;
+    if (refused) {
+        for (int32_t r = 0; r < n_rows; ++r) rows[r] = -1;
         *xo = 0.0;
         *chi2o = 0.0;
         for (int q = 0; q < 5; ++q) po[q] = 0.0;
@@ -620,13 +642,7 @@ static void follow_one(int32_t i, int32_t n, const int32_t *hit, int32_t frame, 
         *sto = 1;
         return;
     }
-    /* 0: the seed fit */
-    for (int32_t k = 0; k < n; ++k) {
-        rows[row0 + k] = hit[k];
-        xs[k] = row_x[row0 + k];
-        ys[k] = y[hit[k]];
-        zs[k] = z[hit[k]];
-    }
+    int32_t lo = row_of(row_offsets, base, n_rows, hit[0]), hi = prev;
     *sto = fit_points(n, xs, ys, zs, prm, xo, p, C, chi2o);
     if (*sto) {
         for (int q = 0; q < 5; ++q) po[q] = p[q];
@@ -635,12 +651,11 @@ static void follow_one(int32_t i, int32_t n, const int32_t *hit, int32_t frame, 
     }
     const int32_t *seg_off = row_offsets + ((size_t)frame * n_sectors + sec) * n_rows;
     /* A: inwards */
-    int32_t lo = row0, hi = row0 + n - 1;
     double plo[5];
     for (int q = 0; q < 5; ++q) plo[q] = p[q];
-    double xcur = row_x[row0];
+    double xcur = row_x[lo];
     int32_t miss = 0;
-    for (int32_t r = row0 - 1; r >= 0; --r) {
+    for (int32_t r = lo - 1; r >= 0; --r) {
         int32_t pick;
         if (!follow_row(p, C, &xcur, row_x[r], seg_off[r], seg_off[r + 1], y, z, prm, fp->gate,
                         tan10, &pick, margin))
@@ -709,7 +724,7 @@ static void follow_one(int32_t i, int32_t n, const int32_t *hit, int32_t frame, 
 
 void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                    const int32_t *frame, const int32_t *sector, const int32_t *first_row,
-                   const int32_t *row_offsets, int32_t n_sectors, int32_t n_rows,
+                   const int32_t *row_offsets, int32_t n_frames, int32_t n_sectors, int32_t n_rows,
                    const double *y, const double *z, const double *row_x,
                    const oracle_fit_params *prm, const oracle_follow_params *fp,
                    int32_t *rows, double *x_out, double *par, double *cov, double *chi2,
@@ -718,7 +733,7 @@ void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits
     #pragma omp parallel for schedule(dynamic, 16)
     for (int32_t i = 0; i < n_tracks; ++i) {
         follow_one(i, offsets[i + 1] - offsets[i], hits + offsets[i], frame[i], sector[i],
-                   first_row[i], row_offsets, n_sectors, n_rows, y, z, row_x, prm, fp,
+                   first_row[i], row_offsets, n_frames, n_sectors, n_rows, y, z, row_x, prm, fp,
                    rows + (size_t)i * n_rows, &x_out[i], &par[(size_t)i * 5],
                    &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i], &margin[i]);
     }

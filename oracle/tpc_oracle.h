@@ -46,7 +46,7 @@ void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
 
 void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                    const int32_t *frame, const int32_t *sector, const int32_t *first_row,
-                   const int32_t *row_offsets, int32_t n_sectors, int32_t n_rows,
+                   const int32_t *row_offsets, int32_t n_frames, int32_t n_sectors, int32_t n_rows,
                    const double *y, const double *z, const double *row_x,
                    const oracle_fit_params *prm, const oracle_follow_params *fp,
                    int32_t *rows, double *x_out, double *par, double *cov, double *chi2,

@@ -194,3 +194,56 @@ def test_kept_tracks_are_distinct_and_hits_ascend():
     for i in np.nonzero(ok)[0]:
         c = out["rows"][i][out["rows"][i] >= 0]
         assert np.unique(seg[c] // fr.n_rows).size == 1, "a track stays in its (frame, sector)"
+
+
+def test_following_seeds_that_skip_rows():
+    # seeds from links across a missing row: every seed hit stays at its own
+    # row, and following reaches the completeness of adjacent-row seeds from
+    # fewer seeds (the inefficiency no longer splits them)
+    from tpcsynth import make_config
+    fr = make_config(1, scale=0.1, hit_eff=0.9)
+    t = fr.track_of
+    sec = np.repeat(np.arange(fr.row_offsets.size - 1), np.diff(fr.row_offsets)) // fr.n_rows
+    row = np.repeat(np.arange(fr.row_offsets.size - 1), np.diff(fr.row_offsets)) % fr.n_rows
+    piece = t.astype(np.int64) * 4096 + sec
+    pk, pn = np.unique(piece[t >= 0], return_counts=True)
+    res = {}
+    for name, nbf in (("adjacent", oracle.neighbours), ("skip", oracle.neighbours_skip)):
+        up, dn = nbf(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+        sd = oracle.ca_seed(fr.row_offsets, up, dn, fr.n_sectors, fr.n_rows, MIN_HITS)
+        fo = oracle.follow(sd, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows,
+                           gate=25.0, max_miss=3, **FIT)
+        assert (fo["status"] == 1).mean() < 0.01          # start failures only
+        for i in np.flatnonzero(fo["status"] != 1):
+            h = sd["hits"][sd["offsets"][i]:sd["offsets"][i + 1]]
+            np.testing.assert_array_equal(fo["rows"][i][row[h]], h)
+        best = {}
+        for r in fo["rows"][fo["status"] == 0]:
+            c = r[r >= 0]
+            c = c[t[c] >= 0]
+            u, n = np.unique(piece[c], return_counts=True)
+            for a, b in zip(u.tolist(), n.tolist()):
+                best[a] = max(best.get(a, 0), b)
+        big = pn >= 20
+        res[name] = (len(sd["offsets"]) - 1,
+                     np.mean([best.get(a, 0) >= 0.8 * b for a, b in zip(pk[big].tolist(), pn[big].tolist())]))
+    assert res["skip"][0] < 0.5 * res["adjacent"][0]
+    assert res["skip"][1] > 0.93 and abs(res["skip"][1] - res["adjacent"][1]) < 0.01
+
+
+def test_following_refuses_malformed_seeds():
+    from tpcsynth import make_config
+    fr = make_config(0)
+    up, dn = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    sd = oracle.ca_seed(fr.row_offsets, up, dn, 1, fr.n_rows, MIN_HITS)
+    o = sd["offsets"]
+    h = sd["hits"][o[0]:o[1]].copy()
+    bad = np.concatenate([h[:2], h[3:4], h[2:3], h[4:]])          # two rows swapped
+    s2 = dict(offsets=np.array([0, len(h), 2 * len(h)], np.int32), hits=np.concatenate([h, bad]).astype(np.int32),
+              frame=np.zeros(2, np.int32), sector=np.zeros(2, np.int32), first_row=np.full(2, sd["first_row"][0], np.int32))
+    fo = oracle.follow(s2, fr.row_offsets, fr.y, fr.z, fr.row_x, 1, fr.n_rows, gate=25.0, max_miss=3, **FIT)
+    assert fo["status"][0] == 0 and fo["status"][1] == 1
+    assert (fo["rows"][1] == -1).all()
+    s3 = dict(s2, frame=np.ones(2, np.int32))
+    assert (oracle.follow(s3, fr.row_offsets, fr.y, fr.z, fr.row_x, 1, fr.n_rows, gate=25.0, max_miss=3,
+                          **FIT)["status"] == 1).all()
