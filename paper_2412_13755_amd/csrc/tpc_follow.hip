@@ -7,10 +7,11 @@
 //                  y cells (about one cluster per cell, counting sort with
 //                  atomics in global memory); non-finite clusters are left out
 //                  (they can never pass the gate)
-//  fl_tracks       thread per seed, double precision throughout: seed fit,
-//                  inward prolongation, outward refit and prolongation,
-//                  final refit; the search in a row scans only the cells
-//                  covering the y extent of the gate ellipse
+//  fl_tracks       thread per seed, double precision throughout: seed fit
+//                  (the seed's hits at the rows that hold them, so seeds may
+//                  skip rows), inward prolongation, outward refit and
+//                  prolongation, final refit; the search in a row scans only
+//                  the cells covering the y extent of the gate ellipse
 //  fl_owner_init   owner key of every cluster := none
 //  fl_claim        thread per refitted track: 64-bit atomicMin of its key
 //                  (n_rows - n_hits, index) on each of its clusters
@@ -346,27 +347,59 @@ __device__ inline void write_track(const FitArgs &F, int i, double xcur, const d
     F.out.status[i] = status;
 }
 
+// Places the seed's hits in the strip, each at the pad row of its (frame,
+// sector) whose id range holds it (seeds from links across a missing row
+// skip rows; first_row is not read): the outermost hit's row by binary
+// search over the row starts ro[0 .. R], each next one by a walk down.
+// False if a hit lies outside the (frame, sector) or the rows do not rise
+// strictly (then the strip may hold some of the hits).
+__device__ inline bool place_seed(const SeedView &sv, const int32_t *ro, int R, const Strip &S, int &lo,
+                                  int &hi) {
+    const int32_t top = sv.hh[sv.n - 1];
+    if (top < ro[0] || top >= ro[R]) return false;
+    int a = 0, b = R - 1;                          // ro[a] <= top < ro[b + 1]
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (ro[mid] <= top) a = mid;
+        else b = mid - 1;
+    }
+    int r = a;
+    hi = r;
+    S.set(r, top);
+    for (int k = sv.n - 2; k >= 0; --k) {
+        const int32_t id = sv.hh[k];
+        int q = r - 1;
+        while (q >= 0 && ro[q] > id) --q;
+        if (q < 0 || id >= ro[q + 1]) return false;
+        r = q;
+        S.set(r, id);
+    }
+    lo = r;
+    return true;
+}
+
 __device__ inline void follow_one(const FlArgs &A, int i, const Strip &S) {
     const FitArgs &F = A.F;
     const SeedView sv = seed_view(F, i);
     const int R = F.n_rows;
-    for (int r = 0; r < R; ++r)
-        S.set(r, (sv.sane && r >= sv.row0 && r < sv.row0 + sv.n) ? sv.hh[r - sv.row0] : -1);
+    for (int r = 0; r < R; ++r) S.set(r, -1);
     double p[5] = {0, 0, 0, 0, 0};
     SymT<double> C = {};
     double chi2 = 0.0, xcur = 0.0;
     int m = sv.n;
-    if (sv.sane) {
-        // a seed list not written by tpc_ca_seed may hold anything
-        if ((uint32_t)A.frame[i] >= (uint32_t)A.n_frames) m = 0;
-        for (int k = 0; k < sv.n; ++k)
-            if ((uint32_t)sv.hh[k] >= (uint32_t)F.n_clusters) S.set(sv.row0 + k, -1), m = 0;
+    int lo = 0, hi = 0;
+    // a seed list not written by tpc_ca_seed may hold anything
+    bool ok = sv.n >= 3 && sv.o0 >= 0 && sv.o0 <= F.cap_hits - sv.n && sv.sec >= 0 && sv.sec < F.n_sectors &&
+              (uint32_t)A.frame[i] < (uint32_t)A.n_frames;
+    if (ok) {
+        const int32_t *ro = A.row_offsets + ((size_t)A.frame[i] * F.n_sectors + sv.sec) * R;
+        ok = place_seed(sv, ro, R, S, lo, hi);
     }
-    if (!sv.sane || m != sv.n) {
+    if (!ok) {
+        for (int r = 0; r < R; ++r) S.set(r, -1);
         write_track(F, i, 0.0, p, C, 0.0, sv.n, TPC_FIT_INIT_FAIL);
         return;
     }
-    int lo = sv.row0, hi = sv.row0 + sv.n - 1;
     int status = fit_rows(A, S, lo, hi, m, p, C, chi2, xcur);
     // the seed fit is the result unless a cluster is taken up
     write_track(F, i, xcur, p, C, chi2, m, status);

@@ -161,3 +161,33 @@ def test_follow_without_seeds(torch_dev):
     torch.cuda.synchronize()
     assert int(seeds.n_seeds.item()) == 0
     assert bool((rows == -7).all())
+
+
+def test_following_seeds_that_skip_rows(torch_dev):
+    """Seeds from links across a missing row (10 % pad-row inefficiency):
+    each seed hit at its own row, then the same following as the oracle."""
+    import torch
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    from tpcsynth import make_config
+    fr = make_config(1, scale=0.2, hit_eff=0.9)
+    print("[follow] skip-link seeds: N=%d" % fr.n_clusters, flush=True)
+    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT), "cuda:0")
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours_skip(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    rows, tr = reco.follow(dfr, seeds, GATE, MAX_MISS)
+    torch.cuda.synchronize()
+    T = int(seeds.n_seeds.item())
+    g = dict(rows=rows[:T].cpu().numpy(), x=tr.x[:T].cpu().numpy(), par=tr.par[:T].cpu().numpy(),
+             cov=tr.cov[:T].cpu().numpy(), chi2=tr.chi2[:T].cpu().numpy(), ndf=tr.ndf[:T].cpu().numpy(),
+             status=tr.status[:T].cpu().numpy())
+    su, sdn = oracle.neighbours_skip(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    sd = oracle.ca_seed(fr.row_offsets, su, sdn, fr.n_sectors, fr.n_rows, MIN_HITS)
+    parity.assert_seeds_equal(seeds.to_numpy(), sd)
+    r = oracle.follow(sd, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows, gate=GATE,
+                      max_miss=MAX_MISS, **FIT)
+    row = np.repeat(np.arange(fr.row_offsets.size - 1), np.diff(fr.row_offsets)) % fr.n_rows
+    gapped = sum(int((np.diff(row[h]) > 1).any()) for h in parity.seed_lists(sd))
+    assert gapped > 1000
+    st = compare_follow(g, r)
+    print("[follow] skip-link seeds: gapped %d, %s" % (gapped, st), flush=True)
