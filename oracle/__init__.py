@@ -45,7 +45,29 @@ class FitParams(ctypes.Structure):
 
 
 class Material(ctypes.Structure):
-    _fields_ = [("x0", ctypes.c_double), ("mass", ctypes.c_double), ("chi2_cut", ctypes.c_double)]
+    _fields_ = [("x0", ctypes.c_double), ("mass", ctypes.c_double), ("chi2_cut", ctypes.c_double),
+                ("rho", ctypes.c_double), ("z_over_a", ctypes.c_double), ("mean_exc", ctypes.c_double)]
+
+
+def _material(x0, mass, chi2_cut, gas):
+    rho, zoa, exc = (0.0, 0.5, 1e-7) if gas is None else gas
+    return Material(float(x0), float(mass), float(chi2_cut), float(rho), float(zoa), float(exc))
+
+
+def eloss(p, dx, mass, gas, direction=1.0):
+    """Energy-loss map of the fit for one segment: (status, w', dw'/dt,
+    dw'/dw, straggling variance of w)."""
+    st = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(4)
+    r = lib().oracle_eloss(_p(st), float(dx), ctypes.byref(_material(np.inf, mass, np.inf, gas)),
+                           float(direction), _p(out))
+    return (int(r),) + tuple(float(v) for v in out)
+
+
+def bethe(beta_gamma, mass, z_over_a, mean_exc):
+    """Mean energy loss per density, GeV cm^2/g (Bethe, unit charge, no
+    density effect), as the fit with energy loss takes it."""
+    return lib().oracle_bethe(float(beta_gamma), float(mass), float(z_over_a), float(mean_exc))
 
 
 class FollowParams(ctypes.Structure):
@@ -89,6 +111,10 @@ def lib():
         L.oracle_fit_material.argtypes = [i32, P, P, P, P, P, P, ctypes.POINTER(FitParams),
                                            ctypes.POINTER(Material), P, P, P, P, P, P, P, P]
         L.oracle_fit_material.restype = None
+        L.oracle_bethe.argtypes = [ctypes.c_double] * 4
+        L.oracle_bethe.restype = ctypes.c_double
+        L.oracle_eloss.argtypes = [P, ctypes.c_double, ctypes.POINTER(Material), ctypes.c_double, P]
+        L.oracle_eloss.restype = i32
         L.oracle_neighbours_skip.argtypes = [i32, i32, P, P, P, f32, f32, f32, f32, P, P]
         L.oracle_neighbours_skip.restype = None
         L.oracle_fit_rows.argtypes = [i32, P, P, P, P, P, i32, i32, i32, P, P, P, P,
@@ -201,9 +227,10 @@ def fit(seeds: dict, y, z, row_x, n_rows, *, bz, sigma_y, sigma_z, max_sin, var_
 
 
 def fit_material(seeds: dict, y, z, row_x, *, x0, mass, chi2_cut, bz, sigma_y, sigma_z, max_sin,
-                 var_sin0, var_tgl0, var_qpt0):
-    """Fit with multiple scattering (radiation length x0 cm, mass GeV) and
-    rejection of hits above chi2_cut.  Returns the fit's dict plus
+                 var_sin0, var_tgl0, var_qpt0, gas=None):
+    """Fit with multiple scattering (radiation length x0 cm, mass GeV),
+    energy loss in a gas (rho g/cm^3, Z/A, mean excitation GeV; None: none)
+    and rejection of hits above chi2_cut.  Returns the fit's dict plus
     rejected (uint8 per seed hit) and margin per track."""
     offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
     hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
@@ -213,7 +240,7 @@ def fit_material(seeds: dict, y, z, row_x, *, x0, mass, chi2_cut, bz, sigma_y, s
     rx = np.ascontiguousarray(row_x, dtype=np.float64)
     T = len(offsets) - 1
     prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
-    mat = Material(float(x0), float(mass), float(chi2_cut))
+    mat = _material(x0, mass, chi2_cut, gas)
     out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
                ndf=np.empty(T, np.int32), status=np.empty(T, np.int32),
                rejected=np.zeros(max(hits.size, 1), np.uint8), margin=np.empty(T))
@@ -226,7 +253,7 @@ def fit_material(seeds: dict, y, z, row_x, *, x0, mass, chi2_cut, bz, sigma_y, s
 
 
 def fit_rows(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, err, x0, mass, chi2_cut,
-             bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0, smooth=False):
+             bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0, gas=None, smooth=False):
     """Fit of seeds whose hits may skip pad rows (each hit's row is looked up
     in ``row_offsets``), with per-cluster errors ``err`` ([N, 2] float32
     sigma_y, sigma_z; None: the constants) and material as in fit_material
@@ -249,7 +276,7 @@ def fit_rows(seeds: dict, row_offsets, y, z, row_x, n_sectors, n_rows, *, err, x
     T = len(offsets) - 1
     n_frames = (off.size - 1) // (n_sectors * n_rows)
     prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
-    mat = Material(float(x0), float(mass), float(chi2_cut))
+    mat = _material(x0, mass, chi2_cut, gas)
     out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
                ndf=np.empty(T, np.int32), status=np.empty(T, np.int32),
                rejected=np.zeros(max(hits.size, 1), np.uint8), margin=np.empty(T))

@@ -779,7 +779,9 @@ void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits
 /* lambda, lambda by theta):                                                 */
 /*   C_ss += th2 (1-s^2)(1+t^2), C_tt += th2 (1+t^2)^2,                     */
 /*   C_tw += th2 t w (1+t^2),    C_ww += th2 t^2 w^2     (th2 = theta0^2)    */
-/* (no noise for X0 infinite or w = 0).  After the step, a hit whose         */
+/* (no noise for X0 infinite or w = 0).  Then, with rho > 0, the energy     */
+/* loss of the segment (add_energy_loss; a particle that would stop ends    */
+/* the fit with status 2), then the helix step.  After it, a hit whose       */
 /* predicted-residual chi2 exceeds chi2_cut is not used (flagged; the state  */
 /* goes on from the prediction).  chi2 sums the used hits, ndf = 2 used - 5  */
 /* with the outermost (start) hit counted as used.  margin = smallest        */
@@ -803,6 +805,94 @@ static void add_scattering(const double *p, double dx, const oracle_material *m,
     C[4 * 5 + 4] += th2 * t * t * w * w;
 }
 
+/* Energy loss in the gas (material with rho > 0).  A segment of path ds
+ * (as for the scattering) starting from state p, with momentum
+ * P = sqrt(1+t^2)/|w|, energy E = sqrt(P^2 + m^2), beta = P/E and
+ * gamma = E/m, loses on average ds rho <dE/dx> (Bethe, unit charge, no
+ * density-effect term):
+ *   <dE/dx> = K Z/A / beta^2 (ln(2 m_e beta^2 gamma^2 W / I^2) / 2 - beta^2),
+ *   W = 2 m_e beta^2 gamma^2 / (1 + 2 gamma m_e/m + (m_e/m)^2)  (largest transfer),
+ * K = 0.307075 MeV cm^2/mol, m_e = 0.51099895 MeV, I the mean excitation
+ * energy; and the loss fluctuates with variance (Bohr, relativistic)
+ *   var(E) = K Z/A rho ds m_e (1 - beta^2/2) / (1 - beta^2).
+ * The particle moves outwards, so a step inwards gives back the mean loss:
+ * E' = E + dE (dir = +1; the smoother's outward reference takes it away,
+ * dir = -1), P' = sqrt(E'^2 - m^2), w' = w P / P' (t and s unchanged).  For
+ * the covariance the loss is held fixed: w' depends on w and t through P,
+ *   dw'/dw = (P/P')^3 E'/E,  dw'/dt = w' t/(1+t^2) (1 - E' P^2 / (E P'^2)),
+ * and the straggling is noise on w at the start, var(E) (w E / P^2)^2.
+ * A segment whose mean loss would change the momentum by more than 1 % is
+ * taken without energy loss: the state's momentum is then far from any
+ * track's that crosses the gas (or the particle is about to stop), and the
+ * map, which contracts the q/pT variance strongly at low momentum, would
+ * lock the fit onto it.
+ * Returns 1 if the energy reaches the mass (the particle stops), else 0;
+ * without energy loss (rho = 0, or w = 0) w' = w, J the identity, no noise. */
+static double bethe(double P, double m, double zoa, double I)
+{
+    const double K = 0.307075e-3, me = 0.51099895e-3;     /* GeV cm^2/mol, GeV */
+    double E = sqrt(P * P + m * m), b2 = P * P / (E * E), g = E / m, bg2 = P * P / (m * m);
+    double W = 2.0 * me * bg2 / (1.0 + 2.0 * g * me / m + (me / m) * (me / m));
+    return K * zoa / b2 * (0.5 * log(2.0 * me * bg2 * W / (I * I)) - b2);
+}
+
+double oracle_bethe(double beta_gamma, double mass, double z_over_a, double mean_exc)
+{
+    return bethe(beta_gamma * mass, mass, z_over_a, mean_exc);
+}
+
+static int eloss_map(const double *p, double dx, const oracle_material *m, double dir, double *wo,
+                     double *J43, double *J44, double *varw)
+{
+    double s = p[2], t = p[3], w = p[4];
+    *wo = w;
+    *J43 = 0.0;
+    *J44 = 1.0;
+    *varw = 0.0;
+    if (!(m->rho > 0.0) || w == 0.0) return 0;
+    const double K = 0.307075e-3, me = 0.51099895e-3;
+    double t2 = 1.0 + t * t;
+    double ds = fabs(dx) * sqrt(t2) / sqrt(1.0 - s * s);
+    double P = sqrt(t2) / fabs(w), E = sqrt(P * P + m->mass * m->mass), b2 = P * P / (E * E);
+    double dE = ds * m->rho * bethe(P, m->mass, m->z_over_a, m->mean_exc);
+    double varE = K * m->z_over_a * m->rho * ds * me * (1.0 - 0.5 * b2) / (1.0 - b2);
+    double E1 = E + dir * dE;
+    if (!(E1 > m->mass)) return 1;
+    double P1 = sqrt(E1 * E1 - m->mass * m->mass);
+    if (fabs(P1 - P) > 0.01 * P) return 0;
+    *wo = w * P / P1;
+    *J44 = (P / P1) * (P / P1) * (P / P1) * E1 / E;
+    *J43 = *wo * t / t2 * (1.0 - E1 * P * P / (E * P1 * P1));
+    double dw = w * E / (P * P);
+    *varw = varE * dw * dw;
+    return 0;
+}
+
+int32_t oracle_eloss(const double *p, double dx, const oracle_material *m, double dir, double *out)
+{
+    return eloss_map(p, dx, m, dir, &out[0], &out[1], &out[2], &out[3]);
+}
+
+/* The energy loss of the segment dx in a fit step inwards: straggling
+ * noise added to C, then p, C moved by the map (C <- J C J^T).  Returns 1
+ * if the particle would stop. */
+static int add_energy_loss(double *p, double *C, double dx, const oracle_material *m)
+{
+    double w1, j43, j44, vw;
+    if (eloss_map(p, dx, m, 1.0, &w1, &j43, &j44, &vw)) return 1;
+    double J[25] = {0}, Jt[25], T[25];
+    for (int i = 0; i < 5; ++i) J[i * 5 + i] = 1.0;
+    J[4 * 5 + 3] = j43;
+    J[4 * 5 + 4] = j44;
+    C[24] += vw;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Jt[i * 5 + j] = J[j * 5 + i];
+    mat5_mul(J, C, T);
+    mat5_mul(T, Jt, C);
+    p[4] = w1;
+    return 0;
+}
+
 /* Fit with material of n points at planes xs (ascending), point k with the
  * measurement variances vys[k], vzs[k] (the outermost point's are also the
  * start covariance of y and z). */
@@ -820,6 +910,7 @@ static void fit_material_points(int32_t n, const double *xs, const double *ys, c
     for (int k = n - 2; k >= 0 && !st; --k) {
         double dx = xs[k] - xs[k + 1];
         add_scattering(p, dx, mat, C);
+        if (add_energy_loss(p, C, dx, mat)) { st = 2; break; }
         if (predict(p, C, dx, prm)) { st = 2; break; }
         xcur = xs[k];
         double chi = resid_chi2(p, C, ys[k], zs[k], vys[k], vzs[k]);
@@ -944,13 +1035,16 @@ static int inv5(const double *A, double *X)
     return 0;
 }
 
-/* Smoother about a reference trajectory.  The reference is the fit's final
- * state carried by the exact helix step to every plane (r_k; a step that
- * fails ends the smoothing with status 2).  About it the problem is linear
- * in the deviation d = state - r: the step from plane k to plane k-1 maps d
- * by its Jacobian F_k (taken on the reference), the scattering of that
- * segment adds Q_k (from r_k) before the step, and a hit measures
- * (y, z) of r + d.  A Kalman filter of d runs inwards from plane n-1 (d = 0,
+/* Smoother about a reference trajectory.  The reference starts at the
+ * outermost plane from the fit's final state carried there -- by one exact
+ * helix step, or, with energy loss, plane by plane with the helix step and
+ * the loss of each segment taken away -- and runs inwards by the fit's own
+ * step (energy loss, then helix step): r_{k-1} = f(r_k) (a step or a loss
+ * that fails ends the smoothing with status 2).  About it the problem is
+ * linear in the deviation d = state - r: the step from plane k to plane k-1
+ * maps d by its Jacobian F_k (helix step times energy loss, taken on the
+ * reference), the scattering and the straggling of that segment add Q_k
+ * (from r_k) before the step, and a hit measures (y, z) of r + d.  A Kalman filter of d runs inwards from plane n-1 (d = 0,
  * variances (100 sigma)^2 on y and z and the start variances on the other
  * three), taking the hits the fit used (none it rejected); then the
  * Rauch-Tung-Striebel pass outwards:
@@ -971,18 +1065,34 @@ static int32_t smooth_reference(int32_t n, const double *xs, const double *ys, c
     double *R = w, *FJ = w + (size_t)n * 5, *QS = w + (size_t)n * 30, *D = w + (size_t)n * 55,
            *CD = w + (size_t)n * 60;
     int32_t st = 0;
-    memcpy(R, pfin, sizeof(double) * 5);
-    for (int k = 1; k < n && !st; ++k) {       /* the reference, outwards */
-        double F[25];
-        if (oracle_propagate(pfin, xs[k] - xs[0], prm->bz, prm->max_sin, R + (size_t)k * 5, F)) st = 2;
+    double *Rn = R + (size_t)(n - 1) * 5, F[25];
+    if (mat->rho > 0.0) {                      /* the outermost reference state */
+        double a[5], j43, j44, vw;
+        memcpy(a, pfin, sizeof a);
+        for (int k = 1; k < n && !st; ++k) {
+            double dx = xs[k] - xs[k - 1];
+            if (oracle_propagate(a, dx, prm->bz, prm->max_sin, Rn, F) ||
+                eloss_map(Rn, dx, mat, -1.0, &Rn[4], &j43, &j44, &vw)) st = 2;
+            memcpy(a, Rn, sizeof a);
+        }
+    } else if (oracle_propagate(pfin, xs[n - 1] - xs[0], prm->bz, prm->max_sin, Rn, F)) {
+        st = 2;
     }
-    for (int k = 1; k < n && !st; ++k) {       /* steps inwards along it */
-        double pp[5];
-        double dx = xs[k - 1] - xs[k];
-        if (oracle_propagate(R + (size_t)k * 5, dx, prm->bz, prm->max_sin, pp, FJ + (size_t)k * 25)) st = 2;
+    for (int k = n - 1; k >= 1 && !st; --k) {  /* steps inwards along it */
+        double dx = xs[k - 1] - xs[k], w1, j43, j44, vw, re[5], J[25] = {0};
+        const double *r = R + (size_t)k * 5;
         double *Q = QS + (size_t)k * 25;
         for (int i = 0; i < 25; ++i) Q[i] = 0.0;
-        add_scattering(R + (size_t)k * 5, dx, mat, Q);
+        add_scattering(r, dx, mat, Q);
+        if (eloss_map(r, dx, mat, 1.0, &w1, &j43, &j44, &vw)) { st = 2; break; }
+        Q[24] += vw;
+        memcpy(re, r, sizeof re);
+        re[4] = w1;
+        for (int i = 0; i < 5; ++i) J[i * 5 + i] = 1.0;
+        J[4 * 5 + 3] = j43;
+        J[4 * 5 + 4] = j44;
+        if (oracle_propagate(re, dx, prm->bz, prm->max_sin, R + (size_t)(k - 1) * 5, F)) { st = 2; break; }
+        mat5_mul(F, J, FJ + (size_t)k * 25);
     }
     /* inward filter of the deviation */
     double d[5] = {0, 0, 0, 0, 0}, C[25], chi2 = 0.0;

@@ -20,7 +20,20 @@ typedef struct oracle_material {
     double x0;          /* radiation length of the gas, cm (infinite: no scattering) */
     double mass;        /* mass hypothesis, GeV */
     double chi2_cut;    /* a hit whose predicted-residual chi2 exceeds this is not used */
+    double rho;         /* density of the gas, g/cm^3 (0: no energy loss) */
+    double z_over_a;    /* its Z/A, mol/g */
+    double mean_exc;    /* its mean excitation energy I, GeV */
 } oracle_material;
+
+/* Mean energy loss <dE/dx> per density (GeV cm^2/g) of a unit-charge
+ * particle of the given beta*gamma and mass (Bethe, no density effect). */
+double oracle_bethe(double beta_gamma, double mass, double z_over_a, double mean_exc);
+
+/* The energy-loss map of a segment of plane distance dx from state p
+ * (dir +1: a step inwards, the loss given back; -1: outwards):
+ * out = {w', dw'/dt, dw'/dw, straggling variance of w}.  Returns 1 if the
+ * particle stops, else 0. */
+int32_t oracle_eloss(const double *p, double dx, const oracle_material *m, double dir, double *out);
 
 void oracle_set_threads(int n);
 int oracle_max_threads(void);

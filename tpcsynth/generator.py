@@ -491,10 +491,30 @@ def highland_theta0(p, beta, x_over_x0):
     return HIGHLAND / (beta * p) * np.sqrt(x_over_x0) * (1.0 + 0.038 * np.log(x_over_x0))
 
 
+PROTON_MASS = 0.93827             # GeV
+ELECTRON_MASS = 0.51099895e-3     # GeV
+BETHE_K = 0.307075e-3             # GeV cm^2 / mol
+# (density g/cm^3, Z/A mol/g, mean excitation energy GeV)
+ARGON_GAS = (1.662e-3, 0.45059, 188.0e-9)
+
+
+def mean_dedx(p, mass, rho, z_over_a, mean_exc):
+    """Mean energy loss per cm, GeV/cm, of unit-charge particles of momentum p
+    (GeV/c) in a material (Bethe formula, no density effect)."""
+    e = np.hypot(p, mass)
+    beta2 = (p / e) ** 2
+    bg2 = (p / mass) ** 2
+    ratio = ELECTRON_MASS / mass
+    wmax = 2.0 * ELECTRON_MASS * bg2 / (1.0 + 2.0 * (e / mass) * ratio + ratio * ratio)
+    arg = 2.0 * ELECTRON_MASS * bg2 * wmax / (mean_exc * mean_exc)
+    return BETHE_K * z_over_a * rho / beta2 * (0.5 * np.log(arg) - beta2)
+
+
 def make_scattering_frame(*, n_tracks: int = 200, seed: int = 0, x0_cm: float = 300.0,
                           mass: float = PION_MASS, inv_pt=(0.5, 3.0), phi_range=(-0.06, 0.06),
                           tgl_range=(-0.8, 0.8), n_rows: int = 152, bz: float = 0.5,
-                          sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True) -> Frames:
+                          sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True,
+                          gas=None) -> Frames:
     """One sector (alpha = 0) of tracks stepped plane by plane with multiple scattering.
 
     Each track starts at the origin; from one pad-row plane to the next its
@@ -504,8 +524,13 @@ def make_scattering_frame(*, n_tracks: int = 200, seed: int = 0, x0_cm: float = 
     width theta0 (Highland, with the 3-D path of the segment just traversed
     and the momentum and velocity for the given mass): one in the bending
     plane (phi changes by theta1 / cos(lambda)) and one in lambda; the total
-    momentum is kept, so pT and the curvature follow lambda.  A track stops
-    when it misses the next plane or leaves the row width.  Truth at every
+    momentum is kept, so pT and the curvature follow lambda -- unless a gas
+    (density, Z/A, mean excitation energy) is given: then the particle also
+    loses energy over the segment, the mean loss integrated in 8 sub-steps of
+    the path with the Bethe formula (mean_dedx) and a Gaussian fluctuation of
+    Bohr's width (relativistic), and stops when it has no kinetic energy
+    left.  A track stops when it misses the next plane or leaves the row
+    width.  Truth at every
     cluster: y, z and the direction (s, t, w) of the segment leaving it.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -563,6 +588,19 @@ def make_scattering_frame(*, n_tracks: int = 200, seed: int = 0, x0_cm: float = 
             k2 = rng.normal(0.0, 1.0, n) * th0s
             phin = phin + np.where(alive, k1 / np.cos(lam), 0.0)
             lamn = lam + np.where(alive, k2, 0.0)
+            if gas is not None:
+                rho, zoa, exc = gas
+                e = np.hypot(p, mass)
+                e0 = e.copy()
+                pc = p.copy()
+                for _ in range(8):
+                    e = e - mean_dedx(pc, mass, rho, zoa, exc) * path / 8.0
+                    pc = np.sqrt(np.maximum(e * e - mass * mass, 1e-30))
+                b2 = (p / e0) ** 2
+                var_e = BETHE_K * zoa * rho * path * ELECTRON_MASS * (1.0 - 0.5 * b2) / (1.0 - b2)
+                e = e + rng.normal(0.0, 1.0, n) * np.sqrt(var_e)
+                alive &= e > mass * 1.001
+                p = np.where(alive, np.sqrt(np.maximum(e * e - mass * mass, 1e-30)), p)
         idx = np.nonzero(alive)[0]
         recs.append((idx, np.full(idx.size, k), Yn[idx], Zn[idx], np.sin(phin[idx]), np.tan(lamn[idx]),
                      q[idx] / (p[idx] * np.cos(lamn[idx]))))
