@@ -506,34 +506,36 @@ MAT_X0, MAT_CUT = 2870.0, 30.0
 
 
 def leg_material(args):
-    """tpc_kalman_fit_material on the headline seeds, HIP events on the launch stream."""
+    """tpc_kalman_fit_material (scattering, energy loss in the TPC gas, outlier
+    cut) on the headline seeds, then the fit over rows with the smoother; HIP
+    events on the launch stream."""
     import torch
-    from tpcsynth import make_config, PION_MASS
+    from tpcsynth import make_config, PION_MASS, TPC_GAS
     fr = make_config(1)
     reco = make_reco(fr)
     dfr = reco.upload(fr)
     ws = reco.workspace(dfr)
     up, dn = reco.neighbours(dfr, ws=ws)
     seeds = reco.seed(dfr, up, dn, ws=ws)
-    tr, rej = reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, ws=ws)
+    tr, rej = reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, ws=ws, gas=TPC_GAS)
     torch.cuda.synchronize()
     T, H = int(seeds.n_seeds.item()), int(seeds.n_hits.item())
     stream = torch.cuda.current_stream()
     steps = max(5, args.steps)
     for _ in range(2):
-        reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, tr, rej, ws)
+        reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, tr, rej, ws, gas=TPC_GAS)
     evs = []
     for _ in range(steps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record(stream)
-        reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, tr, rej, ws)
+        reco.fit_material(dfr, seeds, MAT_X0, PION_MASS, MAT_CUT, tr, rej, ws, gas=TPC_GAS)
         e[1].record(stream)
         evs.append(e)
     torch.cuda.synchronize()
     ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    flops = (FLOP_FIT_PER_HIT + 40) * H            # the fit's step and update, plus the noise term
+    flops = (FLOP_FIT_PER_HIT + 80) * H            # the fit's step and update, plus scattering and energy loss
     # the fit over rows followed by the smoother, same seeds and material
-    mat = (MAT_X0, PION_MASS, MAT_CUT)
+    mat = (MAT_X0, PION_MASS, MAT_CUT) + TPC_GAS
     out = reco.smooth(dfr, seeds, material=mat, ws=ws)
     torch.cuda.synchronize()
     evs = []
@@ -546,6 +548,7 @@ def leg_material(args):
     torch.cuda.synchronize()
     ms_s = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     return {"workload": fr.meta["name"], "seeds": T, "seed_hits": H, "x0_cm": MAT_X0, "chi2_cut": MAT_CUT,
+            "gas": {"rho": TPC_GAS[0], "z_over_a": TPC_GAS[1], "mean_exc_gev": TPC_GAS[2]},
             "rejected_hits": int(rej[:H].sum()), "ms": round(ms, 5),
             "tracks_per_s": round(T / ms * 1e3, 1),
             "fit_and_smoother_ms": round(ms_s, 5), "smoothed_hits_per_s": round(H / ms_s * 1e3, 1),

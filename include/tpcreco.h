@@ -208,18 +208,33 @@ tpc_status tpc_kalman_fit(const tpc_context *ctx, const tpc_frames *frames,
  * (1 + 0.038 ln(ds/x0)) (Highland), th2 = theta0^2:
  *   C_ss += th2 (1 - s^2)(1 + t^2), C_tt += th2 (1 + t^2)^2,
  *   C_tw += th2 t w (1 + t^2), C_ww += th2 t^2 w^2
- * (none for x0 infinite or w = 0).  After the helix step, a hit whose
+ * (none for x0 infinite or w = 0).  With rho > 0 the segment's energy loss
+ * follows: the particle moves outwards, so the step inwards gives back the
+ * mean loss ds rho <dE/dx> at fixed direction (Bethe formula, unit charge,
+ * no density term: <dE/dx> = K Z/A / beta^2 (ln(2 m_e beta^2 gamma^2 W /
+ * I^2)/2 - beta^2), W the largest energy transfer, K = 0.307075 MeV cm^2/mol),
+ * E' = E + loss, P' = sqrt(E'^2 - mass^2), w' = w P/P'; the straggling
+ * (Bohr, relativistic: var E = K Z/A rho ds m_e (1 - beta^2/2)/(1 - beta^2))
+ * enters C_ww as var E (w E/P^2)^2, and C <- J C J^T with J the map's
+ * Jacobian in (t, w) at fixed loss.  A segment whose loss would change P by
+ * more than 1 % is taken without it; a particle that would stop ends the
+ * fit with TPC_FIT_SIN_FAIL.  After the helix step, a hit whose
  * predicted-residual chi2 exceeds chi2_cut is not used: the filter goes on
  * from the prediction and rejected[seed hit] = 1 (else 0).  chi2 sums the
  * used hits; ndf = 2 (used hits + 1) - 5, the outermost (start) hit
  * counted.  Double precision throughout.  mat: host pointer; x0 > 0 (cm,
  * infinity = no scattering), mass >= 0 (GeV), chi2_cut > 0 (infinity = keep
- * all).  rejected: optional device uint8 [cap_hits].  ws: TPC_STAGE_FIT
- * workspace. */
+ * all), rho >= 0 (g/cm^3, 0 = no energy loss; with rho > 0 also mass > 0,
+ * z_over_a > 0 (mol/g) and mean_exc > 0 (GeV), all finite, else
+ * TPC_ERR_ARG).  rejected: optional device uint8 [cap_hits].  ws:
+ * TPC_STAGE_FIT workspace. */
 typedef struct tpc_material {
     float x0;
     float mass;
     float chi2_cut;
+    float rho;
+    float z_over_a;
+    float mean_exc;
 } tpc_material;
 tpc_status tpc_kalman_fit_material(const tpc_context *ctx, const tpc_frames *frames,
                                    const tpc_seeds *seeds, const tpc_material *mat,

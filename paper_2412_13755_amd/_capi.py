@@ -65,7 +65,8 @@ class Tune(ctypes.Structure):
 
 
 class Material(ctypes.Structure):
-    _fields_ = [("x0", f32), ("mass", f32), ("chi2_cut", f32)]
+    _fields_ = [("x0", f32), ("mass", f32), ("chi2_cut", f32), ("rho", f32), ("z_over_a", f32),
+                ("mean_exc", f32)]
 
 
 class FollowParams(ctypes.Structure):

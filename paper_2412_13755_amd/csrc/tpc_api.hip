@@ -114,6 +114,10 @@ tpc_status check_material(const tpc_material *mat) {
     if (!(mat->x0 > 0.f)) return fail(TPC_ERR_ARG, "x0 must be > 0");
     if (!(mat->mass >= 0.f) || !isfinite(mat->mass)) return fail(TPC_ERR_ARG, "mass must be finite and >= 0");
     if (!(mat->chi2_cut > 0.f)) return fail(TPC_ERR_ARG, "chi2_cut must be > 0");
+    if (!(mat->rho >= 0.f) || !isfinite(mat->rho)) return fail(TPC_ERR_ARG, "rho must be finite and >= 0");
+    if (mat->rho > 0.f && !(mat->mass > 0.f && mat->z_over_a > 0.f && isfinite(mat->z_over_a) &&
+                            mat->mean_exc > 0.f && isfinite(mat->mean_exc)))
+        return fail(TPC_ERR_ARG, "energy loss needs mass, z_over_a and mean_exc finite and > 0");
     return TPC_OK;
 }
 

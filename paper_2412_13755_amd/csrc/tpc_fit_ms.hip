@@ -7,7 +7,10 @@
 //                 each inward step, the scattering of the segment about to
 //                 be crossed enters the covariance (Highland, from the state
 //                 at the plane the step leaves), then the helix step and
-//                 transport; the hit's predicted-residual chi2 decides
+//                 transport (with energy loss, the loss of the segment
+//                 is given back between the two, a map of q/pT whose
+//                 Jacobian and straggling noise enter the covariance);
+//                 the hit's predicted-residual chi2 decides
 //                 whether it is used (update) or rejected (flagged).  The
 //                 next hit's coordinates are loaded a step ahead.
 //                 ROWS: the pad row of every hit is looked up in the
@@ -20,15 +23,18 @@
 //                 during the fit each next row is resolved a step ahead.
 //                 ERRS: hit h is measured with variances err[h]^2.
 //  smooth_tracks  thread per seed, after the fit over rows: the state at
-//                 every hit's plane from all hits.  The reference is the
-//                 fit's final state (FP64, from the fit kernel) carried by
-//                 exact helix steps to every plane; about it a Kalman filter
-//                 of the deviation runs inwards (Jacobians and scattering
-//                 noise taken on the reference, diffuse start, the hits the
-//                 fit used; rows as the fit stored them), storing the
-//                 filtered deviation and covariance of each hit (20
-//                 doubles); then the Rauch-Tung-Striebel pass outwards
-//                 recomputes the reference steps and solves with
+//                 every hit's plane from all hits.  The reference starts
+//                 at the outermost plane from the fit's final state (FP64,
+//                 from the fit kernel) -- one helix step, or plane by plane
+//                 with the energy loss taken away -- and runs inwards by the
+//                 fit's own step; along it a Kalman filter of the deviation
+//                 runs inwards (Jacobians, scattering and straggling noise
+//                 taken on the reference, diffuse start, the hits the fit
+//                 used; rows as the fit stored them), storing per hit the
+//                 filtered deviation, its covariance and the reference (26
+//                 doubles, 16-byte stores); then the Rauch-Tung-Striebel
+//                 pass outwards reads them back, takes the step inwards
+//                 from each stored reference for F, and solves with
 //                 P = F (C + Q) F^T by a Cholesky factorisation.
 #include "tpc_fit_common.hpp"
 #include "tpc_fit_ms.hpp"
@@ -40,6 +46,8 @@ struct MsArgs {
     double kbz;            // -c Bz in double precision
     double x0, mass2, cut;
     bool scatter;          // x0 finite
+    bool eloss;            // rho > 0
+    double mass, rho, zoa, mexc;   // energy loss: mass, density, Z/A, mean excitation energy
     uint8_t *rejected;     // [cap_hits] or null
     // fits over any rows
     const int32_t *row_offsets;   // cluster layout of the frames
@@ -66,6 +74,56 @@ __device__ inline void add_scattering(const MsArgs &A, const double p[5], double
     C.c33 += th2 * t2 * t2;
     C.c43 += th2 * t * w * t2;
     C.c44 += th2 * t * t * w * w;
+}
+
+// Energy-loss map of a segment of plane distance dx from state p (the
+// particle moves outwards: dir = +1 gives the mean loss back, a step
+// inwards; -1 takes it away).  Mean loss ds rho <dE/dx> with the Bethe
+// formula (unit charge, no density term), straggling variance of Bohr's
+// relativistic form; P' = sqrt(E'^2 - m^2), w' = w P/P'.  With the loss
+// held fixed, w' depends on t and w: j43 = dw'/dt, j44 = dw'/dw; vw is the
+// straggling as variance of w at the start.  A segment that would change
+// the momentum by more than 1 % is left alone (identity, no noise).  Returns
+// true if the particle stops.
+__device__ inline bool eloss_map(const MsArgs &A, const double p[5], double dx, double dir, double &wo,
+                                 double &j43, double &j44, double &vw) {
+    const double s = p[2], t = p[3], w = p[4];
+    wo = w;
+    j43 = 0.0;
+    j44 = 1.0;
+    vw = 0.0;
+    if (w == 0.0) return false;
+    const double K = 0.307075e-3, me = 0.51099895e-3;
+    const double m = A.mass;
+    const double t2 = 1.0 + t * t;
+    const double ds = fabs(dx) * sqrt(t2) / sqrt(1.0 - s * s);
+    const double P = sqrt(t2) / fabs(w);
+    const double E = sqrt(P * P + m * m);
+    const double b2 = P * P / (E * E), g = E / m, bg2 = P * P / (m * m), r = me / m;
+    const double W = 2.0 * me * bg2 / (1.0 + 2.0 * g * r + r * r);
+    const double dedx = K * A.zoa / b2 * (0.5 * log(2.0 * me * bg2 * W / (A.mexc * A.mexc)) - b2);
+    const double E1 = E + dir * (ds * A.rho * dedx);
+    if (!(E1 > m)) return true;
+    const double P1 = sqrt(E1 * E1 - m * m);
+    if (fabs(P1 - P) > 0.01 * P) return false;
+    const double q = P / P1;
+    wo = w * q;
+    j44 = q * q * q * E1 / E;
+    j43 = wo * t / t2 * (1.0 - E1 * P * P / (E * P1 * P1));
+    const double varE = K * A.zoa * A.rho * ds * me * (1.0 - 0.5 * b2) / (1.0 - b2);
+    const double dw = w * E / (P * P);
+    vw = varE * dw * dw;
+    return false;
+}
+
+// C <- J C J^T for J the identity but for row 4 = (0, 0, 0, a, b).
+__device__ inline void eloss_cov(SymT<double> &C, double a, double b) {
+    const double c30 = C.c30, c31 = C.c31, c32 = C.c32, c33 = C.c33, c43 = C.c43, c44 = C.c44;
+    C.c40 = a * c30 + b * C.c40;
+    C.c41 = a * c31 + b * C.c41;
+    C.c42 = a * c32 + b * C.c42;
+    C.c43 = a * c33 + b * c43;
+    C.c44 = a * a * c33 + 2.0 * a * b * c43 + b * b * c44;
 }
 
 // Row of cluster id at or below row r_hi of a (frame, sector) whose R + 1
@@ -194,6 +252,16 @@ __device__ inline void fit_ms_one(const MsArgs &A, int i, const float *xs) {
             const double xk = (double)xs[rk];
             const double dx = xk - xcur;
             add_scattering(A, p, dx, C);
+            if (A.eloss) {
+                double w1, a, b, vw;
+                if (eloss_map(A, p, dx, 1.0, w1, a, b, vw)) {
+                    status = TPC_FIT_SIN_FAIL;
+                    break;
+                }
+                C.c44 += vw;
+                eloss_cov(C, a, b);
+                p[4] = w1;
+            }
             StepJac J;
             if (!helix_step<double, double>(p, dx, A.kbz, F.max_sin, J)) {
                 status = TPC_FIT_SIN_FAIL;
@@ -245,6 +313,19 @@ __global__ void __launch_bounds__(TPC_BLOCK) fit_ms_tracks(MsArgs A) {
     if (T > A.F.cap_seeds) T = A.F.cap_seeds;
     for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK)
         fit_ms_one<ROWS, ERRS>(A, i, xs);
+}
+
+// Per seed hit the smoother keeps the filtered deviation (5), its
+// covariance (15, packed) and the reference state (5), padded to 26 doubles.
+constexpr int SM_REC = 26;
+
+__device__ inline void load_record(const double *rec, double w[SM_REC]) {
+    const double2 *v = reinterpret_cast<const double2 *>(rec);
+    for (int q = 0; q < SM_REC / 2; ++q) {
+        const double2 x = v[q];
+        w[2 * q] = x.x;
+        w[2 * q + 1] = x.y;
+    }
 }
 
 struct SmArgs {
@@ -339,22 +420,34 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
     if (status == TPC_FIT_OK) {
         // the fit accepted the seed and stored the row of every hit
         const double *pf = S.w.pfin + (size_t)i * 5;
-        double *wd = S.w.wd + (size_t)sv.o0 * 20;
+        double *wd = S.w.wd + (size_t)sv.o0 * SM_REC;
         const int16_t *wr = S.w.wrow + sv.o0;
         const int ra = wr[n - 1], rc = wr[0];
         const uint8_t *rej = S.rej + sv.o0;
-        // inwards: reference at the outermost plane, then steps along it
+        // the reference at the outermost plane: one helix step from the fit's
+        // final state, or, with energy loss, plane by plane taking the loss away
         double R[5];
         for (int q = 0; q < 5; ++q) R[q] = pf[q];
         StepJac J;
-        if (!helix_step<double, double>(R, (double)xs[ra] - (double)xs[rc], A.kbz, F.max_sin, J))
+        if (A.eloss) {
+            for (int k = 1; k < n && status == TPC_FIT_OK; ++k) {
+                const double dx = (double)xs[wr[k]] - (double)xs[wr[k - 1]];
+                double w1 = R[4], a, b, vw;
+                if (!helix_step<double, double>(R, dx, A.kbz, F.max_sin, J) ||
+                    eloss_map(A, R, dx, -1.0, w1, a, b, vw))
+                    status = TPC_FIT_SIN_FAIL;
+                R[4] = w1;
+            }
+        } else if (!helix_step<double, double>(R, (double)xs[ra] - (double)xs[rc], A.kbz, F.max_sin, J)) {
             status = TPC_FIT_SIN_FAIL;
+        }
         double vy = F.vy, vz = F.vz;
         if (ERRS) {
             const float2 e = A.err[sv.hh[n - 1]];
             vy = (double)e.x * (double)e.x;
             vz = (double)e.y * (double)e.y;
         }
+        // inwards along the reference: Kalman filter of the deviation d
         double d[5] = {0, 0, 0, 0, 0};
         SymT<double> C = {};
         C.c00 = 1e4 * vy;
@@ -371,7 +464,20 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                 const double dx = (double)xs[rcur] - (double)xs[rk];
                 SymT<double> Q = {};
                 add_scattering(A, R, dx, Q);
-                sym_add(C, Q);
+                if (A.eloss) {
+                    double w1, a, b, vw;
+                    if (eloss_map(A, R, dx, 1.0, w1, a, b, vw)) {
+                        status = TPC_FIT_SIN_FAIL;
+                        break;
+                    }
+                    Q.c44 += vw;
+                    sym_add(C, Q);
+                    eloss_cov(C, a, b);
+                    d[4] = a * d[3] + b * d[4];
+                    R[4] = w1;
+                } else {
+                    sym_add(C, Q);
+                }
                 if (!helix_step<double, double>(R, dx, A.kbz, F.max_sin, J)) {
                     status = TPC_FIT_SIN_FAIL;
                     break;
@@ -397,25 +503,37 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                     break;
                 }
             }
-            double *w = wd + (size_t)k * 20;
-            for (int q = 0; q < 5; ++q) w[q] = d[q];
-            const double cc[15] = {C.c00, C.c10, C.c11, C.c20, C.c21, C.c22, C.c30, C.c31,
-                                   C.c32, C.c33, C.c40, C.c41, C.c42, C.c43, C.c44};
-            for (int q = 0; q < 15; ++q) w[5 + q] = cc[q];
+            // d, C and the reference: 26 doubles as 13 16-byte stores (the
+            // record is 16-byte aligned)
+            double2 *w = reinterpret_cast<double2 *>(wd + (size_t)k * SM_REC);
+            w[0] = make_double2(d[0], d[1]);
+            w[1] = make_double2(d[2], d[3]);
+            w[2] = make_double2(d[4], C.c00);
+            w[3] = make_double2(C.c10, C.c11);
+            w[4] = make_double2(C.c20, C.c21);
+            w[5] = make_double2(C.c22, C.c30);
+            w[6] = make_double2(C.c31, C.c32);
+            w[7] = make_double2(C.c33, C.c40);
+            w[8] = make_double2(C.c41, C.c42);
+            w[9] = make_double2(C.c43, C.c44);
+            w[10] = make_double2(R[0], R[1]);
+            w[11] = make_double2(R[2], R[3]);
+            w[12] = make_double2(R[4], 0.0);
         }
         // outwards: Rauch-Tung-Striebel
         if (status == TPC_FIT_OK) {
             double ds[5], Cs[5][5];
-            for (int q = 0; q < 5; ++q) { R[q] = pf[q]; ds[q] = wd[q]; }
             {
+                double w[SM_REC];
+                load_record(wd, w);
+                for (int q = 0; q < 5; ++q) ds[q] = w[q];
                 SymT<double> C0;
-                const double *w = wd;
                 C0.c00 = w[5]; C0.c10 = w[6]; C0.c11 = w[7]; C0.c20 = w[8]; C0.c21 = w[9];
                 C0.c22 = w[10]; C0.c30 = w[11]; C0.c31 = w[12]; C0.c32 = w[13]; C0.c33 = w[14];
                 C0.c40 = w[15]; C0.c41 = w[16]; C0.c42 = w[17]; C0.c43 = w[18]; C0.c44 = w[19];
                 sym_dense(C0, Cs);
+                for (int q = 0; q < 5; ++q) hp[q] = (float)(w[20 + q] + ds[q]);
             }
-            for (int q = 0; q < 5; ++q) hp[q] = (float)(R[q] + ds[q]);
             {
                 const SymT<double> P0 = sym_packed(Cs);
                 const double cc[15] = {P0.c00, P0.c10, P0.c11, P0.c20, P0.c21, P0.c22, P0.c30, P0.c31,
@@ -425,39 +543,58 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
             int rprev = wr[0];
             for (int k = 1; k < n; ++k) {
                 const int r = wr[k];
-                // the reference at plane k, and the step from it back inwards
-                if (!helix_step<double, double>(R, (double)xs[r] - (double)xs[rprev], A.kbz, F.max_sin, J)) {
-                    status = TPC_FIT_SIN_FAIL;
-                    break;
-                }
-                double Rt[5] = {R[0], R[1], R[2], R[3], R[4]};
+                double w[SM_REC];
+                load_record(wd + (size_t)k * SM_REC, w);
+                const double dk[5] = {w[0], w[1], w[2], w[3], w[4]};
+                SymT<double> Ck;
+                Ck.c00 = w[5]; Ck.c10 = w[6]; Ck.c11 = w[7]; Ck.c20 = w[8]; Ck.c21 = w[9];
+                Ck.c22 = w[10]; Ck.c30 = w[11]; Ck.c31 = w[12]; Ck.c32 = w[13]; Ck.c33 = w[14];
+                Ck.c40 = w[15]; Ck.c41 = w[16]; Ck.c42 = w[17]; Ck.c43 = w[18]; Ck.c44 = w[19];
+                const double Rk[5] = {w[20], w[21], w[22], w[23], w[24]};
+                // the step inwards from the reference at plane k: F = Jh Je
                 const double dxi = (double)xs[rprev] - (double)xs[r];
+                SymT<double> Pq = Ck, Q = {};
+                add_scattering(A, Rk, dxi, Q);
+                double Rt[5] = {Rk[0], Rk[1], Rk[2], Rk[3], Rk[4]};
+                double ea = 0.0, eb = 1.0;
+                if (A.eloss) {
+                    double w1, vw;
+                    if (eloss_map(A, Rk, dxi, 1.0, w1, ea, eb, vw)) {
+                        status = TPC_FIT_SIN_FAIL;
+                        break;
+                    }
+                    Q.c44 += vw;
+                    Rt[4] = w1;
+                }
                 StepJac Jk;
                 if (!helix_step<double, double>(Rt, dxi, A.kbz, F.max_sin, Jk)) {
                     status = TPC_FIT_SIN_FAIL;
                     break;
                 }
-                SymT<double> Ck;
-                const double *w = wd + (size_t)k * 20;
-                const double dk[5] = {w[0], w[1], w[2], w[3], w[4]};
-                Ck.c00 = w[5]; Ck.c10 = w[6]; Ck.c11 = w[7]; Ck.c20 = w[8]; Ck.c21 = w[9];
-                Ck.c22 = w[10]; Ck.c30 = w[11]; Ck.c31 = w[12]; Ck.c32 = w[13]; Ck.c33 = w[14];
-                Ck.c40 = w[15]; Ck.c41 = w[16]; Ck.c42 = w[17]; Ck.c43 = w[18]; Ck.c44 = w[19];
-                SymT<double> Pq = Ck, Q = {};
-                add_scattering(A, R, dxi, Q);
                 sym_add(Pq, Q);
+                double Cd[5][5], X[5][5], ed[5] = {dk[0], dk[1], dk[2], dk[3], dk[4]};
+                sym_dense(Ck, Cd);
+                if (A.eloss) {
+                    eloss_cov(Pq, ea, eb);
+                    ed[4] = ea * dk[3] + eb * dk[4];
+                    double EC[5][5];
+                    for (int a = 0; a < 5; ++a)
+                        for (int b = 0; b < 5; ++b)
+                            EC[a][b] = a < 4 ? Cd[a][b] : ea * Cd[3][b] + eb * Cd[4][b];
+                    jac_times(Jk, EC, X);                    // F C_k
+                } else {
+                    jac_times(Jk, Cd, X);                    // F C_k
+                }
                 sym_transport<double, false>(Pq, Jk);       // P = F (C_k + Q) F^T
-                double P[5][5], Pd[5][5], Cd[5][5], X[5][5];
+                double P[5][5], Pd[5][5];
                 sym_dense(Pq, P);
                 sym_dense(Pq, Pd);
-                sym_dense(Ck, Cd);
-                jac_times(Jk, Cd, X);                        // F C_k
                 if (!chol_solve(P, X)) {                     // X = P^-1 F C_k = G^T
                     status = TPC_FIT_NUM_FAIL;
                     break;
                 }
                 double pd[5], e[5], nds[5];
-                jac_apply(Jk, dk, pd);
+                jac_apply(Jk, ed, pd);
                 for (int q = 0; q < 5; ++q) e[q] = ds[q] - pd[q];
                 for (int a = 0; a < 5; ++a) {
                     double acc = dk[a];
@@ -482,7 +619,7 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                     }
                 for (int q = 0; q < 5; ++q) ds[q] = nds[q];
                 float *o = hp + (size_t)k * 5;
-                for (int q = 0; q < 5; ++q) o[q] = (float)(R[q] + ds[q]);
+                for (int q = 0; q < 5; ++q) o[q] = (float)(Rk[q] + ds[q]);
                 float *oc = hc + (size_t)k * 15;
                 int q = 0;
                 for (int a = 0; a < 5; ++a)
@@ -529,6 +666,11 @@ MsArgs make_ms_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seed
     A.scatter = mat && mat->x0 < INFINITY;
     A.mass2 = mat ? (double)mat->mass * (double)mat->mass : 0.0;
     A.cut = mat ? (double)mat->chi2_cut : (double)INFINITY;
+    A.eloss = mat && mat->rho > 0.f;
+    A.mass = mat ? (double)mat->mass : 0.0;
+    A.rho = mat ? (double)mat->rho : 0.0;
+    A.zoa = mat ? (double)mat->z_over_a : 0.0;
+    A.mexc = mat ? (double)mat->mean_exc : 0.0;
     A.rejected = rejected;
     A.row_offsets = fr->row_offsets;
     A.frame = sd->frame;
@@ -572,7 +714,7 @@ size_t smooth_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, SmWs *out
     const size_t fb = fit_ws_layout(nullptr, cap_seeds, cap_hits, nullptr, nullptr);
     WsCarver w(ws ? (void *)((char *)ws + fb) : nullptr);
     double *pfin = w.take<double>((size_t)(cap_seeds > 0 ? cap_seeds : 1) * 5);
-    double *wd = w.take<double>((size_t)(cap_hits > 0 ? cap_hits : 1) * 20);
+    double *wd = w.take<double>((size_t)(cap_hits > 0 ? cap_hits : 1) * SM_REC);
     int16_t *wrow = w.take<int16_t>((size_t)(cap_hits > 0 ? cap_hits : 1));
     if (out) *out = SmWs{pfin, wd, wrow};
     return fb + ((w.off + 255) & ~size_t(255));

@@ -248,13 +248,16 @@ class Reco:
         return tracks
 
     def fit_material(self, frames: DeviceFrames, seeds: Seeds, x0: float, mass: float, chi2_cut: float,
-                     tracks: Optional[Tracks] = None, rejected: Optional[torch.Tensor] = None, ws=None):
-        """tpc_kalman_fit_material: returns (Tracks, rejected uint8 per seed hit)."""
+                     tracks: Optional[Tracks] = None, rejected: Optional[torch.Tensor] = None, ws=None,
+                     gas: Optional[tuple] = None):
+        """tpc_kalman_fit_material, with energy loss in ``gas`` = (rho g/cm^3,
+        Z/A, mean excitation energy GeV) if given: returns (Tracks, rejected
+        uint8 per seed hit)."""
         tracks = self.alloc_tracks(seeds) if tracks is None else tracks
         if rejected is None:
             rejected = torch.zeros(max(seeds.hits.numel(), 1), dtype=torch.uint8, device=self.device)
         ws = self.workspace(frames) if ws is None else ws
-        mat = C.Material(float(x0), float(mass), float(chi2_cut))
+        mat = C.Material(float(x0), float(mass), float(chi2_cut), *(float(v) for v in (gas or ())))
         sc = seeds.c()
         tc = tracks.c()
         C.check(C.lib().tpc_kalman_fit_material(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc),
@@ -267,7 +270,9 @@ class Reco:
                  rejected: Optional[torch.Tensor] = None, ws=None):
         """tpc_kalman_fit_rows: seeds whose hits may skip pad rows, optional
         per-cluster errors ([N, 2] float32 sigma_y, sigma_z on the device) and
-        material (x0, mass, chi2_cut).  Returns (Tracks, rejected)."""
+        material (x0, mass, chi2_cut), optionally followed by the gas for
+        energy loss (rho, Z/A, mean excitation energy).  Returns (Tracks,
+        rejected)."""
         tracks = self.alloc_tracks(seeds) if tracks is None else tracks
         if rejected is None:
             rejected = torch.zeros(max(seeds.hits.numel(), 1), dtype=torch.uint8, device=self.device)

@@ -1,6 +1,7 @@
 """GPU parity of the fit with material (tpc_kalman_fit_material through the
 C-ABI) against the oracle on the oracle's seeds (the GPU's are checked to be
-the same first).  Rejection flags must equal the oracle's for every track
+the same first).  Energy loss in a gas: protons in a dense argon, the headline
+frame in the TPC's Ne-CO2-N2.  Rejection flags must equal the oracle's for every track
 whose hits' chi2 all lie farther than 1e-6 (relative) from the cut; the
 refits are held to the fit tolerances (1e-4 parameters, 1e-3 covariance and
 chi2)."""
@@ -10,7 +11,7 @@ import pytest
 import oracle
 from tests.conftest import NB, MIN_HITS, FIT
 from tests import parity
-from tpcsynth import make_config, make_scattering_frame, PION_MASS
+from tpcsynth import make_config, make_scattering_frame, PION_MASS, PROTON_MASS, ARGON_GAS, TPC_GAS
 
 pytestmark = pytest.mark.gpu
 
@@ -22,7 +23,11 @@ def torch_dev():
     return torch
 
 
-def check(fr, x0, cut, label, displace=None):
+def _f32(gas):
+    return None if gas is None else tuple(float(np.float32(v)) for v in gas)
+
+
+def check(fr, x0, cut, label, displace=None, mass=PION_MASS, gas=None):
     import torch
     from paper_2412_13755_amd.reco import Reco, RecoConfig
     print("[material] %s: N=%d x0=%g cut=%g" % (label, fr.n_clusters, x0, cut), flush=True)
@@ -42,13 +47,13 @@ def check(fr, x0, cut, label, displace=None):
         fr2 = type(fr)(**{**fr.__dict__, "y": y})
         dfr = reco.upload(fr2)
         seeds.hit_yz = None
-    tr, rej = reco.fit_material(dfr, seeds, x0, PION_MASS, cut)
+    tr, rej = reco.fit_material(dfr, seeds, x0, mass, cut, gas=gas)
     torch.cuda.synchronize()
     T = len(rs["offsets"]) - 1
     H = rs["hits"].size
     g = {k: getattr(tr, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "chi2", "ndf", "status")}
     grej = rej[:H].cpu().numpy()
-    r = oracle.fit_material(rs, y, fr.z, fr.row_x, x0=x0, mass=PION_MASS, chi2_cut=cut, **FIT)
+    r = oracle.fit_material(rs, y, fr.z, fr.row_x, x0=x0, mass=mass, chi2_cut=cut, gas=_f32(gas), **FIT)
     robust = r["margin"] >= 1e-6
     assert (~robust).sum() <= max(2, T // 1000), (~robust).sum()
     seg = np.repeat(np.arange(T), np.diff(rs["offsets"]))
@@ -86,3 +91,17 @@ def test_displaced_hits(torch_dev):
 def test_no_material_is_the_plain_fit(torch_dev):
     fr = make_config(0)
     check(fr, float("inf"), float("inf"), "no material")
+
+
+DENSE_GAS = (0.05, ARGON_GAS[1], ARGON_GAS[2])      # argon 30 times denser, X0 = 391 cm
+
+
+def test_energy_loss_protons(torch_dev):
+    fr = make_scattering_frame(n_tracks=400, seed=21, x0_cm=391.0, mass=PROTON_MASS, inv_pt=(0.7, 2.0),
+                               gas=DENSE_GAS)
+    check(fr, 391.0, 30.0, "protons, dense gas", mass=PROTON_MASS, gas=DENSE_GAS)
+
+
+def test_headline_frame_with_energy_loss(torch_dev):
+    st, r = check(make_config(1), 2870.0, 30.0, "full-tpc-event-1e4, Ne-CO2-N2", gas=TPC_GAS)
+    assert st["compared"] > 20000

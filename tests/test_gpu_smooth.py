@@ -4,14 +4,15 @@ smoothed state at every seed hit's plane to the same tolerances (1e-4
 relative on parameters with the fit's floors, 1e-3 on the covariance
 relative to the product of standard deviations).  Tracks whose rejection
 decisions lie within 1e-6 (relative) of the cut are left out (the oracle
-reports that margin)."""
+reports that margin).  With energy loss: protons in a dense argon, the
+headline frame in the TPC's Ne-CO2-N2."""
 import numpy as np
 import pytest
 
 import oracle
 from tests.conftest import NB, FIT, MIN_HITS
 from tests import parity
-from tpcsynth import make_config, make_scattering_frame, PION_MASS
+from tpcsynth import make_config, make_scattering_frame, PION_MASS, PROTON_MASS, ARGON_GAS, TPC_GAS
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +39,10 @@ def check(fr, label, skip=False, err=None, material=None):
     ru, rd = nb(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
     rs = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, MIN_HITS)
     parity.assert_seeds_equal(seeds.to_numpy(), rs)
-    x0, mass, cut = material if material is not None else (np.inf, PION_MASS, np.inf)
+    x0, mass, cut = material[:3] if material is not None else (np.inf, PION_MASS, np.inf)
+    gas = None if material is None or len(material) == 3 else tuple(float(np.float32(v)) for v in material[3:])
     r = oracle.fit_rows(rs, fr.row_offsets, fr.y, fr.z, fr.row_x, fr.n_sectors, fr.n_rows, err=err,
-                        x0=x0, mass=mass, chi2_cut=cut, smooth=True, **FIT)
+                        x0=x0, mass=mass, chi2_cut=cut, gas=gas, smooth=True, **FIT)
     T, H = len(rs["offsets"]) - 1, rs["hits"].size
     g = {k: getattr(tr, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "chi2", "ndf", "status")}
     robust = r["margin"] >= 1e-6
@@ -86,3 +88,14 @@ def test_headline_frame(torch_dev):
 def test_skip_seeds_errors_and_rejection(torch_dev):
     fr = make_config(1, scale=0.2, err_scale=(0.5, 2.0), hit_eff=0.9)
     check(fr, "skip seeds, per-cluster errors, cut", skip=True, err=fr.err, material=(300.0, PION_MASS, 30.0))
+
+
+def test_energy_loss_protons(torch_dev):
+    gas = (0.05, ARGON_GAS[1], ARGON_GAS[2])
+    fr = make_scattering_frame(n_tracks=400, seed=11, x0_cm=391.0, mass=PROTON_MASS, inv_pt=(0.7, 2.0), gas=gas)
+    check(fr, "protons, dense gas", material=(391.0, PROTON_MASS, 30.0) + gas)
+
+
+def test_headline_frame_with_energy_loss(torch_dev):
+    st = check(make_config(1), "full-tpc-event-1e4, Ne-CO2-N2", material=(2870.0, PION_MASS, 30.0) + TPC_GAS)
+    assert st["hits"] > 900000

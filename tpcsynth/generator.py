@@ -496,6 +496,9 @@ ELECTRON_MASS = 0.51099895e-3     # GeV
 BETHE_K = 0.307075e-3             # GeV cm^2 / mol
 # (density g/cm^3, Z/A mol/g, mean excitation energy GeV)
 ARGON_GAS = (1.662e-3, 0.45059, 188.0e-9)
+# Ne-CO2-N2 90-10-5 by volume at 20 C, from its components by mass
+# fraction (Z/A averaged, ln I averaged with weights w Z/A)
+TPC_GAS = (0.948e-3, 0.4966, 121.8e-9)
 
 
 def mean_dedx(p, mass, rho, z_over_a, mean_exc):
