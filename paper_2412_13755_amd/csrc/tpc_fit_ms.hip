@@ -31,11 +31,12 @@
 //                 runs inwards (Jacobians, scattering and straggling noise
 //                 taken on the reference, diffuse start, the hits the fit
 //                 used; rows as the fit stored them), storing per hit the
-//                 filtered deviation, its covariance and the reference (26
-//                 doubles, 16-byte stores); then the Rauch-Tung-Striebel
-//                 pass outwards reads them back, takes the step inwards
-//                 from each stored reference for F, and solves with
-//                 P = F (C + Q) F^T by a Cholesky factorisation.
+//                 filtered deviation, its covariance, the reference and the
+//                 step that arrived there (Jacobian, noise, energy-loss
+//                 factors; 38 doubles, 16-byte stores); then the
+//                 Rauch-Tung-Striebel pass outwards reads them back (no
+//                 step is taken again) and solves with P = F (C + Q) F^T
+//                 by a Cholesky factorisation.
 #include "tpc_fit_common.hpp"
 #include "tpc_fit_ms.hpp"
 
@@ -47,7 +48,8 @@ struct MsArgs {
     double x0, mass2, cut;
     bool scatter;          // x0 finite
     bool eloss;            // rho > 0
-    double mass, rho, zoa, mexc;   // energy loss: mass, density, Z/A, mean excitation energy
+    double mass, rho, zoa;         // energy loss: mass, density, Z/A,
+    double inv_mass2, me_over_m, inv_exc2;   // 1/m^2, m_e/m, 1/I^2
     uint8_t *rejected;     // [cap_hits] or null
     // fits over any rows
     const int32_t *row_offsets;   // cluster layout of the frames
@@ -58,60 +60,78 @@ struct MsArgs {
     int16_t *rows_out;            // [cap_hits] row of every seed hit (ROWS), or null
 };
 
-// Adds the scattering of a segment of plane distance dx to C (state p at
-// the plane the segment starts from).
-__device__ inline void add_scattering(const MsArgs &A, const double p[5], double dx, SymT<double> &C) {
+// The segment of plane distance dx about to be crossed, seen from the
+// state p at the plane the step leaves: path ds = |dx| sqrt(1+t^2) /
+// sqrt(1-s^2), momentum P = sqrt(1+t^2)/|w|, energy E, beta^2 = P^2/E^2.
+struct Segment {
+    double ds, P, E, b2;
+};
+
+__device__ inline Segment segment(const MsArgs &A, const double p[5], double dx) {
+    const double s = p[2], t = p[3], w = p[4];
+    const double st = sqrt(1.0 + t * t);
+    Segment g;
+    g.ds = fabs(dx) * st / sqrt(1.0 - s * s);
+    g.P = st / fabs(w);
+    const double P2 = g.P * g.P;
+    const double E2 = P2 + A.mass2;
+    g.E = sqrt(E2);
+    g.b2 = P2 / E2;
+    return g;
+}
+
+// Adds the scattering of the segment to C (Highland: theta0^2 =
+// (0.0136 / (beta P))^2 ds/X0 (1 + 0.038 ln(ds/X0))^2; the logarithm, which
+// only scales the noise, in single precision).
+__device__ inline void add_scattering(const MsArgs &A, const double p[5], const Segment &g, SymT<double> &C) {
     const double s = p[2], t = p[3], w = p[4];
     if (!A.scatter || w == 0.0) return;
     const double t2 = 1.0 + t * t;
-    const double ds = fabs(dx) * sqrt(t2) / sqrt(1.0 - s * s);
-    const double pm = sqrt(t2) / fabs(w);
-    const double beta = pm / sqrt(pm * pm + A.mass2);
-    const double xr = ds / A.x0;
-    const double th = 0.0136 / (beta * pm) * sqrt(xr) * (1.0 + 0.038 * log(xr));
-    const double th2 = th * th;
+    const double xr = g.ds / A.x0;
+    const double f = 1.0 + 0.038 * (double)logf((float)xr);
+    const double k = 0.0136 * 0.0136 / (g.b2 * g.P * g.P);
+    const double th2 = k * xr * f * f;
     C.c22 += th2 * (1.0 - s * s) * t2;
     C.c33 += th2 * t2 * t2;
     C.c43 += th2 * t * w * t2;
     C.c44 += th2 * t * t * w * w;
 }
 
-// Energy-loss map of a segment of plane distance dx from state p (the
-// particle moves outwards: dir = +1 gives the mean loss back, a step
-// inwards; -1 takes it away).  Mean loss ds rho <dE/dx> with the Bethe
-// formula (unit charge, no density term), straggling variance of Bohr's
-// relativistic form; P' = sqrt(E'^2 - m^2), w' = w P/P'.  With the loss
-// held fixed, w' depends on t and w: j43 = dw'/dt, j44 = dw'/dw; vw is the
-// straggling as variance of w at the start.  A segment that would change
-// the momentum by more than 1 % is left alone (identity, no noise).  Returns
-// true if the particle stops.
-__device__ inline bool eloss_map(const MsArgs &A, const double p[5], double dx, double dir, double &wo,
+// Energy-loss map of the segment (the particle moves outwards: dir = +1
+// gives the mean loss back, a step inwards; -1 takes it away).  Mean loss
+// ds rho <dE/dx> with the Bethe formula (unit charge, no density term; its
+// logarithm in single precision, which changes the loss by ~1e-7 of
+// itself), straggling variance of Bohr's relativistic form;
+// P' = sqrt(E'^2 - m^2), w' = w P/P'.  With the loss held fixed, w' depends
+// on t and w: j43 = dw'/dt, j44 = dw'/dw; vw is the straggling as variance
+// of w at the start.  A segment that would change the momentum by more than
+// 1 % is left alone (identity, no noise).  Returns true if the particle
+// stops.
+__device__ inline bool eloss_map(const MsArgs &A, const double p[5], const Segment &g, double dir, double &wo,
                                  double &j43, double &j44, double &vw) {
-    const double s = p[2], t = p[3], w = p[4];
+    const double t = p[3], w = p[4];
     wo = w;
     j43 = 0.0;
     j44 = 1.0;
     vw = 0.0;
     if (w == 0.0) return false;
     const double K = 0.307075e-3, me = 0.51099895e-3;
-    const double m = A.mass;
-    const double t2 = 1.0 + t * t;
-    const double ds = fabs(dx) * sqrt(t2) / sqrt(1.0 - s * s);
-    const double P = sqrt(t2) / fabs(w);
-    const double E = sqrt(P * P + m * m);
-    const double b2 = P * P / (E * E), g = E / m, bg2 = P * P / (m * m), r = me / m;
-    const double W = 2.0 * me * bg2 / (1.0 + 2.0 * g * r + r * r);
-    const double dedx = K * A.zoa / b2 * (0.5 * log(2.0 * me * bg2 * W / (A.mexc * A.mexc)) - b2);
-    const double E1 = E + dir * (ds * A.rho * dedx);
+    const double m = A.mass, P2 = g.P * g.P;
+    const double bg2 = P2 * A.inv_mass2, r = A.me_over_m;
+    const double W = 2.0 * me * bg2 / (1.0 + 2.0 * (g.E / m) * r + r * r);
+    const double L = (double)logf((float)(2.0 * me * bg2 * W * A.inv_exc2));
+    const double dedx = K * A.zoa / g.b2 * (0.5 * L - g.b2);
+    const double E1 = g.E + dir * (g.ds * A.rho * dedx);
     if (!(E1 > m)) return true;
-    const double P1 = sqrt(E1 * E1 - m * m);
-    if (fabs(P1 - P) > 0.01 * P) return false;
-    const double q = P / P1;
+    const double P1 = sqrt(E1 * E1 - A.mass2);
+    if (fabs(P1 - g.P) > 0.01 * g.P) return false;
+    const double q = g.P / P1, e = E1 / g.E;
     wo = w * q;
-    j44 = q * q * q * E1 / E;
-    j43 = wo * t / t2 * (1.0 - E1 * P * P / (E * P1 * P1));
-    const double varE = K * A.zoa * A.rho * ds * me * (1.0 - 0.5 * b2) / (1.0 - b2);
-    const double dw = w * E / (P * P);
+    j44 = q * q * q * e;
+    const double t2 = 1.0 + t * t;
+    j43 = wo * t / t2 * (1.0 - e * q * q);
+    const double varE = K * A.zoa * A.rho * g.ds * me * (1.0 - 0.5 * g.b2) / (1.0 - g.b2);
+    const double dw = w * g.E / P2;
     vw = varE * dw * dw;
     return false;
 }
@@ -251,16 +271,19 @@ __device__ inline void fit_ms_one(const MsArgs &A, int i, const float *xs) {
             }
             const double xk = (double)xs[rk];
             const double dx = xk - xcur;
-            add_scattering(A, p, dx, C);
-            if (A.eloss) {
-                double w1, a, b, vw;
-                if (eloss_map(A, p, dx, 1.0, w1, a, b, vw)) {
-                    status = TPC_FIT_SIN_FAIL;
-                    break;
+            if (A.scatter || A.eloss) {
+                const Segment g = segment(A, p, dx);
+                add_scattering(A, p, g, C);
+                if (A.eloss) {
+                    double w1, a, b, vw;
+                    if (eloss_map(A, p, g, 1.0, w1, a, b, vw)) {
+                        status = TPC_FIT_SIN_FAIL;
+                        break;
+                    }
+                    C.c44 += vw;
+                    eloss_cov(C, a, b);
+                    p[4] = w1;
                 }
-                C.c44 += vw;
-                eloss_cov(C, a, b);
-                p[4] = w1;
             }
             StepJac J;
             if (!helix_step<double, double>(p, dx, A.kbz, F.max_sin, J)) {
@@ -316,8 +339,11 @@ __global__ void __launch_bounds__(TPC_BLOCK) fit_ms_tracks(MsArgs A) {
 }
 
 // Per seed hit the smoother keeps the filtered deviation (5), its
-// covariance (15, packed) and the reference state (5), padded to 26 doubles.
-constexpr int SM_REC = 26;
+// covariance (15, packed), the reference state (5) and the step that
+// arrived at the hit's plane from the next one out (helix Jacobian (6),
+// scattering and straggling noise (4), energy-loss factors (2)), padded to
+// 38 doubles.
+constexpr int SM_REC = 38;
 
 __device__ inline void load_record(const double *rec, double w[SM_REC]) {
     const double2 *v = reinterpret_cast<const double2 *>(rec);
@@ -434,7 +460,7 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                 const double dx = (double)xs[wr[k]] - (double)xs[wr[k - 1]];
                 double w1 = R[4], a, b, vw;
                 if (!helix_step<double, double>(R, dx, A.kbz, F.max_sin, J) ||
-                    eloss_map(A, R, dx, -1.0, w1, a, b, vw))
+                    eloss_map(A, R, segment(A, R, dx), -1.0, w1, a, b, vw))
                     status = TPC_FIT_SIN_FAIL;
                 R[4] = w1;
             }
@@ -458,22 +484,26 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
         int rk = ra;
         int rn = wr[n - 2];                 // loaded a step ahead
         for (int k = n - 1; k >= 0 && status == TPC_FIT_OK; --k) {
+            // the step that arrives at plane k: its noise and energy-loss
+            // factors, kept for the outward pass with its Jacobian J
+            SymT<double> Q = {};
+            double ea = 0.0, eb = 1.0;
             if (k < n - 1) {
                 const int rcur = rn;
                 if (k > 0) rn = wr[k - 1];
                 const double dx = (double)xs[rcur] - (double)xs[rk];
-                SymT<double> Q = {};
-                add_scattering(A, R, dx, Q);
+                const Segment g = (A.scatter || A.eloss) ? segment(A, R, dx) : Segment{};
+                add_scattering(A, R, g, Q);
                 if (A.eloss) {
-                    double w1, a, b, vw;
-                    if (eloss_map(A, R, dx, 1.0, w1, a, b, vw)) {
+                    double w1, vw;
+                    if (eloss_map(A, R, g, 1.0, w1, ea, eb, vw)) {
                         status = TPC_FIT_SIN_FAIL;
                         break;
                     }
                     Q.c44 += vw;
                     sym_add(C, Q);
-                    eloss_cov(C, a, b);
-                    d[4] = a * d[3] + b * d[4];
+                    eloss_cov(C, ea, eb);
+                    d[4] = ea * d[3] + eb * d[4];
                     R[4] = w1;
                 } else {
                     sym_add(C, Q);
@@ -503,8 +533,9 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                     break;
                 }
             }
-            // d, C and the reference: 26 doubles as 13 16-byte stores (the
-            // record is 16-byte aligned)
+            // d, C, the reference and the arriving step (Jacobian, the four
+            // noise terms, energy-loss factors): 38 doubles as 19 16-byte
+            // stores (the record is 16-byte aligned)
             double2 *w = reinterpret_cast<double2 *>(wd + (size_t)k * SM_REC);
             w[0] = make_double2(d[0], d[1]);
             w[1] = make_double2(d[2], d[3]);
@@ -518,14 +549,25 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
             w[9] = make_double2(C.c43, C.c44);
             w[10] = make_double2(R[0], R[1]);
             w[11] = make_double2(R[2], R[3]);
-            w[12] = make_double2(R[4], 0.0);
+            w[12] = make_double2(R[4], J.f02);
+            w[13] = make_double2(J.f04, J.f12);
+            w[14] = make_double2(J.f13, J.f14);
+            w[15] = make_double2(J.f24, Q.c22);
+            w[16] = make_double2(Q.c33, Q.c43);
+            w[17] = make_double2(Q.c44, ea);
+            w[18] = make_double2(eb, 0.0);
         }
         // outwards: Rauch-Tung-Striebel
         if (status == TPC_FIT_OK) {
             double ds[5], Cs[5][5];
+            // the step from plane 1 to plane 0 is stored with plane 0
+            StepJac Jk;
+            double q22, q33, q43, q44, ea, eb;
             {
                 double w[SM_REC];
                 load_record(wd, w);
+                Jk = StepJac{w[25], w[26], w[27], w[28], w[29], w[30]};
+                q22 = w[31]; q33 = w[32]; q43 = w[33]; q44 = w[34]; ea = w[35]; eb = w[36];
                 for (int q = 0; q < 5; ++q) ds[q] = w[q];
                 SymT<double> C0;
                 C0.c00 = w[5]; C0.c10 = w[6]; C0.c11 = w[7]; C0.c20 = w[8]; C0.c21 = w[9];
@@ -540,9 +582,7 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                                        P0.c32, P0.c33, P0.c40, P0.c41, P0.c42, P0.c43, P0.c44};
                 for (int q = 0; q < 15; ++q) hc[q] = (float)cc[q];
             }
-            int rprev = wr[0];
             for (int k = 1; k < n; ++k) {
-                const int r = wr[k];
                 double w[SM_REC];
                 load_record(wd + (size_t)k * SM_REC, w);
                 const double dk[5] = {w[0], w[1], w[2], w[3], w[4]};
@@ -551,27 +591,13 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                 Ck.c22 = w[10]; Ck.c30 = w[11]; Ck.c31 = w[12]; Ck.c32 = w[13]; Ck.c33 = w[14];
                 Ck.c40 = w[15]; Ck.c41 = w[16]; Ck.c42 = w[17]; Ck.c43 = w[18]; Ck.c44 = w[19];
                 const double Rk[5] = {w[20], w[21], w[22], w[23], w[24]};
-                // the step inwards from the reference at plane k: F = Jh Je
-                const double dxi = (double)xs[rprev] - (double)xs[r];
-                SymT<double> Pq = Ck, Q = {};
-                add_scattering(A, Rk, dxi, Q);
-                double Rt[5] = {Rk[0], Rk[1], Rk[2], Rk[3], Rk[4]};
-                double ea = 0.0, eb = 1.0;
-                if (A.eloss) {
-                    double w1, vw;
-                    if (eloss_map(A, Rk, dxi, 1.0, w1, ea, eb, vw)) {
-                        status = TPC_FIT_SIN_FAIL;
-                        break;
-                    }
-                    Q.c44 += vw;
-                    Rt[4] = w1;
-                }
-                StepJac Jk;
-                if (!helix_step<double, double>(Rt, dxi, A.kbz, F.max_sin, Jk)) {
-                    status = TPC_FIT_SIN_FAIL;
-                    break;
-                }
-                sym_add(Pq, Q);
+                // the step inwards from plane k: F = Jh Je, noise Q (stored
+                // with plane k - 1 by the filter)
+                SymT<double> Pq = Ck;
+                Pq.c22 += q22;
+                Pq.c33 += q33;
+                Pq.c43 += q43;
+                Pq.c44 += q44;
                 double Cd[5][5], X[5][5], ed[5] = {dk[0], dk[1], dk[2], dk[3], dk[4]};
                 sym_dense(Ck, Cd);
                 if (A.eloss) {
@@ -624,7 +650,9 @@ __device__ inline void smooth_one(const SmArgs &S, int i, const float *xs) {
                 int q = 0;
                 for (int a = 0; a < 5; ++a)
                     for (int b = 0; b <= a; ++b, ++q) oc[q] = (float)Cs[a][b];
-                rprev = r;
+                // the step from plane k + 1, stored with plane k
+                Jk = StepJac{w[25], w[26], w[27], w[28], w[29], w[30]};
+                q22 = w[31]; q33 = w[32]; q43 = w[33]; q44 = w[34]; ea = w[35]; eb = w[36];
             }
         }
         if (status != TPC_FIT_OK) F.out.status[i] = status;
@@ -670,7 +698,9 @@ MsArgs make_ms_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seed
     A.mass = mat ? (double)mat->mass : 0.0;
     A.rho = mat ? (double)mat->rho : 0.0;
     A.zoa = mat ? (double)mat->z_over_a : 0.0;
-    A.mexc = mat ? (double)mat->mean_exc : 0.0;
+    A.inv_mass2 = A.eloss ? 1.0 / A.mass2 : 0.0;
+    A.me_over_m = A.eloss ? 0.51099895e-3 / A.mass : 0.0;
+    A.inv_exc2 = A.eloss ? 1.0 / ((double)mat->mean_exc * (double)mat->mean_exc) : 0.0;
     A.rejected = rejected;
     A.row_offsets = fr->row_offsets;
     A.frame = sd->frame;

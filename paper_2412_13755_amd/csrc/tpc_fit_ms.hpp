@@ -19,7 +19,7 @@ hipError_t launch_fit_rows(const tpc_context *ctx, const tpc_frames *fr, const t
 // per-hit filtered deviations and rows).
 struct SmWs {
     double *pfin;      // [cap_seeds][5] final states of the fit
-    double *wd;        // [cap_hits][26] filtered deviation, covariance, reference
+    double *wd;        // [cap_hits][38] filtered deviation, covariance, reference, arriving step
     int16_t *wrow;     // [cap_hits] pad row of each hit
 };
 size_t smooth_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, SmWs *out);
