@@ -21,11 +21,19 @@
  *                j*64 + k belongs to coder k (64 coders, all starting at
  *                2^16); the block is coded backwards (j descending, k
  *                descending) onto one word stack
- *   stream       little-endian: u32 magic "RANS", u32 version 1, u64 n,
- *                i32 lo, u32 R, u32 L, u32 B, u32 number of blocks, u32 0,
- *                u32 f[R], u32 word_start[blocks + 1] (offsets into the word
+ *   stream       little-endian: u32 magic "RANS", u32 version 2, u64 n,
+ *                i32 lo, u32 R, u32 L, u32 B, u32 number of blocks, u32 T,
+ *                the frequency table in T bytes (zero-padded to a multiple
+ *                of 4), u32 word_start[blocks + 1] (offsets into the word
  *                area), u32 state[blocks][64] (final coder states), u16
  *                words (each block's stack, last pushed first)
+ *   table        the decoder's metadata, compressed (Sec. 4.3 says it is):
+ *                for each present symbol s in ascending order, the run of
+ *                absent symbols before it (s - s_prev - 1, s_prev = -1 at
+ *                first) and f_s - 1, each as an unsigned LEB128 varint (7
+ *                bits per byte, low group first, high bit set on every
+ *                byte but the last; at most 3 bytes, as both values are
+ *                below 2^21).  Absent symbols have f = 0.
  *
  * Decoding runs the block forwards (j ascending, k ascending): slot = x mod M,
  * s = the symbol with cum_s <= slot < cum_s + f_s, x <- f_s (x >> L) + slot -
@@ -66,10 +74,42 @@ int64_t oracle_rans_freqs(const uint32_t *c, uint32_t R, uint64_t n, uint32_t L,
     return D;
 }
 
+/* Largest table: 6 bytes for each of at most min(R, 2^16) present symbols,
+ * padded to 4. */
+static size_t table_bound(uint32_t R)
+{
+    size_t d = R < 65536u ? R : 65536u;
+    return (6 * d + 3) & ~(size_t)3;
+}
+
 size_t oracle_rans_bound(int64_t n, uint32_t R, uint32_t B)
 {
     uint64_t blocks = n > 0 ? ((uint64_t)n + B - 1) / B : 0;
-    return 40 + 4 * (size_t)R + 4 * (size_t)(blocks + 1) + 4 * RANS_LANES * (size_t)blocks + 2 * (size_t)n;
+    return 40 + table_bound(R) + 4 * (size_t)(blocks + 1) + 4 * RANS_LANES * (size_t)blocks + 2 * (size_t)n;
+}
+
+static size_t put_varint(uint8_t *p, uint32_t v)
+{
+    size_t k = 0;
+    while (v >= 0x80u) {
+        p[k++] = (uint8_t)(v | 0x80u);
+        v >>= 7;
+    }
+    p[k++] = (uint8_t)v;
+    return k;
+}
+
+/* Reads a varint of at most 3 bytes from p[*at..end); returns 0, or -1. */
+static int get_varint(const uint8_t *p, size_t end, size_t *at, uint32_t *v)
+{
+    uint32_t x = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (*at >= end) return -1;
+        uint8_t b = p[(*at)++];
+        x |= (uint32_t)(b & 0x7fu) << (7 * k);
+        if (!(b & 0x80u)) { *v = x; return 0; }
+    }
+    return -1;
 }
 
 /* Returns 0, -1 for bad parameters or an alphabet too large, -2 if the
@@ -97,12 +137,18 @@ int32_t oracle_rans_encode(const int32_t *sym, int64_t n, uint32_t L, uint32_t B
     for (uint32_t s = 0, acc = 0; s < R; ++s) { cum[s] = acc; acc += f[s]; }
     uint32_t blocks = n ? (uint32_t)(((uint64_t)n + B - 1) / B) : 0;
     uint8_t *p = out;
-    put32(p, RANS_MAGIC); put32(p + 4, 1); put64(p + 8, (uint64_t)n);
+    size_t T = 0;
+    for (uint32_t s = 0, prev = (uint32_t)-1; s < R; ++s) {
+        if (!f[s]) continue;
+        T += put_varint(p + 40 + T, s - prev - 1);
+        T += put_varint(p + 40 + T, f[s] - 1);
+        prev = s;
+    }
+    put32(p, RANS_MAGIC); put32(p + 4, 2); put64(p + 8, (uint64_t)n);
     put32(p + 16, (uint32_t)lo); put32(p + 20, R); put32(p + 24, L); put32(p + 28, B);
-    put32(p + 32, blocks); put32(p + 36, 0);
-    p += 40;
-    for (uint32_t s = 0; s < R; ++s) put32(p + 4 * (size_t)s, f[s]);
-    p += 4 * (size_t)R;
+    put32(p + 32, blocks); put32(p + 36, (uint32_t)T);
+    while (T % 4) p[40 + T++] = 0;
+    p += 40 + T;
     uint8_t *starts = p;
     p += 4 * (size_t)(blocks + 1);
     uint8_t *states = p;
@@ -146,30 +192,41 @@ int32_t oracle_rans_encode(const int32_t *sym, int64_t n, uint32_t L, uint32_t B
 /* Returns 0, or -1 for a malformed stream or too small an output. */
 int32_t oracle_rans_decode(const uint8_t *in, size_t size, int32_t *out, int64_t cap, int64_t *n_out)
 {
-    if (size < 40 || get32(in) != RANS_MAGIC || get32(in + 4) != 1) return -1;
+    if (size < 40 || get32(in) != RANS_MAGIC || get32(in + 4) != 2) return -1;
     uint64_t n = get64(in + 8);
     int32_t lo = (int32_t)get32(in + 16);
     uint32_t R = get32(in + 20), L = get32(in + 24), B = get32(in + 28), blocks = get32(in + 32);
+    uint32_t T = get32(in + 36);
     *n_out = (int64_t)n;
     if (L < 1 || L > 16 || B < RANS_LANES || B % RANS_LANES || (int64_t)n > cap) return -1;
-    if (blocks != (n ? (uint32_t)((n + B - 1) / B) : 0)) return -1;
-    size_t head = 40 + 4 * (size_t)R + 4 * (size_t)(blocks + 1) + 4 * RANS_LANES * (size_t)blocks;
+    if (blocks != (n ? (uint32_t)((n + B - 1) / B) : 0) || R > (1u << 20) || T > table_bound(R)) return -1;
+    size_t T4 = ((size_t)T + 3) & ~(size_t)3;
+    size_t head = 40 + T4 + 4 * (size_t)(blocks + 1) + 4 * RANS_LANES * (size_t)blocks;
     if (size < head) return -1;
-    const uint8_t *fp = in + 40, *starts = fp + 4 * (size_t)R, *states = starts + 4 * (size_t)(blocks + 1);
+    const uint8_t *starts = in + 40 + T4, *states = starts + 4 * (size_t)(blocks + 1);
     const uint8_t *words = in + head;
     size_t n_words = (size - head) / 2;
     uint32_t M = 1u << L;
     uint32_t *f = (uint32_t *)malloc(4 * (size_t)(R ? R : 1));
     uint32_t *cum = (uint32_t *)malloc(4 * (size_t)(R ? R : 1));
     uint32_t *slot_sym = (uint32_t *)malloc(4 * (size_t)M);
+    /* the table: (run of absent symbols, f - 1) pairs using exactly T bytes */
+    int32_t bad = 0;
+    memset(f, 0, 4 * (size_t)(R ? R : 1));
+    for (size_t at = 40, end = 40 + (size_t)T, s = 0; at < end && !bad;) {
+        uint32_t gap, fm1;
+        if (get_varint(in, end, &at, &gap) || get_varint(in, end, &at, &fm1)) { bad = 1; break; }
+        s += gap;
+        if (s >= R || fm1 >= M) { bad = 1; break; }
+        f[s++] = fm1 + 1;
+    }
     uint64_t acc = 0;
     for (uint32_t s = 0; s < R; ++s) {
-        f[s] = get32(fp + 4 * (size_t)s);
         cum[s] = (uint32_t)acc;
         for (uint32_t q = 0; q < f[s] && acc + q < M; ++q) slot_sym[acc + q] = s;
         acc += f[s];
     }
-    int32_t st = (n && acc != M) ? -1 : 0;
+    int32_t st = (bad || (n && acc != M)) ? -1 : 0;
     for (uint32_t b = 0; b < blocks && !st; ++b) {
         int64_t i0 = (int64_t)b * B, i1 = i0 + B < (int64_t)n ? i0 + B : (int64_t)n;
         uint32_t x[RANS_LANES];

@@ -18,18 +18,37 @@ import oracle
 HEAD = 40
 
 
+def _varints(b):
+    """Unsigned LEB128 values of a byte string."""
+    out, v, sh = [], 0, 0
+    for x in b:
+        v |= (x & 0x7F) << sh
+        sh += 7
+        if not x & 0x80:
+            out.append(v)
+            v, sh = 0, 0
+    assert sh == 0
+    return out
+
+
 def _parse(stream):
-    magic, ver, n, lo, R, L, B, nb, _ = struct.unpack_from("<IIQiIIIII", stream, 0)
+    magic, ver, n, lo, R, L, B, nb, T = struct.unpack_from("<IIQiIIIII", stream, 0)
     p = HEAD
-    f = np.frombuffer(stream, np.uint32, R, p)
-    p += 4 * R
+    table = bytes(stream[p:p + T])
+    v = _varints(table)
+    f = np.zeros(R, np.uint32)
+    s = -1
+    for gap, fm1 in zip(v[0::2], v[1::2]):
+        s += gap + 1
+        f[s] = fm1 + 1
+    p += (T + 3) // 4 * 4
     starts = np.frombuffer(stream, np.uint32, nb + 1, p)
     p += 4 * (nb + 1)
     states = np.frombuffer(stream, np.uint32, 64 * nb, p).reshape(nb, 64)
     p += 256 * nb
     words = np.frombuffer(stream, np.uint16, (len(stream) - p) // 2, p)
     return dict(magic=magic, ver=ver, n=n, lo=lo, R=R, L=L, B=B, nb=nb, f=f, starts=starts,
-                states=states, words=words)
+                states=states, words=words, table=table)
 
 
 def test_one_symbol_per_coder_is_one_step_from_the_start_state():
@@ -38,8 +57,10 @@ def test_one_symbol_per_coder_is_one_step_from_the_start_state():
     # coder k codes only symbol k from x = 2^16: x' = (2^16 div f) 2^4 + (2^16 mod f) + cum
     st = _parse(oracle.rans_encode(np.array([0, 1, 1, 2]), 4, 64))
     assert (st["magic"], st["ver"], st["n"], st["lo"], st["R"], st["L"], st["B"], st["nb"]) == (
-        0x534E4152, 1, 4, 0, 3, 4, 64, 1)
+        0x534E4152, 2, 4, 0, 3, 4, 64, 1)
     np.testing.assert_array_equal(st["f"], [4, 8, 4])
+    # the table: (run of absent symbols, f - 1) per present symbol
+    assert st["table"] == bytes([0, 3, 0, 7, 0, 3])
     want = np.full(64, 1 << 16)
     want[:4] = [(65536 // 4) * 16 + 0, (65536 // 8) * 16 + 4, (65536 // 8) * 16 + 4,
                 (65536 // 4) * 16 + 12]
@@ -132,3 +153,37 @@ def test_rejects_too_many_symbols_and_corruption():
     s[-7] ^= 0x5A
     with pytest.raises(ValueError):
         oracle.rans_decode(bytes(s))
+
+
+def test_the_table_is_compressed():
+    # symbols 0 (3 times) and 1000 (once), L = 12: f = floor(c (4096 - 2) / 4) + 1 =
+    # (3071, 1024), the shortfall 1 to symbol 0: (3072, 1024); pairs (0, 3071) and
+    # (999, 1023): 3071 = 0x0BFF -> FF 17, 999 = 0x3E7 -> E7 07, 1023 -> FF 07
+    s = oracle.rans_encode(np.array([0, 0, 1000, 0]), 12, 64)
+    st = _parse(s)
+    assert st["R"] == 1001
+    assert st["table"] == bytes([0x00, 0xFF, 0x17, 0xE7, 0x07, 0xFF, 0x07])
+    assert list(np.nonzero(st["f"])[0]) == [0, 1000] and list(st["f"][[0, 1000]]) == [3072, 1024]
+    # 7 table bytes (padded to 8) against 4 R = 4004 raw
+    assert len(s) == HEAD + 8 + 4 * 2 + 256 + 2 * st["words"].size
+    # a dense alphabet: at most 2 + 3 bytes per present symbol, far below 4 bytes per entry
+    x = np.random.default_rng(4).integers(0, 16000, 200_000).astype(np.int32)
+    st = _parse(oracle.rans_encode(x, 16, 65536))
+    D = int((st["f"] > 0).sum())
+    assert len(st["table"]) <= 3 * D + 16 and len(st["table"]) < 0.8 * 4 * st["R"]
+    np.testing.assert_array_equal(st["f"] > 0, np.bincount(x - x.min(), minlength=st["R"]) > 0)
+
+
+def test_malformed_tables_are_refused():
+    x = np.random.default_rng(3).integers(0, 40, 5000).astype(np.int32)
+    s = bytearray(oracle.rans_encode(x, 12, 1024))
+    T = struct.unpack_from("<I", s, 36)[0]
+    for what, mutate in [("a 4-byte varint", lambda b: b.__setitem__(slice(HEAD, HEAD + 3), b"\x80\x80\x80")),
+                         ("a symbol past the range", lambda b: b.__setitem__(HEAD + T - 2, 0x7F)),
+                         ("a table length short of a pair", lambda b: struct.pack_into("<I", b, 36, T - 1)),
+                         ("a table length past the bound", lambda b: struct.pack_into("<I", b, 36, 10**6)),
+                         ("version 1", lambda b: struct.pack_into("<I", b, 4, 1))]:
+        b = bytearray(s)
+        mutate(b)
+        with pytest.raises(ValueError):
+            oracle.rans_decode(bytes(b))
