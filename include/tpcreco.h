@@ -394,10 +394,16 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
  *   interleaving blocks of B symbols; symbol 64 j + k of a block belongs to
  *                coder k (64 coders starting at 2^16); a block is coded
  *                backwards (j, then k, descending) onto one word stack;
- *   stream       little-endian: u32 magic 0x534E4152, u32 version 1, u64 n,
- *                i32 lo, u32 R, u32 L, u32 B, u32 blocks, u32 0; u32 f[R];
+ *   stream       little-endian: u32 magic 0x534E4152, u32 version 2, u64 n,
+ *                i32 lo, u32 R, u32 L, u32 B, u32 blocks, u32 T; the
+ *                frequency table in T bytes, zero-padded to a multiple of 4;
  *                u32 word_start[blocks + 1] (in words); u32 state[blocks][64];
- *                u16 words, each block's stack last pushed first.
+ *                u16 words, each block's stack last pushed first;
+ *   table        compressed, as the paper does with the decoding metadata:
+ *                for each present symbol in ascending order, the run of
+ *                absent symbols before it and f - 1, each an unsigned LEB128
+ *                varint (7 bits a byte, low group first, high bit on all but
+ *                the last byte; at most 3 bytes).
  * A decoder runs each block forwards: slot = x mod 2^L, s with
  * cum_s <= slot < cum_s + f_s, x <- f_s (x >> L) + slot - cum_s, and while
  * x < 2^16, x <- x 2^16 + next word. */
@@ -411,7 +417,8 @@ typedef struct tpc_rans_params {
 tpc_status tpc_rans_workspace_bytes(int64_t n, const tpc_rans_params *params, size_t *bytes);
 
 /* Largest stream for n symbols whose range is at most `range` (host call):
- * 40 + 4 range + 4 (blocks + 1) + 256 blocks + 2 n bytes. */
+ * 40 + (6 min(range, 2^16) rounded up to 4) + 4 (blocks + 1) + 256 blocks
+ * + 2 n bytes (no range when n = 0). */
 tpc_status tpc_rans_max_bytes(int64_t n, int64_t range, const tpc_rans_params *params, size_t *bytes);
 
 /* Codes symbols[0..n) (device int32, 0 <= n < 2^31) into out (device, 4-byte
@@ -463,8 +470,10 @@ tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *frames, const
  * bytes) into symbols (device int32, capacity `cap` < 2^31).  *n_out (device
  * int64) receives the stream's symbol count; *dev_status (device int32)
  * TPC_OK, TPC_ERR_CAPACITY (more symbols than cap; nothing written) or
- * TPC_ERR_ARG (malformed: bad header, frequencies not summing to 2^L, a
- * block not returning its coders to 2^16 or not using exactly its words;
+ * TPC_ERR_ARG (malformed: bad header or version, a table varint longer than 3
+ * bytes or cut off, an odd number of varints, a symbol past the range,
+ * frequencies not summing to 2^L, a block not returning its coders to 2^16
+ * or not using exactly its words;
  * the symbols written are then meaningless).  Every read is bounds-checked
  * against `size`.  ws: tpc_rans_decode_workspace_bytes() bytes. */
 tpc_status tpc_rans_decode_workspace_bytes(size_t *bytes);

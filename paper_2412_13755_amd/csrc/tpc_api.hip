@@ -472,7 +472,10 @@ tpc_status tpc_rans_max_bytes(int64_t n, int64_t range, const tpc_rans_params *p
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(TPC_ERR_ARG, "n outside 0..2^31-1");
     if (range < 0 || range > TPC_RANS_MAX_RANGE) return fail(TPC_ERR_ARG, "range outside 0..2^20");
     const int64_t nb = n > 0 ? (n + p->block_symbols - 1) / p->block_symbols : 0;
-    *bytes = (size_t)(40 + 4 * (n > 0 ? range : 0) + 4 * (nb + 1) + 4 * TPC_RANS_LANES * nb + 2 * n);
+    // the compressed table: at most 6 bytes for each of at most min(range, 2^16)
+    // present symbols, padded to 4
+    const int64_t d = n > 0 ? (range < 65536 ? range : 65536) : 0;
+    *bytes = (size_t)(40 + ((6 * d + 3) & ~(int64_t)3) + 4 * (nb + 1) + 4 * TPC_RANS_LANES * nb + 2 * n);
     return TPC_OK;
 }
 

@@ -13,6 +13,12 @@
 //  rs_freq      one workgroup: number of symbols present, most frequent
 //               symbol, scaled frequencies (integer arithmetic, exactly the
 //               stated rule), their exclusive scan
+//  rs_table     one workgroup: the frequency table compressed for the
+//               stream -- per present symbol, in ascending order, the run of
+//               absent symbols before it and f - 1 as LEB128 varints --
+//               by two scans (the present symbols' ranks, then the pairs'
+//               byte offsets); positions and bytes in the histogram's
+//               buffer, which no later kernel reads
 //  rs_encode    one wavefront per block of B symbols, lane k = coder k; the
 //               block is coded backwards round by round (symbols loaded eight
 //               rounds at a time, the coding table in LDS for ranges up to
@@ -22,7 +28,7 @@
 //               push them, into a per-block scratch stack
 //  rs_scan      exclusive scan of the blocks' word counts
 //  rd_*         the decoder (see below)
-//  rs_pack      the stream: header, frequency table, block word offsets,
+//  rs_pack      the stream: header, compressed frequency table, block word offsets,
 //               final coder states, every block's stack reversed; nothing is
 //               written and the status says TPC_ERR_CAPACITY when the
 //               stream (its exact size is reported) does not fit
@@ -44,8 +50,8 @@ struct RsArgs {
     const int64_t *n_dev;  // optional device symbol count
     int64_t n_cap;
     int32_t L, B, nb;
-    int32_t *mm;           // [0] min, [1] max, [2] status (device)
-    uint32_t *counts;      // [TPC_RANS_MAX_RANGE]
+    int32_t *mm;           // [0] min, [1] max, [2] status, [3] table bytes (device)
+    uint32_t *counts;      // [TPC_RANS_MAX_RANGE] histogram, then the table's positions and bytes
     uint4 *fc;             // [TPC_RANS_MAX_RANGE] (frequency, cumulative, reciprocal, shifts)
     uint32_t *wcount;      // [nb] words of each block
     uint32_t *wstart;      // [nb + 1]
@@ -85,6 +91,7 @@ __global__ void rs_init(RsBatch Bt) {
         A.mm[0] = 0x7fffffff;
         A.mm[1] = (int32_t)0x80000000;
         A.mm[2] = TPC_OK;
+        A.mm[3] = 0;
     }
 }
 
@@ -304,6 +311,66 @@ __global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsBatch Bt) {
     }
 }
 
+// Compressed frequency table.  The histogram's buffer holds, after the
+// frequencies are made, the present symbols in rank order (RS_TAB_POS) and
+// the table's bytes (RS_TAB_BYTES on).
+#define RS_TAB_BYTES 65536
+
+__device__ inline int varint_len(uint32_t v) { return v < 128u ? 1 : (v < 16384u ? 2 : 3); }
+
+__device__ inline int put_varint(uint8_t *p, uint32_t v) {
+    int k = 0;
+    while (v >= 0x80u) {
+        p[k++] = (uint8_t)(v | 0x80u);
+        v >>= 7;
+    }
+    p[k++] = (uint8_t)v;
+    return k;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_table(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    if (A.mm[2] != TPC_OK) return;
+    const int64_t R = rs_range(A);
+    uint32_t *pos = A.counts;                                   // [D <= 2^16]
+    uint8_t *tb = reinterpret_cast<uint8_t *>(A.counts + RS_TAB_BYTES);
+    // ranks of the present symbols
+    int D = 0;
+    for (int64_t c0 = 0; c0 < R; c0 += TPC_BLOCK) {
+        const int64_t s = c0 + threadIdx.x;
+        const int present = s < R && A.fc[s].x > 0u;
+        int tot;
+        const int ex = block_exclusive_scan(present, sh, &tot);
+        if (present) pos[D + ex] = (uint32_t)s;
+        D += tot;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // each pair's bytes at the exclusive scan of the pairs' lengths
+    int T = 0;
+    for (int c0 = 0; c0 < D; c0 += TPC_BLOCK) {
+        const int k = c0 + threadIdx.x;
+        uint32_t gap = 0, fm1 = 0;
+        int len = 0;
+        if (k < D) {
+            const uint32_t sk = pos[k];
+            gap = sk - (k > 0 ? pos[k - 1] + 1u : 0u);
+            fm1 = A.fc[sk].x - 1u;
+            len = varint_len(gap) + varint_len(fm1);
+        }
+        int tot;
+        const int ex = block_exclusive_scan(len, sh, &tot);
+        if (k < D) {
+            const int o = T + ex;
+            const int a = put_varint(tb + o, gap);
+            put_varint(tb + o + a, fm1);
+        }
+        T += tot;
+    }
+    if (threadIdx.x == 0) A.mm[3] = T;
+}
+
 // One block of symbols by one wavefront; T is the coding table (LDS or
 // global memory, a separate instantiation each so that the loads are not
 // generic).
@@ -400,8 +467,9 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsBatch Bt) {
     const RsArgs A = rs_job(Bt);
     const int st0 = A.mm[2];
     const int64_t R = st0 == TPC_OK ? rs_range(A) : 0;
+    const uint64_t T = st0 == TPC_OK ? (uint64_t)A.mm[3] : 0ull, T4 = (T + 3ull) & ~3ull;
     const uint64_t words = A.wstart[A.nb];
-    const uint64_t head = RS_HEAD + 4ull * R + 4ull * (A.nb + 1) + 4ull * RS_LANES * A.nb;
+    const uint64_t head = RS_HEAD + T4 + 4ull * (A.nb + 1) + 4ull * RS_LANES * A.nb;
     const uint64_t total = head + 2ull * words;
     const bool fits = st0 == TPC_OK && total <= A.cap;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -413,7 +481,7 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsBatch Bt) {
     const int G = gridDim.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         put32(o, RS_MAGIC);
-        put32(o + 4, 1u);
+        put32(o + 4, 2u);
         put32(o + 8, (uint32_t)((uint64_t)A.n & 0xffffffffu));
         put32(o + 12, (uint32_t)((uint64_t)A.n >> 32));
         put32(o + 16, (uint32_t)(A.n > 0 ? A.mm[0] : 0));
@@ -421,12 +489,18 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_pack(RsBatch Bt) {
         put32(o + 24, (uint32_t)A.L);
         put32(o + 28, (uint32_t)A.B);
         put32(o + 32, (uint32_t)A.nb);
-        put32(o + 36, 0u);
+        put32(o + 36, (uint32_t)T);
     }
-    // frequency table, word offsets, states: spread over the grid
+    // compressed table (zero-padded to 4 bytes), word offsets, states: spread
+    // over the grid
+    const uint32_t *tb = A.counts + RS_TAB_BYTES;
     uint32_t *ft = reinterpret_cast<uint32_t *>(o + RS_HEAD);
-    for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < R; s += (int64_t)G * TPC_BLOCK) ft[s] = A.fc[s].x;
-    uint32_t *ws = ft + R;
+    for (int64_t q = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; q < (int64_t)(T4 / 4); q += (int64_t)G * TPC_BLOCK) {
+        const uint32_t v = tb[q];
+        const int64_t keep = (int64_t)T - 4 * q;                 // bytes of this word inside the table
+        ft[q] = keep >= 4 ? v : (v & ((1u << (8 * keep)) - 1u));
+    }
+    uint32_t *ws = ft + T4 / 4;
     for (int64_t b = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; b <= A.nb; b += (int64_t)G * TPC_BLOCK) ws[b] = A.wstart[b];
     uint32_t *sts = ws + A.nb + 1;
     for (int64_t q = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; q < (int64_t)A.nb * RS_LANES; q += (int64_t)G * TPC_BLOCK)
@@ -454,18 +528,26 @@ struct RdArgs {
     int64_t cap;
     int64_t *n_out;
     int32_t *dev_status;
-    int64_t *hd;          // parsed header: n, lo, R, L, B, nb, word area offset, status
+    int64_t *hd;          // parsed header: n, lo, R, L, B, nb, word area offset, status, table bytes
+    uint32_t *freq;       // [TPC_RANS_MAX_RANGE] the table, expanded
+    uint32_t *vals;       // [RD_MAX_TABLE] the table's varints
     uint32_t *cum;        // [TPC_RANS_MAX_RANGE + 1]
     uint4 *slot;          // [2^16]
 };
 
 __device__ inline uint32_t get32(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
 
+// Largest compressed table: 6 bytes for each of at most min(R, 2^16)
+// present symbols.
+#define RD_MAX_TABLE (6 * 65536)
+__device__ inline int64_t table_bound(int64_t R) { return 6 * (R < 65536 ? R : 65536); }
+
 __global__ void rd_head(RdArgs A) {
     if (threadIdx.x != 0) return;
     int st = TPC_OK;
     int64_t n = 0, lo = 0, R = 0, L = 0, B = 0, nb = 0, head = 0;
-    if (A.size < RS_HEAD || get32(A.in) != RS_MAGIC || get32(A.in + 4) != 1u) {
+    int64_t T = 0;
+    if (A.size < RS_HEAD || get32(A.in) != RS_MAGIC || get32(A.in + 4) != 2u) {
         st = TPC_ERR_ARG;
     } else {
         n = (int64_t)((uint64_t)get32(A.in + 8) | ((uint64_t)get32(A.in + 12) << 32));
@@ -474,44 +556,96 @@ __global__ void rd_head(RdArgs A) {
         L = get32(A.in + 24);
         B = get32(A.in + 28);
         nb = get32(A.in + 32);
-        head = RS_HEAD + 4 * R + 4 * (nb + 1) + 4 * (int64_t)RS_LANES * nb;
+        T = get32(A.in + 36);
+        head = RS_HEAD + ((T + 3) & ~(int64_t)3) + 4 * (nb + 1) + 4 * (int64_t)RS_LANES * nb;
         if (n < 0 || n >= ((int64_t)1 << 31) || L < 1 || L > 16 || B < RS_LANES || B % RS_LANES ||
             R > TPC_RANS_MAX_RANGE || nb != (n > 0 ? (n + B - 1) / B : 0) || (n > 0 && R < 1) ||
-            (uint64_t)head > A.size)
+            T > table_bound(R) || (uint64_t)head > A.size)
             st = TPC_ERR_ARG;
         else if (n > A.cap)
             st = TPC_ERR_CAPACITY;
     }
     int64_t *h = A.hd;
-    h[0] = n; h[1] = lo; h[2] = R; h[3] = L; h[4] = B; h[5] = nb; h[6] = head; h[7] = st;
+    h[0] = n; h[1] = lo; h[2] = R; h[3] = L; h[4] = B; h[5] = nb; h[6] = head; h[7] = st; h[8] = T;
 }
 
+// The table: its varints (a byte ends one when its high bit is clear; a
+// varint is at most 3 bytes), then the (run, f - 1) pairs placed by a scan
+// of run + 1, then the cumulative frequencies.  Malformed tables (a varint
+// too long or cut off, an odd number of varints, a symbol past the range,
+// f above 2^L, frequencies not summing to 2^L) are refused.
 __global__ void __launch_bounds__(TPC_BLOCK) rd_table(RdArgs A) {
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     __shared__ int bad;
     if (A.hd[7] != TPC_OK) return;
-    const int64_t R = A.hd[2], L = A.hd[3];
+    const int64_t R = A.hd[2], L = A.hd[3], T = A.hd[8];
     const uint32_t M = 1u << L;
-    const uint32_t *f = reinterpret_cast<const uint32_t *>(A.in + RS_HEAD);
+    const uint8_t *tb = A.in + RS_HEAD;
     if (threadIdx.x == 0) bad = 0;
+    for (int64_t s = threadIdx.x; s < R; s += TPC_BLOCK) A.freq[s] = 0u;
+    // varints: the one a byte ends is the number of ends before it
+    int nv = 0;
+    for (int64_t c0 = 0; c0 < T; c0 += TPC_BLOCK) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint8_t bi = i < T ? tb[i] : (uint8_t)0x80;
+        const int end = i < T && !(bi & 0x80);
+        int tot;
+        const int ex = block_exclusive_scan(end, sh, &tot);
+        if (end) {
+            uint32_t v = bi;
+            // the continuation bytes before it (inside the table)
+            int k = 1;
+            while (k <= 3 && i - k >= 0 && (tb[i - k] & 0x80)) {
+                v = (v << 7) | (uint32_t)(tb[i - k] & 0x7f);
+                ++k;
+            }
+            if (k > 3) bad = 1;                               // 4 or more bytes
+            A.vals[nv + ex] = v;
+        }
+        nv += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && ((T > 0 && (tb[T - 1] & 0x80)) || (nv & 1))) bad = 1;
+    __threadfence_block();
+    __syncthreads();
+    // pairs: symbol k at (sum over pairs up to k of run + 1) - 1
+    const int np = nv / 2;
+    int64_t carry = 0;
+    for (int c0 = 0; c0 < np && !bad; c0 += TPC_BLOCK) {
+        const int k = c0 + threadIdx.x;
+        uint32_t step = 0, fm1 = 0;
+        if (k < np) {
+            const uint32_t run = A.vals[2 * k];
+            fm1 = A.vals[2 * k + 1];
+            step = run < (uint32_t)R ? run + 1u : (uint32_t)R + 1u;   // past the range either way
+        }
+        int tot;
+        const int ex = block_exclusive_scan((int)step, sh, &tot);
+        if (k < np) {
+            const int64_t s = carry + ex + (int64_t)step - 1;
+            if (s >= R || fm1 >= M) bad = 1;
+            else A.freq[s] = fm1 + 1u;
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    __threadfence_block();
     __syncthreads();
     // 64-bit running sum: a table summing past M (however it would wrap) is refused
-    uint64_t carry = 0;
+    uint64_t csum = 0;
     for (int64_t c0 = 0; c0 < R; c0 += TPC_BLOCK) {
         const int64_t s = c0 + threadIdx.x;
-        const uint32_t v = s < R ? f[s] : 0u;
-        if (v > M) bad = 1;
+        const uint32_t v = s < R ? A.freq[s] : 0u;
         int tot;
-        const int ex = block_exclusive_scan((int)(v > M ? 0 : v), sh, &tot);
-        const uint64_t c = carry + (uint64_t)ex;
+        const int ex = block_exclusive_scan((int)v, sh, &tot);
+        const uint64_t c = csum + (uint64_t)ex;
         if (s < R) A.cum[s] = c <= M ? (uint32_t)c : M;
-        carry += (uint64_t)tot;
-        if (carry > M && threadIdx.x == 0) bad = 1;
+        csum += (uint64_t)tot;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        A.cum[R] = carry <= M ? (uint32_t)carry : M;
-        if (bad || (A.hd[0] > 0 && carry != M)) A.hd[7] = TPC_ERR_ARG;
+        A.cum[R] = csum <= M ? (uint32_t)csum : M;
+        if (bad || (A.hd[0] > 0 && csum != M)) A.hd[7] = TPC_ERR_ARG;
     }
 }
 
@@ -519,7 +653,7 @@ __global__ void __launch_bounds__(TPC_BLOCK) rd_table(RdArgs A) {
 __global__ void __launch_bounds__(TPC_BLOCK) rd_slots(RdArgs A) {
     if (A.hd[7] != TPC_OK) return;
     const int64_t R = A.hd[2];
-    const uint32_t *f = reinterpret_cast<const uint32_t *>(A.in + RS_HEAD);
+    const uint32_t *f = A.freq;
     for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < R; s += (int64_t)gridDim.x * TPC_BLOCK) {
         const uint32_t c = A.cum[s], fs = f[s];
         for (uint32_t q = 0; q < fs && c + q < (1u << 16); ++q) A.slot[c + q] = make_uint4((uint32_t)s, fs, q, 0u);
@@ -532,7 +666,7 @@ __global__ void __launch_bounds__(TPC_BLOCK) rd_decode(RdArgs A) {
     const int64_t n = A.hd[0], lo = A.hd[1], R = A.hd[2], B = A.hd[4], nb = A.hd[5], head = A.hd[6];
     const int L = (int)A.hd[3];
     const uint32_t mask_M = (1u << L) - 1u;
-    const uint8_t *base = A.in + RS_HEAD + 4 * R;
+    const uint8_t *base = A.in + RS_HEAD + ((A.hd[8] + 3) & ~(int64_t)3);
     const uint32_t *ws = reinterpret_cast<const uint32_t *>(base);
     const uint32_t *sts = ws + nb + 1;
     const uint16_t *words = reinterpret_cast<const uint16_t *>(A.in + head);
@@ -646,6 +780,7 @@ hipError_t launch_rans_batch(int count, const RansJob *jobs, int32_t L, int32_t 
     hipLaunchKernelGGL(rs_clear, dim3(grid_over(TPC_RANS_MAX_RANGE, 1024), count), dim3(TPC_BLOCK), 0, st, Bt);
     hipLaunchKernelGGL(rs_hist, dim3(gs, count), dim3(TPC_BLOCK), 0, st, Bt);
     hipLaunchKernelGGL(rs_freq, one, dim3(RS_FREQ_THREADS), 0, st, Bt);
+    hipLaunchKernelGGL(rs_table, one, dim3(TPC_BLOCK), 0, st, Bt);
     const int eb = (nb_cap + TPC_BLOCK / TPC_WAVE - 1) / (TPC_BLOCK / TPC_WAVE);
     if (eb > 0) hipLaunchKernelGGL(rs_encode, dim3(eb, count), dim3(TPC_BLOCK), 0, st, Bt);
     hipLaunchKernelGGL(rs_scan, one, dim3(TPC_BLOCK), 0, st, Bt);
@@ -662,7 +797,9 @@ size_t rans_batch_ws_bytes(int count, const RansJob *jobs, int32_t B) {
 
 size_t rans_decode_ws_bytes() {
     WsCarver w(nullptr);
-    w.take<int64_t>(8);
+    w.take<int64_t>(9);
+    w.take<uint32_t>(TPC_RANS_MAX_RANGE);
+    w.take<uint32_t>(RD_MAX_TABLE);
     w.take<uint32_t>(TPC_RANS_MAX_RANGE + 1);
     w.take<uint4>(1 << 16);
     return (w.off + 255) & ~size_t(255);
@@ -678,7 +815,9 @@ hipError_t launch_rans_decode(const void *in, uint64_t size, int32_t *out, int64
     A.cap = cap;
     A.n_out = n_out;
     A.dev_status = dev_status;
-    A.hd = w.take<int64_t>(8);
+    A.hd = w.take<int64_t>(9);
+    A.freq = w.take<uint32_t>(TPC_RANS_MAX_RANGE);
+    A.vals = w.take<uint32_t>(RD_MAX_TABLE);
     A.cum = w.take<uint32_t>(TPC_RANS_MAX_RANGE + 1);
     A.slot = w.take<uint4>(1 << 16);
     hipLaunchKernelGGL(rd_head, dim3(1), dim3(TPC_WAVE), 0, st, A);

@@ -151,7 +151,18 @@ def test_decoder_refuses_bad_streams(torch_dev):
     assert _decode(s[:100], len(x))[2] == -1             # truncated tables
     bad = bytearray(s); bad[-101] ^= 0x40
     assert _decode(bytes(bad), len(x))[2] == -1          # a flipped word
-    bad = bytearray(s); bad[40:44] = (0xFFFFFFF0).to_bytes(4, "little")
+    # the compressed table: (run, f - 1) varints from byte 40, T bytes (header word 9)
+    T = int.from_bytes(s[36:40], "little")
+    assert 80 <= T <= 160                                # 40 symbols, f - 1 below 2^14
+    bad = bytearray(s); bad[41] = 0x7F
     assert _decode(bytes(bad), len(x))[2] == -1          # frequencies summing past 2^L
-    bad = bytearray(s); bad[40:44] = (1 << 31).to_bytes(4, "little"); bad[44:48] = (1 << 31).to_bytes(4, "little")
-    assert _decode(bytes(bad), len(x))[2] == -1          # a sum that wraps in 32 bits
+    bad = bytearray(s); bad[40:43] = b"\x80\x80\x80"
+    assert _decode(bytes(bad), len(x))[2] == -1          # a varint of 4 bytes or more
+    bad = bytearray(s); bad[40] = 0x7F
+    assert _decode(bytes(bad), len(x))[2] == -1          # a symbol past the range
+    bad = bytearray(s); bad[36:40] = (T - 1).to_bytes(4, "little")
+    assert _decode(bytes(bad), len(x))[2] == -1          # a table cut inside a pair
+    bad = bytearray(s); bad[36:40] = (10**6).to_bytes(4, "little")
+    assert _decode(bytes(bad), len(x))[2] == -1          # a table past its bound
+    bad = bytearray(s); bad[4] = 1
+    assert _decode(bytes(bad), len(x))[2] == -1          # version 1
