@@ -54,6 +54,32 @@ def _material(x0, mass, chi2_cut, gas):
     return Material(float(x0), float(mass), float(chi2_cut), float(rho), float(zoa), float(exc))
 
 
+def transfer(p, x, da, xt, bz, max_sin):
+    """State p at plane x rotated into the frame turned by da and carried to
+    plane xt of that frame: (status, state, Jacobian)."""
+    out = np.zeros(5)
+    J = np.zeros((5, 5))
+    st = lib().oracle_transfer(_p(np.ascontiguousarray(p, dtype=np.float64)), float(x), float(da), float(xt),
+                               float(bz), float(max_sin), _p(out), _p(J))
+    return int(st), out, J
+
+
+def merge(tracks: dict, frame, sector, n_sectors, *, bz, max_sin, cut):
+    """Mutual-best links between fitted segments of neighbouring sectors:
+    (next, prev, chi2) per track."""
+    x = np.ascontiguousarray(tracks["x"], dtype=np.float64)
+    par = np.ascontiguousarray(tracks["par"], dtype=np.float64)
+    cov = np.ascontiguousarray(tracks["cov"], dtype=np.float64)
+    st = np.ascontiguousarray(tracks["status"], dtype=np.int32)
+    fr = np.ascontiguousarray(frame, dtype=np.int32)
+    sc = np.ascontiguousarray(sector, dtype=np.int32)
+    T = x.size
+    nxt, prv, chi = np.empty(T, np.int32), np.empty(T, np.int32), np.empty(T)
+    lib().oracle_merge(T, _p(x), _p(par), _p(cov), _p(st), _p(fr), _p(sc), int(n_sectors), float(bz),
+                       float(max_sin), float(cut), _p(nxt), _p(prv), _p(chi))
+    return nxt, prv, chi
+
+
 def eloss(p, dx, mass, gas, direction=1.0):
     """Energy-loss map of the fit for one segment: (status, w', dw'/dt,
     dw'/dw, straggling variance of w)."""
@@ -111,6 +137,11 @@ def lib():
         L.oracle_fit_material.argtypes = [i32, P, P, P, P, P, P, ctypes.POINTER(FitParams),
                                            ctypes.POINTER(Material), P, P, P, P, P, P, P, P]
         L.oracle_fit_material.restype = None
+        d_ = ctypes.c_double
+        L.oracle_transfer.argtypes = [P, d_, d_, d_, d_, d_, P, P]
+        L.oracle_transfer.restype = i32
+        L.oracle_merge.argtypes = [i32, P, P, P, P, P, P, i32, d_, d_, d_, P, P, P]
+        L.oracle_merge.restype = None
         L.oracle_bethe.argtypes = [ctypes.c_double] * 4
         L.oracle_bethe.restype = ctypes.c_double
         L.oracle_eloss.argtypes = [P, ctypes.c_double, ctypes.POINTER(Material), ctypes.c_double, P]

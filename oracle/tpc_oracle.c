@@ -1241,3 +1241,139 @@ void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hi
                      hit_cov ? hit_cov + (size_t)offsets[i] * 15 : NULL);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Merging of track segments across sector edges (the survey's next row f1; */
+/* the paper gives no algorithm).  A particle that crosses from one sector   */
+/* into the next on the same side leaves a fitted segment in each; their     */
+/* states, carried to a common plane, agree within their covariances.        */
+/*  transfer  the state p at plane x of one sector's frame, rotated into the */
+/*            frame turned by da (a point (x, y) -> (x cos da + y sin da,     */
+/*            -x sin da + y cos da), phi -> phi - da with cos phi > 0 kept),  */
+/*            then carried along the helix to plane xt of that frame.  Its   */
+/*            Jacobian: the step's (at fixed distance) times the rotation's   */
+/*            (dy'/dy = cos da, ds'/ds = cos da + (s/c) sin da), plus the     */
+/*            move of the start plane with y (dx'/dy = sin da), which         */
+/*            shortens the step: minus the end state's derivative along x     */
+/*            (s/c, t/c, kappa, 0, 0) times sin da in the y column.           */
+/*  pairs     fitted segments (status 0) A, B of one frame in neighbouring    */
+/*            sectors of one side, A's innermost point at the smaller radius: */
+/*            chi2 = d^T (J C_A J^T + C_B)^-1 d, d = transfer(A to B's        */
+/*            innermost plane) - p_B.  (t and q/pT are unchanged by the       */
+/*            transfer, so a pair whose t or q/pT difference alone exceeds    */
+/*            the cut in its own variance cannot pass and is not computed.)   */
+/*  links     A's best outer partner is the B of smallest chi2 <= cut (the   */
+/*            smaller index on ties), B's best inner partner likewise; A and  */
+/*            B are linked when each is the other's best: next[A] = B,        */
+/*            prev[B] = A, chi2[A] = the pair's chi2; else -1 (chi2 0).       */
+/* ------------------------------------------------------------------------ */
+int32_t oracle_transfer(const double *p, double x, double da, double xt, double bz, double max_sin,
+                        double *pout, double *J)
+{
+    double y = p[0], s = p[2];
+    if (!(fabs(s) < 1.0)) return 2;
+    double c = sqrt(1.0 - s * s), ca = cos(da), sa = sin(da);
+    double x1 = x * ca + y * sa;
+    double q[5] = {-x * sa + y * ca, p[1], s * ca - c * sa, p[3], p[4]};
+    if (!(c * ca + s * sa > 0.0)) return 2;
+    double F[25];
+    if (oracle_propagate(q, xt - x1, bz, max_sin, pout, J ? F : NULL)) return 2;
+    if (J) {
+        double Rm[25] = {0};
+        for (int i = 0; i < 5; ++i) Rm[i * 5 + i] = 1.0;
+        Rm[0] = ca;
+        Rm[2 * 5 + 2] = ca + s / c * sa;
+        mat5_mul(F, Rm, J);
+        double s2 = pout[2], c2 = sqrt(1.0 - s2 * s2);
+        double v[5] = {s2 / c2, p[3] / c2, -C_LIGHT * bz * p[4], 0.0, 0.0};
+        for (int i = 0; i < 5; ++i) J[i * 5 + 0] -= v[i] * sa;
+    }
+    return 0;
+}
+
+#define PI_D 3.14159265358979323846
+
+static void unpack_cov(const double *co, double *C)
+{
+    for (int i = 0, k = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j, ++k) C[i * 5 + j] = C[j * 5 + i] = co[k];
+}
+
+static double sector_angle(int32_t sec, int32_t n_sectors)
+{
+    return n_sectors == 1 ? 0.0 : (double)(sec % 18) * (PI_D / 9.0) + PI_D / 18.0;
+}
+
+/* chi2 of carrying track a onto track b (INFINITY if it cannot be formed). */
+static double pair_chi2(int32_t a, int32_t b, const double *x, const double *par, const double *cov,
+                        const int32_t *sector, int32_t n_sectors, double bz, double max_sin)
+{
+    double da = sector_angle(sector[b], n_sectors) - sector_angle(sector[a], n_sectors);
+    if (da > PI_D) da -= 2.0 * PI_D;
+    if (da < -PI_D) da += 2.0 * PI_D;
+    double pa[5], J[25], Ca[25], Cb[25], T1[25], Jt[25], S[25], Si[25], d[5];
+    unpack_cov(cov + (size_t)a * 15, Ca);
+    unpack_cov(cov + (size_t)b * 15, Cb);
+    if (oracle_transfer(par + (size_t)a * 5, x[a], da, x[b], bz, max_sin, pa, J)) return INFINITY;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Jt[i * 5 + j] = J[j * 5 + i];
+    mat5_mul(J, Ca, T1);
+    mat5_mul(T1, Jt, S);
+    for (int i = 0; i < 25; ++i) S[i] += Cb[i];
+    if (inv5(S, Si)) return INFINITY;
+    for (int i = 0; i < 5; ++i) d[i] = pa[i] - par[(size_t)b * 5 + i];
+    double chi = 0.0;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) chi += d[i] * Si[i * 5 + j] * d[j];
+    return chi > 0.0 ? chi : INFINITY;
+}
+
+static int neighbours_of(int32_t sa, int32_t sb, int32_t n_sectors)
+{
+    if (n_sectors != 36 || sa / 18 != sb / 18) return 0;
+    int32_t d = ((sb % 18) - (sa % 18) + 18) % 18;
+    return d == 1 || d == 17;
+}
+
+void oracle_merge(int32_t n_tracks, const double *x, const double *par, const double *cov, const int32_t *status,
+                  const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double max_sin,
+                  double cut, int32_t *next, int32_t *prev, double *chi2)
+{
+    int32_t *bo = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_tracks ? n_tracks : 1));
+    int32_t *bi = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_tracks ? n_tracks : 1));
+    double *co = (double *)malloc(sizeof(double) * (size_t)(n_tracks ? n_tracks : 1));
+    double *ci = (double *)malloc(sizeof(double) * (size_t)(n_tracks ? n_tracks : 1));
+    for (int32_t i = 0; i < n_tracks; ++i) { bo[i] = bi[i] = -1; co[i] = ci[i] = INFINITY; }
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t a = 0; a < n_tracks; ++a) {
+        if (status[a]) continue;
+        double ra = hypot(x[a], par[(size_t)a * 5]);
+        for (int32_t b = 0; b < n_tracks; ++b) {
+            if (status[b] || frame[b] != frame[a] || !neighbours_of(sector[a], sector[b], n_sectors)) continue;
+            double rb = hypot(x[b], par[(size_t)b * 5]);
+            /* a is the inner segment of the pair */
+            const double *ca = cov + (size_t)a * 15, *cb = cov + (size_t)b * 15;
+            double dt = par[(size_t)a * 5 + 3] - par[(size_t)b * 5 + 3];
+            double dw = par[(size_t)a * 5 + 4] - par[(size_t)b * 5 + 4];
+            if (dt * dt > cut * (ca[9] + cb[9]) || dw * dw > cut * (ca[14] + cb[14])) continue;
+            if (ra < rb) {
+                double chi = pair_chi2(a, b, x, par, cov, sector, n_sectors, bz, max_sin);
+                if (chi <= cut && chi < co[a]) { co[a] = chi; bo[a] = b; }
+            } else if (rb < ra) {
+                double chi = pair_chi2(b, a, x, par, cov, sector, n_sectors, bz, max_sin);
+                if (chi <= cut && chi < ci[a]) { ci[a] = chi; bi[a] = b; }
+            }
+        }
+    }
+    for (int32_t a = 0; a < n_tracks; ++a) {
+        int32_t b = bo[a];
+        int linked = b >= 0 && bi[b] == a;
+        next[a] = linked ? b : -1;
+        chi2[a] = linked ? co[a] : 0.0;
+    }
+    for (int32_t b = 0; b < n_tracks; ++b) {
+        int32_t a = bi[b];
+        prev[b] = (a >= 0 && next[a] == b) ? a : -1;
+    }
+    free(bo); free(bi); free(co); free(ci);
+}

@@ -90,6 +90,16 @@ size_t oracle_rans_bound(int64_t n, uint32_t R, uint32_t B);
 int32_t oracle_rans_encode(const int32_t *sym, int64_t n, uint32_t L, uint32_t B, uint32_t max_range,
                            uint8_t *out, size_t cap, size_t *size);
 int32_t oracle_rans_decode(const uint8_t *in, size_t size, int32_t *out, int64_t cap, int64_t *n_out);
+/* Cross-sector merging of fitted segments (see tpc_oracle.c): the transfer
+ * of a state into a frame turned by da and on to plane xt (J may be NULL;
+ * returns 0 or 2), and the mutual-best links between segments of
+ * neighbouring sectors. */
+int32_t oracle_transfer(const double *p, double x, double da, double xt, double bz, double max_sin,
+                        double *pout, double *J);
+void oracle_merge(int32_t n_tracks, const double *x, const double *par, const double *cov, const int32_t *status,
+                  const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double max_sin,
+                  double cut, int32_t *next, int32_t *prev, double *chi2);
+
 void oracle_ctf_build(int32_t n_tracks, int32_t n_rows, int32_t n_sectors, int32_t n_segments,
                       const int32_t *row_offsets, const float *y, const float *z,
                       const int32_t *rows, const int32_t *status, const int32_t *frame,
