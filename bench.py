@@ -30,6 +30,8 @@ Extra legs, reported beside the headline value:
            rANS coding of all of them in one batch (scale 2^14, blocks of
            2^13, counts read on the device), eagerly and as a graph;
            clusters/s and bits per cluster
+  merge    the headline event's fitted segments linked across sector edges
+           (tpc_track_merge, chi2 cut 30): ms per call, links, segments/s
   material the fit with multiple scattering (radiation length 2870 cm, pion
            mass) and outlier rejection (chi2 > 30) on the headline seeds, and
            the same fit over rows followed by the smoother (tpc_kalman_smooth)
@@ -84,7 +86,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf,material,skip")
+    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf,material,skip,merge")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--stages-workload", type=int, default=1,
@@ -586,6 +588,38 @@ def _one_seed_coverage(fr, sd, min_clusters=20, frac=0.8):
     return float(np.mean(got >= frac * nbig)) if big.size else 0.0
 
 
+def leg_merge(args):
+    """tpc_track_merge on the headline event's fitted seeds, HIP events on the launch stream."""
+    import torch
+    from tpcsynth import make_config
+    fr = make_config(1)
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    ws = reco.workspace(dfr)
+    up, dn = reco.neighbours(dfr, ws=ws)
+    seeds = reco.seed(dfr, up, dn, ws=ws)
+    tr = reco.fit(dfr, seeds)
+    nxt, prv, chi = reco.merge(seeds, tr, MERGE_CUT)
+    torch.cuda.synchronize()
+    T = int(seeds.n_seeds.item())
+    stream = torch.cuda.current_stream()
+    evs = []
+    for _ in range(max(5, args.steps)):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        nxt, prv, chi = reco.merge(seeds, tr, MERGE_CUT)
+        e[1].record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    links = int((nxt[:T] >= 0).sum().item())
+    return {"workload": fr.meta["name"], "seeds": T, "chi2_cut": MERGE_CUT, "links": links, "ms": round(ms, 5),
+            "segments_per_s": round(T / ms * 1e3, 1)}
+
+
+MERGE_CUT = 30.0
+
+
 def leg_skip(args, with_cpu=True):
     """Row-skipping path on the headline frame with 10% pad-row inefficiency
     (neighbours across a missing row, seeding, the fit over the hits' rows)
@@ -759,6 +793,8 @@ def main():
         out["material"] = leg_material(args)
     if "skip" in legs:
         out["skip"] = leg_skip(args, not args.no_cpu)
+    if "merge" in legs:
+        out["merge"] = leg_merge(args)
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:

@@ -379,6 +379,27 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
                             int32_t *rows, tpc_tracks *tracks, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* Merging of fitted segments across sector edges (the continuation of track
+ * following across sectors, which the paper's reconstruction implies but
+ * does not describe).  A particle crossing from one sector into the next on
+ * the same side leaves a fitted segment in each.  For segments A, B of one
+ * frame in neighbouring sectors of one side (36-sector geometry only),
+ * both with status TPC_FIT_OK, A's innermost point (x, y) at the smaller
+ * radius: A's state is rotated into B's frame (turned by the sectors' angle
+ * difference da: a point (x, y) -> (x cos da + y sin da, -x sin da + y cos
+ * da), phi -> phi - da, cos phi > 0 required) and carried along the helix
+ * to B's plane x; chi2 = d^T (J C_A J^T + C_B)^-1 d with d the state
+ * difference and J the transfer's Jacobian (in FP64).  A's best outer
+ * partner is the B of smallest chi2 <= chi2_cut (smaller index on ties), B's
+ * best inner partner likewise; when each is the other's best, next[A] = B,
+ * prev[B] = A and chi2[A] = the pair's chi2; otherwise -1 and 0.  Seeds must
+ * be ordered by (frame, sector), as tpc_ca_seed writes them.  tracks: as a
+ * fit writes them, one per seed.  next, prev, chi2: device [cap_seeds]
+ * (int32, int32, float); the first min(*n_seeds, cap_seeds) are written.
+ * chi2_cut > 0 and finite, else TPC_ERR_ARG. */
+tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *seeds, const tpc_tracks *tracks,
+                           float chi2_cut, int32_t *next, int32_t *prev, float *chi2, void *stream);
+
 /* Entropy coding of a time frame's integer arrays (Sec. 4.3: every flat
  * integer array is coded on its own with range asymmetric numeral systems,
  * the symbol distribution counted for each frame, several coders

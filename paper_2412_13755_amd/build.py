@@ -31,6 +31,7 @@ SOURCES = {
     "tpc_rans.hip": [],
     "tpc_ctf.hip": [],
     "tpc_fit_ms.hip": [],
+    "tpc_merge.hip": [],
     "tpc_nb_skip.hip": ["-ffp-contract=off"],
 }
 

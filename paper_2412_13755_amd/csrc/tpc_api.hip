@@ -12,6 +12,7 @@
 #include "tpc_internal.hpp"
 #include "tpc_fit_ms.hpp"
 #include "tpc_nb_skip.hpp"
+#include "tpc_merge.hpp"
 #include "tpc_rans_dec.hpp"
 
 namespace {
@@ -422,6 +423,20 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *fr, const 
     hipError_t e = launch_follow(ctx, fr, sd, (double)prm->gate_chi2, prm->max_miss, rows, tr, ws,
                                  (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "follow kernels");
+}
+
+tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr, float chi2_cut,
+                           int32_t *next, int32_t *prev, float *chi2, void *stream) {
+    g_err[0] = 0;
+    if (!ctx) return fail(TPC_ERR_ARG, "null context");
+    tpc_status s = check_seeds_for_fit(sd);
+    if (s) return s;
+    if ((s = check_tracks(sd, tr))) return s;
+    if (!(chi2_cut > 0.f) || !isfinite(chi2_cut)) return fail(TPC_ERR_ARG, "chi2_cut must be finite and > 0");
+    if (sd->cap_seeds > 0 && (!next || !prev || !chi2)) return fail(TPC_ERR_ARG, "null merge outputs");
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_merge(ctx, sd, tr, (double)chi2_cut, next, prev, chi2, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "merge kernels");
 }
 
 tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,

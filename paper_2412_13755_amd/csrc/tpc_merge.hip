@@ -1,0 +1,245 @@
+// Merging of fitted track segments across sector edges (gfx950).  A particle
+// that crosses from one sector into the next on the same side leaves a
+// fitted segment in each; carried to a common plane, their states agree
+// within their covariances.
+//
+//  mg_best         thread per segment: over the segments of the two
+//                  neighbouring sectors of its (frame, side) -- a contiguous
+//                  seed range each, found by binary search, since seeds are
+//                  ordered by first cluster and clusters by (frame, sector,
+//                  row) -- its best outer partner (its innermost point at
+//                  the smaller radius) and best inner partner: smallest chi2
+//                  <= cut, smaller index on ties.  Pairs whose tan(lambda) or
+//                  q/pT difference alone exceeds the cut in its own variance
+//                  are dropped first (both are unchanged by the transfer, so
+//                  such a pair cannot pass); the survivors of each chunk of
+//                  64 candidates go to the lane's own LDS column and only
+//                  they are transferred.  FP64 throughout.
+//  mg_link_next    next[a] = b when a's best outer partner b has a as its
+//                  best inner partner (else -1, chi2 0)
+//  mg_link_prev    prev[b] = a when next[a] = b
+//
+// The transfer: a state at plane x of the inner segment's frame is rotated
+// into the outer segment's frame (turned by da: a point (x, y) ->
+// (x cos da + y sin da, -x sin da + y cos da), phi -> phi - da, cos phi > 0
+// kept) and carried along the helix to the outer segment's innermost plane;
+// its Jacobian is the step's (at fixed distance) times the rotation's, plus
+// the move of the start plane with y, which shortens the step.
+#include "tpc_fit_math.hpp"
+#include "tpc_merge.hpp"
+
+namespace {
+
+struct MgArgs {
+    const float *x, *par, *cov;
+    const int32_t *status, *frame, *sector, *n_seeds;
+    int32_t cap, n_sectors;
+    double kbz, cut;
+    float max_sin;
+    int32_t *next, *prev;
+    float *chi2;
+};
+
+__device__ inline int mg_count(const MgArgs &A) {
+    const int n = *A.n_seeds;
+    return n < 0 ? 0 : (n < A.cap ? n : A.cap);
+}
+
+__device__ inline int64_t mg_key(const MgArgs &A, int i) {
+    return (int64_t)A.frame[i] * A.n_sectors + A.sector[i];
+}
+
+// First seed index in [0, T) whose key is >= k.
+__device__ inline int mg_lower(const MgArgs &A, int T, int64_t k) {
+    int lo = 0, hi = T;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (mg_key(A, mid) < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline double sector_angle(int sec, int n_sectors) {
+    const double pi = 3.14159265358979323846;
+    return n_sectors == 1 ? 0.0 : (double)(sec % 18) * (pi / 9.0) + pi / 18.0;
+}
+
+// chi2 of carrying segment a onto segment b (INFINITY if it cannot be formed).
+__device__ double pair_chi2(const MgArgs &A, int a, int b) {
+    const double pi = 3.14159265358979323846;
+    double da = sector_angle(A.sector[b], A.n_sectors) - sector_angle(A.sector[a], A.n_sectors);
+    if (da > pi) da -= 2.0 * pi;
+    if (da < -pi) da += 2.0 * pi;
+    const float *pa = A.par + (size_t)a * 5, *pb = A.par + (size_t)b * 5;
+    const double x = (double)A.x[a], y = (double)pa[0], s = (double)pa[2], t = (double)pa[3], w = (double)pa[4];
+    if (!(fabs(s) < 1.0)) return INFINITY;
+    const double c = sqrt(1.0 - s * s), ca = cos(da), sa = sin(da);
+    if (!(c * ca + s * sa > 0.0)) return INFINITY;
+    const double x1 = x * ca + y * sa;
+    double q[5] = {-x * sa + y * ca, (double)pa[1], s * ca - c * sa, t, w};
+    StepJac F;
+    if (!helix_step<double, double>(q, (double)A.x[b] - x1, A.kbz, A.max_sin, F)) return INFINITY;
+    // J = F R - v e_0^T sin(da), R = diag(ca, 1, ca + (s/c) sa, 1, 1), v = (s2/c2, t/c2, kappa, 0, 0)
+    const double r22 = ca + s / c * sa;
+    const double s2 = q[2], c2 = sqrt(1.0 - s2 * s2), kap = A.kbz * w;
+    double J[3][5];
+    J[0][0] = ca - sa * s2 / c2; J[0][1] = 0.0; J[0][2] = F.f02 * r22; J[0][3] = 0.0;   J[0][4] = F.f04;
+    J[1][0] = -sa * t / c2;      J[1][1] = 1.0; J[1][2] = F.f12 * r22; J[1][3] = F.f13; J[1][4] = F.f14;
+    J[2][0] = -sa * kap;         J[2][1] = 0.0; J[2][2] = r22;         J[2][3] = 0.0;   J[2][4] = F.f24;
+    double Ca[5][5], S[5][5];
+    const float *ca_ = A.cov + (size_t)a * 15, *cb_ = A.cov + (size_t)b * 15;
+    for (int i = 0, k = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j, ++k) {
+            Ca[i][j] = Ca[j][i] = (double)ca_[k];
+            S[i][j] = S[j][i] = (double)cb_[k];
+        }
+    // S += J Ca J^T, with rows 3 and 4 of J those of the identity
+    double JC[5][5];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) {
+            double acc = 0.0;
+            if (i < 3)
+                for (int k = 0; k < 5; ++k) acc += J[i][k] * Ca[k][j];
+            else
+                acc = Ca[i][j];
+            JC[i][j] = acc;
+        }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double acc = 0.0;
+            if (j < 3)
+                for (int k = 0; k < 5; ++k) acc += JC[i][k] * J[j][k];
+            else
+                acc = JC[i][j];
+            S[i][j] += acc;
+            if (j != i) S[j][i] = S[i][j];
+        }
+    double d[5];
+    for (int i = 0; i < 5; ++i) d[i] = q[i] - (double)pb[i];
+    // chi2 = |L^-1 d|^2 with S = L L^T
+    double L[5][5], z[5], chi = 0.0;
+    for (int i = 0; i < 5; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double acc = S[i][j];
+            for (int k = 0; k < j; ++k) acc -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(acc > 0.0)) return INFINITY;
+                L[i][i] = sqrt(acc);
+            } else {
+                L[i][j] = acc / L[j][j];
+            }
+        }
+        double acc = d[i];
+        for (int k = 0; k < i; ++k) acc -= L[i][k] * z[k];
+        z[i] = acc / L[i][i];
+        chi += z[i] * z[i];
+    }
+    return chi > 0.0 ? chi : INFINITY;
+}
+
+// Candidates of one lane that pass the tan(lambda) / q/pT test, per chunk of
+// the neighbouring sector's segments: kept in the lane's own LDS column, so
+// that the transfer runs over short lists (a wavefront's iterations are the
+// longest list of its lanes) instead of every candidate of every lane.
+#define MG_CHUNK 64
+
+__global__ void __launch_bounds__(TPC_BLOCK) mg_best(MgArgs A) {
+    __shared__ int cand[MG_CHUNK][TPC_BLOCK];
+    const int T = mg_count(A);
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+        int bo = -1, bi = -1;
+        double co = INFINITY, ci_ = INFINITY;
+        if (A.status[i] == 0 && A.n_sectors == 36) {
+            const float *pi_ = A.par + (size_t)i * 5, *ci = A.cov + (size_t)i * 15;
+            const double ri = hypot((double)A.x[i], (double)pi_[0]);
+            const double ti = (double)pi_[3], wi = (double)pi_[4], vti = (double)ci[9], vwi = (double)ci[14];
+            const int sec = A.sector[i], side = sec / 18, s18 = sec % 18;
+            for (int e = 0; e < 2; ++e) {
+                const int sn = side * 18 + (e == 0 ? (s18 + 1) % 18 : (s18 + 17) % 18);
+                const int64_t key = (int64_t)A.frame[i] * A.n_sectors + sn;
+                const int j0 = mg_lower(A, T, key), j1 = mg_lower(A, T, key + 1);
+                for (int c0 = j0; c0 < j1; c0 += MG_CHUNK) {
+                    const int c1 = c0 + MG_CHUNK < j1 ? c0 + MG_CHUNK : j1;
+                    int n = 0;
+                    for (int j = c0; j < c1; ++j) {
+                        if (A.status[j] != 0) continue;
+                        const float *pj = A.par + (size_t)j * 5, *cj = A.cov + (size_t)j * 15;
+                        const double dt = ti - (double)pj[3], dw = wi - (double)pj[4];
+                        if (dt * dt > A.cut * (vti + (double)cj[9]) || dw * dw > A.cut * (vwi + (double)cj[14]))
+                            continue;
+                        cand[n++][threadIdx.x] = j;
+                    }
+                    for (int k = 0; k < n; ++k) {
+                        const int j = cand[k][threadIdx.x];
+                        const double rj = hypot((double)A.x[j], (double)A.par[(size_t)j * 5]);
+                        if (ri < rj) {                        // j outside: an outer partner
+                            const double chi = pair_chi2(A, i, j);
+                            if (chi <= A.cut && (chi < co || (chi == co && j < bo))) {
+                                co = chi;
+                                bo = j;
+                            }
+                        } else if (rj < ri) {                 // an inner partner
+                            const double chi = pair_chi2(A, j, i);
+                            if (chi <= A.cut && (chi < ci_ || (chi == ci_ && j < bi))) {
+                                ci_ = chi;
+                                bi = j;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        A.next[i] = bo;
+        A.chi2[i] = bo >= 0 ? (float)co : 0.f;
+        A.prev[i] = bi;
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) mg_link_next(MgArgs A) {
+    const int T = mg_count(A);
+    for (int a = blockIdx.x * TPC_BLOCK + threadIdx.x; a < T; a += gridDim.x * TPC_BLOCK) {
+        const int b = A.next[a];
+        const bool linked = b >= 0 && b < T && A.prev[b] == a;
+        if (!linked) {
+            A.next[a] = -1;
+            A.chi2[a] = 0.f;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) mg_link_prev(MgArgs A) {
+    const int T = mg_count(A);
+    for (int b = blockIdx.x * TPC_BLOCK + threadIdx.x; b < T; b += gridDim.x * TPC_BLOCK) {
+        const int a = A.prev[b];
+        if (!(a >= 0 && a < T && A.next[a] == b)) A.prev[b] = -1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr, double cut,
+                        int32_t *next, int32_t *prev, float *chi2, hipStream_t st) {
+    MgArgs A;
+    A.x = tr->x;
+    A.par = tr->par;
+    A.cov = tr->cov;
+    A.status = tr->status;
+    A.frame = sd->frame;
+    A.sector = sd->sector;
+    A.n_seeds = sd->n_seeds;
+    A.cap = sd->cap_seeds;
+    A.n_sectors = ctx->cfg.n_sectors;
+    A.kbz = -0.00299792458 * (double)ctx->cfg.bz;
+    A.cut = cut;
+    A.max_sin = ctx->cfg.max_sin;
+    A.next = next;
+    A.prev = prev;
+    A.chi2 = chi2;
+    int g = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL(mg_best, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(mg_link_next, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(mg_link_prev, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    return hipGetLastError();
+}

@@ -28,7 +28,7 @@ def test_header_declares_the_path():
     names = declared_functions()
     for n in ("tpc_create", "tpc_destroy", "tpc_workspace_bytes", "tpc_neighbours", "tpc_ca_seed",
               "tpc_kalman_fit", "tpc_ckpt_bytes", "tpc_chi2_sum", "tpc_fit_adjoint",
-              "tpc_track_follow", "tpc_rans_encode", "tpc_rans_workspace_bytes",
+              "tpc_track_follow", "tpc_track_merge", "tpc_rans_encode", "tpc_rans_workspace_bytes",
               "tpc_rans_max_bytes", "tpc_ctf_build", "tpc_rans_encode_batch",
               "tpc_rans_batch_workspace_bytes", "tpc_kalman_fit_material", "tpc_rans_decode",
               "tpc_rans_decode_workspace_bytes", "tpc_neighbours_skip", "tpc_kalman_fit_rows",
