@@ -9,10 +9,12 @@
 //                  ordered by first cluster and clusters by (frame, sector,
 //                  row) -- its best outer partner (its innermost point at
 //                  the smaller radius) and best inner partner: smallest chi2
-//                  <= cut, smaller index on ties.  Pairs whose tan(lambda) or
-//                  q/pT difference alone exceeds the cut in its own variance
-//                  are dropped first (both are unchanged by the transfer, so
-//                  such a pair cannot pass); the survivors of each chunk of
+//                  <= cut, smaller index on ties.  Pairs whose (tan(lambda),
+//                  q/pT) difference alone has a chi2 above the cut are
+//                  dropped first (both are unchanged by the transfer, so
+//                  their covariance block is the sum of the two segments',
+//                  and a sub-vector's chi2 never exceeds the full one: such a
+//                  pair cannot pass); the survivors of each chunk of
 //                  64 candidates go to the lane's own LDS column and only
 //                  they are transferred.  FP64 throughout.
 //  mg_link_next    next[a] = b when a's best outer partner b has a as its
@@ -65,16 +67,22 @@ __device__ inline double sector_angle(int sec, int n_sectors) {
     return n_sectors == 1 ? 0.0 : (double)(sec % 18) * (pi / 9.0) + pi / 18.0;
 }
 
-// chi2 of carrying segment a onto segment b (INFINITY if it cannot be formed).
-__device__ double pair_chi2(const MgArgs &A, int a, int b) {
+// The angle that turns sector a's frame into sector b's, wrapped to (-pi, pi].
+__device__ inline double turn_angle(int sa, int sb, int n_sectors) {
     const double pi = 3.14159265358979323846;
-    double da = sector_angle(A.sector[b], A.n_sectors) - sector_angle(A.sector[a], A.n_sectors);
+    double da = sector_angle(sb, n_sectors) - sector_angle(sa, n_sectors);
     if (da > pi) da -= 2.0 * pi;
     if (da < -pi) da += 2.0 * pi;
+    return da;
+}
+
+// chi2 of carrying segment a onto segment b (INFINITY if it cannot be
+// formed); ca, sa: cos and sin of the turn from a's sector to b's.
+__device__ double pair_chi2(const MgArgs &A, int a, int b, double ca, double sa) {
     const float *pa = A.par + (size_t)a * 5, *pb = A.par + (size_t)b * 5;
     const double x = (double)A.x[a], y = (double)pa[0], s = (double)pa[2], t = (double)pa[3], w = (double)pa[4];
     if (!(fabs(s) < 1.0)) return INFINITY;
-    const double c = sqrt(1.0 - s * s), ca = cos(da), sa = sin(da);
+    const double c = sqrt(1.0 - s * s);
     if (!(c * ca + s * sa > 0.0)) return INFINITY;
     const double x1 = x * ca + y * sa;
     double q[5] = {-x * sa + y * ca, (double)pa[1], s * ca - c * sa, t, w};
@@ -154,19 +162,31 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_best(MgArgs A) {
             const float *pi_ = A.par + (size_t)i * 5, *ci = A.cov + (size_t)i * 15;
             const double ri = hypot((double)A.x[i], (double)pi_[0]);
             const double ti = (double)pi_[3], wi = (double)pi_[4], vti = (double)ci[9], vwi = (double)ci[14];
+            const double cti = (double)ci[13];
             const int sec = A.sector[i], side = sec / 18, s18 = sec % 18;
             for (int e = 0; e < 2; ++e) {
                 const int sn = side * 18 + (e == 0 ? (s18 + 1) % 18 : (s18 + 17) % 18);
                 const int64_t key = (int64_t)A.frame[i] * A.n_sectors + sn;
                 const int j0 = mg_lower(A, T, key), j1 = mg_lower(A, T, key + 1);
+                // the turn from this sector to the neighbour's (outer partners) and back
+                const double da = turn_angle(sec, sn, A.n_sectors);
+                const double cda = cos(da), sda = sin(da);
+                const double dback = turn_angle(sn, sec, A.n_sectors);
+                const double cdb = cos(dback), sdb = sin(dback);
                 for (int c0 = j0; c0 < j1; c0 += MG_CHUNK) {
                     const int c1 = c0 + MG_CHUNK < j1 ? c0 + MG_CHUNK : j1;
                     int n = 0;
                     for (int j = c0; j < c1; ++j) {
                         if (A.status[j] != 0) continue;
                         const float *pj = A.par + (size_t)j * 5, *cj = A.cov + (size_t)j * 15;
+                        // the (t, w) block of the pair's covariance is the sum of the
+                        // two (the transfer leaves t and w alone), and its chi2
+                        // never exceeds the full one
                         const double dt = ti - (double)pj[3], dw = wi - (double)pj[4];
-                        if (dt * dt > A.cut * (vti + (double)cj[9]) || dw * dw > A.cut * (vwi + (double)cj[14]))
+                        const double s33 = vti + (double)cj[9], s44 = vwi + (double)cj[14];
+                        const double s43 = cti + (double)cj[13];
+                        const double det = s33 * s44 - s43 * s43;
+                        if (det > 0.0 && (s44 * dt * dt - 2.0 * s43 * dt * dw + s33 * dw * dw) > A.cut * det)
                             continue;
                         cand[n++][threadIdx.x] = j;
                     }
@@ -174,13 +194,13 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_best(MgArgs A) {
                         const int j = cand[k][threadIdx.x];
                         const double rj = hypot((double)A.x[j], (double)A.par[(size_t)j * 5]);
                         if (ri < rj) {                        // j outside: an outer partner
-                            const double chi = pair_chi2(A, i, j);
+                            const double chi = pair_chi2(A, i, j, cda, sda);
                             if (chi <= A.cut && (chi < co || (chi == co && j < bo))) {
                                 co = chi;
                                 bo = j;
                             }
                         } else if (rj < ri) {                 // an inner partner
-                            const double chi = pair_chi2(A, j, i);
+                            const double chi = pair_chi2(A, j, i, cdb, sdb);
                             if (chi <= A.cut && (chi < ci_ || (chi == ci_ && j < bi))) {
                                 ci_ = chi;
                                 bi = j;
