@@ -66,7 +66,8 @@ def transfer(p, x, da, xt, bz, max_sin):
 
 def merge(tracks: dict, frame, sector, n_sectors, *, bz, max_sin, cut):
     """Mutual-best links between fitted segments of neighbouring sectors:
-    (next, prev, chi2) per track."""
+    (next, prev, chi2, merged_par [T, 5], merged_cov [T, 15]) per track (the
+    linked pair combined at the outer segment's plane; zeros if unlinked)."""
     x = np.ascontiguousarray(tracks["x"], dtype=np.float64)
     par = np.ascontiguousarray(tracks["par"], dtype=np.float64)
     cov = np.ascontiguousarray(tracks["cov"], dtype=np.float64)
@@ -75,9 +76,10 @@ def merge(tracks: dict, frame, sector, n_sectors, *, bz, max_sin, cut):
     sc = np.ascontiguousarray(sector, dtype=np.int32)
     T = x.size
     nxt, prv, chi = np.empty(T, np.int32), np.empty(T, np.int32), np.empty(T)
+    mp, mc = np.zeros((max(T, 1), 5)), np.zeros((max(T, 1), 15))
     lib().oracle_merge(T, _p(x), _p(par), _p(cov), _p(st), _p(fr), _p(sc), int(n_sectors), float(bz),
-                       float(max_sin), float(cut), _p(nxt), _p(prv), _p(chi))
-    return nxt, prv, chi
+                       float(max_sin), float(cut), _p(nxt), _p(prv), _p(chi), _p(mp), _p(mc))
+    return nxt, prv, chi, mp[:T], mc[:T]
 
 
 def eloss(p, dx, mass, gas, direction=1.0):
@@ -140,7 +142,7 @@ def lib():
         d_ = ctypes.c_double
         L.oracle_transfer.argtypes = [P, d_, d_, d_, d_, d_, P, P]
         L.oracle_transfer.restype = i32
-        L.oracle_merge.argtypes = [i32, P, P, P, P, P, P, i32, d_, d_, d_, P, P, P]
+        L.oracle_merge.argtypes = [i32, P, P, P, P, P, P, i32, d_, d_, d_, P, P, P, P, P]
         L.oracle_merge.restype = None
         L.oracle_bethe.argtypes = [ctypes.c_double] * 4
         L.oracle_bethe.restype = ctypes.c_double

@@ -1266,6 +1266,12 @@ void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hi
 /*            smaller index on ties), B's best inner partner likewise; A and  */
 /*            B are linked when each is the other's best: next[A] = B,        */
 /*            prev[B] = A, chi2[A] = the pair's chi2; else -1 (chi2 0).       */
+/*  refit     for a linked A, the two segments combined at B's plane: A's     */
+/*            transferred state (covariance P = J C_A J^T) and B's, each      */
+/*            independent of the other, fused by x = p_A' + P S^-1 (p_B -     */
+/*            p_A'), C = P S^-1 C_B (= P - P S^-1 P), S = P + C_B -- the      */
+/*            joint fit of both segments' hits for the linearised problem    */
+/*            (zeros if unlinked).                                           */
 /* ------------------------------------------------------------------------ */
 int32_t oracle_transfer(const double *p, double x, double da, double xt, double bz, double max_sin,
                         double *pout, double *J)
@@ -1304,9 +1310,14 @@ static double sector_angle(int32_t sec, int32_t n_sectors)
     return n_sectors == 1 ? 0.0 : (double)(sec % 18) * (PI_D / 9.0) + PI_D / 18.0;
 }
 
-/* chi2 of carrying track a onto track b (INFINITY if it cannot be formed). */
-static double pair_chi2(int32_t a, int32_t b, const double *x, const double *par, const double *cov,
-                        const int32_t *sector, int32_t n_sectors, double bz, double max_sin)
+/* chi2 of carrying track a onto track b (INFINITY if it cannot be formed);
+ * with mp, mc non-null also the two combined at b's plane (the transferred
+ * state of a, covariance P = J C_a J^T, and b's: x = p_a' + P S^-1 (p_b -
+ * p_a'), C = P S^-1 C_b, which equals P - P S^-1 P but has no difference
+ * of large terms, symmetrised; S = P + C_b; packed). */
+static double pair_fuse(int32_t a, int32_t b, const double *x, const double *par, const double *cov,
+                        const int32_t *sector, int32_t n_sectors, double bz, double max_sin, double *mp,
+                        double *mc)
 {
     double da = sector_angle(sector[b], n_sectors) - sector_angle(sector[a], n_sectors);
     if (da > PI_D) da -= 2.0 * PI_D;
@@ -1315,17 +1326,42 @@ static double pair_chi2(int32_t a, int32_t b, const double *x, const double *par
     unpack_cov(cov + (size_t)a * 15, Ca);
     unpack_cov(cov + (size_t)b * 15, Cb);
     if (oracle_transfer(par + (size_t)a * 5, x[a], da, x[b], bz, max_sin, pa, J)) return INFINITY;
+    double P[25];
     for (int i = 0; i < 5; ++i)
         for (int j = 0; j < 5; ++j) Jt[i * 5 + j] = J[j * 5 + i];
     mat5_mul(J, Ca, T1);
-    mat5_mul(T1, Jt, S);
-    for (int i = 0; i < 25; ++i) S[i] += Cb[i];
+    mat5_mul(T1, Jt, P);
+    for (int i = 0; i < 25; ++i) S[i] = P[i] + Cb[i];
     if (inv5(S, Si)) return INFINITY;
     for (int i = 0; i < 5; ++i) d[i] = pa[i] - par[(size_t)b * 5 + i];
     double chi = 0.0;
     for (int i = 0; i < 5; ++i)
         for (int j = 0; j < 5; ++j) chi += d[i] * Si[i * 5 + j] * d[j];
+    if (mp && mc) {
+        double K[25], C[25];
+        mat5_mul(P, Si, K);                        /* K = P S^-1 */
+        for (int i = 0; i < 5; ++i) {
+            double acc = pa[i];
+            for (int j = 0; j < 5; ++j) acc -= K[i * 5 + j] * d[j];   /* d = p_a' - p_b */
+            mp[i] = acc;
+        }
+        /* C = P S^-1 C_b (= C_b S^-1 P), symmetrised: no difference of two
+         * large terms when one segment's covariance dwarfs the other's */
+        double SC[25], PSC[25], CSP[25];
+        mat5_mul(Si, Cb, SC);
+        mat5_mul(P, SC, PSC);
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j) CSP[i * 5 + j] = PSC[j * 5 + i];
+        for (int i = 0; i < 25; ++i) C[i] = 0.5 * (PSC[i] + CSP[i]);
+        pack_cov(C, mc);
+    }
     return chi > 0.0 ? chi : INFINITY;
+}
+
+static double pair_chi2(int32_t a, int32_t b, const double *x, const double *par, const double *cov,
+                        const int32_t *sector, int32_t n_sectors, double bz, double max_sin)
+{
+    return pair_fuse(a, b, x, par, cov, sector, n_sectors, bz, max_sin, NULL, NULL);
 }
 
 static int neighbours_of(int32_t sa, int32_t sb, int32_t n_sectors)
@@ -1337,7 +1373,7 @@ static int neighbours_of(int32_t sa, int32_t sb, int32_t n_sectors)
 
 void oracle_merge(int32_t n_tracks, const double *x, const double *par, const double *cov, const int32_t *status,
                   const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double max_sin,
-                  double cut, int32_t *next, int32_t *prev, double *chi2)
+                  double cut, int32_t *next, int32_t *prev, double *chi2, double *mpar, double *mcov)
 {
     int32_t *bo = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_tracks ? n_tracks : 1));
     int32_t *bi = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_tracks ? n_tracks : 1));
@@ -1375,5 +1411,13 @@ void oracle_merge(int32_t n_tracks, const double *x, const double *par, const do
         int32_t a = bi[b];
         prev[b] = (a >= 0 && next[a] == b) ? a : -1;
     }
+    if (mpar && mcov)
+        for (int32_t a = 0; a < n_tracks; ++a) {
+            double *mp = mpar + (size_t)a * 5, *mc = mcov + (size_t)a * 15;
+            for (int i = 0; i < 5; ++i) mp[i] = 0.0;
+            for (int i = 0; i < 15; ++i) mc[i] = 0.0;
+            if (next[a] >= 0)
+                pair_fuse(a, next[a], x, par, cov, sector, n_sectors, bz, max_sin, mp, mc);
+        }
     free(bo); free(bi); free(co); free(ci);
 }

@@ -98,7 +98,7 @@ int32_t oracle_transfer(const double *p, double x, double da, double xt, double 
                         double *pout, double *J);
 void oracle_merge(int32_t n_tracks, const double *x, const double *par, const double *cov, const int32_t *status,
                   const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double max_sin,
-                  double cut, int32_t *next, int32_t *prev, double *chi2);
+                  double cut, int32_t *next, int32_t *prev, double *chi2, double *mpar, double *mcov);
 
 void oracle_ctf_build(int32_t n_tracks, int32_t n_rows, int32_t n_sectors, int32_t n_segments,
                       const int32_t *row_offsets, const float *y, const float *z,

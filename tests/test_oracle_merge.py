@@ -12,7 +12,9 @@
   link between pure segments joins one particle; at least 88 % of the
   sector-edge junctions (a particle's outermost piece in one sector and
   its innermost in the next) are linked; links are mutual, chi2 <= cut,
-  and a single-sector frame has none.
+  and a single-sector frame has none; the two segments combined at the
+  outer one's plane have unit pulls against the truth there, no variance
+  above the outer segment's alone and a smaller q/pT variance.
 """
 import numpy as np
 import pytest
@@ -81,18 +83,18 @@ def event():
     up, dn = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
     sd = oracle.ca_seed(fr.row_offsets, up, dn, fr.n_sectors, fr.n_rows, MIN_HITS)
     o = oracle.fit(sd, fr.y, fr.z, fr.row_x, fr.n_rows, **FIT)
-    nxt, prv, chi = oracle.merge(o, sd["frame"], sd["sector"], fr.n_sectors, bz=BZ, max_sin=MS, cut=CUT)
+    nxt, prv, chi, mp, mc = oracle.merge(o, sd["frame"], sd["sector"], fr.n_sectors, bz=BZ, max_sin=MS, cut=CUT)
     off = sd["offsets"]
     tid = np.full(len(off) - 1, -1)
     for i in range(len(off) - 1):
         tt = fr.track_of[sd["hits"][off[i]:off[i + 1]]]
         if tt[0] >= 0 and (tt == tt[0]).all():
             tid[i] = tt[0]
-    return fr, sd, o, nxt, prv, chi, tid
+    return fr, sd, o, nxt, prv, chi, tid, mp, mc
 
 
 def test_links_are_mutual_and_within_the_cut(event):
-    fr, sd, o, nxt, prv, chi, tid = event
+    fr, sd, o, nxt, prv, chi, tid, mp, mc = event
     L = np.nonzero(nxt >= 0)[0]
     assert L.size > 1000
     np.testing.assert_array_equal(prv[nxt[L]], L)
@@ -105,7 +107,7 @@ def test_links_are_mutual_and_within_the_cut(event):
 
 
 def test_links_join_one_particle_with_chi2_of_five_dof(event):
-    fr, sd, o, nxt, prv, chi, tid = event
+    fr, sd, o, nxt, prv, chi, tid, mp, mc = event
     L = np.nonzero(nxt >= 0)[0]
     pure = (tid[L] >= 0) & (tid[nxt[L]] >= 0)
     assert pure.sum() > 1000
@@ -114,7 +116,7 @@ def test_links_join_one_particle_with_chi2_of_five_dof(event):
 
 
 def test_sector_edge_junctions_are_linked(event):
-    fr, sd, o, nxt, prv, chi, tid = event
+    fr, sd, o, nxt, prv, chi, tid, mp, mc = event
     ok = (o["status"] == 0) & (tid >= 0)
     r = np.hypot(o["x"], o["par"][:, 0])
     idx = np.nonzero(ok)[0]
@@ -137,10 +139,31 @@ def test_sector_edge_junctions_are_linked(event):
     assert linked / junctions >= 0.88, linked / junctions
 
 
+def test_combined_pairs_have_unit_pulls_and_gain_information(event):
+    # the fused state of a linked pure pair at the outer segment's innermost
+    # plane against the generator's truth at that cluster
+    fr, sd, o, nxt, prv, chi, tid, mp, mc = event
+    L = np.nonzero(nxt >= 0)[0]
+    L = L[(tid[L] >= 0) & (tid[nxt[L]] == tid[L])]
+    h = sd["hits"][sd["offsets"][nxt[L]]]
+    tru = np.stack([fr.y_true[h], fr.z_true[h], fr.s_true[h], fr.t_true[h], fr.w_true[h]], 1)
+    C = oracle.unpack_cov(mc[L])
+    var = np.einsum("tii->ti", C)
+    pulls = (mp[L] - tru) / np.sqrt(var)
+    width = np.quantile(np.abs(pulls), 0.683, axis=0)
+    assert len(L) > 1000
+    assert np.all(np.abs(width - 1.0) < 0.1), width
+    assert np.all(np.abs(np.median(pulls, 0)) < 0.1)
+    vb = np.einsum("tii->ti", oracle.unpack_cov(o["cov"][nxt[L]]))
+    assert np.all(var <= vb * (1 + 1e-9))
+    assert np.median(var[:, 4] / vb[:, 4]) < 0.9                # q/pT gains from the inner segment
+    assert not mp[nxt < 0].any() and not mc[nxt < 0].any()
+
+
 def test_single_sector_has_no_links():
     fr = make_config(0)
     up, dn = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
     sd = oracle.ca_seed(fr.row_offsets, up, dn, fr.n_sectors, fr.n_rows, MIN_HITS)
     o = oracle.fit(sd, fr.y, fr.z, fr.row_x, fr.n_rows, **FIT)
-    nxt, prv, chi = oracle.merge(o, sd["frame"], sd["sector"], 1, bz=BZ, max_sin=MS, cut=CUT)
+    nxt, prv, chi, _, _ = oracle.merge(o, sd["frame"], sd["sector"], 1, bz=BZ, max_sin=MS, cut=CUT)
     assert np.all(nxt == -1) and np.all(prv == -1)
