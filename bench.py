@@ -31,7 +31,8 @@ Extra legs, reported beside the headline value:
            2^13, counts read on the device), eagerly and as a graph;
            clusters/s and bits per cluster
   merge    the headline event's fitted segments linked across sector edges
-           (tpc_track_merge, chi2 cut 30): ms per call, links, segments/s
+           and each linked pair combined (tpc_track_merge, chi2 cut 30): ms
+           per call, links, segments/s
   material the fit with multiple scattering (radiation length 2870 cm, pion
            mass) and outlier rejection (chi2 > 30) on the headline seeds, and
            the same fit over rows followed by the smoother (tpc_kalman_smooth)
@@ -599,7 +600,7 @@ def leg_merge(args):
     up, dn = reco.neighbours(dfr, ws=ws)
     seeds = reco.seed(dfr, up, dn, ws=ws)
     tr = reco.fit(dfr, seeds)
-    nxt, prv, chi = reco.merge(seeds, tr, MERGE_CUT)
+    nxt, prv, chi, mp, mc = reco.merge(seeds, tr, MERGE_CUT)
     torch.cuda.synchronize()
     T = int(seeds.n_seeds.item())
     stream = torch.cuda.current_stream()
@@ -607,7 +608,7 @@ def leg_merge(args):
     for _ in range(max(5, args.steps)):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record(stream)
-        nxt, prv, chi = reco.merge(seeds, tr, MERGE_CUT)
+        nxt, prv, chi, mp, mc = reco.merge(seeds, tr, MERGE_CUT)
         e[1].record(stream)
         evs.append(e)
     torch.cuda.synchronize()

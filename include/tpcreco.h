@@ -396,9 +396,16 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
  * be ordered by (frame, sector), as tpc_ca_seed writes them.  tracks: as a
  * fit writes them, one per seed.  next, prev, chi2: device [cap_seeds]
  * (int32, int32, float); the first min(*n_seeds, cap_seeds) are written.
+ * merged_par [cap_seeds][5], merged_cov [cap_seeds][15] (device float, both
+ * or neither may be NULL): for a linked A the pair refitted as one at B's
+ * plane, in B's frame -- A's transferred state (covariance P = J C_A J^T)
+ * and B's, independent fits of disjoint hits, combined: x = p_A' +
+ * P S^-1 (p_B - p_A'), C = P S^-1 C_B, S = P + C_B (the joint fit of both
+ * segments' hits for the linearised problem); zeros where unlinked.
  * chi2_cut > 0 and finite, else TPC_ERR_ARG. */
 tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *seeds, const tpc_tracks *tracks,
-                           float chi2_cut, int32_t *next, int32_t *prev, float *chi2, void *stream);
+                           float chi2_cut, int32_t *next, int32_t *prev, float *chi2, float *merged_par,
+                           float *merged_cov, void *stream);
 
 /* Entropy coding of a time frame's integer arrays (Sec. 4.3: every flat
  * integer array is coded on its own with range asymmetric numeral systems,

@@ -18,7 +18,9 @@
 //                  64 candidates go to the lane's own LDS column and only
 //                  they are transferred.  FP64 throughout.
 //  mg_link_next    next[a] = b when a's best outer partner b has a as its
-//                  best inner partner (else -1, chi2 0)
+//                  best inner partner (else -1, chi2 0); optionally the pair
+//                  combined at b's plane (a's transferred state fused with
+//                  b's: the joint fit of both for the linearised problem)
 //  mg_link_prev    prev[b] = a when next[a] = b
 //
 // The transfer: a state at plane x of the inner segment's frame is rotated
@@ -40,6 +42,7 @@ struct MgArgs {
     float max_sin;
     int32_t *next, *prev;
     float *chi2;
+    float *mpar, *mcov;      // optional combined states of linked pairs
 };
 
 __device__ inline int mg_count(const MgArgs &A) {
@@ -77,8 +80,11 @@ __device__ inline double turn_angle(int sa, int sb, int n_sectors) {
 }
 
 // chi2 of carrying segment a onto segment b (INFINITY if it cannot be
-// formed); ca, sa: cos and sin of the turn from a's sector to b's.
-__device__ double pair_chi2(const MgArgs &A, int a, int b, double ca, double sa) {
+// formed); ca, sa: cos and sin of the turn from a's sector to b's.  With mp,
+// mc non-null also the two combined at b's plane: a's transferred state
+// (covariance P = J C_a J^T) and b's fused, x = p_a' + P S^-1 (p_b - p_a'),
+// C = P S^-1 C_b (= P - P S^-1 P), S = P + C_b (packed, in float).
+__device__ double pair_fuse(const MgArgs &A, int a, int b, double ca, double sa, float *mp, float *mc) {
     const float *pa = A.par + (size_t)a * 5, *pb = A.par + (size_t)b * 5;
     const double x = (double)A.x[a], y = (double)pa[0], s = (double)pa[2], t = (double)pa[3], w = (double)pa[4];
     if (!(fabs(s) < 1.0)) return INFINITY;
@@ -95,12 +101,12 @@ __device__ double pair_chi2(const MgArgs &A, int a, int b, double ca, double sa)
     J[0][0] = ca - sa * s2 / c2; J[0][1] = 0.0; J[0][2] = F.f02 * r22; J[0][3] = 0.0;   J[0][4] = F.f04;
     J[1][0] = -sa * t / c2;      J[1][1] = 1.0; J[1][2] = F.f12 * r22; J[1][3] = F.f13; J[1][4] = F.f14;
     J[2][0] = -sa * kap;         J[2][1] = 0.0; J[2][2] = r22;         J[2][3] = 0.0;   J[2][4] = F.f24;
-    double Ca[5][5], S[5][5];
+    double Ca[5][5], Cb[5][5], S[5][5], P[5][5];
     const float *ca_ = A.cov + (size_t)a * 15, *cb_ = A.cov + (size_t)b * 15;
     for (int i = 0, k = 0; i < 5; ++i)
         for (int j = 0; j <= i; ++j, ++k) {
             Ca[i][j] = Ca[j][i] = (double)ca_[k];
-            S[i][j] = S[j][i] = (double)cb_[k];
+            S[i][j] = S[j][i] = Cb[i][j] = Cb[j][i] = (double)cb_[k];
         }
     // S += J Ca J^T, with rows 3 and 4 of J those of the identity
     double JC[5][5];
@@ -120,6 +126,7 @@ __device__ double pair_chi2(const MgArgs &A, int a, int b, double ca, double sa)
                 for (int k = 0; k < 5; ++k) acc += JC[i][k] * J[j][k];
             else
                 acc = JC[i][j];
+            P[i][j] = P[j][i] = acc;
             S[i][j] += acc;
             if (j != i) S[j][i] = S[i][j];
         }
@@ -143,7 +150,45 @@ __device__ double pair_chi2(const MgArgs &A, int a, int b, double ca, double sa)
         z[i] = acc / L[i][i];
         chi += z[i] * z[i];
     }
+    if (mp && mc) {
+        // X = S^-1 P by the two triangular solves, column by column
+        double X[5][5];
+        for (int c = 0; c < 5; ++c) {
+            double y[5];
+            for (int i = 0; i < 5; ++i) {
+                double acc = P[i][c];
+                for (int k = 0; k < i; ++k) acc -= L[i][k] * y[k];
+                y[i] = acc / L[i][i];
+            }
+            for (int i = 4; i >= 0; --i) {
+                double acc = y[i];
+                for (int k = i + 1; k < 5; ++k) acc -= L[k][i] * X[k][c];
+                X[i][c] = acc / L[i][i];
+            }
+        }
+        // d = p_a' - p_b: x = p_a' - P S^-1 d = p_a' - X^T d
+        for (int i = 0; i < 5; ++i) {
+            double acc = q[i];
+            for (int k = 0; k < 5; ++k) acc -= X[k][i] * d[k];
+            mp[i] = (float)acc;
+        }
+        // C = P S^-1 C_b = X^T C_b, symmetrised (equal to P - P S^-1 P, with
+        // no difference of large terms when one covariance dwarfs the other)
+        for (int i = 0, k = 0; i < 5; ++i)
+            for (int j = 0; j <= i; ++j, ++k) {
+                double u = 0.0, v = 0.0;
+                for (int m = 0; m < 5; ++m) {
+                    u += X[m][i] * Cb[m][j];
+                    v += X[m][j] * Cb[m][i];
+                }
+                mc[k] = (float)(0.5 * (u + v));
+            }
+    }
     return chi > 0.0 ? chi : INFINITY;
+}
+
+__device__ inline double pair_chi2(const MgArgs &A, int a, int b, double ca, double sa) {
+    return pair_fuse(A, a, b, ca, sa, nullptr, nullptr);
 }
 
 // Candidates of one lane that pass the tan(lambda) / q/pT test, per chunk of
@@ -225,6 +270,15 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_link_next(MgArgs A) {
             A.next[a] = -1;
             A.chi2[a] = 0.f;
         }
+        if (A.mpar) {
+            float *mp = A.mpar + (size_t)a * 5, *mc = A.mcov + (size_t)a * 15;
+            for (int q = 0; q < 5; ++q) mp[q] = 0.f;
+            for (int q = 0; q < 15; ++q) mc[q] = 0.f;
+            if (linked) {
+                const double da = turn_angle(A.sector[a], A.sector[b], A.n_sectors);
+                pair_fuse(A, a, b, cos(da), sin(da), mp, mc);
+            }
+        }
     }
 }
 
@@ -239,7 +293,7 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_link_prev(MgArgs A) {
 }  // namespace
 
 hipError_t launch_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr, double cut,
-                        int32_t *next, int32_t *prev, float *chi2, hipStream_t st) {
+                        int32_t *next, int32_t *prev, float *chi2, float *mpar, float *mcov, hipStream_t st) {
     MgArgs A;
     A.x = tr->x;
     A.par = tr->par;
@@ -256,6 +310,8 @@ hipError_t launch_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_t
     A.next = next;
     A.prev = prev;
     A.chi2 = chi2;
+    A.mpar = mpar;
+    A.mcov = mcov;
     int g = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     hipLaunchKernelGGL(mg_best, dim3(g), dim3(TPC_BLOCK), 0, st, A);

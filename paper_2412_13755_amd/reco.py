@@ -339,17 +339,21 @@ class Reco:
 
     def merge(self, seeds: Seeds, tracks: Tracks, chi2_cut: float):
         """tpc_track_merge: links between fitted segments of neighbouring
-        sectors.  Returns (next, prev, chi2) per seed (int32, int32, float32)."""
+        sectors.  Returns (next, prev, chi2, merged_par [T, 5], merged_cov
+        [T, 15]) per seed (int32, int32, float32, float32, float32)."""
         T = max(seeds.frame.numel(), 1)
         d = self.device
         nxt = torch.full((T,), -1, dtype=torch.int32, device=d)
         prv = torch.full((T,), -1, dtype=torch.int32, device=d)
         chi = torch.zeros(T, dtype=torch.float32, device=d)
+        mp = torch.zeros(T, 5, dtype=torch.float32, device=d)
+        mc = torch.zeros(T, 15, dtype=torch.float32, device=d)
         sc = seeds.c()
         tc = tracks.c()
         C.check(C.lib().tpc_track_merge(self._ctx, ctypes.byref(sc), ctypes.byref(tc), ctypes.c_float(chi2_cut),
-                                        nxt.data_ptr(), prv.data_ptr(), chi.data_ptr(), _stream_handle(d)))
-        return nxt, prv, chi
+                                        nxt.data_ptr(), prv.data_ptr(), chi.data_ptr(), mp.data_ptr(),
+                                        mc.data_ptr(), _stream_handle(d)))
+        return nxt, prv, chi, mp, mc
 
     def alloc_ctf(self, frames: DeviceFrames, seeds: Seeds) -> dict:
         T, N = seeds.frame.numel(), max(frames.n_clusters, 1)

@@ -1,7 +1,8 @@
 """GPU parity of the merging of fitted segments across sector edges
 (tpc_track_merge through the C-ABI) against the oracle run on the same
 fitted tracks (the GPU fit's float outputs): the links (next, prev) equal,
-the chi2 of every link within 1e-6 (relative; the GPU reports it in float).
+the chi2 of every link within 1e-6 (relative; the GPU reports it in float),
+the combined state of every linked pair within the fit's tolerances.
 On the headline event (26 707 seeds, 36 sectors), on 64 uneven frames
 (links never cross frames) and on a single sector (no links)."""
 import numpy as np
@@ -9,6 +10,7 @@ import pytest
 
 import oracle
 from tests.conftest import NB, FIT, MIN_HITS
+from tests import parity
 from tpcsynth import make_config
 
 pytestmark = pytest.mark.gpu
@@ -31,7 +33,7 @@ def check(fr, label):
     up, dn = reco.neighbours(dfr)
     seeds = reco.seed(dfr, up, dn)
     tr = reco.fit(dfr, seeds)
-    nxt, prv, chi = reco.merge(seeds, tr, CUT)
+    nxt, prv, chi, mp, mc = reco.merge(seeds, tr, CUT)
     torch.cuda.synchronize()
     T = int(seeds.n_seeds.item())
     g = {k: getattr(tr, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "status")}
@@ -39,7 +41,7 @@ def check(fr, label):
     sector = seeds.sector[:T].cpu().numpy()
     key = frame.astype(np.int64) * fr.n_sectors + sector
     assert np.all(np.diff(key) >= 0)
-    rn, rp, rc = oracle.merge({k: v.astype(np.float64) for k, v in g.items()}, frame, sector, fr.n_sectors,
+    rn, rp, rc, rmp, rmc = oracle.merge({k: v.astype(np.float64) for k, v in g.items()}, frame, sector, fr.n_sectors,
                               bz=FIT["bz"], max_sin=FIT["max_sin"], cut=CUT)
     gn, gp, gc = nxt[:T].cpu().numpy(), prv[:T].cpu().numpy(), chi[:T].cpu().numpy()
     np.testing.assert_array_equal(gn, rn)
@@ -47,6 +49,15 @@ def check(fr, label):
     L = rn >= 0
     np.testing.assert_allclose(gc[L], rc[L], rtol=1e-6)
     assert np.all(gc[~L] == 0)
+    # the combined states of linked pairs: the fit tolerances (reading of the fit parity)
+    gmp, gmc = mp[:T].cpu().numpy().astype(np.float64), mc[:T].cpu().numpy().astype(np.float64)
+    assert not gmp[~L].any() and not gmc[~L].any()
+    tol = parity.PAR_RTOL * np.maximum(np.abs(rmp[L]), parity.PAR_FLOOR)
+    assert not (np.abs(gmp[L] - rmp[L]) > tol).any(), np.abs(gmp[L] - rmp[L]).max()
+    if L.any():
+        C1, C2 = oracle.unpack_cov(gmc[L]), oracle.unpack_cov(rmc[L])
+        sd_ = np.sqrt(np.einsum("tii->ti", C2))
+        assert (np.abs(C1 - C2) / (sd_[:, :, None] * sd_[:, None, :])).max() <= parity.COV_RTOL
     print("[merge] %s: seeds %d links %d" % (label, T, int(L.sum())), flush=True)
     return int(L.sum()), T
 
