@@ -154,3 +154,31 @@ def test_upload_validates_offsets():
         DeviceFrames.from_numpy(np.array([0, 3, 2, 4]), y, y, 1, 1, 3, device="cpu")
     with pytest.raises(ValueError):
         DeviceFrames.from_numpy(np.array([0, 1, 2, 3]), y, y, 1, 1, 3, device="cpu")
+
+
+def test_merge_host_checks(capi):
+    # every check runs on the host before any launch; a zero-capacity call
+    # returns TPC_OK without touching the device (the context is only read
+    # by the launch)
+    L = capi.lib()
+    ctx = ctypes.create_string_buffer(8192)
+    word = ctypes.c_int32(0)
+    w = ctypes.addressof(word)
+    sd = capi.SeedsC(0, 0, w, w, w, None, None, None, None, None)
+    tr = capi.TracksC()
+    buf = ctypes.create_string_buffer(64)
+    b = ctypes.addressof(buf)
+    assert L.tpc_track_merge(None, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
+                             None) == capi.TPC_ERR_ARG
+    assert "context" in L.tpc_last_error().decode()
+    assert L.tpc_track_merge(ctx, None, ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
+                             None) == capi.TPC_ERR_ARG
+    for cut in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(cut), b, b, b, None, None,
+                                 None) == capi.TPC_ERR_ARG
+        assert "chi2_cut" in L.tpc_last_error().decode()
+    assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, b, None,
+                             None) == capi.TPC_ERR_ARG
+    assert "merged" in L.tpc_last_error().decode()
+    assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
+                             None) == capi.TPC_OK
