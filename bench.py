@@ -34,8 +34,9 @@ Extra legs, reported beside the headline value:
            and each linked pair combined (tpc_track_merge, chi2 cut 30): ms
            per call, links, segments/s
   material the fit with multiple scattering (radiation length 2870 cm, pion
-           mass) and outlier rejection (chi2 > 30) on the headline seeds, and
-           the same fit over rows followed by the smoother (tpc_kalman_smooth)
+           mass), energy loss in the TPC's Ne-CO2-N2 gas and outlier
+           rejection (chi2 > 30) on the headline seeds, and the same fit over
+           rows followed by the smoother (tpc_kalman_smooth)
   skip     the headline event with 10% pad-row inefficiency: neighbours across
            one missing row + seeding + the fit over the hits' own rows, against
            the adjacent-row path on the same frame (times per call, seed
