@@ -105,3 +105,12 @@ def test_energy_loss_protons(torch_dev):
 def test_headline_frame_with_energy_loss(torch_dev):
     st, r = check(make_config(1), 2870.0, 30.0, "full-tpc-event-1e4, Ne-CO2-N2", gas=TPC_GAS)
     assert st["compared"] > 20000
+
+
+def test_energy_loss_past_the_cap(torch_dev):
+    # a gas 600 times denser than argon: about half of the segments would change
+    # the momentum by more than 1 % and are taken without energy loss
+    heavy = (1.0, ARGON_GAS[1], ARGON_GAS[2])
+    fr = make_scattering_frame(n_tracks=400, seed=23, x0_cm=391.0, mass=PROTON_MASS, inv_pt=(0.7, 3.0),
+                               gas=DENSE_GAS)
+    check(fr, 391.0, 30.0, "protons, gas past the 1% cap", mass=PROTON_MASS, gas=heavy)

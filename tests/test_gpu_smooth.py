@@ -99,3 +99,11 @@ def test_energy_loss_protons(torch_dev):
 def test_headline_frame_with_energy_loss(torch_dev):
     st = check(make_config(1), "full-tpc-event-1e4, Ne-CO2-N2", material=(2870.0, PION_MASS, 30.0) + TPC_GAS)
     assert st["hits"] > 900000
+
+
+def test_energy_loss_past_the_cap(torch_dev):
+    # about half of the segments past the 1 % cap (taken without energy loss),
+    # in the fit, the smoother's outward reference and its filter
+    gas = (0.05, ARGON_GAS[1], ARGON_GAS[2])
+    fr = make_scattering_frame(n_tracks=400, seed=13, x0_cm=391.0, mass=PROTON_MASS, inv_pt=(0.7, 3.0), gas=gas)
+    check(fr, "protons, gas past the 1% cap", material=(391.0, PROTON_MASS, 30.0, 1.0, ARGON_GAS[1], ARGON_GAS[2]))
