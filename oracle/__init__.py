@@ -82,6 +82,30 @@ def merge(tracks: dict, frame, sector, n_sectors, *, bz, max_sin, cut):
     return nxt, prv, chi, mp[:T], mc[:T]
 
 
+def leg_circle(p, x, alpha, bz):
+    """(status, m = (X_c, Y_c, kappa, tan lambda), 4x5 Jacobian) of a segment's circle."""
+    m = np.zeros(4)
+    J = np.zeros((4, 5))
+    st = lib().oracle_leg_circle(_p(np.ascontiguousarray(p, dtype=np.float64)), float(x), float(alpha), float(bz),
+                                 _p(m), _p(J))
+    return int(st), m, J
+
+
+def legs(tracks: dict, frame, sector, n_sectors, *, bz, cut):
+    """Mutual-best pairing of the legs of loopers: (leg, leg_chi2) per track."""
+    x = np.ascontiguousarray(tracks["x"], dtype=np.float64)
+    par = np.ascontiguousarray(tracks["par"], dtype=np.float64)
+    cov = np.ascontiguousarray(tracks["cov"], dtype=np.float64)
+    st = np.ascontiguousarray(tracks["status"], dtype=np.int32)
+    fr = np.ascontiguousarray(frame, dtype=np.int32)
+    sc = np.ascontiguousarray(sector, dtype=np.int32)
+    T = x.size
+    leg, chi = np.empty(T, np.int32), np.empty(T)
+    lib().oracle_legs(T, _p(x), _p(par), _p(cov), _p(st), _p(fr), _p(sc), int(n_sectors), float(bz), float(cut),
+                      _p(leg), _p(chi))
+    return leg, chi
+
+
 def eloss(p, dx, mass, gas, direction=1.0):
     """Energy-loss map of the fit for one segment: (status, w', dw'/dt,
     dw'/dw, straggling variance of w)."""
@@ -144,6 +168,10 @@ def lib():
         L.oracle_transfer.restype = i32
         L.oracle_merge.argtypes = [i32, P, P, P, P, P, P, i32, d_, d_, d_, P, P, P, P, P]
         L.oracle_merge.restype = None
+        L.oracle_leg_circle.argtypes = [P, d_, d_, d_, P, P]
+        L.oracle_leg_circle.restype = i32
+        L.oracle_legs.argtypes = [i32, P, P, P, P, P, P, i32, d_, d_, P, P]
+        L.oracle_legs.restype = None
         L.oracle_bethe.argtypes = [ctypes.c_double] * 4
         L.oracle_bethe.restype = ctypes.c_double
         L.oracle_eloss.argtypes = [P, ctypes.c_double, ctypes.POINTER(Material), ctypes.c_double, P]

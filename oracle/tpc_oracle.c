@@ -1421,3 +1421,147 @@ void oracle_merge(int32_t n_tracks, const double *x, const double *par, const do
         }
     free(bo); free(bi); free(co); free(ci);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Legs of loopers.  A particle whose circle stays inside the TPC turns back */
+/* inwards; the returning leg is fitted as a track running outwards, i.e.   */
+/* along the same circle in the other sense: its fitted q/pT and tan lambda */
+/* have the opposite signs, its circle centre is the same point.  Each       */
+/* segment's circle: curvature kappa = -c Bz w, centre (x - s/kappa,         */
+/* y + sqrt(1-s^2)/kappa) in its frame, turned to global coordinates by its */
+/* sector angle.  m = (X_c, Y_c, kappa, t); for two legs of one particle     */
+/* m_A - D m_B = 0 with D = diag(1, 1, -1, -1).  chi2 = d^T (J_A C_A J_A^T + */
+/* D J_B C_B J_B^T D)^-1 d (4 degrees of freedom), J the Jacobian of m in   */
+/* (y, z, s, t, w).  Candidates: fitted segments (status 0) of one frame and */
+/* side, in any sectors (the legs' seeded pieces lie far apart in azimuth),  */
+/* both with a circle radius                                                 */
+/* below 250 cm (only a circle smaller than the TPC can return; the margin   */
+/* keeps poorly measured radii).  Partners are mutual best below the cut    */
+/* (smaller index on ties): leg[A] = B, leg[B] = A, leg_chi2 the pair's     */
+/* chi2; else -1 and 0.                                                      */
+/* ------------------------------------------------------------------------ */
+#define LEG_MAX_RADIUS 250.0
+
+/* m and its Jacobian (4x5, row-major) for one segment; returns 1 if its
+ * circle is too large or the state is degenerate. */
+int32_t oracle_leg_circle(const double *p, double x, double alpha, double bz, double *m, double *J)
+{
+    double y = p[0], s = p[2], t = p[3], w = p[4];
+    double k = -C_LIGHT * bz, kap = k * w;
+    if (!(fabs(s) < 1.0) || !(fabs(kap) * LEG_MAX_RADIUS > 1.0)) return 1;
+    double c = sqrt(1.0 - s * s), ca = cos(alpha), sa = sin(alpha);
+    double xc = x - s / kap, yc = y + c / kap;
+    m[0] = xc * ca - yc * sa;
+    m[1] = xc * sa + yc * ca;
+    m[2] = kap;
+    m[3] = t;
+    if (J) {
+        /* local centre: d xc = (0, 0, -1/kap, 0, s k / kap^2), d yc = (1, 0, -s/(c kap), 0, -c k / kap^2) */
+        double dxc[5] = {0.0, 0.0, -1.0 / kap, 0.0, s * k / (kap * kap)};
+        double dyc[5] = {1.0, 0.0, -s / (c * kap), 0.0, -c * k / (kap * kap)};
+        for (int j = 0; j < 5; ++j) {
+            J[0 * 5 + j] = dxc[j] * ca - dyc[j] * sa;
+            J[1 * 5 + j] = dxc[j] * sa + dyc[j] * ca;
+            J[2 * 5 + j] = j == 4 ? k : 0.0;
+            J[3 * 5 + j] = j == 3 ? 1.0 : 0.0;
+        }
+    }
+    return 0;
+}
+
+static int inv4(const double *A, double *X)
+{
+    double M[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) M[i][j] = j < 4 ? A[i * 4 + j] : (j - 4 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 4; ++i)
+            if (fabs(M[i][c]) > fabs(M[piv][c])) piv = i;
+        if (!(fabs(M[piv][c]) > 0.0)) return 1;
+        if (piv != c)
+            for (int j = 0; j < 8; ++j) { double q = M[c][j]; M[c][j] = M[piv][j]; M[piv][j] = q; }
+        double d = M[c][c];
+        for (int j = 0; j < 8; ++j) M[c][j] /= d;
+        for (int i = 0; i < 4; ++i) {
+            if (i == c) continue;
+            double f = M[i][c];
+            for (int j = 0; j < 8; ++j) M[i][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) X[i * 4 + j] = M[i][j + 4];
+    return 0;
+}
+
+/* J C J^T (4x4) of a segment's packed covariance. */
+static void leg_cov(const double *J, const double *co, double *out)
+{
+    double C[25], JC[20];
+    unpack_cov(co, C);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 5; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 5; ++k) acc += J[i * 5 + k] * C[k * 5 + j];
+            JC[i * 5 + j] = acc;
+        }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 5; ++k) acc += JC[i * 5 + k] * J[j * 5 + k];
+            out[i * 4 + j] = acc;
+        }
+}
+
+static int leg_candidates(int32_t sa, int32_t sb, int32_t n_sectors)
+{
+    return n_sectors == 36 && sa / 18 == sb / 18;
+}
+
+void oracle_legs(int32_t n_tracks, const double *x, const double *par, const double *cov, const int32_t *status,
+                 const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double cut,
+                 int32_t *leg, double *leg_chi2)
+{
+    int32_t *best = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_tracks ? n_tracks : 1));
+    double *bchi = (double *)malloc(sizeof(double) * (size_t)(n_tracks ? n_tracks : 1));
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t a = 0; a < n_tracks; ++a) {
+        best[a] = -1;
+        bchi[a] = INFINITY;
+        double ma[4], Ja[20], Sa[16];
+        if (status[a] || oracle_leg_circle(par + (size_t)a * 5, x[a], sector_angle(sector[a], n_sectors), bz, ma, Ja))
+            continue;
+        leg_cov(Ja, cov + (size_t)a * 15, Sa);
+        for (int32_t b = 0; b < n_tracks; ++b) {
+            double mb[4], Jb[20], Sb[16], S[16], Si[16], d[4];
+            if (b == a || status[b] || frame[b] != frame[a] || !leg_candidates(sector[a], sector[b], n_sectors))
+                continue;
+            if (oracle_leg_circle(par + (size_t)b * 5, x[b], sector_angle(sector[b], n_sectors), bz, mb, Jb)) continue;
+            leg_cov(Jb, cov + (size_t)b * 15, Sb);
+            /* D Sb D flips the signs of the (centre, kappa/t) cross terms */
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    double sg = ((i < 2) == (j < 2)) ? 1.0 : -1.0;
+                    S[i * 4 + j] = Sa[i * 4 + j] + sg * Sb[i * 4 + j];
+                }
+            d[0] = ma[0] - mb[0];
+            d[1] = ma[1] - mb[1];
+            d[2] = ma[2] + mb[2];
+            d[3] = ma[3] + mb[3];
+            if (d[2] * d[2] > cut * S[10] || d[3] * d[3] > cut * S[15]) continue;
+            if (inv4(S, Si)) continue;
+            double chi = 0.0;
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) chi += d[i] * Si[i * 4 + j] * d[j];
+            if (chi > 0.0 && chi <= cut && chi < bchi[a]) { bchi[a] = chi; best[a] = b; }
+        }
+    }
+    for (int32_t a = 0; a < n_tracks; ++a) {
+        int32_t b = best[a];
+        int linked = b >= 0 && best[b] == a;
+        leg[a] = linked ? b : -1;
+        leg_chi2[a] = linked ? bchi[a] : 0.0;
+    }
+    free(best);
+    free(bchi);
+}

@@ -100,6 +100,15 @@ void oracle_merge(int32_t n_tracks, const double *x, const double *par, const do
                   const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double max_sin,
                   double cut, int32_t *next, int32_t *prev, double *chi2, double *mpar, double *mcov);
 
+/* Legs of loopers (see tpc_oracle.c): a segment's circle in global
+ * coordinates m = (X_c, Y_c, kappa, tan lambda) with its 4x5 Jacobian (J may
+ * be NULL; returns 1 for a circle too large or a degenerate state), and the
+ * mutual-best pairing of legs. */
+int32_t oracle_leg_circle(const double *p, double x, double alpha, double bz, double *m, double *J);
+void oracle_legs(int32_t n_tracks, const double *x, const double *par, const double *cov, const int32_t *status,
+                 const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double cut,
+                 int32_t *leg, double *leg_chi2);
+
 void oracle_ctf_build(int32_t n_tracks, int32_t n_rows, int32_t n_sectors, int32_t n_segments,
                       const int32_t *row_offsets, const float *y, const float *z,
                       const int32_t *rows, const int32_t *status, const int32_t *frame,
