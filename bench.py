@@ -30,9 +30,9 @@ Extra legs, reported beside the headline value:
            rANS coding of all of them in one batch (scale 2^14, blocks of
            2^13, counts read on the device), eagerly and as a graph;
            clusters/s and bits per cluster
-  merge    the headline event's fitted segments linked across sector edges
-           and each linked pair combined (tpc_track_merge, chi2 cut 30): ms
-           per call, links, segments/s
+  merge    the headline event's fitted segments linked across sector edges,
+           each linked pair combined, and the legs of loopers paired
+           (tpc_track_merge, chi2 cut 30): ms per call, links, segments/s
   material the fit with multiple scattering (radiation length 2870 cm, pion
            mass), energy loss in the TPC's Ne-CO2-N2 gas and outlier
            rejection (chi2 > 30) on the headline seeds, and the same fit over
@@ -601,7 +601,7 @@ def leg_merge(args):
     up, dn = reco.neighbours(dfr, ws=ws)
     seeds = reco.seed(dfr, up, dn, ws=ws)
     tr = reco.fit(dfr, seeds)
-    nxt, prv, chi, mp, mc = reco.merge(seeds, tr, MERGE_CUT)
+    nxt, prv, chi, mp, mc, leg, lchi = reco.merge(seeds, tr, MERGE_CUT)
     torch.cuda.synchronize()
     T = int(seeds.n_seeds.item())
     stream = torch.cuda.current_stream()
@@ -609,13 +609,15 @@ def leg_merge(args):
     for _ in range(max(5, args.steps)):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record(stream)
-        nxt, prv, chi, mp, mc = reco.merge(seeds, tr, MERGE_CUT)
+        nxt, prv, chi, mp, mc, leg, lchi = reco.merge(seeds, tr, MERGE_CUT)
         e[1].record(stream)
         evs.append(e)
     torch.cuda.synchronize()
     ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     links = int((nxt[:T] >= 0).sum().item())
-    return {"workload": fr.meta["name"], "seeds": T, "chi2_cut": MERGE_CUT, "links": links, "ms": round(ms, 5),
+    legs = int((leg[:T] >= 0).sum().item()) // 2
+    return {"workload": fr.meta["name"], "seeds": T, "chi2_cut": MERGE_CUT, "links": links, "looper_leg_pairs": legs,
+            "ms": round(ms, 5),
             "segments_per_s": round(T / ms * 1e3, 1)}
 
 

@@ -402,10 +402,19 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
  * and B's, independent fits of disjoint hits, combined: x = p_A' +
  * P S^-1 (p_B - p_A'), C = P S^-1 C_B, S = P + C_B (the joint fit of both
  * segments' hits for the linearised problem); zeros where unlinked.
- * chi2_cut > 0 and finite, else TPC_ERR_ARG. */
+ * leg [cap_seeds] (int32), leg_chi2 [cap_seeds] (float), both or neither
+ * NULL: the legs of loopers.  A returning leg is fitted as a track running
+ * outwards along the same circle in the other sense (same centre, curvature
+ * and tan(lambda) of opposite signs).  Per segment m = (X_c, Y_c, kappa,
+ * tan(lambda)), the circle centre in global coordinates (kappa = -c Bz q/pT);
+ * two fitted segments of one frame and side (any sectors), both with circle
+ * radius below 250 cm, compare by chi2 = d^T (J_A C_A J_A^T + D J_B C_B J_B^T
+ * D)^-1 d, d = m_A - D m_B, D = diag(1, 1, -1, -1); mutual best partners
+ * with chi2 <= chi2_cut (smaller index on ties) get leg[A] = B, leg[B] = A;
+ * else -1 and 0.  chi2_cut > 0 and finite, else TPC_ERR_ARG. */
 tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *seeds, const tpc_tracks *tracks,
                            float chi2_cut, int32_t *next, int32_t *prev, float *chi2, float *merged_par,
-                           float *merged_cov, void *stream);
+                           float *merged_cov, int32_t *leg, float *leg_chi2, void *stream);
 
 /* Entropy coding of a time frame's integer arrays (Sec. 4.3: every flat
  * integer array is coded on its own with range asymmetric numeral systems,

@@ -126,7 +126,7 @@ SIGNATURES = {
                               ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), P, P, ctypes.c_size_t,
                               P]),
     "tpc_track_merge": (i32, [P, ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), ctypes.c_float, P, P, P, P, P,
-                              P]),
+                              P, P, P]),
     "tpc_track_follow": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
                                ctypes.POINTER(FollowParams), P, ctypes.POINTER(TracksC), P,
                                ctypes.c_size_t, P]),

@@ -427,7 +427,7 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *fr, const 
 
 tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr, float chi2_cut,
                            int32_t *next, int32_t *prev, float *chi2, float *merged_par, float *merged_cov,
-                           void *stream) {
+                           int32_t *leg, float *leg_chi2, void *stream) {
     g_err[0] = 0;
     if (!ctx) return fail(TPC_ERR_ARG, "null context");
     tpc_status s = check_seeds_for_fit(sd);
@@ -436,9 +436,10 @@ tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *sd, const tp
     if (!(chi2_cut > 0.f) || !isfinite(chi2_cut)) return fail(TPC_ERR_ARG, "chi2_cut must be finite and > 0");
     if (sd->cap_seeds > 0 && (!next || !prev || !chi2)) return fail(TPC_ERR_ARG, "null merge outputs");
     if (!merged_par != !merged_cov) return fail(TPC_ERR_ARG, "merged_par and merged_cov must both be given or both null");
+    if (!leg != !leg_chi2) return fail(TPC_ERR_ARG, "leg and leg_chi2 must both be given or both null");
     if (sd->cap_seeds == 0) return TPC_OK;
-    hipError_t e = launch_merge(ctx, sd, tr, (double)chi2_cut, next, prev, chi2, merged_par, merged_cov,
-                                (hipStream_t)stream);
+    hipError_t e = launch_merge(ctx, sd, tr, (double)chi2_cut, next, prev, chi2, merged_par, merged_cov, leg,
+                                leg_chi2, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "merge kernels");
 }
 

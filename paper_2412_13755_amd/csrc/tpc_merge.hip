@@ -22,6 +22,10 @@
 //                  combined at b's plane (a's transferred state fused with
 //                  b's: the joint fit of both for the linearised problem)
 //  mg_link_prev    prev[b] = a when next[a] = b
+//  lg_best, lg_link  optionally, the legs of loopers: per segment the
+//                  best partner among the segments of its frame and side
+//                  whose circle matches with curvature and tan(lambda)
+//                  reversed, then mutual best
 //
 // The transfer: a state at plane x of the inner segment's frame is rotated
 // into the outer segment's frame (turned by da: a point (x, y) ->
@@ -43,6 +47,8 @@ struct MgArgs {
     int32_t *next, *prev;
     float *chi2;
     float *mpar, *mcov;      // optional combined states of linked pairs
+    int32_t *leg;            // optional pairing of the legs of loopers
+    float *leg_chi2;
 };
 
 __device__ inline int mg_count(const MgArgs &A) {
@@ -290,10 +296,154 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_link_prev(MgArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Legs of loopers.  A returning leg is fitted as a track running outwards
+// along the same circle in the other sense: the same centre, curvature and
+// tan(lambda) of opposite signs.  m = (X_c, Y_c, kappa, t) per segment in
+// global coordinates, compared as m_A - D m_B, D = diag(1, 1, -1, -1), with
+// chi2 = d^T (J_A C_A J_A^T + D J_B C_B J_B^T D)^-1 d (4 dof).  Candidates:
+// fitted segments of one frame and side in any sectors, circle radius below
+// 250 cm.
+
+#define LEG_MAX_RADIUS 250.0
+
+struct Circle {
+    double m[4];
+    double S[4][4];       // J C J^T
+};
+
+// The circle of segment i (false if too large or degenerate).
+__device__ bool leg_circle(const MgArgs &A, int i, Circle &o) {
+    const float *p = A.par + (size_t)i * 5, *co = A.cov + (size_t)i * 15;
+    const double y = (double)p[0], s = (double)p[2], t = (double)p[3], w = (double)p[4];
+    const double k = A.kbz, kap = k * w;
+    if (!(fabs(s) < 1.0) || !(fabs(kap) * LEG_MAX_RADIUS > 1.0)) return false;
+    const double al = sector_angle(A.sector[i], A.n_sectors);
+    const double c = sqrt(1.0 - s * s), ca = cos(al), sa = sin(al);
+    const double x = (double)A.x[i];
+    const double xc = x - s / kap, yc = y + c / kap;
+    o.m[0] = xc * ca - yc * sa;
+    o.m[1] = xc * sa + yc * ca;
+    o.m[2] = kap;
+    o.m[3] = t;
+    const double dxc[5] = {0.0, 0.0, -1.0 / kap, 0.0, s * k / (kap * kap)};
+    const double dyc[5] = {1.0, 0.0, -s / (c * kap), 0.0, -c * k / (kap * kap)};
+    double J[4][5];
+    for (int j = 0; j < 5; ++j) {
+        J[0][j] = dxc[j] * ca - dyc[j] * sa;
+        J[1][j] = dxc[j] * sa + dyc[j] * ca;
+        J[2][j] = j == 4 ? k : 0.0;
+        J[3][j] = j == 3 ? 1.0 : 0.0;
+    }
+    double C[5][5];
+    for (int a = 0, q = 0; a < 5; ++a)
+        for (int b = 0; b <= a; ++b, ++q) C[a][b] = C[b][a] = (double)co[q];
+    double JC[4][5];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 5; ++b) {
+            double acc = 0.0;
+            for (int q = 0; q < 5; ++q) acc += J[a][q] * C[q][b];
+            JC[a][b] = acc;
+        }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            double acc = 0.0;
+            for (int q = 0; q < 5; ++q) acc += JC[a][q] * J[b][q];
+            o.S[a][b] = acc;
+        }
+    return true;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK) lg_best(MgArgs A) {
+    __shared__ int cand[MG_CHUNK][TPC_BLOCK];
+    const int T = mg_count(A);
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+        int best = -1;
+        double bchi = INFINITY;
+        Circle ci;
+        if (A.status[i] == 0 && A.n_sectors == 36 && leg_circle(A, i, ci)) {
+            const int side = A.sector[i] / 18;
+            const int64_t key = (int64_t)A.frame[i] * A.n_sectors + side * 18;
+            const int j0 = mg_lower(A, T, key), j1 = mg_lower(A, T, key + 18);
+            const double k2 = A.kbz * A.kbz;
+            const double wi = (double)A.par[(size_t)i * 5 + 4], ti = (double)A.par[(size_t)i * 5 + 3];
+            const double vwi = (double)A.cov[(size_t)i * 15 + 14], vti = (double)A.cov[(size_t)i * 15 + 9];
+            for (int c0 = j0; c0 < j1; c0 += MG_CHUNK) {
+                const int c1 = c0 + MG_CHUNK < j1 ? c0 + MG_CHUNK : j1;
+                int n = 0;
+                for (int j = c0; j < c1; ++j) {
+                    if (j == i || A.status[j] != 0) continue;
+                    const float *pj = A.par + (size_t)j * 5, *cj = A.cov + (size_t)j * 15;
+                    // curvature and tan(lambda) alone (their rows of J are exact
+                    // and need no circle): a pair failing either cannot pass
+                    const double dk = A.kbz * (wi + (double)pj[4]), dt = ti + (double)pj[3];
+                    if (dk * dk > A.cut * k2 * (vwi + (double)cj[14]) || dt * dt > A.cut * (vti + (double)cj[9]))
+                        continue;
+                    cand[n++][threadIdx.x] = j;
+                }
+                for (int q = 0; q < n; ++q) {
+                    const int j = cand[q][threadIdx.x];
+                    Circle cj;
+                    if (!leg_circle(A, j, cj)) continue;
+                    double S[4][4], d[4];
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 4; ++b)
+                            S[a][b] = ci.S[a][b] + (((a < 2) == (b < 2)) ? 1.0 : -1.0) * cj.S[a][b];
+                    d[0] = ci.m[0] - cj.m[0];
+                    d[1] = ci.m[1] - cj.m[1];
+                    d[2] = ci.m[2] + cj.m[2];
+                    d[3] = ci.m[3] + cj.m[3];
+                    // chi2 = |L^-1 d|^2, S = L L^T
+                    double L[4][4], z[4], chi = 0.0;
+                    bool ok = true;
+                    for (int a = 0; a < 4 && ok; ++a) {
+                        for (int b = 0; b <= a; ++b) {
+                            double acc = S[a][b];
+                            for (int m = 0; m < b; ++m) acc -= L[a][m] * L[b][m];
+                            if (a == b) {
+                                if (!(acc > 0.0)) { ok = false; break; }
+                                L[a][a] = sqrt(acc);
+                            } else {
+                                L[a][b] = acc / L[b][b];
+                            }
+                        }
+                        if (!ok) break;
+                        double acc = d[a];
+                        for (int m = 0; m < a; ++m) acc -= L[a][m] * z[m];
+                        z[a] = acc / L[a][a];
+                        chi += z[a] * z[a];
+                    }
+                    if (ok && chi > 0.0 && chi <= A.cut && (chi < bchi || (chi == bchi && j < best))) {
+                        bchi = chi;
+                        best = j;
+                    }
+                }
+            }
+        }
+        A.leg[i] = best;
+        A.leg_chi2[i] = best >= 0 ? (float)bchi : 0.f;
+    }
+}
+
+// Mutual best, in place: a segment whose best does not choose it back is
+// cleared; the value another thread reads can only change from "not me" to
+// -1, and a mutual pair is never cleared.
+__global__ void __launch_bounds__(TPC_BLOCK) lg_link(MgArgs A) {
+    const int T = mg_count(A);
+    for (int a = blockIdx.x * TPC_BLOCK + threadIdx.x; a < T; a += gridDim.x * TPC_BLOCK) {
+        const int b = A.leg[a];
+        if (!(b >= 0 && b < T && A.leg[b] == a)) {
+            A.leg[a] = -1;
+            A.leg_chi2[a] = 0.f;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_tracks *tr, double cut,
-                        int32_t *next, int32_t *prev, float *chi2, float *mpar, float *mcov, hipStream_t st) {
+                        int32_t *next, int32_t *prev, float *chi2, float *mpar, float *mcov, int32_t *leg,
+                        float *leg_chi2, hipStream_t st) {
     MgArgs A;
     A.x = tr->x;
     A.par = tr->par;
@@ -312,10 +462,16 @@ hipError_t launch_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_t
     A.chi2 = chi2;
     A.mpar = mpar;
     A.mcov = mcov;
+    A.leg = leg;
+    A.leg_chi2 = leg_chi2;
     int g = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     hipLaunchKernelGGL(mg_best, dim3(g), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(mg_link_next, dim3(g), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(mg_link_prev, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    if (leg) {
+        hipLaunchKernelGGL(lg_best, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+        hipLaunchKernelGGL(lg_link, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    }
     return hipGetLastError();
 }

@@ -339,8 +339,8 @@ class Reco:
 
     def merge(self, seeds: Seeds, tracks: Tracks, chi2_cut: float):
         """tpc_track_merge: links between fitted segments of neighbouring
-        sectors.  Returns (next, prev, chi2, merged_par [T, 5], merged_cov
-        [T, 15]) per seed (int32, int32, float32, float32, float32)."""
+        sectors, and the pairing of the legs of loopers.  Returns (next, prev,
+        chi2, merged_par [T, 5], merged_cov [T, 15], leg, leg_chi2) per seed."""
         T = max(seeds.frame.numel(), 1)
         d = self.device
         nxt = torch.full((T,), -1, dtype=torch.int32, device=d)
@@ -348,12 +348,14 @@ class Reco:
         chi = torch.zeros(T, dtype=torch.float32, device=d)
         mp = torch.zeros(T, 5, dtype=torch.float32, device=d)
         mc = torch.zeros(T, 15, dtype=torch.float32, device=d)
+        leg = torch.full((T,), -1, dtype=torch.int32, device=d)
+        lchi = torch.zeros(T, dtype=torch.float32, device=d)
         sc = seeds.c()
         tc = tracks.c()
         C.check(C.lib().tpc_track_merge(self._ctx, ctypes.byref(sc), ctypes.byref(tc), ctypes.c_float(chi2_cut),
                                         nxt.data_ptr(), prv.data_ptr(), chi.data_ptr(), mp.data_ptr(),
-                                        mc.data_ptr(), _stream_handle(d)))
-        return nxt, prv, chi, mp, mc
+                                        mc.data_ptr(), leg.data_ptr(), lchi.data_ptr(), _stream_handle(d)))
+        return nxt, prv, chi, mp, mc, leg, lchi
 
     def alloc_ctf(self, frames: DeviceFrames, seeds: Seeds) -> dict:
         T, N = seeds.frame.numel(), max(frames.n_clusters, 1)

@@ -169,16 +169,19 @@ def test_merge_host_checks(capi):
     buf = ctypes.create_string_buffer(64)
     b = ctypes.addressof(buf)
     assert L.tpc_track_merge(None, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
-                             None) == capi.TPC_ERR_ARG
+                             None, None, None) == capi.TPC_ERR_ARG
     assert "context" in L.tpc_last_error().decode()
     assert L.tpc_track_merge(ctx, None, ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
-                             None) == capi.TPC_ERR_ARG
+                             None, None, None) == capi.TPC_ERR_ARG
     for cut in (0.0, -1.0, float("nan"), float("inf")):
         assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(cut), b, b, b, None, None,
-                                 None) == capi.TPC_ERR_ARG
+                                 None, None, None) == capi.TPC_ERR_ARG
         assert "chi2_cut" in L.tpc_last_error().decode()
     assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, b, None,
-                             None) == capi.TPC_ERR_ARG
+                             None, None, None) == capi.TPC_ERR_ARG
     assert "merged" in L.tpc_last_error().decode()
     assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
-                             None) == capi.TPC_OK
+                             b, None, None) == capi.TPC_ERR_ARG
+    assert "leg" in L.tpc_last_error().decode()
+    assert L.tpc_track_merge(ctx, ctypes.byref(sd), ctypes.byref(tr), ctypes.c_float(30.0), b, b, b, None, None,
+                             None, None, None) == capi.TPC_OK

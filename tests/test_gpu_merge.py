@@ -2,7 +2,8 @@
 (tpc_track_merge through the C-ABI) against the oracle run on the same
 fitted tracks (the GPU fit's float outputs): the links (next, prev) equal,
 the chi2 of every link within 1e-6 (relative; the GPU reports it in float),
-the combined state of every linked pair within the fit's tolerances.
+the combined state of every linked pair within the fit's tolerances, the
+pairing of looper legs equal and its chi2 within 1e-6.
 On the headline event (26 707 seeds, 36 sectors), on 64 uneven frames
 (links never cross frames) and on a single sector (no links)."""
 import numpy as np
@@ -33,7 +34,7 @@ def check(fr, label):
     up, dn = reco.neighbours(dfr)
     seeds = reco.seed(dfr, up, dn)
     tr = reco.fit(dfr, seeds)
-    nxt, prv, chi, mp, mc = reco.merge(seeds, tr, CUT)
+    nxt, prv, chi, mp, mc, leg, lchi = reco.merge(seeds, tr, CUT)
     torch.cuda.synchronize()
     T = int(seeds.n_seeds.item())
     g = {k: getattr(tr, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "status")}
@@ -58,7 +59,16 @@ def check(fr, label):
         C1, C2 = oracle.unpack_cov(gmc[L]), oracle.unpack_cov(rmc[L])
         sd_ = np.sqrt(np.einsum("tii->ti", C2))
         assert (np.abs(C1 - C2) / (sd_[:, :, None] * sd_[:, None, :])).max() <= parity.COV_RTOL
-    print("[merge] %s: seeds %d links %d" % (label, T, int(L.sum())), flush=True)
+    # the legs of loopers
+    rl, rlc = oracle.legs({k: v.astype(np.float64) for k, v in g.items()}, frame, sector, fr.n_sectors,
+                          bz=FIT["bz"], cut=CUT)
+    gl, glc = leg[:T].cpu().numpy(), lchi[:T].cpu().numpy()
+    np.testing.assert_array_equal(gl, rl)
+    P = rl >= 0
+    np.testing.assert_allclose(glc[P], rlc[P], rtol=1e-6)
+    assert np.all(glc[~P] == 0)
+    print("[merge] %s: seeds %d links %d looper legs paired %d" % (label, T, int(L.sum()), int(P.sum()) // 2),
+          flush=True)
     return int(L.sum()), T
 
 
