@@ -357,20 +357,59 @@ __device__ bool leg_circle(const MgArgs &A, int i, Circle &o) {
 __global__ void __launch_bounds__(TPC_BLOCK) lg_best(MgArgs A) {
     __shared__ int cand[MG_CHUNK][TPC_BLOCK];
     const int T = mg_count(A);
-    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    const double k2 = A.kbz * A.kbz;
+    // whole workgroups step together, so every lane of a wavefront stays in
+    // the loop body (the shuffles below need them all)
+    for (int base = blockIdx.x * TPC_BLOCK; base < T; base += gridDim.x * TPC_BLOCK) {
+        const int i = base + threadIdx.x;
         int best = -1;
         double bchi = INFINITY;
         Circle ci;
-        if (A.status[i] == 0 && A.n_sectors == 36 && leg_circle(A, i, ci)) {
-            const int side = A.sector[i] / 18;
-            const int64_t key = (int64_t)A.frame[i] * A.n_sectors + side * 18;
-            const int j0 = mg_lower(A, T, key), j1 = mg_lower(A, T, key + 18);
-            const double k2 = A.kbz * A.kbz;
-            const double wi = (double)A.par[(size_t)i * 5 + 4], ti = (double)A.par[(size_t)i * 5 + 3];
-            const double vwi = (double)A.cov[(size_t)i * 15 + 14], vti = (double)A.cov[(size_t)i * 15 + 9];
-            for (int c0 = j0; c0 < j1; c0 += MG_CHUNK) {
-                const int c1 = c0 + MG_CHUNK < j1 ? c0 + MG_CHUNK : j1;
-                int n = 0;
+        const bool live = i < T && A.status[i] == 0 && A.n_sectors == 36 && leg_circle(A, i, ci);
+        int j0 = 0, j1 = 0;
+        double wi = 0.0, ti = 0.0, vwi = 0.0, vti = 0.0;
+        if (live) {
+            const int64_t key = (int64_t)A.frame[i] * A.n_sectors + (A.sector[i] / 18) * 18;
+            j0 = mg_lower(A, T, key);
+            j1 = mg_lower(A, T, key + 18);
+            wi = (double)A.par[(size_t)i * 5 + 4];
+            ti = (double)A.par[(size_t)i * 5 + 3];
+            vwi = (double)A.cov[(size_t)i * 15 + 14];
+            vti = (double)A.cov[(size_t)i * 15 + 9];
+        }
+        // one candidate range for every live lane (its segments share a frame
+        // and side): lanes load one candidate each per chunk and test it on
+        // shuffled copies; otherwise each lane walks its own range
+        const unsigned long long lv = __ballot(live);
+        const int lead = lv ? __ffsll((long long)lv) - 1 : 0;
+        const int L0 = __shfl(j0, lead), L1 = __shfl(j1, lead);
+        const bool shared_range = __all(!live || (j0 == L0 && j1 == L1));
+        const int r0 = shared_range ? L0 : j0, r1 = shared_range ? L1 : j1;
+        for (int c0 = r0; c0 < r1; c0 += MG_CHUNK) {
+            const int c1 = c0 + MG_CHUNK < r1 ? c0 + MG_CHUNK : r1;
+            int n = 0;
+            if (shared_range) {
+                const int jl = c0 + lane;
+                double wq = 0.0, tq = 0.0, vwq = 0.0, vtq = 0.0;
+                int okq = 0;
+                if (jl < c1) {
+                    okq = A.status[jl] == 0;
+                    wq = (double)A.par[(size_t)jl * 5 + 4];
+                    tq = (double)A.par[(size_t)jl * 5 + 3];
+                    vwq = (double)A.cov[(size_t)jl * 15 + 14];
+                    vtq = (double)A.cov[(size_t)jl * 15 + 9];
+                }
+                for (int q = 0; q < c1 - c0; ++q) {
+                    const int ok = __shfl(okq, q);
+                    const double wj = __shfl(wq, q), tj = __shfl(tq, q);
+                    const double vwj = __shfl(vwq, q), vtj = __shfl(vtq, q);
+                    const double dk = A.kbz * (wi + wj), dt = ti + tj;
+                    if (live && ok && c0 + q != i && !(dk * dk > A.cut * k2 * (vwi + vwj)) &&
+                        !(dt * dt > A.cut * (vti + vtj)))
+                        cand[n++][threadIdx.x] = c0 + q;
+                }
+            } else if (live) {
                 for (int j = c0; j < c1; ++j) {
                     if (j == i || A.status[j] != 0) continue;
                     const float *pj = A.par + (size_t)j * 5, *cj = A.cov + (size_t)j * 15;
@@ -381,47 +420,49 @@ __global__ void __launch_bounds__(TPC_BLOCK) lg_best(MgArgs A) {
                         continue;
                     cand[n++][threadIdx.x] = j;
                 }
-                for (int q = 0; q < n; ++q) {
-                    const int j = cand[q][threadIdx.x];
-                    Circle cj;
-                    if (!leg_circle(A, j, cj)) continue;
-                    double S[4][4], d[4];
-                    for (int a = 0; a < 4; ++a)
-                        for (int b = 0; b < 4; ++b)
-                            S[a][b] = ci.S[a][b] + (((a < 2) == (b < 2)) ? 1.0 : -1.0) * cj.S[a][b];
-                    d[0] = ci.m[0] - cj.m[0];
-                    d[1] = ci.m[1] - cj.m[1];
-                    d[2] = ci.m[2] + cj.m[2];
-                    d[3] = ci.m[3] + cj.m[3];
-                    // chi2 = |L^-1 d|^2, S = L L^T
-                    double L[4][4], z[4], chi = 0.0;
-                    bool ok = true;
-                    for (int a = 0; a < 4 && ok; ++a) {
-                        for (int b = 0; b <= a; ++b) {
-                            double acc = S[a][b];
-                            for (int m = 0; m < b; ++m) acc -= L[a][m] * L[b][m];
-                            if (a == b) {
-                                if (!(acc > 0.0)) { ok = false; break; }
-                                L[a][a] = sqrt(acc);
-                            } else {
-                                L[a][b] = acc / L[b][b];
-                            }
+            }
+            for (int q = 0; q < n; ++q) {
+                const int j = cand[q][threadIdx.x];
+                Circle cj;
+                if (!leg_circle(A, j, cj)) continue;
+                double S[4][4], d[4];
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b)
+                        S[a][b] = ci.S[a][b] + (((a < 2) == (b < 2)) ? 1.0 : -1.0) * cj.S[a][b];
+                d[0] = ci.m[0] - cj.m[0];
+                d[1] = ci.m[1] - cj.m[1];
+                d[2] = ci.m[2] + cj.m[2];
+                d[3] = ci.m[3] + cj.m[3];
+                // chi2 = |L^-1 d|^2, S = L L^T
+                double L[4][4], z[4], chi = 0.0;
+                bool ok = true;
+                for (int a = 0; a < 4 && ok; ++a) {
+                    for (int b = 0; b <= a; ++b) {
+                        double acc = S[a][b];
+                        for (int m = 0; m < b; ++m) acc -= L[a][m] * L[b][m];
+                        if (a == b) {
+                            if (!(acc > 0.0)) { ok = false; break; }
+                            L[a][a] = sqrt(acc);
+                        } else {
+                            L[a][b] = acc / L[b][b];
                         }
-                        if (!ok) break;
-                        double acc = d[a];
-                        for (int m = 0; m < a; ++m) acc -= L[a][m] * z[m];
-                        z[a] = acc / L[a][a];
-                        chi += z[a] * z[a];
                     }
-                    if (ok && chi > 0.0 && chi <= A.cut && (chi < bchi || (chi == bchi && j < best))) {
-                        bchi = chi;
-                        best = j;
-                    }
+                    if (!ok) break;
+                    double acc = d[a];
+                    for (int m = 0; m < a; ++m) acc -= L[a][m] * z[m];
+                    z[a] = acc / L[a][a];
+                    chi += z[a] * z[a];
+                }
+                if (ok && chi > 0.0 && chi <= A.cut && (chi < bchi || (chi == bchi && j < best))) {
+                    bchi = chi;
+                    best = j;
                 }
             }
         }
-        A.leg[i] = best;
-        A.leg_chi2[i] = best >= 0 ? (float)bchi : 0.f;
+        if (i < T) {
+            A.leg[i] = best;
+            A.leg_chi2[i] = best >= 0 ? (float)bchi : 0.f;
+        }
     }
 }
 
