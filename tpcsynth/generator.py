@@ -106,6 +106,28 @@ class Frames:
                       cut(self.err))
 
 
+    def sector_view(self, f: int, s: int) -> "Frames":
+        """Sector ``s`` of frame ``f`` alone, as a one-sector frame with ids
+        rebased to 0 (its first cluster is global id ``first_id(f, s)``).
+        Reconstruction within a sector never reads another sector, so a
+        sector's links and seeds are those of the whole frame, rebased."""
+        R = self.n_rows
+        i0 = (f * self.n_sectors + s) * R
+        off = self.row_offsets[i0:i0 + R + 1]
+        a, b = int(off[0]), int(off[-1])
+        sl = slice(a, b)
+
+        def cut(v):
+            return None if v is None else v[sl]
+        return Frames(1, 1, R, self.row_x, (off - a).astype(np.int32), self.y[sl], self.z[sl], self.bz,
+                      self.sigma_y, self.sigma_z, cut(self.track_of), cut(self.y_true), cut(self.z_true),
+                      cut(self.s_true), cut(self.t_true), cut(self.w_true), None,
+                      dict(self.meta, sector_of=(f, s), first_id=a), cut(self.err))
+
+    def first_id(self, f: int, s: int) -> int:
+        return int(self.row_offsets[(f * self.n_sectors + s) * self.n_rows])
+
+
 # ----------------------------------------------------------------------------
 # helix crossings
 
@@ -269,6 +291,32 @@ def _crossings_parallel(tr: Tracks, row_x, n_sectors, bz, max_turns, workers=Non
     return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
 
 
+def _segment_order(key: np.ndarray, tieb: Optional[np.ndarray]) -> np.ndarray:
+    """Permutation sorting by (key, tieb, original index): the order of
+    ``np.lexsort((tieb, key))`` (``tieb`` None: by key, stable), computed as
+    a sort by tieb followed by stable 16-bit radix passes over the key, which
+    is several times faster on 10^7-10^8 clusters."""
+    n = key.size
+    if tieb is None:
+        o1 = np.arange(n)
+    else:
+        o1 = np.argsort(tieb)
+        t = tieb[o1]
+        if np.any(t[1:] == t[:-1]):          # equal draws: keep their index order
+            o1 = np.argsort(tieb, kind="stable")
+    k = key[o1].astype(np.int64)
+    if k.size and k.min() < 0:
+        raise ValueError("negative segment key")
+    shift = 0
+    while shift == 0 or (k.size and (k.max() >> shift) > 0):
+        part = ((k >> shift) & 0xFFFF).astype(np.uint16)
+        p = np.argsort(part, kind="stable")
+        o1 = o1[p]
+        k = k[p]
+        shift += 16
+    return o1
+
+
 def _draw_tracks(rng, n, phi_range, looper_frac, trunc_frac, n_rows, frame=0, t0=None):
     q = np.where(rng.random(n) < 0.5, -1, 1).astype(np.int8)
     inv_pt = rng.uniform(0.2, 5.0, n)
@@ -297,12 +345,16 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
                 bz: float = 0.5, sigma_y: float = 0.05, sigma_z: float = 0.06, smear: bool = True,
                 shuffle: bool = True, max_turns: int = 3, keep_truth: bool = False,
                 hit_eff: float = 1.0, tracks: Optional[Tracks] = None,
-                err_scale: Optional[Sequence[float]] = None) -> Frames:
+                err_scale: Optional[Sequence[float]] = None,
+                noise_sectors: Optional[Sequence[int]] = None) -> Frames:
     """General generator; ``make_config`` fixes the parameters of the five workloads.
 
     ``err_scale=(lo, hi)`` gives every track cluster its own resolution: the
     nominal sigma_y and sigma_z times two independent factors drawn uniformly
-    in [lo, hi], stored in ``err`` (noise clusters get the nominal values)."""
+    in [lo, hi], stored in ``err`` (noise clusters get the nominal values).
+    ``noise_sectors`` puts the noise clusters only in the listed sectors
+    (default: all), so that a frame whose tracks cover a few sectors keeps
+    the noise density of a full frame there."""
     rng = np.random.Generator(np.random.PCG64(seed))
     row_x = make_row_x(n_rows)
     F = len(tracks_per_frame)
@@ -354,7 +406,10 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
     n_noise = int(round(noise_frac / (1.0 - noise_frac) * n_sig)) if noise_frac > 0 else 0
     if n_noise:
         nf = rng.integers(0, F, n_noise)
-        ns = rng.integers(0, n_sectors, n_noise)
+        if noise_sectors is None:
+            ns = rng.integers(0, n_sectors, n_noise)
+        else:
+            ns = np.asarray(noise_sectors, dtype=np.int64)[rng.integers(0, len(noise_sectors), n_noise)]
         nr = rng.integers(0, n_rows, n_noise)
         half = row_x[nr].astype(np.float64) * TAN10
         ny = rng.uniform(-1.0, 1.0, n_noise) * half
@@ -376,8 +431,8 @@ def make_frames(*, n_sectors: int = 36, n_rows: int = 152, tracks_per_frame: Seq
     else:
         st, tt, wt = cr["s"], cr["t"], cr["w"]
     key = (frame * n_sectors + sec) * n_rows + row
-    tieb = rng.random(key.size) if shuffle else np.arange(key.size, dtype=np.float64)
-    order = np.lexsort((tieb, key))
+    tieb = rng.random(key.size) if shuffle else None
+    order = _segment_order(key, tieb)
     NR = F * n_sectors * n_rows
     counts = np.bincount(key, minlength=NR)
     offs = np.zeros(NR + 1, dtype=np.int64)
