@@ -63,25 +63,39 @@ void oracle_neighbours(int32_t n_segments, int32_t n_rows, const int32_t *row_of
     int32_t n = row_offsets[n_segments];
     for (int32_t i = 0; i < n; ++i) { up[i] = -1; dn[i] = -1; }
 
-    #pragma omp parallel for schedule(dynamic, 16)
+    #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t seg = 0; seg < n_segments; ++seg) {
         int32_t r = seg % n_rows;
         if (r == 0 || r == n_rows - 1) continue;
         int32_t h0 = row_offsets[seg], h1 = row_offsets[seg + 1];
         int32_t u0 = row_offsets[seg + 1], u1 = row_offsets[seg + 2];   /* row r+1 */
         int32_t d0 = row_offsets[seg - 1], d1 = row_offsets[seg];       /* row r-1 */
+        /* the down clusters inside h's window, in ascending id: the window   */
+        /* test of d does not depend on u, so it is made once per h and the   */
+        /* pair loop below visits the same d, in the same order, as a test    */
+        /* repeated for every u would                                         */
+        int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(d1 - d0 + 1));
+        float *dby = (float *)malloc(sizeof(float) * (size_t)(d1 - d0 + 1));
+        float *dbz = (float *)malloc(sizeof(float) * (size_t)(d1 - d0 + 1));
         for (int32_t h = h0; h < h1; ++h) {
             int found = 0;
             float best_q = 0.0f;
             int32_t best_u = -1, best_d = -1;
+            int32_t nd = 0;
+            for (int32_t d = d0; d < d1; ++d) {
+                float by = y[h] - y[d];
+                float bz = z[h] - z[d];
+                if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
+                dl[nd] = d; dby[nd] = by; dbz[nd] = bz; ++nd;
+            }
             for (int32_t u = u0; u < u1; ++u) {
                 float ay = y[u] - y[h];
                 float az = z[u] - z[h];
                 if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
-                for (int32_t d = d0; d < d1; ++d) {
-                    float by = y[h] - y[d];
-                    float bz = z[h] - z[d];
-                    if (!(fabsf(by) <= win_y && fabsf(bz) <= win_z)) continue;
+                for (int32_t k = 0; k < nd; ++k) {
+                    int32_t d = dl[k];
+                    float by = dby[k];
+                    float bz = dbz[k];
                     float dy = ay - by;
                     float dz = az - bz;
                     if (!(fabsf(dy) <= cut_y && fabsf(dz) <= cut_z)) continue;
@@ -97,6 +111,7 @@ void oracle_neighbours(int32_t n_segments, int32_t n_rows, const int32_t *row_of
             up[h] = best_u;
             dn[h] = best_d;
         }
+        free(dl); free(dby); free(dbz);
     }
 }
 
