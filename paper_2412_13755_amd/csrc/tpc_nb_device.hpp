@@ -12,16 +12,24 @@
 //
 // Design: one workgroup per h-row (frame, sector, row) segment.  Each of
 // the two neighbouring rows is put on a y-z cell grid sized from the data
-// (cell edges at least 1.01 x the window) and counting-sorted by cell; then
-// every thread takes clusters h of its row and scans the up-row cells that
-// overlap its window, and for each up candidate in the window, the down-row
-// cells that overlap the cut interval around the straight-line prediction.
-// Rows of up to TPC_LDS_ROW clusters are binned by the query workgroup
-// itself into LDS, both rows in one counting sort with up to four cells per
-// cluster (the row pair is read once, coalesced, and every candidate access
-// is an LDS access); larger rows use a cell-sorted copy in global memory
-// written beforehand by nb_bin (at most one cell per cluster and
-// TPC_CELL_CAP cells per row).  The cells scanned are derived from the
+// and counting-sorted by cell; then every thread takes clusters h of its row
+// and scans the up-row cells that overlap its window, and for each up
+// candidate in the window, the down-row cells that overlap the cut interval
+// around the straight-line prediction.  Rows of up to TPC_LDS_ROW clusters
+// are binned by the query workgroup itself into LDS, both rows in one
+// counting sort with up to four cells per cluster (the row pair is read
+// once, coalesced, and every candidate access is an LDS access).
+//
+// Dense rows (a neighbouring row of more than TPC_LDS_ROW clusters, as in a
+// continuous-readout time frame with ~10^4 clusters per pad row): the h-row
+// and both neighbouring rows are first counting-sorted by z alone into a
+// global copy (nb_bin_seg).  The query workgroup then walks its h-row in
+// slabs of consecutive sorted clusters (nearby z); a slab's window in z
+// selects a contiguous range of each neighbouring row's sorted copy, which
+// is binned into LDS exactly as a small row pair, and the slab's clusters
+// are searched there.  A slab whose ranges exceed the LDS is halved; a
+// slab of the smallest size that still does not fit is searched directly
+// in the global sorted copies.  The cells scanned are derived from the
 // window and cut intervals with a safety margin (see best_pair), so they
 // over-cover the candidates and the exact predicates decide.
 #include "tpc_internal.hpp"
@@ -41,16 +49,17 @@ __device__ inline int cell_coord(float v, float v0, float iw, int n) {
     return (int)c;                                  // floor for c >= 0
 }
 
-// Grid of one row: cell edges >= 1.01 x the window, at most min(n, cap)
-// cells.  ext = (ymin, ymax, zmin, zmax) of the finite coordinates.
+// Grid of one row: cell edges >= edge x the window (1.01 by default), at
+// most min(n, cap) cells.  ext = (ymin, ymax, zmin, zmax) of the finite
+// coordinates.
 __device__ inline SegGrid row_grid(float ymin, float ymax, float zmin, float zmax, int n, int cap,
-                                   float win_y, float win_z) {
+                                   float win_y, float win_z, float edge = 1.01f) {
 #pragma clang fp contract(off)
     if (!(ymin <= ymax)) { ymin = 0.f; ymax = 0.f; }
     if (!(zmin <= zmax)) { zmin = 0.f; zmax = 0.f; }
     const int c = n < cap ? n : cap;
     const float ry = ymax - ymin, rz = zmax - zmin;
-    const float fz = rz / (1.01f * win_z), fy = ry / (1.01f * win_y);
+    const float fz = rz / (edge * win_z), fy = ry / (edge * win_y);
     const int nzmax = fz >= (float)c ? c : (fz >= 1.0f ? (int)fz : 1);
     const int nymax = fy >= (float)c ? c : (fy >= 1.0f ? (int)fy : 1);
     const int nz = nzmax;
@@ -130,20 +139,33 @@ __device__ inline void row_sort(const float *__restrict__ y, const float *__rest
 }
 
 // Rows of at most this many clusters are binned in LDS by the query
-// workgroup itself; larger rows go through the global cell-sorted copy.
+// workgroup itself; an h-row with a larger neighbouring row is dense.
 #define TPC_LDS_ROW 1024
 
 __device__ inline int seg_size(const int32_t *off, int s) { return off[s + 1] - off[s]; }
 
-// Does the query of h-row `seg` use the global cell-sorted rows?
-__device__ inline bool query_global(const int32_t *off, int seg, int n_rows) {
+// Is `seg` a non-empty interior h-row with a neighbouring row of more than
+// TPC_LDS_ROW clusters (searched in slabs over the z-sorted rows)?
+__device__ inline bool dense_hrow(const int32_t *off, int seg, int n_rows) {
     const int r = seg % n_rows;
-    if (r == 0 || r == n_rows - 1) return false;
+    if (r == 0 || r == n_rows - 1 || seg_size(off, seg) == 0) return false;
     return seg_size(off, seg - 1) > TPC_LDS_ROW || seg_size(off, seg + 1) > TPC_LDS_ROW;
 }
 
-// Global binning of segment `seg`, done only when a neighbouring h-row's
-// query needs it (whole workgroup; contains barriers; L: LDS scratch).
+// Grid of a row in z alone: min(n, cap) cells of equal length over the
+// finite z extent (ny = 1, so every y falls in the one cell column).
+__device__ inline SegGrid zrow_grid(float zmin, float zmax, int n, int cap) {
+#pragma clang fp contract(off)
+    if (!(zmin <= zmax)) { zmin = 0.f; zmax = 0.f; }
+    const int c = n < cap ? n : cap;
+    const float rz = zmax - zmin;
+    const int nz = (rz > 0.f && c > 1) ? c : 1;
+    return SegGrid{0.f, zmin, 0.f, nz > 1 ? (float)nz / rz : 0.f, 1, nz, 0, 0};
+}
+
+// z-sorted global copy of segment `seg`, made only when it is a dense h-row
+// or a neighbouring row of one (whole workgroup; contains barriers; L: LDS
+// scratch).
 struct BinLds {
     int cnt[TPC_CELL_CAP];
     float red[4][TPC_BLOCK / TPC_WAVE];
@@ -160,8 +182,8 @@ __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict
     float (*red)[TPC_BLOCK / TPC_WAVE] = L.red;
     int *scan_sh = L.scan_sh;
     const int r = seg % n_rows;
-    const bool need = (r >= 1 && query_global(off, seg - 1, n_rows)) ||
-                      (r <= n_rows - 2 && query_global(off, seg + 1, n_rows));
+    const bool need = dense_hrow(off, seg, n_rows) || (r >= 1 && dense_hrow(off, seg - 1, n_rows)) ||
+                      (r <= n_rows - 2 && dense_hrow(off, seg + 1, n_rows));
     if (!need) return;
     __syncthreads();                 // LDS reuse across calls in a persistent loop
     const int a = off[seg], b = off[seg + 1], n = b - a;
@@ -176,7 +198,7 @@ __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict
     }
     float ext[4];
     row_extent(y, z, a, b, red, ext);
-    const SegGrid g = row_grid(ext[0], ext[1], ext[2], ext[3], n, TPC_CELL_CAP, win_y, win_z);
+    const SegGrid g = zrow_grid(ext[2], ext[3], n, TPC_CELL_CAP);
     if (threadIdx.x == 0) grid[seg] = g;
     row_sort(y, z, a, b, g, cnt, scan_sh, sy, sz, sid, cstart + base, a);
 }
@@ -338,43 +360,70 @@ struct PairLdsT {
 using PairLds = PairLdsT<TPC_LDS_ROW, TPC_LDS_CELLS>;
 using PairLdsSmall = PairLdsT<TPC_LDS_ROW_S, TPC_LDS_CELLS_S>;
 
-// Bins the down row [ra0, rb0) and the up row [ra1, rb1) with one LDS
+// Bins a down row of n0 clusters and an up row of n1 clusters with one LDS
 // counting sort over the concatenated cell range (whole workgroup; contains
-// barriers).  On return the down row occupies cells [0, C0) with grid gd, the
-// up row cells C0 + [0, C1) with grid gu, and cell c holds positions
-// [cs[c], cs[c+1]) of y/z/rel.
+// barriers).  src(k, y, z, rel) gives cluster k of the pair (the down row
+// first) and its id relative to its row's first cluster.  On return the
+// down row occupies cells [0, C0) with grid gd, the up row cells C0 + [0, C1)
+// with grid gu, and cell c holds positions [cs[c], cs[c+1]) of y/z/rel.
+// Cell edges are at least `edge` windows.
 __device__ inline int pair_cell(float yv, float zv, const SegGrid &g) {
     return cell_coord(yv, g.y0, g.iwy, g.ny) * g.nz + cell_coord(zv, g.z0, g.iwz, g.nz);
 }
 
 template <int CELLS>
 __device__ inline SegGrid pair_grid(float ymin, float ymax, float zmin, float zmax, int n, float win_y,
-                                    float win_z) {
+                                    float win_z, float edge) {
     if (n == 0) return SegGrid{0.f, 0.f, 0.f, 0.f, 0, 0, 0, 0};
     const int cap = 4 * n < CELLS ? 4 * n : CELLS;
-    return row_grid(ymin, ymax, zmin, zmax, cap, cap, win_y, win_z);
+    return row_grid(ymin, ymax, zmin, zmax, cap, cap, win_y, win_z, edge);
 }
 
-template <int ROW, int CELLS>
-__device__ inline void pair_bin(const float *__restrict__ y, const float *__restrict__ z, int ra0, int rb0,
-                                int ra1, int rb1, float win_y, float win_z, PairLdsT<ROW, CELLS> &L,
-                                SegGrid &gd, SegGrid &gu, int &C0) {
+// The clusters of two row ranges of the frame arrays: [ra0, ra0 + n0), then
+// [ra1, ...); relative ids are the offsets in the range.
+struct RowPairSrc {
+    const float *y, *z;
+    int ra0, n0, ra1;
+    __device__ void operator()(int k, float &vy, float &vz, uint16_t &rel) const {
+        const int i = k < n0 ? ra0 + k : ra1 + (k - n0);
+        vy = y[i];
+        vz = z[i];
+        rel = (uint16_t)(k < n0 ? k : k - n0);
+    }
+};
+
+// Two position ranges of the z-sorted copies (sy, sz, sid): [pa0, pa0 + n0)
+// of the down row, whose first cluster id is base0, then [pa1, ...) of the
+// up row (base1).
+struct SortedPairSrc {
+    const float *sy, *sz;
+    const int32_t *sid;
+    int pa0, n0, pa1, base0, base1;
+    __device__ void operator()(int k, float &vy, float &vz, uint16_t &rel) const {
+        const int p = k < n0 ? pa0 + k : pa1 + (k - n0);
+        vy = sy[p];
+        vz = sz[p];
+        rel = (uint16_t)(sid[p] - (k < n0 ? base0 : base1));
+    }
+};
+
+template <int ROW, int CELLS, class Src>
+__device__ inline void pair_bin(const Src &src, int n0, int n1, float win_y, float win_z, float edge,
+                                PairLdsT<ROW, CELLS> &L, SegGrid &gd, SegGrid &gu, int &C0) {
 #pragma clang fp contract(off)
     constexpr int PT = 2 * ROW / TPC_BLOCK;      // row-pair clusters per thread
     const int tid = threadIdx.x;
-    const int n0 = rb0 - ra0, n1 = rb1 - ra1, nt = n0 + n1;
+    const int nt = n0 + n1;
     // both rows are read once, into registers (one global round trip)
     float vy[PT], vz[PT];
+    uint16_t vr[PT];
 #pragma unroll
     for (int j = 0; j < PT; ++j) {
         const int k = tid + j * TPC_BLOCK;
         vy[j] = 0.f;
         vz[j] = 0.f;
-        if (k < nt) {
-            const int i = k < n0 ? ra0 + k : ra1 + (k - n0);
-            vy[j] = y[i];
-            vz[j] = z[i];
-        }
+        vr[j] = 0;
+        if (k < nt) src(k, vy[j], vz[j], vr[j]);
     }
     // finite extents of both rows
     float e[8] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
@@ -406,8 +455,8 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
             v = (j & 1) ? fmaxf(v, L.red[j][w]) : fminf(v, L.red[j][w]);
         e[j] = v;
     }
-    gd = pair_grid<CELLS>(e[0], e[1], e[2], e[3], n0, win_y, win_z);
-    gu = pair_grid<CELLS>(e[4], e[5], e[6], e[7], n1, win_y, win_z);
+    gd = pair_grid<CELLS>(e[0], e[1], e[2], e[3], n0, win_y, win_z, edge);
+    gu = pair_grid<CELLS>(e[4], e[5], e[6], e[7], n1, win_y, win_z, edge);
     C0 = gd.ny * gd.nz;
     const int C = C0 + gu.ny * gu.nz;
     for (int c = tid; c < C + 2; c += TPC_BLOCK) L.cs[c] = 0;
@@ -444,7 +493,7 @@ __device__ inline void pair_bin(const float *__restrict__ y, const float *__rest
             const int slot = atomicAdd(&L.cs[cell[j] + 1], 1);
             L.y[slot] = vy[j];
             L.z[slot] = vz[j];
-            L.rel[slot] = (uint16_t)(k < n0 ? k : k - n0);
+            L.rel[slot] = vr[j];
         }
     }
     __syncthreads();
@@ -459,13 +508,129 @@ __device__ inline bool small_pair(const int32_t *off, int seg) {
 // Which segments a query call handles.
 enum NbClass { NB_ALL = 0, NB_SMALL = 1, NB_NOT_SMALL = 2 };
 
+// Tunables of the dense-row search: h clusters per slab (the slab's
+// clusters are consecutive in the z-sorted h-row), the smallest slab before
+// the global fallback, and the LDS cell edge of a slab's row pair in windows.
+#ifndef TPC_NB_SLAB
+#define TPC_NB_SLAB 512
+#endif
+#ifndef TPC_NB_SLAB_MIN
+#define TPC_NB_SLAB_MIN 64
+#endif
+#ifndef TPC_NB_DENSE_EDGE
+#define TPC_NB_DENSE_EDGE 0.5f
+#endif
+
+// Positions [x, y) of the z-sorted copy of a row (grid g, cell starts cs)
+// that hold every cluster with z in [lo, hi] (whole cells: cell_coord is
+// monotonic, so a cluster with z in the interval lies in a cell between
+// those of lo and hi).
+__device__ inline int2 zrange(const SegGrid &g, const int32_t *cs, float lo, float hi) {
+    if (g.ny <= 0) return make_int2(0, 0);
+    const int c0 = cell_coord(lo, g.z0, g.iwz, g.nz), c1 = cell_coord(hi, g.z0, g.iwz, g.nz);
+    return make_int2(cs[c0], cs[c1 + 1]);
+}
+
+// Dense h-row `seg` (whole workgroup; contains barriers): slabs of
+// consecutive clusters of its z-sorted copy.  A partner of h passes the
+// window test only if its z lies within win_z of z_h (the difference is one
+// rounding), so the neighbouring rows' clusters with z in the slab's finite
+// z extent widened by win_z and a margin far above that rounding hold every
+// candidate; their positions form one range of each z-sorted copy.  Both
+// ranges are binned into LDS and the slab's clusters searched there; a slab
+// whose ranges do not fit is halved, and at TPC_NB_SLAB_MIN clusters it is
+// searched in the global copies instead.  The outcome of best_pair does not
+// depend on which superset of the candidates it is given.
+template <int ROW, int CELLS>
+__device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, float win_y, float win_z,
+                                      float cut_y, float cut_z, const SegGrid *__restrict__ grid,
+                                      const int32_t *__restrict__ cstart, const float *__restrict__ sy,
+                                      const float *__restrict__ sz, const int32_t *__restrict__ sid,
+                                      int32_t *__restrict__ up, int32_t *__restrict__ dn,
+                                      PairLdsT<ROW, CELLS> &L) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const int a = off[seg], n = off[seg + 1] - a;
+    const int sd = seg - 1, su = seg + 1;
+    const int based = off[sd], baseu = off[su];
+    const SegGrid gdg = grid[sd], gug = grid[su];
+    const int32_t *csd = cstart + based + sd;
+    const int32_t *csu = cstart + baseu + su;
+    // relative ids are 16-bit in LDS
+    const bool rel_ok = seg_size(off, sd) <= 65536 && seg_size(off, su) <= 65536;
+    int P = TPC_NB_SLAB;
+    for (int p0 = 0; p0 < n;) {
+        const int pn = n - p0 < P ? n - p0 : P;
+        float lo = INFINITY, hi = -INFINITY;
+        for (int k = tid; k < pn; k += TPC_BLOCK) {
+            const float zv = sz[a + p0 + k];
+            if (isfinite(zv)) { lo = fminf(lo, zv); hi = fmaxf(hi, zv); }
+        }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        __syncthreads();             // the previous slab's search is done with L
+        if ((tid & (TPC_WAVE - 1)) == 0) {
+            L.red[0][tid / TPC_WAVE] = lo;
+            L.red[1][tid / TPC_WAVE] = hi;
+        }
+        __syncthreads();
+        lo = L.red[0][0];
+        hi = L.red[1][0];
+        for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w) {
+            lo = fminf(lo, L.red[0][w]);
+            hi = fmaxf(hi, L.red[1][w]);
+        }
+        __syncthreads();             // everyone has read L.red
+        int2 rd = make_int2(0, 0), ru = make_int2(0, 0);
+        if (lo <= hi) {
+            const float m = 1e-5f * (fmaxf(fabsf(lo), fabsf(hi)) + win_z + cut_z) + 1e-6f;
+            const float w = win_z + m;
+            rd = zrange(gdg, csd, lo - w, hi + w);
+            ru = zrange(gug, csu, lo - w, hi + w);
+        }
+        const int nd = rd.y - rd.x, nu = ru.y - ru.x;
+        const bool fits = rel_ok && nd <= ROW && nu <= ROW;
+        if (!fits && P > TPC_NB_SLAB_MIN) {
+            P >>= 1;
+            continue;
+        }
+        if (fits) {
+            SegGrid gd, gu;
+            int C0;
+            pair_bin(SortedPairSrc{sy, sz, sid, rd.x, nd, ru.x, based, baseu}, nd, nu, win_y, win_z,
+                     TPC_NB_DENSE_EDGE, L, gd, gu, C0);
+            for (int k = tid; k < pn; k += TPC_BLOCK) {
+                const int p = a + p0 + k;
+                const Best bt = best_pair(sy[p], sz[p], L.y, L.z, L.rel, L.cs + C0, gu, baseu, L.y, L.z,
+                                          L.rel, L.cs, gd, based, win_y, win_z, cut_y, cut_z);
+                const int32_t h = sid[p];
+                up[h] = bt.u;
+                dn[h] = bt.d;
+            }
+        } else {
+            for (int k = tid; k < pn; k += TPC_BLOCK) {
+                const int p = a + p0 + k;
+                const Best bt = best_pair(sy[p], sz[p], sy, sz, sid, csu, gug, 0, sy, sz, sid, csd, gdg, 0,
+                                          win_y, win_z, cut_y, cut_z);
+                const int32_t h = sid[p];
+                up[h] = bt.u;
+                dn[h] = bt.d;
+            }
+        }
+        p0 += pn;
+        P = TPC_NB_SLAB;
+    }
+    __syncthreads();                 // LDS reuse across calls in a persistent loop
+}
+
 // Best triplet of every cluster of h-row `seg` (whole workgroup; contains
 // barriers; L is the workgroup's LDS scratch).  When both neighbouring rows
 // hold at most ROW clusters the workgroup bins them itself into LDS
 // (coalesced reads, then every candidate access is an LDS access);
-// otherwise it reads the global cell-sorted rows written by nb_bin_seg.
-// cls selects the segments handled (the others return at once), so that a
-// small-LDS and a large-LDS launch can share the rows between them.
+// otherwise (a dense row, only in the TPC_LDS_ROW form) it searches slabs
+// of the z-sorted rows written by nb_bin_seg.  cls selects the segments
+// handled (the others return at once), so that a small-LDS and a large-LDS
+// launch can share the rows between them.
 template <int ROW, int CELLS>
 __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, int32_t n_rows,
                                     const float *__restrict__ y, const float *__restrict__ z,
@@ -475,6 +640,7 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
                                     const int32_t *__restrict__ sid, int32_t *__restrict__ up,
                                     int32_t *__restrict__ dn, PairLdsT<ROW, CELLS> &L, NbClass cls) {
 #pragma clang fp contract(off)
+    static_assert(ROW == TPC_LDS_ROW || ROW == TPC_LDS_ROW_S, "row-pair LDS forms");
     const int r = seg % n_rows;
     const int a = off[seg], b = off[seg + 1];
     const bool edge = r == 0 || r == n_rows - 1;
@@ -495,7 +661,8 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
         }
         SegGrid gd, gu;
         int C0;
-        pair_bin(y, z, ra0, a, ra1, off[seg + 2], win_y, win_z, L, gd, gu, C0);
+        pair_bin(RowPairSrc{y, z, ra0, a - ra0, ra1}, a - ra0, off[seg + 2] - ra1, win_y, win_z, 1.01f, L,
+                 gd, gu, C0);
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
             if (i >= a + TPC_BLOCK) {
                 hy = y[i];
@@ -509,15 +676,8 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
         __syncthreads();             // LDS reuse across calls in a persistent loop
         return;
     }
-    const SegGrid gu = grid[seg + 1], gd = grid[seg - 1];
-    const int32_t *csu = cstart + off[seg + 1] + seg + 1;
-    const int32_t *csd = cstart + off[seg - 1] + seg - 1;
-    for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
-        const Best bt = best_pair(y[i], z[i], sy, sz, sid, csu, gu, 0, sy, sz, sid, csd, gd, 0, win_y,
-                                  win_z, cut_y, cut_z);
-        up[i] = bt.u;
-        dn[i] = bt.d;
-    }
+    if constexpr (ROW == TPC_LDS_ROW)
+        nb_query_dense(seg, off, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid, up, dn, L);
 }
 
 }  // namespace tpc_nb
