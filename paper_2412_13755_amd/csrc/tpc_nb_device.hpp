@@ -232,14 +232,17 @@ __device__ inline bool better(float q, int32_t u, int32_t d, const Best &b) {
 // paired with that list.  If more down clusters are in the window, each up
 // candidate instead scans the down-row cells that overlap the cut interval
 // around its straight-line prediction c = h - (A / B)(u - h), of half-width
-// A (A + B) / 2 cut.  Cells scanned are those overlapping the window (or
+// A (A + B) / 2 cut.  Without LIST (rows dense enough that the list would
+// overflow anyway) the per-up-candidate scan is used directly; the pairs
+// visited, and so the result, are the same.  Cells scanned are those
+// overlapping the window (or
 // cut) interval widened by a margin m far above the rounding of the
 // predicates and of c; as cell_coord is monotonic, every cluster that can
 // pass the exact predicates is visited.  A cluster h with a non-finite
 // coordinate fails every window, so it is skipped.
 #define TPC_NB_DLIST 8
 
-template <int A = 1, int B = 1, class FP, class IP, class CP>
+template <int A = 1, int B = 1, bool LIST = true, class FP, class IP, class CP>
 __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS, const SegGrid &gu,
                                  int32_t ubase, FP DY, FP DZ, IP DI, CP DCS, const SegGrid &gd,
                                  int32_t dbase, float win_y, float win_z, float cut_y, float cut_z) {
@@ -263,7 +266,7 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
 #pragma unroll
     for (int j = 0; j < TPC_NB_DLIST; ++j) { lb[j][0] = 0.f; lb[j][1] = 0.f; ld[j] = -1; }
     int nd = 0;
-    {
+    if constexpr (LIST) {
         const int y0 = cell_coord(yh - wdy, gd.y0, gd.iwy, gd.ny), y1 = cell_coord(yh + wdy, gd.y0, gd.iwy, gd.ny);
         const int z0 = cell_coord(zh - wdz, gd.z0, gd.iwz, gd.nz), z1 = cell_coord(zh + wdz, gd.z0, gd.iwz, gd.nz);
         for (int iy = y0; iy <= y1; ++iy) {
@@ -282,8 +285,8 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
             }
         }
     }
-    if (nd == 0) return best;
-    const bool listed = nd <= TPC_NB_DLIST;
+    if (LIST && nd == 0) return best;
+    const bool listed = LIST && nd <= TPC_NB_DLIST;
     const int yu0 = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny), yu1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
     const int zu0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz), zu1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
     for (int iyu = yu0; iyu <= yu1; ++iyu) {
@@ -345,7 +348,9 @@ __device__ inline Best best_pair(float yh, float zh, FP UY, FP UZ, IP UI, CP UCS
 // the cells around h hold few candidates.  Two sizes: the small one keeps
 // the workgroup's LDS at 18 KB (8 workgroups per CU), the large one at
 // 37 KB for rows of up to TPC_LDS_ROW clusters.
+#ifndef TPC_LDS_CELLS
 #define TPC_LDS_CELLS 2048
+#endif
 #define TPC_LDS_ROW_S 512
 #define TPC_LDS_CELLS_S 1024
 
@@ -366,7 +371,7 @@ using PairLdsSmall = PairLdsT<TPC_LDS_ROW_S, TPC_LDS_CELLS_S>;
 // first) and its id relative to its row's first cluster.  On return the
 // down row occupies cells [0, C0) with grid gd, the up row cells C0 + [0, C1)
 // with grid gu, and cell c holds positions [cs[c], cs[c+1]) of y/z/rel.
-// Cell edges are at least `edge` windows.
+// Cell edges are at least edge_d (down row) and edge_u (up row) windows.
 __device__ inline int pair_cell(float yv, float zv, const SegGrid &g) {
     return cell_coord(yv, g.y0, g.iwy, g.ny) * g.nz + cell_coord(zv, g.z0, g.iwz, g.nz);
 }
@@ -408,7 +413,8 @@ struct SortedPairSrc {
 };
 
 template <int ROW, int CELLS, class Src>
-__device__ inline void pair_bin(const Src &src, int n0, int n1, float win_y, float win_z, float edge,
+__device__ inline void pair_bin(const Src &src, int n0, int n1, float win_y, float win_z, float edge_d,
+                                float edge_u,
                                 PairLdsT<ROW, CELLS> &L, SegGrid &gd, SegGrid &gu, int &C0) {
 #pragma clang fp contract(off)
     constexpr int PT = 2 * ROW / TPC_BLOCK;      // row-pair clusters per thread
@@ -455,8 +461,8 @@ __device__ inline void pair_bin(const Src &src, int n0, int n1, float win_y, flo
             v = (j & 1) ? fmaxf(v, L.red[j][w]) : fminf(v, L.red[j][w]);
         e[j] = v;
     }
-    gd = pair_grid<CELLS>(e[0], e[1], e[2], e[3], n0, win_y, win_z, edge);
-    gu = pair_grid<CELLS>(e[4], e[5], e[6], e[7], n1, win_y, win_z, edge);
+    gd = pair_grid<CELLS>(e[0], e[1], e[2], e[3], n0, win_y, win_z, edge_d);
+    gu = pair_grid<CELLS>(e[4], e[5], e[6], e[7], n1, win_y, win_z, edge_u);
     C0 = gd.ny * gd.nz;
     const int C = C0 + gu.ny * gu.nz;
     for (int c = tid; c < C + 2; c += TPC_BLOCK) L.cs[c] = 0;
@@ -505,21 +511,47 @@ __device__ inline bool small_pair(const int32_t *off, int seg) {
     return seg_size(off, seg - 1) <= TPC_LDS_ROW_S && seg_size(off, seg + 1) <= TPC_LDS_ROW_S;
 }
 
-// Which segments a query call handles.
-enum NbClass { NB_ALL = 0, NB_SMALL = 1, NB_NOT_SMALL = 2 };
+// Which segments a query call handles: rows whose neighbour rows fit the
+// small LDS form, the other rows whose neighbour rows fit the large form,
+// both, or the dense rows (a neighbour row of more than TPC_LDS_ROW).
+enum NbClass { NB_NOT_DENSE = 0, NB_SMALL = 1, NB_LARGE = 2, NB_DENSE = 3 };
 
 // Tunables of the dense-row search: h clusters per slab (the slab's
 // clusters are consecutive in the z-sorted h-row), the smallest slab before
-// the global fallback, and the LDS cell edge of a slab's row pair in windows.
+// the global fallback, the row-pair LDS size of a slab, and the LDS cell
+// edges of a slab's down and up rows in windows (the down row is only
+// searched around predictions, in boxes of twice the cuts; the up row in
+// windows).
 #ifndef TPC_NB_SLAB
 #define TPC_NB_SLAB 512
 #endif
 #ifndef TPC_NB_SLAB_MIN
 #define TPC_NB_SLAB_MIN 64
 #endif
-#ifndef TPC_NB_DENSE_EDGE
-#define TPC_NB_DENSE_EDGE 0.5f
+#ifndef TPC_NB_DENSE_ROW
+#define TPC_NB_DENSE_ROW 1024
 #endif
+#ifndef TPC_NB_DENSE_CELLS
+#define TPC_NB_DENSE_CELLS 2048
+#endif
+#ifndef TPC_NB_DENSE_EDGE_D
+#define TPC_NB_DENSE_EDGE_D 0.25f
+#endif
+#ifndef TPC_NB_DENSE_EDGE_U
+#define TPC_NB_DENSE_EDGE_U 0.34f
+#endif
+#define TPC_NB_QUEUE (2 * TPC_WAVE)      // (h, up candidate) ring of a wavefront
+
+// LDS of a dense-row workgroup: the slab's row pair, the slab's clusters h,
+// their best keys so far and one (h, up candidate) ring per wavefront.
+template <int ROW, int CELLS, int S>
+struct DenseLdsT {
+    PairLdsT<ROW, CELLS> pair;
+    float2 hyz[S];
+    unsigned long long best[S];
+    uint32_t q[TPC_BLOCK / TPC_WAVE][TPC_NB_QUEUE];
+};
+using DenseLds = DenseLdsT<TPC_NB_DENSE_ROW, TPC_NB_DENSE_CELLS, TPC_NB_SLAB>;
 
 // Positions [x, y) of the z-sorted copy of a row (grid g, cell starts cs)
 // that hold every cluster with z in [lo, hi] (whole cells: cell_coord is
@@ -531,24 +563,187 @@ __device__ inline int2 zrange(const SegGrid &g, const int32_t *cs, float lo, flo
     return make_int2(cs[c0], cs[c1 + 1]);
 }
 
+// Key of a passing triplet: the score's bit pattern (q >= +0, where the
+// bits order like the values), then the up and down ids relative to their
+// rows' first ids; the smallest key is the lexicographic best (q, u, d).
+__device__ inline unsigned long long triplet_key(float q, uint32_t urel, uint32_t drel) {
+    return ((unsigned long long)__float_as_uint(q) << 32) | (urel << 16) | drel;
+}
+
+// Search of one slab (clusters [pb, pb + pn) of the h-row's z-sorted copy)
+// whose row pair is binned in L.pair (whole workgroup; contains barriers).
+// The same candidates and the same single-precision operations as
+// best_pair<1, 1>, organised for lockstep wavefronts: each wavefront owns a
+// share of the slab's clusters and its lanes walk the up-row window cells of
+// one cluster h each, taking a new h when theirs is exhausted; (h, u) pairs
+// passing the window go to the wavefront's ring by ballot rank, and every
+// 64 of them one round scans, a pair per lane, the down-row cells of the
+// pair's prediction box.  A pair's best triplet key goes to its h by a
+// 64-bit LDS atomicMin, so the order of the rounds does not matter.
+template <int ROW, int CELLS, int S>
+__device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy, const float *__restrict__ sz,
+                                   const int32_t *__restrict__ sid, int32_t baseu, int32_t based,
+                                   const SegGrid &gu, const SegGrid &gd, int C0, float win_y, float win_z,
+                                   float cut_y, float cut_z, int32_t *__restrict__ up,
+                                   int32_t *__restrict__ dn, DenseLdsT<ROW, CELLS, S> &L) {
+#pragma clang fp contract(off)
+    constexpr unsigned long long NONE = ~0ull;
+    constexpr int NW = TPC_BLOCK / TPC_WAVE;
+    const int tid = threadIdx.x, lane = tid & (TPC_WAVE - 1), wid = tid / TPC_WAVE;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int k = tid; k < pn; k += TPC_BLOCK) {
+        L.hyz[k] = make_float2(sy[pb + k], sz[pb + k]);
+        L.best[k] = NONE;
+    }
+    __syncthreads();
+    const float *Y = L.pair.y, *Z = L.pair.z;
+    const uint16_t *R = L.pair.rel;
+    const int32_t *UCS = L.pair.cs + C0, *DCS = L.pair.cs;
+    uint32_t *Q = L.q[wid];
+    const bool grids = gu.ny > 0 && gd.ny > 0;
+    const int per = (pn + NW - 1) / NW;
+    const int hb = wid * per < pn ? wid * per : pn;
+    const int he = hb + per < pn ? hb + per : pn;
+    int cursor = hb;                 // next h of this wavefront (same in every lane)
+    int qh = 0, qn = 0;              // ring head and count (same in every lane)
+    int hl = -1;                     // the lane's h, its window cells and position
+    float yh = 0.f, zh = 0.f;
+    int iy = 0, iy1 = -1, zc0 = 0, zc1 = 0, k = 0, ke = 0;
+    while (true) {
+        // the lane's next up candidate; an exhausted h is released
+        if (hl >= 0) {
+            while (k == ke && iy < iy1) {
+                ++iy;
+                k = UCS[iy * gu.nz + zc0];
+                ke = UCS[iy * gu.nz + zc1 + 1];
+            }
+            if (k == ke) hl = -1;
+        }
+        // lanes without an h take the wavefront's next ones
+        const unsigned long long nm = __ballot(hl < 0);
+        if (hl < 0) {
+            const int idx = cursor + __popcll(nm & below);
+            if (idx < he) {
+                hl = idx;
+                const float2 h = L.hyz[idx];
+                yh = h.x;
+                zh = h.y;
+                iy = 0; iy1 = -1; k = 0; ke = 0;
+                if (grids && isfinite(yh) && isfinite(zh)) {
+                    const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
+                    const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
+                    const float wuy = win_y + my, wuz = win_z + mz;
+                    iy = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny);
+                    iy1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
+                    zc0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz);
+                    zc1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
+                    k = UCS[iy * gu.nz + zc0];
+                    ke = UCS[iy * gu.nz + zc1 + 1];
+                    while (k == ke && iy < iy1) {
+                        ++iy;
+                        k = UCS[iy * gu.nz + zc0];
+                        ke = UCS[iy * gu.nz + zc1 + 1];
+                    }
+                }
+                if (k == ke) hl = -1;    // no candidate at all: the h keeps no triplet
+            }
+        }
+        cursor += __popcll(nm);
+        if (cursor > he) cursor = he;
+        const bool live = __ballot(hl >= 0) != 0ull;
+        if (!live && qn == 0 && cursor >= he) break;
+        if (live && qn < TPC_WAVE) {
+            // one window test per lane; passing pairs enter the ring
+            bool push = false;
+            uint32_t item = 0;
+            if (hl >= 0) {
+                const float ay = Y[k] - yh;
+                const float az = Z[k] - zh;
+                push = fabsf(ay) <= win_y && fabsf(az) <= win_z;
+                item = ((uint32_t)hl << 16) | (uint32_t)k;
+                ++k;
+            }
+            const unsigned long long pm = __ballot(push);
+            if (push) Q[(qh + qn + __popcll(pm & below)) & (TPC_NB_QUEUE - 1)] = item;
+            qn += __popcll(pm);
+            continue;
+        }
+        if (qn == 0) continue;
+        // one round: a pair per lane, its down-row prediction box scanned
+        __builtin_amdgcn_wave_barrier();
+        const int n = qn < TPC_WAVE ? qn : TPC_WAVE;
+        if (lane < n) {
+            const uint32_t it = Q[(qh + lane) & (TPC_NB_QUEUE - 1)];
+            const int h2 = (int)(it >> 16), ku = (int)(it & 0xFFFFu);
+            const float2 h = L.hyz[h2];
+            const float my = 1e-5f * (fabsf(h.x) + win_y + cut_y) + 1e-6f;
+            const float mz = 1e-5f * (fabsf(h.y) + win_z + cut_z) + 1e-6f;
+            const float ky = cut_y + my, kz = cut_z + mz;
+            const float ty = Y[ku] - h.x;
+            const float tz = Z[ku] - h.y;
+            const float cy = h.x - ty, cz = h.y - tz;
+            const uint32_t urel = R[ku];
+            int iyd = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
+            const int iyd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
+            const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
+            const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
+            int kd = DCS[iyd * gd.nz + zd0], kde = DCS[iyd * gd.nz + zd1 + 1];
+            unsigned long long key = NONE;
+            while (true) {
+                while (kd == kde && iyd < iyd1) {
+                    ++iyd;
+                    kd = DCS[iyd * gd.nz + zd0];
+                    kde = DCS[iyd * gd.nz + zd1 + 1];
+                }
+                if (kd == kde) break;
+                const float by = h.x - Y[kd];
+                const float bz = h.y - Z[kd];
+                if (fabsf(by) <= win_y && fabsf(bz) <= win_z) {
+                    const float dy = ty - by;
+                    const float dz = tz - bz;
+                    if (fabsf(dy) <= cut_y && fabsf(dz) <= cut_z) {
+                        const float qy = dy * dy;
+                        const float qz = dz * dz;
+                        const unsigned long long kk = triplet_key(qy + qz, urel, R[kd]);
+                        key = kk < key ? kk : key;
+                    }
+                }
+                ++kd;
+            }
+            if (key != NONE) atomicMin(&L.best[h2], key);
+        }
+        qh = (qh + n) & (TPC_NB_QUEUE - 1);
+        qn -= n;
+    }
+    __syncthreads();
+    for (int k2 = tid; k2 < pn; k2 += TPC_BLOCK) {
+        const unsigned long long key = L.best[k2];
+        const int32_t h = sid[pb + k2];
+        up[h] = key == NONE ? -1 : baseu + (int32_t)((key >> 16) & 0xFFFFu);
+        dn[h] = key == NONE ? -1 : based + (int32_t)(key & 0xFFFFu);
+    }
+}
+
 // Dense h-row `seg` (whole workgroup; contains barriers): slabs of
 // consecutive clusters of its z-sorted copy.  A partner of h passes the
 // window test only if its z lies within win_z of z_h (the difference is one
 // rounding), so the neighbouring rows' clusters with z in the slab's finite
 // z extent widened by win_z and a margin far above that rounding hold every
 // candidate; their positions form one range of each z-sorted copy.  Both
-// ranges are binned into LDS and the slab's clusters searched there; a slab
-// whose ranges do not fit is halved, and at TPC_NB_SLAB_MIN clusters it is
-// searched in the global copies instead.  The outcome of best_pair does not
-// depend on which superset of the candidates it is given.
-template <int ROW, int CELLS>
-__device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, float win_y, float win_z,
-                                      float cut_y, float cut_z, const SegGrid *__restrict__ grid,
-                                      const int32_t *__restrict__ cstart, const float *__restrict__ sy,
-                                      const float *__restrict__ sz, const int32_t *__restrict__ sid,
-                                      int32_t *__restrict__ up, int32_t *__restrict__ dn,
-                                      PairLdsT<ROW, CELLS> &L) {
+// ranges are binned into LDS and the slab searched there (slab_search); a
+// slab whose ranges do not fit is halved, and at TPC_NB_SLAB_MIN clusters it
+// is searched in the global copies instead.  The outcome does not depend
+// on which superset of the candidates is searched.
+template <int ROW, int CELLS, int S>
+__device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, int32_t n_rows, float win_y,
+                                    float win_z, float cut_y, float cut_z, const SegGrid *__restrict__ grid,
+                                    const int32_t *__restrict__ cstart, const float *__restrict__ sy,
+                                    const float *__restrict__ sz, const int32_t *__restrict__ sid,
+                                    int32_t *__restrict__ up, int32_t *__restrict__ dn,
+                                    DenseLdsT<ROW, CELLS, S> &L) {
 #pragma clang fp contract(off)
+    static_assert(ROW <= 32768 && S <= 65536, "16-bit ring entries");
+    if (!dense_hrow(off, seg, n_rows)) return;
     const int tid = threadIdx.x;
     const int a = off[seg], n = off[seg + 1] - a;
     const int sd = seg - 1, su = seg + 1;
@@ -556,9 +751,9 @@ __device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, 
     const SegGrid gdg = grid[sd], gug = grid[su];
     const int32_t *csd = cstart + based + sd;
     const int32_t *csu = cstart + baseu + su;
-    // relative ids are 16-bit in LDS
+    // relative ids are 16-bit in the keys and in LDS
     const bool rel_ok = seg_size(off, sd) <= 65536 && seg_size(off, su) <= 65536;
-    int P = TPC_NB_SLAB;
+    int P = S;
     for (int p0 = 0; p0 < n;) {
         const int pn = n - p0 < P ? n - p0 : P;
         float lo = INFINITY, hi = -INFINITY;
@@ -570,17 +765,17 @@ __device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, 
         hi = wave_max(hi);
         __syncthreads();             // the previous slab's search is done with L
         if ((tid & (TPC_WAVE - 1)) == 0) {
-            L.red[0][tid / TPC_WAVE] = lo;
-            L.red[1][tid / TPC_WAVE] = hi;
+            L.pair.red[0][tid / TPC_WAVE] = lo;
+            L.pair.red[1][tid / TPC_WAVE] = hi;
         }
         __syncthreads();
-        lo = L.red[0][0];
-        hi = L.red[1][0];
+        lo = L.pair.red[0][0];
+        hi = L.pair.red[1][0];
         for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w) {
-            lo = fminf(lo, L.red[0][w]);
-            hi = fmaxf(hi, L.red[1][w]);
+            lo = fminf(lo, L.pair.red[0][w]);
+            hi = fmaxf(hi, L.pair.red[1][w]);
         }
-        __syncthreads();             // everyone has read L.red
+        __syncthreads();             // everyone has read L.pair.red
         int2 rd = make_int2(0, 0), ru = make_int2(0, 0);
         if (lo <= hi) {
             const float m = 1e-5f * (fmaxf(fabsf(lo), fabsf(hi)) + win_z + cut_z) + 1e-6f;
@@ -598,15 +793,9 @@ __device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, 
             SegGrid gd, gu;
             int C0;
             pair_bin(SortedPairSrc{sy, sz, sid, rd.x, nd, ru.x, based, baseu}, nd, nu, win_y, win_z,
-                     TPC_NB_DENSE_EDGE, L, gd, gu, C0);
-            for (int k = tid; k < pn; k += TPC_BLOCK) {
-                const int p = a + p0 + k;
-                const Best bt = best_pair(sy[p], sz[p], L.y, L.z, L.rel, L.cs + C0, gu, baseu, L.y, L.z,
-                                          L.rel, L.cs, gd, based, win_y, win_z, cut_y, cut_z);
-                const int32_t h = sid[p];
-                up[h] = bt.u;
-                dn[h] = bt.d;
-            }
+                     TPC_NB_DENSE_EDGE_D, TPC_NB_DENSE_EDGE_U, L.pair, gd, gu, C0);
+            slab_search(a + p0, pn, sy, sz, sid, baseu, based, gu, gd, C0, win_y, win_z, cut_y, cut_z, up, dn,
+                        L);
         } else {
             for (int k = tid; k < pn; k += TPC_BLOCK) {
                 const int p = a + p0 + k;
@@ -618,7 +807,7 @@ __device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, 
             }
         }
         p0 += pn;
-        P = TPC_NB_SLAB;
+        P = S;
     }
     __syncthreads();                 // LDS reuse across calls in a persistent loop
 }
@@ -627,10 +816,9 @@ __device__ inline void nb_query_dense(int seg, const int32_t *__restrict__ off, 
 // barriers; L is the workgroup's LDS scratch).  When both neighbouring rows
 // hold at most ROW clusters the workgroup bins them itself into LDS
 // (coalesced reads, then every candidate access is an LDS access);
-// otherwise (a dense row, only in the TPC_LDS_ROW form) it searches slabs
-// of the z-sorted rows written by nb_bin_seg.  cls selects the segments
-// handled (the others return at once), so that a small-LDS and a large-LDS
-// launch can share the rows between them.
+// dense rows are left to nb_dense_seg.  cls selects the segments handled
+// (the others return at once), so that a small-LDS and a large-LDS launch
+// can share the rows between them.
 template <int ROW, int CELLS>
 __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, int32_t n_rows,
                                     const float *__restrict__ y, const float *__restrict__ z,
@@ -645,7 +833,8 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
     const int a = off[seg], b = off[seg + 1];
     const bool edge = r == 0 || r == n_rows - 1;
     const bool small = !edge && a != b && small_pair(off, seg);
-    if ((cls == NB_SMALL && !small) || (cls == NB_NOT_SMALL && small)) return;
+    if ((cls == NB_SMALL && !small) || (cls == NB_LARGE && small)) return;
+    if (dense_hrow(off, seg, n_rows)) return;
     if (edge) {
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) { up[i] = -1; dn[i] = -1; }
         return;
@@ -661,8 +850,8 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
         }
         SegGrid gd, gu;
         int C0;
-        pair_bin(RowPairSrc{y, z, ra0, a - ra0, ra1}, a - ra0, off[seg + 2] - ra1, win_y, win_z, 1.01f, L,
-                 gd, gu, C0);
+        pair_bin(RowPairSrc{y, z, ra0, a - ra0, ra1}, a - ra0, off[seg + 2] - ra1, win_y, win_z, 1.01f,
+                 1.01f, L, gd, gu, C0);
         for (int i = a + threadIdx.x; i < b; i += TPC_BLOCK) {
             if (i >= a + TPC_BLOCK) {
                 hy = y[i];
@@ -676,8 +865,6 @@ __device__ inline void nb_query_seg(int seg, const int32_t *__restrict__ off, in
         __syncthreads();             // LDS reuse across calls in a persistent loop
         return;
     }
-    if constexpr (ROW == TPC_LDS_ROW)
-        nb_query_dense(seg, off, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid, up, dn, L);
 }
 
 }  // namespace tpc_nb

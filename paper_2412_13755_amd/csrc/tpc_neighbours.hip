@@ -1,6 +1,7 @@
 // Neighbour search stage kernels: one workgroup per (frame, sector, row)
 // segment; the per-segment work is in tpc_nb_device.hpp.  nb_bin only works
-// on segments next to a row too large for the LDS path.
+// on dense rows and their neighbouring rows (z-sorted copies), and
+// nb_query_dense only on dense rows.
 #include "tpc_nb_device.hpp"
 
 namespace {
@@ -25,7 +26,7 @@ nb_query_small(const int32_t *__restrict__ off, int32_t n_rows, const float *__r
                          nullptr, nullptr, up, dn, L, tpc_nb::NB_SMALL);
 }
 
-// All other rows: large LDS form, or the global cell-sorted rows.
+// Rows whose neighbour rows fit the large LDS form.
 __global__ void __launch_bounds__(TPC_BLOCK)
 nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
          const float *__restrict__ z, float win_y, float win_z, float cut_y, float cut_z,
@@ -34,7 +35,17 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
     __shared__ tpc_nb::PairLds L;
     const int seg = xcd_item(blockIdx.x, gridDim.x);
     tpc_nb::nb_query_seg(seg, off, n_rows, y, z, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
-                         sz, sid, up, dn, L, tpc_nb::NB_NOT_SMALL);
+                         sz, sid, up, dn, L, tpc_nb::NB_LARGE);
+}
+
+// Dense rows: slabs of the z-sorted rows, searched in LDS.
+__global__ void __launch_bounds__(TPC_BLOCK)
+nb_query_dense(const int32_t *__restrict__ off, int32_t n_rows, float win_y, float win_z, float cut_y,
+               float cut_z, const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
+               const int32_t *sid, int32_t *up, int32_t *dn) {
+    __shared__ tpc_nb::DenseLds L;
+    const int seg = xcd_item(blockIdx.x, gridDim.x);
+    tpc_nb::nb_dense_seg(seg, off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid, up, dn, L);
 }
 
 }  // namespace
@@ -51,6 +62,8 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
     hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
                        fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz,
                        ws.sid, up, dn);
+    hipLaunchKernelGGL(nb_query_dense, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, c.win_y,
+                       c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid, up, dn);
     return hipGetLastError();
 }
 

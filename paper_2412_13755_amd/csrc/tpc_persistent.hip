@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(TPC_BLOCK)
 persist_reco(PersistArgs P) {
     __shared__ union {
         tpc_nb::PairLds nb;
+        tpc_nb::DenseLds dense;
         tpc_nb::BinLds bin;
         uint32_t caw[TPC_CA_CAP];
     } U;
@@ -145,7 +146,10 @@ persist_reco(PersistArgs P) {
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.y, P.z, P.win_y, P.win_z, P.cut_y, P.cut_z,
                              P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.nb,
-                             tpc_nb::NB_ALL);
+                             tpc_nb::NB_NOT_DENSE);
+    for (int seg = bid; seg < P.NR; seg += G)
+        tpc_nb::nb_dense_seg(seg, P.off, P.n_rows, P.win_y, P.win_z, P.cut_y, P.cut_z, P.nb.grid, P.nb.cstart,
+                             P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.dense);
     if (!grid_sync(P)) return;
     for (int item = bid; item < P.NB; item += G)
         tpc_ca::ca_block_item(item, P.N, P.n_rows, P.off, P.up, P.dn, P.ca, U.caw);

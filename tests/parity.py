@@ -62,3 +62,89 @@ def compare_fit(gpu: dict, ref: dict, max_fail_frac=1e-4):
                 worst_par=float(dpar.max()) if dpar.size else 0.0,
                 worst_cov=float(dcov.max()) if dcov.size else 0.0,
                 worst_chi2=float(dchi.max()) if dchi.size else 0.0)
+
+
+def sector_results(fr, s, up, dn, seeds, tracks=None, f=0):
+    """The GPU results of sector ``s`` of frame ``f`` rebased as a one-sector
+    frame (ids minus the sector's first id), in the layout the oracle
+    returns for ``fr.sector_view(f, s)``.  Reconstruction within a sector
+    reads no other sector, so these are that view's results.  ``seeds`` is
+    a dict of host arrays (Seeds.to_numpy()); ``tracks`` a dict of host
+    arrays indexed by seed, or None."""
+    sv = fr.sector_view(f, s)
+    a = fr.first_id(f, s)
+    b = a + sv.n_clusters
+    gu = np.array(up[a:b], dtype=np.int64)
+    gd = np.array(dn[a:b], dtype=np.int64)
+    gu[gu >= 0] -= a
+    gd[gd >= 0] -= a
+    o = np.asarray(seeds["offsets"])
+    h = np.asarray(seeds["hits"])
+    first = h[o[:-1]] if len(o) > 1 else np.zeros(0, np.int64)
+    i0, i1 = np.searchsorted(first, a), np.searchsorted(first, b)
+    sd = dict(offsets=o[i0:i1 + 1] - o[i0], hits=h[o[i0]:o[i1]] - a,
+              frame=np.zeros(i1 - i0, np.int32), sector=np.zeros(i1 - i0, np.int32),
+              first_row=np.asarray(seeds["first_row"])[i0:i1])
+    assert np.all(np.asarray(seeds["sector"])[i0:i1] == s) and np.all(np.asarray(seeds["frame"])[i0:i1] == f)
+    tr = None if tracks is None else {k: np.asarray(v)[i0:i1] for k, v in tracks.items()}
+    return sv, gu.astype(np.int32), gd.astype(np.int32), sd, tr
+
+
+def check_sector(fr, s, up, dn, seeds, tracks, nb, min_hits, fit_prm, f=0):
+    """Oracle on one sector of a frame against the GPU's results for it:
+    identical links and seeds, fit within tolerance.  Returns statistics."""
+    sv, gu, gd, gs, gt = sector_results(fr, s, up, dn, seeds, tracks, f)
+    ru, rd = oracle.neighbours(sv.row_offsets, sv.y, sv.z, sv.n_rows, **nb)
+    np.testing.assert_array_equal(gu, ru, err_msg="up links differ in sector %d" % s)
+    np.testing.assert_array_equal(gd, rd, err_msg="down links differ in sector %d" % s)
+    rs = oracle.ca_seed(sv.row_offsets, ru, rd, 1, sv.n_rows, min_hits)
+    assert_seeds_equal(gs, rs)
+    st = dict(sector=s, clusters=sv.n_clusters, linked=int((ru >= 0).sum()), seeds=len(rs["offsets"]) - 1)
+    if gt is not None:
+        rt = oracle.fit(rs, sv.y, sv.z, sv.row_x, sv.n_rows, **fit_prm)
+        st["fit"] = compare_fit(gt, rt)
+    return st
+
+
+def check_link_invariants(row_offsets, n_rows, up, dn):
+    """Properties of the links that hold at any size: a partner lies in the
+    adjacent row of the same (frame, sector), clusters of the first and last
+    rows have none, and up and down partners come together."""
+    off = np.asarray(row_offsets, np.int64)
+    up = np.asarray(up, np.int64)
+    dn = np.asarray(dn, np.int64)
+    N = off[-1]
+    seg = np.repeat(np.arange(off.size - 1), np.diff(off))
+    r = seg % n_rows
+    has = up >= 0
+    assert np.array_equal(has, dn >= 0), "up and down partners must come together"
+    assert not has[(r == 0) | (r == n_rows - 1)].any(), "edge rows have no partners"
+    assert up.max(initial=-1) < N and dn.max(initial=-1) < N
+    assert np.array_equal(seg[up[has]], seg[has] + 1), "up partner not in the next row"
+    assert np.array_equal(seg[dn[has]], seg[has] - 1), "down partner not in the previous row"
+    return int(has.sum())
+
+
+def check_seed_invariants(row_offsets, n_sectors, n_rows, seeds, min_hits):
+    """Properties of the seeds that hold at any size: at least min_hits
+    hits each, one hit per row in consecutive rows of one (frame, sector)
+    from first_row up, no cluster in two seeds, seeds ordered by first hit."""
+    off = np.asarray(row_offsets, np.int64)
+    o = np.asarray(seeds["offsets"], np.int64)
+    h = np.asarray(seeds["hits"], np.int64)
+    T = len(o) - 1
+    ln = np.diff(o)
+    assert (ln >= min_hits).all(), "seed shorter than min_hits"
+    seg = np.repeat(np.arange(off.size - 1), np.diff(off))
+    hs = seg[h]
+    inner = np.ones(h.size, bool)
+    inner[o[1:] - 1] = False                    # last hit of each seed
+    assert np.array_equal(hs[1:][inner[:-1]], hs[:-1][inner[:-1]] + 1), "hits not in consecutive rows"
+    first = hs[o[:-1]]
+    assert np.array_equal(first % n_rows, np.asarray(seeds["first_row"])), "first_row"
+    fs = first // n_rows
+    assert np.array_equal(fs % n_sectors, np.asarray(seeds["sector"])), "sector"
+    assert np.array_equal(fs // n_sectors, np.asarray(seeds["frame"])), "frame"
+    assert np.unique(h).size == h.size, "a cluster in two seeds"
+    assert (np.diff(h[o[:-1]]) > 0).all(), "seeds not ordered by first hit"
+    return T
