@@ -273,21 +273,25 @@ def _crossings_job(args):
 
 
 def _crossings_parallel(tr: Tracks, row_x, n_sectors, bz, max_turns, workers=None):
-    """Same result as ``_crossings``; large track sets are split over processes."""
+    """Same result as ``_crossings``; large track sets are split over threads
+    (the work is numpy array code that runs without the interpreter lock).
+    Threads, not forked processes: a fork of a process whose GPU runtime is
+    already initialised (a profiler does that before the program starts)
+    can deadlock in the child."""
     import os
+    from concurrent.futures import ThreadPoolExecutor
     n = len(tr)
     if workers is None:
         workers = min(16, len(os.sched_getaffinity(0)))
     if n < 20000 or workers <= 1:
         return _crossings(tr, row_x, n_sectors, bz, max_turns)
-    import multiprocessing as mp
     bounds = np.linspace(0, n, workers * 4 + 1).astype(int)
     jobs = []
     for a, b in zip(bounds[:-1], bounds[1:]):
         sub = Tracks(*[getattr(tr, f.name)[a:b] for f in dataclasses.fields(Tracks)])
         jobs.append((sub, row_x, n_sectors, bz, max_turns, a))
-    with mp.get_context("fork").Pool(workers) as pool:
-        parts = pool.map(_crossings_job, jobs)
+    with ThreadPoolExecutor(workers) as pool:
+        parts = list(pool.map(_crossings_job, jobs))
     return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
 
 
