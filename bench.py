@@ -1,22 +1,27 @@
 """Throughput of the TPC tracking path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,batched,adjoint]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,event,batched,...]
 
 One step = neighbour finding + cellular-automaton seeding + Kalman fit of one
 synthetic time frame whose clusters are already resident in device memory
-(no host transfer inside the timed region).  The headline workload is one
-central Pb-Pb-like event over the full TPC: 36 sectors x 152 pad rows,
-10^4 helix tracks (8% low-pT loopers, half truncated), 10% noise, about
-1.3 M clusters.  The launch form (staged kernels or one persistent kernel,
-grid, fit order) is the autotuner's choice for this workload.
+(no host transfer inside the timed region).  The headline workload is a
+continuous-readout time frame: 50 Pb-Pb-like collisions spread uniformly
+over a 100 us drift window (z shifted by the drift), 5x10^5 helix tracks (8%
+low-pT loopers, half truncated), 10% noise, 6.4x10^7 clusters over 36
+sectors x 152 pad rows (4x10^3 to 1.7x10^4 clusters per row).  The launch
+form (staged kernels or one persistent kernel, grid, fit order) is the
+autotuner's choice for this workload.  The oracle runs on one sector of the
+frame (cpu_baseline) and its results gate the reported value.
 
 Extra legs, reported beside the headline value:
+  event    the same path on one central event over the full TPC (10^4 tracks,
+           1.3x10^6 clusters)
   batched  64 time frames of uneven size (log-uniform 100..20000 tracks):
            plain per-frame calls vs all frames in one persistent launch
            replayed as a graph
   adjoint  10^5 tracks with an injected distortion map: full gradient
            evaluations per second (fit with checkpoints + chi2 sum + adjoint)
-  follow   track following after the fit on the headline workload: every seed
+  follow   track following after the fit on the full-TPC event: every seed
            prolonged with chi2-gated cluster pickup (gate 25, up to 3 empty
            rows crossed), refitted, duplicates removed; the oracle is timed
            on the same seeds
@@ -25,12 +30,12 @@ Extra legs, reported beside the headline value:
            symbols): symbols/s of tpc_rans_encode with the array resident in
            HBM, against the paper's CPU figure of 10^9 symbols/s; the oracle
            coder is timed on 2^24 of the symbols
-  ctf      compression of the headline frame: track following, then (timed)
+  ctf      compression of the full-TPC event: track following, then (timed)
            the track-model residual transform into 17 integer arrays and the
            rANS coding of all of them in one batch (scale 2^14, blocks of
            2^13, counts read on the device), eagerly and as a graph;
            clusters/s and bits per cluster
-  merge    the headline event's fitted segments linked across sector edges,
+  merge    the full-TPC event's fitted segments linked across sector edges,
            each linked pair combined, and the legs of loopers paired
            (tpc_track_merge, chi2 cut 30): ms per call, links, segments/s
   material the fit with multiple scattering (radiation length 2870 cm, pion
@@ -71,6 +76,7 @@ MIN_HITS = 5
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 VALU_PEAK_TFLOPS = 78.6        # MI355X vector FMA, FP64 (= non-packed FP32), TFLOP/s
+ALU_PEAK_TOPS = 39.3           # one FP32 VALU operation per lane per clock: 256 CU x 64 lanes x 2.4 GHz
 
 # Algorithmic work per unit: the method's own inputs and outputs per stage.
 B_NB_PER_CLUSTER = 16          # read y, z; write up, dn
@@ -80,6 +86,9 @@ B_SEED_PER_SEED = 16           # write offset, frame, sector, first row
 B_FIT_PER_HIT = 8              # read the hit's y, z
 B_FIT_PER_TRACK = 24 + 96      # read seed record; write 24 words
 FLOP_FIT_PER_HIT = 300         # helix step ~35, Jacobian ~30, F C F^T ~110, update ~125
+NB_OPS_DENSE = 200             # FP32 operations per cluster of the neighbour search by predicted
+                               # position at the continuous frame's density: window tests of the
+                               # up candidates, then the down candidates around each prediction
 FOLLOW_GATE, FOLLOW_MAX_MISS = 25.0, 3
 
 
@@ -88,11 +97,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--legs", default="main,batched,adjoint,follow,rans,ctf,material,skip,merge")
+    ap.add_argument("--legs", default="main,event,batched,adjoint,follow,rans,ctf,material,skip,merge")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--stages-workload", type=int, default=1,
-                    help="workload of the stages leg (1: full-TPC event, 3: 64 uneven frames)")
+    ap.add_argument("--stages-workload", type=int, default=2,
+                    help="workload of the stages leg (2: continuous time frame, 1: full-TPC event, "
+                         "3: 64 uneven frames)")
     return ap.parse_args()
 
 
@@ -106,53 +116,89 @@ def make_reco(fr):
                 "cuda:0")
 
 
-def cpu_baseline(fr, budget_s):
-    """The oracle (as it stands) on the same frame, repeated within a time budget."""
+CPU_SECTOR = 7                 # sector of the headline frame the oracle runs on
+
+
+def cpu_baseline(fr, host, budget_s):
+    """The oracle (as it stands) on one full-density sector of the headline
+    frame, repeated within a time budget; its results are also compared with
+    the GPU's for that sector (a sector reads no other sector), which gates
+    the reported value.  Returns (baseline, parity)."""
     import oracle
+    from tests import parity
     cores = len(os.sched_getaffinity(0))
     oracle.set_threads(cores)
+    up, dn, sd, tr = host
+    sv, gu, gd, gs, gt = parity.sector_results(fr, CPU_SECTOR, up, dn, sd, tr)
     times = []
     t_start = time.perf_counter()
     while True:
         t0 = time.perf_counter()
-        up, dn = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
-        sd = oracle.ca_seed(fr.row_offsets, up, dn, fr.n_sectors, fr.n_rows, MIN_HITS)
-        oracle.fit(sd, fr.y, fr.z, fr.row_x, fr.n_rows, **FIT)
+        ru, rd = oracle.neighbours(sv.row_offsets, sv.y, sv.z, sv.n_rows, **NB)
+        rs = oracle.ca_seed(sv.row_offsets, ru, rd, 1, sv.n_rows, MIN_HITS)
+        rt = oracle.fit(rs, sv.y, sv.z, sv.row_x, sv.n_rows, **FIT)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s or len(times) >= 20:
             break
     t = float(np.median(times))
-    return {"value": round(fr.n_clusters / t / 1e6, 4), "unit": "M clusters/s",
+    check = {"sector": CPU_SECTOR, "clusters": sv.n_clusters}
+    try:
+        np.testing.assert_array_equal(gu, ru)
+        np.testing.assert_array_equal(gd, rd)
+        parity.assert_seeds_equal(gs, rs)
+        check["fit"] = parity.compare_fit(gt, rt)
+        check["links_seeds_identical"] = True
+        check["ok"] = True
+    except AssertionError as e:
+        check["ok"] = False
+        check["error"] = str(e)[:300]
+    base = {"value": round(sv.n_clusters / t / 1e6, 4), "unit": "M clusters/s",
             "cores": int(oracle.max_threads()), "kind": "oracle",
-            "sample": "the whole headline frame (%d clusters), %d runs, median %.3f s; FP32 "
-                      "neighbours, integer seeding, FP64 fit" % (fr.n_clusters, len(times), t)}
+            "sample": "sector %d of the headline frame (%d clusters at full density), %d runs, median "
+                      "%.3f s; FP32 neighbours, integer seeding, FP64 fit" % (CPU_SECTOR, sv.n_clusters,
+                                                                            len(times), t)}
+    return base, check
 
 
-# HBM traffic of the fit kernel per launch, from the committed counter
-# profile; used only while the kernel sources are those it was taken on.
+# HBM traffic per launch from the committed counter profiles; used only
+# while the kernel sources are those the counters were taken on.
 FIT_SOURCES = ("tpc_fit.hip", "tpc_fit_common.hpp", "tpc_fit_math.hpp", "tpc_internal.hpp")
 FIT_PROFILE = os.path.join(ROOT, "profiles", "fit_full_tpc_event_1e4_hbm.txt")
+NB_SOURCES = ("tpc_neighbours.hip", "tpc_nb_device.hpp", "tpc_internal.hpp")
+NB_PROFILE = os.path.join(ROOT, "profiles", "neighbours_continuous_tf_50x1e4.txt")
 
 
-def fit_source_sha():
+def source_sha(files):
     h = hashlib.sha256()
-    for f in FIT_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2412_13755_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def fit_profile_traffic():
-    """Calibrated HBM bytes per fit_tracks launch, or None if the profile is
-    missing or was taken on other kernel sources."""
+def fit_source_sha():
+    return source_sha(FIT_SOURCES)
+
+
+def profile_traffic(path, files):
+    """Calibrated HBM bytes per launch recorded in a profile summary, or None
+    if it is missing or was taken on other kernel sources."""
     try:
-        with open(FIT_PROFILE) as f:
+        with open(path) as f:
             kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
     except OSError:
         return None
-    if kv.get("source_sha256", "").strip() != fit_source_sha():
+    if kv.get("source_sha256", "").strip() != source_sha(files):
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def fit_profile_traffic():
+    return profile_traffic(FIT_PROFILE, FIT_SOURCES)
+
+
+def nb_profile_traffic():
+    return profile_traffic(NB_PROFILE, NB_SOURCES)
 
 
 def timed(fn, steps, warmup):
@@ -167,33 +213,14 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
-def leg_main(args):
+def stage_events(reco, dfr, out, ws, steps):
+    """Mean HIP-event time of each stage call of the staged path, recorded on
+    the launch stream (the current torch stream)."""
     import torch
-    from paper_2412_13755_amd import tune
-    from paper_2412_13755_amd.reco import ReconstructGraph
-    from tpcsynth import make_config
-    fr = make_config(1)
-    log("headline workload: %d clusters" % fr.n_clusters)
-    reco = make_reco(fr)
-    dfr = reco.upload(fr)
-    best = tune.autotune(reco, dfr, use_cache=False, repeats=5)
-    log("autotune: %s" % json.dumps(best))
-    out = reco.reconstruct(dfr, best["mode"], best["tune"])
-    torch.cuda.synchronize()
-    seeds = out[2]
-    n_seeds, n_hits = int(seeds.n_seeds.item()), int(seeds.n_hits.item())
-    assert int(seeds.status.item()) == 0
-    ms_eager = timed(lambda: reco.reconstruct(dfr, best["mode"], best["tune"], out),
-                     args.steps, args.warmup)
-    g = ReconstructGraph(reco, dfr, best["mode"], best["tune"])
-    ms_graph = timed(g.replay, args.steps, args.warmup)
-    ms = min(ms_eager, ms_graph)
-    # per-stage event timing of the staged path on the launch stream
+    up, dn, sd, tr = out
     stream = torch.cuda.current_stream()
-    ws = reco.workspace(dfr)
-    up, dn, sd, tr = reco.reconstruct(dfr, "staged")
     evs = []
-    for i in range(args.steps):
+    for _ in range(steps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         e[0].record(stream)
         reco.neighbours(dfr, up, dn, ws)
@@ -204,29 +231,77 @@ def leg_main(args):
         e[3].record(stream)
         evs.append(e)
     torch.cuda.synchronize()
-    st = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs])
-    stage_ms = st.mean(axis=0)
+    return np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs]).mean(axis=0)
+
+
+def fit_roofline(n_hits, n_seeds, fit_ms, traffic=None):
+    """Roofline of fit_tracks (the only kernel of tpc_kalman_fit when the
+    seeds carry their hit coordinates) against the FP64 vector peak."""
+    flops = FLOP_FIT_PER_HIT * n_hits
+    achieved = flops / (fit_ms * 1e-3) / 1e12
+    nbytes = B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5), "traffic": traffic,
+            "kernel": "fit_tracks", "avg_ms": round(fit_ms, 5), "algorithmic_flops": int(flops),
+            "algorithmic_bytes": int(nbytes),
+            "hbm_frac": round(nbytes / (fit_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
+
+
+def leg_path(args, k):
+    """The whole path (neighbours + seeding + fit) on workload k: the
+    autotuner's launch form, eagerly and as a graph replay, then each stage
+    of the staged path timed with HIP events.  Returns (result, frames,
+    host copies of the staged outputs)."""
+    import torch
+    from paper_2412_13755_amd import tune
+    from paper_2412_13755_amd.reco import ReconstructGraph
+    from tpcsynth import make_config
+    t0 = time.perf_counter()
+    fr = make_config(k)
+    log("workload %s: %d clusters (generated in %.1f s)" % (fr.meta["name"], fr.n_clusters,
+                                                           time.perf_counter() - t0))
+    reco = make_reco(fr)
+    dfr = reco.upload(fr)
+    best = tune.autotune(reco, dfr, use_cache=False, repeats=5 if k != 2 else 3)
+    log("autotune: %s" % json.dumps(best))
+    out = reco.reconstruct(dfr, best["mode"], best["tune"])
+    torch.cuda.synchronize()
+    seeds = out[2]
+    n_seeds, n_hits = int(seeds.n_seeds.item()), int(seeds.n_hits.item())
+    assert int(seeds.status.item()) == 0
+    steps = args.steps if k != 2 else max(5, args.steps // 5)
+    ms_eager = timed(lambda: reco.reconstruct(dfr, best["mode"], best["tune"], out), steps, args.warmup)
+    g = ReconstructGraph(reco, dfr, best["mode"], best["tune"])
+    ms_graph = timed(g.replay, steps, args.warmup)
+    del g
+    ms = min(ms_eager, ms_graph)
+    log("path: eager %.3f ms, graph %.3f ms" % (ms_eager, ms_graph))
+    # per-stage event timing of the staged path on the launch stream
+    ws = reco.workspace(dfr)
+    st_out = reco.reconstruct(dfr, "staged")
+    stage_ms = stage_events(reco, dfr, st_out, ws, steps)
     N = dfr.n_clusters
     names = ["tpc_neighbours", "tpc_ca_seed", "tpc_kalman_fit"]
-    # Roofline of the dominant kernel: the Kalman filter (fit_tracks, the only
-    # kernel of tpc_kalman_fit when the seeds carry their hit coordinates),
-    # timed by the events around tpc_kalman_fit on its launch stream.
-    fit_ms = float(stage_ms[2])
-    fit_flops = FLOP_FIT_PER_HIT * n_hits
-    achieved = fit_flops / (fit_ms * 1e-3) / 1e12
-    fit_bytes = B_FIT_PER_HIT * n_hits + B_FIT_PER_TRACK * n_seeds
-    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
-            "traffic": fit_profile_traffic(),
-            "kernel": "fit_tracks", "avg_ms": round(fit_ms, 5),
-            "algorithmic_flops": int(fit_flops), "algorithmic_bytes": int(fit_bytes),
-            "hbm_frac": round(fit_bytes / (fit_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
     nb_gbs = B_NB_PER_CLUSTER * N / (stage_ms[0] * 1e-3) / 1e9
     seed_bytes = B_SEED_PER_CLUSTER * N + B_SEED_PER_HIT * n_hits + B_SEED_PER_SEED * n_seeds
+    if k == 2:
+        # neighbour search on dense rows (nb_bin + nb_query_dense, ~95% of
+        # the stage): plain FP32 ALU work, NB_OPS_DENSE operations per cluster
+        ops = NB_OPS_DENSE * N
+        achieved = ops / (stage_ms[0] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": ALU_PEAK_TOPS, "unit": "Top/s",
+                "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": nb_profile_traffic(),
+                "kernel": "tpc_neighbours (nb_bin + nb_query_dense)", "avg_ms": round(float(stage_ms[0]), 5),
+                "algorithmic_ops": int(ops), "algorithmic_bytes": int(B_NB_PER_CLUSTER * N),
+                "hbm_frac": round(nb_gbs / HBM_PEAK_GBS, 6)}
+    else:
+        roof = fit_roofline(n_hits, n_seeds, float(stage_ms[2]), fit_profile_traffic())
     res = {
         "value": round(N / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 5),
         "config": {"workload": fr.meta["name"], "clusters": N, "tracks_generated": fr.meta["n_tracks"],
+                   "collisions": 50 if k == 2 else 1,
                    "seeds": n_seeds, "seed_hits": n_hits, "sectors": fr.n_sectors, "rows": fr.n_rows,
+                   "max_row_clusters": int(np.diff(fr.row_offsets).max()),
                    "mode": best["mode"], "tune": best["tune"],
                    "graph": ms_graph <= ms_eager},
         "tracks_per_s": round(n_seeds / (ms * 1e-3), 1),
@@ -235,9 +310,21 @@ def leg_main(args):
         "stage_ms_staged": {n: round(float(v), 5) for n, v in zip(names, stage_ms)},
         "stage_hbm_frac": {"tpc_neighbours": round(nb_gbs / HBM_PEAK_GBS, 5),
                            "tpc_ca_seed": round(seed_bytes / (stage_ms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "stage_fit_roofline": fit_roofline(n_hits, n_seeds, float(stage_ms[2])),
         "roofline": roof,
     }
-    return res, fr
+    up, dn, sd, tr = st_out
+    T = n_seeds
+    host = (up.cpu().numpy(), dn.cpu().numpy(), sd.to_numpy(),
+            {k2: getattr(tr, k2)[:T].cpu().numpy() for k2 in ("x", "par", "cov", "chi2", "ndf", "status")})
+    # the autotuner's form must give the staged form's results
+    same = (np.array_equal(out[0].cpu().numpy(), host[0]) and np.array_equal(out[1].cpu().numpy(), host[1])
+            and int(out[2].n_seeds.item()) == T)
+    res["launch_form_matches_staged"] = bool(same)
+    del out, st_out, ws
+    reco.close()
+    torch.cuda.empty_cache()
+    return res, fr, host
 
 
 def leg_batched(args):
@@ -756,6 +843,9 @@ def main():
     if legs == {"copy"}:
         print(json.dumps({"copy": leg_copy(args)}), flush=True)
         return
+    if legs == {"event"}:
+        print(json.dumps({"event": leg_path(args, 1)[0]}), flush=True)
+        return
     if legs == {"stages"}:
         print(json.dumps({"stages": leg_stages(args)}), flush=True)
         return
@@ -774,7 +864,7 @@ def main():
     if legs == {"rans"}:
         print(json.dumps({"rans": leg_rans(args, not args.no_cpu)}), flush=True)
         return
-    main_res, fr = leg_main(args)
+    main_res, fr, host = leg_path(args, 2)
     out = {
         "metric": "M clusters/s through CA seed+Kalman fit (plain vs batched); adjoint grads/s",
         "value": main_res.pop("value"), "unit": "M clusters/s", "n_gpus": 1, "steps": args.steps,
@@ -783,6 +873,9 @@ def main():
         "config": main_res.pop("config"),
     }
     out.update(main_res)
+    if "event" in legs:
+        ev, _, _ = leg_path(args, 1)
+        out["event"] = ev
     if "batched" in legs:
         out["batched"] = leg_batched(args)
     if "adjoint" in legs:
@@ -802,7 +895,11 @@ def main():
     if "copy" in legs:
         out["copy"] = leg_copy(args)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(fr, args.cpu_seconds)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(fr, host, args.cpu_seconds)
+        if not out["parity"]["ok"]:
+            out["value"] = None              # no number for a run that fails parity
+    else:
+        out["parity"] = {"ok": None, "note": "not checked (--no-cpu)"}
     print(json.dumps(out), flush=True)
 
 
