@@ -540,18 +540,10 @@ enum NbClass { NB_NOT_DENSE = 0, NB_SMALL = 1, NB_LARGE = 2, NB_DENSE = 3 };
 #ifndef TPC_NB_DENSE_EDGE_U
 #define TPC_NB_DENSE_EDGE_U 0.34f
 #endif
-#define TPC_NB_QUEUE (2 * TPC_WAVE)      // (h, up candidate) ring of a wavefront
-
-// LDS of a dense-row workgroup: the slab's row pair, the slab's clusters h,
-// their best keys so far and one (h, up candidate) ring per wavefront.
-template <int ROW, int CELLS, int S>
-struct DenseLdsT {
-    PairLdsT<ROW, CELLS> pair;
-    float2 hyz[S];
-    unsigned long long best[S];
-    uint32_t q[TPC_BLOCK / TPC_WAVE][TPC_NB_QUEUE];
-};
-using DenseLds = DenseLdsT<TPC_NB_DENSE_ROW, TPC_NB_DENSE_CELLS, TPC_NB_SLAB>;
+// LDS of a dense-row workgroup: the slab's row pair.
+template <int ROW, int CELLS>
+using DenseLdsT = PairLdsT<ROW, CELLS>;
+using DenseLds = DenseLdsT<TPC_NB_DENSE_ROW, TPC_NB_DENSE_CELLS>;
 
 // Positions [x, y) of the z-sorted copy of a row (grid g, cell starts cs)
 // that hold every cluster with z in [lo, hi] (whole cells: cell_coord is
@@ -563,164 +555,85 @@ __device__ inline int2 zrange(const SegGrid &g, const int32_t *cs, float lo, flo
     return make_int2(cs[c0], cs[c1 + 1]);
 }
 
-// Key of a passing triplet: the score's bit pattern (q >= +0, where the
-// bits order like the values), then the up and down ids relative to their
-// rows' first ids; the smallest key is the lexicographic best (q, u, d).
-__device__ inline unsigned long long triplet_key(float q, uint32_t urel, uint32_t drel) {
-    return ((unsigned long long)__float_as_uint(q) << 32) | (urel << 16) | drel;
-}
-
 // Search of one slab (clusters [pb, pb + pn) of the h-row's z-sorted copy)
-// whose row pair is binned in L.pair (whole workgroup; contains barriers).
-// The same candidates and the same single-precision operations as
-// best_pair<1, 1>, organised for lockstep wavefronts: each wavefront owns a
-// share of the slab's clusters and its lanes walk the up-row window cells of
-// one cluster h each, taking a new h when theirs is exhausted; (h, u) pairs
-// passing the window go to the wavefront's ring by ballot rank, and every
-// 64 of them one round scans, a pair per lane, the down-row cells of the
-// pair's prediction box.  A pair's best triplet key goes to its h by a
-// 64-bit LDS atomicMin, so the order of the rounds does not matter.
-template <int ROW, int CELLS, int S>
+// whose row pair is binned in L (whole workgroup): the result of
+// best_pair<1, 1> for every cluster h, by the same single-precision
+// operations on a pruned set of candidates.  A lane takes clusters h of the
+// slab in turn (consecutive lanes, consecutive positions: nearby z) and walks
+// the up-row cells of h's window; for every u in the window it scans the
+// down-row cells of the box around the prediction 2h - u.  Once a passing
+// triplet of score q* is known the box half-widths shrink from the cuts to
+// sqrt(q*) (1 + 1e-4) plus the rounding margin: a down cluster outside has
+// |dy| or |dz| above sqrt(q*), so fl(dy^2) + fl(dz^2) > q* (rounding is
+// monotonic and both squares are >= 0) and it can neither beat nor tie the
+// best, whose lexicographic order (q, then u id, then d id) is kept
+// exactly.  The candidate loops carry no branches.
+template <int ROW, int CELLS>
 __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy, const float *__restrict__ sz,
                                    const int32_t *__restrict__ sid, int32_t baseu, int32_t based,
                                    const SegGrid &gu, const SegGrid &gd, int C0, float win_y, float win_z,
                                    float cut_y, float cut_z, int32_t *__restrict__ up,
-                                   int32_t *__restrict__ dn, DenseLdsT<ROW, CELLS, S> &L) {
+                                   int32_t *__restrict__ dn, DenseLdsT<ROW, CELLS> &L) {
 #pragma clang fp contract(off)
-    constexpr unsigned long long NONE = ~0ull;
-    constexpr int NW = TPC_BLOCK / TPC_WAVE;
-    const int tid = threadIdx.x, lane = tid & (TPC_WAVE - 1), wid = tid / TPC_WAVE;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    for (int k = tid; k < pn; k += TPC_BLOCK) {
-        L.hyz[k] = make_float2(sy[pb + k], sz[pb + k]);
-        L.best[k] = NONE;
-    }
-    __syncthreads();
-    const float *Y = L.pair.y, *Z = L.pair.z;
-    const uint16_t *R = L.pair.rel;
-    const int32_t *UCS = L.pair.cs + C0, *DCS = L.pair.cs;
-    uint32_t *Q = L.q[wid];
+    const float *Y = L.y, *Z = L.z;
+    const uint16_t *R = L.rel;
+    const int32_t *UCS = L.cs + C0, *DCS = L.cs;
     const bool grids = gu.ny > 0 && gd.ny > 0;
-    const int per = (pn + NW - 1) / NW;
-    const int hb = wid * per < pn ? wid * per : pn;
-    const int he = hb + per < pn ? hb + per : pn;
-    int cursor = hb;                 // next h of this wavefront (same in every lane)
-    int qh = 0, qn = 0;              // ring head and count (same in every lane)
-    int hl = -1;                     // the lane's h, its window cells and position
-    float yh = 0.f, zh = 0.f;
-    int iy = 0, iy1 = -1, zc0 = 0, zc1 = 0, k = 0, ke = 0;
-    while (true) {
-        // the lane's next up candidate; an exhausted h is released
-        if (hl >= 0) {
-            while (k == ke && iy < iy1) {
-                ++iy;
-                k = UCS[iy * gu.nz + zc0];
-                ke = UCS[iy * gu.nz + zc1 + 1];
-            }
-            if (k == ke) hl = -1;
-        }
-        // lanes without an h take the wavefront's next ones
-        const unsigned long long nm = __ballot(hl < 0);
-        if (hl < 0) {
-            const int idx = cursor + __popcll(nm & below);
-            if (idx < he) {
-                hl = idx;
-                const float2 h = L.hyz[idx];
-                yh = h.x;
-                zh = h.y;
-                iy = 0; iy1 = -1; k = 0; ke = 0;
-                if (grids && isfinite(yh) && isfinite(zh)) {
-                    const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
-                    const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
-                    const float wuy = win_y + my, wuz = win_z + mz;
-                    iy = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny);
-                    iy1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
-                    zc0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz);
-                    zc1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
-                    k = UCS[iy * gu.nz + zc0];
-                    ke = UCS[iy * gu.nz + zc1 + 1];
-                    while (k == ke && iy < iy1) {
-                        ++iy;
-                        k = UCS[iy * gu.nz + zc0];
-                        ke = UCS[iy * gu.nz + zc1 + 1];
+    for (int j = threadIdx.x; j < pn; j += TPC_BLOCK) {
+        const int p = pb + j;
+        const float yh = sy[p], zh = sz[p];
+        float qb = INFINITY;
+        uint32_t ub = 0xFFFFFFFFu, db = 0xFFFFFFFFu;
+        if (grids && isfinite(yh) && isfinite(zh)) {
+            const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
+            const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
+            const float wuy = win_y + my, wuz = win_z + mz;
+            int iy = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny);
+            const int iy1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
+            const int zc0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz);
+            const int zc1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
+            for (; iy <= iy1; ++iy) {
+                const int k1 = UCS[iy * gu.nz + zc1 + 1];
+                for (int k = UCS[iy * gu.nz + zc0]; k < k1; ++k) {
+                    const float ay = Y[k] - yh;
+                    const float az = Z[k] - zh;
+                    if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
+                    // down clusters around the prediction c = h - (u - h)
+                    const float cy = yh - ay, cz = zh - az;
+                    const float r = sqrtf(qb) * 1.0001f;           // +inf until a triplet passes
+                    const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
+                    const uint32_t ur = R[k];
+                    int yd = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
+                    const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
+                    const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
+                    const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
+                    for (; yd <= yd1; ++yd) {
+                        const int e1 = DCS[yd * gd.nz + zd1 + 1];
+                        for (int kd = DCS[yd * gd.nz + zd0]; kd < e1; ++kd) {
+                            const float by = yh - Y[kd];
+                            const float bz = zh - Z[kd];
+                            const float dy = ay - by;
+                            const float dz = az - bz;
+                            const float qy = dy * dy;
+                            const float qz = dz * dz;
+                            const float q = qy + qz;
+                            const uint32_t dr = R[kd];
+                            const bool pass = fabsf(by) <= win_y && fabsf(bz) <= win_z && fabsf(dy) <= cut_y &&
+                                              fabsf(dz) <= cut_z;
+                            const bool tie = q == qb;
+                            const bool win = pass && (q < qb || (tie && (ur < ub || (ur == ub && dr < db))));
+                            qb = win ? q : qb;
+                            ub = win ? ur : ub;
+                            db = win ? dr : db;
+                        }
                     }
                 }
-                if (k == ke) hl = -1;    // no candidate at all: the h keeps no triplet
             }
         }
-        cursor += __popcll(nm);
-        if (cursor > he) cursor = he;
-        const bool live = __ballot(hl >= 0) != 0ull;
-        if (!live && qn == 0 && cursor >= he) break;
-        if (live && qn < TPC_WAVE) {
-            // one window test per lane; passing pairs enter the ring
-            bool push = false;
-            uint32_t item = 0;
-            if (hl >= 0) {
-                const float ay = Y[k] - yh;
-                const float az = Z[k] - zh;
-                push = fabsf(ay) <= win_y && fabsf(az) <= win_z;
-                item = ((uint32_t)hl << 16) | (uint32_t)k;
-                ++k;
-            }
-            const unsigned long long pm = __ballot(push);
-            if (push) Q[(qh + qn + __popcll(pm & below)) & (TPC_NB_QUEUE - 1)] = item;
-            qn += __popcll(pm);
-            continue;
-        }
-        if (qn == 0) continue;
-        // one round: a pair per lane, its down-row prediction box scanned
-        __builtin_amdgcn_wave_barrier();
-        const int n = qn < TPC_WAVE ? qn : TPC_WAVE;
-        if (lane < n) {
-            const uint32_t it = Q[(qh + lane) & (TPC_NB_QUEUE - 1)];
-            const int h2 = (int)(it >> 16), ku = (int)(it & 0xFFFFu);
-            const float2 h = L.hyz[h2];
-            const float my = 1e-5f * (fabsf(h.x) + win_y + cut_y) + 1e-6f;
-            const float mz = 1e-5f * (fabsf(h.y) + win_z + cut_z) + 1e-6f;
-            const float ky = cut_y + my, kz = cut_z + mz;
-            const float ty = Y[ku] - h.x;
-            const float tz = Z[ku] - h.y;
-            const float cy = h.x - ty, cz = h.y - tz;
-            const uint32_t urel = R[ku];
-            int iyd = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
-            const int iyd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
-            const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
-            const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
-            int kd = DCS[iyd * gd.nz + zd0], kde = DCS[iyd * gd.nz + zd1 + 1];
-            unsigned long long key = NONE;
-            while (true) {
-                while (kd == kde && iyd < iyd1) {
-                    ++iyd;
-                    kd = DCS[iyd * gd.nz + zd0];
-                    kde = DCS[iyd * gd.nz + zd1 + 1];
-                }
-                if (kd == kde) break;
-                const float by = h.x - Y[kd];
-                const float bz = h.y - Z[kd];
-                if (fabsf(by) <= win_y && fabsf(bz) <= win_z) {
-                    const float dy = ty - by;
-                    const float dz = tz - bz;
-                    if (fabsf(dy) <= cut_y && fabsf(dz) <= cut_z) {
-                        const float qy = dy * dy;
-                        const float qz = dz * dz;
-                        const unsigned long long kk = triplet_key(qy + qz, urel, R[kd]);
-                        key = kk < key ? kk : key;
-                    }
-                }
-                ++kd;
-            }
-            if (key != NONE) atomicMin(&L.best[h2], key);
-        }
-        qh = (qh + n) & (TPC_NB_QUEUE - 1);
-        qn -= n;
-    }
-    __syncthreads();
-    for (int k2 = tid; k2 < pn; k2 += TPC_BLOCK) {
-        const unsigned long long key = L.best[k2];
-        const int32_t h = sid[pb + k2];
-        up[h] = key == NONE ? -1 : baseu + (int32_t)((key >> 16) & 0xFFFFu);
-        dn[h] = key == NONE ? -1 : based + (int32_t)(key & 0xFFFFu);
+        const int32_t h = sid[p];
+        const bool found = ub != 0xFFFFFFFFu;
+        up[h] = found ? baseu + (int32_t)ub : -1;
+        dn[h] = found ? based + (int32_t)db : -1;
     }
 }
 
@@ -734,15 +647,14 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
 // slab whose ranges do not fit is halved, and at TPC_NB_SLAB_MIN clusters it
 // is searched in the global copies instead.  The outcome does not depend
 // on which superset of the candidates is searched.
-template <int ROW, int CELLS, int S>
+template <int ROW, int CELLS>
 __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, int32_t n_rows, float win_y,
                                     float win_z, float cut_y, float cut_z, const SegGrid *__restrict__ grid,
                                     const int32_t *__restrict__ cstart, const float *__restrict__ sy,
                                     const float *__restrict__ sz, const int32_t *__restrict__ sid,
                                     int32_t *__restrict__ up, int32_t *__restrict__ dn,
-                                    DenseLdsT<ROW, CELLS, S> &L) {
+                                    DenseLdsT<ROW, CELLS> &L) {
 #pragma clang fp contract(off)
-    static_assert(ROW <= 32768 && S <= 65536, "16-bit ring entries");
     if (!dense_hrow(off, seg, n_rows)) return;
     const int tid = threadIdx.x;
     const int a = off[seg], n = off[seg + 1] - a;
@@ -753,7 +665,7 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
     const int32_t *csu = cstart + baseu + su;
     // relative ids are 16-bit in the keys and in LDS
     const bool rel_ok = seg_size(off, sd) <= 65536 && seg_size(off, su) <= 65536;
-    int P = S;
+    int P = TPC_NB_SLAB;
     for (int p0 = 0; p0 < n;) {
         const int pn = n - p0 < P ? n - p0 : P;
         float lo = INFINITY, hi = -INFINITY;
@@ -765,17 +677,17 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
         hi = wave_max(hi);
         __syncthreads();             // the previous slab's search is done with L
         if ((tid & (TPC_WAVE - 1)) == 0) {
-            L.pair.red[0][tid / TPC_WAVE] = lo;
-            L.pair.red[1][tid / TPC_WAVE] = hi;
+            L.red[0][tid / TPC_WAVE] = lo;
+            L.red[1][tid / TPC_WAVE] = hi;
         }
         __syncthreads();
-        lo = L.pair.red[0][0];
-        hi = L.pair.red[1][0];
+        lo = L.red[0][0];
+        hi = L.red[1][0];
         for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w) {
-            lo = fminf(lo, L.pair.red[0][w]);
-            hi = fmaxf(hi, L.pair.red[1][w]);
+            lo = fminf(lo, L.red[0][w]);
+            hi = fmaxf(hi, L.red[1][w]);
         }
-        __syncthreads();             // everyone has read L.pair.red
+        __syncthreads();             // everyone has read L.red
         int2 rd = make_int2(0, 0), ru = make_int2(0, 0);
         if (lo <= hi) {
             const float m = 1e-5f * (fmaxf(fabsf(lo), fabsf(hi)) + win_z + cut_z) + 1e-6f;
@@ -793,7 +705,7 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
             SegGrid gd, gu;
             int C0;
             pair_bin(SortedPairSrc{sy, sz, sid, rd.x, nd, ru.x, based, baseu}, nd, nu, win_y, win_z,
-                     TPC_NB_DENSE_EDGE_D, TPC_NB_DENSE_EDGE_U, L.pair, gd, gu, C0);
+                     TPC_NB_DENSE_EDGE_D, TPC_NB_DENSE_EDGE_U, L, gd, gu, C0);
             slab_search(a + p0, pn, sy, sz, sid, baseu, based, gu, gd, C0, win_y, win_z, cut_y, cut_z, up, dn,
                         L);
         } else {
@@ -807,7 +719,7 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
             }
         }
         p0 += pn;
-        P = S;
+        P = TPC_NB_SLAB;
     }
     __syncthreads();                 // LDS reuse across calls in a persistent loop
 }
