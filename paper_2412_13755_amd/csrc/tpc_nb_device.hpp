@@ -163,20 +163,74 @@ __device__ inline SegGrid zrow_grid(float zmin, float zmax, int n, int cap) {
     return SegGrid{0.f, zmin, 0.f, nz > 1 ? (float)nz / rz : 0.f, 1, nz, 0, 0};
 }
 
+// Counting sort of clusters [a, b) by cell of grid g through an LDS
+// permutation (whole workgroup; contains barriers): the same cell order as
+// row_sort, but the scatter writes 16-bit local indices into LDS and the
+// sorted copy is then written in position order (coalesced stores, reads
+// gathered from the row), so no partially written cache lines go to HBM.
+// n = b - a <= TPC_BIN_PERM.
+#define TPC_BIN_PERM 24576
+__device__ inline void row_sort_perm(const float *__restrict__ y, const float *__restrict__ z, int a, int b,
+                                     const SegGrid &g, int *cnt, int *scan_sh, uint16_t *perm,
+                                     float *__restrict__ dy, float *__restrict__ dz, int32_t *__restrict__ did,
+                                     int32_t *__restrict__ cs, int obase) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const int cells = g.ny * g.nz;
+    for (int c = tid; c < cells; c += TPC_BLOCK) cnt[c] = 0;
+    __syncthreads();
+    for (int i = a + tid; i < b; i += TPC_BLOCK)
+        atomicAdd(&cnt[cell_coord(y[i], g.y0, g.iwy, g.ny) * g.nz + cell_coord(z[i], g.z0, g.iwz, g.nz)], 1);
+    __syncthreads();
+    const int per = (cells + TPC_BLOCK - 1) / TPC_BLOCK;
+    const int c0 = tid * per;
+    int c1 = c0 + per;
+    if (c1 > cells) c1 = cells;
+    int local = 0;
+    for (int c = c0; c < c1; ++c) local += cnt[c];
+    int total;
+    int run = block_exclusive_scan(local, scan_sh, &total);
+    for (int c = c0; c < c1; ++c) {
+        const int v = cnt[c];
+        cnt[c] = run;                 // becomes the scatter cursor
+        cs[c] = obase + run;
+        run += v;
+    }
+    if (tid == 0) cs[cells] = obase + (b - a);
+    __syncthreads();
+    for (int i = a + tid; i < b; i += TPC_BLOCK) {
+        const int c = cell_coord(y[i], g.y0, g.iwy, g.ny) * g.nz + cell_coord(z[i], g.z0, g.iwz, g.nz);
+        perm[atomicAdd(&cnt[c], 1)] = (uint16_t)(i - a);
+    }
+    __syncthreads();
+    for (int k = tid; k < b - a; k += TPC_BLOCK) {
+        const int i = a + perm[k];
+        dy[obase + k] = y[i];
+        dz[obase + k] = z[i];
+        did[obase + k] = i;
+    }
+    __syncthreads();
+}
+
 // z-sorted global copy of segment `seg`, made only when it is a dense h-row
 // or a neighbouring row of one (whole workgroup; contains barriers; L: LDS
-// scratch).
+// scratch).  With PERM the sort goes through an LDS permutation (rows of up
+// to TPC_BIN_PERM clusters; larger rows scatter directly).
 struct BinLds {
     int cnt[TPC_CELL_CAP];
     float red[4][TPC_BLOCK / TPC_WAVE];
     int scan_sh[TPC_BLOCK / TPC_WAVE];
 };
+struct BinLdsPerm : BinLds {
+    uint16_t perm[TPC_BIN_PERM];
+};
 
+template <class LDS>
 __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict__ off,
                                   const float *__restrict__ y, const float *__restrict__ z, float win_y,
                                   float win_z, SegGrid *__restrict__ grid, int32_t *__restrict__ cstart,
                                   float *__restrict__ sy, float *__restrict__ sz,
-                                  int32_t *__restrict__ sid, BinLds &L) {
+                                  int32_t *__restrict__ sid, LDS &L) {
 #pragma clang fp contract(off)
     int *cnt = L.cnt;
     float (*red)[TPC_BLOCK / TPC_WAVE] = L.red;
@@ -200,6 +254,12 @@ __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict
     row_extent(y, z, a, b, red, ext);
     const SegGrid g = zrow_grid(ext[2], ext[3], n, TPC_CELL_CAP);
     if (threadIdx.x == 0) grid[seg] = g;
+    if constexpr (sizeof(LDS) >= sizeof(BinLdsPerm)) {
+        if (n <= TPC_BIN_PERM) {
+            row_sort_perm(y, z, a, b, g, cnt, scan_sh, L.perm, sy, sz, sid, cstart + base, a);
+            return;
+        }
+    }
     row_sort(y, z, a, b, g, cnt, scan_sh, sy, sz, sid, cstart + base, a);
 }
 
@@ -535,10 +595,10 @@ enum NbClass { NB_NOT_DENSE = 0, NB_SMALL = 1, NB_LARGE = 2, NB_DENSE = 3 };
 #define TPC_NB_DENSE_CELLS 2048
 #endif
 #ifndef TPC_NB_DENSE_EDGE_D
-#define TPC_NB_DENSE_EDGE_D 0.25f
+#define TPC_NB_DENSE_EDGE_D 0.18f
 #endif
 #ifndef TPC_NB_DENSE_EDGE_U
-#define TPC_NB_DENSE_EDGE_U 0.34f
+#define TPC_NB_DENSE_EDGE_U 0.25f
 #endif
 // LDS of a dense-row workgroup: the slab's row pair.
 template <int ROW, int CELLS>
@@ -568,6 +628,160 @@ __device__ inline int2 zrange(const SegGrid &g, const int32_t *cs, float lo, flo
 // monotonic and both squares are >= 0) and it can neither beat nor tie the
 // best, whose lexicographic order (q, then u id, then d id) is kept
 // exactly.  The candidate loops carry no branches.
+#ifndef TPC_NB_DYN
+#define TPC_NB_DYN 1
+#endif
+
+// Down-row box scan of one (h, u) pair: updates the lane's best (qb, ub, db).
+__device__ inline void box_scan(float yh, float zh, float ay, float az, uint32_t ur, float my, float mz,
+                                float cut_y, float cut_z, float win_y, float win_z, const float *Y,
+                                const float *Z, const uint16_t *R, const int32_t *DCS, const SegGrid &gd,
+                                float &qb, uint32_t &ub, uint32_t &db) {
+#pragma clang fp contract(off)
+    const float cy = yh - ay, cz = zh - az;
+    const float r = sqrtf(qb) * 1.0001f;           // +inf until a triplet passes
+    const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
+    int yd = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
+    const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
+    const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
+    const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
+    for (; yd <= yd1; ++yd) {
+        const int e1 = DCS[yd * gd.nz + zd1 + 1];
+        for (int kd = DCS[yd * gd.nz + zd0]; kd < e1; ++kd) {
+            const float by = yh - Y[kd];
+            const float bz = zh - Z[kd];
+            const float dy = ay - by;
+            const float dz = az - bz;
+            const float qy = dy * dy;
+            const float qz = dz * dz;
+            const float q = qy + qz;
+            const uint32_t dr = R[kd];
+            const bool pass = fabsf(by) <= win_y && fabsf(bz) <= win_z && fabsf(dy) <= cut_y &&
+                              fabsf(dz) <= cut_z;
+            const bool tie = q == qb;
+            const bool win = pass && (q < qb || (tie && (ur < ub || (ur == ub && dr < db))));
+            qb = win ? q : qb;
+            ub = win ? ur : ub;
+            db = win ? dr : db;
+        }
+    }
+}
+
+#if TPC_NB_DYN
+// Flat form: the nested walks of one cluster (up-row window cells, their
+// candidates, and for each up cluster in the window the down-row box cells
+// and their candidates) run as one loop in which every iteration tests one
+// LDS candidate per lane, so lanes at different depths of the walk stay in
+// step.  A lane moves to its next cluster (every TPC_BLOCK-th of the slab)
+// when the current one is exhausted.
+template <int ROW, int CELLS>
+__device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy, const float *__restrict__ sz,
+                                   const int32_t *__restrict__ sid, int32_t baseu, int32_t based,
+                                   const SegGrid &gu, const SegGrid &gd, int C0, float win_y, float win_z,
+                                   float cut_y, float cut_z, int32_t *__restrict__ up,
+                                   int32_t *__restrict__ dn, DenseLdsT<ROW, CELLS> &L) {
+#pragma clang fp contract(off)
+    const float *Y = L.y, *Z = L.z;
+    const uint16_t *R = L.rel;
+    const int32_t *UCS = L.cs + C0, *DCS = L.cs;
+    const bool grids = gu.ny > 0 && gd.ny > 0;
+    int j = (int)threadIdx.x - TPC_BLOCK;
+    bool active = false, dmode = false;
+    float yh = 0.f, zh = 0.f, my = 0.f, mz = 0.f, qb = INFINITY, ay = 0.f, az = 0.f;
+    uint32_t ub = 0xFFFFFFFFu, db = 0xFFFFFFFFu, ur = 0;
+    int iy = 0, iy1 = -1, zc0 = 0, zc1 = 0, k = 0, k1 = 0;
+    int yd = 0, yd1 = -1, zd0 = 0, zd1 = 0, kd = 0, e1 = 0;
+    while (true) {
+        if (!active) {
+            j += TPC_BLOCK;
+            if (j < pn) {
+                yh = sy[pb + j];
+                zh = sz[pb + j];
+                qb = INFINITY;
+                ub = 0xFFFFFFFFu;
+                db = 0xFFFFFFFFu;
+                dmode = false;
+                iy = 0; iy1 = -1; k = 0; k1 = 0;
+                if (grids && isfinite(yh) && isfinite(zh)) {
+                    my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
+                    mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
+                    const float wuy = win_y + my, wuz = win_z + mz;
+                    iy = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny);
+                    iy1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
+                    zc0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz);
+                    zc1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
+                    k = UCS[iy * gu.nz + zc0];
+                    k1 = UCS[iy * gu.nz + zc1 + 1];
+                }
+                active = true;
+            }
+        }
+        if (__ballot(active) == 0ull) break;
+        if (!active) continue;
+        if (dmode) {
+            while (kd == e1 && yd < yd1) {
+                ++yd;
+                kd = DCS[yd * gd.nz + zd0];
+                e1 = DCS[yd * gd.nz + zd1 + 1];
+            }
+            dmode = kd < e1;
+        }
+        if (!dmode) {
+            while (k == k1 && iy < iy1) {
+                ++iy;
+                k = UCS[iy * gu.nz + zc0];
+                k1 = UCS[iy * gu.nz + zc1 + 1];
+            }
+            if (k == k1) {                            // cluster done
+                const int32_t h = sid[pb + j];
+                const bool found = ub != 0xFFFFFFFFu;
+                up[h] = found ? baseu + (int32_t)ub : -1;
+                dn[h] = found ? based + (int32_t)db : -1;
+                active = false;
+                continue;
+            }
+        }
+        const int c = dmode ? kd : k;
+        const float cy = Y[c], cz = Z[c];
+        const uint32_t rr = R[c];
+        if (dmode) {
+            ++kd;
+            const float by = yh - cy;
+            const float bz = zh - cz;
+            const float dy = ay - by;
+            const float dz = az - bz;
+            const float qy = dy * dy;
+            const float qz = dz * dz;
+            const float q = qy + qz;
+            const bool pass = fabsf(by) <= win_y && fabsf(bz) <= win_z && fabsf(dy) <= cut_y &&
+                              fabsf(dz) <= cut_z;
+            const bool tie = q == qb;
+            const bool win = pass && (q < qb || (tie && (ur < ub || (ur == ub && rr < db))));
+            qb = win ? q : qb;
+            ub = win ? ur : ub;
+            db = win ? rr : db;
+        } else {
+            ++k;
+            ay = cy - yh;
+            az = cz - zh;
+            if (fabsf(ay) <= win_y && fabsf(az) <= win_z) {
+                // down clusters around the prediction c = h - (u - h)
+                ur = rr;
+                const float py = yh - ay, pz = zh - az;
+                const float r = sqrtf(qb) * 1.0001f;   // +inf until a triplet passes
+                const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
+                yd = cell_coord(py - ky, gd.y0, gd.iwy, gd.ny);
+                yd1 = cell_coord(py + ky, gd.y0, gd.iwy, gd.ny);
+                zd0 = cell_coord(pz - kz, gd.z0, gd.iwz, gd.nz);
+                zd1 = cell_coord(pz + kz, gd.z0, gd.iwz, gd.nz);
+                kd = DCS[yd * gd.nz + zd0];
+                e1 = DCS[yd * gd.nz + zd1 + 1];
+                dmode = true;
+            }
+        }
+    }
+}
+#else
 template <int ROW, int CELLS>
 __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy, const float *__restrict__ sz,
                                    const int32_t *__restrict__ sid, int32_t baseu, int32_t based,
@@ -636,6 +850,8 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
         dn[h] = found ? based + (int32_t)db : -1;
     }
 }
+
+#endif
 
 // Dense h-row `seg` (whole workgroup; contains barriers): slabs of
 // consecutive clusters of its z-sorted copy.  A partner of h passes the

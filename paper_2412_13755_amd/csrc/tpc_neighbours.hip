@@ -10,7 +10,7 @@ __global__ void __launch_bounds__(TPC_BLOCK)
 nb_bin(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
        const float *__restrict__ z, float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy,
        float *sz, int32_t *sid) {
-    __shared__ tpc_nb::BinLds L;
+    __shared__ tpc_nb::BinLdsPerm L;
     const int seg = xcd_item(blockIdx.x, gridDim.x);
     tpc_nb::nb_bin_seg(seg, n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid, L);
 }
