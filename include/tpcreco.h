@@ -177,6 +177,26 @@ tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *frames,
                        const int32_t *up, const int32_t *dn, tpc_seeds *seeds,
                        int32_t *dev_status, void *ws, size_t ws_bytes, void *stream);
 
+/* Seeding without any allocation, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid allocation): tpc_ca_seed with its workspace taken from a
+ * library-owned device array of TPC_NOALLOC_SCRATCH_BYTES per device
+ * (reserved when the library's code is loaded on that device and held until
+ * the process ends; its address is looked up once per device by
+ * tpc_create).  Arguments, results and device status as tpc_ca_seed; no
+ * workspace argument.  Frames whose seeding workspace
+ * (tpc_workspace_bytes with TPC_STAGE_SEED) exceeds the array are refused
+ * with TPC_ERR_WORKSPACE before anything is enqueued (128 MiB: about 2.7 M
+ * clusters over 36 x 152 segments).  The current device must be the
+ * context's.  Every call on a device uses that device's one array, whose
+ * contents persist between calls (the kernels initialise every word they
+ * read): calls that overlap in time on one device race and must be ordered
+ * by the caller, e.g. issued on one stream. */
+#define TPC_NOALLOC_SCRATCH_BYTES (128u << 20)
+tpc_status tpc_ca_seed_noalloc(const tpc_context *ctx, const tpc_frames *frames,
+                               const int32_t *up, const int32_t *dn, tpc_seeds *seeds,
+                               int32_t *dev_status, void *stream);
+
 /* Kalman helix fit of every seed (count read on the device from *n_seeds,
  * clamped to cap_seeds).  State (y, z, sin phi, tan lambda, q/pT) on the
  * pad-row planes, curvature -0.00299792458 * bz * q/pT per cm; start: exact

@@ -114,6 +114,7 @@ SIGNATURES = {
     "tpc_neighbours_skip": (i32, [P, ctypes.POINTER(FramesC), P, P, P, ctypes.c_size_t, P]),
     "tpc_ca_seed": (i32, [P, ctypes.POINTER(FramesC), P, P, ctypes.POINTER(SeedsC), P, P,
                           ctypes.c_size_t, P]),
+    "tpc_ca_seed_noalloc": (i32, [P, ctypes.POINTER(FramesC), P, P, ctypes.POINTER(SeedsC), P, P]),
     "tpc_kalman_fit": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), P,
                              ctypes.POINTER(TracksC), P, ctypes.c_size_t, P, ctypes.c_size_t, P]),
     "tpc_ckpt_bytes": (i32, [P, ctypes.POINTER(SeedsC), ctypes.POINTER(ctypes.c_size_t)]),

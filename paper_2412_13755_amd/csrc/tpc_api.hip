@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "tpc_internal.hpp"
@@ -140,6 +141,33 @@ const char *tpc_status_string(tpc_status s) {
 
 const char *tpc_last_error(void) { return g_err; }
 
+// Seeding scratch of tpc_ca_seed_noalloc: one array per device, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address is taken once per device (in
+// tpc_create, with that device current) and only that address is passed to
+// kernels.
+#define TPC_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[TPC_NOALLOC_SCRATCH_BYTES];
+static void *g_scratch_ptr[TPC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static tpc_status scratch_init(int dev) {
+    if (dev < 0 || dev >= TPC_MAX_DEVICES) return fail(TPC_ERR_ARG, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return TPC_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(TPC_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+    g_scratch_ptr[dev] = p;
+    return TPC_OK;
+}
+
+static void *scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (dev >= 0 && dev < TPC_MAX_DEVICES) ? g_scratch_ptr[dev] : nullptr;
+}
+
 tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
     g_err[0] = 0;
     if (!out) return fail(TPC_ERR_ARG, "null output pointer");
@@ -183,6 +211,8 @@ tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
     e = hipMemcpy(ctx->d_row_x, ctx->row_x_host, sizeof(float) * c.n_rows, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(ctx->d_row_x); delete ctx; return hip_fail(e, "hipMemcpy(row table)"); }
     ctx->persist_grid = persist_grid(ctx);
+    tpc_status ss = scratch_init(dev);
+    if (ss) { (void)hipFree(ctx->d_row_x); delete ctx; return ss; }
     *out = ctx;
     return TPC_OK;
 }
@@ -253,6 +283,35 @@ tpc_status tpc_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const int32
     CaWs l;
     ca_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
     hipError_t e = launch_ca_seed(ctx, fr, up, dn, sd, dev_status, l, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "seeding kernels");
+}
+
+tpc_status tpc_ca_seed_noalloc(const tpc_context *ctx, const tpc_frames *fr, const int32_t *up,
+                               const int32_t *dn, tpc_seeds *sd, int32_t *dev_status, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
+    if (!sd || !dev_status) return fail(TPC_ERR_ARG, "null seeds or dev_status");
+    if (sd->cap_seeds < 0 || sd->cap_hits < 0) return fail(TPC_ERR_ARG, "negative capacity");
+    if (!sd->n_seeds || !sd->n_hits || !sd->offsets) return fail(TPC_ERR_ARG, "null seed counters or offsets");
+    if (sd->cap_seeds > 0 && (!sd->frame || !sd->sector || !sd->first_row))
+        return fail(TPC_ERR_ARG, "null seed arrays");
+    if (sd->cap_hits > 0 && !sd->hits) return fail(TPC_ERR_ARG, "null seed hits");
+    if (((uintptr_t)sd->hit_yz & 7) != 0) return fail(TPC_ERR_ARG, "hit_yz not 8-byte aligned");
+    const size_t need = ca_ws_layout(nullptr, fr->n_clusters, n_segments(ctx, fr), nullptr);
+    if (need > TPC_NOALLOC_SCRATCH_BYTES)
+        return fail(TPC_ERR_WORKSPACE, "frames need %zu bytes of seeding scratch, the built-in scratch holds %zu",
+                    need, (size_t)TPC_NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != ctx->device) return fail(TPC_ERR_ARG, "current device %d is not the context's device %d", dev, ctx->device);
+    void *ws = scratch_ptr(dev);
+    if (!ws) return fail(TPC_ERR_HIP, "no scratch address for device %d", dev);
+    CaWs l;
+    ca_ws_layout(ws, fr->n_clusters, n_segments(ctx, fr), &l);
+    e = launch_ca_seed(ctx, fr, up, dn, sd, dev_status, l, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "seeding kernels");
 }
 

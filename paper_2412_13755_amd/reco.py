@@ -211,6 +211,15 @@ class Reco:
                                     ws.numel(), _stream_handle(self.device)))
         return seeds
 
+    def seed_noalloc(self, frames: DeviceFrames, up, dn, seeds: Seeds) -> Seeds:
+        """tpc_ca_seed_noalloc: seeding into caller-allocated ``seeds`` with
+        the library's built-in scratch (no allocation in the call)."""
+        sc = seeds.c()
+        C.check(C.lib().tpc_ca_seed_noalloc(self._ctx, ctypes.byref(frames.c), up.data_ptr(), dn.data_ptr(),
+                                            ctypes.byref(sc), seeds.status.data_ptr(),
+                                            _stream_handle(self.device)))
+        return seeds
+
     def alloc_tracks(self, seeds: Seeds) -> Tracks:
         T = seeds.frame.numel()
         d = self.device
