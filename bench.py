@@ -165,7 +165,7 @@ def cpu_baseline(fr, host, budget_s):
 FIT_SOURCES = ("tpc_fit.hip", "tpc_fit_common.hpp", "tpc_fit_math.hpp", "tpc_internal.hpp")
 FIT_PROFILE = os.path.join(ROOT, "profiles", "fit_full_tpc_event_1e4_hbm.txt")
 NB_SOURCES = ("tpc_neighbours.hip", "tpc_nb_device.hpp", "tpc_internal.hpp")
-NB_PROFILE = os.path.join(ROOT, "profiles", "neighbours_continuous_tf_50x1e4.txt")
+NB_PROFILE = os.path.join(ROOT, "profiles", "path_continuous_tf_50x1e4.txt")
 
 
 def source_sha(files):
@@ -845,6 +845,12 @@ def main():
         return
     if legs == {"event"}:
         print(json.dumps({"event": leg_path(args, 1)[0]}), flush=True)
+        return
+    if legs == {"batched"}:
+        print(json.dumps({"batched": leg_batched(args)}), flush=True)
+        return
+    if legs == {"adjoint"}:
+        print(json.dumps({"adjoint": leg_adjoint(args)}), flush=True)
         return
     if legs == {"stages"}:
         print(json.dumps({"stages": leg_stages(args)}), flush=True)

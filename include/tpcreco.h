@@ -101,8 +101,13 @@ typedef struct tpc_tracks {
 typedef struct tpc_context tpc_context;
 
 /* Validates `cfg`, checks that the current HIP device is gfx950 and uploads
- * the row table (the only allocation the library makes).  On success *out
- * owns a context for the current device; free it with tpc_destroy(). */
+ * the row table (the only allocation the library makes).  The pad-row
+ * planes must be equally spaced (the neighbour predicate's second
+ * difference assumes it): a pitch row_x[r] - row_x[r-1] further than
+ * TPC_PITCH_TOL times the mean pitch from it is refused with TPC_ERR_ARG.
+ * On success *out owns a context for the current device; free it with
+ * tpc_destroy(). */
+#define TPC_PITCH_TOL 1e-3
 tpc_status tpc_create(const tpc_config *cfg, tpc_context **out);
 void tpc_destroy(tpc_context *ctx);
 
@@ -436,7 +441,7 @@ tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *seeds, const
                            float chi2_cut, int32_t *next, int32_t *prev, float *chi2, float *merged_par,
                            float *merged_cov, int32_t *leg, float *leg_chi2, void *stream);
 
-/* Entropy coding of a time frame's integer arrays (Sec. 4.3: every flat
+/* Entropy coding of a time frame's integer arrays (Sec. 4.1: every flat
  * integer array is coded on its own with range asymmetric numeral systems,
  * the symbol distribution counted for each frame, several coders
  * interleaved on one stream).  This library's coder:
@@ -490,7 +495,7 @@ tpc_status tpc_rans_encode(const int32_t *symbols, int64_t n, const tpc_rans_par
                            void *ws, size_t ws_bytes, void *stream);
 
 /* Track-model residual transform: a frame's clusters as flat integer
- * arrays for the entropy coder (Sec. 4.3 reduces every detector's time
+ * arrays for the entropy coder (Sec. 4.1 reduces every detector's time
  * frame to integer arrays and codes each on its own; the arrays below are
  * this library's reading for the TPC).  Q(v) = rint(v * (1/q)) in single
  * precision (1/q rounded to float), 0 when not finite or beyond +-2^30.

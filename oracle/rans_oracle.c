@@ -4,7 +4,7 @@
  * check and the CPU baseline of the benchmark call it; the GPU library never
  * does, and the two share no code.
  *
- * The paper (Sec. 4.3, compression) codes every flat integer array of a time
+ * The paper (Sec. 4.1, compact encoding) codes every flat integer array of a time
  * frame on its own with range asymmetric numeral systems, with the symbol
  * distribution counted for each time frame, and interleaves several coders on
  * one stream.  The parameters below are this project's reading:
@@ -27,7 +27,7 @@
  *                of 4), u32 word_start[blocks + 1] (offsets into the word
  *                area), u32 state[blocks][64] (final coder states), u16
  *                words (each block's stack, last pushed first)
- *   table        the decoder's metadata, compressed (Sec. 4.3 says it is):
+ *   table        the decoder's metadata, compressed (Sec. 4.1 says it is):
  *                for each present symbol s in ascending order, the run of
  *                absent symbols before it (s - s_prev - 1, s_prev = -1 at
  *                first) and f_s - 1, each as an unsigned LEB128 varint (7

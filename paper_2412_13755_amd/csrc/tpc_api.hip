@@ -181,6 +181,17 @@ tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
         if (!isfinite(c.row_x[r])) return fail(TPC_ERR_ARG, "row_x[%d] not finite", r);
         if (r > 0 && !(c.row_x[r] > c.row_x[r - 1])) return fail(TPC_ERR_ARG, "row_x not increasing at %d", r);
     }
+    {
+        // the neighbour predicate's second difference assumes equally spaced
+        // planes: every pitch within TPC_PITCH_TOL of the mean pitch
+        const double mean = ((double)c.row_x[c.n_rows - 1] - (double)c.row_x[0]) / (c.n_rows - 1);
+        for (int r = 1; r < c.n_rows; ++r) {
+            const double p = (double)c.row_x[r] - (double)c.row_x[r - 1];
+            if (fabs(p - mean) > TPC_PITCH_TOL * mean)
+                return fail(TPC_ERR_ARG, "non-uniform row pitch: row_x[%d] - row_x[%d] = %g, mean %g", r, r - 1, p,
+                            mean);
+        }
+    }
     if (!(fabsf(c.bz) >= 1e-6f) || !isfinite(c.bz)) return fail(TPC_ERR_ARG, "|bz| < 1e-6");
     if (!(c.sigma_y > 0.f) || !(c.sigma_z > 0.f)) return fail(TPC_ERR_ARG, "sigma_y, sigma_z must be > 0");
     if (!(c.win_y > 0.f) || !(c.win_z > 0.f) || !isfinite(c.win_y) || !isfinite(c.win_z))

@@ -172,6 +172,131 @@ __device__ inline void ca_block_item(int item, int32_t N, int32_t n_rows, const 
     }
 }
 
+// Blocks of more than TPC_CA_CAP clusters whose rows each hold at most
+// TPC_CA_SWEEP_ROW clusters are ranked by a sweep over their rows from the
+// bottom up instead (ca_sweep_item); larger rows jump in pack.
+#define TPC_CA_SWEEP_ROW 20480      // 2 x 20480 words: the whole 160 KB of LDS (a multiple of 1024)
+
+// Which ranking a block uses: 0 jumping in LDS, 1 row sweep, 2 jumping in
+// global memory.
+__device__ inline int ca_block_class(int item, int32_t n_rows, const int32_t *__restrict__ off) {
+    const int nbs = ca_blocks_per_sector(n_rows);
+    const int fs = item / nbs, bb = item % nbs;
+    const int r0 = bb * TPC_CA_ROWS;
+    const int r1 = r0 + TPC_CA_ROWS < n_rows ? r0 + TPC_CA_ROWS : n_rows;
+    if (off[fs * n_rows + r1] - off[fs * n_rows + r0] <= TPC_CA_CAP) return 0;
+    for (int r = r0; r < r1; ++r)
+        if (off[fs * n_rows + r + 1] - off[fs * n_rows + r] > TPC_CA_SWEEP_ROW) return 2;
+    return 1;
+}
+
+// Step 1 for a block of class 1: the same outputs as ca_block_item, by a
+// sweep over the block's rows from the bottom up that keeps the previous
+// row in LDS: its up partners (pu) and its words (pw: member - lo in bits
+// 0-23, distance in 24-28, keeps a link up in bit 30, down in bit 31).  For
+// a cluster h of row r with partner d = dn[h] in row r - 1 the link is kept
+// if pu says d's up partner is h; then d keeps its link up (its bit 30 is
+// set from here), and, inside the block, h's lowest member and distance are
+// d's, one link further.  Partners outside the adjacent rows (links across
+// a missing row) are checked in global memory, and the ranking then starts
+// at h; ca_tops continues any ranking down through kept links, so the
+// bottoms and positions it finds are the same.  A row's words go to pack
+// one row later, once the row above has set their up bits, so every global
+// access but those of the links across a missing row is coalesced.
+// P: 2 x TPC_CA_SWEEP_ROW words.  Contains barriers: call from the whole
+// workgroup of TPC_CA_SWEEP_T threads.
+#define TPC_CA_SWEEP_T 1024
+#define TPC_CA_W_UP 0x40000000u
+#define TPC_CA_W_DN 0x80000000u
+__device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const int32_t *__restrict__ off,
+                                     const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                     const CaWs &ws, uint32_t *P) {
+    constexpr int J = TPC_CA_SWEEP_ROW / TPC_CA_SWEEP_T;   // clusters of a row per thread
+    const int nbs = ca_blocks_per_sector(n_rows);
+    const int fs = item / nbs, bb = item % nbs;
+    const int r0 = bb * TPC_CA_ROWS;
+    const int r1 = r0 + TPC_CA_ROWS < n_rows ? r0 + TPC_CA_ROWS : n_rows;
+    const int32_t *ro = off + fs * n_rows;            // row starts of this (frame, sector)
+    const int lo = ro[r0];
+    const int tid = threadIdx.x;
+    uint32_t *pw = P, *pu = P + TPC_CA_SWEEP_ROW;
+    // the up partners of the row below the block
+    int pa = 0, pb = 0;
+    if (r0 > 0) {
+        pa = ro[r0 - 1];
+        pb = ro[r0];
+        for (int k = tid; k < pb - pa; k += TPC_CA_SWEEP_T) pu[k] = (uint32_t)up[pa + k];
+    }
+    __syncthreads();
+    for (int r = r0; r < r1; ++r) {
+        const int a = ro[r], n = ro[r + 1] - a;
+        const int na = r + 1 < n_rows ? ro[r + 1] : 0, nb = r + 1 < n_rows ? ro[r + 2] : 0;  // row above
+        int32_t uu[J];
+        uint32_t ww[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = tid + j * TPC_CA_SWEEP_T;
+            uu[j] = -1;
+            ww[j] = 0;
+            if (k >= n) continue;
+            const int32_t h = a + k;
+            const int32_t d = dn[h], u = up[h];
+            uu[j] = u;
+            const bool dprev = d >= pa && d < pb;
+            const bool hd = dprev ? pu[d - pa] == (uint32_t)h : (valid_id(d, N) && up[d] == h);
+            // a partner up in the row above sets this bit when that row is swept
+            const bool hu = (u >= na && u < nb) ? false : (valid_id(u, N) && dn[u] == h);
+            uint32_t low = (uint32_t)(h - lo), dist = 0;
+            if (hd && dprev && r > r0) {
+                const uint32_t w = atomicOr(&pw[d - pa], TPC_CA_W_UP);
+                low = w & 0xFFFFFFu;
+                dist = ((w >> 24) & 0x1Fu) + 1;
+            }
+            ww[j] = (hd ? TPC_CA_W_DN : 0u) | (hu ? TPC_CA_W_UP : 0u) | (dist << 24) | low;
+            ws.claim[h] = ~0ull;
+            ws.core[h] = 0;
+            ws.memb[h] = -1;                          // set by ca_tops for chain members
+            ws.dlk[h] = hd ? d : -1;
+        }
+        __syncthreads();
+        if (r > r0) {                                 // the row below is complete: its words to pack
+            for (int k = tid; k < pb - pa; k += TPC_CA_SWEEP_T) {
+                const uint32_t w = pw[k];
+                ws.pack[pa + k] = ((unsigned long long)(w >> 30) << 62) |
+                                  ((unsigned long long)((w >> 24) & 0x1Fu) << 32) |
+                                  (uint32_t)(lo + (int32_t)(w & 0xFFFFFFu));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k = tid + j * TPC_CA_SWEEP_T;
+            if (k < n) {
+                pw[k] = ww[j];
+                pu[k] = (uint32_t)uu[j];
+            }
+        }
+        pa = a;
+        pb = a + n;
+        __syncthreads();
+    }
+    // up bits of the block's top row from the row above it, then its words
+    if (r1 < n_rows) {
+        const int a = ro[r1], n = ro[r1 + 1] - a;
+        for (int k = tid; k < n; k += TPC_CA_SWEEP_T) {
+            const int32_t d = dn[a + k];
+            if (d >= pa && d < pb && pu[d - pa] == (uint32_t)(a + k)) atomicOr(&pw[d - pa], TPC_CA_W_UP);
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < pb - pa; k += TPC_CA_SWEEP_T) {
+        const uint32_t w = pw[k];
+        ws.pack[pa + k] = ((unsigned long long)(w >> 30) << 62) |
+                          ((unsigned long long)((w >> 24) & 0x1Fu) << 32) |
+                          (uint32_t)(lo + (int32_t)(w & 0xFFFFFFu));
+    }
+}
+
 // Step 2: every linked cluster follows the block-local lowest members down
 // across block edges (a lowest member whose kept link leaves the block
 // continues below it) to the chain bottom; then the top of each chain

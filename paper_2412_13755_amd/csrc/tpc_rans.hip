@@ -1,6 +1,6 @@
 // rANS entropy coding of an array of 32-bit integers (gfx950): the
 // compression stage of a time frame, where every flat integer array is coded
-// on its own with frequencies counted for that frame (Sec. 4.3).
+// on its own with frequencies counted for that frame (Sec. 4.1).
 //
 //  Every kernel codes a batch of arrays: grid dimension y selects the
 //  array; an array's symbol count may come from device memory.

@@ -277,3 +277,18 @@ def test_dense_rows_every_neighbour_and_ranking_form(torch_dev):
     blocks = fr.row_offsets[np.minimum(seg0 + 16, len(n))] - fr.row_offsets[seg0]
     assert (blocks > 8192).any()
     check_all(fr, "dense rows (48 rows, 2 frames)")
+
+
+def test_non_uniform_row_pitch_refused(torch_dev):
+    """The neighbour predicate's second difference assumes equally spaced
+    pad-row planes: a pitch more than 1e-3 off the mean is refused, float32
+    rounding of a uniform table is accepted."""
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    from paper_2412_13755_amd._capi import TpcError
+    from tpcsynth import make_row_x
+    rx = make_row_x(152)
+    Reco(RecoConfig(row_x=rx, min_hits=MIN_HITS, **NB, **FIT), "cuda:0").close()
+    bad = rx.copy()
+    bad[70:] += np.float32(0.01)                    # one pitch 1% longer
+    with pytest.raises(TpcError, match="pitch"):
+        Reco(RecoConfig(row_x=bad, min_hits=MIN_HITS, **NB, **FIT), "cuda:0")

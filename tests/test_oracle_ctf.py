@@ -1,5 +1,5 @@
 """Pins of the oracle's track-model residual transform (the flat integer
-arrays a time frame is reduced to before entropy coding, Sec. 4.3).
+arrays a time frame is reduced to before entropy coding, Sec. 4.1).
 
 The transform must be lossless up to the quantisation: an inverse written
 here from the arrays' definitions (not from the oracle's code) rebuilds, for

@@ -1,5 +1,5 @@
 """Pins of the oracle's rANS coder (the entropy coding of compressed time
-frames, Sec. 4.3 of the paper: every integer array coded on its own with
+frames, Sec. 4.1 of the paper: every integer array coded on its own with
 rANS, frequencies counted per frame, several coders interleaved).
 
 The expected values come from outside the coder: closed forms of the coder
