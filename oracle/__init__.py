@@ -28,11 +28,20 @@ GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp
              "-shared", "-fPIC"]
 
 
+# TPC_SANITIZE=1 builds and loads liboracle_san.so instead, instrumented
+# with AddressSanitizer and UndefinedBehaviorSanitizer (run the interpreter
+# with gcc's libasan and libubsan preloaded).
+SANITIZE = os.environ.get("TPC_SANITIZE", "") == "1"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+if SANITIZE:
+    _LIB = _LIB.replace("liboracle.so", "liboracle_san.so")
+
+
 def build(force: bool = True) -> str:
     """Compile ``liboracle.so`` with gcc (no fused multiply-add contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *GCC_FLAGS, *_SRCS, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *GCC_FLAGS, *(SAN_FLAGS if SANITIZE else []), *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -200,9 +209,18 @@ def max_threads() -> int:
     return int(lib().oracle_max_threads())
 
 
+def _check_layout(off, n_rows, n):
+    """Row offsets must describe whole sectors of n_rows rows and n clusters."""
+    if off.ndim != 1 or off.size < 1 or (off.size - 1) % n_rows != 0:
+        raise ValueError("row_offsets must hold a whole number of sectors of %d rows plus one" % n_rows)
+    if off[0] != 0 or np.any(np.diff(off) < 0) or int(off[-1]) != n:
+        raise ValueError("row_offsets must start at 0, not decrease and end at the cluster count")
+
+
 def neighbours(row_offsets, y, z, n_rows, win_y, win_z, cut_y, cut_z):
     """Returns (up, dn) int32 arrays: best triplet partners per cluster."""
     off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    _check_layout(off, n_rows, len(y))
     y = np.ascontiguousarray(y, dtype=np.float32)
     z = np.ascontiguousarray(z, dtype=np.float32)
     n = int(off[-1])
@@ -217,6 +235,7 @@ def neighbours_skip(row_offsets, y, z, n_rows, win_y, win_z, cut_y, cut_z):
     """Returns (up, dn): best triplet partners per cluster, one or two rows
     away (a triplet spanning fewer rows always wins)."""
     off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+    _check_layout(off, n_rows, len(y))
     y = np.ascontiguousarray(y, dtype=np.float32)
     z = np.ascontiguousarray(z, dtype=np.float32)
     n = int(off[-1])

@@ -12,7 +12,8 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtpcreco.so")
+LIB_PATH = os.path.join(HERE, "libtpcreco_san.so" if os.environ.get("TPC_SANITIZE", "") == "1"
+                        else "libtpcreco.so")
 
 TPC_OK = 0
 TPC_ERR_ARG = -1

@@ -41,6 +41,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
           "-I", os.path.join(HERE, "..", "include")]
 
 
+# TPC_SANITIZE=1 builds libtpcreco_san.so instead: the host code (argument
+# checks, workspace carving, launch setup) instrumented with clang's
+# AddressSanitizer and UndefinedBehaviorSanitizer; device code is built as
+# usual.  Load it with clang's ASan runtime preloaded.
+SANITIZE = os.environ.get("TPC_SANITIZE", "") == "1"
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+if SANITIZE:
+    BUILD = os.path.join(HERE, "_build_san")
+    LIB = os.path.join(HERE, "libtpcreco_san.so")
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -50,7 +62,7 @@ def hipcc() -> str:
 
 def _compile(src: str, extra) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [hipcc(), *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *COMMON, *extra, *(SAN_HOST if SANITIZE else []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -63,7 +75,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda kv: _compile(*kv), SOURCES.items()))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *(SAN_HOST if SANITIZE else []), *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

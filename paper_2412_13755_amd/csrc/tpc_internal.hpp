@@ -26,7 +26,8 @@ struct SegGrid {
     int32_t ny, nz, pad0, pad1;
 };
 
-// Workspace carving: every buffer starts on a 256-byte boundary.
+// Workspace carving: every buffer starts on a 256-byte boundary.  With a
+// null base only the size is computed (no pointer is formed).
 struct WsCarver {
     char *base;
     size_t off;
@@ -34,7 +35,7 @@ struct WsCarver {
     template <class T>
     T *take(size_t count) {
         off = (off + 255) & ~size_t(255);
-        T *p = reinterpret_cast<T *>(base + off);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
         off += count * sizeof(T);
         return p;
     }

@@ -132,9 +132,16 @@ def test_oracle_golden_cases(case):
 
 
 def test_oracle_empty_frame():
-    off = np.zeros(5, np.int32)
+    off = np.zeros(6, np.int32)                      # one sector of five empty rows
     up, dn = oracle.neighbours(off, np.zeros(0, np.float32), np.zeros(0, np.float32), 5, **NB)
     assert up.size == 0 and dn.size == 0
+
+
+def test_oracle_refuses_partial_sectors():
+    """Row offsets that are not whole sectors would make the search of the
+    last interior row read past the offsets: refused."""
+    with pytest.raises(ValueError):
+        oracle.neighbours(np.zeros(5, np.int32), np.zeros(0, np.float32), np.zeros(0, np.float32), 5, **NB)
 
 
 def test_order_of_clusters_only_relabels():
