@@ -295,6 +295,7 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
                           ((unsigned long long)((w >> 24) & 0x1Fu) << 32) |
                           (uint32_t)(lo + (int32_t)(w & 0xFFFFFFu));
     }
+    __syncthreads();                 // LDS reuse by the workgroup's next block
 }
 
 // Step 2: every linked cluster follows the block-local lowest members down

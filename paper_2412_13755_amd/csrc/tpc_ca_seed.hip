@@ -18,11 +18,13 @@ ca_block(int32_t N, int32_t n_rows, const int32_t *off, const int32_t *up, const
 // Blocks too large for the LDS ranking with rows of at most
 // TPC_CA_SWEEP_ROW clusters: ranked by a bottom-up row sweep.
 __global__ void __launch_bounds__(1024)
-ca_block_sweep(int32_t N, int32_t n_rows, const int32_t *off, const int32_t *up, const int32_t *dn, CaWs ws) {
+ca_block_sweep(int32_t NB, int32_t N, int32_t n_rows, const int32_t *off, const int32_t *up, const int32_t *dn,
+               CaWs ws) {
     __shared__ uint32_t P[2 * TPC_CA_SWEEP_ROW];
-    const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (ca_block_class(item, n_rows, off) != 1) return;
-    ca_sweep_item(item, N, n_rows, off, up, dn, ws, P);
+    for (int it = blockIdx.x; it < NB; it += gridDim.x) {
+        const int item = xcd_item(it, NB);
+        if (ca_block_class(item, n_rows, off) == 1) ca_sweep_item(item, N, n_rows, off, up, dn, ws, P);
+    }
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -157,7 +159,9 @@ hipError_t launch_ca_seed(const tpc_context *ctx, const tpc_frames *fr, const in
     const int32_t N = fr->n_clusters;
     const int NB = fr->n_frames * c.n_sectors * ca_blocks_per_sector(c.n_rows);
     hipLaunchKernelGGL(ca_block, dim3(NB), dim3(1024), 0, st, N, c.n_rows, off, up, dn, ws);
-    hipLaunchKernelGGL(ca_block_sweep, dim3(NB), dim3(1024), 0, st, N, c.n_rows, off, up, dn, ws);
+    const bool sparse = (int64_t)N < (int64_t)TPC_SPARSE_ROW * fr->n_frames * c.n_sectors * c.n_rows;
+    hipLaunchKernelGGL(ca_block_sweep, dim3(sparse && NB > TPC_SPARSE_GRID ? TPC_SPARSE_GRID : NB), dim3(1024), 0,
+                       st, NB, N, c.n_rows, off, up, dn, ws);
     hipLaunchKernelGGL(ca_tops, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, c.n_rows, ws);
     hipLaunchKernelGGL(ca_firsts, dim3(NR), dim3(TPC_BLOCK), 0, st, N, off, up, dn, c.min_hits, ws);
     if (NR <= TPC_SCAN_DIRECT) {

@@ -10,6 +10,8 @@
 #define TPC_BLOCK 256          // threads per workgroup: four 64-wide wavefronts
 #define TPC_WAVE 64
 #define TPC_CELL_CAP 4096      // neighbour-search cells per pad row (LDS histogram size)
+#define TPC_SPARSE_GRID 2048   // grid of the kernels that act on few segments (grid-stride; a multiple of 8) ...
+#define TPC_SPARSE_ROW 256     // ... when rows hold fewer clusters than this on average
 
 struct tpc_context {
     tpc_config cfg;            // row_x points at row_x_host below

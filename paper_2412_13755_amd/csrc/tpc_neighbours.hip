@@ -7,12 +7,14 @@
 namespace {
 
 __global__ void __launch_bounds__(TPC_BLOCK)
-nb_bin(const int32_t *__restrict__ off, int32_t n_rows, const float *__restrict__ y,
+nb_bin(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, const float *__restrict__ y,
        const float *__restrict__ z, float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy,
        float *sz, int32_t *sid) {
     __shared__ tpc_nb::BinLdsPerm L;
-    const int seg = xcd_item(blockIdx.x, gridDim.x);
-    tpc_nb::nb_bin_seg(seg, n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid, L);
+    // xcd_item keeps each workgroup in its XCD's contiguous range of
+    // segments (the grid is NR or a multiple of 8)
+    for (int it = blockIdx.x; it < NR; it += gridDim.x)
+        tpc_nb::nb_bin_seg(xcd_item(it, NR), n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid, L);
 }
 
 // Rows whose neighbour rows fit the small LDS form (18 KB per workgroup).
@@ -38,14 +40,16 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
                          sz, sid, up, dn, L, tpc_nb::NB_LARGE);
 }
 
-// Dense rows: slabs of the z-sorted rows, searched in LDS.
-__global__ void __launch_bounds__(TPC_BLOCK)
-nb_query_dense(const int32_t *__restrict__ off, int32_t n_rows, float win_y, float win_z, float cut_y,
+// Dense rows: slabs of the z-sorted rows, searched in LDS.  Four wavefronts
+// per SIMD (the LDS allows four workgroups per CU): at most 128 VGPRs.
+__global__ void __launch_bounds__(TPC_BLOCK, 4)
+nb_query_dense(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, float win_y, float win_z, float cut_y,
                float cut_z, const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
                const int32_t *sid, int32_t *up, int32_t *dn) {
     __shared__ tpc_nb::DenseLds L;
-    const int seg = xcd_item(blockIdx.x, gridDim.x);
-    tpc_nb::nb_dense_seg(seg, off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid, up, dn, L);
+    for (int it = blockIdx.x; it < NR; it += gridDim.x)
+        tpc_nb::nb_dense_seg(xcd_item(it, NR), off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid,
+                             up, dn, L);
 }
 
 }  // namespace
@@ -55,14 +59,21 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
                              int32_t *dn, const NbWs &ws, hipStream_t st) {
     const int NR = fr->n_frames * ctx->cfg.n_sectors * ctx->cfg.n_rows;
     const tpc_config &c = ctx->cfg;
-    hipLaunchKernelGGL(nb_bin, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
+    // the binning and the dense query only work on dense rows and their
+    // neighbours: on frames whose rows are small on average a grid of at
+    // most TPC_SPARSE_GRID workgroups strides over the segments (no
+    // per-segment dispatch for segments with nothing to do); otherwise one
+    // workgroup per segment, so heavy segments run side by side
+    const bool sparse = (int64_t)fr->n_clusters < (int64_t)TPC_SPARSE_ROW * NR;
+    const int gs = sparse && NR > TPC_SPARSE_GRID ? TPC_SPARSE_GRID : NR;
+    hipLaunchKernelGGL(nb_bin, dim3(gs), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows, fr->y,
                        fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid);
     hipLaunchKernelGGL(nb_query_small, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows,
                        fr->y, fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, up, dn);
     hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
                        fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz,
                        ws.sid, up, dn);
-    hipLaunchKernelGGL(nb_query_dense, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, c.win_y,
+    hipLaunchKernelGGL(nb_query_dense, dim3(gs), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows, c.win_y,
                        c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid, up, dn);
     return hipGetLastError();
 }
