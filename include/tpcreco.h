@@ -337,7 +337,7 @@ tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *frames,
 
 /* Whole path (tpc_neighbours, tpc_ca_seed, tpc_kalman_fit without map or
  * checkpoints) for all n_frames frames of `frames`; results are identical in
- * both modes.
+ * every mode.
  *   TPC_MODE_STAGED      the three stage calls one after another (several
  *                        kernel launches per stage)
  *   TPC_MODE_PERSISTENT  neighbours and seeding in one persistent kernel on
@@ -349,16 +349,33 @@ tpc_status tpc_fit_adjoint(const tpc_context *ctx, const tpc_frames *frames,
  *                        barrier wait exceeds its bounded polling), every
  *                        workgroup leaves and *dev_status is set to
  *                        TPC_ERR_HIP.
+ *   TPC_MODE_PERSISTENT_GRAPH  the persistent sequence captured once into a
+ *                        HIP graph held by the context (keyed by every
+ *                        argument: frames, buffers, workspace, tune) and
+ *                        replayed on `stream` by later calls with the same
+ *                        arguments; the first call with new arguments
+ *                        captures on a stream of the context's own and
+ *                        instantiates the graph (host-side allocation),
+ *                        replays allocate nothing.  The buffers must stay
+ *                        valid while the context keeps the graph (until
+ *                        tpc_destroy).
  * tune: NULL or { grid: workgroups (0 = resident capacity, larger values are
- * clamped to it), sort_fit: 1 = longest seeds first, 0 = seed order }.
- * Both modes are graph-capturable (no allocation, no host synchronisation).
+ * clamped to it), sort_fit: 1 = longest seeds first, 0 = seed order,
+ * fit_block: workgroup size of the fit (0 = 256; 64, 128 or 256),
+ * fit_spt: about this many seeds per fit thread (0 = 1; at most 64) }.
+ * grid and sort_fit apply to the persistent modes, the fit shape to all.
+ * The staged and persistent modes are graph-capturable (no allocation, no
+ * host synchronisation).
  * ws: TPC_STAGE_NEIGHBOURS|SEED|FIT workspace (staged) or
  * TPC_STAGE_PERSISTENT workspace (persistent). */
 #define TPC_MODE_STAGED      0
 #define TPC_MODE_PERSISTENT  1
+#define TPC_MODE_PERSISTENT_GRAPH 2
 typedef struct tpc_tune {
     int32_t grid;
     int32_t sort_fit;
+    int32_t fit_block;
+    int32_t fit_spt;
 } tpc_tune;
 tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *frames, int32_t mode,
                            const tpc_tune *tune, int32_t *up, int32_t *dn, tpc_seeds *seeds,

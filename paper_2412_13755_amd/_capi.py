@@ -62,7 +62,7 @@ class TracksC(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("grid", i32), ("sort_fit", i32)]
+    _fields_ = [("grid", i32), ("sort_fit", i32), ("fit_block", i32), ("fit_spt", i32)]
 
 
 class Material(ctypes.Structure):
@@ -95,6 +95,7 @@ class RansJobC(ctypes.Structure):
 TPC_RANS_BATCH_MAX = 24
 TPC_MODE_STAGED = 0
 TPC_MODE_PERSISTENT = 1
+TPC_MODE_PERSISTENT_GRAPH = 2
 TPC_STAGE_PERSISTENT = 16
 
 

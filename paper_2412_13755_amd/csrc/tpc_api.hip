@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "tpc_internal.hpp"
 #include "tpc_fit_ms.hpp"
@@ -217,6 +218,7 @@ tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
     ctx->cfg.row_x = ctx->row_x_host;
     ctx->device = dev;
     ctx->d_row_x = nullptr;
+    ctx->graphs = nullptr;
     e = hipMalloc(&ctx->d_row_x, sizeof(float) * TPC_MAX_ROWS);
     if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipMalloc(row table)"); }
     e = hipMemcpy(ctx->d_row_x, ctx->row_x_host, sizeof(float) * c.n_rows, hipMemcpyHostToDevice);
@@ -228,8 +230,92 @@ tpc_status tpc_create(const tpc_config *cfg, tpc_context **out) {
     return TPC_OK;
 }
 
+// Graphs of TPC_MODE_PERSISTENT_GRAPH: one per argument set, keyed by the
+// bytes of every argument (zero-filled first, so padding compares equal),
+// captured on a stream of the context's own and instantiated once.
+struct GraphKey {
+    tpc_frames fr;
+    const int32_t *up, *dn;
+    tpc_seeds sd;
+    tpc_tracks tr;
+    const int32_t *dev_status;
+    const void *ws;
+    size_t ws_bytes;
+    int32_t grid, sort_fit, fit_block, fit_spt;
+};
+struct GraphCache {
+    std::mutex mu;
+    hipStream_t capture = nullptr;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> items;
+};
+static std::mutex g_graph_create_mu;
+
+static void graphs_free(tpc_context *ctx) {
+    GraphCache *g = ctx->graphs;
+    if (!g) return;
+    for (auto &it : g->items) (void)hipGraphExecDestroy(it.second);
+    if (g->capture) (void)hipStreamDestroy(g->capture);
+    delete g;
+    ctx->graphs = nullptr;
+}
+
+static tpc_status graph_replay(const tpc_context *cctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
+                               const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status, void *ws,
+                               size_t ws_bytes, int grid, int sort_fit, int fit_block, int fit_spt,
+                               hipStream_t st) {
+    tpc_context *ctx = const_cast<tpc_context *>(cctx);   // the cache is the context's mutable part
+    GraphKey k;
+    memset(&k, 0, sizeof k);
+    k.fr = *fr;
+    k.up = up;
+    k.dn = dn;
+    k.sd = *sd;
+    k.tr = *tr;
+    k.dev_status = dev_status;
+    k.ws = ws;
+    k.ws_bytes = ws_bytes;
+    k.grid = grid;
+    k.sort_fit = sort_fit;
+    k.fit_block = fit_block;
+    k.fit_spt = fit_spt;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_create_mu);
+        if (!ctx->graphs) ctx->graphs = new (std::nothrow) GraphCache;
+    }
+    GraphCache *g = ctx->graphs;
+    if (!g) return fail(TPC_ERR_ARG, "out of host memory");
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (auto &it : g->items)
+            if (memcmp(&it.first, &k, sizeof k) == 0) { exec = it.second; break; }
+        if (!exec) {
+            hipError_t e = hipSuccess;
+            if (!g->capture) e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+            e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            const hipError_t le = launch_persistent(ctx, fr, up, dn, sd, tr, dev_status, ws, grid, sort_fit,
+                                                    fit_block, fit_spt, g->capture);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(g->capture, &graph);
+            if (le != hipSuccess || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(le != hipSuccess ? le : e, "persistent kernel capture");
+            }
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            g->items.emplace_back(k, exec);
+        }
+    }
+    const hipError_t e = hipGraphLaunch(exec, st);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "hipGraphLaunch");
+}
+
 void tpc_destroy(tpc_context *ctx) {
     if (!ctx) return;
+    graphs_free(ctx);
     if (ctx->d_row_x) (void)hipFree(ctx->d_row_x);
     delete ctx;
 }
@@ -447,21 +533,27 @@ tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *fr, int32_t
     g_err[0] = 0;
     tpc_status s = check_frames(ctx, fr);
     if (s) return s;
-    if (mode != TPC_MODE_STAGED && mode != TPC_MODE_PERSISTENT) return fail(TPC_ERR_ARG, "unknown mode %d", mode);
+    if (mode != TPC_MODE_STAGED && mode != TPC_MODE_PERSISTENT && mode != TPC_MODE_PERSISTENT_GRAPH)
+        return fail(TPC_ERR_ARG, "unknown mode %d", mode);
     if (fr->n_clusters > 0 && (!up || !dn)) return fail(TPC_ERR_ARG, "null up or dn");
     if (!dev_status) return fail(TPC_ERR_ARG, "null dev_status");
     if ((s = check_seeds_for_fit(sd))) return s;
     if (!sd->n_hits || (sd->cap_hits > 0 && !sd->hits)) return fail(TPC_ERR_ARG, "null seed hits");
     if ((s = check_tracks(sd, tr))) return s;
-    if (tune && (tune->grid < 0 || tune->sort_fit < 0 || tune->sort_fit > 1))
+    if (tune && (tune->grid < 0 || tune->sort_fit < 0 || tune->sort_fit > 1 ||
+                 (tune->fit_block != 0 && tune->fit_block != 64 && tune->fit_block != 128 &&
+                  tune->fit_block != 256) ||
+                 tune->fit_spt < 0 || tune->fit_spt > 64))
         return fail(TPC_ERR_ARG, "bad tune values");
     hipStream_t st = (hipStream_t)stream;
+    const int fit_block = tune ? tune->fit_block : 0, fit_spt = tune ? tune->fit_spt : 0;
     if (mode == TPC_MODE_STAGED) {
         if ((s = check_ws(ws, ws_bytes, stage_bytes(ctx, fr, TPC_STAGE_NEIGHBOURS | TPC_STAGE_SEED | TPC_STAGE_FIT))))
             return s;
         if ((s = tpc_neighbours(ctx, fr, up, dn, ws, ws_bytes, stream))) return s;
         if ((s = tpc_ca_seed(ctx, fr, up, dn, sd, dev_status, ws, ws_bytes, stream))) return s;
-        return tpc_kalman_fit(ctx, fr, sd, nullptr, tr, nullptr, 0, ws, ws_bytes, stream);
+        hipError_t e = launch_fit_shaped(ctx, fr, sd, tr, ws, fit_block, fit_spt, st);
+        return e == hipSuccess ? TPC_OK : hip_fail(e, "fit kernels");
     }
     const int64_t NR = n_segments(ctx, fr);
     if ((s = check_ws(ws, ws_bytes, persist_ws_layout(nullptr, fr->n_clusters, NR, sd->cap_seeds,
@@ -470,7 +562,9 @@ tpc_status tpc_reconstruct(const tpc_context *ctx, const tpc_frames *fr, int32_t
     int grid = ctx->persist_grid;
     if (tune && tune->grid > 0 && tune->grid < grid) grid = tune->grid;
     const int sort_fit = tune ? tune->sort_fit : 1;
-    hipError_t e = launch_persistent(ctx, fr, up, dn, sd, tr, dev_status, ws, grid, sort_fit, st);
+    if (mode == TPC_MODE_PERSISTENT_GRAPH)
+        return graph_replay(ctx, fr, up, dn, sd, tr, dev_status, ws, ws_bytes, grid, sort_fit, fit_block, fit_spt, st);
+    hipError_t e = launch_persistent(ctx, fr, up, dn, sd, tr, dev_status, ws, grid, sort_fit, fit_block, fit_spt, st);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "persistent kernel");
 }
 

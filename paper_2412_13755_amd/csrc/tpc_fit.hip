@@ -11,7 +11,7 @@ namespace {
 
 __device__ inline void fit_all(const FitArgs &A) {
     __shared__ float xs[TPC_MAX_ROWS];
-    for (int r = threadIdx.x; r < A.n_rows; r += TPC_BLOCK) xs[r] = A.row_x[r];
+    for (int r = threadIdx.x; r < A.n_rows; r += blockDim.x) xs[r] = A.row_x[r];
     __syncthreads();
     int T = *A.n_seeds;
     if (T > A.cap_seeds) T = A.cap_seeds;
@@ -19,7 +19,10 @@ __device__ inline void fit_all(const FitArgs &A) {
         const int n = *A.n_order;
         T = n < T ? n : T;
     }
-    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+    // grid-stride: a launch of g workgroups of b threads fits every seed
+    // with ceil(T / (g b)) seeds per thread (the launch shape is a tuning
+    // knob; results do not depend on it)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < T; i += gridDim.x * blockDim.x) {
         const int s = A.order ? A.order[i] : i;
         if ((uint32_t)s < (uint32_t)A.cap_seeds) fit_one(A, s, xs);
     }
@@ -142,22 +145,39 @@ hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
         A.hyz = hyz;
         launch_gather(fr, sd, hyz, st);
     }
-    int blocks = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
-    if (blocks > 8192) blocks = 8192;
+    return launch_fit_args(A, st, false, 0, 0);
+}
+
+// Launch shape of the fit: workgroups of `block` threads (0: TPC_BLOCK) and
+// about `spt` seeds per thread (0: one) over the seed capacity.
+hipError_t launch_fit_args(const FitArgs &A, hipStream_t st, bool after_persistent, int block, int spt) {
+    const int b = block > 0 ? block : TPC_BLOCK;
+    const int64_t per = (int64_t)b * (spt > 0 ? spt : 1);
+    int64_t blocks = ((int64_t)A.cap_seeds + per - 1) / per;
+    const int64_t maxb = (int64_t)8192 * TPC_BLOCK / b;
+    if (blocks > maxb) blocks = maxb;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(fit_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);
+    if (after_persistent)
+        hipLaunchKernelGGL(fit_tracks_ordered, dim3((unsigned)blocks), dim3(b), 0, st, A);
+    else
+        hipLaunchKernelGGL(fit_tracks, dim3((unsigned)blocks), dim3(b), 0, st, A);
     return hipGetLastError();
 }
 
-hipError_t launch_fit_args(const FitArgs &A, hipStream_t st, bool after_persistent) {
-    int blocks = (A.cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    if (after_persistent)
-        hipLaunchKernelGGL(fit_tracks_ordered, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);
-    else
-        hipLaunchKernelGGL(fit_tracks, dim3(blocks), dim3(TPC_BLOCK), 0, st, A);
-    return hipGetLastError();
+hipError_t launch_fit_shaped(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                             const tpc_tracks *tr, void *ws, int block, int spt, hipStream_t st) {
+    FitArgs A = make_fit_args(ctx, fr, sd, nullptr);
+    A.out = *tr;
+    A.ckpt = nullptr;
+    if (sd->hit_yz) {
+        A.hyz = reinterpret_cast<const float2 *>(sd->hit_yz);
+    } else {
+        float2 *hyz;
+        fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz);
+        A.hyz = hyz;
+        launch_gather(fr, sd, hyz, st);
+    }
+    return launch_fit_args(A, st, false, block, spt);
 }
 
 size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part) {

@@ -13,12 +13,14 @@
 #define TPC_SPARSE_GRID 2048   // grid of the kernels that act on few segments (grid-stride; a multiple of 8) ...
 #define TPC_SPARSE_ROW 256     // ... when rows hold fewer clusters than this on average
 
+struct GraphCache;
 struct tpc_context {
     tpc_config cfg;            // row_x points at row_x_host below
     float row_x_host[TPC_MAX_ROWS];
     float *d_row_x;            // device copy of the row table
     int device;
     int persist_grid;          // resident workgroups of the persistent kernel
+    GraphCache *graphs;        // instantiated graphs of TPC_MODE_PERSISTENT_GRAPH
 };
 
 // Per-segment neighbour-search grid: cell (iy, iz) of a cluster is
@@ -83,7 +85,9 @@ size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, int
 int persist_grid(const tpc_context *ctx);
 hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
                              const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status,
-                             void *ws, int grid, int sort_fit, hipStream_t st);
+                             void *ws, int grid, int sort_fit, int fit_block, int fit_spt, hipStream_t st);
+hipError_t launch_fit_shaped(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                             const tpc_tracks *tr, void *ws, int block, int spt, hipStream_t st);
 
 size_t follow_ws_layout(void *ws, int64_t N, int64_t NR, void *index_out);
 

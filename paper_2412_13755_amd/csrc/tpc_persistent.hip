@@ -320,7 +320,7 @@ int persist_grid(const tpc_context *ctx) {
 
 hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32_t *up, int32_t *dn,
                              const tpc_seeds *sd, const tpc_tracks *tr, int32_t *dev_status,
-                             void *ws, int grid, int sort_fit, hipStream_t st) {
+                             void *ws, int grid, int sort_fit, int fit_block, int fit_spt, hipStream_t st) {
     const tpc_config &c = ctx->cfg;
     PersistArgs P;
     P.off = fr->row_offsets;
@@ -354,7 +354,7 @@ hipError_t launch_persistent(const tpc_context *ctx, const tpc_frames *fr, int32
         F.order = P.perm;
         F.n_order = P.n_placed;
     }
-    launch_fit_args(F, st, true);
+    launch_fit_args(F, st, true, fit_block, fit_spt);
     hipLaunchKernelGGL(persist_status, dim3(1), dim3(64), 0, st, P);
     return hipGetLastError();
 }

@@ -425,8 +425,11 @@ class Reco:
     def reconstruct(self, frames: DeviceFrames, mode: str = "staged", tune=None, out=None, ws=None):
         """neighbours -> seeds -> fit for all frames, on one stream, no host
         synchronisation.  mode "staged" runs the stage kernels, "persistent"
-        one persistent kernel.  ``out`` = (up, dn, seeds, tracks) to reuse
-        buffers (e.g. for graph capture).  tune = (grid, sort_fit) or None."""
+        one persistent kernel, "persistent_graph" the persistent sequence as a
+        HIP graph held by the context (captured on the first call with these
+        buffers, replayed afterwards).  ``out`` = (up, dn, seeds, tracks) to
+        reuse buffers (e.g. for graph capture).  tune = (grid, sort_fit[,
+        fit_block, fit_spt]) or None."""
         if out is None:
             N = frames.n_clusters
             up = torch.empty(N, dtype=torch.int32, device=self.device)
@@ -435,10 +438,11 @@ class Reco:
             tracks = self.alloc_tracks(seeds)
         else:
             up, dn, seeds, tracks = out
-        m = {"staged": C.TPC_MODE_STAGED, "persistent": C.TPC_MODE_PERSISTENT}[mode]
+        m = {"staged": C.TPC_MODE_STAGED, "persistent": C.TPC_MODE_PERSISTENT,
+             "persistent_graph": C.TPC_MODE_PERSISTENT_GRAPH}[mode]
         if ws is None:
             ws = self.workspace(frames, C.TPC_STAGE_PERSISTENT if m else C.TPC_STAGE_ALL)
-        t = None if tune is None else C.Tune(int(tune[0]), int(tune[1]))
+        t = None if tune is None else C.Tune(*([int(v) for v in tune] + [0] * (4 - len(tune))))
         sc = seeds.c()
         tc = tracks.c()
         C.check(C.lib().tpc_reconstruct(self._ctx, ctypes.byref(frames.c), m,

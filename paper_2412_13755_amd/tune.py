@@ -1,7 +1,8 @@
 """Autotuner for the whole-path launch: picks the mode (staged kernels or one
-persistent kernel) and, for the persistent kernel, the grid size and the fit
-order (longest seeds first or seed order), by timing each candidate on the
-caller's own frames.  Results are cached in a JSON file keyed by device and
+persistent kernel), for the persistent kernel the grid size and the fit
+order (longest seeds first or seed order), and the fit's launch shape
+(workgroup size, seeds per thread: tracks per wavefront = 64 x that), by
+timing each candidate on the caller's own frames.  Results are cached in a JSON file keyed by device and
 workload shape (TPCRECO_TUNE_CACHE, default ~/.cache/tpcreco/tune.json).
 
 Every candidate produces identical results; only the time differs.
@@ -29,11 +30,17 @@ def _key(reco: Reco, frames: DeviceFrames) -> str:
 
 
 def candidates(reco: Reco):
+    """(mode, tune) pairs; tune = (grid, sort_fit, fit_block, fit_spt)."""
     cap = reco.persistent_grid()
     out = [("staged", None)]
+    for fb in (64, 128, 256):
+        for spt in (1, 2):
+            if (fb, spt) != (256, 1):
+                out.append(("staged", (0, 0, fb, spt)))
     for g in sorted({cap, max(1, cap // 2), max(1, cap // 4)}, reverse=True):
         for sf in (1, 0):
-            out.append(("persistent", (g, sf)))
+            out.append(("persistent", (g, sf, 0, 0)))
+    out.append(("persistent", (cap, 1, 128, 1)))
     return out
 
 
@@ -54,7 +61,7 @@ def time_candidate(reco: Reco, frames: DeviceFrames, mode, tune, out, repeats=5)
 
 
 def autotune(reco: Reco, frames: DeviceFrames, use_cache: bool = True, repeats: int = 5) -> dict:
-    """Returns {"mode": ..., "tune": (grid, sort_fit) or None, "ms": ..., "table": [...]}."""
+    """Returns {"mode": ..., "tune": (grid, sort_fit, fit_block, fit_spt) or None, "ms": ..., "table": [...]}."""
     path = _cache_path()
     key = _key(reco, frames)
     cache = {}

@@ -114,3 +114,45 @@ def test_autotuner_returns_a_valid_choice(tmp_path, monkeypatch):
     assert best["mode"] in ("staged", "persistent") and len(best["table"]) >= 3
     again = tune.autotune(reco, dfr)
     assert again["cached"] and again["mode"] == best["mode"]
+
+
+@pytest.mark.parametrize("tune", [(0, 0, 64, 1), (0, 0, 128, 2), (0, 0, 256, 3)])
+def test_fit_launch_shapes_identical(tune):
+    """The fit's workgroup size and seeds per thread change only the launch
+    shape: tracks bit-identical to the default shape, in both modes."""
+    fr = make_config(1, scale=0.1)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    ref = _host(*reco.reconstruct(dfr, "staged"))
+    _same(ref, _host(*reco.reconstruct(dfr, "staged", tune)))
+    _same(ref, _host(*reco.reconstruct(dfr, "persistent", (0, 1) + tune[2:])))
+
+
+def test_persistent_graph_mode():
+    """TPC_MODE_PERSISTENT_GRAPH: captured on the first call, replayed after;
+    every call equals the staged form; other arguments get their own graph."""
+    import torch
+    fr = make_config(3, scale=0.02)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    ref = _host(*reco.reconstruct(dfr, "staged"))
+    out = reco.reconstruct(dfr, "persistent")
+    for rep in range(3):
+        for t in out[:2]:
+            t.fill_(-7)                                # replays must rewrite everything
+        out[2].n_seeds.zero_()
+        torch.cuda.synchronize()
+        got = reco.reconstruct(dfr, "persistent_graph", None, out)
+        _same(ref, _host(*got))
+    got2 = reco.reconstruct(dfr, "persistent_graph", (reco.persistent_grid() // 2, 0))
+    _same(ref, _host(*got2))
+
+
+def test_bad_tune_refused():
+    from paper_2412_13755_amd._capi import TpcError
+    fr = make_config(0)
+    reco = _reco(fr)
+    dfr = reco.upload(fr)
+    for bad in ((0, 0, 96, 1), (0, 0, 64, 65), (0, 2, 0, 0), (-1, 0, 0, 0)):
+        with pytest.raises(TpcError):
+            reco.reconstruct(dfr, "staged", bad)
