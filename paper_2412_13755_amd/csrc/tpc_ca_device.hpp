@@ -303,13 +303,12 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
 // continues below it) to the chain bottom; then the top of each chain
 // records the chain length and top at the bottom and claims the chain's
 // unlinked end clusters (chains of >= min_hits - 2 clusters).
-__device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict__ off,
-                                   const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
-                                   int32_t min_hits, int32_t n_rows, const CaWs &ws) {
-    const int a = off[seg], b = off[seg + 1];
-    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
+__device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restrict__ up,
+                                   const int32_t *__restrict__ dn, int32_t min_hits, int32_t n_rows,
+                                   const CaWs &ws) {
+    {
         const unsigned long long w0 = ws.pack[h];
-        if (!pack_linked(w0)) continue;
+        if (!pack_linked(w0)) return;
         int32_t bot = pack_node(w0);
         int32_t pos = pack_dist(w0);
         for (int it = 0; it < n_rows; ++it) {         // bound: one hop per block
@@ -336,6 +335,13 @@ __device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict
     }
 }
 
+__device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict__ off,
+                                   const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                   int32_t min_hits, int32_t n_rows, const CaWs &ws) {
+    const int a = off[seg], b = off[seg + 1];
+    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) ca_tops_one(h, N, up, dn, min_hits, n_rows, ws);
+}
+
 // Seed length of the chain with bottom bb (0 if it is no seed).
 __device__ inline int32_t seed_len(const int32_t *up, const int32_t *dn, int32_t N, int32_t min_hits,
                                    const CaWs &ws, int32_t bb, int32_t *won_b) {
@@ -352,6 +358,29 @@ __device__ inline int32_t seed_len(const int32_t *up, const int32_t *dn, int32_t
     return len >= min_hits ? len : 0;
 }
 
+// Seed recognised at cluster h: the chain bottom it starts from and the seed
+// length, fb = -1 if none (h is the first cluster of at most one seed).
+__device__ inline void ca_first_one(int32_t h, int32_t N, const int32_t *__restrict__ up,
+                                    const int32_t *__restrict__ dn, int32_t min_hits, const CaWs &ws,
+                                    int32_t &fb, int32_t &len) {
+    fb = -1;
+    len = 0;
+    if (ws.core[h] >= 2) {                       // h is a bottom
+        int32_t wb;
+        int32_t l = seed_len(up, dn, N, min_hits, ws, h, &wb);
+        if (l > 0 && !wb) { fb = h; len = l; }
+    } else if (ws.claim[h] != ~0ull) {           // h is a claimed end
+        int32_t bb = (int32_t)(ws.claim[h] & 0xffffffffull);
+        if (valid_id(bb, N) && dn[bb] == h) {    // claimed as the bottom end of bb
+            int32_t wb;
+            int32_t l = seed_len(up, dn, N, min_hits, ws, bb, &wb);
+            if (l > 0) { fb = bb; len = l; }
+        }
+    }
+    ws.fbot[h] = fb;
+    ws.flen[h] = len;
+}
+
 // Contains barriers: call from the whole workgroup.
 __device__ inline void ca_firsts_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                      const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
@@ -360,21 +389,8 @@ __device__ inline void ca_firsts_seg(int seg, int32_t N, const int32_t *__restri
     const int a = off[seg], b = off[seg + 1];
     int cnt = 0, hits = 0;
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        int32_t fb = -1, len = 0;
-        if (ws.core[h] >= 2) {                       // h is a bottom
-            int32_t wb;
-            int32_t l = seed_len(up, dn, N, min_hits, ws, h, &wb);
-            if (l > 0 && !wb) { fb = h; len = l; }
-        } else if (ws.claim[h] != ~0ull) {           // h is a claimed end
-            int32_t bb = (int32_t)(ws.claim[h] & 0xffffffffull);
-            if (valid_id(bb, N) && dn[bb] == h) {    // claimed as the bottom end of bb
-                int32_t wb;
-                int32_t l = seed_len(up, dn, N, min_hits, ws, bb, &wb);
-                if (l > 0) { fb = bb; len = l; }
-            }
-        }
-        ws.fbot[h] = fb;
-        ws.flen[h] = len;
+        int32_t fb, len;
+        ca_first_one(h, N, up, dn, min_hits, ws, fb, len);
         cnt += fb >= 0;
         hits += len;
     }
@@ -384,6 +400,61 @@ __device__ inline void ca_firsts_seg(int seg, int32_t N, const int32_t *__restri
     if (threadIdx.x == 0) {
         ws.segcnt[seg] = tc;
         ws.seghits[seg] = th;
+    }
+}
+
+// The same for one wavefront (no barriers; several wavefronts of a
+// workgroup may work on different segments).
+__device__ inline void ca_firsts_wave(int seg, int32_t N, const int32_t *__restrict__ off,
+                                      const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
+                                      int32_t min_hits, const CaWs &ws) {
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    const int a = off[seg], b = off[seg + 1];
+    int cnt = 0, hits = 0;
+    for (int h = a + lane; h < b; h += TPC_WAVE) {
+        int32_t fb, len;
+        ca_first_one(h, N, up, dn, min_hits, ws, fb, len);
+        cnt += fb >= 0;
+        hits += len;
+    }
+#pragma unroll
+    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) {
+        cnt += __shfl_xor(cnt, d, TPC_WAVE);
+        hits += __shfl_xor(hits, d, TPC_WAVE);
+    }
+    if (lane == 0) {
+        ws.segcnt[seg] = cnt;
+        ws.seghits[seg] = hits;
+    }
+}
+
+// Record of the seed starting at cluster h (chain bottom fb, length len) as
+// seed i with hits from offset o, within capacity.
+__device__ inline void ca_place_one(int32_t h, int32_t fb, int32_t len, int i, int o, int32_t N,
+                                    const int32_t *__restrict__ up, const float *__restrict__ y,
+                                    const float *__restrict__ z, int frame, int sector, int row,
+                                    int32_t cap_seeds, int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws,
+                                    int32_t *len_hist) {
+    if (i < cap_seeds && o + len <= cap_hits) {
+        sd.offsets[i] = o;
+        sd.offsets[i + 1] = o + len;   // equals the next seed's offset: the placed
+                                       // prefix stays well formed on overflow
+        sd.frame[i] = frame;
+        sd.sector[i] = sector;
+        sd.first_row[i] = row;
+        const int32_t wb = (h != fb);
+        if (wb) {
+            sd.hits[o] = h;
+            if (sd.hit_yz) put_yz(sd.hit_yz, o, y[h], z[h]);
+        }
+        const int32_t m = ws.core[fb];
+        if (len > m + wb) {
+            const int32_t et = up[ws.ctop[fb]];
+            sd.hits[o + len - 1] = et;
+            if (sd.hit_yz && valid_id(et, N)) put_yz(sd.hit_yz, o + len - 1, y[et], z[et]);
+        }
+        ws.choff[fb] = o + wb;
+        if (len_hist) atomicAdd(&len_hist[len < TPC_MAX_ROWS ? len : TPC_MAX_ROWS], 1);
     }
 }
 
@@ -408,33 +479,52 @@ __device__ inline void ca_place_seg(int seg, int32_t N, const int32_t *__restric
         int tc, th;
         int pc = block_exclusive_scan(fb >= 0 ? 1 : 0, sh, &tc);
         int ph = block_exclusive_scan(len, sh, &th);
-        if (fb >= 0) {
-            const int i = carry_c + pc;
-            const int o = carry_h + ph;
-            if (i < cap_seeds && o + len <= cap_hits) {
-                sd.offsets[i] = o;
-                sd.offsets[i + 1] = o + len;   // equals the next seed's offset: the placed
-                                               // prefix stays well formed on overflow
-                sd.frame[i] = frame;
-                sd.sector[i] = sector;
-                sd.first_row[i] = row;
-                const int32_t wb = (h != fb);
-                if (wb) {
-                    sd.hits[o] = h;
-                    if (sd.hit_yz) put_yz(sd.hit_yz, o, y[h], z[h]);
-                }
-                const int32_t m = ws.core[fb];
-                if (len > m + wb) {
-                    const int32_t et = up[ws.ctop[fb]];
-                    sd.hits[o + len - 1] = et;
-                    if (sd.hit_yz && valid_id(et, N)) put_yz(sd.hit_yz, o + len - 1, y[et], z[et]);
-                }
-                ws.choff[fb] = o + wb;
-                if (len_hist) atomicAdd(&len_hist[len < TPC_MAX_ROWS ? len : TPC_MAX_ROWS], 1);
-            }
-        }
+        if (fb >= 0)
+            ca_place_one(h, fb, len, carry_c + pc, carry_h + ph, N, up, y, z, frame, sector, row, cap_seeds,
+                         cap_hits, sd, ws, len_hist);
         carry_c += tc;
         carry_h += th;
+    }
+}
+
+// The same for one wavefront (no barriers; the seeds get the same indices:
+// the prefixes run over the segment's clusters in the same order).
+__device__ inline void ca_place_wave(int seg, int32_t N, const int32_t *__restrict__ off,
+                                     const int32_t *__restrict__ up, const float *__restrict__ y,
+                                     const float *__restrict__ z, int32_t n_sectors, int32_t n_rows,
+                                     int32_t cap_seeds, int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws,
+                                     int32_t *len_hist) {
+    const int lane = threadIdx.x & (TPC_WAVE - 1);
+    const int a = off[seg], b = off[seg + 1];
+    int carry_c = ws.segbs[seg], carry_h = ws.segbh[seg];
+    const int frame = seg / (n_sectors * n_rows);
+    const int sector = (seg / n_rows) % n_sectors;
+    const int row = seg % n_rows;
+    for (int base = a; base < b; base += TPC_WAVE) {
+        const int h = base + lane;
+        int32_t fb = -1, len = 0;
+        if (h < b) { fb = ws.fbot[h]; len = ws.flen[h]; }
+        const int f = fb >= 0 ? 1 : 0;
+        const int ic = wave_inclusive_scan(f), ih = wave_inclusive_scan(len);
+        if (fb >= 0)
+            ca_place_one(h, fb, len, carry_c + ic - f, carry_h + ih - len, N, up, y, z, frame, sector, row,
+                         cap_seeds, cap_hits, sd, ws, len_hist);
+        carry_c += __shfl(ic, TPC_WAVE - 1, TPC_WAVE);
+        carry_h += __shfl(ih, TPC_WAVE - 1, TPC_WAVE);
+    }
+}
+
+__device__ inline void ca_members_one(int32_t h, int32_t N, const float *__restrict__ y,
+                                      const float *__restrict__ z, int32_t cap_hits, const tpc_seeds &sd,
+                                      const CaWs &ws) {
+    {
+        const int32_t bb = ws.memb[h];                // -1 unless h is in a chain
+        if (!valid_id(bb, N)) return;
+        const int32_t o = ws.choff[bb], k = ws.mpos[h];
+        if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) {
+            sd.hits[o + k] = h;
+            if (sd.hit_yz) put_yz(sd.hit_yz, o + k, y[h], z[h]);
+        }
     }
 }
 
@@ -443,15 +533,7 @@ __device__ inline void ca_members_seg(int seg, int32_t N, const int32_t *__restr
                                       const float *__restrict__ y, const float *__restrict__ z,
                                       int32_t cap_hits, const tpc_seeds &sd, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
-    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        const int32_t bb = ws.memb[h];                // -1 unless h is in a chain
-        if (!valid_id(bb, N)) continue;
-        const int32_t o = ws.choff[bb], k = ws.mpos[h];
-        if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) {
-            sd.hits[o + k] = h;
-            if (sd.hit_yz) put_yz(sd.hit_yz, o + k, y[h], z[h]);
-        }
-    }
+    for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) ca_members_one(h, N, y, z, cap_hits, sd, ws);
 }
 
 }  // namespace tpc_ca

@@ -225,6 +225,14 @@ struct BinLdsPerm : BinLds {
     uint16_t perm[TPC_BIN_PERM];
 };
 
+// Does segment `seg` need a z-sorted copy (a dense h-row or a neighbouring
+// row of one)?
+__device__ inline bool nb_bin_needed(const int32_t *off, int seg, int n_rows) {
+    const int r = seg % n_rows;
+    return dense_hrow(off, seg, n_rows) || (r >= 1 && dense_hrow(off, seg - 1, n_rows)) ||
+           (r <= n_rows - 2 && dense_hrow(off, seg + 1, n_rows));
+}
+
 template <class LDS>
 __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict__ off,
                                   const float *__restrict__ y, const float *__restrict__ z, float win_y,
@@ -235,10 +243,7 @@ __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict
     int *cnt = L.cnt;
     float (*red)[TPC_BLOCK / TPC_WAVE] = L.red;
     int *scan_sh = L.scan_sh;
-    const int r = seg % n_rows;
-    const bool need = dense_hrow(off, seg, n_rows) || (r >= 1 && dense_hrow(off, seg - 1, n_rows)) ||
-                      (r <= n_rows - 2 && dense_hrow(off, seg + 1, n_rows));
-    if (!need) return;
+    if (!nb_bin_needed(off, seg, n_rows)) return;
     __syncthreads();                 // LDS reuse across calls in a persistent loop
     const int a = off[seg], b = off[seg + 1], n = b - a;
     const int base = a + seg;

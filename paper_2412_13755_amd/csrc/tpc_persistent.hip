@@ -14,6 +14,10 @@
 //          chunk sums | chunk scan (one workgroup) | segment scan |
 //          place + length histogram | members + length scan (one workgroup) |
 //          gather hit coordinates + order by length
+// (firsts and place take a segment per wavefront; before the binning, every thread flags segments: those needing a z-sorted
+// copy and the dense h-rows go to two work lists, so that those phases hand
+// out only segments with work; tops and members, whose work is per cluster,
+// stride over the clusters instead of the segments)
 // The fit is not a phase: its ~230 registers per lane would cap the
 // occupancy of every phase at two wavefronts per SIMD.  It runs next, over
 // the seeds longest first (with sort_fit), so the lanes of a wavefront carry
@@ -50,6 +54,8 @@ struct PersistArgs {
     int32_t *len_cur;    // [TPC_MAX_ROWS + 1]
     int32_t *perm;       // [cap_seeds]
     int32_t *n_placed;   // [1]
+    int32_t *bin_list, *dense_list;   // [NR] segments needing a z-sorted copy / dense h-rows
+    int32_t *n_lists;    // [2] their lengths
     float2 *hyz;         // [cap_hits] seed-ordered hit coordinates
     int32_t nchunks;
     int32_t sort_fit;
@@ -123,11 +129,12 @@ __global__ void __launch_bounds__(TPC_BLOCK)
 persist_init(PersistArgs P) {
     const int t = blockIdx.x * TPC_BLOCK + threadIdx.x;
     if (t < TPC_BAR_WORDS) P.bar[t] = 0;
-    if (t == 0) { *P.err = 0; *P.n_placed = 0; }
+    if (t == 0) { *P.err = 0; *P.n_placed = 0; P.n_lists[0] = 0; P.n_lists[1] = 0; }
     if (t <= TPC_MAX_ROWS) { P.len_hist[t] = 0; P.len_cur[t] = 0; }
 }
 
-__global__ void __launch_bounds__(TPC_BLOCK)
+// Four workgroups per CU (the LDS union allows four): at most 128 VGPRs.
+__global__ void __launch_bounds__(TPC_BLOCK, 4)
 persist_reco(PersistArgs P) {
     __shared__ union {
         tpc_nb::PairLds nb;
@@ -137,28 +144,43 @@ persist_reco(PersistArgs P) {
     } U;
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     __shared__ int bc[2];
+    __shared__ int lhist[TPC_MAX_ROWS + 1], lbase[TPC_MAX_ROWS + 1];
     const int G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
 
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_nb::nb_bin_seg(seg, P.n_rows, P.off, P.y, P.z, P.win_y, P.win_z, P.nb.grid, P.nb.cstart,
-                           P.nb.sy, P.nb.sz, P.nb.sid, U.bin);
+    // work lists of the binning and the dense query (order within a list is
+    // irrelevant: every listed segment is processed whole by one workgroup)
+    for (int s = bid * TPC_BLOCK + tid; s < P.NR; s += G * TPC_BLOCK) {
+        if (tpc_nb::nb_bin_needed(P.off, s, P.n_rows)) P.bin_list[atomicAdd(&P.n_lists[0], 1)] = s;
+        if (tpc_nb::dense_hrow(P.off, s, P.n_rows)) P.dense_list[atomicAdd(&P.n_lists[1], 1)] = s;
+    }
+    if (!grid_sync(P)) return;
+    {
+        const int nl = P.n_lists[0];
+        for (int k = bid; k < nl; k += G)
+            tpc_nb::nb_bin_seg(P.bin_list[k], P.n_rows, P.off, P.y, P.z, P.win_y, P.win_z, P.nb.grid,
+                               P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, U.bin);
+    }
     if (!grid_sync(P)) return;
     for (int seg = bid; seg < P.NR; seg += G)
         tpc_nb::nb_query_seg(seg, P.off, P.n_rows, P.y, P.z, P.win_y, P.win_z, P.cut_y, P.cut_z,
                              P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.nb,
                              tpc_nb::NB_NOT_DENSE);
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_nb::nb_dense_seg(seg, P.off, P.n_rows, P.win_y, P.win_z, P.cut_y, P.cut_z, P.nb.grid, P.nb.cstart,
-                             P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.dense);
+    {
+        const int nl = P.n_lists[1];
+        for (int k = bid; k < nl; k += G)
+            tpc_nb::nb_dense_seg(P.dense_list[k], P.off, P.n_rows, P.win_y, P.win_z, P.cut_y, P.cut_z,
+                                 P.nb.grid, P.nb.cstart, P.nb.sy, P.nb.sz, P.nb.sid, P.up, P.dn, U.dense);
+    }
     if (!grid_sync(P)) return;
     for (int item = bid; item < P.NB; item += G)
         tpc_ca::ca_block_item(item, P.N, P.n_rows, P.off, P.up, P.dn, P.ca, U.caw);
     if (!grid_sync(P)) return;
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_tops_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
+    for (int h = bid * TPC_BLOCK + tid; h < P.N; h += G * TPC_BLOCK)
+        tpc_ca::ca_tops_one(h, P.N, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
     if (!grid_sync(P)) return;
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_firsts_seg(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
+    // a segment per wavefront (a workgroup's four wavefronts take four)
+    for (int seg = bid * (TPC_BLOCK / TPC_WAVE) + tid / TPC_WAVE; seg < P.NR; seg += G * (TPC_BLOCK / TPC_WAVE))
+        tpc_ca::ca_firsts_wave(seg, P.N, P.off, P.up, P.dn, P.min_hits, P.ca);
     if (!grid_sync(P)) return;
     // chunk sums of the per-segment seed and hit counts
     for (int ch = bid; ch < P.nchunks; ch += G) {
@@ -221,12 +243,21 @@ persist_reco(PersistArgs P) {
         }
     }
     if (!grid_sync(P)) return;
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_place_seg(seg, P.N, P.off, P.up, P.dn, P.y, P.z, P.n_sectors, P.n_rows, P.sd.cap_seeds,
-                             P.sd.cap_hits, P.sd, P.ca, P.len_hist);
+    // the seeds' length histogram is counted per workgroup in LDS and added
+    // to the global one bin by bin (one global atomic per seed on a few hot
+    // bins serialises)
+    for (int i = tid; i <= TPC_MAX_ROWS; i += TPC_BLOCK) lhist[i] = 0;
+    __syncthreads();
+    for (int seg = bid * (TPC_BLOCK / TPC_WAVE) + tid / TPC_WAVE; seg < P.NR; seg += G * (TPC_BLOCK / TPC_WAVE))
+        tpc_ca::ca_place_wave(seg, P.N, P.off, P.up, P.y, P.z, P.n_sectors, P.n_rows, P.sd.cap_seeds,
+                              P.sd.cap_hits, P.sd, P.ca, P.sort_fit ? lhist : nullptr);
+    __syncthreads();
+    if (P.sort_fit)
+        for (int i = tid; i <= TPC_MAX_ROWS; i += TPC_BLOCK)
+            if (lhist[i]) atomicAdd(&P.len_hist[i], lhist[i]);
     if (!grid_sync(P)) return;
-    for (int seg = bid; seg < P.NR; seg += G)
-        tpc_ca::ca_members_seg(seg, P.N, P.off, P.up, P.dn, P.y, P.z, P.sd.cap_hits, P.sd, P.ca);
+    for (int h = bid * TPC_BLOCK + tid; h < P.N; h += G * TPC_BLOCK)
+        tpc_ca::ca_members_one(h, P.N, P.y, P.z, P.sd.cap_hits, P.sd, P.ca);
     if (bid == 0 && P.sort_fit) {
         // bin starts in descending length order
         if (tid == 0) {
@@ -252,11 +283,27 @@ persist_reco(PersistArgs P) {
             P.hyz[j] = (uint32_t)id < (uint32_t)P.N ? make_float2(P.y[id], P.z[id]) : make_float2(0.f, 0.f);
         }
         if (P.sort_fit) {
+            // the workgroup counts its seeds per length in LDS, reserves one
+            // range per length in the global order, then places them (the
+            // order within a length is immaterial)
             const int np = *P.n_placed;
+            for (int i = tid; i <= TPC_MAX_ROWS; i += TPC_BLOCK) lhist[i] = 0;
+            __syncthreads();
+            for (int i = bid * TPC_BLOCK + tid; i < np; i += G * TPC_BLOCK) {
+                const int n = P.sd.offsets[i + 1] - P.sd.offsets[i];
+                atomicAdd(&lhist[n < TPC_MAX_ROWS ? (n > 0 ? n : 0) : TPC_MAX_ROWS], 1);
+            }
+            __syncthreads();
+            for (int i = tid; i <= TPC_MAX_ROWS; i += TPC_BLOCK) {
+                const int c = lhist[i];
+                lbase[i] = c ? P.len_hist[i] + atomicAdd(&P.len_cur[i], c) : 0;
+                lhist[i] = 0;
+            }
+            __syncthreads();
             for (int i = bid * TPC_BLOCK + tid; i < np; i += G * TPC_BLOCK) {
                 const int n = P.sd.offsets[i + 1] - P.sd.offsets[i];
                 const int len = n < TPC_MAX_ROWS ? (n > 0 ? n : 0) : TPC_MAX_ROWS;
-                const int slot = P.len_hist[len] + atomicAdd(&P.len_cur[len], 1);
+                const int slot = lbase[len] + atomicAdd(&lhist[len], 1);
                 if (slot < np) P.perm[slot] = i;
             }
         }
@@ -289,6 +336,9 @@ size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, int
     int32_t *cur = w.take<int32_t>(TPC_MAX_ROWS + 1);
     int32_t *perm = w.take<int32_t>(cap_seeds > 0 ? cap_seeds : 1);
     int32_t *np = w.take<int32_t>(1);
+    int32_t *bl = w.take<int32_t>(NR > 0 ? NR : 1);
+    int32_t *dl = w.take<int32_t>(NR > 0 ? NR : 1);
+    int32_t *nl = w.take<int32_t>(2);
     float2 *hyz = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
     if (P) {
         P->hyz = hyz;
@@ -302,6 +352,9 @@ size_t persist_ws_layout(void *ws, int64_t N, int64_t NR, int64_t cap_seeds, int
         P->len_cur = cur;
         P->perm = perm;
         P->n_placed = np;
+        P->bin_list = bl;
+        P->dense_list = dl;
+        P->n_lists = nl;
         P->nchunks = (int32_t)nchunks;
     }
     return (w.off + 255) & ~size_t(255);
