@@ -115,6 +115,45 @@ def legs(tracks: dict, frame, sector, n_sectors, *, bz, cut):
     return leg, chi
 
 
+def refit(seeds: dict, tracks: dict, nxt, prv, leg, y, z, row_x, n_rows, n_sectors, *, bz, sigma_y,
+          sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0, map_: Optional[np.ndarray] = None):
+    """Tracks assembled from linked segments and refitted over all their hits.
+
+    ``tracks`` holds the segments' fit status; ``nxt``, ``prv`` the
+    sector-edge links, ``leg`` the looper-leg pairing (or None).  Returns a
+    dict: track_id [T]; the chain refits x, par, cov, chi2, ndf, status at
+    each chain's head (status 5 elsewhere); loop_par [T, 4], loop_cov [T, 10],
+    loop_chi2 [T] (the joint circle of each leg pair at its smaller index,
+    chi2 -1 elsewhere; absent when ``leg`` is None)."""
+    offsets = np.ascontiguousarray(seeds["offsets"], dtype=np.int32)
+    hits = np.ascontiguousarray(seeds["hits"], dtype=np.int32)
+    sec = np.ascontiguousarray(seeds["sector"], dtype=np.int32)
+    fr = np.ascontiguousarray(seeds["first_row"], dtype=np.int32)
+    st = np.ascontiguousarray(tracks["status"], dtype=np.int32)
+    nx = np.ascontiguousarray(nxt, dtype=np.int32)
+    pv = np.ascontiguousarray(prv, dtype=np.int32)
+    lg = None if leg is None else np.ascontiguousarray(leg, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    rx = np.ascontiguousarray(row_x, dtype=np.float64)
+    T = len(offsets) - 1
+    assert st.size == T and nx.size == T and pv.size == T and (lg is None or lg.size == T)
+    prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
+    mp = None if map_ is None else np.ascontiguousarray(map_, dtype=np.float64)
+    n1 = max(T, 1)
+    out = dict(track_id=np.empty(n1, np.int32), x=np.empty(n1), par=np.empty((n1, 5)), cov=np.empty((n1, 15)),
+               chi2=np.empty(n1), ndf=np.empty(n1, np.int32), status=np.empty(n1, np.int32))
+    if lg is not None:
+        out.update(loop_par=np.empty((n1, 4)), loop_cov=np.empty((n1, 10)), loop_chi2=np.empty(n1))
+    q = lambda k: None if k not in out else _p(out[k])
+    lib().oracle_refit(T, _p(offsets), _p(hits), _p(sec), _p(fr), _p(st), _p(nx), _p(pv),
+                       None if lg is None else _p(lg), _p(y), _p(z), _p(rx), int(n_rows), int(n_sectors),
+                       None if mp is None else _p(mp), ctypes.byref(prm), _p(out["track_id"]), _p(out["x"]),
+                       _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndf"]), _p(out["status"]),
+                       q("loop_par"), q("loop_cov"), q("loop_chi2"))
+    return {k: v[:T] for k, v in out.items()}
+
+
 def eloss(p, dx, mass, gas, direction=1.0):
     """Energy-loss map of the fit for one segment: (status, w', dw'/dt,
     dw'/dw, straggling variance of w)."""
@@ -181,6 +220,9 @@ def lib():
         L.oracle_leg_circle.restype = i32
         L.oracle_legs.argtypes = [i32, P, P, P, P, P, P, i32, d_, d_, P, P]
         L.oracle_legs.restype = None
+        L.oracle_refit.argtypes = [i32, P, P, P, P, P, P, P, P, P, P, P, i32, i32, P,
+                                   ctypes.POINTER(FitParams), P, P, P, P, P, P, P, P, P, P]
+        L.oracle_refit.restype = None
         L.oracle_bethe.argtypes = [ctypes.c_double] * 4
         L.oracle_bethe.restype = ctypes.c_double
         L.oracle_eloss.argtypes = [P, ctypes.c_double, ctypes.POINTER(Material), ctypes.c_double, P]

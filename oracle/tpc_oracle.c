@@ -1580,3 +1580,267 @@ void oracle_legs(int32_t n_tracks, const double *x, const double *par, const dou
     free(best);
     free(bchi);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Tracks assembled from linked segments and refitted over all their hits   */
+/* (the survey's next row f1; the paper gives no algorithm).                 */
+/*  links     a next link i -> j counts when j = next[i] is a segment other  */
+/*            than i with prev[j] = i and both fits have status 0; a leg     */
+/*            link i -- j when leg[j] = i likewise.                          */
+/*  track id  the connected components of the segments of status 0 under    */
+/*            both kinds of link, each named by its smallest segment index  */
+/*            (-1 for a segment whose own fit failed).                       */
+/*  chains    a head is a segment of status 0 with no counted prev link; its */
+/*            chain follows the next links outwards (at most 18 segments,    */
+/*            one per sector of a side; longer: status 6).  Its hits, k =    */
+/*            0..n-1, are the head's in ascending row, then the next         */
+/*            segment's, and so on, each measured in its own sector's frame  */
+/*            (corrected by the map of its sector and row when one is given).*/
+/*  refit     the seed fit of that hit list: the exact circle through hits   */
+/*            n-1, (n-1)/2 and 0, all turned into the frame of hit n-1 (a    */
+/*            point (x, y) of a sector at angle a_s seen from the frame at    */
+/*            angle a_t: (x cos d - y sin d, x sin d + y cos d), d = a_s -   */
+/*            a_t), gives the start at hit n-1 with the start covariance;    */
+/*            the filter then runs inwards, k = n-2 .. 0: within a segment   */
+/*            the helix step to the plane of hit k, across a segment         */
+/*            boundary the transfer above into the frame of hit k's segment  */
+/*            and on to its plane (C <- J C J^T), then the update.  Written  */
+/*            at the head: the state at its innermost hit in its frame, chi2,*/
+/*            ndf = 2n - 5, status as the fit's; every other segment gets   */
+/*            status 5 and zeros.  A chain of one segment is that segment's */
+/*            seed fit.                                                      */
+/*  loopers   for each counted leg link i -- j (i < j) between two chains    */
+/*            whose refits have status 0: the circles m (above) of the two  */
+/*            chains' refitted states at their heads, fused in the sense of  */
+/*            i's chain: S = S_i + D S_j D, d = m_i - D m_j, x = m_i - S_i    */
+/*            S^-1 d, C = S_i S^-1 D S_j D (symmetrised), chi2 = d^T S^-1 d  */
+/*            (the joint circle of both legs for the linearised problem),    */
+/*            written at i; elsewhere zeros and chi2 -1.                     */
+/* ------------------------------------------------------------------------ */
+#define REFIT_MAX_CHAIN 18
+#define REFIT_NOT_HEAD 5
+#define REFIT_LONG_CHAIN 6
+
+static int next_link(int32_t i, int32_t n, const int32_t *next, const int32_t *prev, const int32_t *status)
+{
+    int32_t j = next[i];
+    return j >= 0 && j < n && j != i && prev[j] == i && status[i] == 0 && status[j] == 0 ? j : -1;
+}
+
+static int prev_link(int32_t i, int32_t n, const int32_t *next, const int32_t *prev, const int32_t *status)
+{
+    int32_t a = prev[i];
+    return a >= 0 && a < n && a != i && next[a] == i && status[i] == 0 && status[a] == 0 ? a : -1;
+}
+
+static int leg_link(int32_t i, int32_t n, const int32_t *leg, const int32_t *status)
+{
+    if (!leg) return -1;
+    int32_t j = leg[i];
+    return j >= 0 && j < n && j != i && leg[j] == i && status[i] == 0 && status[j] == 0 ? j : -1;
+}
+
+static int32_t uf_root(int32_t *p, int32_t x)
+{
+    while (p[x] != x) x = p[x];
+    return x;
+}
+
+/* The head of i's chain (walking prev links), or -1 if there is none
+ * within the chain length limit. */
+static int32_t chain_head(int32_t i, int32_t n, const int32_t *next, const int32_t *prev, const int32_t *status)
+{
+    for (int32_t step = 0; step < REFIT_MAX_CHAIN; ++step) {
+        int32_t a = prev_link(i, n, next, prev, status);
+        if (a < 0) return i;
+        i = a;
+    }
+    return -1;
+}
+
+static void refit_chain(int32_t head, int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
+                        const int32_t *sector, const int32_t *first_row, const int32_t *status,
+                        const int32_t *next, const int32_t *prev, const double *y, const double *z,
+                        const double *row_x, int32_t n_rows, int32_t n_sectors, const double *map,
+                        const oracle_fit_params *prm, double *xo, double *po, double *co, double *chi2o,
+                        int32_t *ndfo, int32_t *sto)
+{
+    int32_t segs[REFIT_MAX_CHAIN];
+    int32_t ns = 0, n = 0, s = head;
+    *xo = 0.0;
+    *chi2o = 0.0;
+    *ndfo = 0;
+    for (int i = 0; i < 5; ++i) po[i] = 0.0;
+    for (int i = 0; i < 15; ++i) co[i] = 0.0;
+    while (s >= 0) {
+        if (ns == REFIT_MAX_CHAIN) { *sto = REFIT_LONG_CHAIN; return; }
+        segs[ns++] = s;
+        n += offsets[s + 1] - offsets[s];
+        s = next_link(s, n_tracks, next, prev, status);
+    }
+    *ndfo = 2 * n - 5;
+    for (int q = 0; q < ns; ++q) {
+        int32_t g = segs[q], m = offsets[g + 1] - offsets[g];
+        if (m < 1 || first_row[g] < 0 || first_row[g] + m > n_rows || sector[g] < 0 || sector[g] >= n_sectors) {
+            *sto = 1;
+            return;
+        }
+    }
+    /* the hit list: plane x, measurement and sector of each hit */
+    double *hx = (double *)malloc(sizeof(double) * (size_t)n * 3);
+    int32_t *hs = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * 2);
+    double *hy = hx + n, *hz = hx + 2 * (size_t)n;
+    int32_t *hg = hs + n;
+    int32_t k = 0;
+    for (int q = 0; q < ns; ++q) {
+        int32_t g = segs[q], m = offsets[g + 1] - offsets[g];
+        for (int32_t e = 0; e < m; ++e, ++k) {
+            int32_t r = first_row[g] + e, c = hits[offsets[g] + e];
+            hx[k] = row_x[r];
+            hy[k] = y[c];
+            hz[k] = z[c];
+            if (map) {
+                hy[k] -= map[((size_t)sector[g] * n_rows + r) * 2 + 0];
+                hz[k] -= map[((size_t)sector[g] * n_rows + r) * 2 + 1];
+            }
+            hs[k] = sector[g];
+            hg[k] = g;
+        }
+    }
+    double p[5], C[25];
+    int32_t st = 1;
+    if (n >= 3) {
+        /* the start: hits 0, (n-1)/2, n-1 in the frame of hit n-1 */
+        int32_t idx[3] = {0, (n - 1) / 2, n - 1};
+        double xs[3], ys[3], zs[3];
+        double at = sector_angle(hs[n - 1], n_sectors);
+        for (int q = 0; q < 3; ++q) {
+            int32_t h = idx[q];
+            double d = sector_angle(hs[h], n_sectors) - at;
+            xs[q] = hx[h] * cos(d) - hy[h] * sin(d);
+            ys[q] = hx[h] * sin(d) + hy[h] * cos(d);
+            zs[q] = hz[h];
+        }
+        xs[2] = hx[n - 1];
+        ys[2] = hy[n - 1];
+        st = start_points(3, xs, ys, zs, prm, p, C);
+    }
+    double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
+    double chi2 = 0.0, xcur = hx[n - 1];
+    for (k = n - 2; k >= 0 && !st; --k) {
+        if (hg[k] == hg[k + 1]) {
+            if (predict(p, C, hx[k] - hx[k + 1], prm)) { st = 2; break; }
+        } else {
+            double da = sector_angle(hs[k], n_sectors) - sector_angle(hs[k + 1], n_sectors);
+            if (da > PI_D) da -= 2.0 * PI_D;
+            if (da < -PI_D) da += 2.0 * PI_D;
+            double pn[5], J[25], JC[25], Jt[25];
+            if (oracle_transfer(p, hx[k + 1], da, hx[k], prm->bz, prm->max_sin, pn, J)) { st = 2; break; }
+            mat5_mul(J, C, JC);
+            for (int a = 0; a < 5; ++a)
+                for (int b = 0; b < 5; ++b) Jt[a * 5 + b] = J[b * 5 + a];
+            mat5_mul(JC, Jt, C);
+            for (int a = 0; a < 5; ++a) p[a] = pn[a];
+        }
+        xcur = hx[k];
+        if (update(p, C, hy[k], hz[k], vy, vz, &chi2)) { st = 3; break; }
+    }
+    if (n >= 3) {
+        *xo = xcur;
+        *chi2o = chi2;
+        for (int i = 0; i < 5; ++i) po[i] = p[i];
+        pack_cov(C, co);
+    }
+    *sto = st;
+    free(hx);
+    free(hs);
+}
+
+void oracle_refit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits, const int32_t *sector,
+                  const int32_t *first_row, const int32_t *status, const int32_t *next, const int32_t *prev,
+                  const int32_t *leg, const double *y, const double *z, const double *row_x, int32_t n_rows,
+                  int32_t n_sectors, const double *map, const oracle_fit_params *prm, int32_t *track_id,
+                  double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *rstatus,
+                  double *loop_par, double *loop_cov, double *loop_chi2)
+{
+    /* track ids: union of the linked segments, the smaller index the root */
+    for (int32_t i = 0; i < n_tracks; ++i) track_id[i] = status[i] == 0 ? i : -1;
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        int32_t nb[2] = {next_link(i, n_tracks, next, prev, status), leg_link(i, n_tracks, leg, status)};
+        for (int e = 0; e < 2; ++e) {
+            if (nb[e] < 0) continue;
+            int32_t a = uf_root(track_id, i), b = uf_root(track_id, nb[e]);
+            if (a < b) track_id[b] = a;
+            else if (b < a) track_id[a] = b;
+        }
+    }
+    for (int32_t i = 0; i < n_tracks; ++i)
+        if (track_id[i] >= 0) track_id[i] = uf_root(track_id, i);
+    /* chain refits at the heads */
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        double *po = par + (size_t)i * 5, *co = cov + (size_t)i * 15;
+        if (status[i] != 0 || prev_link(i, n_tracks, next, prev, status) >= 0) {
+            x_out[i] = 0.0;
+            chi2[i] = 0.0;
+            ndf[i] = 0;
+            rstatus[i] = REFIT_NOT_HEAD;
+            for (int q = 0; q < 5; ++q) po[q] = 0.0;
+            for (int q = 0; q < 15; ++q) co[q] = 0.0;
+            continue;
+        }
+        refit_chain(i, n_tracks, offsets, hits, sector, first_row, status, next, prev, y, z, row_x, n_rows,
+                    n_sectors, map, prm, &x_out[i], po, co, &chi2[i], &ndf[i], &rstatus[i]);
+    }
+    if (!loop_par) return;
+    /* the joint circle of each pair of looper legs */
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        double *lp = loop_par + (size_t)i * 4, *lc = loop_cov + (size_t)i * 10;
+        for (int q = 0; q < 4; ++q) lp[q] = 0.0;
+        for (int q = 0; q < 10; ++q) lc[q] = 0.0;
+        loop_chi2[i] = -1.0;
+        int32_t j = leg_link(i, n_tracks, leg, status);
+        if (j <= i) continue;
+        int32_t hi = chain_head(i, n_tracks, next, prev, status), hj = chain_head(j, n_tracks, next, prev, status);
+        if (hi < 0 || hj < 0 || hi == hj || rstatus[hi] != 0 || rstatus[hj] != 0) continue;
+        double mi[4], mj[4], Ji[20], Jj[20], Si[16], Sj[16], S[16], Sinv[16], d[4];
+        if (oracle_leg_circle(par + (size_t)hi * 5, x_out[hi], sector_angle(sector[hi], n_sectors), prm->bz, mi, Ji) ||
+            oracle_leg_circle(par + (size_t)hj * 5, x_out[hj], sector_angle(sector[hj], n_sectors), prm->bz, mj, Jj))
+            continue;
+        leg_cov(Ji, cov + (size_t)hi * 15, Si);
+        leg_cov(Jj, cov + (size_t)hj * 15, Sj);
+        /* D S_j D: the (centre, kappa/t) cross terms change sign */
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                Sj[a * 4 + b] *= ((a < 2) == (b < 2)) ? 1.0 : -1.0;
+                S[a * 4 + b] = Si[a * 4 + b] + Sj[a * 4 + b];
+            }
+        d[0] = mi[0] - mj[0];
+        d[1] = mi[1] - mj[1];
+        d[2] = mi[2] + mj[2];
+        d[3] = mi[3] + mj[3];
+        if (inv4(S, Sinv)) continue;
+        double K[16], Cf[16], chi = 0.0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double acc = 0.0;
+                for (int q = 0; q < 4; ++q) acc += Si[a * 4 + q] * Sinv[q * 4 + b];
+                K[a * 4 + b] = acc;                           /* S_i S^-1 */
+            }
+        for (int a = 0; a < 4; ++a) {
+            double acc = mi[a];
+            for (int q = 0; q < 4; ++q) acc -= K[a * 4 + q] * d[q];
+            lp[a] = acc;
+            for (int b = 0; b < 4; ++b) chi += d[a] * Sinv[a * 4 + b] * d[b];
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double acc = 0.0;
+                for (int q = 0; q < 4; ++q) acc += K[a * 4 + q] * Sj[q * 4 + b];
+                Cf[a * 4 + b] = acc;
+            }
+        for (int a = 0, q = 0; a < 4; ++a)
+            for (int b = 0; b <= a; ++b, ++q) lc[q] = 0.5 * (Cf[a * 4 + b] + Cf[b * 4 + a]);
+        loop_chi2[i] = chi;
+    }
+}

@@ -109,6 +109,17 @@ void oracle_legs(int32_t n_tracks, const double *x, const double *par, const dou
                  const int32_t *frame, const int32_t *sector, int32_t n_sectors, double bz, double cut,
                  int32_t *leg, double *leg_chi2);
 
+/* Tracks assembled from linked segments and refitted over all their hits
+ * (see tpc_oracle.c): component ids, the refit of each chain at its head
+ * (status 5 elsewhere, 6 for a chain of more than 18 segments) and the joint
+ * circle of each pair of looper legs (leg and loop_* may be NULL). */
+void oracle_refit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits, const int32_t *sector,
+                  const int32_t *first_row, const int32_t *status, const int32_t *next, const int32_t *prev,
+                  const int32_t *leg, const double *y, const double *z, const double *row_x, int32_t n_rows,
+                  int32_t n_sectors, const double *map, const oracle_fit_params *prm, int32_t *track_id,
+                  double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *rstatus,
+                  double *loop_par, double *loop_cov, double *loop_chi2);
+
 void oracle_ctf_build(int32_t n_tracks, int32_t n_rows, int32_t n_sectors, int32_t n_segments,
                       const int32_t *row_offsets, const float *y, const float *z,
                       const int32_t *rows, const int32_t *status, const int32_t *frame,
