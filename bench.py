@@ -678,7 +678,9 @@ def _one_seed_coverage(fr, sd, min_clusters=20, frac=0.8):
 
 
 def leg_merge(args):
-    """tpc_track_merge on the headline event's fitted seeds, HIP events on the launch stream."""
+    """tpc_track_merge on the headline event's fitted seeds (links only, then
+    links and looper legs) and tpc_track_refit on its links: each C-ABI call
+    between HIP events on the launch stream, into preallocated outputs."""
     import torch
     from tpcsynth import make_config
     fr = make_config(1)
@@ -688,24 +690,37 @@ def leg_merge(args):
     up, dn = reco.neighbours(dfr, ws=ws)
     seeds = reco.seed(dfr, up, dn, ws=ws)
     tr = reco.fit(dfr, seeds)
-    nxt, prv, chi, mp, mc, leg, lchi = reco.merge(seeds, tr, MERGE_CUT)
+    out = reco.alloc_merge(seeds, legs=True)
+    nxt, prv, chi, mp, mc, leg, lchi = reco.merge(seeds, tr, MERGE_CUT, out=out)
+    rf = reco.refit(dfr, seeds, tr, nxt, prv, leg)
     torch.cuda.synchronize()
     T = int(seeds.n_seeds.item())
     stream = torch.cuda.current_stream()
-    evs = []
-    for _ in range(max(5, args.steps)):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record(stream)
-        nxt, prv, chi, mp, mc, leg, lchi = reco.merge(seeds, tr, MERGE_CUT)
-        e[1].record(stream)
-        evs.append(e)
-    torch.cuda.synchronize()
-    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+
+    def timed_events(fn):
+        evs = []
+        for _ in range(max(5, args.steps)):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record(stream)
+            fn()
+            e[1].record(stream)
+            evs.append(e)
+        torch.cuda.synchronize()
+        return float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+
+    ms_links = timed_events(lambda: reco.merge(seeds, tr, MERGE_CUT, out=out, legs=False))
+    ms_legs = timed_events(lambda: reco.merge(seeds, tr, MERGE_CUT, out=out, legs=True))
+    ms_refit = timed_events(lambda: reco.refit(dfr, seeds, tr, nxt, prv, leg, out=rf))
     links = int((nxt[:T] >= 0).sum().item())
     legs = int((leg[:T] >= 0).sum().item()) // 2
+    st = rf["refit"].status[:T]
+    heads = int((st != 5).sum().item())
+    multi = int(((st != 5) & (nxt[:T] >= 0)).sum().item())
+    tracks = int(torch.unique(rf["track_id"][:T][rf["track_id"][:T] >= 0]).numel())
     return {"workload": fr.meta["name"], "seeds": T, "chi2_cut": MERGE_CUT, "links": links, "looper_leg_pairs": legs,
-            "ms": round(ms, 5),
-            "segments_per_s": round(T / ms * 1e3, 1)}
+            "ms_links": round(ms_links, 5), "ms_links_and_legs": round(ms_legs, 5),
+            "ms_refit": round(ms_refit, 5), "chains": heads, "multi_segment_chains": multi, "tracks": tracks,
+            "segments_per_s": round(T / ms_legs * 1e3, 1)}
 
 
 MERGE_CUT = 30.0

@@ -53,6 +53,8 @@ typedef int32_t tpc_status;
 #define TPC_FIT_SIN_FAIL     2   /* propagation reached |sin phi| >= max_sin */
 #define TPC_FIT_NUM_FAIL     3   /* singular residual covariance or non-finite state */
 #define TPC_FOLLOW_DUPLICATE 4   /* tpc_track_follow: fewer than half of its clusters are its own */
+#define TPC_REFIT_NOT_HEAD   5   /* tpc_track_refit: not the head of a chain (nothing written) */
+#define TPC_REFIT_LONG_CHAIN 6   /* tpc_track_refit: a chain of more than 18 segments */
 
 /* Reconstruction constants.  Copied at tpc_create(); the context is immutable. */
 typedef struct tpc_config {
@@ -457,6 +459,48 @@ tpc_status tpc_track_follow(const tpc_context *ctx, const tpc_frames *frames,
 tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *seeds, const tpc_tracks *tracks,
                            float chi2_cut, int32_t *next, int32_t *prev, float *chi2, float *merged_par,
                            float *merged_cov, int32_t *leg, float *leg_chi2, void *stream);
+
+/* Tracks assembled from linked segments and refitted over all their hits
+ * (the step after merging; the paper implies it but does not describe it).
+ * Links: a next link i -> j counts when j = next[i] is another segment with
+ * prev[j] = i and both segment fits (segments->status) are TPC_FIT_OK; a leg
+ * link i -- j when leg[j] = i likewise (leg NULL: none).  next, prev and leg
+ * are read as tpc_track_merge writes them.
+ * track_id [cap_seeds] (device int32): the connected components of the
+ * segments of status TPC_FIT_OK under both kinds of link, each named by its
+ * smallest segment index; -1 for a segment whose own fit failed.
+ * refit: as a fit writes tracks, one entry per segment.  A chain head (status
+ * TPC_FIT_OK, no counted prev link) gets the refit of its chain -- the head
+ * and the segments its next links reach, at most 18 (else
+ * TPC_REFIT_LONG_CHAIN) -- over all their hits k = 0..n-1 (the head's in
+ * ascending row, then the next segment's, ...), each measured in its own
+ * sector's frame and corrected by `map` as tpc_kalman_fit does: the exact
+ * circle through hits n-1, (n-1)/2 and 0, all seen from the frame of hit n-1
+ * (a point (x, y) of a sector at angle a_s seen from the frame at angle a_t:
+ * (x cos d - y sin d, x sin d + y cos d), d = a_s - a_t, sector angles as in
+ * tpc_track_merge), starts the filter at hit n-1 with the start covariance;
+ * it runs inwards, a helix step within a segment and, across a segment
+ * boundary, the rotation into the inner segment's frame and the step on to
+ * its plane (the transfer of tpc_track_merge, covariance J C J^T), each
+ * followed by the update.  Written at the head: the state at its innermost
+ * hit in its frame, chi2, ndf = 2n - 5, status TPC_FIT_*.  Every other
+ * segment gets status TPC_REFIT_NOT_HEAD and zeros.  A chain of one segment
+ * is refitted exactly as its seed fit.
+ * loop_par [cap_seeds][4], loop_cov [cap_seeds][10] (packed lower
+ * triangle), loop_chi2 [cap_seeds] (device float; all three or none, and
+ * none when leg is NULL): for each counted leg link i -- j with i < j whose
+ * chains' refits have status TPC_FIT_OK, the joint circle of the two legs
+ * at index i: the circles m = (X_c, Y_c, kappa, tan lambda) of the two
+ * refitted chains at their heads (as tpc_track_merge's legs), fused in the
+ * sense of i's chain: S = S_i + D S_j D, d = m_i - D m_j, m = m_i - S_i S^-1
+ * d, C = S_i S^-1 D S_j D, chi2 = d^T S^-1 d; elsewhere zeros and chi2 -1.
+ * Seeds are read as tpc_ca_seed writes them (hit_yz is not used); the first
+ * min(*n_seeds, cap_seeds) entries of each output are written.  No
+ * workspace. */
+tpc_status tpc_track_refit(const tpc_context *ctx, const tpc_frames *frames, const tpc_seeds *seeds,
+                           const tpc_tracks *segments, const int32_t *next, const int32_t *prev,
+                           const int32_t *leg, const float *map, int32_t *track_id, tpc_tracks *refit,
+                           float *loop_par, float *loop_cov, float *loop_chi2, void *stream);
 
 /* Entropy coding of a time frame's integer arrays (Sec. 4.1: every flat
  * integer array is coded on its own with range asymmetric numeral systems,

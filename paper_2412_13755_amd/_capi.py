@@ -24,6 +24,8 @@ TPC_ERR_WORKSPACE = -5
 
 TPC_FIT_OK, TPC_FIT_INIT_FAIL, TPC_FIT_SIN_FAIL, TPC_FIT_NUM_FAIL = 0, 1, 2, 3
 TPC_FOLLOW_DUPLICATE = 4
+TPC_REFIT_NOT_HEAD = 5
+TPC_REFIT_LONG_CHAIN = 6
 
 TPC_STAGE_NEIGHBOURS = 1
 TPC_STAGE_SEED = 2
@@ -130,6 +132,8 @@ SIGNATURES = {
                               P]),
     "tpc_track_merge": (i32, [P, ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), ctypes.c_float, P, P, P, P, P,
                               P, P, P]),
+    "tpc_track_refit": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC), ctypes.POINTER(TracksC), P, P,
+                              P, P, P, ctypes.POINTER(TracksC), P, P, P, P]),
     "tpc_track_follow": (i32, [P, ctypes.POINTER(FramesC), ctypes.POINTER(SeedsC),
                                ctypes.POINTER(FollowParams), P, ctypes.POINTER(TracksC), P,
                                ctypes.c_size_t, P]),

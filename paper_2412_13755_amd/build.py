@@ -32,6 +32,7 @@ SOURCES = {
     "tpc_ctf.hip": [],
     "tpc_fit_ms.hip": [],
     "tpc_merge.hip": [],
+    "tpc_refit.hip": [],
     "tpc_nb_skip.hip": ["-ffp-contract=off"],
 }
 

@@ -15,6 +15,7 @@
 #include "tpc_fit_ms.hpp"
 #include "tpc_nb_skip.hpp"
 #include "tpc_merge.hpp"
+#include "tpc_refit.hpp"
 #include "tpc_rans_dec.hpp"
 
 namespace {
@@ -605,6 +606,26 @@ tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *sd, const tp
     hipError_t e = launch_merge(ctx, sd, tr, (double)chi2_cut, next, prev, chi2, merged_par, merged_cov, leg,
                                 leg_chi2, (hipStream_t)stream);
     return e == hipSuccess ? TPC_OK : hip_fail(e, "merge kernels");
+}
+
+tpc_status tpc_track_refit(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
+                           const tpc_tracks *seg, const int32_t *next, const int32_t *prev, const int32_t *leg,
+                           const float *map, int32_t *track_id, tpc_tracks *out, float *loop_par,
+                           float *loop_cov, float *loop_chi2, void *stream) {
+    g_err[0] = 0;
+    tpc_status s = check_frames(ctx, fr);
+    if (s) return s;
+    if ((s = check_seeds_for_fit(sd))) return s;
+    if (!seg || (sd->cap_seeds > 0 && !seg->status)) return fail(TPC_ERR_ARG, "null segment status");
+    if ((s = check_tracks(sd, out))) return s;
+    if (sd->cap_seeds > 0 && (!next || !prev || !track_id)) return fail(TPC_ERR_ARG, "null links or track ids");
+    const int nl = (loop_par != nullptr) + (loop_cov != nullptr) + (loop_chi2 != nullptr);
+    if (nl != 0 && nl != 3) return fail(TPC_ERR_ARG, "loop_par, loop_cov and loop_chi2 must all be given or all null");
+    if (nl && !leg) return fail(TPC_ERR_ARG, "looper circles need leg links");
+    if (sd->cap_seeds == 0) return TPC_OK;
+    hipError_t e = launch_refit(ctx, fr, sd, seg, next, prev, leg, map, track_id, out, loop_par, loop_cov,
+                                loop_chi2, (hipStream_t)stream);
+    return e == hipSuccess ? TPC_OK : hip_fail(e, "refit kernels");
 }
 
 tpc_status tpc_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,

@@ -346,25 +346,64 @@ class Reco:
                                          ws.data_ptr(), ws.numel(), _stream_handle(self.device)))
         return rows, tracks
 
-    def merge(self, seeds: Seeds, tracks: Tracks, chi2_cut: float):
-        """tpc_track_merge: links between fitted segments of neighbouring
-        sectors, and the pairing of the legs of loopers.  Returns (next, prev,
-        chi2, merged_par [T, 5], merged_cov [T, 15], leg, leg_chi2) per seed."""
+    def alloc_merge(self, seeds: Seeds, legs: bool = True) -> dict:
+        """Output tensors of tpc_track_merge (merged states and, with legs,
+        the looper pairing)."""
         T = max(seeds.frame.numel(), 1)
         d = self.device
-        nxt = torch.full((T,), -1, dtype=torch.int32, device=d)
-        prv = torch.full((T,), -1, dtype=torch.int32, device=d)
-        chi = torch.zeros(T, dtype=torch.float32, device=d)
-        mp = torch.zeros(T, 5, dtype=torch.float32, device=d)
-        mc = torch.zeros(T, 15, dtype=torch.float32, device=d)
-        leg = torch.full((T,), -1, dtype=torch.int32, device=d)
-        lchi = torch.zeros(T, dtype=torch.float32, device=d)
+        out = dict(next=torch.empty(T, dtype=torch.int32, device=d), prev=torch.empty(T, dtype=torch.int32, device=d),
+                   chi2=torch.empty(T, device=d), merged_par=torch.empty(T, 5, device=d),
+                   merged_cov=torch.empty(T, 15, device=d))
+        if legs:
+            out.update(leg=torch.empty(T, dtype=torch.int32, device=d), leg_chi2=torch.empty(T, device=d))
+        return out
+
+    def merge(self, seeds: Seeds, tracks: Tracks, chi2_cut: float, out: Optional[dict] = None, legs: bool = True):
+        """tpc_track_merge: links between fitted segments of neighbouring
+        sectors, and (legs=True) the pairing of the legs of loopers.  Returns
+        (next, prev, chi2, merged_par [T, 5], merged_cov [T, 15], leg,
+        leg_chi2) per seed (leg, leg_chi2 None without legs); `out` from
+        alloc_merge is filled in place."""
+        out = self.alloc_merge(seeds, legs) if out is None else out
+        if legs and "leg" not in out:
+            raise ValueError("legs requested but out has no leg buffers")
+        leg, lchi = (out["leg"], out["leg_chi2"]) if legs else (None, None)
         sc = seeds.c()
         tc = tracks.c()
         C.check(C.lib().tpc_track_merge(self._ctx, ctypes.byref(sc), ctypes.byref(tc), ctypes.c_float(chi2_cut),
-                                        nxt.data_ptr(), prv.data_ptr(), chi.data_ptr(), mp.data_ptr(),
-                                        mc.data_ptr(), leg.data_ptr(), lchi.data_ptr(), _stream_handle(d)))
-        return nxt, prv, chi, mp, mc, leg, lchi
+                                        out["next"].data_ptr(), out["prev"].data_ptr(), out["chi2"].data_ptr(),
+                                        out["merged_par"].data_ptr(), out["merged_cov"].data_ptr(),
+                                        None if leg is None else leg.data_ptr(),
+                                        None if lchi is None else lchi.data_ptr(), _stream_handle(self.device)))
+        return out["next"], out["prev"], out["chi2"], out["merged_par"], out["merged_cov"], leg, lchi
+
+    def refit(self, frames: DeviceFrames, seeds: Seeds, segments: Tracks, nxt: torch.Tensor, prv: torch.Tensor,
+              leg: Optional[torch.Tensor] = None, map_: Optional[torch.Tensor] = None, out: Optional[dict] = None):
+        """tpc_track_refit: track ids over the merging links, the refit of
+        every chain of linked segments over all its hits (at the chain's
+        head) and, with leg links, the joint circle of each pair of looper
+        legs.  Returns a dict: track_id, refit (Tracks), and with leg
+        loop_par [T, 4], loop_cov [T, 10], loop_chi2 [T]."""
+        self._check_map(map_)
+        if out is None:
+            T = max(seeds.frame.numel(), 1)
+            d = self.device
+            out = dict(track_id=torch.empty(T, dtype=torch.int32, device=d), refit=self.alloc_tracks(seeds))
+            if leg is not None:
+                out.update(loop_par=torch.empty(T, 4, device=d), loop_cov=torch.empty(T, 10, device=d),
+                           loop_chi2=torch.empty(T, device=d))
+        lp = out.get("loop_par") if leg is not None else None
+        sc = seeds.c()
+        gc = segments.c()
+        rc = out["refit"].c()
+        C.check(C.lib().tpc_track_refit(self._ctx, ctypes.byref(frames.c), ctypes.byref(sc), ctypes.byref(gc),
+                                        nxt.data_ptr(), prv.data_ptr(), None if leg is None else leg.data_ptr(),
+                                        None if map_ is None else map_.data_ptr(), out["track_id"].data_ptr(),
+                                        ctypes.byref(rc), None if lp is None else lp.data_ptr(),
+                                        None if lp is None else out["loop_cov"].data_ptr(),
+                                        None if lp is None else out["loop_chi2"].data_ptr(),
+                                        _stream_handle(self.device)))
+        return out
 
     def alloc_ctf(self, frames: DeviceFrames, seeds: Seeds) -> dict:
         T, N = seeds.frame.numel(), max(frames.n_clusters, 1)
