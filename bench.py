@@ -885,6 +885,9 @@ def main():
     if legs == {"rans"}:
         print(json.dumps({"rans": leg_rans(args, not args.no_cpu)}), flush=True)
         return
+    if legs == {"merge"}:
+        print(json.dumps({"merge": leg_merge(args)}), flush=True)
+        return
     main_res, fr, host = leg_path(args, 2)
     out = {
         "metric": "M clusters/s through CA seed+Kalman fit (plain vs batched); adjoint grads/s",

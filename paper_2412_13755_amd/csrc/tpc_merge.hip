@@ -197,19 +197,38 @@ __device__ inline double pair_chi2(const MgArgs &A, int a, int b, double ca, dou
     return pair_fuse(A, a, b, ca, sa, nullptr, nullptr);
 }
 
-// Candidates of one lane that pass the tan(lambda) / q/pT test, per chunk of
-// the neighbouring sector's segments: kept in the lane's own LDS column, so
-// that the transfer runs over short lists (a wavefront's iterations are the
-// longest list of its lanes) instead of every candidate of every lane.
+// MG_SPLIT lanes of one wavefront share a segment and take every
+// MG_SPLIT-th candidate of each neighbouring sector (enough wavefronts for
+// the chip); their best partners are reduced by shuffles at the end
+// (smaller chi2, then smaller index: the serial order's choice).  Per chunk
+// of MG_CHUNK candidates, the ones that pass the tan(lambda) / q/pT test go
+// to the lane's own LDS column, so that the transfer runs over short lists
+// (a wavefront's iterations are the longest list of its lanes) instead of
+// every candidate of every lane.
+#define MG_SPLIT 4
 #define MG_CHUNK 64
+#define MG_LANE_CHUNK (MG_CHUNK / MG_SPLIT)
+
+// (chi, j) of another lane replaces this lane's best when smaller, or equal
+// with a smaller index
+__device__ inline void best_merge(double &chi, int &j, double oc, int oj) {
+    if (oc < chi || (oc == chi && oj >= 0 && (j < 0 || oj < j))) {
+        chi = oc;
+        j = oj;
+    }
+}
 
 __global__ void __launch_bounds__(TPC_BLOCK) mg_best(MgArgs A) {
-    __shared__ int cand[MG_CHUNK][TPC_BLOCK];
+    __shared__ int cand[MG_LANE_CHUNK][TPC_BLOCK];
     const int T = mg_count(A);
-    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+    const int sub = threadIdx.x % MG_SPLIT;
+    const int per_block = TPC_BLOCK / MG_SPLIT;
+    // whole workgroups step together: every lane reaches the shuffles
+    for (int base = blockIdx.x * per_block; base < T; base += gridDim.x * per_block) {
+        const int i = base + threadIdx.x / MG_SPLIT;
         int bo = -1, bi = -1;
         double co = INFINITY, ci_ = INFINITY;
-        if (A.status[i] == 0 && A.n_sectors == 36) {
+        if (i < T && A.status[i] == 0 && A.n_sectors == 36) {
             const float *pi_ = A.par + (size_t)i * 5, *ci = A.cov + (size_t)i * 15;
             const double ri = hypot((double)A.x[i], (double)pi_[0]);
             const double ti = (double)pi_[3], wi = (double)pi_[4], vti = (double)ci[9], vwi = (double)ci[14];
@@ -227,7 +246,7 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_best(MgArgs A) {
                 for (int c0 = j0; c0 < j1; c0 += MG_CHUNK) {
                     const int c1 = c0 + MG_CHUNK < j1 ? c0 + MG_CHUNK : j1;
                     int n = 0;
-                    for (int j = c0; j < c1; ++j) {
+                    for (int j = c0 + sub; j < c1; j += MG_SPLIT) {
                         if (A.status[j] != 0) continue;
                         const float *pj = A.par + (size_t)j * 5, *cj = A.cov + (size_t)j * 15;
                         // the (t, w) block of the pair's covariance is the sum of the
@@ -261,9 +280,16 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_best(MgArgs A) {
                 }
             }
         }
-        A.next[i] = bo;
-        A.chi2[i] = bo >= 0 ? (float)co : 0.f;
-        A.prev[i] = bi;
+#pragma unroll
+        for (int d = 1; d < MG_SPLIT; d <<= 1) {
+            best_merge(co, bo, __shfl_xor(co, d, TPC_WAVE), __shfl_xor(bo, d, TPC_WAVE));
+            best_merge(ci_, bi, __shfl_xor(ci_, d, TPC_WAVE), __shfl_xor(bi, d, TPC_WAVE));
+        }
+        if (i < T && sub == 0) {
+            A.next[i] = bo;
+            A.chi2[i] = bo >= 0 ? (float)co : 0.f;
+            A.prev[i] = bi;
+        }
     }
 }
 
@@ -309,11 +335,11 @@ __global__ void __launch_bounds__(TPC_BLOCK) mg_link_prev(MgArgs A) {
 
 struct Circle {
     double m[4];
-    double S[4][4];       // J C J^T
+    double s00, s10, s11, s20, s21, s22, s30, s31, s32, s33;   // J C J^T, lower triangle
 };
 
 // The circle of segment i (false if too large or degenerate).
-__device__ bool leg_circle(const MgArgs &A, int i, Circle &o) {
+__device__ __forceinline__ bool leg_circle(const MgArgs &A, int i, Circle &o) {
     const float *p = A.par + (size_t)i * 5, *co = A.cov + (size_t)i * 15;
     const double y = (double)p[0], s = (double)p[2], t = (double)p[3], w = (double)p[4];
     const double k = A.kbz, kap = k * w;
@@ -329,6 +355,7 @@ __device__ bool leg_circle(const MgArgs &A, int i, Circle &o) {
     const double dxc[5] = {0.0, 0.0, -1.0 / kap, 0.0, s * k / (kap * kap)};
     const double dyc[5] = {1.0, 0.0, -s / (c * kap), 0.0, -c * k / (kap * kap)};
     double J[4][5];
+#pragma unroll
     for (int j = 0; j < 5; ++j) {
         J[0][j] = dxc[j] * ca - dyc[j] * sa;
         J[1][j] = dxc[j] * sa + dyc[j] * ca;
@@ -336,130 +363,160 @@ __device__ bool leg_circle(const MgArgs &A, int i, Circle &o) {
         J[3][j] = j == 3 ? 1.0 : 0.0;
     }
     double C[5][5];
+#pragma unroll
     for (int a = 0, q = 0; a < 5; ++a)
+#pragma unroll
         for (int b = 0; b <= a; ++b, ++q) C[a][b] = C[b][a] = (double)co[q];
     double JC[4][5];
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
         for (int b = 0; b < 5; ++b) {
             double acc = 0.0;
+#pragma unroll
             for (int q = 0; q < 5; ++q) acc += J[a][q] * C[q][b];
             JC[a][b] = acc;
         }
+    double S[4][4];
+#pragma unroll
     for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
             double acc = 0.0;
+#pragma unroll
             for (int q = 0; q < 5; ++q) acc += JC[a][q] * J[b][q];
-            o.S[a][b] = acc;
+            S[a][b] = acc;
         }
+    o.s00 = S[0][0];
+    o.s10 = S[1][0]; o.s11 = S[1][1];
+    o.s20 = S[2][0]; o.s21 = S[2][1]; o.s22 = S[2][2];
+    o.s30 = S[3][0]; o.s31 = S[3][1]; o.s32 = S[3][2]; o.s33 = S[3][3];
     return true;
 }
 
+// chi2 of legs a and b (m_a - D m_b against S_a + D S_b D, D = diag(1, 1,
+// -1, -1): the (centre, kappa/t) cross terms of S_b change sign), by a 4x4
+// Cholesky; INFINITY if the sum is not positive definite.
+__device__ __forceinline__ double leg_chi2(const Circle &a, const Circle &b) {
+    const double d0 = a.m[0] - b.m[0], d1 = a.m[1] - b.m[1], d2 = a.m[2] + b.m[2], d3 = a.m[3] + b.m[3];
+    const double S00 = a.s00 + b.s00, S10 = a.s10 + b.s10, S11 = a.s11 + b.s11;
+    const double S20 = a.s20 - b.s20, S21 = a.s21 - b.s21, S22 = a.s22 + b.s22;
+    const double S30 = a.s30 - b.s30, S31 = a.s31 - b.s31, S32 = a.s32 + b.s32, S33 = a.s33 + b.s33;
+    bool ok = S00 > 0.0;
+    const double L00 = sqrt(ok ? S00 : 1.0);
+    const double L10 = S10 / L00, L20 = S20 / L00, L30 = S30 / L00;
+    const double e11 = S11 - L10 * L10;
+    ok = ok && e11 > 0.0;
+    const double L11 = sqrt(ok ? e11 : 1.0);
+    const double L21 = (S21 - L20 * L10) / L11, L31 = (S31 - L30 * L10) / L11;
+    const double e22 = S22 - L20 * L20 - L21 * L21;
+    ok = ok && e22 > 0.0;
+    const double L22 = sqrt(ok ? e22 : 1.0);
+    const double L32 = (S32 - L30 * L20 - L31 * L21) / L22;
+    const double e33 = S33 - L30 * L30 - L31 * L31 - L32 * L32;
+    ok = ok && e33 > 0.0;
+    const double L33 = sqrt(ok ? e33 : 1.0);
+    const double z0 = d0 / L00;
+    const double z1 = (d1 - L10 * z0) / L11;
+    const double z2 = (d2 - L20 * z0 - L21 * z1) / L22;
+    const double z3 = (d3 - L30 * z0 - L31 * z1 - L32 * z2) / L33;
+    return ok ? z0 * z0 + z1 * z1 + z2 * z2 + z3 * z3 : INFINITY;
+}
+
+// Candidates are the segments of the segment's (frame, side): one
+// contiguous seed range.  LG_SPLIT lanes of one wavefront share a segment
+// and take every LG_SPLIT-th candidate, so that the chip holds enough
+// wavefronts; their best candidates are reduced by shuffles at the end
+// (smaller chi2, then smaller index: the serial order's choice).  The
+// workgroup walks the union of its segments' ranges in tiles of TPC_BLOCK
+// segments: each thread forms the circle of one tile segment into LDS, then
+// the lanes test the tile from there.  Each circle is formed once per
+// workgroup and tile instead of once per pair.
+#define LG_SPLIT 8
+#define LG_SEGS (TPC_BLOCK / LG_SPLIT)
+
+struct LegTile {
+    double m[4][TPC_BLOCK];
+    double s[10][TPC_BLOCK];
+    int ok[TPC_BLOCK];
+};
+
 __global__ void __launch_bounds__(TPC_BLOCK) lg_best(MgArgs A) {
-    __shared__ int cand[MG_CHUNK][TPC_BLOCK];
+    __shared__ LegTile tile;
+    __shared__ int span[2];
     const int T = mg_count(A);
-    const int lane = threadIdx.x & (TPC_WAVE - 1);
-    const double k2 = A.kbz * A.kbz;
-    // whole workgroups step together, so every lane of a wavefront stays in
-    // the loop body (the shuffles below need them all)
-    for (int base = blockIdx.x * TPC_BLOCK; base < T; base += gridDim.x * TPC_BLOCK) {
-        const int i = base + threadIdx.x;
+    const int sub = threadIdx.x % LG_SPLIT;
+    // whole workgroups step together: every lane reaches the barriers and
+    // the shuffles
+    for (int base = blockIdx.x * LG_SEGS; base < T; base += gridDim.x * LG_SEGS) {
+        const int i = base + threadIdx.x / LG_SPLIT;
         int best = -1;
         double bchi = INFINITY;
         Circle ci;
         const bool live = i < T && A.status[i] == 0 && A.n_sectors == 36 && leg_circle(A, i, ci);
-        int j0 = 0, j1 = 0;
-        double wi = 0.0, ti = 0.0, vwi = 0.0, vti = 0.0;
+        int j0 = T, j1 = 0;
         if (live) {
             const int64_t key = (int64_t)A.frame[i] * A.n_sectors + (A.sector[i] / 18) * 18;
             j0 = mg_lower(A, T, key);
             j1 = mg_lower(A, T, key + 18);
-            wi = (double)A.par[(size_t)i * 5 + 4];
-            ti = (double)A.par[(size_t)i * 5 + 3];
-            vwi = (double)A.cov[(size_t)i * 15 + 14];
-            vti = (double)A.cov[(size_t)i * 15 + 9];
         }
-        // one candidate range for every live lane (its segments share a frame
-        // and side): lanes load one candidate each per chunk and test it on
-        // shuffled copies; otherwise each lane walks its own range
-        const unsigned long long lv = __ballot(live);
-        const int lead = lv ? __ffsll((long long)lv) - 1 : 0;
-        const int L0 = __shfl(j0, lead), L1 = __shfl(j1, lead);
-        const bool shared_range = __all(!live || (j0 == L0 && j1 == L1));
-        const int r0 = shared_range ? L0 : j0, r1 = shared_range ? L1 : j1;
-        for (int c0 = r0; c0 < r1; c0 += MG_CHUNK) {
-            const int c1 = c0 + MG_CHUNK < r1 ? c0 + MG_CHUNK : r1;
-            int n = 0;
-            if (shared_range) {
-                const int jl = c0 + lane;
-                double wq = 0.0, tq = 0.0, vwq = 0.0, vtq = 0.0;
-                int okq = 0;
-                if (jl < c1) {
-                    okq = A.status[jl] == 0;
-                    wq = (double)A.par[(size_t)jl * 5 + 4];
-                    tq = (double)A.par[(size_t)jl * 5 + 3];
-                    vwq = (double)A.cov[(size_t)jl * 15 + 14];
-                    vtq = (double)A.cov[(size_t)jl * 15 + 9];
-                }
-                for (int q = 0; q < c1 - c0; ++q) {
-                    const int ok = __shfl(okq, q);
-                    const double wj = __shfl(wq, q), tj = __shfl(tq, q);
-                    const double vwj = __shfl(vwq, q), vtj = __shfl(vtq, q);
-                    const double dk = A.kbz * (wi + wj), dt = ti + tj;
-                    if (live && ok && c0 + q != i && !(dk * dk > A.cut * k2 * (vwi + vwj)) &&
-                        !(dt * dt > A.cut * (vti + vtj)))
-                        cand[n++][threadIdx.x] = c0 + q;
-                }
-            } else if (live) {
-                for (int j = c0; j < c1; ++j) {
-                    if (j == i || A.status[j] != 0) continue;
-                    const float *pj = A.par + (size_t)j * 5, *cj = A.cov + (size_t)j * 15;
-                    // curvature and tan(lambda) alone (their rows of J are exact
-                    // and need no circle): a pair failing either cannot pass
-                    const double dk = A.kbz * (wi + (double)pj[4]), dt = ti + (double)pj[3];
-                    if (dk * dk > A.cut * k2 * (vwi + (double)cj[14]) || dt * dt > A.cut * (vti + (double)cj[9]))
+        if (threadIdx.x == 0) {
+            span[0] = T;
+            span[1] = 0;
+        }
+        __syncthreads();
+        if (live && sub == 0) {
+            atomicMin(&span[0], j0);
+            atomicMax(&span[1], j1);
+        }
+        __syncthreads();
+        const int u0 = span[0], u1 = span[1];
+        for (int c0 = u0; c0 < u1; c0 += TPC_BLOCK) {
+            const int c = c0 + threadIdx.x;
+            Circle cc;
+            const bool okc = c < u1 && A.status[c] == 0 && leg_circle(A, c, cc);
+            tile.ok[threadIdx.x] = okc;
+            if (okc) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tile.m[q][threadIdx.x] = cc.m[q];
+                tile.s[0][threadIdx.x] = cc.s00; tile.s[1][threadIdx.x] = cc.s10; tile.s[2][threadIdx.x] = cc.s11;
+                tile.s[3][threadIdx.x] = cc.s20; tile.s[4][threadIdx.x] = cc.s21; tile.s[5][threadIdx.x] = cc.s22;
+                tile.s[6][threadIdx.x] = cc.s30; tile.s[7][threadIdx.x] = cc.s31; tile.s[8][threadIdx.x] = cc.s32;
+                tile.s[9][threadIdx.x] = cc.s33;
+            }
+            __syncthreads();
+            const int n = u1 - c0 < TPC_BLOCK ? u1 - c0 : TPC_BLOCK;
+            if (live) {
+                const int q0 = j0 > c0 ? j0 - c0 : 0;
+                const int q1 = j1 - c0 < n ? j1 - c0 : n;
+                // this lane's candidates: q = sub (mod LG_SPLIT) in [q0, q1)
+                for (int q = q0 + ((sub - q0 % LG_SPLIT + LG_SPLIT) % LG_SPLIT); q < q1; q += LG_SPLIT) {
+                    const int j = c0 + q;
+                    if (!tile.ok[q] || j == i) continue;
+                    // curvature and tan(lambda) alone (exact rows of J): a pair
+                    // failing either cannot pass the full test
+                    const double dk = ci.m[2] + tile.m[2][q], dt = ci.m[3] + tile.m[3][q];
+                    if (dk * dk > A.cut * (ci.s22 + tile.s[5][q]) || dt * dt > A.cut * (ci.s33 + tile.s[9][q]))
                         continue;
-                    cand[n++][threadIdx.x] = j;
-                }
-            }
-            for (int q = 0; q < n; ++q) {
-                const int j = cand[q][threadIdx.x];
-                Circle cj;
-                if (!leg_circle(A, j, cj)) continue;
-                double S[4][4], d[4];
-                for (int a = 0; a < 4; ++a)
-                    for (int b = 0; b < 4; ++b)
-                        S[a][b] = ci.S[a][b] + (((a < 2) == (b < 2)) ? 1.0 : -1.0) * cj.S[a][b];
-                d[0] = ci.m[0] - cj.m[0];
-                d[1] = ci.m[1] - cj.m[1];
-                d[2] = ci.m[2] + cj.m[2];
-                d[3] = ci.m[3] + cj.m[3];
-                // chi2 = |L^-1 d|^2, S = L L^T
-                double L[4][4], z[4], chi = 0.0;
-                bool ok = true;
-                for (int a = 0; a < 4 && ok; ++a) {
-                    for (int b = 0; b <= a; ++b) {
-                        double acc = S[a][b];
-                        for (int m = 0; m < b; ++m) acc -= L[a][m] * L[b][m];
-                        if (a == b) {
-                            if (!(acc > 0.0)) { ok = false; break; }
-                            L[a][a] = sqrt(acc);
-                        } else {
-                            L[a][b] = acc / L[b][b];
-                        }
+                    Circle cj;
+                    cj.m[0] = tile.m[0][q]; cj.m[1] = tile.m[1][q]; cj.m[2] = tile.m[2][q]; cj.m[3] = tile.m[3][q];
+                    cj.s00 = tile.s[0][q]; cj.s10 = tile.s[1][q]; cj.s11 = tile.s[2][q]; cj.s20 = tile.s[3][q];
+                    cj.s21 = tile.s[4][q]; cj.s22 = tile.s[5][q]; cj.s30 = tile.s[6][q]; cj.s31 = tile.s[7][q];
+                    cj.s32 = tile.s[8][q]; cj.s33 = tile.s[9][q];
+                    const double chi = leg_chi2(ci, cj);
+                    if (chi > 0.0 && chi <= A.cut && chi < bchi) {   // j ascends: ties keep the smaller
+                        bchi = chi;
+                        best = j;
                     }
-                    if (!ok) break;
-                    double acc = d[a];
-                    for (int m = 0; m < a; ++m) acc -= L[a][m] * z[m];
-                    z[a] = acc / L[a][a];
-                    chi += z[a] * z[a];
-                }
-                if (ok && chi > 0.0 && chi <= A.cut && (chi < bchi || (chi == bchi && j < best))) {
-                    bchi = chi;
-                    best = j;
                 }
             }
+            __syncthreads();
         }
-        if (i < T) {
+#pragma unroll
+        for (int d = 1; d < LG_SPLIT; d <<= 1) {
+            best_merge(bchi, best, __shfl_xor(bchi, d, TPC_WAVE), __shfl_xor(best, d, TPC_WAVE));
+        }
+        if (i < T && sub == 0) {
             A.leg[i] = best;
             A.leg_chi2[i] = best >= 0 ? (float)bchi : 0.f;
         }
@@ -507,11 +564,15 @@ hipError_t launch_merge(const tpc_context *ctx, const tpc_seeds *sd, const tpc_t
     A.leg_chi2 = leg_chi2;
     int g = (sd->cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
-    hipLaunchKernelGGL(mg_best, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+    int gm = (int)(((int64_t)sd->cap_seeds * MG_SPLIT + TPC_BLOCK - 1) / TPC_BLOCK);
+    gm = gm < 1 ? 1 : (gm > 8192 ? 8192 : gm);
+    hipLaunchKernelGGL(mg_best, dim3(gm), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(mg_link_next, dim3(g), dim3(TPC_BLOCK), 0, st, A);
     hipLaunchKernelGGL(mg_link_prev, dim3(g), dim3(TPC_BLOCK), 0, st, A);
     if (leg) {
-        hipLaunchKernelGGL(lg_best, dim3(g), dim3(TPC_BLOCK), 0, st, A);
+        int gl = (int)(((int64_t)sd->cap_seeds * LG_SPLIT + TPC_BLOCK - 1) / TPC_BLOCK);
+        gl = gl < 1 ? 1 : (gl > 8192 ? 8192 : gl);
+        hipLaunchKernelGGL(lg_best, dim3(gl), dim3(TPC_BLOCK), 0, st, A);
         hipLaunchKernelGGL(lg_link, dim3(g), dim3(TPC_BLOCK), 0, st, A);
     }
     return hipGetLastError();
