@@ -160,6 +160,65 @@ def cpu_baseline(fr, host, budget_s):
     return base, check
 
 
+def batched_cpu_check(fr, out, frames=(0, 40)):
+    """The oracle on sector CPU_SECTOR of a few frames of the batched input
+    against a batched run's results for them (frames and sectors are
+    independent units).  `out` = (up, dn, seeds, tracks) on the device."""
+    from tests import parity
+    up, dn, seeds, tracks = out
+    T = int(seeds.n_seeds.item())
+    sd = seeds.to_numpy()
+    tr = {k: getattr(tracks, k)[:T].cpu().numpy() for k in ("x", "par", "cov", "chi2", "ndf", "status")}
+    hu, hd = up.cpu().numpy(), dn.cpu().numpy()
+    check = {"sector": CPU_SECTOR, "frames": list(frames)}
+    try:
+        st = [parity.check_sector(fr, CPU_SECTOR, hu, hd, sd, tr, NB, MIN_HITS, FIT, f) for f in frames]
+        check["clusters"] = int(sum(x["clusters"] for x in st))
+        check["worst_par"] = max(x["fit"]["worst_par"] for x in st)
+        check["ok"] = True
+    except AssertionError as e:
+        check["ok"] = False
+        check["error"] = str(e)[:300]
+    return check
+
+
+def adjoint_cpu_check(fr, seeds, grad, n_entries=16):
+    """The adjoint at map 0 against central finite differences of the oracle
+    on sector CPU_SECTOR of the frame (its map entries depend on that sector's
+    seeds only), on the oracle's own seeds for it, which must equal the
+    GPU's."""
+    import oracle
+    sd = seeds.to_numpy()
+    sv = fr.sector_view(0, CPU_SECTOR)
+    check = {"sector": CPU_SECTOR, "clusters": sv.n_clusters}
+    try:
+        ru, rd = oracle.neighbours(sv.row_offsets, sv.y, sv.z, sv.n_rows, **NB)
+        rs = oracle.ca_seed(sv.row_offsets, ru, rd, 1, sv.n_rows, MIN_HITS)
+        a, b = fr.first_id(0, CPU_SECTOR), fr.first_id(0, CPU_SECTOR) + sv.n_clusters
+        o, h = np.asarray(sd["offsets"]), np.asarray(sd["hits"])
+        first = h[o[:-1]]
+        i0, i1 = np.searchsorted(first, a), np.searchsorted(first, b)
+        np.testing.assert_array_equal(o[i0:i1 + 1] - o[i0], rs["offsets"])
+        np.testing.assert_array_equal(h[o[i0]:o[i1]] - a, rs["hits"])
+        g = grad[CPU_SECTOR]
+        cov = np.argwhere(np.abs(g).sum(axis=1) > 0)[:, 0]
+        rng = np.random.default_rng(7)
+        rows = rng.choice(cov, size=min(n_entries // 2, cov.size), replace=False)
+        entries = [(0, int(r), ax) for r in rows for ax in (0, 1)]
+        fd = oracle.fd_map_gradient(rs, sv.y, sv.z, sv.row_x, sv.n_rows, np.zeros((1, sv.n_rows, 2)), entries,
+                                    h=1e-3, **FIT)
+        gg = np.array([g[r, ax] for _, r, ax in entries], dtype=np.float64)
+        err = float(np.linalg.norm(gg - fd) / np.linalg.norm(fd))
+        floor = 1e-3 * np.abs(fd).max()
+        worst = float(np.max(np.abs(gg - fd) / np.maximum(np.abs(fd), floor)))
+        check.update(entries=len(entries), rel_l2=err, worst_entry=worst, seeds_identical=True)
+        check["ok"] = err <= 1e-3 and worst <= 1e-3
+    except AssertionError as e:
+        check["ok"] = False
+        check["error"] = str(e)[:300]
+    return check
+
+
 # HBM traffic per launch from the committed counter profiles; used only
 # while the kernel sources are those the counters were taken on.
 FIT_SOURCES = ("tpc_fit.hip", "tpc_fit_common.hpp", "tpc_fit_math.hpp", "tpc_internal.hpp")
@@ -356,7 +415,12 @@ def leg_batched(args):
     gs = ReconstructGraph(reco, dfr, "staged")
     ms_staged_batched = timed(gs.replay, steps, 2)
     N = dfr.n_clusters
+    checks = {}
+    if not args.no_cpu:
+        checks = {"persistent": batched_cpu_check(fr, g.replay()), "staged": batched_cpu_check(fr, gs.replay())}
+    ok = all(c["ok"] for c in checks.values())
     return {"workload": fr.meta["name"], "frames": fr.n_frames, "clusters": N,
+            "parity": checks if checks else {"ok": None, "note": "not checked (--no-cpu)"},
             "plain_per_frame": {"ms": round(ms_plain, 4), "M_clusters_per_s": round(N / ms_plain / 1e3, 3)},
             "batched_persistent_graph": {"ms": round(ms_persist, 4),
                                          "M_clusters_per_s": round(N / ms_persist / 1e3, 3),
@@ -364,8 +428,8 @@ def leg_batched(args):
             "batched_staged_graph": {"ms": round(ms_staged_batched, 4),
                                      "M_clusters_per_s": round(N / ms_staged_batched / 1e3, 3)},
             "autotune_choice": {"mode": best["mode"], "tune": best["tune"]},
-            "speedup_persistent_vs_plain": round(ms_plain / ms_persist, 3),
-            "speedup_batched_vs_plain": round(ms_plain / min(ms_persist, ms_staged_batched), 3)}
+            "speedup_persistent_vs_plain": round(ms_plain / ms_persist, 3) if ok else None,
+            "speedup_batched_vs_plain": round(ms_plain / min(ms_persist, ms_staged_batched), 3) if ok else None}
 
 
 def leg_adjoint(args):
@@ -389,9 +453,14 @@ def leg_adjoint(args):
         loss.backward()
     steps = max(3, args.steps // 5)
     ms = timed(step, steps, 2)
-    return {"workload": fr.meta["name"], "clusters": dfr.n_clusters, "seeds": T, "seed_hits": H,
-            "ms_per_gradient": round(ms, 4), "grads_per_s": round(1e3 / ms, 3),
-            "tracks_per_s": round(T / ms * 1e3, 1), "ckpt_rows": reco.cfg.ckpt_rows}
+    res = {"workload": fr.meta["name"], "clusters": dfr.n_clusters, "seeds": T, "seed_hits": H,
+           "ms_per_gradient": round(ms, 4), "grads_per_s": round(1e3 / ms, 3),
+           "tracks_per_s": round(T / ms * 1e3, 1), "ckpt_rows": reco.cfg.ckpt_rows}
+    if not args.no_cpu:
+        res["parity"] = adjoint_cpu_check(fr, seeds, m.grad.cpu().numpy())
+        if not res["parity"]["ok"]:
+            res["grads_per_s"] = None            # no number for a run that fails parity
+    return res
 
 
 def leg_follow(args, with_cpu=True):

@@ -190,7 +190,7 @@ def lib():
         L.oracle_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
         L.oracle_propagate.restype = i32
         L.oracle_fit.argtypes = [i32, P, P, P, P, P, P, P, i32, P, ctypes.POINTER(FitParams),
-                                 P, P, P, P, P, P]
+                                 P, P, P, P, P, P, P]
         L.oracle_fit.restype = None
         L.oracle_follow.argtypes = [i32, P, P, P, P, P, P, i32, i32, i32, P, P, P,
                                     ctypes.POINTER(FitParams), ctypes.POINTER(FollowParams),
@@ -325,6 +325,11 @@ def fit(seeds: dict, y, z, row_x, n_rows, *, bz, sigma_y, sigma_z, max_sin, var_
         var_tgl0, var_qpt0, map_: Optional[np.ndarray] = None):
     """Double-precision Kalman fit of every seed.
 
+    Besides the fit, ``sin_margin`` reports each fit's closest approach to
+    its direction thresholds: min(max_sin - |sin phi|, cos phi) at the start,
+    then max_sin - max(|s|, |s'|) over the helix steps taken (negative at a
+    step that failed; -inf for degenerate start points).
+
     ``y``, ``z`` are promoted to float64 (pass float64 truth to avoid the
     float32 rounding of stored clusters).  ``map_`` is [S, R, 2] (dy, dz)
     subtracted from the clusters of each (sector, row).
@@ -340,11 +345,11 @@ def fit(seeds: dict, y, z, row_x, n_rows, *, bz, sigma_y, sigma_z, max_sin, var_
     prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
     mp = None if map_ is None else np.ascontiguousarray(map_, dtype=np.float64)
     out = dict(x=np.empty(T), par=np.empty((T, 5)), cov=np.empty((T, 15)), chi2=np.empty(T),
-               ndf=np.empty(T, np.int32), status=np.empty(T, np.int32))
+               ndf=np.empty(T, np.int32), status=np.empty(T, np.int32), sin_margin=np.empty(T))
     lib().oracle_fit(T, _p(offsets), _p(hits), _p(sec), _p(fr), _p(y), _p(z), _p(rx), n_rows,
                      None if mp is None else _p(mp), ctypes.byref(prm), _p(out["x"]),
                      _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndf"]),
-                     _p(out["status"]))
+                     _p(out["status"]), _p(out["sin_margin"]))
     return out
 
 

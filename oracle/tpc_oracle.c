@@ -447,9 +447,11 @@ static int32_t update(double *p, double *C, double my, double mz, double vy, dou
 
 /* Exact circle through hits n-1 (outermost), (n-1)/2 and 0: the state at
  * x of hit n-1 and the start covariance; returns 0 or 1 (degenerate points,
- * or a direction at the start not towards +x or with |sin phi| >= max_sin). */
-static int32_t start_points(int32_t n, const double *xs, const double *ys, const double *zs,
-                            const oracle_fit_params *prm, double *p, double *C)
+ * or a direction at the start not towards +x or with |sin phi| >= max_sin).
+ * With smargin non-null also the distance of the start direction from those
+ * two thresholds, min(max_sin - |sin phi|, cos phi) (-inf if degenerate). */
+static int32_t start_points_m(int32_t n, const double *xs, const double *ys, const double *zs,
+                              const oracle_fit_params *prm, double *p, double *C, double *smargin)
 {
     int a = n - 1, b = (n - 1) / 2, c = 0;
     double bcx = xs[b] - xs[c], bcy = ys[b] - ys[c];
@@ -471,6 +473,10 @@ static int32_t start_points(int32_t n, const double *xs, const double *ys, const
     p[3] = (zs[a] - zs[c]) / (lac * g_of(uc));
     p[4] = -kap0 / (C_LIGHT * prm->bz);
     if (!st && (!(cos(phiA) > 0.0) || !(fabs(p[2]) < prm->max_sin))) st = 1;
+    if (smargin) {
+        double m1 = prm->max_sin - fabs(p[2]), m2 = cos(phiA);
+        *smargin = (!(prod > 0.0) || !(fabs(ua) < 1.0) || !(fabs(uc) < 1.0)) ? -INFINITY : (m1 < m2 ? m1 : m2);
+    }
     for (int i = 0; i < 25; ++i) C[i] = 0.0;
     C[0] = prm->sigma_y * prm->sigma_y;
     C[6] = prm->sigma_z * prm->sigma_z;
@@ -480,29 +486,52 @@ static int32_t start_points(int32_t n, const double *xs, const double *ys, const
     return st;
 }
 
+static int32_t start_points(int32_t n, const double *xs, const double *ys, const double *zs,
+                            const oracle_fit_params *prm, double *p, double *C)
+{
+    return start_points_m(n, xs, ys, zs, prm, p, C, NULL);
+}
+
 /* Inward fit of n points at planes xs (ascending), as described above: state
- * p and full covariance C at xs[0] (or where the filter stopped), chi2, status. */
-static int32_t fit_points(int32_t n, const double *xs, const double *ys, const double *zs,
-                          const oracle_fit_params *prm, double *xo, double *p, double *C, double *chi2o)
+ * p and full covariance C at xs[0] (or where the filter stopped), chi2, status.
+ * With margin non-null also the fit's closest approach to its direction
+ * thresholds: the start's (start_points_m), then max_sin - max(|s|, |s'|)
+ * of every helix step taken (negative at a step that failed); only a report,
+ * the fit is the same. */
+static int32_t fit_points_m(int32_t n, const double *xs, const double *ys, const double *zs,
+                            const oracle_fit_params *prm, double *xo, double *p, double *C, double *chi2o,
+                            double *margin)
 {
     *chi2o = 0.0;
     *xo = 0.0;
     for (int i = 0; i < 5; ++i) p[i] = 0.0;
     for (int i = 0; i < 25; ++i) C[i] = 0.0;
+    if (margin) *margin = -INFINITY;
     if (n < 3) return 1;
-    int32_t st = start_points(n, xs, ys, zs, prm, p, C);
+    double mg = 0.0;
+    int32_t st = start_points_m(n, xs, ys, zs, prm, p, C, &mg);
     int a = n - 1;
     double vy = prm->sigma_y * prm->sigma_y, vz = prm->sigma_z * prm->sigma_z;
     double chi2 = 0.0;
     double xcur = xs[a];
     for (int k = n - 2; k >= 0 && !st; --k) {
+        double s1 = p[2], s2 = s1 - C_LIGHT * prm->bz * p[4] * (xs[k] - xs[k + 1]);
+        double ms = prm->max_sin - (fabs(s1) > fabs(s2) ? fabs(s1) : fabs(s2));
+        if (ms < mg) mg = ms;
         if (predict(p, C, xs[k] - xs[k + 1], prm)) { st = 2; break; }
         xcur = xs[k];
         if (update(p, C, ys[k], zs[k], vy, vz, &chi2)) { st = 3; break; }
     }
     *xo = xcur;
     *chi2o = chi2;
+    if (margin) *margin = mg;
     return st;
+}
+
+static int32_t fit_points(int32_t n, const double *xs, const double *ys, const double *zs,
+                          const oracle_fit_params *prm, double *xo, double *p, double *C, double *chi2o)
+{
+    return fit_points_m(n, xs, ys, zs, prm, xo, p, C, chi2o, NULL);
 }
 
 static void pack_cov(const double *C, double *co)
@@ -516,9 +545,11 @@ static void pack_cov(const double *C, double *co)
 static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
                     const double *y, const double *z, const double *row_x, int32_t n_rows,
                     const double *map, const oracle_fit_params *prm,
-                    double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto)
+                    double *xo, double *po, double *co, double *chi2o, int32_t *ndfo, int32_t *sto,
+                    double *margin)
 {
     double xs[512], ys[512], zs[512], C[25];
+    if (margin) *margin = -INFINITY;
     *ndfo = 2 * n - 5;
     if (n < 3 || n > 512) {
         *chi2o = 0.0;
@@ -538,7 +569,7 @@ static void fit_one(int32_t n, const int32_t *hit, int32_t sec, int32_t row0,
             zs[k] -= map[((size_t)sec * n_rows + r) * 2 + 1];
         }
     }
-    *sto = fit_points(n, xs, ys, zs, prm, xo, po, C, chi2o);
+    *sto = fit_points_m(n, xs, ys, zs, prm, xo, po, C, chi2o, margin);
     pack_cov(C, co);
 }
 
@@ -546,13 +577,14 @@ void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                 const int32_t *sector, const int32_t *first_row,
                 const double *y, const double *z, const double *row_x, int32_t n_rows,
                 const double *map, const oracle_fit_params *prm,
-                double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status)
+                double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
+                double *margin)
 {
     #pragma omp parallel for schedule(dynamic, 64)
     for (int32_t i = 0; i < n_tracks; ++i) {
         fit_one(offsets[i + 1] - offsets[i], hits + offsets[i], sector[i], first_row[i],
                 y, z, row_x, n_rows, map, prm, &x_out[i], &par[(size_t)i * 5],
-                &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i]);
+                &cov[(size_t)i * 15], &chi2[i], &ndf[i], &status[i], margin ? &margin[i] : NULL);
     }
 }
 

@@ -55,7 +55,8 @@ void oracle_fit(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                 const int32_t *sector, const int32_t *first_row,
                 const double *y, const double *z, const double *row_x, int32_t n_rows,
                 const double *map, const oracle_fit_params *prm,
-                double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status);
+                double *x_out, double *par, double *cov, double *chi2, int32_t *ndf, int32_t *status,
+                double *margin);
 
 void oracle_follow(int32_t n_tracks, const int32_t *offsets, const int32_t *hits,
                    const int32_t *frame, const int32_t *sector, const int32_t *first_row,

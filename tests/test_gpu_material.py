@@ -108,9 +108,19 @@ def test_headline_frame_with_energy_loss(torch_dev):
 
 
 def test_energy_loss_past_the_cap(torch_dev):
-    # a gas 600 times denser than argon: about half of the segments would change
-    # the momentum by more than 1 % and are taken without energy loss
+    # protons simulated in the dense argon, fitted with a gas 600 times denser
+    # than argon (1 g/cm^3): about a fifth of the fit's steps (0.19 measured
+    # on the generator's truth) would change the momentum by more than 1 % and
+    # are taken without energy loss, the rest with it, so both branches of the
+    # energy-loss map are compared
     heavy = (1.0, ARGON_GAS[1], ARGON_GAS[2])
     fr = make_scattering_frame(n_tracks=400, seed=23, x0_cm=391.0, mass=PROTON_MASS, inv_pt=(0.7, 3.0),
                                gas=DENSE_GAS)
-    check(fr, 391.0, 30.0, "protons, gas past the 1% cap", mass=PROTON_MASS, gas=heavy)
+    st, r = check(fr, 391.0, 30.0, "protons, gas past the 1% cap", mass=PROTON_MASS, gas=heavy)
+    rs = oracle.ca_seed(fr.row_offsets, *oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB),
+                        fr.n_sectors, fr.n_rows, MIN_HITS)
+    frac = parity.capped_fraction(fr, rs, PROTON_MASS, _f32(heavy))
+    print("[material] steps past the cap: %.3f" % frac, flush=True)
+    assert 0.1 <= frac <= 0.9, frac
+    # in the simulation's own gas no step reaches the cap
+    assert parity.capped_fraction(fr, rs, PROTON_MASS, _f32(DENSE_GAS)) < 0.01

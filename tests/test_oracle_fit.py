@@ -188,3 +188,32 @@ def test_fd_gradient_matches_independent_autograd():
     np.testing.assert_allclose(fd, ag, rtol=1e-6, atol=1e-6 * scale)
     # entries no seed covers have zero gradient
     assert np.all(g[np.abs(g).sum(axis=2) == 0] == 0)
+
+
+def test_direction_margin_is_the_distance_to_the_threshold():
+    """The oracle's sin_margin report: a track that passed its fit with the
+    smallest margins fails when max_sin drops by a little more than the
+    margin and passes when it drops by a little less; failed steps report a
+    negative margin."""
+    fr = make_frames(n_sectors=1, tracks_per_frame=(3000,), seed=31, smear=True, keep_truth=True,
+                     phi_range=(-math.radians(40), math.radians(40)), looper_frac=0.3)
+    sd = truth_runs(fr, 10)
+    prm = dict(FIT, max_sin=0.8)
+    r = oracle.fit(sd, fr.y, fr.z, fr.row_x, fr.n_rows, **prm)
+    ok = r["status"] == 0
+    assert np.all(r["sin_margin"][ok] > 0)
+    assert np.all(r["sin_margin"][r["status"] == 2] <= 0)
+    assert (r["status"] == 2).sum() > 5
+    # the closest passes whose binding threshold is max_sin (not cos phi at the start)
+    cand = np.nonzero(ok & (r["sin_margin"] < 0.05))[0]
+    assert cand.size >= 10
+    checked = 0
+    for i in cand[np.argsort(r["sin_margin"][cand])][:20]:
+        one = oracle.subset_seeds(sd, np.array([i]))
+        m = r["sin_margin"][i]
+        lo = oracle.fit(one, fr.y, fr.z, fr.row_x, fr.n_rows, **dict(prm, max_sin=prm["max_sin"] - m * (1 + 1e-6)))
+        hi = oracle.fit(one, fr.y, fr.z, fr.row_x, fr.n_rows, **dict(prm, max_sin=prm["max_sin"] - m * (1 - 1e-6)))
+        if hi["status"][0] == 0:
+            assert lo["status"][0] != 0
+            checked += 1
+    assert checked >= 10
