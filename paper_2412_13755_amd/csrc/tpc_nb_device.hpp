@@ -672,6 +672,12 @@ __device__ inline void box_scan(float yh, float zh, float ay, float az, uint32_t
     }
 }
 
+// The square root of the box set-up is the hardware estimate (a few ulp at
+// most; a denormal q* may give 0, which only shrinks the box to its
+// rounding margin, still far above sqrt(q*)): the 1e-4 widening covers it,
+// and the correctly rounded sequence cost 6 % of the dense search.
+#define TPC_NB_SQRT(v) __builtin_amdgcn_sqrtf(v)
+
 #if TPC_NB_DYN
 // Flat form: the nested walks of one cluster (up-row window cells, their
 // candidates, and for each up cluster in the window the down-row box cells
@@ -773,7 +779,7 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
                 // down clusters around the prediction c = h - (u - h)
                 ur = rr;
                 const float py = yh - ay, pz = zh - az;
-                const float r = sqrtf(qb) * 1.0001f;   // +inf until a triplet passes
+                const float r = TPC_NB_SQRT(qb) * 1.0001f;   // +inf until a triplet passes
                 const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
                 yd = cell_coord(py - ky, gd.y0, gd.iwy, gd.ny);
                 yd1 = cell_coord(py + ky, gd.y0, gd.iwy, gd.ny);
