@@ -93,6 +93,30 @@ __device__ inline void row_extent(const float *__restrict__ y, const float *__re
     ext[0] = ymin; ext[1] = ymax; ext[2] = zmin; ext[3] = zmax;
 }
 
+// Finite z extent of clusters [a, b) (whole workgroup; contains barriers).
+__device__ inline void row_zextent(const float *__restrict__ z, int a, int b, float (*red)[TPC_BLOCK / TPC_WAVE],
+                                   float &zlo, float &zhi) {
+    float zmin = INFINITY, zmax = -INFINITY;
+    for (int i = a + (int)threadIdx.x; i < b; i += TPC_BLOCK) {
+        const float zv = z[i];
+        if (isfinite(zv)) { zmin = fminf(zmin, zv); zmax = fmaxf(zmax, zv); }
+    }
+    zmin = wave_min(zmin);
+    zmax = wave_max(zmax);
+    const int wid = threadIdx.x / TPC_WAVE, lane = threadIdx.x & (TPC_WAVE - 1);
+    __syncthreads();
+    if (lane == 0) { red[0][wid] = zmin; red[1][wid] = zmax; }
+    __syncthreads();
+    zmin = red[0][0];
+    zmax = red[1][0];
+    for (int w = 1; w < TPC_BLOCK / TPC_WAVE; ++w) {
+        zmin = fminf(zmin, red[0][w]);
+        zmax = fmaxf(zmax, red[1][w]);
+    }
+    zlo = zmin;
+    zhi = zmax;
+}
+
 // Counting sort of clusters [a, b) by cell of grid g (whole workgroup;
 // contains barriers).  Writes y, z, global id in cell order to
 // dy/dz/did[obase + k] and cell starts cs[c] = obase + first position of
@@ -168,7 +192,8 @@ __device__ inline SegGrid zrow_grid(float zmin, float zmax, int n, int cap) {
 // row_sort, but the scatter writes 16-bit local indices into LDS and the
 // sorted copy is then written in position order (coalesced stores, reads
 // gathered from the row), so no partially written cache lines go to HBM.
-// n = b - a <= TPC_BIN_PERM.
+// n = b - a <= TPC_BIN_PERM.  g has one cell column (a zrow_grid, ny = 1),
+// so the cell is z's alone and y is read only by the final gather.
 #define TPC_BIN_PERM 24576
 __device__ inline void row_sort_perm(const float *__restrict__ y, const float *__restrict__ z, int a, int b,
                                      const SegGrid &g, int *cnt, int *scan_sh, uint16_t *perm,
@@ -179,8 +204,7 @@ __device__ inline void row_sort_perm(const float *__restrict__ y, const float *_
     const int cells = g.ny * g.nz;
     for (int c = tid; c < cells; c += TPC_BLOCK) cnt[c] = 0;
     __syncthreads();
-    for (int i = a + tid; i < b; i += TPC_BLOCK)
-        atomicAdd(&cnt[cell_coord(y[i], g.y0, g.iwy, g.ny) * g.nz + cell_coord(z[i], g.z0, g.iwz, g.nz)], 1);
+    for (int i = a + tid; i < b; i += TPC_BLOCK) atomicAdd(&cnt[cell_coord(z[i], g.z0, g.iwz, g.nz)], 1);
     __syncthreads();
     const int per = (cells + TPC_BLOCK - 1) / TPC_BLOCK;
     const int c0 = tid * per;
@@ -199,7 +223,7 @@ __device__ inline void row_sort_perm(const float *__restrict__ y, const float *_
     if (tid == 0) cs[cells] = obase + (b - a);
     __syncthreads();
     for (int i = a + tid; i < b; i += TPC_BLOCK) {
-        const int c = cell_coord(y[i], g.y0, g.iwy, g.ny) * g.nz + cell_coord(z[i], g.z0, g.iwz, g.nz);
+        const int c = cell_coord(z[i], g.z0, g.iwz, g.nz);
         perm[atomicAdd(&cnt[c], 1)] = (uint16_t)(i - a);
     }
     __syncthreads();
@@ -255,9 +279,9 @@ __device__ inline void nb_bin_seg(int seg, int n_rows, const int32_t *__restrict
         }
         return;
     }
-    float ext[4];
-    row_extent(y, z, a, b, red, ext);
-    const SegGrid g = zrow_grid(ext[2], ext[3], n, TPC_CELL_CAP);
+    float zlo, zhi;
+    row_zextent(z, a, b, red, zlo, zhi);
+    const SegGrid g = zrow_grid(zlo, zhi, n, TPC_CELL_CAP);
     if (threadIdx.x == 0) grid[seg] = g;
     if constexpr (sizeof(LDS) >= sizeof(BinLdsPerm)) {
         if (n <= TPC_BIN_PERM) {
