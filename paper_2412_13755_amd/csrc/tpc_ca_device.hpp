@@ -45,11 +45,14 @@ __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
 // path of such links, one row per link.  Rows are grouped in blocks of
 // TPC_CA_ROWS per (frame, sector); pack[h] holds the lowest member of h's
 // chain inside h's block (bits 0-31, global id), how many links down it is
-// (bits 32-59) and whether h keeps a link up (bit 62) / down (bit 63).
+// (bits 32-59), whether that member is the chain's bottom (it keeps no link
+// down, bit 61; set by the LDS rankings, so that ca_tops need not look) and
+// whether h keeps a link up (bit 62) / down (bit 63).
 
 #define TPC_CA_ROWS 16          // rows per ranking block
 #define TPC_CA_CAP 8192         // clusters per block ranked in LDS
 #define TPC_CA_ROUNDS 5         // > log2(TPC_CA_ROWS): links inside a block
+#define TPC_CA_BOT (1ull << 61)
 #define TPC_CA_UP (1ull << 62)
 #define TPC_CA_DN (1ull << 63)
 // LDS word: local node (bits 0-19), distance (20-29), up (30), down (31)
@@ -144,7 +147,9 @@ __device__ inline void ca_block_item(int item, int32_t N, int32_t n_rows, const 
         }
         for (int k = tid; k < n; k += T) {
             const uint32_t v = W[k];
-            ws.pack[lo + k] = ((unsigned long long)(v >> 30) << 62) |
+            // the lowest member keeps no link down: it is the chain's bottom
+            const bool bot = !(W[v & TPC_CA_NODE] & 0x80000000u);
+            ws.pack[lo + k] = ((unsigned long long)(v >> 30) << 62) | (bot ? TPC_CA_BOT : 0ull) |
                               ((unsigned long long)((v >> 20) & 0x3FFu) << 32) |
                               (uint32_t)(lo + (int32_t)(v & TPC_CA_NODE));
         }
@@ -193,7 +198,8 @@ __device__ inline int ca_block_class(int item, int32_t n_rows, const int32_t *__
 // Step 1 for a block of class 1: the same outputs as ca_block_item, by a
 // sweep over the block's rows from the bottom up that keeps the previous
 // row in LDS: its up partners (pu) and its words (pw: member - lo in bits
-// 0-23, distance in 24-28, keeps a link up in bit 30, down in bit 31).  For
+// 0-23, distance in 24-28, the member is the chain's bottom in bit 29, keeps
+// a link up in bit 30, down in bit 31).  For
 // a cluster h of row r with partner d = dn[h] in row r - 1 the link is kept
 // if pu says d's up partner is h; then d keeps its link up (its bit 30 is
 // set from here), and, inside the block, h's lowest member and distance are
@@ -206,6 +212,7 @@ __device__ inline int ca_block_class(int item, int32_t n_rows, const int32_t *__
 // P: 2 x TPC_CA_SWEEP_ROW words.  Contains barriers: call from the whole
 // workgroup of TPC_CA_SWEEP_T threads.
 #define TPC_CA_SWEEP_T 1024
+#define TPC_CA_W_BOT 0x20000000u
 #define TPC_CA_W_UP 0x40000000u
 #define TPC_CA_W_DN 0x80000000u
 __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const int32_t *__restrict__ off,
@@ -246,13 +253,14 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
             const bool hd = dprev ? pu[d - pa] == (uint32_t)h : (valid_id(d, N) && up[d] == h);
             // a partner up in the row above sets this bit when that row is swept
             const bool hu = (u >= na && u < nb) ? false : (valid_id(u, N) && dn[u] == h);
-            uint32_t low = (uint32_t)(h - lo), dist = 0;
+            uint32_t low = (uint32_t)(h - lo), dist = 0, bot = hd ? 0u : TPC_CA_W_BOT;
             if (hd && dprev && r > r0) {
                 const uint32_t w = atomicOr(&pw[d - pa], TPC_CA_W_UP);
                 low = w & 0xFFFFFFu;
                 dist = ((w >> 24) & 0x1Fu) + 1;
+                bot = w & TPC_CA_W_BOT;
             }
-            ww[j] = (hd ? TPC_CA_W_DN : 0u) | (hu ? TPC_CA_W_UP : 0u) | (dist << 24) | low;
+            ww[j] = (hd ? TPC_CA_W_DN : 0u) | (hu ? TPC_CA_W_UP : 0u) | bot | (dist << 24) | low;
             ws.claim[h] = ~0ull;
             ws.core[h] = 0;
             ws.memb[h] = -1;                          // set by ca_tops for chain members
@@ -262,7 +270,7 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
         if (r > r0) {                                 // the row below is complete: its words to pack
             for (int k = tid; k < pb - pa; k += TPC_CA_SWEEP_T) {
                 const uint32_t w = pw[k];
-                ws.pack[pa + k] = ((unsigned long long)(w >> 30) << 62) |
+                ws.pack[pa + k] = ((unsigned long long)(w >> 30) << 62) | ((w & TPC_CA_W_BOT) ? TPC_CA_BOT : 0ull) |
                                   ((unsigned long long)((w >> 24) & 0x1Fu) << 32) |
                                   (uint32_t)(lo + (int32_t)(w & 0xFFFFFFu));
             }
@@ -291,7 +299,7 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
     }
     for (int k = tid; k < pb - pa; k += TPC_CA_SWEEP_T) {
         const uint32_t w = pw[k];
-        ws.pack[pa + k] = ((unsigned long long)(w >> 30) << 62) |
+        ws.pack[pa + k] = ((unsigned long long)(w >> 30) << 62) | ((w & TPC_CA_W_BOT) ? TPC_CA_BOT : 0ull) |
                           ((unsigned long long)((w >> 24) & 0x1Fu) << 32) |
                           (uint32_t)(lo + (int32_t)(w & 0xFFFFFFu));
     }
@@ -311,7 +319,7 @@ __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restri
         if (!pack_linked(w0)) return;
         int32_t bot = pack_node(w0);
         int32_t pos = pack_dist(w0);
-        for (int it = 0; it < n_rows; ++it) {         // bound: one hop per block
+        for (int it = 0; it < n_rows && !(w0 & TPC_CA_BOT); ++it) {   // bound: one hop per block
             const int32_t e = valid_id(bot, N) ? ws.dlk[bot] : -1;
             if (e < 0) break;
             const unsigned long long w = ws.pack[e];
