@@ -34,8 +34,9 @@ fit_tracks(FitArgs A) {
     fit_all(A);
 }
 
-// The fit after the persistent kernel (longest first with sort_fit): the
-// same code under its own name, so profiles tell the two launches apart.
+// The fit in length order (the staged fit of many seeds, or after the
+// persistent kernel with sort_fit): the same code under its own name, so
+// profiles tell the launches apart.
 __global__ void __launch_bounds__(TPC_BLOCK)
 fit_tracks_ordered(FitArgs A) {
     fit_all(A);
@@ -87,7 +88,88 @@ chi2_final(const double *__restrict__ part, int32_t nparts, float *__restrict__ 
     if (threadIdx.x == 0) *loss = (float)sh[0];
 }
 
+// Seeds in descending length order (the order within a length is
+// immaterial: every seed's fit is its own), so that the lanes of a
+// wavefront filter about as many hits each.  Counted per workgroup in LDS
+// and added to the global histogram bin by bin; the workgroup then reserves
+// one range per length and places its seeds there.
+__device__ inline int len_bin(const int32_t *offsets, int i) {
+    const int n = offsets[i + 1] - offsets[i];
+    return n < TPC_MAX_ROWS ? (n > 0 ? n : 0) : TPC_MAX_ROWS;
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fit_order_count(const int32_t *__restrict__ n_seeds, int32_t cap, const int32_t *__restrict__ offsets,
+                int32_t *__restrict__ hist, int32_t *__restrict__ cur) {
+    __shared__ int lh[TPC_MAX_ROWS + 1];
+    for (int b = threadIdx.x; b <= TPC_MAX_ROWS; b += TPC_BLOCK) lh[b] = 0;
+    __syncthreads();
+    const int T = *n_seeds < cap ? *n_seeds : cap;
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK)
+        atomicAdd(&lh[len_bin(offsets, i)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b <= TPC_MAX_ROWS; b += TPC_BLOCK)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+__global__ void fit_order_clear(int32_t *__restrict__ hist, int32_t *__restrict__ cur) {
+    for (int b = threadIdx.x; b <= TPC_MAX_ROWS; b += blockDim.x) {
+        hist[b] = 0;
+        cur[b] = 0;
+    }
+}
+
+// Bin starts in descending length order, and the number of seeds.
+__global__ void fit_order_starts(int32_t *__restrict__ hist, int32_t *__restrict__ n_order) {
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int len = TPC_MAX_ROWS; len >= 0; --len) {
+            const int c = hist[len];
+            hist[len] = run;
+            run += c;
+        }
+        *n_order = run;
+    }
+}
+
+__global__ void __launch_bounds__(TPC_BLOCK)
+fit_order_place(const int32_t *__restrict__ n_seeds, int32_t cap, const int32_t *__restrict__ offsets,
+                const int32_t *__restrict__ start, int32_t *__restrict__ cur, int32_t *__restrict__ order) {
+    __shared__ int lh[TPC_MAX_ROWS + 1], lb[TPC_MAX_ROWS + 1];
+    for (int b = threadIdx.x; b <= TPC_MAX_ROWS; b += TPC_BLOCK) lh[b] = 0;
+    __syncthreads();
+    const int T = *n_seeds < cap ? *n_seeds : cap;
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK)
+        atomicAdd(&lh[len_bin(offsets, i)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b <= TPC_MAX_ROWS; b += TPC_BLOCK) {
+        const int c = lh[b];
+        lb[b] = c ? start[b] + atomicAdd(&cur[b], c) : 0;
+        lh[b] = 0;
+    }
+    __syncthreads();
+    for (int i = blockIdx.x * TPC_BLOCK + threadIdx.x; i < T; i += gridDim.x * TPC_BLOCK) {
+        const int b = len_bin(offsets, i);
+        const int slot = lb[b] + atomicAdd(&lh[b], 1);
+        if (slot < T) order[slot] = i;
+    }
+}
+
 }  // namespace
+
+// The length order of the seeds into ord (workspace); sets A.order.
+static void launch_fit_order(FitArgs &A, const FitOrderWs &ord, hipStream_t st) {
+    int blocks = (A.cap_seeds + TPC_BLOCK - 1) / TPC_BLOCK;
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    hipLaunchKernelGGL(fit_order_clear, dim3(1), dim3(TPC_BLOCK), 0, st, ord.hist, ord.cur);
+    hipLaunchKernelGGL(fit_order_count, dim3(blocks), dim3(TPC_BLOCK), 0, st, A.n_seeds, A.cap_seeds, A.offsets,
+                       ord.hist, ord.cur);
+    hipLaunchKernelGGL(fit_order_starts, dim3(1), dim3(64), 0, st, ord.hist, ord.n);
+    hipLaunchKernelGGL(fit_order_place, dim3(blocks), dim3(TPC_BLOCK), 0, st, A.n_seeds, A.cap_seeds, A.offsets,
+                       ord.hist, ord.cur, ord.order);
+    A.order = ord.order;
+    A.n_order = ord.n;
+}
 
 FitArgs make_fit_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
                       const float *map) {
@@ -137,27 +219,29 @@ hipError_t launch_fit(const tpc_context *ctx, const tpc_frames *fr, const tpc_se
     FitArgs A = make_fit_args(ctx, fr, sd, map);
     A.out = *tr;
     A.ckpt = ckpt;
+    float2 *hyz;
+    FitOrderWs ord;
+    fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz, &ord);
     if (sd->hit_yz) {
         A.hyz = reinterpret_cast<const float2 *>(sd->hit_yz);
     } else {
-        float2 *hyz;
-        fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz);
         A.hyz = hyz;
         launch_gather(fr, sd, hyz, st);
     }
-    return launch_fit_args(A, st, false, 0, 0);
+    if (sd->cap_seeds >= TPC_FIT_ORDER_MIN) launch_fit_order(A, ord, st);
+    return launch_fit_args(A, st, A.order != nullptr, 0, 0);
 }
 
 // Launch shape of the fit: workgroups of `block` threads (0: TPC_BLOCK) and
 // about `spt` seeds per thread (0: one) over the seed capacity.
-hipError_t launch_fit_args(const FitArgs &A, hipStream_t st, bool after_persistent, int block, int spt) {
+hipError_t launch_fit_args(const FitArgs &A, hipStream_t st, bool ordered, int block, int spt) {
     const int b = block > 0 ? block : TPC_BLOCK;
     const int64_t per = (int64_t)b * (spt > 0 ? spt : 1);
     int64_t blocks = ((int64_t)A.cap_seeds + per - 1) / per;
     const int64_t maxb = (int64_t)8192 * TPC_BLOCK / b;
     if (blocks > maxb) blocks = maxb;
     if (blocks < 1) blocks = 1;
-    if (after_persistent)
+    if (ordered)
         hipLaunchKernelGGL(fit_tracks_ordered, dim3((unsigned)blocks), dim3(b), 0, st, A);
     else
         hipLaunchKernelGGL(fit_tracks, dim3((unsigned)blocks), dim3(b), 0, st, A);
@@ -169,15 +253,17 @@ hipError_t launch_fit_shaped(const tpc_context *ctx, const tpc_frames *fr, const
     FitArgs A = make_fit_args(ctx, fr, sd, nullptr);
     A.out = *tr;
     A.ckpt = nullptr;
+    float2 *hyz;
+    FitOrderWs ord;
+    fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz, &ord);
     if (sd->hit_yz) {
         A.hyz = reinterpret_cast<const float2 *>(sd->hit_yz);
     } else {
-        float2 *hyz;
-        fit_ws_layout(ws, sd->cap_seeds, sd->cap_hits, nullptr, &hyz);
         A.hyz = hyz;
         launch_gather(fr, sd, hyz, st);
     }
-    return launch_fit_args(A, st, false, block, spt);
+    if (sd->cap_seeds >= TPC_FIT_ORDER_MIN) launch_fit_order(A, ord, st);
+    return launch_fit_args(A, st, A.order != nullptr, block, spt);
 }
 
 size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part) {
@@ -188,13 +274,20 @@ size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part) {
     return (w.off + 255) & ~size_t(255);
 }
 
-// Fit workspace: the chi2 partials, then the seed-ordered hit coordinates.
-size_t fit_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, double **part, float2 **hyz) {
+// Fit workspace: the chi2 partials, the seed-ordered hit coordinates, then
+// the length order of the seeds.
+size_t fit_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, double **part, float2 **hyz,
+                     FitOrderWs *ord) {
     const size_t a = chi2_ws_layout(ws, cap_seeds, part);
     WsCarver w(ws);
     w.off = a;
     float2 *h = w.take<float2>(cap_hits > 0 ? cap_hits : 1);
     if (hyz) *hyz = h;
+    int32_t *o = w.take<int32_t>(cap_seeds > 0 ? cap_seeds : 1);
+    int32_t *hi = w.take<int32_t>(TPC_MAX_ROWS + 1);
+    int32_t *cu = w.take<int32_t>(TPC_MAX_ROWS + 1);
+    int32_t *n = w.take<int32_t>(1);
+    if (ord) *ord = FitOrderWs{o, hi, cu, n};
     return (w.off + 255) & ~size_t(255);
 }
 

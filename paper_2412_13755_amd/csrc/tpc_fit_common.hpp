@@ -258,5 +258,5 @@ __host__ __device__ inline void adj_one(const FitArgs &F, const int32_t *status,
 
 FitArgs make_fit_args(const tpc_context *ctx, const tpc_frames *fr, const tpc_seeds *sd,
                       const float *map);
-hipError_t launch_fit_args(const FitArgs &A, hipStream_t st, bool after_persistent = false, int block = 0,
+hipError_t launch_fit_args(const FitArgs &A, hipStream_t st, bool ordered = false, int block = 0,
                            int spt = 0);

@@ -74,7 +74,15 @@ struct CaWs {
 size_t nb_ws_layout(void *ws, int64_t N, int64_t NR, NbWs *out);
 size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out);
 size_t chi2_ws_layout(void *ws, int64_t cap_seeds, double **part);
-size_t fit_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, double **part, float2 **hyz);
+// Length order of the seeds for the fit: order[cap_seeds], the per-length
+// bin starts and cursors, the number of ordered seeds.  Fits of at least
+// TPC_FIT_ORDER_MIN seed slots run in that order.
+struct FitOrderWs {
+    int32_t *order, *hist, *cur, *n;
+};
+#define TPC_FIT_ORDER_MIN 4096
+size_t fit_ws_layout(void *ws, int64_t cap_seeds, int64_t cap_hits, double **part, float2 **hyz,
+                     FitOrderWs *ord = nullptr);
 hipError_t launch_gather(const tpc_frames *fr, const tpc_seeds *sd, float2 *hyz, hipStream_t st);
 size_t adj_ws_layout(void *ws, int64_t cap_hits, int64_t cap_seeds, int64_t n_fs, int32_t n_rows,
                      int32_t K, float2 **g, double **tape, float2 **partial, float2 **hyz);
