@@ -1290,10 +1290,11 @@ void oracle_fit_rows(int32_t n_tracks, const int32_t *offsets, const int32_t *hi
 }
 
 /* ------------------------------------------------------------------------ */
-/* Merging of track segments across sector edges (the survey's next row f1; */
-/* the paper gives no algorithm).  A particle that crosses from one sector   */
-/* into the next on the same side leaves a fitted segment in each; their     */
-/* states, carried to a common plane, agree within their covariances.        */
+/* Merging of track segments across sector edges (a step after the fit that */
+/* the paper implies but gives no algorithm for).  A particle that crosses  */
+/* from one sector into the next on the same side leaves a fitted segment   */
+/* in each; their states, carried to a common plane, agree within their     */
+/* covariances.                                                             */
 /*  transfer  the state p at plane x of one sector's frame, rotated into the */
 /*            frame turned by da (a point (x, y) -> (x cos da + y sin da,     */
 /*            -x sin da + y cos da), phi -> phi - da with cos phi > 0 kept),  */
@@ -1615,7 +1616,7 @@ void oracle_legs(int32_t n_tracks, const double *x, const double *par, const dou
 
 /* ------------------------------------------------------------------------ */
 /* Tracks assembled from linked segments and refitted over all their hits   */
-/* (the survey's next row f1; the paper gives no algorithm).                 */
+/* (a step after merging that the paper implies but does not describe).     */
 /*  links     a next link i -> j counts when j = next[i] is a segment other  */
 /*            than i with prev[j] = i and both fits have status 0; a leg     */
 /*            link i -- j when leg[j] = i likewise.                          */
