@@ -494,7 +494,10 @@ tpc_status tpc_track_merge(const tpc_context *ctx, const tpc_seeds *seeds, const
  * refitted chains at their heads (as tpc_track_merge's legs), fused in the
  * sense of i's chain: S = S_i + D S_j D, d = m_i - D m_j, m = m_i - S_i S^-1
  * d, C = S_i S^-1 D S_j D, chi2 = d^T S^-1 d; elsewhere zeros and chi2 -1.
- * Seeds are read as tpc_ca_seed writes them (hit_yz is not used); the first
+ * Seeds are read as tpc_ca_seed writes them from adjacent-row links: hit j of
+ * a seed lies in row first_row + j, as tpc_kalman_fit reads them (hit_yz is
+ * not used); a segment whose rows leave 0..n_rows-1 or whose hit ids leave
+ * the frames makes its chain's status TPC_FIT_INIT_FAIL.  The first
  * min(*n_seeds, cap_seeds) entries of each output are written.  No
  * workspace. */
 tpc_status tpc_track_refit(const tpc_context *ctx, const tpc_frames *frames, const tpc_seeds *seeds,
