@@ -138,6 +138,7 @@ def refit(seeds: dict, tracks: dict, nxt, prv, leg, y, z, row_x, n_rows, n_secto
     rx = np.ascontiguousarray(row_x, dtype=np.float64)
     T = len(offsets) - 1
     assert st.size == T and nx.size == T and pv.size == T and (lg is None or lg.size == T)
+    assert hits.size == 0 or (hits.min() >= 0 and hits.max() < y.size), "seed hit ids outside the clusters"
     prm = FitParams(bz, sigma_y, sigma_z, max_sin, var_sin0, var_tgl0, var_qpt0)
     mp = None if map_ is None else np.ascontiguousarray(map_, dtype=np.float64)
     n1 = max(T, 1)
