@@ -179,3 +179,97 @@ def capped_fraction(fr, seeds, mass, gas):
             total += 1
             capped += w1 == p[4] and vw == 0.0
     return capped / max(total, 1)
+
+
+def oracle_chain(fr, nb, min_hits, fit_prm, cut, legs=True):
+    """The oracle's own chain on a frame: neighbours, seeds, float64 fits,
+    the merging links and (with legs) the pairing of looper legs."""
+    ru, rd = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **nb)
+    rs = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, min_hits)
+    ro = oracle.fit(rs, fr.y, fr.z, fr.row_x, fr.n_rows, **fit_prm)
+    rn, rp, rc, rmp, rmc = oracle.merge(ro, rs["frame"], rs["sector"], fr.n_sectors, bz=fit_prm["bz"],
+                                        max_sin=fit_prm["max_sin"], cut=cut)
+    out = dict(up=ru, dn=rd, seeds=rs, fit=ro, next=rn, prev=rp, chi2=rc, mpar=rmp, mcov=rmc)
+    if legs:
+        out["leg"], out["leg_chi2"] = oracle.legs(ro, rs["frame"], rs["sector"], fr.n_sectors, bz=fit_prm["bz"],
+                                                  cut=cut)
+    return out
+
+
+MERGE_DIFF = 2e-3       # share of the links a marginal decision may change
+
+
+def compare_merge(g, r):
+    """Merging of the GPU's chain (dict: next, prev, chi2, mpar, mcov and
+    optionally leg, leg_chi2; host arrays) against the oracle's own chain
+    (oracle_chain).  The GPU compares chi2 of float fits with the cut, the
+    oracle of float64 fits, so a link or pairing may differ where that
+    decision is marginal: at most MERGE_DIFF of the links.  Where they agree
+    the chi2 is within 10x the fit's chi2 tolerance and the combined state
+    within 10x the fit tolerances.  Returns statistics."""
+    gn, gp = np.asarray(g["next"]), np.asarray(g["prev"])
+    rn = np.asarray(r["next"])
+    T = rn.size
+    nl = max(int((rn >= 0).sum()), 1)
+    # the GPU's links are mutual
+    L = np.nonzero(gn >= 0)[0]
+    np.testing.assert_array_equal(gp[gn[L]], L)
+    assert (gp >= 0).sum() == L.size
+    dn_ = int((gn != rn).sum())
+    assert dn_ <= max(2, MERGE_DIFF * nl), "links differ at %d of %d" % (dn_, nl)
+    A = (gn == rn) & (rn >= 0)
+    gc = np.asarray(g["chi2"], np.float64)
+    np.testing.assert_allclose(gc[A], r["chi2"][A], rtol=10 * CHI2_RTOL, atol=1e-4)
+    assert np.all(gc[gn < 0] == 0)
+    gmp, gmc = np.asarray(g["mpar"], np.float64), np.asarray(g["mcov"], np.float64)
+    tol = 10 * PAR_RTOL * np.maximum(np.abs(r["mpar"][A]), PAR_FLOOR)
+    assert not (np.abs(gmp[A] - r["mpar"][A]) > tol).any(), np.abs(gmp[A] - r["mpar"][A]).max(axis=0)
+    if A.any():
+        C1, C2 = oracle.unpack_cov(gmc[A]), oracle.unpack_cov(r["mcov"][A])
+        sd_ = np.sqrt(np.einsum("tii->ti", C2))
+        assert (np.abs(C1 - C2) / (sd_[:, :, None] * sd_[:, None, :])).max() <= 10 * COV_RTOL
+    assert not gmp[gn < 0].any() and not gmc[gn < 0].any()
+    st = dict(segments=T, links=int((rn >= 0).sum()), links_differ=dn_)
+    if "leg" in g and g["leg"] is not None:
+        gl, rl = np.asarray(g["leg"]), np.asarray(r["leg"])
+        P = np.nonzero(gl >= 0)[0]
+        np.testing.assert_array_equal(gl[gl[P]], P)
+        dl_ = int((gl != rl).sum())
+        assert dl_ <= max(2, MERGE_DIFF * nl), "leg pairs differ at %d" % dl_
+        B = (gl == rl) & (rl >= 0)
+        glc = np.asarray(g["leg_chi2"], np.float64)
+        np.testing.assert_allclose(glc[B], r["leg_chi2"][B], rtol=10 * CHI2_RTOL, atol=1e-4)
+        assert np.all(glc[gl < 0] == 0)
+        st.update(leg_pairs=int((rl >= 0).sum()) // 2, legs_differ=dl_)
+    return st
+
+
+def link_components(status, nxt, leg=None):
+    """Connected components of the segments of status 0 under the mutual
+    next/prev and leg links (breadth-first search), each named by its
+    smallest segment; -1 for the others."""
+    from collections import deque
+    status = np.asarray(status)
+    nxt = np.asarray(nxt)
+    T = status.size
+    adj = [[] for _ in range(T)]
+    for i in range(T):
+        for j in (nxt[i], -1 if leg is None else np.asarray(leg)[i]):
+            if j >= 0 and status[i] == 0 and status[j] == 0:
+                adj[i].append(int(j))
+                adj[j].append(i)
+    out = np.full(T, -1, np.int64)
+    for s in range(T):
+        if status[s] != 0 or out[s] >= 0:
+            continue
+        comp, dq = [s], deque([s])
+        out[s] = s
+        while dq:
+            u = dq.popleft()
+            for v in adj[u]:
+                if out[v] < 0:
+                    out[v] = s
+                    comp.append(v)
+                    dq.append(v)
+        out[comp] = min(comp)
+    return out

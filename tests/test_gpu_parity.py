@@ -228,7 +228,10 @@ def test_fit_with_map_matches_oracle(torch_dev):
     mp = np.random.default_rng(0).normal(0, 0.2, (fr.n_sectors, fr.n_rows, 2)).astype(np.float32)
     tr = reco.fit(dfr, seeds, torch.from_numpy(mp).cuda())
     torch.cuda.synchronize()
-    sd = seeds.to_numpy()
+    # the oracle fits its own seeds, equal to the GPU's
+    ru, rd = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    sd = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, MIN_HITS)
+    parity.assert_seeds_equal(seeds.to_numpy(), sd)
     T = len(sd["offsets"]) - 1
     gt = dict(x=tr.x[:T].cpu().numpy(), par=tr.par[:T].cpu().numpy(), cov=tr.cov[:T].cpu().numpy(),
               chi2=tr.chi2[:T].cpu().numpy(), ndf=tr.ndf[:T].cpu().numpy(),

@@ -12,10 +12,10 @@ same clusters; the GPU does the same in its kernels.
   refitted within the fit tolerances (parameters 1e-4 relative with
   floors, covariance 1e-3 of the standard deviations, chi2 1e-3); heads,
   members and ndf equal;
-* the track ids equal the oracle's component ids of the GPU's own links
-  (integers, exact), and so do the refits of every chain against the
-  oracle refitting the GPU's chains; the joint looper circles are within
-  the same tolerances where both sides formed them;
+* the track ids are the connected components of the GPU's own links (a
+  breadth-first search in the test), and equal the oracle's where the links
+  agree; the joint looper circles are within the same tolerances where
+  both sides paired the same legs over the same chains;
 * on 64 uneven frames (no link crosses a frame) and on one sector (no
   links: every refit is its seed fit)."""
 import numpy as np
@@ -81,35 +81,21 @@ def check(fr, label, expect_links=True):
     out = reco.refit(dfr, seeds, tr, nxt, prv, leg)
     torch.cuda.synchronize()
     T = int(seeds.n_seeds.item())
-    # the oracle's own chain
-    ru, rd = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
-    np.testing.assert_array_equal(up.cpu().numpy(), ru)
-    np.testing.assert_array_equal(dn.cpu().numpy(), rd)
-    rs = oracle.ca_seed(fr.row_offsets, ru, rd, fr.n_sectors, fr.n_rows, MIN_HITS)
+    # the oracle's own chain from the same clusters
+    r = parity.oracle_chain(fr, NB, MIN_HITS, FIT, CUT)
+    rs, ro = r["seeds"], r["fit"]
+    np.testing.assert_array_equal(up.cpu().numpy(), r["up"])
+    np.testing.assert_array_equal(dn.cpu().numpy(), r["dn"])
     parity.assert_seeds_equal(seeds.to_numpy(), rs)
-    ro = oracle.fit(rs, fr.y, fr.z, fr.row_x, fr.n_rows, **FIT)
     g = _host(tr, T)
     parity.compare_fit(g, ro)
-    rn, rp, rc, rmp, rmc = oracle.merge(ro, rs["frame"], rs["sector"], fr.n_sectors, bz=FIT["bz"],
-                                        max_sin=FIT["max_sin"], cut=CUT)
-    rl, rlc = oracle.legs(ro, rs["frame"], rs["sector"], fr.n_sectors, bz=FIT["bz"], cut=CUT)
-    gn, gp_, gc = nxt[:T].cpu().numpy(), prv[:T].cpu().numpy(), chi[:T].cpu().numpy()
-    gl, glc = leg[:T].cpu().numpy(), lchi[:T].cpu().numpy()
-    # merging decisions: equal but for marginal ones
-    dn_ = int((gn != rn).sum())
-    dl_ = int((gl != rl).sum())
-    nl = max(int((rn >= 0).sum()), 1)
-    print("[refit] %s: seeds %d links %d (differ %d) legs %d (differ %d)" % (
-        label, T, int((rn >= 0).sum()), dn_, int((rl >= 0).sum()) // 2, dl_), flush=True)
-    assert dn_ <= max(2, MAX_LINK_DIFF * nl) and dl_ <= max(2, MAX_LINK_DIFF * nl)
-    L = (gn == rn) & (rn >= 0)
-    np.testing.assert_allclose(gc[L], rc[L], rtol=parity.CHI2_RTOL * 10, atol=1e-4)
-    gmp, gmc = mp[:T].cpu().numpy().astype(np.float64), mc[:T].cpu().numpy().astype(np.float64)
-    tol = 10 * parity.PAR_RTOL * np.maximum(np.abs(rmp[L]), parity.PAR_FLOOR)
-    assert not (np.abs(gmp[L] - rmp[L]) > tol).any(), np.abs(gmp[L] - rmp[L]).max(axis=0)
-    P = (gl == rl) & (rl >= 0)
-    np.testing.assert_allclose(glc[P], rlc[P], rtol=parity.CHI2_RTOL * 10, atol=1e-4)
-    # refits of the oracle's own chains where both sides built the same chain
+    gn, gp_ = nxt[:T].cpu().numpy(), prv[:T].cpu().numpy()
+    gl = leg[:T].cpu().numpy()
+    mst = parity.compare_merge(dict(next=gn, prev=gp_, chi2=chi[:T].cpu().numpy(), mpar=mp[:T].cpu().numpy(),
+                                    mcov=mc[:T].cpu().numpy(), leg=gl, leg_chi2=lchi[:T].cpu().numpy()), r)
+    rn, rp, rl = r["next"], r["prev"], r["leg"]
+    print("[refit] %s: %s" % (label, mst), flush=True)
+    # refits of the chains both sides built the same way
     rr = oracle.refit(rs, ro, rn, rp, rl, fr.y, fr.z, fr.row_x, fr.n_rows, fr.n_sectors, **FIT)
     gr = _host(out["refit"], T)
     hg = np.nonzero(gr["status"] != 5)[0]
@@ -124,23 +110,32 @@ def check(fr, label, expect_links=True):
         label, len(cr), multi, st["compared"], st["worst_par"], st["worst_cov"]), flush=True)
     if expect_links:
         assert multi > 500
-    # the GPU's own links through the oracle: ids exact, every chain within tolerance
-    ro_g = {k: v.astype(np.float64) if v.dtype.kind == "f" else v for k, v in g.items()}
-    rr2 = oracle.refit(rs, ro_g, gn, gp_, gl, fr.y, fr.z, fr.row_x, fr.n_rows, fr.n_sectors, **FIT)
-    np.testing.assert_array_equal(out["track_id"][:T].cpu().numpy(), rr2["track_id"])
-    np.testing.assert_array_equal(gr["status"] == 5, rr2["status"] == 5)
-    parity.compare_fit(gr, rr2)
-    lg = out["loop_chi2"][:T].cpu().numpy()
-    lr = rr2["loop_chi2"]
-    both = (lg >= 0) & (lr >= 0)
-    assert (lg >= 0).sum() - both.sum() <= max(1, 1e-3 * len(lg))
-    assert (lr >= 0).sum() - both.sum() <= max(1, 1e-3 * len(lg))
-    if both.any():
+    # heads and members: a segment is a head exactly when its fit succeeded
+    # and no counted prev link reaches it (a property of the GPU's own links)
+    head = (g["status"] == 0) & (gp_ < 0)
+    np.testing.assert_array_equal(gr["status"] != 5, head)
+    # track ids: the components of the GPU's own links; equal to the
+    # oracle's where both sides linked the same way
+    gid = out["track_id"][:T].cpu().numpy()
+    np.testing.assert_array_equal(gid, parity.link_components(g["status"], gn, gl))
+    if np.array_equal(gn, rn) and np.array_equal(gl, rl) and np.array_equal(g["status"] == 0, ro["status"] == 0):
+        np.testing.assert_array_equal(gid, rr["track_id"])
+    # joint looper circles of the pairs both sides formed over the same chains
+    lg, lr = out["loop_chi2"][:T].cpu().numpy(), rr["loop_chi2"]
+    def heads_of(p, i):
+        while p[i] >= 0:
+            i = p[i]
+        return i
+    both = np.array([i for i in np.nonzero((lg >= 0) & (lr >= 0))[0]
+                     if gl[i] == rl[i] and cg.get(heads_of(gp_, i)) == cr.get(heads_of(rp, i))
+                     and cg.get(heads_of(gp_, gl[i])) == cr.get(heads_of(rp, rl[i]))], dtype=np.int64)
+    assert ((lg >= 0) != (lr >= 0)).sum() <= max(2, parity.MERGE_DIFF * max(int((rl >= 0).sum()), 1))
+    if both.size:
         np.testing.assert_allclose(lg[both], lr[both], rtol=1e-2, atol=1e-3)
         _compare_circles(out["loop_par"][:T].cpu().numpy().astype(np.float64)[both], out["loop_cov"][:T].cpu()
-                         .numpy().astype(np.float64)[both], rr2["loop_par"][both], rr2["loop_cov"][both])
+                         .numpy().astype(np.float64)[both], rr["loop_par"][both], rr["loop_cov"][both])
     assert not out["loop_par"][:T].cpu().numpy()[lg < 0].any()
-    return multi, int(both.sum())
+    return multi, int(both.size)
 
 
 def test_headline_event(torch_dev):
@@ -173,12 +168,20 @@ def test_refit_with_map_and_without_legs(torch_dev):
     torch.cuda.synchronize()
     assert "loop_par" not in out
     T = int(seeds.n_seeds.item())
-    sd = seeds.to_numpy()
+    # the oracle's own chain, its refit with the same map
+    r = parity.oracle_chain(fr, NB, MIN_HITS, FIT, CUT, legs=False)
+    parity.assert_seeds_equal(seeds.to_numpy(), r["seeds"])
+    gn, gp_ = nxt[:T].cpu().numpy(), prv[:T].cpu().numpy()
+    ref = oracle.refit(r["seeds"], r["fit"], r["next"], r["prev"], None, fr.y, fr.z, fr.row_x, fr.n_rows,
+                       fr.n_sectors, map_=mp.astype(np.float64), **FIT)
     g = _host(tr, T)
-    ref = oracle.refit(sd, g, nxt[:T].cpu().numpy(), prv[:T].cpu().numpy(), None, fr.y, fr.z, fr.row_x,
-                       fr.n_rows, fr.n_sectors, map_=mp.astype(np.float64), **FIT)
-    np.testing.assert_array_equal(out["track_id"][:T].cpu().numpy(), ref["track_id"])
-    parity.compare_fit(_host(out["refit"], T), ref)
+    np.testing.assert_array_equal(out["track_id"][:T].cpu().numpy(), parity.link_components(g["status"], gn))
+    gr = _host(out["refit"], T)
+    cg = _chains(gn, gp_, np.nonzero(gr["status"] != 5)[0])
+    cr = _chains(r["next"], r["prev"], np.nonzero(ref["status"] != 5)[0])
+    same = np.array(sorted(h for h in cg if h in cr and cg[h] == cr[h]), dtype=np.int64)
+    assert same.size >= 0.995 * max(len(cr), 1) and (gn[same] >= 0).sum() > 100
+    parity.compare_fit({k: v[same] for k, v in gr.items()}, {k: v[same] for k, v in ref.items()})
 
 
 def test_refit_arguments_refused(torch_dev):
@@ -211,3 +214,43 @@ def test_refit_arguments_refused(torch_dev):
                              None, None, None, None)
     assert st == C.TPC_ERR_ARG
     torch.cuda.synchronize()
+
+
+def test_chain_longer_than_a_side(torch_dev):
+    """Links that chain 19 segments (more than the 18 sectors of a side) are
+    refused at the head with TPC_REFIT_LONG_CHAIN, the shorter chain of 18
+    is refitted, and every non-head gets TPC_REFIT_NOT_HEAD -- as the
+    oracle on its own seeds and fits with the same (test-made) links."""
+    import torch
+    from paper_2412_13755_amd import _capi as C
+    from paper_2412_13755_amd.reco import Reco, RecoConfig
+    fr = make_config(1, scale=0.05)
+    reco = Reco(RecoConfig(row_x=fr.row_x, n_sectors=fr.n_sectors, min_hits=MIN_HITS, **NB, **FIT), "cuda:0")
+    dfr = reco.upload(fr)
+    up, dn = reco.neighbours(dfr)
+    seeds = reco.seed(dfr, up, dn)
+    tr = reco.fit(dfr, seeds)
+    torch.cuda.synchronize()
+    T = int(seeds.n_seeds.item())
+    r = parity.oracle_chain(fr, NB, MIN_HITS, FIT, CUT, legs=False)
+    parity.assert_seeds_equal(seeds.to_numpy(), r["seeds"])
+    g = _host(tr, T)
+    ok = np.nonzero((g["status"] == 0) & (r["fit"]["status"] == 0))[0]
+    for length, want in ((19, C.TPC_REFIT_LONG_CHAIN), (18, None)):
+        c = ok[:length]
+        nxt = np.full(seeds.frame.numel(), -1, np.int32)
+        prv = np.full(seeds.frame.numel(), -1, np.int32)
+        nxt[c[:-1]], prv[c[1:]] = c[1:], c[:-1]
+        out = reco.refit(dfr, seeds, tr, torch.from_numpy(nxt).cuda(), torch.from_numpy(prv).cuda())
+        torch.cuda.synchronize()
+        st = out["refit"].status[:T].cpu().numpy()
+        ref = oracle.refit(r["seeds"], r["fit"], nxt[:T], prv[:T], None, fr.y, fr.z, fr.row_x, fr.n_rows,
+                           fr.n_sectors, **FIT)
+        both = (g["status"] == 0) == (r["fit"]["status"] == 0)
+        np.testing.assert_array_equal(st[both], ref["status"][both])
+        assert np.all(st[c[1:]] == C.TPC_REFIT_NOT_HEAD)
+        if want is not None:
+            assert st[c[0]] == want
+        else:
+            assert st[c[0]] != C.TPC_REFIT_LONG_CHAIN and out["refit"].ndf[c[0]].item() == ref["ndf"][c[0]]
+        np.testing.assert_array_equal(out["track_id"][:T].cpu().numpy(), parity.link_components(g["status"], nxt[:T]))
