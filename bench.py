@@ -584,7 +584,7 @@ def leg_rans(args, with_cpu=True):
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                         "algorithmic_bytes": alg,
-                        "calls": "rs_init, rs_minmax, rs_clear, rs_hist, rs_freq, rs_table, rs_encode, rs_scan, rs_pack"}}
+                        "calls": "rs_init, rs_window, rs_minmax, rs_clear, rs_hist, rs_freq, rs_table, rs_encode, rs_scan, rs_pack"}}
     if with_cpu:
         import oracle
         xs = x[:1 << 24].cpu().numpy()

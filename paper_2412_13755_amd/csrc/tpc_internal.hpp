@@ -106,7 +106,7 @@ hipError_t launch_ctf_build(const tpc_context *ctx, const tpc_frames *fr, const 
 
 #define TPC_RANS_MAX_RANGE (1 << 20)   // widest symbol range max - min + 1 of one array
 struct RansWs {
-    int32_t *mm;                 // min, max, status
+    int32_t *mm;                 // min, max, status, table bytes, histogram offset, window flag, centre
     uint32_t *counts;            // [TPC_RANS_MAX_RANGE] histogram
     uint4 *fc;                   // [TPC_RANS_MAX_RANGE] (frequency, cumulative frequency, reciprocal, shifts)
     uint32_t *wcount, *wstart;   // [nb], [nb + 1] words per coding block, their prefix

@@ -5,8 +5,16 @@
 //  Every kernel codes a batch of arrays: grid dimension y selects the
 //  array; an array's symbol count may come from device memory.
 //  rs_init      min / max / status words
-//  rs_minmax    grid reduction of the symbol range
-//  rs_clear     zero the histogram over the range (fails if wider than 2^20)
+//  rs_window    (large arrays) zero the whole histogram: it is counted in the
+//               same pass as the range, relative to a window of 2^20 symbols
+//               centred on the first symbol
+//  rs_minmax    grid reduction of the symbol range; for large arrays also
+//               the histogram over that window (LDS-private for the 8192
+//               symbols around the first one, global atomics for the rest);
+//               a symbol outside the window flags the two-pass path
+//  rs_clear     zero the histogram over the range (fails if wider than 2^20);
+//               for a large array whose window held every symbol, only the
+//               offset of the range in the window is set
 //  rs_hist      histogram: LDS-private per workgroup when the range fits
 //               (8192 bins; eight copies of each bin up to 1024), global
 //               atomics otherwise; 16-byte symbol loads
@@ -50,7 +58,10 @@ struct RsArgs {
     const int64_t *n_dev;  // optional device symbol count
     int64_t n_cap;
     int32_t L, B, nb;
-    int32_t *mm;           // [0] min, [1] max, [2] status, [3] table bytes (device)
+    int32_t fused;         // range and histogram in one pass (large arrays)
+    int32_t *mm;           // [0] min, [1] max, [2] status, [3] table bytes, [4] offset of
+                           // the range in counts, [5] a symbol left the window,
+                           // [6] the window's centre (device)
     uint32_t *counts;      // [TPC_RANS_MAX_RANGE] histogram, then the table's positions and bytes
     uint4 *fc;             // [TPC_RANS_MAX_RANGE] (frequency, cumulative, reciprocal, shifts)
     uint32_t *wcount;      // [nb] words of each block
@@ -92,6 +103,9 @@ __global__ void rs_init(RsBatch Bt) {
         A.mm[1] = (int32_t)0x80000000;
         A.mm[2] = TPC_OK;
         A.mm[3] = 0;
+        A.mm[4] = 0;
+        A.mm[5] = 0;
+        A.mm[6] = A.n > 0 ? A.sym[0] : 0;
     }
 }
 
@@ -109,23 +123,65 @@ __device__ inline Vec4Split vec4_split(const int32_t *p, int64_t n) {
     return v;
 }
 
+// Arrays of at least this many symbols count their histogram in the range
+// pass (the whole 2^20-entry histogram is cleared for them).
+#define RS_FUSE_MIN (1 << 22)
+#define RS_WIN_HALF (TPC_RANS_MAX_RANGE / 2)
+#define RS_LDS_HALF (RS_LDS_BINS / 2)
+
+__global__ void __launch_bounds__(TPC_BLOCK) rs_window(RsBatch Bt) {
+    const RsArgs A = rs_job(Bt);
+    if (!A.fused) return;
+    for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < TPC_RANS_MAX_RANGE;
+         s += (int64_t)gridDim.x * TPC_BLOCK)
+        A.counts[s] = 0;
+}
+
 __global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsBatch Bt) {
     const RsArgs A = rs_job(Bt);
     __shared__ int sh[2][TPC_BLOCK / TPC_WAVE];
+    __shared__ uint32_t h[RS_LDS_BINS];
     int lo = 0x7fffffff, hi = (int)0x80000000;
     const Vec4Split V = vec4_split(A.sym, A.n);
     const int4 *v4 = reinterpret_cast<const int4 *>(A.sym + V.head);
     const int64_t gtid = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x, G = (int64_t)gridDim.x * TPC_BLOCK;
+    // large arrays: counts relative to the window [c - 2^19, c + 2^19) of
+    // the first symbol c; the 8192 symbols around c in LDS
+    const int64_t c = A.mm[6];
+    bool out = false;
+    if (A.fused) {
+        for (int b = threadIdx.x; b < RS_LDS_BINS; b += TPC_BLOCK) h[b] = 0;
+        __syncthreads();
+    }
+    auto add = [&](int v) {
+        const int64_t d = (int64_t)v - c;
+        if (d >= -RS_LDS_HALF && d < RS_LDS_HALF) atomicAdd(&h[d + RS_LDS_HALF], 1u);
+        else if (d >= -RS_WIN_HALF && d < RS_WIN_HALF) atomicAdd(&A.counts[d + RS_WIN_HALF], 1u);
+        else out = true;
+    };
     for (int64_t q = gtid; q < V.nv; q += G) {
         const int4 v = v4[q];
         lo = min(lo, min(min(v.x, v.y), min(v.z, v.w)));
         hi = max(hi, max(max(v.x, v.y), max(v.z, v.w)));
+        if (A.fused) {
+            add(v.x);
+            add(v.y);
+            add(v.z);
+            add(v.w);
+        }
     }
     for (int64_t i = gtid; i < V.head + (A.n - V.head - 4 * V.nv); i += G) {
         const int64_t j = i < V.head ? i : V.head + 4 * V.nv + (i - V.head);
         const int v = A.sym[j];
         lo = min(lo, v);
         hi = max(hi, v);
+        if (A.fused) add(v);
+    }
+    if (A.fused) {
+        if (out) A.mm[5] = 1;
+        __syncthreads();
+        for (int b = threadIdx.x; b < RS_LDS_BINS; b += TPC_BLOCK)
+            if (h[b]) atomicAdd(&A.counts[b - RS_LDS_HALF + RS_WIN_HALF], h[b]);
     }
 #pragma unroll
     for (int d = TPC_WAVE / 2; d > 0; d >>= 1) {
@@ -150,11 +206,20 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_minmax(RsBatch Bt) {
     }
 }
 
+// The histogram of a large array counted in its window: the range's offset
+// in it (read by rs_freq), unless a symbol left the window.
+__device__ inline bool rs_windowed(const RsArgs &A) { return A.fused && A.mm[5] == 0; }
+
 __global__ void __launch_bounds__(TPC_BLOCK) rs_clear(RsBatch Bt) {
     const RsArgs A = rs_job(Bt);
     const int64_t R = rs_range(A);
     if (R > TPC_RANS_MAX_RANGE) {
         if (blockIdx.x == 0 && threadIdx.x == 0) A.mm[2] = TPC_ERR_ARG;
+        return;
+    }
+    if (rs_windowed(A)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && A.n > 0)
+            A.mm[4] = (int32_t)((int64_t)A.mm[0] - ((int64_t)A.mm[6] - RS_WIN_HALF));
         return;
     }
     for (int64_t s = (int64_t)blockIdx.x * TPC_BLOCK + threadIdx.x; s < R; s += (int64_t)gridDim.x * TPC_BLOCK)
@@ -171,7 +236,7 @@ __global__ void __launch_bounds__(TPC_BLOCK) rs_hist(RsBatch Bt) {
     const RsArgs A = rs_job(Bt);
     __shared__ uint32_t h[RS_LDS_BINS];
     const int64_t R = rs_range(A);
-    if (R > TPC_RANS_MAX_RANGE) return;
+    if (R > TPC_RANS_MAX_RANGE || rs_windowed(A)) return;
     if ((int64_t)blockIdx.x * TPC_BLOCK * 4 >= A.n) return;     // no symbols for this workgroup
     const int lo = A.mm[0];
     const int mode = R <= RS_COPY_BINS ? 2 : (R <= RS_LDS_BINS ? 1 : 0);
@@ -241,6 +306,7 @@ __device__ inline unsigned long long rs_block_max(unsigned long long v, unsigned
 
 __global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsBatch Bt) {
     const RsArgs A = rs_job(Bt);
+    const uint32_t *cnt = A.counts + A.mm[4];      // the range's first symbol
     __shared__ long long sh[RS_FREQ_THREADS / TPC_WAVE];
     __shared__ unsigned long long shk[RS_FREQ_THREADS / TPC_WAVE];
     __shared__ int scan_sh[RS_FREQ_THREADS / TPC_WAVE];
@@ -251,7 +317,7 @@ __global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsBatch Bt) {
     long long d = 0;
     unsigned long long best = 0;
     for (int64_t s = threadIdx.x; s < R; s += RS_FREQ_THREADS) {
-        const uint32_t c = A.counts[s];
+        const uint32_t c = cnt[s];
         d += c > 0;
         const unsigned long long key = ((unsigned long long)c << 32) | (0xffffffffull - (uint64_t)s);
         best = key > best ? key : best;
@@ -265,7 +331,7 @@ __global__ void __launch_bounds__(RS_FREQ_THREADS) rs_freq(RsBatch Bt) {
     const int64_t sbest = (int64_t)(0xffffffffull - (best & 0xffffffffull));
     long long part = 0;
     for (int64_t s = threadIdx.x; s < R; s += RS_FREQ_THREADS) {
-        const uint32_t c = A.counts[s];
+        const uint32_t c = cnt[s];
         const uint32_t f = c ? (uint32_t)((uint64_t)c * (M - (uint64_t)D) / (uint64_t)A.n + 1) : 0u;
         A.fc[s].x = f;
         part += f;
@@ -729,7 +795,7 @@ size_t rans_ws_layout(void *ws, int64_t n, int32_t B, RansWs *out) {
     WsCarver w(ws);
     const int64_t nb = n > 0 ? (n + B - 1) / B : 0;
     RansWs r;
-    r.mm = w.take<int32_t>(4);
+    r.mm = w.take<int32_t>(8);
     r.counts = w.take<uint32_t>(TPC_RANS_MAX_RANGE);
     r.fc = w.take<uint4>(TPC_RANS_MAX_RANGE);
     r.wcount = w.take<uint32_t>(nb > 0 ? nb : 1);
@@ -757,6 +823,7 @@ hipError_t launch_rans_batch(int count, const RansJob *jobs, int32_t L, int32_t 
         A.n_cap = J.n;
         A.L = L;
         A.B = B;
+        A.fused = J.n >= RS_FUSE_MIN;
         A.nb = (int32_t)(J.n > 0 ? (J.n + B - 1) / B : 0);
         A.mm = W.mm;
         A.counts = W.counts;
@@ -776,6 +843,10 @@ hipError_t launch_rans_batch(int count, const RansJob *jobs, int32_t L, int32_t 
     const int gs = grid_over((ncap + 15) / 16, 2048);
     const dim3 one(1, count);
     hipLaunchKernelGGL(rs_init, one, dim3(TPC_WAVE), 0, st, Bt);
+    bool any_fused = false;
+    for (int k = 0; k < count; ++k) any_fused = any_fused || Bt.a[k].fused;
+    if (any_fused)
+        hipLaunchKernelGGL(rs_window, dim3(grid_over(TPC_RANS_MAX_RANGE, 1024), count), dim3(TPC_BLOCK), 0, st, Bt);
     hipLaunchKernelGGL(rs_minmax, dim3(gs, count), dim3(TPC_BLOCK), 0, st, Bt);
     hipLaunchKernelGGL(rs_clear, dim3(grid_over(TPC_RANS_MAX_RANGE, 1024), count), dim3(TPC_BLOCK), 0, st, Bt);
     hipLaunchKernelGGL(rs_hist, dim3(gs, count), dim3(TPC_BLOCK), 0, st, Bt);

@@ -85,6 +85,24 @@ def test_large_array(torch_dev):
     _check(x, 14, 1 << 15, "2^24 normal")
 
 
+def test_large_arrays_counted_in_one_pass(torch_dev):
+    """Arrays of 2^22 symbols or more count their histogram in the range pass,
+    relative to a window of 2^20 around the first symbol: in the window (the
+    first symbol at the range's low end), one symbol beyond it (the two-pass
+    path takes over), and a range wider than 2^20 (refused)."""
+    rng = np.random.default_rng(12)
+    x = np.abs(np.round(rng.normal(0.0, 300.0, 1 << 22))).astype(np.int32)
+    x[0] = 0                                                   # the window's centre at the minimum
+    _check(x, 14, 1 << 15, "2^22, first symbol at the minimum")
+    y = x.copy()
+    y[12345] = 900_000                                         # range < 2^20, beyond the window
+    _check(y, 14, 1 << 15, "2^22, one symbol beyond the window")
+    z = x.copy()
+    z[777] = 1 << 21                                           # range beyond 2^20
+    _, _, st = _gpu(z, 14, 1 << 15)
+    assert st == -1
+
+
 def test_repeat_is_identical(torch_dev):
     x = np.random.default_rng(10).integers(-100, 100, 300_000).astype(np.int32)
     a, _, _ = _gpu(x, 12, 4096)
