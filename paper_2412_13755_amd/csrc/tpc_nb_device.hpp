@@ -194,7 +194,9 @@ __device__ inline SegGrid zrow_grid(float zmin, float zmax, int n, int cap) {
 // gathered from the row), so no partially written cache lines go to HBM.
 // n = b - a <= TPC_BIN_PERM.  g has one cell column (a zrow_grid, ny = 1),
 // so the cell is z's alone and y is read only by the final gather.
-#define TPC_BIN_PERM 24576
+#ifndef TPC_BIN_PERM
+#define TPC_BIN_PERM 17408   // 51 KB of LDS: three binning workgroups per CU
+#endif
 __device__ inline void row_sort_perm(const float *__restrict__ y, const float *__restrict__ z, int a, int b,
                                      const SegGrid &g, int *cnt, int *scan_sh, uint16_t *perm,
                                      float *__restrict__ dy, float *__restrict__ dz, int32_t *__restrict__ did,
