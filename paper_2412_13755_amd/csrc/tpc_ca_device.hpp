@@ -49,9 +49,13 @@ __device__ inline unsigned long long claim_key(int32_t m, int32_t b) {
 // down, bit 61; set by the LDS rankings, so that ca_tops need not look) and
 // whether h keeps a link up (bit 62) / down (bit 63).
 
+#ifndef TPC_CA_ROWS
 #define TPC_CA_ROWS 16          // rows per ranking block
+#endif
 #define TPC_CA_CAP 8192         // clusters per block ranked in LDS
+#ifndef TPC_CA_ROUNDS
 #define TPC_CA_ROUNDS 5         // > log2(TPC_CA_ROWS): links inside a block
+#endif
 #define TPC_CA_BOT (1ull << 61)
 #define TPC_CA_UP (1ull << 62)
 #define TPC_CA_DN (1ull << 63)
@@ -107,7 +111,7 @@ __device__ inline void ca_block_item(int item, int32_t N, int32_t n_rows, const 
             const int32_t h = lo + k;
             const bool hd = bd[j] == h, hu = bu[j] == h;
             ws.claim[h] = ~0ull;
-            ws.core[h] = 0;
+            ws.cc[h] = make_int2(0, -1);
             ws.memb[h] = -1;                          // set by ca_tops for chain members
             ws.dlk[h] = hd ? d[j] : -1;
             const bool in = hd && d[j] >= lo && d[j] < hi && d[j] != h;
@@ -262,7 +266,7 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
             }
             ww[j] = (hd ? TPC_CA_W_DN : 0u) | (hu ? TPC_CA_W_UP : 0u) | bot | (dist << 24) | low;
             ws.claim[h] = ~0ull;
-            ws.core[h] = 0;
+            ws.cc[h] = make_int2(0, -1);
             ws.memb[h] = -1;                          // set by ca_tops for chain members
             ws.dlk[h] = hd ? d : -1;
         }
@@ -330,9 +334,8 @@ __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restri
         ws.mpos[h] = pos;
         if (!(w0 & TPC_CA_UP) && valid_id(bot, N)) {  // h is the top: chain of pos + 1 clusters
             const int32_t m = pos + 1;
-            ws.core[bot] = m;
+            ws.cc[bot] = make_int2(m, -1);
             ws.ctop[bot] = h;
-            ws.choff[bot] = -1;
             if (m >= min_hits - 2) {
                 const unsigned long long key = claim_key(m, bot);
                 const int32_t eb = dn[bot], et = up[h];
@@ -353,7 +356,7 @@ __device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict
 // Seed length of the chain with bottom bb (0 if it is no seed).
 __device__ inline int32_t seed_len(const int32_t *up, const int32_t *dn, int32_t N, int32_t min_hits,
                                    const CaWs &ws, int32_t bb, int32_t *won_b) {
-    int32_t m = ws.core[bb];
+    int32_t m = ws.cc[bb].x;
     int32_t wb = 0, wt = 0;
     if (m >= min_hits - 2) {
         unsigned long long key = claim_key(m, bb);
@@ -373,7 +376,7 @@ __device__ inline void ca_first_one(int32_t h, int32_t N, const int32_t *__restr
                                     int32_t &fb, int32_t &len) {
     fb = -1;
     len = 0;
-    if (ws.core[h] >= 2) {                       // h is a bottom
+    if (ws.cc[h].x >= 2) {                       // h is a bottom
         int32_t wb;
         int32_t l = seed_len(up, dn, N, min_hits, ws, h, &wb);
         if (l > 0 && !wb) { fb = h; len = l; }
@@ -455,13 +458,13 @@ __device__ inline void ca_place_one(int32_t h, int32_t fb, int32_t len, int i, i
             sd.hits[o] = h;
             if (sd.hit_yz) put_yz(sd.hit_yz, o, y[h], z[h]);
         }
-        const int32_t m = ws.core[fb];
+        const int32_t m = ws.cc[fb].x;
         if (len > m + wb) {
             const int32_t et = up[ws.ctop[fb]];
             sd.hits[o + len - 1] = et;
             if (sd.hit_yz && valid_id(et, N)) put_yz(sd.hit_yz, o + len - 1, y[et], z[et]);
         }
-        ws.choff[fb] = o + wb;
+        ws.cc[fb].y = o + wb;
         if (len_hist) atomicAdd(&len_hist[len < TPC_MAX_ROWS ? len : TPC_MAX_ROWS], 1);
     }
 }
@@ -528,8 +531,9 @@ __device__ inline void ca_members_one(int32_t h, int32_t N, const float *__restr
     {
         const int32_t bb = ws.memb[h];                // -1 unless h is in a chain
         if (!valid_id(bb, N)) return;
-        const int32_t o = ws.choff[bb], k = ws.mpos[h];
-        if (o >= 0 && k >= 0 && k < ws.core[bb] && o + k < cap_hits) {
+        const int2 c = ws.cc[bb];                    // (chain length, core offset)
+        const int32_t o = c.y, k = ws.mpos[h];
+        if (o >= 0 && k >= 0 && k < c.x && o + k < cap_hits) {
             sd.hits[o + k] = h;
             if (sd.hit_yz) put_yz(sd.hit_yz, o + k, y[h], z[h]);
         }

@@ -189,13 +189,12 @@ size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out) {
     l.claim = w.take<unsigned long long>(N);
     l.pack = w.take<unsigned long long>(N);
     l.dlk = w.take<int32_t>(N);
-    l.core = w.take<int32_t>(N);
+    l.cc = w.take<int2>(N);
     l.ctop = w.take<int32_t>(N);
     l.memb = w.take<int32_t>(N);
     l.mpos = w.take<int32_t>(N);
     l.fbot = w.take<int32_t>(N);
     l.flen = w.take<int32_t>(N);
-    l.choff = w.take<int32_t>(N);
     l.segcnt = w.take<int32_t>(NR);
     l.seghits = w.take<int32_t>(NR);
     l.segbs = w.take<int32_t>(NR);

@@ -56,13 +56,13 @@ struct CaWs {
     unsigned long long *claim;   // [N] smallest claim key per cluster
     unsigned long long *pack;    // [N] (distance << 32) | lowest chain member in the row block
     int32_t *dlk;                // [N] kept link down, -1 if none
-    int32_t *core;               // [N] chain length at a bottom, 0 elsewhere
+    int2 *cc;                    // [N] at a bottom: (chain length, hit offset of the chain core or
+                                 // -1 if no seed), read together; (0, -1) elsewhere
     int32_t *ctop;               // [N] chain top at a bottom
     int32_t *memb;               // [N] bottom of the chain a linked cluster is in
     int32_t *mpos;               // [N] its position in that chain
     int32_t *fbot;               // [N] at a seed's first cluster: the chain bottom, else -1
     int32_t *flen;               // [N] at a seed's first cluster: seed length
-    int32_t *choff;              // [N] at a bottom: hit offset of the chain core, -1 if no seed
     int32_t *segcnt, *seghits;   // [NR] seeds / seed hits starting in the segment
     int32_t *segbs, *segbh;      // [NR] exclusive prefixes of the above
     int32_t *chunk_c, *chunk_h;  // [ceil(NR / TPC_SCAN_CHUNK)] chunk sums, then their prefixes
