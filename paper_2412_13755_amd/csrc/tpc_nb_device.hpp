@@ -658,59 +658,35 @@ __device__ inline int2 zrange(const SegGrid &g, const int32_t *cs, float lo, flo
 // |dy| or |dz| above sqrt(q*), so fl(dy^2) + fl(dz^2) > q* (rounding is
 // monotonic and both squares are >= 0) and it can neither beat nor tie the
 // best, whose lexicographic order (q, then u id, then d id) is kept
-// exactly.  The candidate loops carry no branches.
-#ifndef TPC_NB_DYN
-#define TPC_NB_DYN 1
-#endif
-
-// Down-row box scan of one (h, u) pair: updates the lane's best (qb, ub, db).
-__device__ inline void box_scan(float yh, float zh, float ay, float az, uint32_t ur, float my, float mz,
-                                float cut_y, float cut_z, float win_y, float win_z, const float *Y,
-                                const float *Z, const uint16_t *R, const int32_t *DCS, const SegGrid &gd,
-                                float &qb, uint32_t &ub, uint32_t &db) {
-#pragma clang fp contract(off)
-    const float cy = yh - ay, cz = zh - az;
-    const float r = sqrtf(qb) * 1.0001f;           // +inf until a triplet passes
-    const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
-    int yd = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
-    const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
-    const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
-    const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
-    for (; yd <= yd1; ++yd) {
-        const int e1 = DCS[yd * gd.nz + zd1 + 1];
-        for (int kd = DCS[yd * gd.nz + zd0]; kd < e1; ++kd) {
-            const float by = yh - Y[kd];
-            const float bz = zh - Z[kd];
-            const float dy = ay - by;
-            const float dz = az - bz;
-            const float qy = dy * dy;
-            const float qz = dz * dz;
-            const float q = qy + qz;
-            const uint32_t dr = R[kd];
-            const bool pass = fabsf(by) <= win_y && fabsf(bz) <= win_z && fabsf(dy) <= cut_y &&
-                              fabsf(dz) <= cut_z;
-            const bool tie = q == qb;
-            const bool win = pass && (q < qb || (tie && (ur < ub || (ur == ub && dr < db))));
-            qb = win ? q : qb;
-            ub = win ? ur : ub;
-            db = win ? dr : db;
-        }
-    }
-}
-
-// The square root of the box set-up is the hardware estimate (a few ulp at
+// exactly.
+//
+// The nested walks of one cluster (up-row window cells, their candidates,
+// and for each up cluster in the window the down-row box cells and their
+// candidates) run as one flat loop in which every iteration tests one LDS
+// candidate per lane, so lanes at different depths of the walk stay in
+// step; a lane moves to its next cluster (every TPC_BLOCK-th of the slab,
+// loaded while it searches the current one) when the current one is
+// exhausted.  One candidate test serves both walks: a candidate c at
+// (t_y, t_z) = (y_c - y_h, z_c - z_h) passes the window test on |t| in
+// either; an up candidate then starts a down box, a down candidate is
+// scored with d_y = a_y + t_y, equal (rounding included) to
+// a_y - (y_h - y_d) since fl(y_h - y_d) = -fl(y_d - y_h).  The best so far
+// is one 64-bit key (bits of q, then the up and down ids, 16 bits each), so
+// the lexicographic order is one unsigned comparison (q >= 0, whose bit
+// patterns order as its values) and the test carries no branches.
+//
+// Cell ranges are computed in cell units: the window's or the prediction's
+// cell coordinate is (y_h - y0) iw (minus a_y iw for the prediction), its
+// half-width (w + m) iw plus e = 1e-6 (|y0| iw + 1) cells, where w is the
+// window or min(cut, sqrt(q*) (1 + 1e-4)).  These products round
+// differently from cell_coord at the range's edge by a few units of 2^-24
+// of (|y_h| + |y0| + w) iw, which m (1e-5 of |y_h| + window + cut) and e
+// cover, so every cluster that can pass lies in the cells scanned.  The
+// square root of the box set-up is the hardware estimate (a few ulp at
 // most; a denormal q* may give 0, which only shrinks the box to its
-// rounding margin, still far above sqrt(q*)): the 1e-4 widening covers it,
-// and the correctly rounded sequence cost 6 % of the dense search.
-#define TPC_NB_SQRT(v) __builtin_amdgcn_sqrtf(v)
+// rounding margin, still far above sqrt(q*)): the 1e-4 widening covers it.
+__device__ inline int cell_in(float c, float nmax) { return (int)__builtin_amdgcn_fmed3f(c, 0.0f, nmax); }
 
-#if TPC_NB_DYN
-// Flat form: the nested walks of one cluster (up-row window cells, their
-// candidates, and for each up cluster in the window the down-row box cells
-// and their candidates) run as one loop in which every iteration tests one
-// LDS candidate per lane, so lanes at different depths of the walk stay in
-// step.  A lane moves to its next cluster (every TPC_BLOCK-th of the slab)
-// when the current one is exhausted.
 template <int ROW, int CELLS>
 __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy, const float *__restrict__ sz,
                                    const int32_t *__restrict__ sid, int32_t baseu, int32_t based,
@@ -722,33 +698,56 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
     const uint16_t *R = L.rel;
     const int32_t *UCS = L.cs + C0, *DCS = L.cs;
     const bool grids = gu.ny > 0 && gd.ny > 0;
+    constexpr uint64_t NONE = (0x7F800000ull << 32) | 0xFFFFFFFFull;
+    const float edy = 1e-6f * (fabsf(gd.y0) * gd.iwy + 1.0f), edz = 1e-6f * (fabsf(gd.z0) * gd.iwz + 1.0f);
+    const float euy = 1e-6f * (fabsf(gu.y0) * gu.iwy + 1.0f), euz = 1e-6f * (fabsf(gu.z0) * gu.iwz + 1.0f);
+    const float dny = (float)(gd.ny - 1), dnz = (float)(gd.nz - 1);
+    const float uny = (float)(gu.ny - 1), unz = (float)(gu.nz - 1);
+    const float wcy = win_y + cut_y, wcz = win_z + cut_z;
     int j = (int)threadIdx.x - TPC_BLOCK;
     bool active = false, dmode = false;
-    float yh = 0.f, zh = 0.f, my = 0.f, mz = 0.f, qb = INFINITY, ay = 0.f, az = 0.f;
-    uint32_t ub = 0xFFFFFFFFu, db = 0xFFFFFFFFu, ur = 0;
+    float yh = 0.f, zh = 0.f, hy = 0.f, hz = 0.f, my = 0.f, mz = 0.f, ay = 0.f, az = 0.f;
+    float yn = 0.f, zn = 0.f;
+    int32_t idn = 0, hid = 0;
+    if ((int)threadIdx.x < pn) {
+        yn = sy[pb + threadIdx.x];
+        zn = sz[pb + threadIdx.x];
+        idn = sid[pb + threadIdx.x];
+    }
+    uint64_t best = NONE;
+    uint32_t urs = 0;
     int iy = 0, iy1 = -1, zc0 = 0, zc1 = 0, k = 0, k1 = 0;
     int yd = 0, yd1 = -1, zd0 = 0, zd1 = 0, kd = 0, e1 = 0;
     while (true) {
         if (!active) {
             j += TPC_BLOCK;
             if (j < pn) {
-                yh = sy[pb + j];
-                zh = sz[pb + j];
-                qb = INFINITY;
-                ub = 0xFFFFFFFFu;
-                db = 0xFFFFFFFFu;
+                yh = yn;
+                zh = zn;
+                hid = idn;
+                if (j + TPC_BLOCK < pn) {
+                    yn = sy[pb + j + TPC_BLOCK];
+                    zn = sz[pb + j + TPC_BLOCK];
+                    idn = sid[pb + j + TPC_BLOCK];
+                }
+                best = NONE;
                 dmode = false;
                 iy = 0; iy1 = -1; k = 0; k1 = 0;
                 if (grids && isfinite(yh) && isfinite(zh)) {
-                    my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
-                    mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
-                    const float wuy = win_y + my, wuz = win_z + mz;
-                    iy = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny);
-                    iy1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
-                    zc0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz);
-                    zc1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
-                    k = UCS[iy * gu.nz + zc0];
-                    k1 = UCS[iy * gu.nz + zc1 + 1];
+                    my = __builtin_fmaf(fabsf(yh) + wcy, 1e-5f, 1e-6f);
+                    mz = __builtin_fmaf(fabsf(zh) + wcz, 1e-5f, 1e-6f);
+                    hy = (yh - gd.y0) * gd.iwy;
+                    hz = (zh - gd.z0) * gd.iwz;
+                    const float uy = (yh - gu.y0) * gu.iwy, uz = (zh - gu.z0) * gu.iwz;
+                    const float wy = __builtin_fmaf(win_y + my, gu.iwy, euy);
+                    const float wz = __builtin_fmaf(win_z + mz, gu.iwz, euz);
+                    iy = cell_in(uy - wy, uny);
+                    iy1 = cell_in(uy + wy, uny);
+                    zc0 = cell_in(uz - wz, unz);
+                    zc1 = cell_in(uz + wz, unz);
+                    const int row = __mul24(iy, gu.nz);
+                    k = UCS[row + zc0];
+                    k1 = UCS[row + zc1 + 1];
                 }
                 active = true;
             }
@@ -770,125 +769,48 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
                 k1 = UCS[iy * gu.nz + zc1 + 1];
             }
             if (k == k1) {                            // cluster done
-                const int32_t h = sid[pb + j];
-                const bool found = ub != 0xFFFFFFFFu;
-                up[h] = found ? baseu + (int32_t)ub : -1;
-                dn[h] = found ? based + (int32_t)db : -1;
+                const bool found = best != NONE;
+                up[hid] = found ? baseu + (int32_t)((uint32_t)best >> 16) : -1;
+                dn[hid] = found ? based + (int32_t)((uint32_t)best & 0xFFFFu) : -1;
                 active = false;
                 continue;
             }
         }
         const int c = dmode ? kd : k;
-        const float cy = Y[c], cz = Z[c];
+        kd += (int)dmode;
+        k += (int)!dmode;
+        const float ty = Y[c] - yh;
+        const float tz = Z[c] - zh;
         const uint32_t rr = R[c];
-        if (dmode) {
-            ++kd;
-            const float by = yh - cy;
-            const float bz = zh - cz;
-            const float dy = ay - by;
-            const float dz = az - bz;
-            const float qy = dy * dy;
-            const float qz = dz * dz;
-            const float q = qy + qz;
-            const bool pass = fabsf(by) <= win_y && fabsf(bz) <= win_z && fabsf(dy) <= cut_y &&
-                              fabsf(dz) <= cut_z;
-            const bool tie = q == qb;
-            const bool win = pass && (q < qb || (tie && (ur < ub || (ur == ub && rr < db))));
-            qb = win ? q : qb;
-            ub = win ? ur : ub;
-            db = win ? rr : db;
-        } else {
-            ++k;
-            ay = cy - yh;
-            az = cz - zh;
-            if (fabsf(ay) <= win_y && fabsf(az) <= win_z) {
-                // down clusters around the prediction c = h - (u - h)
-                ur = rr;
-                const float py = yh - ay, pz = zh - az;
-                const float r = TPC_NB_SQRT(qb) * 1.0001f;   // +inf until a triplet passes
-                const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
-                yd = cell_coord(py - ky, gd.y0, gd.iwy, gd.ny);
-                yd1 = cell_coord(py + ky, gd.y0, gd.iwy, gd.ny);
-                zd0 = cell_coord(pz - kz, gd.z0, gd.iwz, gd.nz);
-                zd1 = cell_coord(pz + kz, gd.z0, gd.iwz, gd.nz);
-                kd = DCS[yd * gd.nz + zd0];
-                e1 = DCS[yd * gd.nz + zd1 + 1];
-                dmode = true;
-            }
+        const bool inwin = (fabsf(ty) <= win_y) & (fabsf(tz) <= win_z);
+        const float dy = ay + ty;
+        const float dz = az + tz;
+        const float qy = dy * dy;
+        const float qz = dz * dz;
+        const float q = qy + qz;
+        const uint64_t key = ((uint64_t)__float_as_uint(q) << 32) | (uint64_t)(urs | rr);
+        const bool win = dmode & inwin & (fabsf(dy) <= cut_y) & (fabsf(dz) <= cut_z) & (key < best);
+        best = win ? key : best;
+        if (!dmode && inwin) {
+            // down clusters around the prediction h - (u - h)
+            ay = ty;
+            az = tz;
+            urs = rr << 16;
+            const float r = __builtin_amdgcn_sqrtf(__uint_as_float((uint32_t)(best >> 32))) * 1.0001f;
+            const float py = __builtin_fmaf(-ty, gd.iwy, hy), pz = __builtin_fmaf(-tz, gd.iwz, hz);
+            const float ky = __builtin_fmaf(fminf(cut_y, r) + my, gd.iwy, edy);
+            const float kz = __builtin_fmaf(fminf(cut_z, r) + mz, gd.iwz, edz);
+            yd = cell_in(py - ky, dny);
+            yd1 = cell_in(py + ky, dny);
+            zd0 = cell_in(pz - kz, dnz);
+            zd1 = cell_in(pz + kz, dnz);
+            const int row = __mul24(yd, gd.nz);
+            kd = DCS[row + zd0];
+            e1 = DCS[row + zd1 + 1];
+            dmode = true;
         }
     }
 }
-#else
-template <int ROW, int CELLS>
-__device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy, const float *__restrict__ sz,
-                                   const int32_t *__restrict__ sid, int32_t baseu, int32_t based,
-                                   const SegGrid &gu, const SegGrid &gd, int C0, float win_y, float win_z,
-                                   float cut_y, float cut_z, int32_t *__restrict__ up,
-                                   int32_t *__restrict__ dn, DenseLdsT<ROW, CELLS> &L) {
-#pragma clang fp contract(off)
-    const float *Y = L.y, *Z = L.z;
-    const uint16_t *R = L.rel;
-    const int32_t *UCS = L.cs + C0, *DCS = L.cs;
-    const bool grids = gu.ny > 0 && gd.ny > 0;
-    for (int j = threadIdx.x; j < pn; j += TPC_BLOCK) {
-        const int p = pb + j;
-        const float yh = sy[p], zh = sz[p];
-        float qb = INFINITY;
-        uint32_t ub = 0xFFFFFFFFu, db = 0xFFFFFFFFu;
-        if (grids && isfinite(yh) && isfinite(zh)) {
-            const float my = 1e-5f * (fabsf(yh) + win_y + cut_y) + 1e-6f;
-            const float mz = 1e-5f * (fabsf(zh) + win_z + cut_z) + 1e-6f;
-            const float wuy = win_y + my, wuz = win_z + mz;
-            int iy = cell_coord(yh - wuy, gu.y0, gu.iwy, gu.ny);
-            const int iy1 = cell_coord(yh + wuy, gu.y0, gu.iwy, gu.ny);
-            const int zc0 = cell_coord(zh - wuz, gu.z0, gu.iwz, gu.nz);
-            const int zc1 = cell_coord(zh + wuz, gu.z0, gu.iwz, gu.nz);
-            for (; iy <= iy1; ++iy) {
-                const int k1 = UCS[iy * gu.nz + zc1 + 1];
-                for (int k = UCS[iy * gu.nz + zc0]; k < k1; ++k) {
-                    const float ay = Y[k] - yh;
-                    const float az = Z[k] - zh;
-                    if (!(fabsf(ay) <= win_y && fabsf(az) <= win_z)) continue;
-                    // down clusters around the prediction c = h - (u - h)
-                    const float cy = yh - ay, cz = zh - az;
-                    const float r = sqrtf(qb) * 1.0001f;           // +inf until a triplet passes
-                    const float ky = fminf(cut_y, r) + my, kz = fminf(cut_z, r) + mz;
-                    const uint32_t ur = R[k];
-                    int yd = cell_coord(cy - ky, gd.y0, gd.iwy, gd.ny);
-                    const int yd1 = cell_coord(cy + ky, gd.y0, gd.iwy, gd.ny);
-                    const int zd0 = cell_coord(cz - kz, gd.z0, gd.iwz, gd.nz);
-                    const int zd1 = cell_coord(cz + kz, gd.z0, gd.iwz, gd.nz);
-                    for (; yd <= yd1; ++yd) {
-                        const int e1 = DCS[yd * gd.nz + zd1 + 1];
-                        for (int kd = DCS[yd * gd.nz + zd0]; kd < e1; ++kd) {
-                            const float by = yh - Y[kd];
-                            const float bz = zh - Z[kd];
-                            const float dy = ay - by;
-                            const float dz = az - bz;
-                            const float qy = dy * dy;
-                            const float qz = dz * dz;
-                            const float q = qy + qz;
-                            const uint32_t dr = R[kd];
-                            const bool pass = fabsf(by) <= win_y && fabsf(bz) <= win_z && fabsf(dy) <= cut_y &&
-                                              fabsf(dz) <= cut_z;
-                            const bool tie = q == qb;
-                            const bool win = pass && (q < qb || (tie && (ur < ub || (ur == ub && dr < db))));
-                            qb = win ? q : qb;
-                            ub = win ? ur : ub;
-                            db = win ? dr : db;
-                        }
-                    }
-                }
-            }
-        }
-        const int32_t h = sid[p];
-        const bool found = ub != 0xFFFFFFFFu;
-        up[h] = found ? baseu + (int32_t)ub : -1;
-        dn[h] = found ? based + (int32_t)db : -1;
-    }
-}
-
-#endif
 
 // Dense h-row `seg` (whole workgroup; contains barriers): slabs of
 // consecutive clusters of its z-sorted copy.  A partner of h passes the
