@@ -782,14 +782,16 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
         const float ty = Y[c] - yh;
         const float tz = Z[c] - zh;
         const uint32_t rr = R[c];
-        const bool inwin = (fabsf(ty) <= win_y) & (fabsf(tz) <= win_z);
+        // bitwise, not short-circuit, conjunctions: no branches in the test
+        const bool inwin = (int)(fabsf(ty) <= win_y) & (int)(fabsf(tz) <= win_z);
         const float dy = ay + ty;
         const float dz = az + tz;
         const float qy = dy * dy;
         const float qz = dz * dz;
         const float q = qy + qz;
         const uint64_t key = ((uint64_t)__float_as_uint(q) << 32) | (uint64_t)(urs | rr);
-        const bool win = dmode & inwin & (fabsf(dy) <= cut_y) & (fabsf(dz) <= cut_z) & (key < best);
+        const bool win = (int)dmode & (int)inwin & (int)(fabsf(dy) <= cut_y) & (int)(fabsf(dz) <= cut_z) &
+                         (int)(key < best);
         best = win ? key : best;
         if (!dmode && inwin) {
             // down clusters around the prediction h - (u - h)
