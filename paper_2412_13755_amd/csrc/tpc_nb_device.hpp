@@ -631,9 +631,13 @@ enum NbClass { NB_NOT_DENSE = 0, NB_SMALL = 1, NB_LARGE = 2, NB_DENSE = 3 };
 #ifndef TPC_NB_DENSE_EDGE_U
 #define TPC_NB_DENSE_EDGE_U 0.25f
 #endif
-// LDS of a dense-row workgroup: the slab's row pair.
+// LDS of a dense-row workgroup: the slab's row pair and the slab's results
+// (up id << 16 | down id relative to their rows, all ones for none), which
+// are written out once the slab is searched.
 template <int ROW, int CELLS>
-using DenseLdsT = PairLdsT<ROW, CELLS>;
+struct DenseLdsT : PairLdsT<ROW, CELLS> {
+    uint32_t res[TPC_NB_SLAB];
+};
 using DenseLds = DenseLdsT<TPC_NB_DENSE_ROW, TPC_NB_DENSE_CELLS>;
 
 // Positions [x, y) of the z-sorted copy of a row (grid g, cell starts cs)
@@ -708,11 +712,9 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
     bool active = false, dmode = false;
     float yh = 0.f, zh = 0.f, hy = 0.f, hz = 0.f, my = 0.f, mz = 0.f, ay = 0.f, az = 0.f;
     float yn = 0.f, zn = 0.f;
-    int32_t idn = 0, hid = 0;
     if ((int)threadIdx.x < pn) {
         yn = sy[pb + threadIdx.x];
         zn = sz[pb + threadIdx.x];
-        idn = sid[pb + threadIdx.x];
     }
     uint64_t best = NONE;
     uint32_t urs = 0;
@@ -724,11 +726,9 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
             if (j < pn) {
                 yh = yn;
                 zh = zn;
-                hid = idn;
                 if (j + TPC_BLOCK < pn) {
                     yn = sy[pb + j + TPC_BLOCK];
                     zn = sz[pb + j + TPC_BLOCK];
-                    idn = sid[pb + j + TPC_BLOCK];
                 }
                 best = NONE;
                 dmode = false;
@@ -769,9 +769,7 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
                 k1 = UCS[iy * gu.nz + zc1 + 1];
             }
             if (k == k1) {                            // cluster done
-                const bool found = best != NONE;
-                up[hid] = found ? baseu + (int32_t)((uint32_t)best >> 16) : -1;
-                dn[hid] = found ? based + (int32_t)((uint32_t)best & 0xFFFFu) : -1;
+                L.res[j] = best != NONE ? (uint32_t)best : 0xFFFFFFFFu;
                 active = false;
                 continue;
             }
@@ -812,6 +810,16 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
             dmode = true;
         }
     }
+    // results in the slab's order (ids read coalesced; the search loop
+    // issues no global store, whose completion its waits for the next
+    // cluster's loads would also wait for)
+    __syncthreads();
+    for (int p = threadIdx.x; p < pn; p += TPC_BLOCK) {
+        const uint32_t r = L.res[p];
+        const int32_t h = sid[pb + p];
+        up[h] = r == 0xFFFFFFFFu ? -1 : baseu + (int32_t)(r >> 16);
+        dn[h] = r == 0xFFFFFFFFu ? -1 : based + (int32_t)(r & 0xFFFFu);
+    }
 }
 
 // Dense h-row `seg` (whole workgroup; contains barriers): slabs of
@@ -840,8 +848,9 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
     const SegGrid gdg = grid[sd], gug = grid[su];
     const int32_t *csd = cstart + based + sd;
     const int32_t *csu = cstart + baseu + su;
-    // relative ids are 16-bit in the keys and in LDS
-    const bool rel_ok = seg_size(off, sd) <= 65536 && seg_size(off, su) <= 65536;
+    // relative ids are 16-bit in the keys and in LDS (at most 65534, so a
+    // result is never all ones)
+    const bool rel_ok = seg_size(off, sd) <= 65535 && seg_size(off, su) <= 65535;
     int P = TPC_NB_SLAB;
     for (int p0 = 0; p0 < n;) {
         const int pn = n - p0 < P ? n - p0 : P;

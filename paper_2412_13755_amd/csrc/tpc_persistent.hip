@@ -141,10 +141,13 @@ persist_reco(PersistArgs P) {
         tpc_nb::DenseLds dense;
         tpc_nb::BinLds bin;
         uint32_t caw[TPC_CA_CAP];
+        struct {
+            int hist[TPC_MAX_ROWS + 1], base[TPC_MAX_ROWS + 1];
+        } len;                           // seed lengths (placement and fit order)
     } U;
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
     __shared__ int bc[2];
-    __shared__ int lhist[TPC_MAX_ROWS + 1], lbase[TPC_MAX_ROWS + 1];
+    int *lhist = U.len.hist, *lbase = U.len.base;
     const int G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
 
     // work lists of the binning and the dense query (order within a list is

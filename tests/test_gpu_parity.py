@@ -282,6 +282,29 @@ def test_dense_rows_every_neighbour_and_ranking_form(torch_dev):
     check_all(fr, "dense rows (48 rows, 2 frames)")
 
 
+def test_sixteen_bit_row_ids(torch_dev):
+    """Rows at the width of the dense search's relative ids (16 bits, the
+    all-ones pattern reserved for no partner): an h-row between two rows of
+    65 535 clusters is searched in LDS slabs with ids up to 65 534, one next
+    to a row of 65 536 clusters in the global copies.  Clusters uniform over
+    the rows (6.5 per cm^2), every link and seed exact."""
+    from tpcsynth.generator import Frames, make_row_x
+    rng = np.random.default_rng(65535)
+    sizes = np.array([65535, 3000, 65535, 3000, 65536])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    y = rng.uniform(-20.0, 20.0, off[-1]).astype(np.float32)
+    z = rng.uniform(0.0, 250.0, off[-1]).astype(np.float32)
+    fr = Frames(1, 1, 5, make_row_x(5), off, y, z)
+    gu, gd, _, _ = run_gpu(fr)
+    ru, rd = oracle.neighbours(fr.row_offsets, fr.y, fr.z, fr.n_rows, **NB)
+    np.testing.assert_array_equal(gu, ru, err_msg="up links differ")
+    np.testing.assert_array_equal(gd, rd, err_msg="down links differ")
+    # partners with the largest ids of the 65 535-cluster rows are found
+    linked = rd[off[1]:off[2]]
+    assert (linked >= 0).mean() > 0.9 and linked.max() >= off[0] + 65000
+    assert (gu[off[3]:off[4]] >= off[4]).any()
+
+
 def test_non_uniform_row_pitch_refused(torch_dev):
     """The neighbour predicate's second difference assumes equally spaced
     pad-row planes: a pitch more than 1e-3 off the mean is refused, float32
