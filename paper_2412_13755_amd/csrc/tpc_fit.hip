@@ -119,17 +119,29 @@ __global__ void fit_order_clear(int32_t *__restrict__ hist, int32_t *__restrict_
     }
 }
 
-// Bin starts in descending length order, and the number of seeds.
-__global__ void fit_order_starts(int32_t *__restrict__ hist, int32_t *__restrict__ n_order) {
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int len = TPC_MAX_ROWS; len >= 0; --len) {
-            const int c = hist[len];
-            hist[len] = run;
-            run += c;
-        }
-        *n_order = run;
+// Bin starts in descending length order, and the number of seeds (one
+// wavefront: lane l takes the bins TPC_MAX_ROWS - 5l down to
+// TPC_MAX_ROWS - 5l - 4, then a wave scan of the lanes' sums).
+__global__ void __launch_bounds__(TPC_WAVE)
+fit_order_starts(int32_t *__restrict__ hist, int32_t *__restrict__ n_order) {
+    static_assert(5 * TPC_WAVE > TPC_MAX_ROWS, "five bins per lane cover every length");
+    const int l = threadIdx.x;
+    int c[5], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int len = TPC_MAX_ROWS - 5 * l - q;
+        c[q] = len >= 0 ? hist[len] : 0;
+        sum += c[q];
     }
+    const int inc = wave_inclusive_scan(sum);
+    int run = inc - sum;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int len = TPC_MAX_ROWS - 5 * l - q;
+        if (len >= 0) hist[len] = run;
+        run += c[q];
+    }
+    if (l == TPC_WAVE - 1) *n_order = inc;
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)
@@ -164,7 +176,7 @@ static void launch_fit_order(FitArgs &A, const FitOrderWs &ord, hipStream_t st) 
     hipLaunchKernelGGL(fit_order_clear, dim3(1), dim3(TPC_BLOCK), 0, st, ord.hist, ord.cur);
     hipLaunchKernelGGL(fit_order_count, dim3(blocks), dim3(TPC_BLOCK), 0, st, A.n_seeds, A.cap_seeds, A.offsets,
                        ord.hist, ord.cur);
-    hipLaunchKernelGGL(fit_order_starts, dim3(1), dim3(64), 0, st, ord.hist, ord.n);
+    hipLaunchKernelGGL(fit_order_starts, dim3(1), dim3(TPC_WAVE), 0, st, ord.hist, ord.n);
     hipLaunchKernelGGL(fit_order_place, dim3(blocks), dim3(TPC_BLOCK), 0, st, A.n_seeds, A.cap_seeds, A.offsets,
                        ord.hist, ord.cur, ord.order);
     A.order = ord.order;
