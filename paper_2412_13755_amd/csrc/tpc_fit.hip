@@ -119,29 +119,10 @@ __global__ void fit_order_clear(int32_t *__restrict__ hist, int32_t *__restrict_
     }
 }
 
-// Bin starts in descending length order, and the number of seeds (one
-// wavefront: lane l takes the bins TPC_MAX_ROWS - 5l down to
-// TPC_MAX_ROWS - 5l - 4, then a wave scan of the lanes' sums).
+// Bin starts in descending length order, and the number of seeds.
 __global__ void __launch_bounds__(TPC_WAVE)
 fit_order_starts(int32_t *__restrict__ hist, int32_t *__restrict__ n_order) {
-    static_assert(5 * TPC_WAVE > TPC_MAX_ROWS, "five bins per lane cover every length");
-    const int l = threadIdx.x;
-    int c[5], sum = 0;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const int len = TPC_MAX_ROWS - 5 * l - q;
-        c[q] = len >= 0 ? hist[len] : 0;
-        sum += c[q];
-    }
-    const int inc = wave_inclusive_scan(sum);
-    int run = inc - sum;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const int len = TPC_MAX_ROWS - 5 * l - q;
-        if (len >= 0) hist[len] = run;
-        run += c[q];
-    }
-    if (l == TPC_WAVE - 1) *n_order = inc;
+    len_starts_wave(hist, n_order);
 }
 
 __global__ void __launch_bounds__(TPC_BLOCK)

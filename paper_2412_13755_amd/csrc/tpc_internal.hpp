@@ -169,6 +169,31 @@ __device__ inline int wave_inclusive_scan(int v) {
     return v;
 }
 
+// Seed-length bins hist[0 .. TPC_MAX_ROWS] -> their starts in descending
+// length order, and the number of seeds into *total (one whole wavefront:
+// lane l takes the bins TPC_MAX_ROWS - 5l down to TPC_MAX_ROWS - 5l - 4,
+// then a wave scan of the lanes' sums).
+__device__ inline void len_starts_wave(int32_t *hist, int32_t *total) {
+    static_assert(5 * TPC_WAVE > TPC_MAX_ROWS, "five bins per lane cover every length");
+    const int l = threadIdx.x & (TPC_WAVE - 1);
+    int c[5], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int len = TPC_MAX_ROWS - 5 * l - q;
+        c[q] = len >= 0 ? hist[len] : 0;
+        sum += c[q];
+    }
+    const int inc = wave_inclusive_scan(sum);
+    int run = inc - sum;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int len = TPC_MAX_ROWS - 5 * l - q;
+        if (len >= 0) hist[len] = run;
+        run += c[q];
+    }
+    if (l == TPC_WAVE - 1) *total = inc;
+}
+
 // Exclusive scan over the TPC_BLOCK threads of a workgroup; returns the prefix
 // of this thread and writes the block total to *total.  `sh` holds
 // TPC_BLOCK / TPC_WAVE ints of LDS.  Contains barriers: call from every thread.

@@ -262,16 +262,8 @@ persist_reco(PersistArgs P) {
     for (int h = bid * TPC_BLOCK + tid; h < P.N; h += G * TPC_BLOCK)
         tpc_ca::ca_members_one(h, P.N, P.y, P.z, P.sd.cap_hits, P.sd, P.ca);
     if (bid == 0 && P.sort_fit) {
-        // bin starts in descending length order
-        if (tid == 0) {
-            int run = 0;
-            for (int len = TPC_MAX_ROWS; len >= 0; --len) {
-                const int c = P.len_hist[len];
-                P.len_hist[len] = run;
-                run += c;
-            }
-            *P.n_placed = run;
-        }
+        // bin starts in descending length order (the first wavefront)
+        if (tid < TPC_WAVE) len_starts_wave(P.len_hist, P.n_placed);
     }
     if (!grid_sync(P)) return;
     {
