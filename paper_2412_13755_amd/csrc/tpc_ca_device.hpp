@@ -12,19 +12,20 @@
 // order), so it matches the sequential definition exactly.
 //
 //   ca_block   per (frame, sector, block of TPC_CA_ROWS rows): kept links
-//              of every cluster (resetting its claim, length and membership
-//              slots), then pointer jumping in LDS to the lowest chain member
-//              inside the block and the distance to it (pack)
-//   ca_tops    every chain member follows the block-local lowest members
-//              down across block edges to the chain bottom (at most one hop
-//              per block) and gets its bottom and position; each chain's top
-//              records its length and claims the chain's unlinked ends
-//              (>= min_hits-2 clusters)
+//              of every cluster (resetting its claim and length slots), then
+//              pointer jumping in LDS to the lowest chain member inside the
+//              block and the distance to it (pack)
+//   ca_tops    chain tops and block-local lowest members follow the lowest
+//              members down across block edges to the chain bottom (at most
+//              one hop per block); a lowest member records its bottom and
+//              position, each chain's top records its length and claims the
+//              chain's unlinked ends (>= min_hits-2 clusters)
 //   ca_firsts  each seed is recognised at its first cluster (the won bottom
 //              end or the bottom itself); per-segment seed and hit counts
 //   ca_scan    exclusive prefix over segments, totals, capacity check
 //   ca_place   seed records, end clusters, core offsets
-//   ca_members every chain member writes itself into its seed
+//   ca_members every chain member writes itself into its seed (bottom and
+//              position from its block's lowest member)
 #include "tpc_internal.hpp"
 
 namespace tpc_ca {
@@ -71,8 +72,8 @@ __device__ inline int32_t pack_dist(unsigned long long w) { return (int32_t)((w 
 __device__ inline bool pack_linked(unsigned long long w) { return (w & (TPC_CA_UP | TPC_CA_DN)) != 0; }
 
 // Step 1, block `item` of (frame, sector, row block): the kept links of
-// every cluster (its slots for claims, chain length and membership are
-// reset on the way), then in-place pointer jumping to the lowest chain
+// every cluster (its slots for claims and chain length are reset on the
+// way), then in-place pointer jumping to the lowest chain
 // member inside the block (a word always holds a valid (node, distance)
 // pair, so reading a neighbour's word before or after its update in the
 // same round is equally correct, and every round at least doubles the span
@@ -112,7 +113,6 @@ __device__ inline void ca_block_item(int item, int32_t N, int32_t n_rows, const 
             const bool hd = bd[j] == h, hu = bu[j] == h;
             ws.claim[h] = ~0ull;
             ws.cc[h] = make_int2(0, -1);
-            ws.memb[h] = -1;                          // set by ca_tops for chain members
             ws.dlk[h] = hd ? d[j] : -1;
             const bool in = hd && d[j] >= lo && d[j] < hi && d[j] != h;
             if (lds) {
@@ -267,7 +267,6 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
             ww[j] = (hd ? TPC_CA_W_DN : 0u) | (hu ? TPC_CA_W_UP : 0u) | bot | (dist << 24) | low;
             ws.claim[h] = ~0ull;
             ws.cc[h] = make_int2(0, -1);
-            ws.memb[h] = -1;                          // set by ca_tops for chain members
             ws.dlk[h] = hd ? d : -1;
         }
         __syncthreads();
@@ -310,17 +309,23 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
     __syncthreads();                 // LDS reuse by the workgroup's next block
 }
 
-// Step 2: every linked cluster follows the block-local lowest members down
-// across block edges (a lowest member whose kept link leaves the block
-// continues below it) to the chain bottom; then the top of each chain
-// records the chain length and top at the bottom and claims the chain's
-// unlinked end clusters (chains of >= min_hits - 2 clusters).
+// Step 2: the chain tops and the block-local lowest members that are not
+// their chain's bottom follow the block-local lowest members down across
+// block edges (a lowest member whose kept link leaves the block continues
+// below it) to the chain bottom; a lowest member records its bottom and
+// position (every member of its block segment adds its distance to it), and
+// the top of each chain records the chain length and top at the bottom and
+// claims the chain's unlinked end clusters (chains of >= min_hits - 2
+// clusters).  Other members have nothing to do here.
 __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restrict__ up,
                                    const int32_t *__restrict__ dn, int32_t min_hits, int32_t n_rows,
                                    const CaWs &ws) {
     {
         const unsigned long long w0 = ws.pack[h];
         if (!pack_linked(w0)) return;
+        const bool top = !(w0 & TPC_CA_UP);
+        const bool lowest = pack_node(w0) == h && !(w0 & TPC_CA_BOT);
+        if (!top && !lowest) return;
         int32_t bot = pack_node(w0);
         int32_t pos = pack_dist(w0);
         for (int it = 0; it < n_rows && !(w0 & TPC_CA_BOT); ++it) {   // bound: one hop per block
@@ -330,9 +335,8 @@ __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restri
             pos += 1 + pack_dist(w);
             bot = pack_node(w);
         }
-        ws.memb[h] = bot;
-        ws.mpos[h] = pos;
-        if (!(w0 & TPC_CA_UP) && valid_id(bot, N)) {  // h is the top: chain of pos + 1 clusters
+        if (lowest) ws.mrec[h] = make_int2(bot, pos);
+        if (top && valid_id(bot, N)) {                // chain of pos + 1 clusters
             const int32_t m = pos + 1;
             ws.cc[bot] = make_int2(m, -1);
             ws.ctop[bot] = h;
@@ -525,14 +529,25 @@ __device__ inline void ca_place_wave(int seg, int32_t N, const int32_t *__restri
     }
 }
 
+// Every chain member writes itself into its seed: its chain's bottom and
+// its position from it come from its block-local lowest member (the bottom
+// itself, or the record ca_tops left there) and its distance to that member.
 __device__ inline void ca_members_one(int32_t h, int32_t N, const float *__restrict__ y,
                                       const float *__restrict__ z, int32_t cap_hits, const tpc_seeds &sd,
                                       const CaWs &ws) {
     {
-        const int32_t bb = ws.memb[h];                // -1 unless h is in a chain
+        const unsigned long long w = ws.pack[h];
+        if (!pack_linked(w)) return;
+        int32_t bb = pack_node(w), k = pack_dist(w);
+        if (!(w & TPC_CA_BOT)) {
+            if (!valid_id(bb, N)) return;
+            const int2 r = ws.mrec[bb];
+            bb = r.x;
+            k += r.y;
+        }
         if (!valid_id(bb, N)) return;
         const int2 c = ws.cc[bb];                    // (chain length, core offset)
-        const int32_t o = c.y, k = ws.mpos[h];
+        const int32_t o = c.y;
         if (o >= 0 && k >= 0 && k < c.x && o + k < cap_hits) {
             sd.hits[o + k] = h;
             if (sd.hit_yz) put_yz(sd.hit_yz, o + k, y[h], z[h]);

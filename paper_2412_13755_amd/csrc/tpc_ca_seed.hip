@@ -191,8 +191,7 @@ size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out) {
     l.dlk = w.take<int32_t>(N);
     l.cc = w.take<int2>(N);
     l.ctop = w.take<int32_t>(N);
-    l.memb = w.take<int32_t>(N);
-    l.mpos = w.take<int32_t>(N);
+    l.mrec = w.take<int2>(N);
     l.fbot = w.take<int32_t>(N);
     l.flen = w.take<int32_t>(N);
     l.segcnt = w.take<int32_t>(NR);

@@ -59,8 +59,8 @@ struct CaWs {
     int2 *cc;                    // [N] at a bottom: (chain length, hit offset of the chain core or
                                  // -1 if no seed), read together; (0, -1) elsewhere
     int32_t *ctop;               // [N] chain top at a bottom
-    int32_t *memb;               // [N] bottom of the chain a linked cluster is in
-    int32_t *mpos;               // [N] its position in that chain
+    int2 *mrec;                  // [N] at a block-local lowest member that is not its chain's
+                                 // bottom: (chain bottom, position from it)
     int32_t *fbot;               // [N] at a seed's first cluster: the chain bottom, else -1
     int32_t *flen;               // [N] at a seed's first cluster: seed length
     int32_t *segcnt, *seghits;   // [NR] seeds / seed hits starting in the segment
