@@ -321,6 +321,7 @@ __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restri
                                    const int32_t *__restrict__ dn, int32_t min_hits, int32_t n_rows,
                                    const CaWs &ws) {
     {
+        ws.fbot[h] = -1;                          // set by ca_firsts at a seed's first cluster
         const unsigned long long w0 = ws.pack[h];
         if (!pack_linked(w0)) return;
         const bool top = !(w0 & TPC_CA_UP);
@@ -354,6 +355,10 @@ __device__ inline void ca_tops_seg(int seg, int32_t N, const int32_t *__restrict
                                    const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
                                    int32_t min_hits, int32_t n_rows, const CaWs &ws) {
     const int a = off[seg], b = off[seg + 1];
+    if (threadIdx.x == 0) {                       // counted into by ca_firsts
+        ws.segcnt[seg] = 0;
+        ws.seghits[seg] = 0;
+    }
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) ca_tops_one(h, N, up, dn, min_hits, n_rows, ws);
 }
 
@@ -373,48 +378,81 @@ __device__ inline int32_t seed_len(const int32_t *up, const int32_t *dn, int32_t
     return len >= min_hits ? len : 0;
 }
 
-// Seed recognised at cluster h: the chain bottom it starts from and the seed
-// length, fb = -1 if none (h is the first cluster of at most one seed).
-__device__ inline void ca_first_one(int32_t h, int32_t N, const int32_t *__restrict__ up,
-                                    const int32_t *__restrict__ dn, int32_t min_hits, const CaWs &ws,
-                                    int32_t &fb, int32_t &len) {
-    fb = -1;
+// Seed of the chain with bottom h, recognised there: its first cluster (h,
+// or the bottom end below h if h's chain won it) gets the bottom and the
+// seed length (fbot, flen; fbot is -1 at every other cluster, from
+// ca_tops); returns that first cluster, or -1 if the chain is no seed.  A
+// first cluster belongs to one seed at most: a won end has one winner.
+__device__ inline int32_t ca_first_one(int32_t h, int32_t N, const int32_t *__restrict__ up,
+                                       const int32_t *__restrict__ dn, int32_t min_hits, const CaWs &ws,
+                                       int32_t &len) {
     len = 0;
-    if (ws.cc[h].x >= 2) {                       // h is a bottom
-        int32_t wb;
-        int32_t l = seed_len(up, dn, N, min_hits, ws, h, &wb);
-        if (l > 0 && !wb) { fb = h; len = l; }
-    } else if (ws.claim[h] != ~0ull) {           // h is a claimed end
-        int32_t bb = (int32_t)(ws.claim[h] & 0xffffffffull);
-        if (valid_id(bb, N) && dn[bb] == h) {    // claimed as the bottom end of bb
-            int32_t wb;
-            int32_t l = seed_len(up, dn, N, min_hits, ws, bb, &wb);
-            if (l > 0) { fb = bb; len = l; }
-        }
-    }
-    ws.fbot[h] = fb;
-    ws.flen[h] = len;
+    if (ws.cc[h].x < 2) return -1;               // h is no chain bottom
+    int32_t wb;
+    const int32_t l = seed_len(up, dn, N, min_hits, ws, h, &wb);
+    if (l == 0) return -1;
+    const int32_t first = wb ? dn[h] : h;        // a won end is a valid id
+    ws.fbot[first] = h;
+    ws.flen[first] = l;
+    len = l;
+    return first;
 }
 
-// Contains barriers: call from the whole workgroup.
+// Rows down from segment seg to the segment of cluster e (a chain bottom's
+// bottom end lies one or two rows down in the same frame and sector), 0 for
+// e in seg itself; at most TPC_CA_BELOW.
+#define TPC_CA_BELOW 2
+__device__ inline int rows_below(const int32_t *__restrict__ off, int seg, int32_t e) {
+    int d = 0;
+    while (d < TPC_CA_BELOW && seg - d > 0 && e < off[seg - d]) ++d;
+    return d;
+}
+
+// Seeds recognised at the bottoms of segment seg, counted (seeds and hits)
+// into the segments of their first clusters: seg itself or up to
+// TPC_CA_BELOW rows down (ca_tops zeroed the counts).  Contains barriers:
+// call from the whole workgroup.
 __device__ inline void ca_firsts_seg(int seg, int32_t N, const int32_t *__restrict__ off,
                                      const int32_t *__restrict__ up, const int32_t *__restrict__ dn,
                                      int32_t min_hits, const CaWs &ws) {
-    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    __shared__ int acc[2 * (TPC_CA_BELOW + 1)];
+    if (threadIdx.x < 2 * (TPC_CA_BELOW + 1)) acc[threadIdx.x] = 0;
+    __syncthreads();
     const int a = off[seg], b = off[seg + 1];
-    int cnt = 0, hits = 0;
+    int cnt[TPC_CA_BELOW + 1] = {}, hits[TPC_CA_BELOW + 1] = {};
     for (int h = a + threadIdx.x; h < b; h += TPC_BLOCK) {
-        int32_t fb, len;
-        ca_first_one(h, N, up, dn, min_hits, ws, fb, len);
-        cnt += fb >= 0;
-        hits += len;
+        int32_t len;
+        const int32_t f = ca_first_one(h, N, up, dn, min_hits, ws, len);
+        if (f >= 0) {
+            const int d = f == h ? 0 : rows_below(off, seg, f);
+#pragma unroll
+            for (int q = 0; q <= TPC_CA_BELOW; ++q) {
+                cnt[q] += d == q;
+                hits[q] += d == q ? len : 0;
+            }
+        }
     }
-    int tc, th;
-    block_exclusive_scan(cnt, sh, &tc);
-    block_exclusive_scan(hits, sh, &th);
-    if (threadIdx.x == 0) {
-        ws.segcnt[seg] = tc;
-        ws.seghits[seg] = th;
+#pragma unroll
+    for (int q = 0; q <= TPC_CA_BELOW; ++q) {
+#pragma unroll
+        for (int x = TPC_WAVE / 2; x > 0; x >>= 1) {
+            cnt[q] += __shfl_xor(cnt[q], x, TPC_WAVE);
+            hits[q] += __shfl_xor(hits[q], x, TPC_WAVE);
+        }
+    }
+    if ((threadIdx.x & (TPC_WAVE - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q <= TPC_CA_BELOW; ++q) {
+            if (cnt[q]) {
+                atomicAdd(&acc[2 * q], cnt[q]);
+                atomicAdd(&acc[2 * q + 1], hits[q]);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= TPC_CA_BELOW && seg - (int)threadIdx.x >= 0 && acc[2 * threadIdx.x]) {
+        atomicAdd(&ws.segcnt[seg - threadIdx.x], acc[2 * threadIdx.x]);
+        atomicAdd(&ws.seghits[seg - threadIdx.x], acc[2 * threadIdx.x + 1]);
     }
 }
 
@@ -425,21 +463,38 @@ __device__ inline void ca_firsts_wave(int seg, int32_t N, const int32_t *__restr
                                       int32_t min_hits, const CaWs &ws) {
     const int lane = threadIdx.x & (TPC_WAVE - 1);
     const int a = off[seg], b = off[seg + 1];
-    int cnt = 0, hits = 0;
+    int cnt[TPC_CA_BELOW + 1] = {}, hits[TPC_CA_BELOW + 1] = {};
     for (int h = a + lane; h < b; h += TPC_WAVE) {
-        int32_t fb, len;
-        ca_first_one(h, N, up, dn, min_hits, ws, fb, len);
-        cnt += fb >= 0;
-        hits += len;
+        int32_t len;
+        const int32_t f = ca_first_one(h, N, up, dn, min_hits, ws, len);
+        if (f >= 0) {
+            const int d = f == h ? 0 : rows_below(off, seg, f);
+#pragma unroll
+            for (int q = 0; q <= TPC_CA_BELOW; ++q) {
+                cnt[q] += d == q;
+                hits[q] += d == q ? len : 0;
+            }
+        }
     }
 #pragma unroll
-    for (int d = TPC_WAVE / 2; d > 0; d >>= 1) {
-        cnt += __shfl_xor(cnt, d, TPC_WAVE);
-        hits += __shfl_xor(hits, d, TPC_WAVE);
+    for (int q = 0; q <= TPC_CA_BELOW; ++q) {
+#pragma unroll
+        for (int x = TPC_WAVE / 2; x > 0; x >>= 1) {
+            cnt[q] += __shfl_xor(cnt[q], x, TPC_WAVE);
+            hits[q] += __shfl_xor(hits[q], x, TPC_WAVE);
+        }
     }
-    if (lane == 0) {
-        ws.segcnt[seg] = cnt;
-        ws.seghits[seg] = hits;
+    if (lane <= TPC_CA_BELOW && seg - lane >= 0) {
+        int c = 0, hh = 0;
+#pragma unroll
+        for (int q = 0; q <= TPC_CA_BELOW; ++q) {
+            c = lane == q ? cnt[q] : c;
+            hh = lane == q ? hits[q] : hh;
+        }
+        if (c) {
+            atomicAdd(&ws.segcnt[seg - lane], c);
+            atomicAdd(&ws.seghits[seg - lane], hh);
+        }
     }
 }
 
@@ -490,7 +545,8 @@ __device__ inline void ca_place_seg(int seg, int32_t N, const int32_t *__restric
     for (int base = a; base < b; base += TPC_BLOCK) {
         const int h = base + threadIdx.x;
         int32_t fb = -1, len = 0;
-        if (h < b) { fb = ws.fbot[h]; len = ws.flen[h]; }
+        if (h < b) fb = ws.fbot[h];
+        if (fb >= 0) len = ws.flen[h];
         int tc, th;
         int pc = block_exclusive_scan(fb >= 0 ? 1 : 0, sh, &tc);
         int ph = block_exclusive_scan(len, sh, &th);
@@ -518,7 +574,8 @@ __device__ inline void ca_place_wave(int seg, int32_t N, const int32_t *__restri
     for (int base = a; base < b; base += TPC_WAVE) {
         const int h = base + lane;
         int32_t fb = -1, len = 0;
-        if (h < b) { fb = ws.fbot[h]; len = ws.flen[h]; }
+        if (h < b) fb = ws.fbot[h];
+        if (fb >= 0) len = ws.flen[h];
         const int f = fb >= 0 ? 1 : 0;
         const int ic = wave_inclusive_scan(f), ih = wave_inclusive_scan(len);
         if (fb >= 0)

@@ -180,6 +180,10 @@ persist_reco(PersistArgs P) {
     if (!grid_sync(P)) return;
     for (int h = bid * TPC_BLOCK + tid; h < P.N; h += G * TPC_BLOCK)
         tpc_ca::ca_tops_one(h, P.N, P.up, P.dn, P.min_hits, P.n_rows, P.ca);
+    for (int s = bid * TPC_BLOCK + tid; s < P.NR; s += G * TPC_BLOCK) {   // counted into by the next phase
+        P.ca.segcnt[s] = 0;
+        P.ca.seghits[s] = 0;
+    }
     if (!grid_sync(P)) return;
     // a segment per wavefront (a workgroup's four wavefronts take four)
     for (int seg = bid * (TPC_BLOCK / TPC_WAVE) + tid / TPC_WAVE; seg < P.NR; seg += G * (TPC_BLOCK / TPC_WAVE))
