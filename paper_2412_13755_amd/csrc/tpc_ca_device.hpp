@@ -314,8 +314,9 @@ __device__ inline void ca_sweep_item(int item, int32_t N, int32_t n_rows, const 
 // block edges (a lowest member whose kept link leaves the block continues
 // below it) to the chain bottom; a lowest member records its bottom and
 // position (every member of its block segment adds its distance to it), and
-// the top of each chain records the chain length and top at the bottom and
-// claims the chain's unlinked end clusters (chains of >= min_hits - 2
+// the top of each chain records the chain length and the cluster above the
+// top (the top end candidate) at the bottom and claims the chain's unlinked
+// end clusters (chains of >= min_hits - 2
 // clusters).  Other members have nothing to do here.
 __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restrict__ up,
                                    const int32_t *__restrict__ dn, int32_t min_hits, int32_t n_rows,
@@ -339,11 +340,12 @@ __device__ inline void ca_tops_one(int32_t h, int32_t N, const int32_t *__restri
         if (lowest) ws.mrec[h] = make_int2(bot, pos);
         if (top && valid_id(bot, N)) {                // chain of pos + 1 clusters
             const int32_t m = pos + 1;
+            const int32_t et = up[h];
             ws.cc[bot] = make_int2(m, -1);
-            ws.ctop[bot] = h;
+            ws.cend[bot] = et;
             if (m >= min_hits - 2) {
                 const unsigned long long key = claim_key(m, bot);
-                const int32_t eb = dn[bot], et = up[h];
+                const int32_t eb = dn[bot];
                 if (valid_id(eb, N) && !pack_linked(ws.pack[eb])) atomicMin(&ws.claim[eb], key);
                 if (valid_id(et, N) && !pack_linked(ws.pack[et])) atomicMin(&ws.claim[et], key);
             }
@@ -369,7 +371,7 @@ __device__ inline int32_t seed_len(const int32_t *up, const int32_t *dn, int32_t
     int32_t wb = 0, wt = 0;
     if (m >= min_hits - 2) {
         unsigned long long key = claim_key(m, bb);
-        int32_t eb = dn[bb], et = up[ws.ctop[bb]];
+        int32_t eb = dn[bb], et = ws.cend[bb];
         wb = (valid_id(eb, N) && ws.claim[eb] == key);
         wt = (valid_id(et, N) && ws.claim[et] == key);
     }
@@ -519,7 +521,7 @@ __device__ inline void ca_place_one(int32_t h, int32_t fb, int32_t len, int i, i
         }
         const int32_t m = ws.cc[fb].x;
         if (len > m + wb) {
-            const int32_t et = up[ws.ctop[fb]];
+            const int32_t et = ws.cend[fb];
             sd.hits[o + len - 1] = et;
             if (sd.hit_yz && valid_id(et, N)) put_yz(sd.hit_yz, o + len - 1, y[et], z[et]);
         }

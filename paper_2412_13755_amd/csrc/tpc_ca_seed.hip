@@ -190,7 +190,7 @@ size_t ca_ws_layout(void *ws, int64_t N, int64_t NR, CaWs *out) {
     l.pack = w.take<unsigned long long>(N);
     l.dlk = w.take<int32_t>(N);
     l.cc = w.take<int2>(N);
-    l.ctop = w.take<int32_t>(N);
+    l.cend = w.take<int32_t>(N);
     l.mrec = w.take<int2>(N);
     l.fbot = w.take<int32_t>(N);
     l.flen = w.take<int32_t>(N);

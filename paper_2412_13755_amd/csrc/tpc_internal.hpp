@@ -58,7 +58,7 @@ struct CaWs {
     int32_t *dlk;                // [N] kept link down, -1 if none
     int2 *cc;                    // [N] at a bottom: (chain length, hit offset of the chain core or
                                  // -1 if no seed), read together; (0, -1) elsewhere
-    int32_t *ctop;               // [N] chain top at a bottom
+    int32_t *cend;               // [N] at a bottom: the up link of its chain's top (top end candidate)
     int2 *mrec;                  // [N] at a block-local lowest member that is not its chain's
                                  // bottom: (chain bottom, position from it)
     int32_t *fbot;               // [N] at a seed's first cluster: the chain bottom, else -1
