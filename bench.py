@@ -239,9 +239,9 @@ def fit_source_sha():
     return source_sha(FIT_SOURCES)
 
 
-def profile_traffic(path, files):
-    """Calibrated HBM bytes per launch recorded in a profile summary, or None
-    if it is missing or was taken on other kernel sources."""
+def profile_keys(path, files):
+    """The key = value lines of a profile summary, or None if it is missing or
+    was taken on other kernel sources."""
     try:
         with open(path) as f:
             kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
@@ -249,7 +249,27 @@ def profile_traffic(path, files):
         return None
     if kv.get("source_sha256", "").strip() != source_sha(files):
         return None
-    return int(float(kv["traffic_bytes_per_launch"]))
+    return kv
+
+
+def profile_traffic(path, files):
+    """Calibrated HBM bytes per launch recorded in a profile summary, or None."""
+    kv = profile_keys(path, files)
+    return None if kv is None else int(float(kv["traffic_bytes_per_launch"]))
+
+
+def profile_valu(path, files, ms):
+    """Executed VALU lane operations per launch from the profile's counters
+    (SQ_INSTS_VALU x 64 x the active-lane fraction) and their rate over a
+    launch of ms, against the issue peak of one lane operation per lane per
+    clock (ALU_PEAK_TOPS); None without a matching profile."""
+    kv = profile_keys(path, files)
+    if kv is None or "valu_lane_ops_per_launch" not in kv:
+        return None
+    ops = float(kv["valu_lane_ops_per_launch"])
+    rate = ops / (ms * 1e-3) / 1e12
+    return {"lane_ops_per_launch": int(ops), "achieved": round(rate, 4), "peak": ALU_PEAK_TOPS,
+            "unit": "Top/s", "frac": round(rate / ALU_PEAK_TOPS, 5)}
 
 
 def fit_profile_traffic():
@@ -354,7 +374,8 @@ def leg_path(args, k):
                 "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": nb_profile_traffic(),
                 "kernel": "tpc_neighbours (nb_bin + nb_query_dense)", "avg_ms": round(float(stage_ms[0]), 5),
                 "algorithmic_ops": int(ops), "algorithmic_bytes": int(B_NB_PER_CLUSTER * N),
-                "hbm_frac": round(nb_gbs / HBM_PEAK_GBS, 6)}
+                "hbm_frac": round(nb_gbs / HBM_PEAK_GBS, 6),
+                "executed_valu": profile_valu(NB_PROFILE, NB_SOURCES, float(stage_ms[0]))}
     else:
         roof = fit_roofline(n_hits, n_seeds, float(stage_ms[2]), fit_profile_traffic())
     res = {
