@@ -9,12 +9,14 @@ namespace {
 __global__ void __launch_bounds__(TPC_BLOCK)
 nb_bin(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, const float *__restrict__ y,
        const float *__restrict__ z, float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy,
-       float *sz, int32_t *sid) {
+       float *sz, int32_t *sid, const int32_t *__restrict__ order) {
     __shared__ tpc_nb::BinLdsPerm L;
-    // xcd_item keeps each workgroup in its XCD's contiguous range of
-    // segments (the grid is NR or a multiple of 8)
+    // order: largest dense h-rows first, or null: xcd_item keeps each
+    // workgroup in its XCD's contiguous range of segments (the grid is NR or
+    // a multiple of 8)
     for (int it = blockIdx.x; it < NR; it += gridDim.x)
-        tpc_nb::nb_bin_seg(xcd_item(it, NR), n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid, L);
+        tpc_nb::nb_bin_seg(order ? order[it] : xcd_item(it, NR), n_rows, off, y, z, win_y, win_z, grid, cstart,
+                           sy, sz, sid, L);
 }
 
 // Rows whose neighbour rows fit the small LDS form (18 KB per workgroup).
@@ -40,16 +42,58 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
                          sz, sid, up, dn, L, tpc_nb::NB_LARGE);
 }
 
+// Segments in the order the dense query takes them: dense h-rows by
+// descending size in steps of 128 clusters (the largest start first, so the
+// last workgroups to finish are small ones), then the other segments (one
+// workgroup: a counting sort; the order within a step is immaterial).
+#define TPC_NB_ORDER_BINS 512
+__global__ void __launch_bounds__(TPC_BLOCK)
+nb_dense_order(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, int32_t *__restrict__ order) {
+    __shared__ int start[TPC_NB_ORDER_BINS + 1];
+    __shared__ int sh[TPC_BLOCK / TPC_WAVE];
+    static_assert(3 * TPC_BLOCK > TPC_NB_ORDER_BINS, "three bins per thread cover every key");
+    const int tid = threadIdx.x;
+    for (int k = tid; k <= TPC_NB_ORDER_BINS; k += TPC_BLOCK) start[k] = 0;
+    __syncthreads();
+    auto key = [&](int s) {
+        if (!tpc_nb::dense_hrow(off, s, n_rows)) return 0;
+        const int b = tpc_nb::seg_size(off, s) >> 7;
+        return 1 + (b < TPC_NB_ORDER_BINS - 1 ? b : TPC_NB_ORDER_BINS - 1);
+    };
+    for (int s = tid; s < NR; s += TPC_BLOCK) atomicAdd(&start[key(s)], 1);
+    __syncthreads();
+    // thread t takes keys TPC_NB_ORDER_BINS - 3t down to TPC_NB_ORDER_BINS - 3t - 2
+    int c[3], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int k = TPC_NB_ORDER_BINS - 3 * tid - q;
+        c[q] = k >= 0 ? start[k] : 0;
+        sum += c[q];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, sh, &total);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int k = TPC_NB_ORDER_BINS - 3 * tid - q;
+        if (k >= 0) start[k] = run;
+        run += c[q];
+    }
+    __syncthreads();
+    for (int s = tid; s < NR; s += TPC_BLOCK) order[atomicAdd(&start[key(s)], 1)] = s;
+}
+
 // Dense rows: slabs of the z-sorted rows, searched in LDS.  Four wavefronts
 // per SIMD (the LDS allows four workgroups per CU): at most 128 VGPRs.
+// order: the segments largest dense h-row first, or null for the XCD
+// ranges of xcd_item.
 __global__ void __launch_bounds__(TPC_BLOCK, 4)
 nb_query_dense(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, float win_y, float win_z, float cut_y,
                float cut_z, const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
-               const int32_t *sid, int32_t *up, int32_t *dn) {
+               const int32_t *sid, const int32_t *__restrict__ order, int32_t *up, int32_t *dn) {
     __shared__ tpc_nb::DenseLds L;
     for (int it = blockIdx.x; it < NR; it += gridDim.x)
-        tpc_nb::nb_dense_seg(xcd_item(it, NR), off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid,
-                             up, dn, L);
+        tpc_nb::nb_dense_seg(order ? order[it] : xcd_item(it, NR), off, n_rows, win_y, win_z, cut_y, cut_z, grid,
+                             cstart, sy, sz, sid, up, dn, L);
 }
 
 }  // namespace
@@ -66,15 +110,24 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
     // workgroup per segment, so heavy segments run side by side
     const bool sparse = (int64_t)fr->n_clusters < (int64_t)TPC_SPARSE_ROW * NR;
     const int gs = sparse && NR > TPC_SPARSE_GRID ? TPC_SPARSE_GRID : NR;
+    // frames of dense rows: the binning and the dense query take the largest
+    // dense h-rows first, so that the tail of a grid of workgroups of very
+    // different lengths is made of short ones
+    const int32_t *order = nullptr;
+    if (!sparse) {
+        hipLaunchKernelGGL(nb_dense_order, dim3(1), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows,
+                           ws.order);
+        order = ws.order;
+    }
     hipLaunchKernelGGL(nb_bin, dim3(gs), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows, fr->y,
-                       fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid);
+                       fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid, order);
     hipLaunchKernelGGL(nb_query_small, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows,
                        fr->y, fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, up, dn);
     hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
                        fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz,
                        ws.sid, up, dn);
     hipLaunchKernelGGL(nb_query_dense, dim3(gs), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows, c.win_y,
-                       c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid, up, dn);
+                       c.win_z, c.cut_y, c.cut_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid, order, up, dn);
     return hipGetLastError();
 }
 
@@ -86,6 +139,7 @@ size_t nb_ws_layout(void *ws, int64_t N, int64_t NR, NbWs *out) {
     l.sy = w.take<float>(N);
     l.sz = w.take<float>(N);
     l.sid = w.take<int32_t>(N);
+    l.order = w.take<int32_t>(NR);
     if (out) *out = l;
     return (w.off + 255) & ~size_t(255);
 }
