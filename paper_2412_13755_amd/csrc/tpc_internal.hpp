@@ -216,6 +216,46 @@ __device__ inline int block_exclusive_scan(int v, int *sh, int *total) {
     return before + inc - v;
 }
 
+// A permutation of [0, n) into order: items by descending key(i) in
+// [0, TPC_ORDER_BINS], any order within a key (one workgroup of TPC_BLOCK
+// threads, a counting sort; contains barriers).  start: TPC_ORDER_BINS + 1
+// ints of LDS, sh: TPC_BLOCK / TPC_WAVE ints of LDS.
+#define TPC_ORDER_BINS 512
+template <class Key>
+__device__ inline void order_desc(int n, Key key, int32_t *order, int *start, int *sh) {
+    static_assert(3 * TPC_BLOCK > TPC_ORDER_BINS, "three bins per thread cover every key");
+    const int tid = threadIdx.x;
+    for (int k = tid; k <= TPC_ORDER_BINS; k += TPC_BLOCK) start[k] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += TPC_BLOCK) atomicAdd(&start[key(i)], 1);
+    __syncthreads();
+    // thread t takes keys TPC_ORDER_BINS - 3t down to TPC_ORDER_BINS - 3t - 2
+    int c[3], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int k = TPC_ORDER_BINS - 3 * tid - q;
+        c[q] = k >= 0 ? start[k] : 0;
+        sum += c[q];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, sh, &total);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int k = TPC_ORDER_BINS - 3 * tid - q;
+        if (k >= 0) start[k] = run;
+        run += c[q];
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += TPC_BLOCK) order[atomicAdd(&start[key(i)], 1)] = i;
+}
+
+// Size key of segment s for order_desc: 1 + its clusters / 128 (capped),
+// 0 if empty.
+__device__ inline int seg_size_key(const int32_t *off, int s) {
+    const int b = (off[s + 1] - off[s]) >> 7;
+    return off[s + 1] == off[s] ? 0 : 1 + (b < TPC_ORDER_BINS - 1 ? b : TPC_ORDER_BINS - 1);
+}
+
 __device__ inline float wave_min(float v) {
 #pragma unroll
     for (int d = TPC_WAVE / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, TPC_WAVE));

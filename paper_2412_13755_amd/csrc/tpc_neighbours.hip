@@ -9,14 +9,13 @@ namespace {
 __global__ void __launch_bounds__(TPC_BLOCK)
 nb_bin(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, const float *__restrict__ y,
        const float *__restrict__ z, float win_y, float win_z, SegGrid *grid, int32_t *cstart, float *sy,
-       float *sz, int32_t *sid, const int32_t *__restrict__ order) {
+       float *sz, int32_t *sid) {
     __shared__ tpc_nb::BinLdsPerm L;
-    // order: largest dense h-rows first, or null: xcd_item keeps each
-    // workgroup in its XCD's contiguous range of segments (the grid is NR or
-    // a multiple of 8)
+    // xcd_item keeps each workgroup in its XCD's contiguous range of
+    // segments (the grid is NR or a multiple of 8); taking the largest rows
+    // first, as the dense query does, made the binning slower
     for (int it = blockIdx.x; it < NR; it += gridDim.x)
-        tpc_nb::nb_bin_seg(order ? order[it] : xcd_item(it, NR), n_rows, off, y, z, win_y, win_z, grid, cstart,
-                           sy, sz, sid, L);
+        tpc_nb::nb_bin_seg(xcd_item(it, NR), n_rows, off, y, z, win_y, win_z, grid, cstart, sy, sz, sid, L);
 }
 
 // Rows whose neighbour rows fit the small LDS form (18 KB per workgroup).
@@ -44,42 +43,13 @@ nb_query(const int32_t *__restrict__ off, int32_t n_rows, const float *__restric
 
 // Segments in the order the dense query takes them: dense h-rows by
 // descending size in steps of 128 clusters (the largest start first, so the
-// last workgroups to finish are small ones), then the other segments (one
-// workgroup: a counting sort; the order within a step is immaterial).
-#define TPC_NB_ORDER_BINS 512
+// last workgroups to finish are small ones), then the other segments.
 __global__ void __launch_bounds__(TPC_BLOCK)
 nb_dense_order(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, int32_t *__restrict__ order) {
-    __shared__ int start[TPC_NB_ORDER_BINS + 1];
+    __shared__ int start[TPC_ORDER_BINS + 1];
     __shared__ int sh[TPC_BLOCK / TPC_WAVE];
-    static_assert(3 * TPC_BLOCK > TPC_NB_ORDER_BINS, "three bins per thread cover every key");
-    const int tid = threadIdx.x;
-    for (int k = tid; k <= TPC_NB_ORDER_BINS; k += TPC_BLOCK) start[k] = 0;
-    __syncthreads();
-    auto key = [&](int s) {
-        if (!tpc_nb::dense_hrow(off, s, n_rows)) return 0;
-        const int b = tpc_nb::seg_size(off, s) >> 7;
-        return 1 + (b < TPC_NB_ORDER_BINS - 1 ? b : TPC_NB_ORDER_BINS - 1);
-    };
-    for (int s = tid; s < NR; s += TPC_BLOCK) atomicAdd(&start[key(s)], 1);
-    __syncthreads();
-    // thread t takes keys TPC_NB_ORDER_BINS - 3t down to TPC_NB_ORDER_BINS - 3t - 2
-    int c[3], sum = 0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int k = TPC_NB_ORDER_BINS - 3 * tid - q;
-        c[q] = k >= 0 ? start[k] : 0;
-        sum += c[q];
-    }
-    int total;
-    int run = block_exclusive_scan(sum, sh, &total);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int k = TPC_NB_ORDER_BINS - 3 * tid - q;
-        if (k >= 0) start[k] = run;
-        run += c[q];
-    }
-    __syncthreads();
-    for (int s = tid; s < NR; s += TPC_BLOCK) order[atomicAdd(&start[key(s)], 1)] = s;
+    order_desc(NR, [&](int s) { return tpc_nb::dense_hrow(off, s, n_rows) ? seg_size_key(off, s) : 0; }, order,
+               start, sh);
 }
 
 // Dense rows: slabs of the z-sorted rows, searched in LDS.  Four wavefronts
@@ -110,9 +80,9 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
     // workgroup per segment, so heavy segments run side by side
     const bool sparse = (int64_t)fr->n_clusters < (int64_t)TPC_SPARSE_ROW * NR;
     const int gs = sparse && NR > TPC_SPARSE_GRID ? TPC_SPARSE_GRID : NR;
-    // frames of dense rows: the binning and the dense query take the largest
-    // dense h-rows first, so that the tail of a grid of workgroups of very
-    // different lengths is made of short ones
+    // frames of dense rows: the dense query takes the largest dense h-rows
+    // first, so that the tail of a grid of workgroups of very different
+    // lengths is made of short ones
     const int32_t *order = nullptr;
     if (!sparse) {
         hipLaunchKernelGGL(nb_dense_order, dim3(1), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows,
@@ -120,7 +90,7 @@ hipError_t launch_neighbours(const tpc_context *ctx, const tpc_frames *fr, int32
         order = ws.order;
     }
     hipLaunchKernelGGL(nb_bin, dim3(gs), dim3(TPC_BLOCK), 0, st, fr->row_offsets, NR, c.n_rows, fr->y,
-                       fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid, order);
+                       fr->z, c.win_y, c.win_z, ws.grid, ws.cstart, ws.sy, ws.sz, ws.sid);
     hipLaunchKernelGGL(nb_query_small, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows,
                        fr->y, fr->z, c.win_y, c.win_z, c.cut_y, c.cut_z, up, dn);
     hipLaunchKernelGGL(nb_query, dim3(NR), dim3(TPC_BLOCK), 0, st, fr->row_offsets, c.n_rows, fr->y,
