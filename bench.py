@@ -372,7 +372,7 @@ def leg_path(args, k):
         achieved = ops / (stage_ms[0] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": ALU_PEAK_TOPS, "unit": "Top/s",
                 "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": nb_profile_traffic(),
-                "kernel": "tpc_neighbours (nb_bin + nb_query_dense)", "avg_ms": round(float(stage_ms[0]), 5),
+                "kernel": "tpc_neighbours (nb_dense_order + nb_bin + nb_query_dense)", "avg_ms": round(float(stage_ms[0]), 5),
                 "algorithmic_ops": int(ops), "algorithmic_bytes": int(B_NB_PER_CLUSTER * N),
                 "hbm_frac": round(nb_gbs / HBM_PEAK_GBS, 6),
                 "executed_valu": profile_valu(NB_PROFILE, NB_SOURCES, float(stage_ms[0]))}
