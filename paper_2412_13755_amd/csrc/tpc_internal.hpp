@@ -50,7 +50,7 @@ struct NbWs {
     int32_t *cstart;    // [N + NR + 1]: cell starts of segment s at row_offsets[s] + s
     float *sy, *sz;     // [N] clusters sorted by cell within each segment
     int32_t *sid;       // [N] their global ids
-    int32_t *order;     // [NR] dense h-rows largest first, then the other segments
+    int32_t *order;     // [TPC_NB_PARTS NR] parts of dense h-rows largest first, then the rest
 };
 
 struct CaWs {

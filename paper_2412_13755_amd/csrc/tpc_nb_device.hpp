@@ -822,6 +822,13 @@ __device__ inline void slab_search(int pb, int pn, const float *__restrict__ sy,
     }
 }
 
+// Start of part k of a dense h-row of n z-sorted clusters searched in
+// `parts` parts by different workgroups: k / parts of it, rounded down to
+// whole slabs (part parts ends at n).
+__device__ inline int dense_split(int n, int k, int parts) {
+    return k >= parts ? n : (int)((int64_t)n * k / parts) / TPC_NB_SLAB * TPC_NB_SLAB;
+}
+
 // Dense h-row `seg` (whole workgroup; contains barriers): slabs of
 // consecutive clusters of its z-sorted copy.  A partner of h passes the
 // window test only if its z lies within win_z of z_h (the difference is one
@@ -838,11 +845,12 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
                                     const int32_t *__restrict__ cstart, const float *__restrict__ sy,
                                     const float *__restrict__ sz, const int32_t *__restrict__ sid,
                                     int32_t *__restrict__ up, int32_t *__restrict__ dn,
-                                    DenseLdsT<ROW, CELLS> &L) {
+                                    DenseLdsT<ROW, CELLS> &L, int part = 0, int parts = 1) {
 #pragma clang fp contract(off)
     if (!dense_hrow(off, seg, n_rows)) return;
     const int tid = threadIdx.x;
     const int a = off[seg], n = off[seg + 1] - a;
+    const int lo = dense_split(n, part, parts), hi = dense_split(n, part + 1, parts);
     const int sd = seg - 1, su = seg + 1;
     const int based = off[sd], baseu = off[su];
     const SegGrid gdg = grid[sd], gug = grid[su];
@@ -852,8 +860,8 @@ __device__ inline void nb_dense_seg(int seg, const int32_t *__restrict__ off, in
     // result is never all ones)
     const bool rel_ok = seg_size(off, sd) <= 65535 && seg_size(off, su) <= 65535;
     int P = TPC_NB_SLAB;
-    for (int p0 = 0; p0 < n;) {
-        const int pn = n - p0 < P ? n - p0 : P;
+    for (int p0 = lo; p0 < hi;) {
+        const int pn = hi - p0 < P ? hi - p0 : P;
         float lo = INFINITY, hi = -INFINITY;
         for (int k = tid; k < pn; k += TPC_BLOCK) {
             const float zv = sz[a + p0 + k];
