@@ -75,17 +75,22 @@ nb_query_dense(const int32_t *__restrict__ off, int32_t NR, int32_t n_rows, floa
                float cut_z, const SegGrid *grid, const int32_t *cstart, const float *sy, const float *sz,
                const int32_t *sid, const int32_t *__restrict__ order, int32_t *up, int32_t *dn) {
     __shared__ tpc_nb::DenseLds L;
-    if (order) {
-        for (int it = blockIdx.x; it < TPC_NB_PARTS * NR; it += gridDim.x) {
+    // one call site of the search for both forms: a second inlined copy
+    // took the kernel past its 128 VGPRs into scratch spills
+    const int items = order ? TPC_NB_PARTS * NR : NR;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        int seg, part = 0, parts = 1;
+        if (order) {
             const int item = order[it];
-            tpc_nb::nb_dense_seg(item / TPC_NB_PARTS, off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy,
-                                 sz, sid, up, dn, L, item % TPC_NB_PARTS, TPC_NB_PARTS);
+            seg = item / TPC_NB_PARTS;
+            part = item % TPC_NB_PARTS;
+            parts = TPC_NB_PARTS;
+        } else {
+            seg = xcd_item(it, NR);
         }
-        return;
+        tpc_nb::nb_dense_seg(seg, off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid, up, dn, L,
+                             part, parts);
     }
-    for (int it = blockIdx.x; it < NR; it += gridDim.x)
-        tpc_nb::nb_dense_seg(xcd_item(it, NR), off, n_rows, win_y, win_z, cut_y, cut_z, grid, cstart, sy, sz, sid,
-                             up, dn, L);
 }
 
 }  // namespace
