@@ -229,12 +229,16 @@ __device__ inline void row_sort_perm(const float *__restrict__ y, const float *_
         perm[atomicAdd(&cnt[c], 1)] = (uint16_t)(i - a);
     }
     __syncthreads();
+    // the gathers through the permutation are random within the row: z
+    // first, then y, so that a workgroup's reads span one row array at a
+    // time (the rows in flight on an XCD then miss its L2 less)
     for (int k = tid; k < b - a; k += TPC_BLOCK) {
         const int i = a + perm[k];
-        dy[obase + k] = y[i];
         dz[obase + k] = z[i];
         did[obase + k] = i;
     }
+    __syncthreads();
+    for (int k = tid; k < b - a; k += TPC_BLOCK) dy[obase + k] = y[a + perm[k]];
     __syncthreads();
 }
 
